@@ -1,0 +1,210 @@
+/*
+ * rsim.h - C ABI of librsim: MI355X (gfx950) FMCW radar echo synthesis.
+ *
+ * The problem, as stated in Section 3 of "A Simulation Method for MMW Radar Sensing
+ * in Traffic Intersection Based on BART Algorithm" (arXiv 2208.10939): vehicles with
+ * positions and velocities in an intersection (Section 3.1, Table 1), a radar
+ * transmitting FMCW chirps (eq. (8)) from P Tx to Q Rx antennas, whose echo
+ * (eqs. (7), (9)-(13)) is sampled into an O x M x N cube (O = P Q channels, M samples
+ * per chirp, N chirps) and turned into a range-Doppler map by FFTs over samples and
+ * chirps (Section 3.3).
+ *
+ * Conventions
+ *  - Every call returns an int32 status: RSIM_OK (0) or a negative RSIM_E* code. On
+ *    failure rsim_last_error() describes it; outputs are then undefined.
+ *  - The caller owns every buffer it passes. Host inputs are copied before the call
+ *    returns. Device outputs are written asynchronously on the given HIP stream
+ *    (hipStream_t passed as void*, NULL = default stream) and are valid only once
+ *    that stream has completed the work.
+ *  - A context is not thread-safe: one context per host thread.
+ *  - World frame of the paper (Table 1): Z up, Y along the lanes, metres, seconds, Hz.
+ *  - Complex values are interleaved (re, im). Echo layout H[scene][o][n][m] with
+ *    channel o = p * Q + q.
+ */
+#ifndef RSIM_H
+#define RSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSIM_ABI_VERSION 1
+
+/* status codes */
+#define RSIM_OK 0
+#define RSIM_EINVAL (-1)  /* bad argument: NULL, NaN/Inf, index out of range, bad id  */
+#define RSIM_ENOMEM (-2)  /* device allocation failed or exceeded rsim_set_mem_limit  */
+#define RSIM_EDEVICE (-3) /* HIP error, no device, or a device call on a host-only ctx */
+#define RSIM_ESTATE (-4)  /* waveform, array or scene missing / inconsistent          */
+#define RSIM_ERANGE (-5)  /* supported-size limit exceeded (see each call)             */
+
+/* precision of rsim_synthesize / rsim_form_rdm */
+#define RSIM_FP32_PHASE64 0 /* FP64 geometry and phase reduction, FP32 sum; complex64 */
+#define RSIM_FP64 1         /* FP64 throughout; complex128 echo                       */
+
+/* visibility-mask mode */
+#define RSIM_MASK_COMPUTE 0 /* compute the lit-facet mask; write it to vis_mask if given */
+#define RSIM_MASK_INPUT 1   /* use vis_mask (device) as given; skip the visibility step */
+
+typedef struct rsim_ctx rsim_ctx;
+
+/* FMCW waveform (eq. (8), Section 4.1). Sample m of chirp n is taken at frequency
+ * f_m = f0 + m * slope / fs and chirp start time t_n = n * chirp_period.
+ * n_samples (M) and n_chirps (N) in 1..4096; rsim_form_rdm needs powers of two. */
+typedef struct {
+  double f0_hz;
+  double slope_hz_per_s;
+  double fs_hz;
+  double chirp_period_s;
+  int32_t n_samples;
+  int32_t n_chirps;
+} rsim_waveform;
+
+/* Options of rsim_synthesize / rsim_form_rdm. Zero-initialised = defaults. */
+typedef struct {
+  int32_t precision; /* RSIM_FP32_PHASE64 (default) or RSIM_FP64                         */
+  int32_t mask_mode; /* RSIM_MASK_COMPUTE (default) or RSIM_MASK_INPUT                   */
+  int32_t use_graph; /* batched call: capture the launches in a hipGraph and replay it  */
+  int32_t persistent;/* batched call: one persistent facet-sum launch over a work queue  */
+  int32_t timing;    /* record per-stage HIP events (read with rsim_last_timings)        */
+  int32_t tile_m;    /* facet-sum samples per thread (0 = autotuned/default; 8..64)       */
+  int32_t tile_f;    /* facets staged per LDS tile (0 = default; 4..32)                   */
+  int32_t reserved;
+} rsim_opts;
+
+/* ---- context ---------------------------------------------------------------------- */
+
+int32_t rsim_abi_version(void);
+
+/* Create a context on HIP device `hip_device`. hip_device = -1 creates a host-only
+ * context: meshes, scenes, waveform and array can be set and validated (and the BVH
+ * built) but every device call returns RSIM_EDEVICE. On failure *out is NULL and
+ * rsim_last_error(NULL) holds the message. */
+int32_t rsim_create(int32_t hip_device, rsim_ctx **out);
+void rsim_destroy(rsim_ctx *ctx);
+
+/* Message of the last failing call on ctx (ctx = NULL: last failure of this thread
+ * outside any context). Valid until the next call on the same ctx / thread. */
+const char *rsim_last_error(const rsim_ctx *ctx);
+
+/* Cap on the library's device allocations in bytes (0 = no cap). A call that would
+ * exceed it fails with RSIM_ENOMEM. */
+int32_t rsim_set_mem_limit(rsim_ctx *ctx, uint64_t bytes);
+
+/* ---- scene ------------------------------------------------------------------------ */
+
+/* Triangle mesh in its body frame: verts_xyz [n_verts][3] float32 metres, tris
+ * [n_tris][3] int32 vertex indices, counter-clockwise = outward normal. The data are
+ * copied and a bounding-volume hierarchy is built once here. Zero-area triangles are
+ * accepted: they never scatter and never block. EINVAL on NaN/Inf or bad indices;
+ * ERANGE beyond 2^26 triangles. */
+int32_t rsim_load_mesh(rsim_ctx *ctx, const float *verts_xyz, int64_t n_verts,
+                       const int32_t *tris, int64_t n_tris, int32_t *mesh_id);
+
+int32_t rsim_create_scene(rsim_ctx *ctx, int32_t *scene_id);
+
+/* Rigid instance of a mesh moving at constant velocity (eq. (12), Section 3.2):
+ * world position x(t) = rot * x_body + pos0 + vel * t. rot is row-major 3x3 and
+ * must be orthonormal. The scene's facets are numbered instance by instance in the
+ * order instances were added. At most 4096 instances per scene. */
+int32_t rsim_add_instance(rsim_ctx *ctx, int32_t scene_id, int32_t mesh_id,
+                          const double rot[9], const double pos0[3], const double vel[3],
+                          int32_t *inst_id);
+
+/* Point scatterers (the point target of eq. (13)): pos0 [n][3], vel [n][3] float64,
+ * amp_re_im [n][2] float64 complex amplitude s in m^2 (echo term s/(4 pi R_t R_r)). */
+int32_t rsim_add_points(rsim_ctx *ctx, int32_t scene_id, const double *pos0,
+                        const double *vel, const double *amp_re_im, int64_t n);
+
+/* Number of facets F of a scene (sum over its instances) and words per chirp of its
+ * lit-facet mask, ceil(F / 32). */
+int32_t rsim_scene_info(rsim_ctx *ctx, int32_t scene_id, int64_t *n_facets,
+                        int64_t *mask_words_per_chirp);
+
+/* ---- radar ------------------------------------------------------------------------ */
+
+int32_t rsim_set_waveform(rsim_ctx *ctx, const rsim_waveform *wf);
+
+/* Antenna element positions in the world frame (Section 2.1, Fig. 3): tx [n_tx][3],
+ * rx [n_rx][3] float64. 1..64 elements each. The Tx and Rx phase centres are the
+ * element means; they define visibility and the facet-integral directions. */
+int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx,
+                       const double *rx_xyz, int32_t n_rx);
+
+/* ---- echo and RDM ------------------------------------------------------------------ */
+
+/* Echo frequency response H (Sections 2.2, 3.2; eqs. (7), (9)-(13)) of each scene:
+ *   H[o,n,m] = sum over lit facets f of  j o_f I_f(k_m) / (4 pi R_t R_r)
+ *              * exp(-j 2 pi (f_m tau - slope tau^2 / 2)),  tau = (R_t + R_r) / c,
+ * with I_f the closed-form physical-optics integral over the triangle, o_f the
+ * obliquity, R_t / R_r the distances from the facet centroid to Tx element p and
+ * Rx element q, geometry frozen at t_n (stop-and-hop); plus point scatterers.
+ * The beat signal of eq. (13) is conj(H).
+ *   echo     DEVICE, [n_scenes][O][N][M] complex64 (complex128 with RSIM_FP64).
+ *   vis_mask DEVICE or NULL, [sum over scenes of N * mask_words(scene)] uint32,
+ *            bit f%32 of word [n][f/32] = facet f lit at chirp n; output with
+ *            RSIM_MASK_COMPUTE, input with RSIM_MASK_INPUT (then required).
+ * ESTATE without waveform/array; EINVAL for an unknown scene id; ERANGE if the
+ * array aperture is too large for the phase factorisation (see DESIGN notes in
+ * rsim_set_array's error message). */
+int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
+                        void *echo, uint32_t *vis_mask, void *hip_stream,
+                        const rsim_opts *opts);
+
+/* Range-Doppler processing (Section 3.3; eqs. (4), (5), (10)-(11)) of n_cubes echo
+ * cubes [O][N][M]: beat x = conj(H), X = FFT over m, Y = FFT over n with zero Doppler
+ * moved to row N/2, rdm = |Y|^2. Unnormalised FFTs, no window.
+ *   echo  DEVICE [n_cubes][O][N][M] complex64 (complex128 with RSIM_FP64)
+ *   rdm   DEVICE [n_cubes][O][N][M] float32 (float64 with RSIM_FP64), row = Doppler
+ *   y_opt DEVICE or NULL, Y in the echo's complex type and layout.
+ * ERANGE unless M and N are powers of two in 2..4096. */
+int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm,
+                      void *y_opt, void *hip_stream, const rsim_opts *opts);
+
+/* Per-stage device times (ms) of the last rsim_synthesize / rsim_form_rdm /
+ * rsim_backward call made with opts.timing = 1, measured with HIP events on the
+ * caller's stream. Blocks until those events complete. Stage order:
+ * 0 visibility, 1 compaction, 2 facet sum (incl. FP64 prep), 3 range FFT,
+ * 4 Doppler FFT + RDM, 5 adjoint facet sum, 6 adjoint FFTs, 7 vertex gather.
+ * Stages not run report 0. n_stages up to 8. */
+int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages);
+
+/* ---- adjoint ------------------------------------------------------------------------ */
+
+/* Gradient of a real loss L through the echo of one scene (FP32 path), with the
+ * lit-facet mask held fixed and chirps recomputed rather than stored.
+ *   grad_echo  DEVICE [O][N][M] complex64: dL/dRe(H) + j dL/dIm(H)
+ *   vis_mask   DEVICE mask of that scene from the forward call (N * mask_words)
+ *   grad_verts host array of n_meshes DEVICE pointers, each [n_verts][3] float32 of
+ *              the scene's meshes in mesh-id order (NULL entries skipped); dL/dx_body
+ *              summed over the instances of each mesh, ACCUMULATED into the buffers.
+ *   grad_vel   DEVICE [n_instances][3] float64, dL/dvel per instance, overwritten.
+ */
+int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
+                      const uint32_t *vis_mask, float *const *grad_verts, int32_t n_meshes,
+                      double *grad_vel, void *hip_stream);
+
+/* Gradient of L with respect to the echo given dL/dRe(Y) + j dL/dIm(Y) of the
+ * Doppler-FFT output (adjoint of rsim_form_rdm's linear part, FP32):
+ *   grad_y DEVICE [n_cubes][O][N][M] complex64 -> grad_echo same layout. */
+int32_t rsim_rdm_adjoint(rsim_ctx *ctx, const void *grad_y, int32_t n_cubes,
+                         void *grad_echo, void *hip_stream);
+
+/* ---- tuning ------------------------------------------------------------------------- */
+
+/* Time the facet-sum tile shapes on the given scenes and keep the fastest as the
+ * default for this (M, O, precision); optionally append it to a JSON-lines cache
+ * file (cache_json_path may be NULL). Synchronous. */
+int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
+                      const char *cache_json_path);
+
+/* Wait for all work the library queued on hip_stream. */
+int32_t rsim_sync(rsim_ctx *ctx, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSIM_H */

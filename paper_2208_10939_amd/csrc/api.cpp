@@ -1,0 +1,1001 @@
+// Host runtime and C ABI of librsim (see include/rsim.h for the contract).
+//
+// The context owns device copies of meshes (vertices, triangles, BVH), per-scene
+// instance tables and work buffers (lit-facet lists per chirp), twiddle tables and
+// timing events. Every launch goes to the caller's stream; nothing here blocks
+// unless the call is documented as synchronous.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rsim.h"
+#include "rsim_internal.h"
+#include "rsim_launch.h"
+
+using namespace rsim;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr int kStages = 8;
+
+struct MeshRec {
+  std::vector<float> verts;
+  std::vector<int32_t> tris;
+  double box_lo[3], box_hi[3];  // body bounding box
+  int depth = -1;
+  int64_t n_nodes = 0, n_leaf = 0;
+  void *d_verts = nullptr, *d_tris = nullptr, *d_nodes = nullptr, *d_leaf = nullptr;
+};
+
+struct InstRec {
+  int32_t mesh;
+  double rot[9], pos0[3], vel[3];
+};
+
+struct SceneRec {
+  std::vector<InstRec> inst;
+  std::vector<double> pt_pos, pt_vel, pt_amp;
+  int64_t n_facets = 0;
+  // device copies (rebuilt when dirty)
+  bool dirty = true;
+  DevInstance *d_inst = nullptr;
+  double *d_pt = nullptr;  // pos [n][3], vel [n][3], amp [n][2]
+  // work buffers sized for (N, F)
+  int32_t buf_N = -1;
+  uint32_t *d_mask = nullptr;
+  int32_t *d_vis_idx = nullptr;
+  int32_t *d_vis_cnt = nullptr;
+};
+
+struct TunedShape {
+  int mb, ft;
+};
+
+// Device-side tables of one batched call: scene views and the longest-first work
+// queue of (scene, chirp, sample tile, channel tile) items.
+struct BatchTables {
+  DevScene *d_scenes = nullptr;
+  int4 *d_items = nullptr;
+  int32_t *d_queue = nullptr;
+  size_t scenes_cap = 0, items_cap = 0;
+  int32_t n_items = 0;
+  // key of the uploaded contents
+  std::vector<int32_t> ids;
+  void *echo = nullptr;
+  uint32_t *mask = nullptr;
+  uint64_t version = 0;
+  int mb = 0;
+  int precision = -1;
+};
+
+struct GraphCache {
+  bool valid = false;
+  std::vector<int32_t> ids;
+  void *echo = nullptr;
+  uint32_t *mask = nullptr;
+  rsim_opts opts{};
+  uint64_t version = 0;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  BatchTables tables;  // the graph replays kernels reading these
+};
+
+}  // namespace
+
+struct rsim_ctx {
+  int device = -1;
+  bool host_only = true;
+  std::string err;
+  uint64_t mem_limit = 0, mem_used = 0;
+  std::map<void *, size_t> allocs;
+  std::vector<MeshRec> meshes;
+  std::vector<SceneRec> scenes;
+  bool have_wf = false, have_arr = false;
+  rsim_waveform wf{};
+  std::vector<double> tx, rx;
+  double *d_elem = nullptr;
+  uint64_t version = 1;  // bumped on any change that invalidates cached graphs
+  std::map<std::pair<int, int>, void *> twiddles;  // (L, precision) -> table
+  void *d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  hipEvent_t ev0[kStages] = {}, ev1[kStages] = {};
+  bool stage_ran[kStages] = {};
+  bool timing_pending = false;
+  hipStream_t capture_stream = nullptr;
+  int cu_count = 0;
+  size_t max_lds = 0;
+  std::map<std::tuple<int, int, int>, TunedShape> tuned;  // (M, O, precision) -> shape
+  BatchTables batch;  // persistent launches outside graphs
+  GraphCache graph;
+};
+
+namespace {
+
+int32_t fail(rsim_ctx *ctx, int32_t code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx)
+    ctx->err = buf;
+  else
+    g_thread_error = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, RSIM_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                     \
+  } while (0)
+
+int32_t dev_alloc(rsim_ctx *ctx, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return RSIM_OK;
+  if (ctx->mem_limit && ctx->mem_used + bytes > ctx->mem_limit)
+    return fail(ctx, RSIM_ENOMEM, "allocation of %zu bytes exceeds the memory limit (%llu used of %llu)",
+                bytes, (unsigned long long)ctx->mem_used, (unsigned long long)ctx->mem_limit);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(ctx, RSIM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  ctx->mem_used += bytes;
+  ctx->allocs[*p] = bytes;
+  return RSIM_OK;
+}
+
+void dev_free(rsim_ctx *ctx, void *p) {
+  if (!p) return;
+  auto it = ctx->allocs.find(p);
+  if (it != ctx->allocs.end()) {
+    ctx->mem_used -= it->second;
+    ctx->allocs.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+template <typename T>
+int32_t upload(rsim_ctx *ctx, T **dst, const T *src, size_t count) {
+  void *p = nullptr;
+  int32_t rc = dev_alloc(ctx, &p, sizeof(T) * count);
+  if (rc) return rc;
+  if (count) {
+    hipError_t e = hipMemcpy(p, src, sizeof(T) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      dev_free(ctx, p);
+      return fail(ctx, RSIM_EDEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+    }
+  }
+  *dst = static_cast<T *>(p);
+  return RSIM_OK;
+}
+
+bool finite_all(const double *p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+bool is_pow2(int v) { return v >= 2 && (v & (v - 1)) == 0; }
+
+int32_t need_device(rsim_ctx *ctx) {
+  if (ctx->host_only) return fail(ctx, RSIM_EDEVICE, "host-only context: no device calls");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return RSIM_OK;
+}
+
+RadarConst radar_const(const rsim_ctx *ctx) {
+  RadarConst rc{};
+  rc.f0 = ctx->wf.f0_hz;
+  rc.slope = ctx->wf.slope_hz_per_s;
+  rc.fs = ctx->wf.fs_hz;
+  rc.df = ctx->wf.slope_hz_per_s / ctx->wf.fs_hz;
+  rc.tc = ctx->wf.chirp_period_s;
+  rc.M = ctx->wf.n_samples;
+  rc.N = ctx->wf.n_chirps;
+  rc.P = static_cast<int32_t>(ctx->tx.size() / 3);
+  rc.Q = static_cast<int32_t>(ctx->rx.size() / 3);
+  for (int k = 0; k < 3; ++k) {
+    double st = 0, sr = 0;
+    for (int p = 0; p < rc.P; ++p) st += ctx->tx[3 * p + k];
+    for (int q = 0; q < rc.Q; ++q) sr += ctx->rx[3 * q + k];
+    rc.tx_c[k] = st / rc.P;
+    rc.rx_c[k] = sr / rc.Q;
+  }
+  return rc;
+}
+
+// Largest |2 pi slope d_p e_q| over any facet position (triangle inequality bound).
+double cross_term_bound(const rsim_ctx *ctx, const RadarConst &rc) {
+  double mt = 0, mr = 0;
+  for (int p = 0; p < rc.P; ++p) {
+    double d = 0;
+    for (int k = 0; k < 3; ++k) d += (ctx->tx[3 * p + k] - rc.tx_c[k]) * (ctx->tx[3 * p + k] - rc.tx_c[k]);
+    mt = std::max(mt, std::sqrt(d));
+  }
+  for (int q = 0; q < rc.Q; ++q) {
+    double d = 0;
+    for (int k = 0; k < 3; ++k) d += (ctx->rx[3 * q + k] - rc.rx_c[k]) * (ctx->rx[3 * q + k] - rc.rx_c[k]);
+    mr = std::max(mr, std::sqrt(d));
+  }
+  return 2.0 * kPi * std::fabs(rc.slope) * mt * mr / (kC0 * kC0);
+}
+
+int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
+  const int N = ctx->wf.n_chirps;
+  if (sc.dirty) {
+    dev_free(ctx, sc.d_inst);
+    dev_free(ctx, sc.d_pt);
+    sc.d_inst = nullptr;
+    sc.d_pt = nullptr;
+    std::vector<DevInstance> di(sc.inst.size());
+    int64_t base = 0;
+    for (size_t i = 0; i < sc.inst.size(); ++i) {
+      const InstRec &r = sc.inst[i];
+      const MeshRec &m = ctx->meshes[r.mesh];
+      DevInstance &d = di[i];
+      std::memcpy(d.rot, r.rot, sizeof(d.rot));
+      std::memcpy(d.pos0, r.pos0, sizeof(d.pos0));
+      std::memcpy(d.vel, r.vel, sizeof(d.vel));
+      // world box of rot * body box, padded for the FP32 traversal inside it
+      for (int k = 0; k < 3; ++k) {
+        double lo = 0, hi = 0;
+        for (int j = 0; j < 3; ++j) {
+          double a = r.rot[3 * k + j] * m.box_lo[j], b = r.rot[3 * k + j] * m.box_hi[j];
+          lo += std::min(a, b);
+          hi += std::max(a, b);
+        }
+        double pad = 1e-6 * (std::fabs(lo) + std::fabs(hi)) + 1e-6;
+        d.box_lo[k] = lo - pad;
+        d.box_hi[k] = hi + pad;
+      }
+      d.verts = static_cast<const float *>(m.d_verts);
+      d.tris = static_cast<const int32_t *>(m.d_tris);
+      d.nodes = static_cast<const BvhNode *>(m.d_nodes);
+      d.leaf = static_cast<const float4 *>(m.d_leaf);
+      d.facet_base = base;
+      d.n_tris = static_cast<int32_t>(m.tris.size() / 3);
+      d.has_bvh = m.depth >= 0 ? 1 : 0;
+      base += d.n_tris;
+    }
+    sc.n_facets = base;
+    int32_t rc = upload(ctx, &sc.d_inst, di.data(), di.size());
+    if (rc) return rc;
+    const size_t np = sc.pt_amp.size() / 2;
+    if (np) {
+      std::vector<double> pts;
+      pts.insert(pts.end(), sc.pt_pos.begin(), sc.pt_pos.end());
+      pts.insert(pts.end(), sc.pt_vel.begin(), sc.pt_vel.end());
+      pts.insert(pts.end(), sc.pt_amp.begin(), sc.pt_amp.end());
+      rc = upload(ctx, &sc.d_pt, pts.data(), pts.size());
+      if (rc) return rc;
+    }
+    sc.dirty = false;
+    sc.buf_N = -1;
+  }
+  if (sc.buf_N != N) {
+    dev_free(ctx, sc.d_mask);
+    dev_free(ctx, sc.d_vis_idx);
+    dev_free(ctx, sc.d_vis_cnt);
+    sc.d_mask = nullptr;
+    sc.d_vis_idx = nullptr;
+    sc.d_vis_cnt = nullptr;
+    const int64_t words = (sc.n_facets + 31) / 32;
+    int32_t rc;
+    if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_mask),
+                        sizeof(uint32_t) * std::max<int64_t>(1, words) * N)))
+      return rc;
+    if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_vis_idx),
+                        sizeof(int32_t) * std::max<int64_t>(1, sc.n_facets) * N)))
+      return rc;
+    if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_vis_cnt), sizeof(int32_t) * N))) return rc;
+    sc.buf_N = N;
+  }
+  return RSIM_OK;
+}
+
+DevScene dev_scene(const SceneRec &sc, uint32_t *mask, void *echo) {
+  DevScene d{};
+  d.inst = sc.d_inst;
+  d.n_inst = static_cast<int32_t>(sc.inst.size());
+  d.n_points = static_cast<int32_t>(sc.pt_amp.size() / 2);
+  d.n_facets = sc.n_facets;
+  d.mask_words = (sc.n_facets + 31) / 32;
+  const size_t np = d.n_points;
+  d.pt_pos0 = sc.d_pt;
+  d.pt_vel = sc.d_pt ? sc.d_pt + 3 * np : nullptr;
+  d.pt_amp = sc.d_pt ? sc.d_pt + 6 * np : nullptr;
+  d.mask = mask;
+  d.vis_idx = sc.d_vis_idx;
+  d.vis_cnt = sc.d_vis_cnt;
+  d.echo = echo;
+  return d;
+}
+
+TunedShape pick_shape(const rsim_ctx *ctx, int precision, const rsim_opts &o) {
+  const int M = ctx->wf.n_samples;
+  const int O = static_cast<int>(ctx->tx.size() / 3 * ctx->rx.size() / 3);
+  TunedShape s = precision ? TunedShape{16, 8} : TunedShape{32, 16};
+  auto it = ctx->tuned.find(std::make_tuple(M, O, precision));
+  if (it != ctx->tuned.end()) s = it->second;
+  if (o.tile_m) s.mb = o.tile_m;
+  if (o.tile_f) s.ft = o.tile_f;
+  return s;
+}
+
+EchoShape echo_shape(const rsim_ctx *ctx, const RadarConst &rc, int mb) {
+  EchoShape sh{};
+  sh.O = rc.P * rc.Q;
+  sh.E = rc.P + rc.Q;
+  sh.O_w = std::min(sh.O, 256);
+  sh.o_tiles = (sh.O + sh.O_w - 1) / sh.O_w;
+  const int blocks_needed = (rc.M + mb - 1) / mb;
+  sh.B_w = std::max(1, std::min(blocks_needed, 512 / sh.O_w));
+  sh.M_t = sh.B_w * mb;
+  sh.m_tiles = (rc.M + sh.M_t - 1) / sh.M_t;
+  sh.two_pi_slope = 2.0 * kPi * rc.slope;
+  return sh;
+}
+
+void *twiddles(rsim_ctx *ctx, int L, int precision, int32_t *status) {
+  auto key = std::make_pair(L, precision);
+  auto it = ctx->twiddles.find(key);
+  if (it != ctx->twiddles.end()) return it->second;
+  const int half = std::max(1, L / 2);
+  void *p = nullptr;
+  if (precision) {
+    std::vector<double> t(2 * half);
+    for (int i = 0; i < half; ++i) {
+      t[2 * i] = std::cos(2.0 * kPi * i / L);
+      t[2 * i + 1] = -std::sin(2.0 * kPi * i / L);
+    }
+    double *d = nullptr;
+    *status = upload(ctx, &d, t.data(), t.size());
+    p = d;
+  } else {
+    std::vector<float> t(2 * half);
+    for (int i = 0; i < half; ++i) {
+      t[2 * i] = static_cast<float>(std::cos(2.0 * kPi * i / L));
+      t[2 * i + 1] = static_cast<float>(-std::sin(2.0 * kPi * i / L));
+    }
+    float *d = nullptr;
+    *status = upload(ctx, &d, t.data(), t.size());
+    p = d;
+  }
+  if (*status) return nullptr;
+  ctx->twiddles[key] = p;
+  return p;
+}
+
+int32_t scratch(rsim_ctx *ctx, size_t bytes, void **out) {
+  if (ctx->scratch_bytes < bytes) {
+    dev_free(ctx, ctx->d_scratch);
+    ctx->d_scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    int32_t rc = dev_alloc(ctx, &ctx->d_scratch, bytes);
+    if (rc) return rc;
+    ctx->scratch_bytes = bytes;
+  }
+  *out = ctx->d_scratch;
+  return RSIM_OK;
+}
+
+void stage_begin(rsim_ctx *ctx, bool on, int k, hipStream_t s) {
+  if (!on) return;
+  (void)hipEventRecord(ctx->ev0[k], s);
+  ctx->stage_ran[k] = true;
+}
+void stage_end(rsim_ctx *ctx, bool on, int k, hipStream_t s) {
+  if (on) (void)hipEventRecord(ctx->ev1[k], s);
+}
+void timing_reset(rsim_ctx *ctx, bool on) {
+  if (!on) return;
+  for (int k = 0; k < kStages; ++k) ctx->stage_ran[k] = false;
+  ctx->timing_pending = true;
+}
+
+int32_t check_radar(rsim_ctx *ctx) {
+  if (!ctx->have_wf) return fail(ctx, RSIM_ESTATE, "waveform not set");
+  if (!ctx->have_arr) return fail(ctx, RSIM_ESTATE, "array not set");
+  return RSIM_OK;
+}
+
+std::vector<DevScene> scene_views(rsim_ctx *ctx, const std::vector<int32_t> &ids, void *echo,
+                                  uint32_t *vis_mask, int precision, const EchoShape &sh) {
+  const RadarConst rc = radar_const(ctx);
+  const size_t csize = precision ? 16 : 8;
+  const int64_t cube = static_cast<int64_t>(sh.O) * rc.N * rc.M;
+  std::vector<DevScene> ds(ids.size());
+  int64_t mask_off = 0;
+  for (size_t i = 0; i < ids.size(); ++i) {
+    SceneRec &sc = ctx->scenes[ids[i]];
+    uint32_t *mask = vis_mask ? vis_mask + mask_off : sc.d_mask;
+    mask_off += static_cast<int64_t>(rc.N) * ((sc.n_facets + 31) / 32);
+    ds[i] = dev_scene(sc, mask, static_cast<char *>(echo) + i * cube * csize);
+  }
+  return ds;
+}
+
+// Upload (synchronously, after draining `s`) the tables of a persistent launch unless the
+// same tables are already resident.
+int32_t prepare_batch(rsim_ctx *ctx, BatchTables &bt, const std::vector<int32_t> &ids,
+                      const std::vector<DevScene> &ds, void *echo, uint32_t *vis_mask,
+                      int precision, int mb, const EchoShape &sh, hipStream_t s) {
+  const RadarConst rc = radar_const(ctx);
+  if (bt.d_items && bt.ids == ids && bt.echo == echo && bt.mask == vis_mask &&
+      bt.version == ctx->version && bt.mb == mb && bt.precision == precision)
+    return RSIM_OK;
+  std::vector<int> order(ds.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ds[a].n_facets + ds[a].n_points > ds[b].n_facets + ds[b].n_points;
+  });
+  std::vector<int4> items;
+  items.reserve(order.size() * rc.N * sh.m_tiles * sh.o_tiles);
+  for (int si : order)
+    for (int n = 0; n < rc.N; ++n)
+      for (int mt = 0; mt < sh.m_tiles; ++mt)
+        for (int ot = 0; ot < sh.o_tiles; ++ot) items.push_back(make_int4(si, n, mt, ot));
+  HIP_TRY(ctx, hipStreamSynchronize(s));  // a previous launch may still read the tables
+  if (bt.scenes_cap < ds.size()) {
+    dev_free(ctx, bt.d_scenes);
+    bt.d_scenes = nullptr;
+    bt.scenes_cap = 0;
+    int32_t r = dev_alloc(ctx, reinterpret_cast<void **>(&bt.d_scenes), sizeof(DevScene) * ds.size());
+    if (r) return r;
+    bt.scenes_cap = ds.size();
+  }
+  if (bt.items_cap < items.size()) {
+    dev_free(ctx, bt.d_items);
+    bt.d_items = nullptr;
+    bt.items_cap = 0;
+    int32_t r = dev_alloc(ctx, reinterpret_cast<void **>(&bt.d_items), sizeof(int4) * items.size());
+    if (r) return r;
+    bt.items_cap = items.size();
+  }
+  if (!bt.d_queue) {
+    int32_t r = dev_alloc(ctx, reinterpret_cast<void **>(&bt.d_queue), 64);
+    if (r) return r;
+  }
+  HIP_TRY(ctx, hipMemcpy(bt.d_scenes, ds.data(), sizeof(DevScene) * ds.size(), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(bt.d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice));
+  bt.n_items = static_cast<int32_t>(items.size());
+  bt.ids = ids;
+  bt.echo = echo;
+  bt.mask = vis_mask;
+  bt.version = ctx->version;
+  bt.mb = mb;
+  bt.precision = precision;
+  return RSIM_OK;
+}
+
+// Enqueue visibility + compaction + facet sum (kernels only; capturable).
+int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const BatchTables *bt,
+                          hipStream_t s, const rsim_opts &o, bool timing) {
+  const RadarConst rc = radar_const(ctx);
+  const int precision = o.precision;
+  const TunedShape ts = pick_shape(ctx, precision, o);
+  const EchoShape sh = echo_shape(ctx, rc, ts.mb);
+  if (o.mask_mode == RSIM_MASK_COMPUTE) {
+    stage_begin(ctx, timing, 0, s);
+    for (auto &d : ds) HIP_TRY(ctx, launch_visibility(d, rc, s));
+    stage_end(ctx, timing, 0, s);
+  }
+  stage_begin(ctx, timing, 1, s);
+  for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, rc.N, s));
+  stage_end(ctx, timing, 1, s);
+  stage_begin(ctx, timing, 2, s);
+  if (bt) {
+    int per_cu = 0;
+    HIP_TRY(ctx, echo_occupancy(precision, ts.mb, ts.ft, sh, &per_cu));
+    const int groups = std::max(1, per_cu) * ctx->cu_count;
+    HIP_TRY(ctx, launch_echo_persistent(precision, ts.mb, ts.ft, bt->d_scenes, bt->d_items,
+                                        bt->n_items, bt->d_queue, rc, ctx->d_elem, sh, groups, s));
+  } else {
+    for (auto &d : ds)
+      HIP_TRY(ctx, launch_echo_plain(precision, ts.mb, ts.ft, d, rc, ctx->d_elem, sh, s));
+  }
+  stage_end(ctx, timing, 2, s);
+  return RSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rsim_abi_version(void) { return RSIM_ABI_VERSION; }
+
+int32_t rsim_create(int32_t hip_device, rsim_ctx **out) {
+  if (!out) return fail(nullptr, RSIM_EINVAL, "rsim_create: out is NULL");
+  *out = nullptr;
+  std::unique_ptr<rsim_ctx> ctx(new rsim_ctx());
+  if (hip_device == -1) {
+    ctx->host_only = true;
+    *out = ctx.release();
+    return RSIM_OK;
+  }
+  if (hip_device < 0) return fail(nullptr, RSIM_EINVAL, "rsim_create: bad device %d", hip_device);
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0)
+    return fail(nullptr, RSIM_EDEVICE, "rsim_create: no HIP device (%s)",
+                e != hipSuccess ? hipGetErrorString(e) : "count = 0");
+  if (hip_device >= count)
+    return fail(nullptr, RSIM_EDEVICE, "rsim_create: device %d of %d", hip_device, count);
+  if ((e = hipSetDevice(hip_device)) != hipSuccess)
+    return fail(nullptr, RSIM_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, hip_device)) != hipSuccess)
+    return fail(nullptr, RSIM_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  ctx->device = hip_device;
+  ctx->host_only = false;
+  ctx->cu_count = prop.multiProcessorCount;
+  ctx->max_lds = prop.sharedMemPerBlock;
+  for (int k = 0; k < kStages; ++k) {
+    if (hipEventCreate(&ctx->ev0[k]) != hipSuccess || hipEventCreate(&ctx->ev1[k]) != hipSuccess)
+      return fail(nullptr, RSIM_EDEVICE, "hipEventCreate failed");
+  }
+  if ((e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+    return fail(nullptr, RSIM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+  *out = ctx.release();
+  return RSIM_OK;
+}
+
+void rsim_destroy(rsim_ctx *ctx) {
+  if (!ctx) return;
+  if (!ctx->host_only) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->graph.exec) (void)hipGraphExecDestroy(ctx->graph.exec);
+    if (ctx->graph.graph) (void)hipGraphDestroy(ctx->graph.graph);
+    for (auto &kv : ctx->allocs) (void)hipFree(kv.first);
+    for (int k = 0; k < kStages; ++k) {
+      if (ctx->ev0[k]) (void)hipEventDestroy(ctx->ev0[k]);
+      if (ctx->ev1[k]) (void)hipEventDestroy(ctx->ev1[k]);
+    }
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  }
+  delete ctx;
+}
+
+const char *rsim_last_error(const rsim_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_thread_error.c_str();
+}
+
+int32_t rsim_set_mem_limit(rsim_ctx *ctx, uint64_t bytes) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  ctx->mem_limit = bytes;
+  return RSIM_OK;
+}
+
+int32_t rsim_load_mesh(rsim_ctx *ctx, const float *verts_xyz, int64_t n_verts, const int32_t *tris,
+                       int64_t n_tris, int32_t *mesh_id) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!mesh_id || n_verts < 0 || n_tris < 0 || (n_verts && !verts_xyz) || (n_tris && !tris))
+    return fail(ctx, RSIM_EINVAL, "rsim_load_mesh: bad pointer or count");
+  if (n_tris > (int64_t(1) << 26) || n_verts > (int64_t(1) << 31) - 1)
+    return fail(ctx, RSIM_ERANGE, "rsim_load_mesh: %lld triangles exceed 2^26", (long long)n_tris);
+  for (int64_t i = 0; i < 3 * n_verts; ++i)
+    if (!std::isfinite(verts_xyz[i]))
+      return fail(ctx, RSIM_EINVAL, "rsim_load_mesh: vertex coordinate %lld is not finite", (long long)i);
+  for (int64_t i = 0; i < 3 * n_tris; ++i)
+    if (tris[i] < 0 || tris[i] >= n_verts)
+      return fail(ctx, RSIM_EINVAL, "rsim_load_mesh: triangle index %lld = %d out of range", (long long)i, tris[i]);
+  MeshRec m;
+  m.verts.assign(verts_xyz, verts_xyz + 3 * n_verts);
+  m.tris.assign(tris, tris + 3 * n_tris);
+  for (int k = 0; k < 3; ++k) {
+    m.box_lo[k] = 0;
+    m.box_hi[k] = 0;
+  }
+  bool first = true;
+  for (int64_t t = 0; t < 3 * n_tris; ++t) {
+    const float *v = &m.verts[3 * static_cast<int64_t>(m.tris[t])];
+    for (int k = 0; k < 3; ++k) {
+      if (first || v[k] < m.box_lo[k]) m.box_lo[k] = v[k];
+      if (first || v[k] > m.box_hi[k]) m.box_hi[k] = v[k];
+    }
+    first = false;
+  }
+  std::vector<BvhNode> nodes;
+  std::vector<float> leaf;
+  m.depth = build_bvh(m.verts.data(), m.tris.data(), n_tris, nodes, leaf);
+  if (m.depth >= kBvhStack)
+    return fail(ctx, RSIM_ERANGE, "rsim_load_mesh: BVH depth %d exceeds %d", m.depth, kBvhStack);
+  m.n_nodes = static_cast<int64_t>(nodes.size());
+  m.n_leaf = static_cast<int64_t>(leaf.size() / 12);
+  if (!ctx->host_only) {
+    int32_t rc = need_device(ctx);
+    if (rc) return rc;
+    float *dv = nullptr;
+    int32_t *dt = nullptr;
+    BvhNode *dn = nullptr;
+    float *dl = nullptr;
+    if ((rc = upload(ctx, &dv, m.verts.data(), m.verts.size()))) return rc;
+    if ((rc = upload(ctx, &dt, m.tris.data(), m.tris.size()))) return rc;
+    if ((rc = upload(ctx, &dn, nodes.data(), nodes.size()))) return rc;
+    if ((rc = upload(ctx, &dl, leaf.data(), leaf.size()))) return rc;
+    m.d_verts = dv;
+    m.d_tris = dt;
+    m.d_nodes = dn;
+    m.d_leaf = dl;
+  }
+  ctx->meshes.push_back(std::move(m));
+  *mesh_id = static_cast<int32_t>(ctx->meshes.size() - 1);
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_create_scene(rsim_ctx *ctx, int32_t *scene_id) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!scene_id) return fail(ctx, RSIM_EINVAL, "scene_id is NULL");
+  ctx->scenes.emplace_back();
+  *scene_id = static_cast<int32_t>(ctx->scenes.size() - 1);
+  ctx->version++;
+  return RSIM_OK;
+}
+
+static int32_t check_scene(rsim_ctx *ctx, int32_t scene_id) {
+  if (scene_id < 0 || scene_id >= static_cast<int32_t>(ctx->scenes.size()))
+    return fail(ctx, RSIM_EINVAL, "unknown scene id %d", scene_id);
+  return RSIM_OK;
+}
+
+int32_t rsim_add_instance(rsim_ctx *ctx, int32_t scene_id, int32_t mesh_id, const double rot[9],
+                          const double pos0[3], const double vel[3], int32_t *inst_id) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  int32_t rc = check_scene(ctx, scene_id);
+  if (rc) return rc;
+  if (mesh_id < 0 || mesh_id >= static_cast<int32_t>(ctx->meshes.size()))
+    return fail(ctx, RSIM_EINVAL, "unknown mesh id %d", mesh_id);
+  if (!rot || !pos0 || !vel) return fail(ctx, RSIM_EINVAL, "rsim_add_instance: NULL argument");
+  if (!finite_all(rot, 9) || !finite_all(pos0, 3) || !finite_all(vel, 3))
+    return fail(ctx, RSIM_EINVAL, "rsim_add_instance: non-finite pose");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double d = 0;
+      for (int k = 0; k < 3; ++k) d += rot[3 * k + i] * rot[3 * k + j];
+      if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-6)
+        return fail(ctx, RSIM_EINVAL, "rsim_add_instance: rotation is not orthonormal");
+    }
+  SceneRec &sc = ctx->scenes[scene_id];
+  if (sc.inst.size() >= 4096) return fail(ctx, RSIM_ERANGE, "more than 4096 instances");
+  InstRec r;
+  r.mesh = mesh_id;
+  std::memcpy(r.rot, rot, sizeof(r.rot));
+  std::memcpy(r.pos0, pos0, sizeof(r.pos0));
+  std::memcpy(r.vel, vel, sizeof(r.vel));
+  sc.inst.push_back(r);
+  sc.n_facets += static_cast<int64_t>(ctx->meshes[mesh_id].tris.size() / 3);
+  if (sc.n_facets > (int64_t(1) << 30)) return fail(ctx, RSIM_ERANGE, "scene exceeds 2^30 facets");
+  sc.dirty = true;
+  ctx->version++;
+  if (inst_id) *inst_id = static_cast<int32_t>(sc.inst.size() - 1);
+  return RSIM_OK;
+}
+
+int32_t rsim_add_points(rsim_ctx *ctx, int32_t scene_id, const double *pos0, const double *vel,
+                        const double *amp_re_im, int64_t n) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  int32_t rc = check_scene(ctx, scene_id);
+  if (rc) return rc;
+  if (n < 0 || (n && (!pos0 || !vel || !amp_re_im)))
+    return fail(ctx, RSIM_EINVAL, "rsim_add_points: bad pointer or count");
+  if (!finite_all(pos0, 3 * n) || !finite_all(vel, 3 * n) || !finite_all(amp_re_im, 2 * n))
+    return fail(ctx, RSIM_EINVAL, "rsim_add_points: non-finite input");
+  SceneRec &sc = ctx->scenes[scene_id];
+  if (sc.pt_amp.size() / 2 + n > (1 << 24)) return fail(ctx, RSIM_ERANGE, "too many points");
+  sc.pt_pos.insert(sc.pt_pos.end(), pos0, pos0 + 3 * n);
+  sc.pt_vel.insert(sc.pt_vel.end(), vel, vel + 3 * n);
+  sc.pt_amp.insert(sc.pt_amp.end(), amp_re_im, amp_re_im + 2 * n);
+  sc.dirty = true;
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_scene_info(rsim_ctx *ctx, int32_t scene_id, int64_t *n_facets, int64_t *mask_words) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  int32_t rc = check_scene(ctx, scene_id);
+  if (rc) return rc;
+  const SceneRec &sc = ctx->scenes[scene_id];
+  if (n_facets) *n_facets = sc.n_facets;
+  if (mask_words) *mask_words = (sc.n_facets + 31) / 32;
+  return RSIM_OK;
+}
+
+int32_t rsim_set_waveform(rsim_ctx *ctx, const rsim_waveform *wf) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!wf) return fail(ctx, RSIM_EINVAL, "waveform is NULL");
+  const double v[4] = {wf->f0_hz, wf->slope_hz_per_s, wf->fs_hz, wf->chirp_period_s};
+  if (!finite_all(v, 4) || wf->f0_hz <= 0 || wf->fs_hz <= 0 || wf->chirp_period_s <= 0 ||
+      wf->slope_hz_per_s == 0)
+    return fail(ctx, RSIM_EINVAL, "rsim_set_waveform: f0, fs, chirp period must be > 0, slope != 0");
+  if (wf->n_samples < 1 || wf->n_samples > 4096 || wf->n_chirps < 1 || wf->n_chirps > 4096)
+    return fail(ctx, RSIM_ERANGE, "rsim_set_waveform: M and N must be in 1..4096");
+  ctx->wf = *wf;
+  ctx->have_wf = true;
+  for (auto &sc : ctx->scenes) sc.buf_N = sc.buf_N == wf->n_chirps ? sc.buf_N : -1;
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx, const double *rx_xyz,
+                       int32_t n_rx) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!tx_xyz || !rx_xyz) return fail(ctx, RSIM_EINVAL, "rsim_set_array: NULL positions");
+  if (n_tx < 1 || n_tx > 64 || n_rx < 1 || n_rx > 64)
+    return fail(ctx, RSIM_ERANGE, "rsim_set_array: 1..64 Tx and 1..64 Rx elements");
+  if (!finite_all(tx_xyz, 3 * n_tx) || !finite_all(rx_xyz, 3 * n_rx))
+    return fail(ctx, RSIM_EINVAL, "rsim_set_array: non-finite position");
+  ctx->tx.assign(tx_xyz, tx_xyz + 3 * n_tx);
+  ctx->rx.assign(rx_xyz, rx_xyz + 3 * n_rx);
+  if (!ctx->host_only) {
+    int32_t rc = need_device(ctx);
+    if (rc) return rc;
+    dev_free(ctx, ctx->d_elem);
+    ctx->d_elem = nullptr;
+    std::vector<double> e(ctx->tx);
+    e.insert(e.end(), ctx->rx.begin(), ctx->rx.end());
+    if ((rc = upload(ctx, &ctx->d_elem, e.data(), e.size()))) return rc;
+  }
+  ctx->have_arr = true;
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes, void *echo,
+                        uint32_t *vis_mask, void *hip_stream, const rsim_opts *opts) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  rsim_opts o{};
+  if (opts) o = *opts;
+  if (!scene_ids || n_scenes < 1 || !echo)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: need scene ids and an echo buffer");
+  if (o.precision != RSIM_FP32_PHASE64 && o.precision != RSIM_FP64)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: unknown precision %d", o.precision);
+  if (o.mask_mode != RSIM_MASK_COMPUTE && o.mask_mode != RSIM_MASK_INPUT)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: unknown mask mode %d", o.mask_mode);
+  if (o.mask_mode == RSIM_MASK_INPUT && !vis_mask)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: RSIM_MASK_INPUT needs vis_mask");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  std::vector<int32_t> ids(scene_ids, scene_ids + n_scenes);
+  for (int32_t id : ids)
+    if ((rc = check_scene(ctx, id))) return rc;
+  const RadarConst rcn = radar_const(ctx);
+  const double eps = cross_term_bound(ctx, rcn);
+  if (eps > 1e-3)
+    return fail(ctx, RSIM_ERANGE,
+                "array aperture too large: |2 pi slope d_p e_q| may reach %.3g rad (limit 1e-3)", eps);
+  const TunedShape ts = pick_shape(ctx, o.precision, o);
+  if (!echo_variant_exists(o.precision, ts.mb, ts.ft))
+    return fail(ctx, RSIM_EINVAL, "no facet-sum variant with tile_m=%d tile_f=%d", ts.mb, ts.ft);
+  if ((rc = need_device(ctx))) return rc;
+  const EchoShape sh = echo_shape(ctx, rcn, ts.mb);
+  if (echo_smem_bytes(o.precision, ts.mb, ts.ft, sh) > ctx->max_lds)
+    return fail(ctx, RSIM_ERANGE, "facet-sum tile needs %zu bytes of LDS (max %zu)",
+                echo_smem_bytes(o.precision, ts.mb, ts.ft, sh), ctx->max_lds);
+  for (int32_t id : ids)
+    if ((rc = ensure_scene_device(ctx, ctx->scenes[id]))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool timing = o.timing != 0;
+  timing_reset(ctx, timing);
+  const std::vector<DevScene> ds = scene_views(ctx, ids, echo, vis_mask, o.precision, sh);
+  if (o.use_graph) {
+    // Capture once per (scenes, buffers, options, scene/radar version); replay after.
+    GraphCache &g = ctx->graph;
+    const bool hit = g.valid && g.ids == ids && g.echo == echo && g.mask == vis_mask &&
+                     g.version == ctx->version && std::memcmp(&g.opts, &o, sizeof(o)) == 0;
+    if (!hit) {
+      HIP_TRY(ctx, hipStreamSynchronize(s));  // an older replay may still be running
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+      g.exec = nullptr;
+      g.graph = nullptr;
+      g.valid = false;
+      if (o.persistent &&
+          (rc = prepare_batch(ctx, g.tables, ids, ds, echo, vis_mask, o.precision, ts.mb, sh, s)))
+        return rc;
+      HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed));
+      int32_t rc2 = enqueue_synthesis(ctx, ds, o.persistent ? &g.tables : nullptr,
+                                      ctx->capture_stream, o, false);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+      if (rc2) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc2;
+      }
+      if (e != hipSuccess) return fail(ctx, RSIM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(ctx, RSIM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
+      g.graph = graph;
+      g.valid = true;
+      g.ids = ids;
+      g.echo = echo;
+      g.mask = vis_mask;
+      g.version = ctx->version;
+      g.opts = o;
+    }
+    stage_begin(ctx, timing, 2, s);
+    HIP_TRY(ctx, hipGraphLaunch(g.exec, s));
+    stage_end(ctx, timing, 2, s);
+    return RSIM_OK;
+  }
+  if (o.persistent &&
+      (rc = prepare_batch(ctx, ctx->batch, ids, ds, echo, vis_mask, o.precision, ts.mb, sh, s)))
+    return rc;
+  return enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing);
+}
+
+int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
+                      const uint32_t *vis_mask, float *const *grad_verts, int32_t n_meshes,
+                      double *grad_vel, void *hip_stream) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  (void)scene_id; (void)grad_echo; (void)vis_mask; (void)grad_verts; (void)n_meshes;
+  (void)grad_vel; (void)hip_stream;
+  return fail(ctx, RSIM_ESTATE, "rsim_backward: adjoint not built yet");
+}
+
+int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm, void *y_opt,
+                      void *hip_stream, const rsim_opts *opts) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  rsim_opts o{};
+  if (opts) o = *opts;
+  if (!echo || n_cubes < 1 || (!rdm && !y_opt))
+    return fail(ctx, RSIM_EINVAL, "rsim_form_rdm: need echo, n_cubes >= 1 and an output");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
+  if (!is_pow2(M) || !is_pow2(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_form_rdm: M=%d and N=%d must be powers of two in 2..4096", M, N);
+  if ((rc = need_device(ctx))) return rc;
+  const int precision = o.precision ? 1 : 0;
+  const size_t csize = precision ? 16 : 8;
+  const int64_t O = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3);
+  const int64_t planes = O * n_cubes;
+  const size_t need_lds = 2 * csize * (std::max(M, N) + 32);
+  if (need_lds > ctx->max_lds) return fail(ctx, RSIM_ERANGE, "FFT length exceeds LDS");
+  void *X = nullptr;
+  if ((rc = scratch(ctx, csize * planes * N * M, &X))) return rc;
+  void *twM = twiddles(ctx, M, precision, &rc);
+  if (rc) return rc;
+  void *twN = twiddles(ctx, N, precision, &rc);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool timing = o.timing != 0;
+  if (timing && !ctx->timing_pending) timing_reset(ctx, true);
+  stage_begin(ctx, timing, 3, s);
+  HIP_TRY(ctx, launch_range_fft(precision, echo, X, planes * N, M, 1, twM, s));
+  stage_end(ctx, timing, 3, s);
+  stage_begin(ctx, timing, 4, s);
+  HIP_TRY(ctx, launch_doppler_fft(precision, X, y_opt, rdm, planes, N, M, 0, twN, s));
+  stage_end(ctx, timing, 4, s);
+  return RSIM_OK;
+}
+
+int32_t rsim_rdm_adjoint(rsim_ctx *ctx, const void *grad_y, int32_t n_cubes, void *grad_echo,
+                         void *hip_stream) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!grad_y || !grad_echo || n_cubes < 1)
+    return fail(ctx, RSIM_EINVAL, "rsim_rdm_adjoint: need grad_y, grad_echo and n_cubes >= 1");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
+  if (!is_pow2(M) || !is_pow2(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_rdm_adjoint: M and N must be powers of two");
+  if ((rc = need_device(ctx))) return rc;
+  const int64_t O = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3);
+  const int64_t planes = O * n_cubes;
+  void *Z = nullptr;
+  if ((rc = scratch(ctx, 8 * planes * N * M, &Z))) return rc;
+  void *twM = twiddles(ctx, M, 0, &rc);
+  if (rc) return rc;
+  void *twN = twiddles(ctx, N, 0, &rc);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // G_H = FFT_m(FFT_n(conj(unshift_n(G_Y)))) for X = FFT_m(conj H), Y = shift FFT_n(X)
+  HIP_TRY(ctx, launch_doppler_fft(0, grad_y, Z, nullptr, planes, N, M, 1, twN, s));
+  HIP_TRY(ctx, launch_range_fft(0, Z, grad_echo, planes * N, M, 0, twM, s));
+  return RSIM_OK;
+}
+
+int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!ms || n_stages < 1 || n_stages > kStages)
+    return fail(ctx, RSIM_EINVAL, "rsim_last_timings: n_stages must be 1..%d", kStages);
+  if (ctx->host_only) return fail(ctx, RSIM_EDEVICE, "host-only context");
+  for (int k = 0; k < n_stages; ++k) {
+    ms[k] = 0.0f;
+    if (!ctx->stage_ran[k]) continue;
+    HIP_TRY(ctx, hipEventSynchronize(ctx->ev1[k]));
+    float v = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&v, ctx->ev0[k], ctx->ev1[k]));
+    ms[k] = v;
+  }
+  ctx->timing_pending = false;
+  return RSIM_OK;
+}
+
+int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
+                      const char *cache_json_path) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!scene_ids || n_scenes < 1) return fail(ctx, RSIM_EINVAL, "rsim_autotune: no scenes");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  if ((rc = need_device(ctx))) return rc;
+  const RadarConst rcn = radar_const(ctx);
+  const int O = rcn.P * rcn.Q;
+  const int64_t cube = static_cast<int64_t>(O) * rcn.N * rcn.M;
+  void *echo = nullptr;
+  if ((rc = dev_alloc(ctx, &echo, 8 * cube * n_scenes))) return rc;
+  struct Cand { int mb, ft; };
+  const Cand cands[] = {{16, 16}, {32, 8}, {32, 16}, {32, 32}, {64, 8}, {64, 16}};
+  float best = 1e30f;
+  TunedShape best_s{32, 16};
+  hipStream_t s = ctx->capture_stream;
+  for (const Cand &c : cands) {
+    rsim_opts o{};
+    o.tile_m = c.mb;
+    o.tile_f = c.ft;
+    o.timing = 1;
+    const EchoShape sh = echo_shape(ctx, rcn, c.mb);
+    if (echo_smem_bytes(0, c.mb, c.ft, sh) > ctx->max_lds) continue;
+    float total = 0.0f;
+    for (int rep = 0; rep < 3; ++rep) {
+      if ((rc = rsim_synthesize(ctx, scene_ids, n_scenes, echo, nullptr, s, &o))) {
+        dev_free(ctx, echo);
+        return rc;
+      }
+      float ms[kStages];
+      if ((rc = rsim_last_timings(ctx, ms, kStages))) {
+        dev_free(ctx, echo);
+        return rc;
+      }
+      if (rep > 0) total += ms[2];  // first run warms up
+    }
+    if (total < best) {
+      best = total;
+      best_s = TunedShape{c.mb, c.ft};
+    }
+  }
+  dev_free(ctx, echo);
+  ctx->tuned[std::make_tuple(rcn.M, O, 0)] = best_s;
+  ctx->version++;
+  if (cache_json_path) {
+    std::ofstream f(cache_json_path, std::ios::app);
+    if (!f) return fail(ctx, RSIM_EINVAL, "cannot open %s", cache_json_path);
+    f << "{\"arch\": \"gfx950\", \"M\": " << rcn.M << ", \"O\": " << O
+      << ", \"precision\": \"fp32\", \"tile_m\": " << best_s.mb << ", \"tile_f\": " << best_s.ft
+      << ", \"facet_sum_ms\": " << best / 2 << "}\n";
+  }
+  return RSIM_OK;
+}
+
+int32_t rsim_sync(rsim_ctx *ctx, void *hip_stream) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  int32_t rc = need_device(ctx);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)));
+  return RSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,521 @@
+// Coherent facet sum: the echo frequency response H[o, n, m] (Sections 2.2, 3.2;
+// eqs. (7), (9)-(13)) for every lit facet of chirp n, frequency sample m and
+// virtual channel o = p Q + q:
+//
+//   H[o,n,m] = sum_f G_f(m) U_fp(m) U_fq(m) exp(+j 2 pi slope d_p e_q)
+//   G_f(m)   = j o_f A_f Phi(k_m b_f) / (2 pi)          (closed-form facet integral)
+//   U_fe(m)  = exp(-j 2 pi psi_e(m)) / R_e,  psi_e(m) = psi_e(0) + m df tau_e
+//
+// which regroups f_m tau - slope tau^2 / 2 (tau = tau_p + tau_q) exactly into a Tx
+// part, an Rx part and the cross term slope d_p e_q, where d_p, e_q are the element
+// delays relative to the phase-centre delays (|2 pi slope d_p e_q| is ~1e-5 rad for
+// the arrays here; it is applied as a short Taylor polynomial, exact to rounding).
+//
+// Work split (one item = chirp n x sample tile x channel tile): a workgroup holds
+// O_w channels x B_w sample blocks; thread (o, b) keeps MB consecutive samples of one
+// channel in registers and advances its phasor from sample to sample with one complex
+// multiply (phase linear in m under stop-and-hop). Per tile of FT lit facets the
+// workgroup stages through LDS, in FP64: facet geometry, element distances, phases
+// reduced to turns (the only FP64 arithmetic of the sum); then G_f(m) for the tile's
+// samples and each element's phasor at every block start. Block starts are re-seeded
+// from FP64 phases, so the recurrence never runs more than MB steps.
+#include "rsim_internal.h"
+#include "rsim_launch.h"
+
+namespace rsim {
+
+template <typename R>
+struct Cx;
+template <>
+struct Cx<float> {
+  using T = float2;
+};
+template <>
+struct Cx<double> {
+  using T = double2;
+};
+
+template <typename R>
+struct EchoTraits;
+template <>
+struct EchoTraits<float> {
+  static constexpr int kSeriesTerms = 8;
+};
+template <>
+struct EchoTraits<double> {
+  static constexpr int kSeriesTerms = 16;
+};
+constexpr double kSeriesGap = 0.5;  // radians: series below, divided-difference form above
+
+struct alignas(8) Geo {
+  double c[3];        // centroid (world) at t_n
+  double tref_t, tref_r;
+  double beta[3];     // w . (x_i - c), metres
+  double amp_re, amp_im;  // G = amp * Phi
+  int32_t valid, pad;
+};
+
+__device__ inline void sincospi_t(float x, float *s, float *c) { sincospif(x, s, c); }
+__device__ inline void sincospi_t(double x, double *s, double *c) { sincospi(x, s, c); }
+
+// exp(-j 2 pi turns) * scale, with the FP64 phase reduced before the conversion.
+template <typename R>
+__device__ inline typename Cx<R>::T phasor_m2pi(double turns, R scale) {
+  const double r = turns - rint(turns);
+  R s, c;
+  sincospi_t(static_cast<R>(2.0 * r), &s, &c);
+  return {c * scale, -s * scale};
+}
+
+// First divided difference of -exp(jx) at nodes given in turns X, Y:
+// -j exp(j pi (X + Y)) sinc(pi (Y - X)).
+template <typename R>
+__device__ inline typename Cx<R>::T first_dd(double X, double Y) {
+  const double S = X + Y;
+  const double D = Y - X;
+  R cs, sn;
+  sincospi_t(static_cast<R>(S - 2.0 * rint(0.5 * S)), &sn, &cs);
+  R sc = R(1);
+  if (D != 0.0) {
+    R s_d, c_d;
+    sincospi_t(static_cast<R>(D - 2.0 * rint(0.5 * D)), &s_d, &c_d);
+    sc = s_d / static_cast<R>(kPi * D);
+  }
+  return {sn * sc, -cs * sc};
+}
+
+// Phi(a0, a1, a2): second divided difference of -exp(jx); nodes in turns (a = 2 pi A).
+template <typename R>
+__device__ typename Cx<R>::T phi_turns(double A0, double A1, double A2) {
+  using C = typename Cx<R>::T;
+  const double mean = (A0 + A1 + A2) / 3.0;
+  const double B0 = A0 - mean, B1 = A1 - mean, B2 = A2 - mean;
+  const double g12 = fabs(B1 - B2), g02 = fabs(B0 - B2), g01 = fabs(B0 - B1);
+  double Bl, Bi, Bj, gmax;
+  if (g12 >= g02 && g12 >= g01) {
+    Bl = B0; Bi = B1; Bj = B2; gmax = g12;
+  } else if (g02 >= g01) {
+    Bl = B1; Bi = B0; Bj = B2; gmax = g02;
+  } else {
+    Bl = B2; Bi = B0; Bj = B1; gmax = g01;
+  }
+  C phi0;
+  if (2.0 * kPi * gmax < kSeriesGap) {
+    // Taylor series about the mean: sum_n j^n h_n(b) / (n+2)!, h_n by the
+    // recurrence h_n = e1 h_{n-1} - e2 h_{n-2} + e3 h_{n-3}.
+    const R b0 = static_cast<R>(2.0 * kPi * B0);
+    const R b1 = static_cast<R>(2.0 * kPi * B1);
+    const R b2 = static_cast<R>(2.0 * kPi * B2);
+    const R e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
+    R hm3 = 0, hm2 = 0, hm1 = 1;  // h_{n-3}, h_{n-2}, h_{n-1} with h_0 = 1
+    R re = R(0.5), im = 0;        // n = 0 term: 1/2!
+    R inv_fact = R(0.5);
+    for (int n = 1; n <= EchoTraits<R>::kSeriesTerms; ++n) {
+      const R h = e1 * hm1 - e2 * hm2 + e3 * hm3;
+      hm3 = hm2;
+      hm2 = hm1;
+      hm1 = h;
+      inv_fact = inv_fact / static_cast<R>(n + 2);
+      const R term = h * inv_fact;
+      switch (n & 3) {  // j^n
+        case 0: re += term; break;
+        case 1: im += term; break;
+        case 2: re -= term; break;
+        default: im -= term; break;
+      }
+    }
+    phi0 = {re, im};
+  } else {
+    const C fj = first_dd<R>(Bl, Bj);
+    const C fi = first_dd<R>(Bl, Bi);
+    const R inv = static_cast<R>(1.0 / (2.0 * kPi * (Bj - Bi)));
+    phi0 = {(fj.x - fi.x) * inv, (fj.y - fi.y) * inv};
+  }
+  // shift back by the mean: Phi(a) = exp(j mean) Phi(a - mean)
+  R ms, mc;
+  const double mr = mean - rint(mean);
+  sincospi_t(static_cast<R>(2.0 * mr), &ms, &mc);
+  return {phi0.x * mc - phi0.y * ms, phi0.x * ms + phi0.y * mc};
+}
+
+__device__ inline int find_inst(const DevInstance *inst, int n_inst, int64_t f) {
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].facet_base <= f)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// FP64 geometry of work entry `item` of chirp n (lit facet, or point after them).
+__device__ void entry_geometry(const DevScene &sc, const RadarConst &rc, int n, int32_t cnt,
+                               int32_t item, Geo &g) {
+  const double t = n * rc.tc;
+  const double inv_c = 1.0 / kC0;
+  double c[3];
+  if (item < cnt) {
+    const int64_t f = sc.vis_idx[static_cast<int64_t>(n) * sc.n_facets + item];
+    const int ii = find_inst(sc.inst, sc.n_inst, f);
+    const DevInstance &I = sc.inst[ii];
+    const int64_t lt = f - I.facet_base;
+    double x[3][3];
+    for (int v = 0; v < 3; ++v) {
+      const int32_t vi = I.tris[3 * lt + v];
+      const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
+      for (int k = 0; k < 3; ++k)
+        x[v][k] = I.rot[3 * k + 0] * b0 + I.rot[3 * k + 1] * b1 + I.rot[3 * k + 2] * b2 +
+                  (I.pos0[k] + I.vel[k] * t);
+    }
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
+      e1[k] = x[1][k] - x[0][k];
+      e2[k] = x[2][k] - x[0][k];
+    }
+    double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                    e1[0] * e2[1] - e1[1] * e2[0]};
+    const double two_area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    double ut[3], ur[3];
+    for (int k = 0; k < 3; ++k) {
+      ut[k] = rc.tx_c[k] - c[k];
+      ur[k] = rc.rx_c[k] - c[k];
+    }
+    const double rt = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+    const double rr = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
+    double w[3];
+    for (int k = 0; k < 3; ++k) w[k] = ut[k] / rt + ur[k] / rr;
+    const double obl = 0.5 * (nv[0] * w[0] + nv[1] * w[1] + nv[2] * w[2]) / two_area;
+    for (int v = 0; v < 3; ++v)
+      g.beta[v] = w[0] * (x[v][0] - c[0]) + w[1] * (x[v][1] - c[1]) + w[2] * (x[v][2] - c[2]);
+    // G = j o A Phi / (2 pi), A = two_area / 2
+    g.amp_re = 0.0;
+    g.amp_im = obl * 0.5 * two_area / (2.0 * kPi);
+    g.tref_t = rt * inv_c;
+    g.tref_r = rr * inv_c;
+    g.valid = two_area > 0.0;
+  } else {
+    const int32_t k = item - cnt;
+    for (int d = 0; d < 3; ++d) c[d] = sc.pt_pos0[3 * k + d] + sc.pt_vel[3 * k + d] * t;
+    double ut[3], ur[3];
+    for (int d = 0; d < 3; ++d) {
+      ut[d] = rc.tx_c[d] - c[d];
+      ur[d] = rc.rx_c[d] - c[d];
+    }
+    g.tref_t = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]) * inv_c;
+    g.tref_r = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]) * inv_c;
+    g.beta[0] = g.beta[1] = g.beta[2] = 0.0;
+    // Phi(0,0,0) = 1/2, so G = s / (4 pi) with amp = s / (2 pi)
+    g.amp_re = sc.pt_amp[2 * k + 0] / (2.0 * kPi);
+    g.amp_im = sc.pt_amp[2 * k + 1] / (2.0 * kPi);
+    g.valid = 1;
+  }
+  g.c[0] = c[0];
+  g.c[1] = c[1];
+  g.c[2] = c[2];
+}
+
+template <typename R, int MB, int FT>
+struct EchoSmem {
+  using C = typename Cx<R>::T;
+  double *elem;  // [E][3]
+  Geo *geo;      // [FT]
+  C *G;          // [FT][M_t]
+  C *U;          // [FT][E][B_w]
+  C *rat;        // [FT][E]
+  R *off;        // [FT][E]
+
+  __device__ void carve(unsigned char *base, const EchoShape &sh) {
+    size_t b = 0;
+    elem = reinterpret_cast<double *>(base + b);
+    b += sizeof(double) * 3 * sh.E;
+    b = (b + 15) & ~size_t(15);
+    geo = reinterpret_cast<Geo *>(base + b);
+    b += sizeof(Geo) * FT;
+    b = (b + 15) & ~size_t(15);
+    G = reinterpret_cast<C *>(base + b);
+    b += sizeof(C) * FT * sh.M_t;
+    U = reinterpret_cast<C *>(base + b);
+    b += sizeof(C) * FT * sh.E * sh.B_w;
+    rat = reinterpret_cast<C *>(base + b);
+    b += sizeof(C) * FT * sh.E;
+    off = reinterpret_cast<R *>(base + b);
+  }
+};
+
+template <typename R, int MB, int FT>
+__device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                          EchoSmem<R, MB, FT> &sm, int n, int mt, int ot) {
+  using C = typename Cx<R>::T;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int P = rc.P, Q = rc.Q, E = sh.E;
+  const int ol = tid % sh.O_w;
+  const int b = tid / sh.O_w;
+  const int o = ot * sh.O_w + ol;
+  const bool o_ok = o < sh.O;
+  const int p = o_ok ? o / Q : 0;
+  const int q = o_ok ? o % Q : 0;
+  const int m_tile0 = mt * sh.M_t;
+  const int m_base = m_tile0 + b * MB;
+  const int32_t cnt = sc.vis_cnt[n];
+  const int32_t total = cnt + sc.n_points;
+  const double slope = rc.slope;
+
+  C acc[MB];
+#pragma unroll
+  for (int j = 0; j < MB; ++j) acc[j] = {R(0), R(0)};
+
+  for (int32_t t0 = 0; t0 < total; t0 += FT) {
+    const int nf = min(FT, total - t0);
+    __syncthreads();  // previous tile fully consumed
+    // stage A: facet / point geometry (FP64)
+    for (int i = tid; i < FT; i += nthr) {
+      if (i < nf)
+        entry_geometry(sc, rc, n, cnt, t0 + i, sm.geo[i]);
+      else
+        sm.geo[i].valid = 0;
+    }
+    __syncthreads();
+    // stage B1: per element distance, phases in FP64 reduced to turns
+    for (int task = tid; task < FT * E; task += nthr) {
+      const int i = task / E, e = task % E;
+      const Geo &g = sm.geo[i];
+      C *Ue = sm.U + (i * E + e) * sh.B_w;
+      if (!g.valid) {
+        for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = {R(0), R(0)};
+        sm.rat[i * E + e] = {R(1), R(0)};
+        sm.off[i * E + e] = R(0);
+        continue;
+      }
+      const double dx = sm.elem[3 * e + 0] - g.c[0];
+      const double dy = sm.elem[3 * e + 1] - g.c[1];
+      const double dz = sm.elem[3 * e + 2] - g.c[2];
+      const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
+      const double tau = Rn / kC0;
+      double psi0, offv;
+      if (e < P) {
+        const double d = tau - g.tref_t;
+        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
+               0.5 * slope * g.tref_t * g.tref_r;
+        offv = sh.two_pi_slope * d;
+      } else {
+        const double d = tau - g.tref_r;
+        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
+               0.5 * slope * g.tref_t * g.tref_r;
+        offv = d;
+      }
+      psi0 -= floor(psi0);
+      double delta = rc.df * tau;
+      delta -= floor(delta);
+      const R inv_r = static_cast<R>(1.0 / Rn);
+      for (int bb = 0; bb < sh.B_w; ++bb) {
+        const double m0 = static_cast<double>(m_tile0 + bb * MB);
+        Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
+      }
+      sm.rat[i * E + e] = phasor_m2pi<R>(delta, R(1));
+      sm.off[i * E + e] = static_cast<R>(offv);
+    }
+    // stage B2: G_f(m) for the tile's samples
+    for (int task = tid; task < FT * sh.M_t; task += nthr) {
+      const int i = task / sh.M_t, j = task % sh.M_t;
+      const Geo &g = sm.geo[i];
+      C val = {R(0), R(0)};
+      if (g.valid) {
+        const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
+        const double s = fm / kC0;  // turns per metre
+        const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
+        const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
+        val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
+      }
+      sm.G[i * sh.M_t + j] = val;
+    }
+    __syncthreads();
+    // stage C: accumulate
+    if (o_ok) {
+      for (int i = 0; i < nf; ++i) {
+        const C up = sm.U[(i * E + p) * sh.B_w + b];
+        const C uq = sm.U[(i * E + P + q) * sh.B_w + b];
+        const C rp = sm.rat[i * E + p];
+        const C rq = sm.rat[i * E + P + q];
+        const R eps = sm.off[i * E + p] * sm.off[i * E + P + q];
+        // exp(j eps) to fourth order (|eps| <= 1e-3 is enforced on the host)
+        const R e2 = eps * eps;
+        const C ce = {R(1) - e2 * (R(0.5) - e2 * R(1.0 / 24.0)), eps * (R(1) - e2 * R(1.0 / 6.0))};
+        C z = {up.x * uq.x - up.y * uq.y, up.x * uq.y + up.y * uq.x};
+        z = {z.x * ce.x - z.y * ce.y, z.x * ce.y + z.y * ce.x};
+        const C r = {rp.x * rq.x - rp.y * rq.y, rp.x * rq.y + rp.y * rq.x};
+        const C *Gi = sm.G + i * sh.M_t + b * MB;
+#pragma unroll
+        for (int j = 0; j < MB; ++j) {
+          const C g = Gi[j];
+          acc[j].x += g.x * z.x - g.y * z.y;
+          acc[j].y += g.x * z.y + g.y * z.x;
+          const R zx = z.x * r.x - z.y * r.y;
+          z.y = z.x * r.y + z.y * r.x;
+          z.x = zx;
+        }
+      }
+    }
+  }
+  if (o_ok) {
+    C *out = static_cast<C *>(sc.echo) + (static_cast<int64_t>(o) * rc.N + n) * rc.M;
+#pragma unroll
+    for (int j = 0; j < MB; ++j)
+      if (m_base + j < rc.M) out[m_base + j] = acc[j];
+  }
+}
+
+template <typename R, int MB, int FT>
+__global__ void __launch_bounds__(512) echo_kernel(DevScene sc, RadarConst rc, const double *elem,
+                                                   EchoShape sh) {
+  extern __shared__ __align__(16) unsigned char echo_smem[];
+  EchoSmem<R, MB, FT> sm;
+  sm.carve(echo_smem, sh);
+  for (int i = threadIdx.x; i < 3 * sh.E; i += blockDim.x) sm.elem[i] = elem[i];
+  const int per_chirp = sh.m_tiles * sh.o_tiles;
+  const int n = blockIdx.x / per_chirp;
+  const int r = blockIdx.x % per_chirp;
+  echo_item<R, MB, FT>(sc, rc, sh, sm, n, r / sh.o_tiles, r % sh.o_tiles);
+}
+
+// Persistent form: a grid sized to the machine drains a queue of work items
+// (scene, chirp, sample tile, channel tile), ordered longest-first by the host.
+template <typename R, int MB, int FT>
+__global__ void __launch_bounds__(512) echo_persistent_kernel(const DevScene *scenes,
+                                                              const int4 *items, int32_t n_items,
+                                                              int32_t *queue, RadarConst rc,
+                                                              const double *elem, EchoShape sh) {
+  extern __shared__ __align__(16) unsigned char echo_smem[];
+  __shared__ int32_t s_item;
+  EchoSmem<R, MB, FT> sm;
+  sm.carve(echo_smem, sh);
+  for (int i = threadIdx.x; i < 3 * sh.E; i += blockDim.x) sm.elem[i] = elem[i];
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int32_t it = s_item;
+    if (it >= n_items) break;  // every workgroup reaches this once the queue is drained
+    const int4 w = items[it];
+    const DevScene sc = scenes[w.x];
+    echo_item<R, MB, FT>(sc, rc, sh, sm, w.y, w.z, w.w);
+  }
+}
+
+__global__ void reset_counter_kernel(int32_t *q) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *q = 0;
+}
+
+template <typename R, int MB, int FT>
+static size_t smem_bytes(const EchoShape &sh) {
+  using C = typename Cx<R>::T;
+  size_t b = sizeof(double) * 3 * sh.E;
+  b = (b + 15) & ~size_t(15);
+  b += sizeof(Geo) * FT;
+  b = (b + 15) & ~size_t(15);
+  b += sizeof(C) * FT * sh.M_t + sizeof(C) * FT * sh.E * sh.B_w + sizeof(C) * FT * sh.E +
+       sizeof(R) * FT * sh.E;
+  return b;
+}
+
+// Host-side dispatch over the compiled (precision, MB, FT) variants.
+struct EchoLaunch {
+  int precision;  // 0 fp32, 1 fp64
+  int mb, ft;
+};
+
+template <typename R, int MB, int FT>
+static hipError_t launch_plain_t(const DevScene &sc, const RadarConst &rc, const double *elem,
+                                 const EchoShape &sh, hipStream_t s) {
+  const size_t lds = smem_bytes<R, MB, FT>(sh);
+  const int threads = sh.O_w * sh.B_w;
+  const unsigned grid = static_cast<unsigned>(rc.N) * sh.m_tiles * sh.o_tiles;
+  hipLaunchKernelGGL((echo_kernel<R, MB, FT>), dim3(grid), dim3(threads), lds, s, sc, rc, elem, sh);
+  return hipGetLastError();
+}
+
+template <typename R, int MB, int FT>
+static hipError_t launch_persistent_t(const DevScene *scenes, const int4 *items, int32_t n_items,
+                                      int32_t *queue, const RadarConst &rc, const double *elem,
+                                      const EchoShape &sh, int n_groups, hipStream_t s) {
+  const size_t lds = smem_bytes<R, MB, FT>(sh);
+  const int threads = sh.O_w * sh.B_w;
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
+  hipLaunchKernelGGL((echo_persistent_kernel<R, MB, FT>), dim3(n_groups), dim3(threads), lds, s,
+                     scenes, items, n_items, queue, rc, elem, sh);
+  return hipGetLastError();
+}
+
+template <typename R, int MB, int FT>
+static hipError_t occupancy_t(const EchoShape &sh, int *groups_per_cu) {
+  const size_t lds = smem_bytes<R, MB, FT>(sh);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      groups_per_cu, reinterpret_cast<const void *>(echo_persistent_kernel<R, MB, FT>),
+      sh.O_w * sh.B_w, lds);
+}
+
+#define RSIM_ECHO_VARIANTS(X) \
+  X(float, 16, 16)            \
+  X(float, 32, 8)             \
+  X(float, 32, 16)            \
+  X(float, 32, 32)            \
+  X(float, 64, 8)             \
+  X(float, 64, 16)            \
+  X(double, 8, 8)             \
+  X(double, 16, 8)            \
+  X(double, 32, 8)
+
+#define RSIM_PREC_OF(R) (sizeof(R) == 8 ? 1 : 0)
+
+hipError_t launch_echo_plain(int precision, int mb, int ft, const DevScene &sc, const RadarConst &rc,
+                             const double *elem, const EchoShape &sh, hipStream_t s) {
+#define X(R, MB, FT)                                              \
+  if (precision == RSIM_PREC_OF(R) && mb == MB && ft == FT)       \
+    return launch_plain_t<R, MB, FT>(sc, rc, elem, sh, s);
+  RSIM_ECHO_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_echo_persistent(int precision, int mb, int ft, const DevScene *scenes,
+                                  const int4 *items, int32_t n_items, int32_t *queue,
+                                  const RadarConst &rc, const double *elem, const EchoShape &sh,
+                                  int n_groups, hipStream_t s) {
+#define X(R, MB, FT)                                                                    \
+  if (precision == RSIM_PREC_OF(R) && mb == MB && ft == FT)                             \
+    return launch_persistent_t<R, MB, FT>(scenes, items, n_items, queue, rc, elem, sh, \
+                                          n_groups, s);
+  RSIM_ECHO_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t echo_occupancy(int precision, int mb, int ft, const EchoShape &sh, int *groups_per_cu) {
+#define X(R, MB, FT)                                        \
+  if (precision == RSIM_PREC_OF(R) && mb == MB && ft == FT) \
+    return occupancy_t<R, MB, FT>(sh, groups_per_cu);
+  RSIM_ECHO_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+bool echo_variant_exists(int precision, int mb, int ft) {
+#define X(R, MB, FT) \
+  if (precision == RSIM_PREC_OF(R) && mb == MB && ft == FT) return true;
+  RSIM_ECHO_VARIANTS(X)
+#undef X
+  return false;
+}
+
+size_t echo_smem_bytes(int precision, int mb, int ft, const EchoShape &sh) {
+#define X(R, MB, FT) \
+  if (precision == RSIM_PREC_OF(R) && mb == MB && ft == FT) return smem_bytes<R, MB, FT>(sh);
+  RSIM_ECHO_VARIANTS(X)
+#undef X
+  return 0;
+}
+
+}  // namespace rsim

@@ -1,0 +1,73 @@
+// Internal definitions shared by the host runtime and the gfx950 kernels of librsim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rsim {
+
+constexpr double kC0 = 299792458.0;  // speed of light, m/s
+constexpr double kPi = 3.14159265358979323846;
+
+// Segment-parameter window of a shadow ray [kTEps, 1 - kTEps]: an occluder counts
+// only strictly between the facet centroid and the antenna phase centre.
+constexpr float kTEps = 1e-6f;
+
+constexpr int kMaxElements = 128;  // Tx + Rx elements
+constexpr int kBvhStack = 64;      // traversal stack depth; the builder caps depth below
+constexpr int kBvhMaxDepth = 60;
+constexpr int kLeafMax = 4;        // triangles per leaf (encoding allows 15)
+
+// Two-wide BVH node: both child boxes live in the parent so one 64-byte fetch tests
+// two boxes. Child ref >= 0: inner node index; < 0: leaf, -(1 + (first << 4 | count)).
+struct alignas(16) BvhNode {
+  float lo0[3], hi0[3];
+  float lo1[3], hi1[3];
+  int32_t c0, c1;
+  int32_t pad0, pad1;
+};
+static_assert(sizeof(BvhNode) == 64, "node size");
+
+// Leaf triangle in BVH order as three float4: (v0.xyz, e1.x) (e1.yz, e2.xy)
+// (e2.z, id bits, 0, 0) with e1 = v1 - v0, e2 = v2 - v0 and id the mesh-local index.
+
+// One rigid instance of a mesh in a scene (device copy).
+struct DevInstance {
+  double rot[9];   // row-major body -> world
+  double pos0[3];  // world position of the body origin at t = 0
+  double vel[3];   // world velocity
+  double box_lo[3], box_hi[3];  // world box of rot * body box (add pos0 + vel t)
+  const float *verts;           // [V][3] body frame
+  const int32_t *tris;          // [F][3]
+  const BvhNode *nodes;         // BVH, root = node 0
+  const float4 *leaf;           // [n_leaf_tris * 3]
+  int64_t facet_base;           // scene-global index of this instance's triangle 0
+  int32_t n_tris;
+  int32_t has_bvh;              // 0 if the mesh has no non-degenerate triangle
+};
+
+// Radar constants passed by value.
+struct RadarConst {
+  double f0, slope, fs, df, tc;  // df = slope / fs
+  double tx_c[3], rx_c[3];       // phase centres (element means)
+  int32_t M, N, P, Q;
+};
+
+// Per-scene device view used by the visibility, compaction and echo kernels.
+struct DevScene {
+  const DevInstance *inst;
+  int32_t n_inst;
+  int32_t n_points;
+  int64_t n_facets;
+  int64_t mask_words;        // per chirp
+  const double *pt_pos0;     // [n_points][3]
+  const double *pt_vel;      // [n_points][3]
+  const double *pt_amp;      // [n_points][2]
+  uint32_t *mask;            // [N][mask_words]
+  int32_t *vis_idx;          // [N][n_facets] compacted lit facets per chirp
+  int32_t *vis_cnt;          // [N]
+  void *echo;                // [O][N][M] complex
+};
+
+}  // namespace rsim

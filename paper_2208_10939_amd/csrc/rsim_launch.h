@@ -1,0 +1,42 @@
+// Host-side entry points of the kernels (implemented in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "rsim_internal.h"
+
+namespace rsim {
+
+// Facet-sum launch shape: a workgroup holds O_w channels x B_w blocks of MB samples.
+struct EchoShape {
+  int32_t O, O_w, o_tiles, B_w, M_t, m_tiles, E, pad;
+  double two_pi_slope;  // 2 pi mu
+};
+
+int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
+              std::vector<BvhNode> &nodes_out, std::vector<float> &leaf_out);
+
+hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream_t s);
+hipError_t launch_compact(const DevScene &sc, int n_chirps, hipStream_t s);
+
+hipError_t launch_echo_plain(int precision, int mb, int ft, const DevScene &sc,
+                             const RadarConst &rc, const double *elem, const EchoShape &sh,
+                             hipStream_t s);
+hipError_t launch_echo_persistent(int precision, int mb, int ft, const DevScene *scenes,
+                                  const int4 *items, int32_t n_items, int32_t *queue,
+                                  const RadarConst &rc, const double *elem, const EchoShape &sh,
+                                  int n_groups, hipStream_t s);
+hipError_t echo_occupancy(int precision, int mb, int ft, const EchoShape &sh, int *groups_per_cu);
+bool echo_variant_exists(int precision, int mb, int ft);
+size_t echo_smem_bytes(int precision, int mb, int ft, const EchoShape &sh);
+
+hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t rows, int M,
+                            int conj_in, const void *tw, hipStream_t s);
+hipError_t launch_doppler_fft(int precision, const void *in, void *y_out, void *rdm,
+                              int64_t planes, int N, int M, int mode, const void *tw,
+                              hipStream_t s);
+
+}  // namespace rsim

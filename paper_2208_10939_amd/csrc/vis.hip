@@ -1,0 +1,252 @@
+// Lit-facet mask per chirp and its compaction into per-chirp facet lists.
+//
+// Single-bounce reading of bidirectional analytic ray tracing (Section 2.2): a
+// forward ray from the transmitter and a backward ray from the receiver meet on the
+// same facet. Facet f is lit at chirp n when it faces both phase centres and
+// neither segment centroid -> phase centre is blocked by another triangle. The
+// geometry is that of chirp start t_n (stop-and-hop, eq. (12) per chirp).
+//
+// Layout: one thread per (facet, chirp); grid (ceil(F / 128), N). The facing test
+// runs in FP64 on world coordinates; the two shadow rays run in FP32 in each
+// candidate instance's body frame, starting at the facet centroid (close to the
+// occluders, so the FP32 Moller-Trumbore test keeps its precision). Each thread
+// owns a column of an LDS stack (stride = block size, conflict-free).
+#include "rsim_internal.h"
+#include "rsim_launch.h"
+
+namespace rsim {
+
+namespace {
+
+__device__ inline int find_instance(const DevInstance *inst, int n_inst, int64_t f) {
+  int lo = 0, hi = n_inst - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].facet_base <= f)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline bool box_hit(const float *lo, const float *hi, float ox, float oy, float oz,
+                               float ix, float iy, float iz) {
+  float tx0 = (lo[0] - ox) * ix, tx1 = (hi[0] - ox) * ix;
+  float ty0 = (lo[1] - oy) * iy, ty1 = (hi[1] - oy) * iy;
+  float tz0 = (lo[2] - oz) * iz, tz1 = (hi[2] - oz) * iz;
+  float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), 1.0f));
+  return tn <= tf;
+}
+
+// Any triangle of the leaf hit by o + t d, t in [kTEps, 1 - kTEps] (closed test)?
+__device__ inline bool leaf_hit(const float4 *leaf, int32_t ref, float ox, float oy, float oz,
+                                float dx, float dy, float dz, int32_t skip) {
+  uint32_t code = static_cast<uint32_t>(-ref - 1);
+  uint32_t first = code >> 4, count = code & 15u;
+  for (uint32_t k = 0; k < count; ++k) {
+    const float4 a = leaf[3 * (first + k) + 0];
+    const float4 b = leaf[3 * (first + k) + 1];
+    const float4 c = leaf[3 * (first + k) + 2];
+    if (__float_as_int(c.y) == skip) continue;
+    // v0 = a.xyz, e1 = (a.w, b.x, b.y), e2 = (b.z, b.w, c.x)
+    float e1x = a.w, e1y = b.x, e1z = b.y;
+    float e2x = b.z, e2y = b.w, e2z = c.x;
+    float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    float det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0f) continue;
+    float inv = 1.0f / det;
+    float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
+    float u = (sx * px + sy * py + sz * pz) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) continue;
+    float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    float v = (dx * qx + dy * qy + dz * qz) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) continue;
+    float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    if (t >= kTEps && t <= 1.0f - kTEps) return true;
+  }
+  return false;
+}
+
+__device__ inline float safe_inv(float d) {
+  const float tiny = 1e-30f;
+  return 1.0f / (fabsf(d) > tiny ? d : copysignf(tiny, d));
+}
+
+// Any-hit traversal of one BLAS for the body-frame segment o -> o + d.
+__device__ bool blas_occluded(const BvhNode *nodes, const float4 *leaf, float ox, float oy,
+                              float oz, float dx, float dy, float dz, int32_t skip,
+                              int32_t *stack, int stride) {
+  const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const BvhNode nd = nodes[node];
+    const bool h0 = box_hit(nd.lo0, nd.hi0, ox, oy, oz, ix, iy, iz);
+    const bool h1 = box_hit(nd.lo1, nd.hi1, ox, oy, oz, ix, iy, iz);
+    int32_t next = -1;
+    if (h0) {
+      if (nd.c0 < 0) {
+        if (leaf_hit(leaf, nd.c0, ox, oy, oz, dx, dy, dz, skip)) return true;
+      } else {
+        next = nd.c0;
+      }
+    }
+    if (h1) {
+      if (nd.c1 < 0) {
+        if (leaf_hit(leaf, nd.c1, ox, oy, oz, dx, dy, dz, skip)) return true;
+      } else if (next >= 0) {
+        stack[sp * stride] = nd.c1;  // depth <= kBvhMaxDepth < kBvhStack
+        ++sp;
+      } else {
+        next = nd.c1;
+      }
+    }
+    if (next < 0) {
+      if (sp == 0) return false;
+      --sp;
+      next = stack[sp * stride];
+    }
+    node = next;
+  }
+}
+
+// Is the world segment c -> s blocked by any triangle of the scene at time t
+// (triangle `self_local` of instance `self_inst` excluded)?
+__device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
+                                const double s[3], int self_inst, int32_t self_local,
+                                int32_t *stack, int stride) {
+  double d[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
+  for (int j = 0; j < sc.n_inst; ++j) {
+    const DevInstance &I = sc.inst[j];
+    if (!I.has_bvh) continue;
+    double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
+    // world-space slab test against the instance box (FP64, conservative box)
+    double tn = 0.0, tf = 1.0;
+    bool miss = false;
+    for (int k = 0; k < 3; ++k) {
+      double lo = I.box_lo[k] + p[k], hi = I.box_hi[k] + p[k];
+      if (d[k] == 0.0) {
+        if (c[k] < lo || c[k] > hi) miss = true;
+        continue;
+      }
+      double a = (lo - c[k]) / d[k], b = (hi - c[k]) / d[k];
+      tn = fmax(tn, fmin(a, b));
+      tf = fmin(tf, fmax(a, b));
+    }
+    if (miss || tn > tf) continue;
+    // body frame: x_body = R^T (x - p)
+    const double *R = I.rot;
+    double q0 = c[0] - p[0], q1 = c[1] - p[1], q2 = c[2] - p[2];
+    float ox = static_cast<float>(R[0] * q0 + R[3] * q1 + R[6] * q2);
+    float oy = static_cast<float>(R[1] * q0 + R[4] * q1 + R[7] * q2);
+    float oz = static_cast<float>(R[2] * q0 + R[5] * q1 + R[8] * q2);
+    float dx = static_cast<float>(R[0] * d[0] + R[3] * d[1] + R[6] * d[2]);
+    float dy = static_cast<float>(R[1] * d[0] + R[4] * d[1] + R[7] * d[2]);
+    float dz = static_cast<float>(R[2] * d[0] + R[5] * d[1] + R[8] * d[2]);
+    int32_t skip = (j == self_inst) ? self_local : -1;
+    if (blas_occluded(I.nodes, I.leaf, ox, oy, oz, dx, dy, dz, skip, stack, stride)) return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(128) vis_kernel(DevScene sc, RadarConst rc) {
+  extern __shared__ int32_t vis_stack[];
+  const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  const double t = n * rc.tc;
+  bool lit = false;
+  if (f < sc.n_facets) {
+    const int ii = find_instance(sc.inst, sc.n_inst, f);
+    const DevInstance &I = sc.inst[ii];
+    const int32_t lt = static_cast<int32_t>(f - I.facet_base);
+    double x[3][3];
+    for (int v = 0; v < 3; ++v) {
+      const int32_t vi = I.tris[3 * lt + v];
+      const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
+      for (int k = 0; k < 3; ++k)
+        x[v][k] = I.rot[3 * k + 0] * b0 + I.rot[3 * k + 1] * b1 + I.rot[3 * k + 2] * b2 +
+                  (I.pos0[k] + I.vel[k] * t);
+    }
+    double c[3], e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+      c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
+      e1[k] = x[1][k] - x[0][k];
+      e2[k] = x[2][k] - x[0][k];
+    }
+    double nx = e1[1] * e2[2] - e1[2] * e2[1];
+    double ny = e1[2] * e2[0] - e1[0] * e2[2];
+    double nz = e1[0] * e2[1] - e1[1] * e2[0];
+    bool nonzero = (nx != 0.0 || ny != 0.0 || nz != 0.0);
+    double ft = nx * (rc.tx_c[0] - c[0]) + ny * (rc.tx_c[1] - c[1]) + nz * (rc.tx_c[2] - c[2]);
+    double fr = nx * (rc.rx_c[0] - c[0]) + ny * (rc.rx_c[1] - c[1]) + nz * (rc.rx_c[2] - c[2]);
+    if (nonzero && ft > 0.0 && fr > 0.0) {
+      int32_t *stk = vis_stack + threadIdx.x;
+      lit = !segment_blocked(sc, t, c, rc.tx_c, ii, lt, stk, blockDim.x) &&
+            !segment_blocked(sc, t, c, rc.rx_c, ii, lt, stk, blockDim.x);
+    }
+  }
+  const unsigned long long bits = __ballot(lit);
+  if ((threadIdx.x & 63) == 0) {
+    const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 5;
+    uint32_t *row = sc.mask + static_cast<int64_t>(n) * sc.mask_words;
+    if (w < sc.mask_words) row[w] = static_cast<uint32_t>(bits);
+    if (w + 1 < sc.mask_words) row[w + 1] = static_cast<uint32_t>(bits >> 32);
+  }
+}
+
+// Per-chirp compaction of the mask into ascending facet indices (deterministic).
+__global__ void __launch_bounds__(1024) compact_kernel(DevScene sc) {
+  __shared__ int32_t s_scan[1024];
+  const int n = blockIdx.x;
+  const uint32_t *row = sc.mask + static_cast<int64_t>(n) * sc.mask_words;
+  const int64_t per = (sc.mask_words + blockDim.x - 1) / blockDim.x;
+  const int64_t w0 = static_cast<int64_t>(threadIdx.x) * per;
+  const int64_t w1 = min(sc.mask_words, w0 + per);
+  const uint32_t tail_bits = static_cast<uint32_t>(sc.n_facets & 31);
+  int32_t cnt = 0;
+  for (int64_t w = w0; w < w1; ++w) {
+    uint32_t b = row[w];
+    if (w == sc.mask_words - 1 && tail_bits) b &= (1u << tail_bits) - 1u;
+    cnt += __popc(b);
+  }
+  s_scan[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
+    int32_t v = (threadIdx.x >= static_cast<unsigned>(off)) ? s_scan[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int32_t pos = s_scan[threadIdx.x] - cnt;
+  int32_t *out = sc.vis_idx + static_cast<int64_t>(n) * sc.n_facets;
+  for (int64_t w = w0; w < w1; ++w) {
+    uint32_t b = row[w];
+    if (w == sc.mask_words - 1 && tail_bits) b &= (1u << tail_bits) - 1u;
+    while (b) {
+      const int bit = __ffs(b) - 1;
+      out[pos++] = static_cast<int32_t>(w * 32 + bit);
+      b &= b - 1u;
+    }
+  }
+  if (threadIdx.x == blockDim.x - 1) sc.vis_cnt[n] = s_scan[threadIdx.x];
+}
+
+hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream_t s) {
+  if (sc.n_facets == 0) return hipSuccess;
+  const int block = 128;
+  dim3 grid(static_cast<unsigned>((sc.n_facets + block - 1) / block), rc.N);
+  const size_t lds = sizeof(int32_t) * kBvhStack * block;
+  hipLaunchKernelGGL(vis_kernel, grid, dim3(block), lds, s, sc, rc);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const DevScene &sc, int n_chirps, hipStream_t s) {
+  hipLaunchKernelGGL(compact_kernel, dim3(n_chirps), dim3(1024), 0, s, sc);
+  return hipGetLastError();
+}
+
+}  // namespace rsim

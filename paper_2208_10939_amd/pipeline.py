@@ -1,0 +1,85 @@
+"""Convenience layer over the binding: load a scene, waveform and array into a context
+and run echo synthesis and range-Doppler processing into torch device tensors.
+All arithmetic happens in librsim; this module only allocates and marshals."""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from .rsim import Context, RSIM_FP32_PHASE64, RSIM_FP64, RSIM_MASK_COMPUTE, RSIM_MASK_INPUT
+
+
+def pack_mask(mask: np.ndarray) -> np.ndarray:
+    """[N, F] bool -> [N, ceil(F/32)] uint32 with bit f % 32 of word f // 32."""
+    mask = np.asarray(mask, bool)
+    n, f = mask.shape
+    words = (f + 31) // 32
+    pad = np.zeros((n, words * 32), bool)
+    pad[:, :f] = mask
+    return np.packbits(pad, axis=1, bitorder="little").view("<u4").reshape(n, words)
+
+
+def unpack_mask(words: np.ndarray, n_facets: int) -> np.ndarray:
+    w = np.ascontiguousarray(words, dtype="<u4")
+    bits = np.unpackbits(w.view(np.uint8).reshape(w.shape[0], -1), axis=1, bitorder="little")
+    return bits[:, :n_facets].astype(bool)
+
+
+class Simulator:
+    """One context holding a list of scenes sharing one waveform and array."""
+
+    def __init__(self, scenes: Sequence, waveform, array, device: int = 0):
+        self.ctx = Context(device)
+        self.ctx.set_waveform(waveform)
+        self.ctx.set_array(array.tx, array.rx)
+        self.wf = waveform
+        self.O = self.ctx.n_channels
+        self.scene_ids = [self.ctx.load_scene(s) for s in scenes]
+        self.n_facets = [self.ctx.scene_info(s)[0] for s in self.scene_ids]
+        self.mask_words = [self.ctx.scene_info(s)[1] for s in self.scene_ids]
+        self.dev = torch.device("cuda", device)
+
+    def echo_buffer(self, n_scenes: int = 1, precision: int = RSIM_FP32_PHASE64):
+        dt = torch.complex128 if precision == RSIM_FP64 else torch.complex64
+        return torch.empty((n_scenes, self.O, self.wf.n_chirps, self.wf.n_samples), dtype=dt,
+                           device=self.dev)
+
+    def mask_buffer(self, which: Optional[Sequence[int]] = None):
+        which = range(len(self.scene_ids)) if which is None else which
+        total = sum(self.wf.n_chirps * self.mask_words[i] for i in which)
+        return torch.zeros(max(1, total), dtype=torch.int32, device=self.dev)
+
+    def synthesize(self, which: Optional[Sequence[int]] = None, precision=RSIM_FP32_PHASE64,
+                   echo=None, mask=None, mask_mode=RSIM_MASK_COMPUTE, **kw):
+        which = list(range(len(self.scene_ids))) if which is None else list(which)
+        if echo is None:
+            echo = self.echo_buffer(len(which), precision)
+        self.ctx.synthesize([self.scene_ids[i] for i in which], echo, mask,
+                            precision=precision, mask_mode=mask_mode, **kw)
+        return echo
+
+    def form_rdm(self, echo, precision=RSIM_FP32_PHASE64, want_y=False, **kw):
+        n_cubes = echo.shape[0]
+        rdt = torch.float64 if precision == RSIM_FP64 else torch.float32
+        rdm = torch.empty(echo.shape, dtype=rdt, device=self.dev)
+        y = torch.empty_like(echo) if want_y else None
+        self.ctx.form_rdm(echo, rdm, y, n_cubes=n_cubes, precision=precision, **kw)
+        return (rdm, y) if want_y else rdm
+
+    def masks_numpy(self, mask_tensor, which: Optional[Sequence[int]] = None):
+        """Split a device mask buffer into per-scene [N, F] bool arrays."""
+        which = list(range(len(self.scene_ids))) if which is None else list(which)
+        raw = mask_tensor.cpu().numpy().view("<u4")
+        out, off = [], 0
+        for i in which:
+            cnt = self.wf.n_chirps * self.mask_words[i]
+            words = raw[off:off + cnt].reshape(self.wf.n_chirps, self.mask_words[i])
+            out.append(unpack_mask(words, self.n_facets[i]))
+            off += cnt
+        return out
+
+    def mask_from_numpy(self, masks: Sequence[np.ndarray]):
+        packed = np.concatenate([pack_mask(m).reshape(-1) for m in masks])
+        return torch.from_numpy(packed.view(np.int32).copy()).to(self.dev)
