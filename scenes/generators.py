@@ -316,17 +316,19 @@ def _hull_parts(length, width, height, n_wheels, cell):
     body_hi = (0.5 * length, 0.5 * width, zb1)
     parts.append(box_mesh(body_lo, body_hi,
                           (nseg(length), nseg(width), nseg(zb1 - zb0))))
-    cab_lo = (-0.30 * length, -0.45 * width, zb1)
+    # the cabin floor sits 2 cm inside the body and the wheels stand 2 cm proud of the
+    # body sides, so no two parts share a plane (no coplanar overlapping triangles)
+    cab_lo = (-0.30 * length, -0.45 * width, zb1 - 0.02)
     cab_hi = (0.25 * length, 0.45 * width, height)
     parts.append(box_mesh(cab_lo, cab_hi,
-                          (nseg(0.55 * length), nseg(0.9 * width), nseg(height - zb1))))
+                          (nseg(0.55 * length), nseg(0.9 * width), nseg(height - zb1 + 0.02))))
     n_theta = max(8, nseg(2 * np.pi * rw))
     n_len = nseg(2 * hw)
     n_rings = max(1, nseg(rw))
     if n_wheels == 2:
         spots = [(-0.35 * length, 0.0), (0.35 * length, 0.0)]
     else:
-        spots = [(sx * 0.32 * length, sy * (0.5 * width - hw))
+        spots = [(sx * 0.32 * length, sy * (0.5 * width - hw + 0.02))
                  for sx in (-1, 1) for sy in (-1, 1)]
     for (x, y) in spots:
         parts.append(cylinder_y_mesh((x, y, rw), rw, hw, n_theta, n_len, n_rings))
@@ -345,7 +347,7 @@ def _hull_count(length, width, height, n_wheels, cell):
         return 4 * (ny * nz + nx * nz + nx * ny)
 
     n = box(nseg(length), nseg(width), nseg(zb1 - zb0))
-    n += box(nseg(0.55 * length), nseg(0.9 * width), nseg(height - zb1))
+    n += box(nseg(0.55 * length), nseg(0.9 * width), nseg(height - zb1 + 0.02))
     n_theta = max(8, nseg(2 * np.pi * rw))
     n_len = nseg(2 * hw)
     n_rings = max(1, nseg(rw))

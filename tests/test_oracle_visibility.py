@@ -87,3 +87,26 @@ def test_hidden_box_is_dark():
     mask, amb = oracle.visibility(sc, _arr(), wf)
     assert not mask[0, big.n_tris:].any()
     assert mask[0, :big.n_tris].any()
+
+
+def test_projection_prefilter_matches_box_prefilter():
+    """The two candidate searches are exact prefilters: they give identical decisions."""
+    import importlib
+    V = importlib.import_module("oracle.visibility")
+    sc = scenes.intersection_scene(21, n_vehicles=3, per_vehicle=500, with_ground=True,
+                                   ground_cell=2.0)
+    tri, _, _ = oracle.world_triangles(sc, 0.0)
+    c, n, _ = oracle.facet_frames(tri)
+    S = scenes.RADAR_POS + np.array([0.01, 0.0, 0.0])
+    idx = np.nonzero(np.einsum("ij,ij->i", n, S - c) > 0)[0]
+    src = np.repeat(S[None], idx.size, 0)
+    occ_p, amb_p = V.segment_occluded(src, c[idx], tri, idx)
+    # force the box path by moving one triangle above the source
+    tri2 = tri.copy()
+    far = tri2.shape[0] - 1
+    tri2[far] += np.array([500.0, 500.0, 100.0])
+    occ_b, amb_b = V.segment_occluded(src, c[idx], tri2, idx)
+    occ_p2, amb_p2 = V.segment_occluded(src, c[idx], np.delete(tri, far, 0), np.where(idx > far, idx - 1, idx))
+    assert occ_p.sum() > 10
+    assert np.array_equal(occ_b, occ_p2) and np.array_equal(amb_b, amb_p2)
+    assert np.array_equal(occ_b, occ_p) and np.array_equal(amb_b, amb_p)
