@@ -118,6 +118,16 @@ int32_t rsim_add_instance(rsim_ctx *ctx, int32_t scene_id, int32_t mesh_id,
 int32_t rsim_add_points(rsim_ctx *ctx, int32_t scene_id, const double *pos0,
                         const double *vel, const double *amp_re_im, int64_t n);
 
+/* Replace a mesh's body-frame vertices (same count; triangles unchanged), e.g. for a
+ * gradient step or a finite-difference probe. The BVH is rebuilt. Synchronous: waits
+ * for queued work on the device first. */
+int32_t rsim_update_mesh(rsim_ctx *ctx, int32_t mesh_id, const float *verts_xyz,
+                         int64_t n_verts);
+
+/* Replace an instance's start position and velocity (eq. (12)). Synchronous. */
+int32_t rsim_set_instance_motion(rsim_ctx *ctx, int32_t scene_id, int32_t inst_id,
+                                 const double pos0[3], const double vel[3]);
+
 /* Number of facets F of a scene (sum over its instances) and words per chirp of its
  * lit-facet mask, ceil(F / 32). */
 int32_t rsim_scene_info(rsim_ctx *ctx, int32_t scene_id, int64_t *n_facets,
@@ -185,6 +195,14 @@ int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages);
 int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                       const uint32_t *vis_mask, float *const *grad_verts, int32_t n_meshes,
                       double *grad_vel, void *hip_stream);
+
+/* Gradient of L with respect to the echo given dL/dP of the power RDM P = |Y|^2 and
+ * the Y of the forward call (FP32): dL/dY = 2 (dL/dP) Y, then the adjoint of the
+ * Doppler and range transforms (Section 3.3).
+ *   grad_rdm DEVICE [n_cubes][O][N][M] float32, y DEVICE complex64 same layout,
+ *   grad_echo DEVICE complex64 [n_cubes][O][N][M]: dL/dRe(H) + j dL/dIm(H). */
+int32_t rsim_rdm_backward(rsim_ctx *ctx, const float *grad_rdm, const void *y, int32_t n_cubes,
+                          void *grad_echo, void *hip_stream);
 
 /* Gradient of L with respect to the echo given dL/dRe(Y) + j dL/dIm(Y) of the
  * Doppler-FFT output (adjoint of rsim_form_rdm's linear part, FP32):

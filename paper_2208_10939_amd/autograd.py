@@ -1,0 +1,62 @@
+"""torch.autograd.Function around the echo synthesis and RDM with the library's
+hand-written adjoint. Visibility is decided in the forward call and held fixed in
+the backward; the backward recomputes every chirp inside the library."""
+from __future__ import annotations
+
+import torch
+
+from .pipeline import Simulator
+
+
+class RadarRDM(torch.autograd.Function):
+    """rdm = RadarRDM.apply(sim, scene_index, vel, *verts)
+
+    sim         Simulator holding the scene
+    scene_index index into sim.scene_ids
+    vel         [n_instances, 3] float64 tensor: instance velocities (world frame)
+    verts       one [n_verts, 3] float32 tensor per mesh of the scene, body frame
+    returns     [O, N, M] float32 power RDM (Doppler rows shifted)
+    """
+
+    @staticmethod
+    def forward(ctx, sim: Simulator, scene_index: int, vel, *verts):
+        sid = sim.scene_ids[scene_index]
+        meshes = sim.ctx.scene_meshes[sid]
+        for mid, v in zip(meshes, verts):
+            sim.ctx.update_mesh(mid, v.detach().cpu().numpy())
+        pos0 = sim.inst_pos0[scene_index]
+        vv = vel.detach().cpu().numpy()
+        for i in range(len(pos0)):
+            sim.ctx.set_instance_motion(sid, i, pos0[i], vv[i])
+        mask = sim.mask_buffer([scene_index])
+        echo = sim.synthesize([scene_index], mask=mask)
+        rdm, y = sim.form_rdm(echo, want_y=True)
+        ctx.sim = sim
+        ctx.scene_index = scene_index
+        ctx.meshes = meshes
+        ctx.n_verts = [v.shape[0] for v in verts]
+        ctx.vert_devices = [v.device for v in verts]
+        ctx.vel_device = vel.device
+        ctx.n_inst = len(pos0)
+        ctx.save_for_backward(mask, y)
+        return rdm[0]
+
+    @staticmethod
+    def backward(ctx, grad_rdm):
+        mask, y = ctx.saved_tensors
+        sim = ctx.sim
+        dev = y.device
+        g = grad_rdm.to(torch.float32).contiguous().reshape(y.shape)
+        grad_echo = torch.empty_like(y)
+        sim.ctx.rdm_backward(g, y, grad_echo)
+        n_mesh_ids = max(ctx.meshes) + 1
+        per_id = [None] * n_mesh_ids
+        grads = []
+        for mid, nv in zip(ctx.meshes, ctx.n_verts):
+            t = torch.zeros((nv, 3), dtype=torch.float32, device=dev)
+            per_id[mid] = t
+            grads.append(t)
+        grad_vel = torch.zeros((ctx.n_inst, 3), dtype=torch.float64, device=dev)
+        sim.ctx.backward(sim.scene_ids[ctx.scene_index], grad_echo, mask, per_id, grad_vel)
+        grads = [g.to(d) for g, d in zip(grads, ctx.vert_devices)]
+        return (None, None, grad_vel.to(ctx.vel_device), *grads)

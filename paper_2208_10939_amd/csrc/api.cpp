@@ -37,6 +37,8 @@ struct MeshRec {
   int depth = -1;
   int64_t n_nodes = 0, n_leaf = 0;
   void *d_verts = nullptr, *d_tris = nullptr, *d_nodes = nullptr, *d_leaf = nullptr;
+  // vertex -> incident (triangle * 3 + corner), for the gradient gather
+  int32_t *d_csr_off = nullptr, *d_csr_ent = nullptr;
 };
 
 struct InstRec {
@@ -117,6 +119,10 @@ struct rsim_ctx {
   int cu_count = 0;
   size_t max_lds = 0;
   std::map<std::tuple<int, int, int>, TunedShape> tuned;  // (M, O, precision) -> shape
+  // adjoint work buffers
+  float *adj_partial = nullptr, *adj_gxw = nullptr;
+  double *adj_vpart = nullptr;
+  size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0;
   BatchTables batch;  // persistent launches outside graphs
   GraphCache graph;
 };
@@ -412,6 +418,69 @@ void timing_reset(rsim_ctx *ctx, bool on) {
   ctx->timing_pending = true;
 }
 
+int32_t check_scene(rsim_ctx *ctx, int32_t scene_id) {
+  if (scene_id < 0 || scene_id >= static_cast<int32_t>(ctx->scenes.size()))
+    return fail(ctx, RSIM_EINVAL, "unknown scene id %d", scene_id);
+  return RSIM_OK;
+}
+
+// Bounding box, BVH and vertex -> (triangle, corner) index of a mesh, uploaded to the
+// device (first = true: fresh mesh; false: vertices changed, triangles unchanged).
+int32_t index_mesh(rsim_ctx *ctx, MeshRec &m, bool first_time) {
+  const int64_t n_tris = static_cast<int64_t>(m.tris.size() / 3);
+  const int64_t n_verts = static_cast<int64_t>(m.verts.size() / 3);
+  for (int k = 0; k < 3; ++k) {
+    m.box_lo[k] = 0;
+    m.box_hi[k] = 0;
+  }
+  bool first = true;
+  for (int64_t t = 0; t < 3 * n_tris; ++t) {
+    const float *v = &m.verts[3 * static_cast<int64_t>(m.tris[t])];
+    for (int k = 0; k < 3; ++k) {
+      if (first || v[k] < m.box_lo[k]) m.box_lo[k] = v[k];
+      if (first || v[k] > m.box_hi[k]) m.box_hi[k] = v[k];
+    }
+    first = false;
+  }
+  std::vector<BvhNode> nodes;
+  std::vector<float> leaf;
+  m.depth = build_bvh(m.verts.data(), m.tris.data(), n_tris, nodes, leaf);
+  if (m.depth >= kBvhStack)
+    return fail(ctx, RSIM_ERANGE, "BVH depth %d exceeds %d", m.depth, kBvhStack);
+  m.n_nodes = static_cast<int64_t>(nodes.size());
+  m.n_leaf = static_cast<int64_t>(leaf.size() / 12);
+  if (ctx->host_only) return RSIM_OK;
+  int32_t rc = need_device(ctx);
+  if (rc) return rc;
+  dev_free(ctx, m.d_verts);
+  dev_free(ctx, m.d_nodes);
+  dev_free(ctx, m.d_leaf);
+  m.d_verts = m.d_nodes = m.d_leaf = nullptr;
+  float *dv = nullptr;
+  BvhNode *dn = nullptr;
+  float *dl = nullptr;
+  if ((rc = upload(ctx, &dv, m.verts.data(), m.verts.size()))) return rc;
+  if ((rc = upload(ctx, &dn, nodes.data(), nodes.size()))) return rc;
+  if ((rc = upload(ctx, &dl, leaf.data(), leaf.size()))) return rc;
+  m.d_verts = dv;
+  m.d_nodes = dn;
+  m.d_leaf = dl;
+  if (first_time) {
+    int32_t *dt = nullptr;
+    if ((rc = upload(ctx, &dt, m.tris.data(), m.tris.size()))) return rc;
+    m.d_tris = dt;
+    // counting sort of corners by vertex
+    std::vector<int32_t> off(n_verts + 1, 0), ent(3 * n_tris);
+    for (int64_t t = 0; t < 3 * n_tris; ++t) off[m.tris[t] + 1]++;
+    for (int64_t v = 0; v < n_verts; ++v) off[v + 1] += off[v];
+    std::vector<int32_t> pos(off.begin(), off.end() - 1);
+    for (int64_t t = 0; t < 3 * n_tris; ++t) ent[pos[m.tris[t]]++] = static_cast<int32_t>(t);
+    if ((rc = upload(ctx, &m.d_csr_off, off.data(), off.size()))) return rc;
+    if ((rc = upload(ctx, &m.d_csr_ent, ent.data(), ent.size()))) return rc;
+  }
+  return RSIM_OK;
+}
+
 int32_t check_radar(rsim_ctx *ctx) {
   if (!ctx->have_wf) return fail(ctx, RSIM_ESTATE, "waveform not set");
   if (!ctx->have_arr) return fail(ctx, RSIM_ESTATE, "array not set");
@@ -602,44 +671,55 @@ int32_t rsim_load_mesh(rsim_ctx *ctx, const float *verts_xyz, int64_t n_verts, c
   MeshRec m;
   m.verts.assign(verts_xyz, verts_xyz + 3 * n_verts);
   m.tris.assign(tris, tris + 3 * n_tris);
-  for (int k = 0; k < 3; ++k) {
-    m.box_lo[k] = 0;
-    m.box_hi[k] = 0;
-  }
-  bool first = true;
-  for (int64_t t = 0; t < 3 * n_tris; ++t) {
-    const float *v = &m.verts[3 * static_cast<int64_t>(m.tris[t])];
-    for (int k = 0; k < 3; ++k) {
-      if (first || v[k] < m.box_lo[k]) m.box_lo[k] = v[k];
-      if (first || v[k] > m.box_hi[k]) m.box_hi[k] = v[k];
-    }
-    first = false;
-  }
-  std::vector<BvhNode> nodes;
-  std::vector<float> leaf;
-  m.depth = build_bvh(m.verts.data(), m.tris.data(), n_tris, nodes, leaf);
-  if (m.depth >= kBvhStack)
-    return fail(ctx, RSIM_ERANGE, "rsim_load_mesh: BVH depth %d exceeds %d", m.depth, kBvhStack);
-  m.n_nodes = static_cast<int64_t>(nodes.size());
-  m.n_leaf = static_cast<int64_t>(leaf.size() / 12);
+  int32_t rc = index_mesh(ctx, m, true);
+  if (rc) return rc;
+  ctx->meshes.push_back(std::move(m));
+  *mesh_id = static_cast<int32_t>(ctx->meshes.size() - 1);
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_update_mesh(rsim_ctx *ctx, int32_t mesh_id, const float *verts_xyz, int64_t n_verts) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (mesh_id < 0 || mesh_id >= static_cast<int32_t>(ctx->meshes.size()))
+    return fail(ctx, RSIM_EINVAL, "unknown mesh id %d", mesh_id);
+  MeshRec &m = ctx->meshes[mesh_id];
+  if (!verts_xyz || n_verts != static_cast<int64_t>(m.verts.size() / 3))
+    return fail(ctx, RSIM_EINVAL, "rsim_update_mesh: need %lld vertices",
+                (long long)(m.verts.size() / 3));
+  for (int64_t i = 0; i < 3 * n_verts; ++i)
+    if (!std::isfinite(verts_xyz[i]))
+      return fail(ctx, RSIM_EINVAL, "rsim_update_mesh: vertex coordinate %lld is not finite", (long long)i);
   if (!ctx->host_only) {
     int32_t rc = need_device(ctx);
     if (rc) return rc;
-    float *dv = nullptr;
-    int32_t *dt = nullptr;
-    BvhNode *dn = nullptr;
-    float *dl = nullptr;
-    if ((rc = upload(ctx, &dv, m.verts.data(), m.verts.size()))) return rc;
-    if ((rc = upload(ctx, &dt, m.tris.data(), m.tris.size()))) return rc;
-    if ((rc = upload(ctx, &dn, nodes.data(), nodes.size()))) return rc;
-    if ((rc = upload(ctx, &dl, leaf.data(), leaf.size()))) return rc;
-    m.d_verts = dv;
-    m.d_tris = dt;
-    m.d_nodes = dn;
-    m.d_leaf = dl;
+    HIP_TRY(ctx, hipDeviceSynchronize());  // kernels may still read the old copies
   }
-  ctx->meshes.push_back(std::move(m));
-  *mesh_id = static_cast<int32_t>(ctx->meshes.size() - 1);
+  m.verts.assign(verts_xyz, verts_xyz + 3 * n_verts);
+  int32_t rc = index_mesh(ctx, m, false);
+  if (rc) return rc;
+  for (auto &sc : ctx->scenes) sc.dirty = true;  // instance tables hold mesh pointers
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_set_instance_motion(rsim_ctx *ctx, int32_t scene_id, int32_t inst_id,
+                                 const double pos0[3], const double vel[3]) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  int32_t rc = check_scene(ctx, scene_id);
+  if (rc) return rc;
+  SceneRec &sc = ctx->scenes[scene_id];
+  if (inst_id < 0 || inst_id >= static_cast<int32_t>(sc.inst.size()))
+    return fail(ctx, RSIM_EINVAL, "unknown instance id %d", inst_id);
+  if (!pos0 || !vel || !finite_all(pos0, 3) || !finite_all(vel, 3))
+    return fail(ctx, RSIM_EINVAL, "rsim_set_instance_motion: bad position or velocity");
+  if (!ctx->host_only) {
+    if ((rc = need_device(ctx))) return rc;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+  }
+  std::memcpy(sc.inst[inst_id].pos0, pos0, sizeof(double) * 3);
+  std::memcpy(sc.inst[inst_id].vel, vel, sizeof(double) * 3);
+  sc.dirty = true;
   ctx->version++;
   return RSIM_OK;
 }
@@ -650,12 +730,6 @@ int32_t rsim_create_scene(rsim_ctx *ctx, int32_t *scene_id) {
   ctx->scenes.emplace_back();
   *scene_id = static_cast<int32_t>(ctx->scenes.size() - 1);
   ctx->version++;
-  return RSIM_OK;
-}
-
-static int32_t check_scene(rsim_ctx *ctx, int32_t scene_id) {
-  if (scene_id < 0 || scene_id >= static_cast<int32_t>(ctx->scenes.size()))
-    return fail(ctx, RSIM_EINVAL, "unknown scene id %d", scene_id);
   return RSIM_OK;
 }
 
@@ -855,9 +929,99 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                       const uint32_t *vis_mask, float *const *grad_verts, int32_t n_meshes,
                       double *grad_vel, void *hip_stream) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
-  (void)scene_id; (void)grad_echo; (void)vis_mask; (void)grad_verts; (void)n_meshes;
-  (void)grad_vel; (void)hip_stream;
-  return fail(ctx, RSIM_ESTATE, "rsim_backward: adjoint not built yet");
+  if (!grad_echo || !vis_mask || n_meshes < 0 || (n_meshes && !grad_verts))
+    return fail(ctx, RSIM_EINVAL, "rsim_backward: need grad_echo, vis_mask and grad buffers");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  if ((rc = check_scene(ctx, scene_id))) return rc;
+  const RadarConst rcn = radar_const(ctx);
+  if (cross_term_bound(ctx, rcn) > 3e-4)
+    return fail(ctx, RSIM_ERANGE, "rsim_backward: array aperture too large for the FP32 sum");
+  if ((rc = need_device(ctx))) return rc;
+  SceneRec &sc = ctx->scenes[scene_id];
+  if ((rc = ensure_scene_device(ctx, sc))) return rc;
+  const EchoShape sh = echo_shape(ctx, rcn, adjoint_tile_m());
+  if (adjoint_smem_bytes(sh) > ctx->max_lds)
+    return fail(ctx, RSIM_ERANGE, "adjoint tile needs %zu bytes of LDS", adjoint_smem_bytes(sh));
+  const int64_t F = sc.n_facets, N = rcn.N;
+  size_t vmax = 1;
+  for (const InstRec &r : sc.inst) vmax = std::max(vmax, ctx->meshes[r.mesh].verts.size() / 3);
+  auto grow_f = [&](float *&p, size_t &cap, size_t need) -> int32_t {
+    if (cap >= need) return RSIM_OK;
+    dev_free(ctx, p);
+    p = nullptr;
+    cap = 0;
+    int32_t r = dev_alloc(ctx, reinterpret_cast<void **>(&p), sizeof(float) * need);
+    if (!r) cap = need;
+    return r;
+  };
+  if ((rc = grow_f(ctx->adj_partial, ctx->adj_partial_n,
+                   std::max<size_t>(1, adjoint_partial_floats(sh, N, F)))))
+    return rc;
+  if ((rc = grow_f(ctx->adj_gxw, ctx->adj_gxw_n, std::max<size_t>(1, N * F * 9)))) return rc;
+  if (ctx->adj_vpart_n < 3 * vmax) {
+    dev_free(ctx, ctx->adj_vpart);
+    ctx->adj_vpart = nullptr;
+    ctx->adj_vpart_n = 0;
+    if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&ctx->adj_vpart), sizeof(double) * 3 * vmax)))
+      return rc;
+    ctx->adj_vpart_n = 3 * vmax;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  DevScene d = dev_scene(sc, const_cast<uint32_t *>(vis_mask), nullptr);
+  const bool timing = ctx->timing_pending;
+  HIP_TRY(ctx, launch_compact(d, rcn.N, s));
+  stage_begin(ctx, timing, 5, s);
+  HIP_TRY(ctx, launch_adjoint(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial, ctx->adj_gxw, s));
+  stage_end(ctx, timing, 5, s);
+  stage_begin(ctx, timing, 7, s);
+  for (size_t i = 0; i < sc.inst.size(); ++i) {
+    const InstRec &r = sc.inst[i];
+    const MeshRec &m = ctx->meshes[r.mesh];
+    float *gv = (r.mesh < n_meshes) ? grad_verts[r.mesh] : nullptr;
+    const double *rot_dev = reinterpret_cast<const double *>(
+        reinterpret_cast<const char *>(sc.d_inst) + i * sizeof(DevInstance) + offsetof(DevInstance, rot));
+    // without grad_vel the velocity sum lands in vpart[0..2], after vpart has been read
+    double *vel_out = grad_vel ? grad_vel + 3 * i : ctx->adj_vpart;
+    const int64_t base = [&] {
+      int64_t b = 0;
+      for (size_t k = 0; k < i; ++k) b += static_cast<int64_t>(ctx->meshes[sc.inst[k].mesh].tris.size() / 3);
+      return b;
+    }();
+    HIP_TRY(ctx, launch_vertex_gather(ctx->adj_gxw, F, rcn.N, rcn.tc, rot_dev, base, m.d_csr_off,
+                                      m.d_csr_ent, static_cast<int32_t>(m.verts.size() / 3), gv,
+                                      ctx->adj_vpart, vel_out, s));
+  }
+  stage_end(ctx, timing, 7, s);
+  return RSIM_OK;
+}
+
+int32_t rsim_rdm_backward(rsim_ctx *ctx, const float *grad_rdm, const void *y, int32_t n_cubes,
+                          void *grad_echo, void *hip_stream) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!grad_rdm || !y || !grad_echo || n_cubes < 1)
+    return fail(ctx, RSIM_EINVAL, "rsim_rdm_backward: need grad_rdm, y, grad_echo, n_cubes >= 1");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
+  if (!is_pow2(M) || !is_pow2(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_rdm_backward: M and N must be powers of two");
+  if ((rc = need_device(ctx))) return rc;
+  const int64_t O = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3);
+  const int64_t planes = O * n_cubes;
+  void *Z = nullptr;
+  if ((rc = scratch(ctx, 8 * planes * N * M, &Z))) return rc;
+  void *twM = twiddles(ctx, M, 0, &rc);
+  if (rc) return rc;
+  void *twN = twiddles(ctx, N, 0, &rc);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool timing = ctx->timing_pending;
+  stage_begin(ctx, timing, 6, s);
+  HIP_TRY(ctx, launch_doppler_fft(0, y, Z, nullptr, planes, N, M, 2, twN, s, grad_rdm));
+  HIP_TRY(ctx, launch_range_fft(0, Z, grad_echo, planes * N, M, 0, twM, s));
+  stage_end(ctx, timing, 6, s);
+  return RSIM_OK;
 }
 
 int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm, void *y_opt,

@@ -19,206 +19,9 @@
 // reduced to turns (the only FP64 arithmetic of the sum); then G_f(m) for the tile's
 // samples and each element's phasor at every block start. Block starts are re-seeded
 // from FP64 phases, so the recurrence never runs more than MB steps.
-#include "rsim_internal.h"
-#include "rsim_launch.h"
+#include "echo_common.h"
 
 namespace rsim {
-
-template <typename R>
-struct Cx;
-template <>
-struct Cx<float> {
-  using T = float2;
-};
-template <>
-struct Cx<double> {
-  using T = double2;
-};
-
-template <typename R>
-struct EchoTraits;
-template <>
-struct EchoTraits<float> {
-  static constexpr int kSeriesTerms = 8;
-};
-template <>
-struct EchoTraits<double> {
-  static constexpr int kSeriesTerms = 16;
-};
-constexpr double kSeriesGap = 0.5;  // radians: series below, divided-difference form above
-
-struct alignas(8) Geo {
-  double c[3];        // centroid (world) at t_n
-  double tref_t, tref_r;
-  double beta[3];     // w . (x_i - c), metres
-  double amp_re, amp_im;  // G = amp * Phi
-  int32_t valid, pad;
-};
-
-__device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-__device__ inline void sincospi_t(float x, float *s, float *c) { sincospif(x, s, c); }
-__device__ inline void sincospi_t(double x, double *s, double *c) { sincospi(x, s, c); }
-
-// exp(-j 2 pi turns) * scale, with the FP64 phase reduced before the conversion.
-template <typename R>
-__device__ inline typename Cx<R>::T phasor_m2pi(double turns, R scale) {
-  const double r = turns - rint(turns);
-  R s, c;
-  sincospi_t(static_cast<R>(2.0 * r), &s, &c);
-  return {c * scale, -s * scale};
-}
-
-// First divided difference of -exp(jx) at nodes given in turns X, Y:
-// -j exp(j pi (X + Y)) sinc(pi (Y - X)).
-template <typename R>
-__device__ inline typename Cx<R>::T first_dd(double X, double Y) {
-  const double S = X + Y;
-  const double D = Y - X;
-  R cs, sn;
-  sincospi_t(static_cast<R>(S - 2.0 * rint(0.5 * S)), &sn, &cs);
-  R sc = R(1);
-  if (D != 0.0) {
-    R s_d, c_d;
-    sincospi_t(static_cast<R>(D - 2.0 * rint(0.5 * D)), &s_d, &c_d);
-    sc = s_d / static_cast<R>(kPi * D);
-  }
-  return {sn * sc, -cs * sc};
-}
-
-// Phi(a0, a1, a2): second divided difference of -exp(jx); nodes in turns (a = 2 pi A).
-template <typename R>
-__device__ typename Cx<R>::T phi_turns(double A0, double A1, double A2) {
-  using C = typename Cx<R>::T;
-  const double mean = (A0 + A1 + A2) / 3.0;
-  const double B0 = A0 - mean, B1 = A1 - mean, B2 = A2 - mean;
-  const double g12 = fabs(B1 - B2), g02 = fabs(B0 - B2), g01 = fabs(B0 - B1);
-  double Bl, Bi, Bj, gmax;
-  if (g12 >= g02 && g12 >= g01) {
-    Bl = B0; Bi = B1; Bj = B2; gmax = g12;
-  } else if (g02 >= g01) {
-    Bl = B1; Bi = B0; Bj = B2; gmax = g02;
-  } else {
-    Bl = B2; Bi = B0; Bj = B1; gmax = g01;
-  }
-  C phi0;
-  if (2.0 * kPi * gmax < kSeriesGap) {
-    // Taylor series about the mean: sum_n j^n h_n(b) / (n+2)!, h_n by the
-    // recurrence h_n = e1 h_{n-1} - e2 h_{n-2} + e3 h_{n-3}.
-    const R b0 = static_cast<R>(2.0 * kPi * B0);
-    const R b1 = static_cast<R>(2.0 * kPi * B1);
-    const R b2 = static_cast<R>(2.0 * kPi * B2);
-    const R e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
-    R hm3 = 0, hm2 = 0, hm1 = 1;  // h_{n-3}, h_{n-2}, h_{n-1} with h_0 = 1
-    R re = R(0.5), im = 0;        // n = 0 term: 1/2!
-    R inv_fact = R(0.5);
-    for (int n = 1; n <= EchoTraits<R>::kSeriesTerms; ++n) {
-      const R h = e1 * hm1 - e2 * hm2 + e3 * hm3;
-      hm3 = hm2;
-      hm2 = hm1;
-      hm1 = h;
-      inv_fact = inv_fact / static_cast<R>(n + 2);
-      const R term = h * inv_fact;
-      switch (n & 3) {  // j^n
-        case 0: re += term; break;
-        case 1: im += term; break;
-        case 2: re -= term; break;
-        default: im -= term; break;
-      }
-    }
-    phi0 = {re, im};
-  } else {
-    const C fj = first_dd<R>(Bl, Bj);
-    const C fi = first_dd<R>(Bl, Bi);
-    const R inv = static_cast<R>(1.0 / (2.0 * kPi * (Bj - Bi)));
-    phi0 = {(fj.x - fi.x) * inv, (fj.y - fi.y) * inv};
-  }
-  // shift back by the mean: Phi(a) = exp(j mean) Phi(a - mean)
-  R ms, mc;
-  const double mr = mean - rint(mean);
-  sincospi_t(static_cast<R>(2.0 * mr), &ms, &mc);
-  return {phi0.x * mc - phi0.y * ms, phi0.x * ms + phi0.y * mc};
-}
-
-__device__ inline int find_inst(const DevInstance *inst, int n_inst, int64_t f) {
-  int lo = 0, hi = n_inst - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (inst[mid].facet_base <= f)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// FP64 geometry of work entry `item` of chirp n (lit facet, or point after them).
-__device__ void entry_geometry(const DevScene &sc, const RadarConst &rc, int n, int32_t cnt,
-                               int32_t item, Geo &g) {
-  const double t = n * rc.tc;
-  const double inv_c = 1.0 / kC0;
-  double c[3];
-  if (item < cnt) {
-    const int64_t f = sc.vis_idx[static_cast<int64_t>(n) * sc.n_facets + item];
-    const int ii = find_inst(sc.inst, sc.n_inst, f);
-    const DevInstance &I = sc.inst[ii];
-    const int64_t lt = f - I.facet_base;
-    double x[3][3];
-    for (int v = 0; v < 3; ++v) {
-      const int32_t vi = I.tris[3 * lt + v];
-      const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
-      for (int k = 0; k < 3; ++k)
-        x[v][k] = I.rot[3 * k + 0] * b0 + I.rot[3 * k + 1] * b1 + I.rot[3 * k + 2] * b2 +
-                  (I.pos0[k] + I.vel[k] * t);
-    }
-    double e1[3], e2[3];
-    for (int k = 0; k < 3; ++k) {
-      c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
-      e1[k] = x[1][k] - x[0][k];
-      e2[k] = x[2][k] - x[0][k];
-    }
-    double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
-                    e1[0] * e2[1] - e1[1] * e2[0]};
-    const double two_area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-    double ut[3], ur[3];
-    for (int k = 0; k < 3; ++k) {
-      ut[k] = rc.tx_c[k] - c[k];
-      ur[k] = rc.rx_c[k] - c[k];
-    }
-    const double rt = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
-    const double rr = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
-    double w[3];
-    for (int k = 0; k < 3; ++k) w[k] = ut[k] / rt + ur[k] / rr;
-    const double obl = 0.5 * (nv[0] * w[0] + nv[1] * w[1] + nv[2] * w[2]) / two_area;
-    for (int v = 0; v < 3; ++v)
-      g.beta[v] = w[0] * (x[v][0] - c[0]) + w[1] * (x[v][1] - c[1]) + w[2] * (x[v][2] - c[2]);
-    // G = j o A Phi / (2 pi), A = two_area / 2
-    g.amp_re = 0.0;
-    g.amp_im = obl * 0.5 * two_area / (2.0 * kPi);
-    g.tref_t = rt * inv_c;
-    g.tref_r = rr * inv_c;
-    g.valid = two_area > 0.0;
-  } else {
-    const int32_t k = item - cnt;
-    for (int d = 0; d < 3; ++d) c[d] = sc.pt_pos0[3 * k + d] + sc.pt_vel[3 * k + d] * t;
-    double ut[3], ur[3];
-    for (int d = 0; d < 3; ++d) {
-      ut[d] = rc.tx_c[d] - c[d];
-      ur[d] = rc.rx_c[d] - c[d];
-    }
-    g.tref_t = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]) * inv_c;
-    g.tref_r = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]) * inv_c;
-    g.beta[0] = g.beta[1] = g.beta[2] = 0.0;
-    // Phi(0,0,0) = 1/2, so G = s / (4 pi) with amp = s / (2 pi)
-    g.amp_re = sc.pt_amp[2 * k + 0] / (2.0 * kPi);
-    g.amp_im = sc.pt_amp[2 * k + 1] / (2.0 * kPi);
-    g.valid = 1;
-  }
-  g.c[0] = c[0];
-  g.c[1] = c[1];
-  g.c[2] = c[2];
-}
 
 template <typename R, int MB, int FT>
 struct EchoSmem {

@@ -79,11 +79,14 @@ __global__ void __launch_bounds__(256) range_fft_kernel(const typename Cx2<R>::T
 // Columns of length N (stride M) of each channel's [N][M] plane.
 // mode 0 (forward): Y = shift_n(FFT_n(X)); writes rdm = |Y|^2 and y_out if given.
 // mode 1 (adjoint input side): Z = FFT_n(conj(unshift_n(G))) written to y_out.
+// mode 2 (RDM backward): as mode 1 with G = 2 (dL/dP) Y formed on the fly from
+//   gp = dL/dP (rdm-shaped) and in = Y, since P = |Y|^2.
 template <typename R>
 __global__ void __launch_bounds__(256) doppler_fft_kernel(const typename Cx2<R>::T *in,
                                                           typename Cx2<R>::T *y_out, R *rdm,
                                                           int64_t planes, int N, int M, int kt,
-                                                          int mode, const typename Cx2<R>::T *tw) {
+                                                          int mode, const typename Cx2<R>::T *tw,
+                                                          const R *gp) {
   using C = typename Cx2<R>::T;
   extern __shared__ __align__(16) unsigned char fft_smem[];
   const int ld = N + 1;
@@ -103,7 +106,13 @@ __global__ void __launch_bounds__(256) doppler_fft_kernel(const typename Cx2<R>:
     } else {
       // row l of G holds Doppler index l' = l - N/2; place it at l' mod N, conjugated
       const int lp = (n + hN) & (N - 1);
-      C v = src[static_cast<int64_t>(n) * M + k0 + c];
+      const int64_t gi = static_cast<int64_t>(n) * M + k0 + c;
+      C v = src[gi];
+      if (mode == 2) {
+        const R s = R(2) * gp[plane * static_cast<int64_t>(N) * M + gi];
+        v.x *= s;
+        v.y *= s;
+      }
       v.y = -v.y;
       a[c * ld + lp] = v;
     }
@@ -141,7 +150,8 @@ static hipError_t launch_range_t(const void *in, void *out, int64_t rows, int M,
 
 template <typename R>
 static hipError_t launch_doppler_t(const void *in, void *y_out, void *rdm, int64_t planes, int N,
-                                   int M, int mode, const void *tw, hipStream_t s) {
+                                   int M, int mode, const void *tw, hipStream_t s,
+                                   const void *gp) {
   using C = typename Cx2<R>::T;
   const int budget = (sizeof(R) == 4) ? 2048 : 1024;
   int kt = max(1, min(32, budget / N));
@@ -151,7 +161,8 @@ static hipError_t launch_doppler_t(const void *in, void *y_out, void *rdm, int64
   const size_t lds = 2 * sizeof(C) * kt * (N + 1);
   hipLaunchKernelGGL(doppler_fft_kernel<R>, dim3(grid), dim3(256), lds, s,
                      static_cast<const C *>(in), static_cast<C *>(y_out), static_cast<R *>(rdm),
-                     planes, N, M, kt, mode, static_cast<const C *>(tw));
+                     planes, N, M, kt, mode, static_cast<const C *>(tw),
+                     static_cast<const R *>(gp));
   return hipGetLastError();
 }
 
@@ -163,9 +174,9 @@ hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t ro
 
 hipError_t launch_doppler_fft(int precision, const void *in, void *y_out, void *rdm,
                               int64_t planes, int N, int M, int mode, const void *tw,
-                              hipStream_t s) {
-  return precision ? launch_doppler_t<double>(in, y_out, rdm, planes, N, M, mode, tw, s)
-                   : launch_doppler_t<float>(in, y_out, rdm, planes, N, M, mode, tw, s);
+                              hipStream_t s, const void *gp) {
+  return precision ? launch_doppler_t<double>(in, y_out, rdm, planes, N, M, mode, tw, s, gp)
+                   : launch_doppler_t<float>(in, y_out, rdm, planes, N, M, mode, tw, s, gp);
 }
 
 }  // namespace rsim

@@ -37,6 +37,19 @@ hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t ro
                             int conj_in, const void *tw, hipStream_t s);
 hipError_t launch_doppler_fft(int precision, const void *in, void *y_out, void *rdm,
                               int64_t planes, int N, int M, int mode, const void *tw,
-                              hipStream_t s);
+                              hipStream_t s, const void *gp = nullptr);
+
+// adjoint of the facet sum (FP32): partial sums per (chirp, lit facet, tile), then
+// per-facet world-vertex gradients gxw [N][F][9]
+size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F);
+size_t adjoint_smem_bytes(const EchoShape &sh);
+int adjoint_tile_m();
+hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
+                          const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
+                          hipStream_t s);
+hipError_t launch_vertex_gather(const float *gxw, int64_t n_facets, int N, double tc,
+                                const double *rot_dev, int64_t facet_base, const int32_t *csr_off,
+                                const int32_t *csr_ent, int32_t n_verts, float *gv, double *vpart,
+                                double *vel_out, hipStream_t s);
 
 }  // namespace rsim

@@ -37,6 +37,7 @@ class Simulator:
         self.wf = waveform
         self.O = self.ctx.n_channels
         self.scene_ids = [self.ctx.load_scene(s) for s in scenes]
+        self.inst_pos0 = [[np.asarray(i.pos0, np.float64) for i in s.instances] for s in scenes]
         self.n_facets = [self.ctx.scene_info(s)[0] for s in self.scene_ids]
         self.mask_words = [self.ctx.scene_info(s)[1] for s in self.scene_ids]
         self.dev = torch.device("cuda", device)

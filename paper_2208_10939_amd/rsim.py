@@ -32,7 +32,8 @@ EXPORTS = (
     "rsim_load_mesh", "rsim_create_scene", "rsim_add_instance", "rsim_add_points",
     "rsim_scene_info", "rsim_set_waveform", "rsim_set_array", "rsim_synthesize",
     "rsim_form_rdm", "rsim_last_timings", "rsim_backward", "rsim_rdm_adjoint",
-    "rsim_autotune", "rsim_sync",
+    "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
+    "rsim_rdm_backward",
 )
 
 
@@ -89,6 +90,9 @@ def lib() -> ctypes.CDLL:
         "rsim_rdm_adjoint": ([vp, vp, i32, vp, vp], i32),
         "rsim_autotune": ([vp, ctypes.POINTER(i32), i32, ctypes.c_char_p], i32),
         "rsim_sync": ([vp, vp], i32),
+        "rsim_update_mesh": ([vp, i32, vp, i64], i32),
+        "rsim_set_instance_motion": ([vp, i32, i32, dp, dp], i32),
+        "rsim_rdm_backward": ([vp, vp, vp, i32, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -185,6 +189,16 @@ class Context:
         self._check(self._L.rsim_add_points(self._h, scene, _dptr(p), _dptr(v), _dptr(ari),
                                             p.shape[0]))
 
+    def update_mesh(self, mesh: int, verts):
+        v = np.ascontiguousarray(verts, dtype=np.float32)
+        self._check(self._L.rsim_update_mesh(self._h, int(mesh), v.ctypes.data, v.shape[0]))
+
+    def set_instance_motion(self, scene: int, inst: int, pos0, vel):
+        p = np.ascontiguousarray(pos0, np.float64).reshape(3)
+        v = np.ascontiguousarray(vel, np.float64).reshape(3)
+        self._check(self._L.rsim_set_instance_motion(self._h, int(scene), int(inst), _dptr(p),
+                                                     _dptr(v)))
+
     def scene_info(self, scene: int):
         nf, nw = ctypes.c_int64(), ctypes.c_int64()
         self._check(self._L.rsim_scene_info(self._h, scene, ctypes.byref(nf), ctypes.byref(nw)))
@@ -199,6 +213,9 @@ class Context:
             self.add_instance(sid, mesh_ids[inst.mesh], inst.rot, inst.pos0, inst.vel)
         if getattr(scene, "points", None) is not None and scene.points.n:
             self.add_points(sid, scene.points.pos0, scene.points.vel, scene.points.amp)
+        if not hasattr(self, "scene_meshes"):
+            self.scene_meshes = {}
+        self.scene_meshes[sid] = mesh_ids
         return sid
 
     # ---- radar -------------------------------------------------------------------
@@ -239,8 +256,12 @@ class Context:
         self._check(self._L.rsim_rdm_adjoint(self._h, _ptr(grad_y), int(n_cubes),
                                               _ptr(grad_echo), _stream(stream)))
 
+    def rdm_backward(self, grad_rdm, y, grad_echo, n_cubes: int = 1, stream=None):
+        self._check(self._L.rsim_rdm_backward(self._h, _ptr(grad_rdm), _ptr(y), int(n_cubes),
+                                              _ptr(grad_echo), _stream(stream)))
+
     def backward(self, scene: int, grad_echo, mask, grad_verts: Sequence, grad_vel, stream=None):
-        arr = (ctypes.c_void_p * len(grad_verts))(*[_ptr(g) for g in grad_verts])
+        arr = (ctypes.c_void_p * max(1, len(grad_verts)))(*[_ptr(g) for g in grad_verts])
         self._check(self._L.rsim_backward(self._h, int(scene), _ptr(grad_echo), _ptr(mask), arr,
                                           len(grad_verts), _ptr(grad_vel), _stream(stream)))
 

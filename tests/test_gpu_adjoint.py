@@ -1,0 +1,143 @@
+"""GPU adjoint vs FP64 central finite differences of the oracle's RDM loss.
+
+Loss L = sum (RDM - T)^2 with T the oracle RDM of a perturbed copy of the scene. The
+lit-facet mask is the oracle's and is held fixed on both sides (the GPU receives it as
+an input mask). Finite differences perturb body-frame vertices (in float64, oracle
+only) and instance velocities."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from scenes import Instance, Mesh, RadarArray, Scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _setup():
+    wf = scenes.paper_waveform(32, 8)
+    full = scenes.sparse_mimo_12x16(wf, 5)
+    arr = RadarArray(tx=full.tx[:3].copy(), rx=full.rx[:5].copy())
+    car = scenes.vehicle_mesh("car", 700)
+    moto = scenes.vehicle_mesh("motorcycle", 400)
+    insts = [Instance(0, scenes.yaw_matrix(1.5), np.array([3.0, 18.0, 0.0]), np.array([0.3, -6.0, 0.0])),
+             Instance(1, scenes.yaw_matrix(-1.4), np.array([-4.0, 24.0, 0.0]), np.array([-0.5, 4.0, 0.0]))]
+    sc = Scene([car, moto], insts)
+    target = scenes.perturbed(sc, 77, pos_sigma=0.02, vel_sigma=0.3, vert_sigma=2e-3)
+    return wf, arr, sc, target
+
+
+def _with(sc, mesh_k=None, vert=None, axis=None, dv=0.0, inst_k=None, vaxis=None, dvel=0.0):
+    meshes = []
+    for k, m in enumerate(sc.meshes):
+        v = m.verts.astype(np.float64)
+        if k == mesh_k:
+            v = v.copy()
+            v[vert, axis] += dv
+        meshes.append(Mesh(verts=v, tris=m.tris, name=m.name))
+    insts = []
+    for k, i in enumerate(sc.instances):
+        vel = i.vel.copy()
+        if k == inst_k:
+            vel[vaxis] += dvel
+        insts.append(Instance(i.mesh, i.rot, i.pos0, vel))
+    return Scene(meshes, insts)
+
+
+def test_adjoint_matches_finite_differences():
+    import torch
+    from paper_2208_10939_amd.pipeline import Simulator
+    _log("case adjoint vs FD (2 vehicles, 3x5 channels, M=32, N=8)")
+    wf, arr, sc, target = _setup()
+    mask, amb = oracle.visibility(sc, arr, wf)
+    T, _ = oracle.rdm_from_echo(oracle.synthesize(target, wf, arr))
+
+    def loss(scene):
+        P, _ = oracle.rdm_from_echo(oracle.synthesize(scene, wf, arr, mask=mask))
+        return oracle.rdm_loss(P, T)
+
+    sim = Simulator([sc], wf, arr)
+    m_t = sim.mask_from_numpy([mask])
+    echo = sim.synthesize(mask=m_t, mask_mode=1)
+    rdm, y = sim.form_rdm(echo, want_y=True)
+    Tt = torch.from_numpy(T.astype(np.float32)).cuda()[None]
+    grad_rdm = 2.0 * (rdm - Tt)
+    grad_echo = torch.empty_like(echo)
+    sim.ctx.rdm_backward(grad_rdm.contiguous(), y, grad_echo)
+    gverts = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+              for m in sc.meshes]
+    gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+    sim.ctx.backward(sim.scene_ids[0], grad_echo, m_t, gverts, gvel)
+    gverts = [g.cpu().numpy().astype(np.float64) for g in gverts]
+    gvel = gvel.cpu().numpy()
+
+    # sampled vertices of facets lit at chirp 0
+    rng = np.random.default_rng(11)
+    tri, inst_of, local_of = oracle.world_triangles(sc, 0.0)
+    lit_f = np.nonzero(mask[0])[0]
+    picks = []
+    for f in rng.choice(lit_f, size=8, replace=False):
+        k = inst_of[f]
+        picks.append((sc.instances[k].mesh, int(sc.meshes[sc.instances[k].mesh].tris[local_of[f], rng.integers(0, 3)])))
+    h = 1e-5
+    fd, ad = [], []
+    for (mk, v) in picks:
+        for ax in range(3):
+            lp = loss(_with(sc, mk, v, ax, +h))
+            lm = loss(_with(sc, mk, v, ax, -h))
+            fd.append((lp - lm) / (2 * h))
+            ad.append(gverts[mk][v, ax])
+    hv = 1e-2
+    for ik in range(len(sc.instances)):
+        for ax in range(2):
+            lp = loss(_with(sc, inst_k=ik, vaxis=ax, dvel=+hv))
+            lm = loss(_with(sc, inst_k=ik, vaxis=ax, dvel=-hv))
+            fd.append((lp - lm) / (2 * hv))
+            ad.append(gvel[ik, ax])
+    fd = np.array(fd)
+    ad = np.array(ad)
+    rel_l2 = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    big = np.abs(fd) > 1e-3 * np.abs(fd).max()
+    rel_c = np.abs(ad - fd)[big] / np.abs(fd)[big]
+    _log(f"  L={loss(sc):.4e} rel_l2={rel_l2:.3e} max_rel_component={rel_c.max():.3e} "
+         f"(n={fd.size}, ambiguous={amb.sum()})")
+    for a, b in zip(ad, fd):
+        _log(f"    adj {a:+.6e} fd {b:+.6e}")
+    assert rel_l2 <= 1e-3
+    assert rel_c.max() <= 1e-2
+
+
+def test_autograd_function_matches_direct_calls():
+    import torch
+    from paper_2208_10939_amd.autograd import RadarRDM
+    from paper_2208_10939_amd.pipeline import Simulator
+    _log("case RadarRDM autograd")
+    wf, arr, sc, target = _setup()
+    sim = Simulator([sc], wf, arr)
+    verts = [torch.from_numpy(m.verts.copy()).requires_grad_(True) for m in sc.meshes]
+    vel = torch.from_numpy(np.stack([i.vel for i in sc.instances])).requires_grad_(True)
+    rdm = RadarRDM.apply(sim, 0, vel, *verts)
+    T, _ = oracle.rdm_from_echo(oracle.synthesize(target, wf, arr))
+    L = ((rdm - torch.from_numpy(T.astype(np.float32)).cuda()) ** 2).sum()
+    L.backward()
+    assert verts[0].grad is not None and vel.grad is not None
+    assert torch.isfinite(verts[0].grad).all() and torch.isfinite(vel.grad).all()
+    assert verts[0].grad.abs().max() > 0
+    # same numbers through the explicit calls with the forward's own mask
+    mask_t = sim.mask_buffer()
+    echo = sim.synthesize(mask=mask_t)
+    P, y = sim.form_rdm(echo, want_y=True)
+    ge = torch.empty_like(echo)
+    sim.ctx.rdm_backward((2.0 * (P - torch.from_numpy(T.astype(np.float32)).cuda()[None])).contiguous(), y, ge)
+    gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda") for m in sc.meshes]
+    gvel = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    sim.ctx.backward(sim.scene_ids[0], ge, mask_t, gv, gvel)
+    assert torch.allclose(verts[0].grad.cuda(), gv[0], rtol=1e-5, atol=1e-6 * gv[0].abs().max().item())
+    assert torch.allclose(vel.grad.cuda(), gvel, rtol=1e-5, atol=1e-8 * gvel.abs().max().item())
