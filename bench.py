@@ -83,6 +83,91 @@ def cpu_baseline(cfg, channels=32):
                        f"{lit} lit facets; numpy float64, single thread")}
 
 
+def measure_fwd_bwd(sim, reps=3):
+    """Forward (echo + RDM) and forward + backward (RDM adjoint + facet-sum adjoint +
+    vertex/velocity gather) for the loss sum (RDM - T)^2 with a fixed target T."""
+    import numpy as np
+    import torch
+    echo = sim.echo_buffer(1)
+    mask = sim.mask_buffer()
+    rdm = torch.empty(echo.shape, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(echo)
+    sid = sim.scene_ids[0]
+    sim.ctx.synthesize([sid], echo, mask)
+    sim.ctx.form_rdm(echo, rdm, y)
+    target = (0.5 * rdm).contiguous()
+    ge = torch.empty_like(echo)
+    meshes = sim.ctx.scene_meshes[sid]
+    gv = [None] * (max(meshes) + 1)
+    for mid in meshes:
+        nv = sim.ctx.mesh_nverts[mid]
+        gv[mid] = torch.zeros((nv, 3), dtype=torch.float32, device="cuda")
+    gvel = torch.zeros((len(sim.inst_pos0[0]), 3), dtype=torch.float64, device="cuda")
+    fwd, tot, stages = [], [], None
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.ctx.synthesize([sid], echo, mask, timing=True)
+        sim.ctx.form_rdm(echo, rdm, y, timing=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        grad = (2.0 * (rdm - target)).contiguous()
+        sim.ctx.rdm_backward(grad, y, ge)
+        sim.ctx.backward(sid, ge, mask, gv, gvel)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        stages = sim.ctx.last_timings()
+        fwd.append(t1 - t0)
+        tot.append(t2 - t0)
+    fwd_ms = 1e3 * float(np.median(fwd[1:]))
+    tot_ms = 1e3 * float(np.median(tot[1:]))
+    return {"fwd_ms": fwd_ms, "fwd_bwd_ms": tot_ms, "ratio": tot_ms / fwd_ms,
+            "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
+
+
+def measure_batched(n_scenes=8, reps=3):
+    """A slice of the 64-scene batched workload (seeds 400...): one persistent,
+    graph-captured launch over all scenes vs one plain launch per scene (equal
+    accuracy: the per-scene results are bit-identical, checked here)."""
+    import numpy as np
+    import torch
+    import scenes
+    from paper_2208_10939_amd.pipeline import Simulator
+    cfg = scenes.c4(n_scenes=n_scenes)
+    sim = Simulator(cfg.scenes, cfg.waveform, cfg.array)
+    n = len(cfg.scenes)
+    plain = sim.echo_buffer(n)
+    batched = sim.echo_buffer(n)
+    mask = sim.mask_buffer()
+
+    def run_plain():
+        for i in range(n):
+            sim.ctx.synthesize([sim.scene_ids[i]], plain[i:i + 1], None)
+
+    def run_batched():
+        sim.ctx.synthesize(sim.scene_ids, batched, mask, persistent=True, use_graph=True)
+
+    times = {}
+    for name, fn in (("plain", run_plain), ("batched", run_batched)):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        times[name] = 1e3 * float(np.median(ts))
+    lit = sum(int(m.sum()) for m in sim.masks_numpy(mask))
+    evals = lit * cfg.waveform.n_samples * cfg.array.n_channels
+    same = bool(torch.equal(plain, batched))
+    return {"scenes": n, "triangles": int(sum(s.n_tris for s in cfg.scenes)),
+            "plain_ms": times["plain"], "batched_ms": times["batched"],
+            "plain_evals_per_s": evals / (times["plain"] * 1e-3),
+            "batched_evals_per_s": evals / (times["batched"] * 1e-3),
+            "bit_identical": same}
+
+
 def calib_copy(mib: int):
     """Plain elementwise copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -101,6 +186,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the forward+backward and batched-vs-plain measurements")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--tile-f", type=int, default=0)
@@ -190,6 +277,11 @@ def main():
             "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
         },
     }
+    if not args.no_extras:
+        _log("bench: forward + backward")
+        out["fwd_bwd"] = measure_fwd_bwd(sim)
+        _log("bench: batched vs plain (8 scenes of the 64-scene workload)")
+        out["batched_vs_plain"] = measure_batched()
     if not args.no_cpu:
         _log("bench: timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -24,8 +24,10 @@ namespace {
 
 constexpr int kAdjVals = 8;  // grad_c (3), sum Re y, t0, t1, t2, pad
 
-__device__ inline float sinc_d(float u, float *sinc_out) {
-  // sinc(u) = sin u / u and its derivative (cos u - sinc u) / u
+// sinc(u) = sin u / u and its derivative (cos u - sinc u) / u at u = pi D, D in turns
+// (FP64, reduced before the FP32 trigonometry).
+__device__ inline float sinc_d(double D, float *sinc_out) {
+  const float u = static_cast<float>(kPi * D);
   const float au = fabsf(u);
   if (au < 0.05f) {
     const float u2 = u * u;
@@ -33,7 +35,7 @@ __device__ inline float sinc_d(float u, float *sinc_out) {
     return u * (-1.0f / 3.0f + u2 * (1.0f / 30.0f - u2 * (1.0f / 840.0f)));
   }
   float s, c;
-  sincosf(u, &s, &c);
+  sincospi_t(static_cast<float>(D - 2.0 * rint(0.5 * D)), &s, &c);
   const float sc = s / u;
   *sinc_out = sc;
   return (c - sc) / u;
@@ -109,10 +111,9 @@ __device__ void phi_grad_turns(double A0, double A1, double A2, float2 *phi, flo
       const double X = B[l], Y = B[other[k]];
       const double S = X + Y;
       float cs, sn;
-      sincospif(static_cast<float>(S - 2.0 * rint(0.5 * S)), &sn, &cs);
-      const float u = static_cast<float>(kPi * (Y - X));
+      sincospi_t(static_cast<float>(S - 2.0 * rint(0.5 * S)), &sn, &cs);
       float sc;
-      const float scd = sinc_d(u, &sc);
+      const float scd = sinc_d(Y - X, &sc);
       // K = -j exp(js) = (sn, -cs)
       F[k] = make_float2(sn * sc, -cs * sc);
       // dF/dx = K (-sinc'/2 + j sinc/2),  dF/dy = K (sinc'/2 + j sinc/2)
@@ -128,7 +129,7 @@ __device__ void phi_grad_turns(double A0, double A1, double A2, float2 *phi, flo
     d[i] = make_float2((p0.x - Fy[1].x) * inv, (p0.y - Fy[1].y) * inv);
   }
   float ms, mc;
-  sincospif(static_cast<float>(2.0 * (mean - rint(mean))), &ms, &mc);
+  sincospi_t(static_cast<float>(2.0 * (mean - rint(mean))), &ms, &mc);
   *phi = make_float2(p0.x * mc - p0.y * ms, p0.x * ms + p0.y * mc);
   for (int k = 0; k < 3; ++k)
     dphi[k] = make_float2(d[k].x * mc - d[k].y * ms, d[k].x * ms + d[k].y * mc);
@@ -144,8 +145,7 @@ template <int MB, int FT>
 struct AdjSmem {
   double *elem;  // [E][3]
   Geo *geo;      // [FT]
-  float2 *G;     // [FT][M_t]
-  float2 *D;     // [FT][3][M_t]
+  float4 *GD;    // [FT][M_t][2]: (G, D0), (D1, D2)
   float2 *U;     // [FT][E][B_w]
   float2 *rat;   // [FT][E]
   float *off;    // [FT][E]
@@ -163,8 +163,7 @@ struct AdjSmem {
     };
     elem = reinterpret_cast<double *>(take(sizeof(double) * 3 * sh.E));
     geo = reinterpret_cast<Geo *>(take(sizeof(Geo) * FT));
-    G = reinterpret_cast<float2 *>(take(sizeof(float2) * FT * sh.M_t));
-    D = reinterpret_cast<float2 *>(take(sizeof(float2) * FT * 3 * sh.M_t));
+    GD = reinterpret_cast<float4 *>(take(sizeof(float4) * FT * 2 * sh.M_t));
     U = reinterpret_cast<float2 *>(take(sizeof(float2) * FT * sh.E * sh.B_w));
     rat = reinterpret_cast<float2 *>(take(sizeof(float2) * FT * sh.E));
     off = reinterpret_cast<float *>(take(sizeof(float) * FT * sh.E));
@@ -180,8 +179,7 @@ struct AdjSmem {
     };
     take(sizeof(double) * 3 * sh.E);
     take(sizeof(Geo) * FT);
-    take(sizeof(float2) * FT * sh.M_t);
-    take(sizeof(float2) * FT * 3 * sh.M_t);
+    take(sizeof(float4) * FT * 2 * sh.M_t);
     take(sizeof(float2) * FT * sh.E * sh.B_w);
     take(sizeof(float2) * FT * sh.E);
     take(sizeof(float) * FT * sh.E);
@@ -192,9 +190,34 @@ struct AdjSmem {
   }
 };
 
-__device__ inline float wave_sum(float v) {
+// Sum over the 64 lanes of a wave: DPP moves inside each 16-lane row (no LDS round
+// trips), then the four row sums read out with readlane (the DPP row-broadcast
+// controls do not exist on this GPU generation). Fixed order: deterministic.
+template <int kCtrl, int kRowMask>
+__device__ inline float dpp_add(float v) {
+  const int t = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, kRowMask, 0xF,
+                                            false);
+  return v + __builtin_bit_cast(float, t);
+}
+
+// DPP reads the registers of inactive lanes as they are, so it is used only when the
+// workgroup is made of whole waves; partial waves take the permute path.
+__device__ inline float wave_sum_partial(float v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+__device__ inline float wave_sum(float v) {
+  v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]: quad sums
+  v = dpp_add<0x141, 0xF>(v);  // row_half_mirror: 8-lane sums
+  v = dpp_add<0x140, 0xF>(v);  // row_mirror: 16-lane (row) sums in every lane
+  const int iv = __builtin_bit_cast(int, v);
+  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 0));
+  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 16));
+  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 32));
+  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 template <int MB, int FT>
@@ -205,6 +228,7 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
   extern __shared__ __align__(16) unsigned char adj_smem[];
   const EchoShape &sh = ash.sh;
   const int waves = (blockDim.x + 63) / 64;
+  const bool whole_waves = (blockDim.x & 63) == 0;
   AdjSmem<MB, FT> sm;
   sm.carve(adj_smem, sh, waves);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -303,8 +327,9 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
           dv[k] = make_float2(km * (ar * dph[k].x - ai * dph[k].y),
                               km * (ar * dph[k].y + ai * dph[k].x));
       }
-      sm.G[i * sh.M_t + j] = gv;
-      for (int k = 0; k < 3; ++k) sm.D[(i * 3 + k) * sh.M_t + j] = dv[k];
+      float4 *dst = sm.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;
+      dst[0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
+      dst[1] = make_float4(dv[1].x, dv[1].y, dv[2].x, dv[2].y);
     }
     __syncthreads();
     for (int i = 0; i < nf; ++i) {
@@ -317,28 +342,39 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
         float2 z = make_float2(up.x * uq.x - up.y * uq.y, up.x * uq.y + up.y * uq.x);
         z = make_float2(z.x - eps * z.y, z.y + eps * z.x);
         const float2 r = make_float2(rp.x * rq.x - rp.y * rq.y, rp.x * rq.y + rp.y * rq.x);
-        const float2 *Gi = sm.G + i * sh.M_t + b * MB;
-        const float2 *D0 = sm.D + (i * 3 + 0) * sh.M_t + b * MB;
-        const float2 *D1 = sm.D + (i * 3 + 1) * sh.M_t + b * MB;
-        const float2 *D2 = sm.D + (i * 3 + 2) * sh.M_t + b * MB;
+        // per sample: (G, D0) and (D1, D2) as two 16-byte LDS reads, a block ahead
+        const float4 *gd = sm.GD + (static_cast<int64_t>(i) * sh.M_t + b * MB) * 2;
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        constexpr int kB = 2;
+        float4 ca[2 * kB], cb[2 * kB];
 #pragma unroll
-        for (int j = 0; j < MB; ++j) {
-          const float2 w = make_float2(fma_r(gq[j].x, z.x, -gq[j].y * z.y),
-                                       fma_r(gq[j].x, z.y, gq[j].y * z.x));
-          const float2 G = Gi[j];
-          const float yx = fma_r(G.x, w.x, -G.y * w.y);
-          const float yy = fma_r(G.x, w.y, G.y * w.x);
-          s0 += yx;
-          s1 += yy;
-          s2 = fma_r(static_cast<float>(m_base + j), yy, s2);
-          const float2 d0 = D0[j], d1 = D1[j], d2 = D2[j];
-          a0 = fma_r(d0.x, w.x, fma_r(-d0.y, w.y, a0));
-          a1 = fma_r(d1.x, w.x, fma_r(-d1.y, w.y, a1));
-          a2 = fma_r(d2.x, w.x, fma_r(-d2.y, w.y, a2));
-          const float zx = fma_r(z.x, r.x, -z.y * r.y);
-          z.y = fma_r(z.x, r.y, z.y * r.x);
-          z.x = zx;
+        for (int u = 0; u < 2 * kB; ++u) ca[u] = gd[u];
+#pragma unroll
+        for (int j0 = 0; j0 < MB; j0 += kB) {
+          if (j0 + kB < MB) {
+#pragma unroll
+            for (int u = 0; u < 2 * kB; ++u) cb[u] = gd[2 * (j0 + kB) + u];
+          }
+#pragma unroll
+          for (int jj = 0; jj < kB; ++jj) {
+            const int j = j0 + jj;
+            const float4 g0 = ca[2 * jj], g1 = ca[2 * jj + 1];  // (G, D0), (D1, D2)
+            const float2 w = make_float2(fma_r(gq[j].x, z.x, -gq[j].y * z.y),
+                                         fma_r(gq[j].x, z.y, gq[j].y * z.x));
+            const float yx = fma_r(g0.x, w.x, -g0.y * w.y);
+            const float yy = fma_r(g0.x, w.y, g0.y * w.x);
+            s0 += yx;
+            s1 += yy;
+            s2 = fma_r(static_cast<float>(m_base + j), yy, s2);
+            a0 = fma_r(g0.z, w.x, fma_r(-g0.w, w.y, a0));
+            a1 = fma_r(g1.x, w.x, fma_r(-g1.y, w.y, a1));
+            a2 = fma_r(g1.z, w.x, fma_r(-g1.w, w.y, a2));
+            const float zx = fma_r(z.x, r.x, -z.y * r.y);
+            z.y = fma_r(z.x, r.y, z.y * r.x);
+            z.x = zx;
+          }
+#pragma unroll
+          for (int u = 0; u < 2 * kB; ++u) ca[u] = cb[u];
         }
         // dL/dR_p and dL/dR_q of this channel, then onto the centroid: dR/dc = -e_hat
         const float tpq = sm.tau[i * E + p] + sm.tau[i * E + P + q];
@@ -357,7 +393,7 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
       const int wv = tid >> 6;
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
-        const float s = wave_sum(v[k]);
+        const float s = whole_waves ? wave_sum(v[k]) : wave_sum_partial(v[k]);
         if ((tid & 63) == 0) sm.red[(i * waves + wv) * kAdjVals + k] = s;
       }
     }
@@ -529,7 +565,7 @@ __global__ void __launch_bounds__(256) velocity_reduce_kernel(const double *vpar
 }  // namespace
 
 constexpr int kAdjMB = 32;
-constexpr int kAdjFT = 8;
+constexpr int kAdjFT = 16;
 
 size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F) {
   return static_cast<size_t>(N) * F * sh.m_tiles * sh.o_tiles * kAdjVals;

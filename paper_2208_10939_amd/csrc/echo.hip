@@ -200,11 +200,29 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
       }
     }
   }
-  if (o_ok) {
-    C *out = static_cast<C *>(sc.echo) + (static_cast<int64_t>(o) * rc.N + n) * rc.M;
+  // Store through LDS in chunks of kOut samples: each thread parks kOut accumulators,
+  // then consecutive lanes write consecutive samples of one channel row, so a wave
+  // writes whole 128-byte runs instead of one 8-byte value per row.
+  constexpr int kOut = (MB < 16) ? MB : 16;
+  C *stage = sm.G;  // the host sizes LDS for O_w x kOut values here
+  C *echo_out = static_cast<C *>(sc.echo);
+  for (int bb = 0; bb < sh.B_w; ++bb) {
 #pragma unroll
-    for (int j = 0; j < MB; ++j)
-      if (m_base + j < rc.M) out[m_base + j] = acc[j];
+    for (int jc = 0; jc < MB; jc += kOut) {
+      __syncthreads();
+      if (b == bb) {
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) stage[ol * kOut + j] = acc[jc + j];
+      }
+      __syncthreads();
+      const int m0 = m_tile0 + bb * MB + jc;
+      for (int e = tid; e < sh.O_w * kOut; e += nthr) {
+        const int oo = ot * sh.O_w + e / kOut;
+        const int m = m0 + e % kOut;
+        if (oo < sh.O && m < rc.M)
+          echo_out[(static_cast<int64_t>(oo) * rc.N + n) * rc.M + m] = stage[e];
+      }
+    }
   }
 }
 
@@ -256,9 +274,11 @@ static size_t smem_bytes(const EchoShape &sh) {
   b = (b + 15) & ~size_t(15);
   b += sizeof(Geo) * FT;
   b = (b + 15) & ~size_t(15);
-  b += sizeof(C) * FT * sh.M_t + sizeof(C) * FT * sh.E * sh.B_w + sizeof(C) * FT * sh.E +
-       sizeof(R) * FT * sh.E;
-  return b;
+  const size_t tile = sizeof(C) * FT * sh.M_t + sizeof(C) * FT * sh.E * sh.B_w +
+                      sizeof(C) * FT * sh.E + sizeof(R) * FT * sh.E;
+  // the output staging reuses the tile region from G on: O_w x min(MB, 16) values
+  const size_t out_stage = sizeof(C) * sh.O_w * ((MB < 16) ? MB : 16);
+  return b + (tile > out_stage ? tile : out_stage);
 }
 
 // Host-side dispatch over the compiled (precision, MB, FT) variants.

@@ -41,7 +41,14 @@ struct alignas(8) Geo {
 __device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-__device__ inline void sincospi_t(float x, float *s, float *c) { sincospif(x, s, c); }
+// sin(pi x), cos(pi x) for |x| <= 1 (every caller reduces first). The FP32 version uses
+// the hardware transcendental unit, which takes revolutions; its error on this range
+// was measured at <= 1.3e-7 absolute on MI355X (ocml sincospif: 5e-8).
+__device__ inline void sincospi_t(float x, float *s, float *c) {
+  const float r = 0.5f * x;
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
 __device__ inline void sincospi_t(double x, double *s, double *c) { sincospi(x, s, c); }
 
 // exp(-j 2 pi turns) * scale, with the FP64 phase reduced before the conversion.

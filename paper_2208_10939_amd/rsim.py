@@ -165,6 +165,9 @@ class Context:
         out = ctypes.c_int32()
         self._check(self._L.rsim_load_mesh(self._h, v.ctypes.data, v.shape[0], t.ctypes.data,
                                            t.shape[0], ctypes.byref(out)))
+        if not hasattr(self, "mesh_nverts"):
+            self.mesh_nverts = {}
+        self.mesh_nverts[out.value] = v.shape[0]
         return out.value
 
     def create_scene(self) -> int:

@@ -114,6 +114,57 @@ def test_adjoint_matches_finite_differences():
     assert rel_c.max() <= 1e-2
 
 
+def test_adjoint_full_array_matches_finite_differences():
+    """Same check with the 12 x 16 sparse array (192 channels: whole-wave workgroups,
+    the DPP reduction path) at a small frame."""
+    import torch
+    from paper_2208_10939_amd.pipeline import Simulator
+    _log("case adjoint vs FD (192 channels, M=16, N=4)")
+    wf = scenes.paper_waveform(16, 4)
+    arr = scenes.sparse_mimo_12x16(wf, 6)
+    car = scenes.vehicle_mesh("car", 500)
+    sc = Scene([car], [Instance(0, scenes.yaw_matrix(1.6), np.array([2.0, 15.0, 0.0]),
+                                np.array([0.2, -5.0, 0.0]))])
+    target = scenes.perturbed(sc, 78, pos_sigma=0.02, vel_sigma=0.3, vert_sigma=2e-3)
+    mask, amb = oracle.visibility(sc, arr, wf)
+    T, _ = oracle.rdm_from_echo(oracle.synthesize(target, wf, arr))
+
+    def loss(scene):
+        P, _ = oracle.rdm_from_echo(oracle.synthesize(scene, wf, arr, mask=mask))
+        return oracle.rdm_loss(P, T)
+
+    sim = Simulator([sc], wf, arr)
+    m_t = sim.mask_from_numpy([mask])
+    echo = sim.synthesize(mask=m_t, mask_mode=1)
+    rdm, y = sim.form_rdm(echo, want_y=True)
+    grad_rdm = 2.0 * (rdm - torch.from_numpy(T.astype(np.float32)).cuda()[None])
+    ge = torch.empty_like(echo)
+    sim.ctx.rdm_backward(grad_rdm.contiguous(), y, ge)
+    gv = [torch.zeros((car.verts.shape[0], 3), dtype=torch.float32, device="cuda")]
+    gvel = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    sim.ctx.backward(sim.scene_ids[0], ge, m_t, gv, gvel)
+    gv = gv[0].cpu().numpy().astype(np.float64)
+    gvel = gvel.cpu().numpy()
+    rng = np.random.default_rng(12)
+    lit_f = np.nonzero(mask[0])[0]
+    verts = [int(car.tris[f, rng.integers(0, 3)]) for f in rng.choice(lit_f, 4, replace=False)]
+    fd, ad = [], []
+    for v in verts:
+        for ax in range(3):
+            d = (loss(_with(sc, 0, v, ax, 1e-5)) - loss(_with(sc, 0, v, ax, -1e-5))) / 2e-5
+            fd.append(d)
+            ad.append(gv[v, ax])
+    for ax in range(2):
+        d = (loss(_with(sc, inst_k=0, vaxis=ax, dvel=1e-2)) -
+             loss(_with(sc, inst_k=0, vaxis=ax, dvel=-1e-2))) / 2e-2
+        fd.append(d)
+        ad.append(gvel[0, ax])
+    fd, ad = np.array(fd), np.array(ad)
+    rel_l2 = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    _log(f"  rel_l2={rel_l2:.3e} (n={fd.size})")
+    assert rel_l2 <= 1e-3
+
+
 def test_autograd_function_matches_direct_calls():
     import torch
     from paper_2208_10939_amd.autograd import RadarRDM
