@@ -37,7 +37,7 @@ def _log(msg):
 
 def _src_hash():
     h = hashlib.sha256()
-    for f in ("echo.hip",):
+    for f in ("echo.hip", "echo_common.h"):
         with open(os.path.join(ROOT, "paper_2208_10939_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
