@@ -22,7 +22,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("facet·freq·channel·chirp evals/s + ms per RDM frame; "
           "fwd+bwd vs fwd, batched vs plain")
-FLOP_PER_EVAL = 14  # one complex phasor step (6) + one complex multiply-accumulate (8)
+# Per facet.freq.channel.chirp evaluation: one phasor step by the three-term recurrence
+# z_{m+1} = 2 cos(t) z_m - z_{m-1} (2 FMA = 4 FLOP) + one complex multiply-accumulate
+# (4 FMA = 8 FLOP).
+FLOP_PER_EVAL = 12
 # VALU FP32 FMA issue without packed-math instructions: 256 CU x 4 SIMD x 16 lanes x
 # 2 FLOP x 2.4 GHz. Packed FP32 (v_pk_fma_f32) would double it to the published
 # 157.3 TFLOP/s; this build keeps packed FP32 out of all device code.
@@ -221,6 +224,17 @@ def main():
         sim.ctx.synthesize([sim.scene_ids[0]], echo, mask, timing=timing, **kw)
         sim.ctx.form_rdm(echo, rdm, None, n_cubes=1, timing=timing)
 
+    tuned = None
+    if not (args.tile_m or args.tile_f):
+        # tile shapes from the library's autotuner, timed on this workload
+        import tempfile
+        fd, tune_path = tempfile.mkstemp(suffix=".jsonl")
+        os.close(fd)
+        sim.ctx.autotune([sim.scene_ids[0]], tune_path)
+        with open(tune_path) as f:
+            tuned = json.loads(f.read().strip().splitlines()[-1])
+        os.remove(tune_path)
+        _log(f"bench: autotuned facet-sum tile {tuned['tile_m']} x {tuned['tile_f']}")
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -262,7 +276,9 @@ def main():
                                "(192 ch), 256 samples x 128 chirps, FP32 sum + FP64 phase",
                    "triangles": int(sc.n_tris), "channels": int(arr.n_channels),
                    "samples": int(wf.n_samples), "chirps": int(wf.n_chirps),
-                   "lit_facets_per_chirp": float(lit.mean()), "seed": cfg.seed},
+                   "lit_facets_per_chirp": float(lit.mean()), "seed": cfg.seed,
+                   "facet_sum_tile": (tuned if tuned else
+                                      {"tile_m": args.tile_m, "tile_f": args.tile_f})},
         "stage_ms": stage_avg,
         "roofline": {
             "bound": "alu",

@@ -29,6 +29,7 @@ struct EchoSmem {
   double *elem;  // [E][3]
   Geo *geo;      // [FT]
   C *G;          // [FT][M_t]
+  C *G1;         // [FT][M_t]: G (-j)^(m mod 4), for quarter-turn-rotated recurrences
   C *U;          // [FT][E][B_w]
   C *rat;        // [FT][E]
   R *off;        // [FT][E]
@@ -42,6 +43,8 @@ struct EchoSmem {
     b += sizeof(Geo) * FT;
     b = (b + 15) & ~size_t(15);
     G = reinterpret_cast<C *>(base + b);
+    b += sizeof(C) * FT * sh.M_t;
+    G1 = reinterpret_cast<C *>(base + b);
     b += sizeof(C) * FT * sh.M_t;
     U = reinterpret_cast<C *>(base + b);
     b += sizeof(C) * FT * sh.E * sh.B_w;
@@ -137,6 +140,15 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
         val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
       }
       sm.G[i * sh.M_t + j] = val;
+      // (-j)^(j mod 4): block starts are multiples of 4 samples
+      C v1;
+      switch (j & 3) {
+        case 0: v1 = val; break;
+        case 1: v1 = {val.y, -val.x}; break;
+        case 2: v1 = {-val.x, -val.y}; break;
+        default: v1 = {-val.y, val.x}; break;
+      }
+      sm.G1[i * sh.M_t + j] = v1;
     }
     __syncthreads();
     // stage C: accumulate. Per sample: one complex multiply-accumulate (4 FMA) and
@@ -163,6 +175,20 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
           z = {fma_r(-eps, z.y, z.x), fma_r(eps, z.x, z.y)};
         }
         const C r = {fma_r(rp.x, rq.x, -rp.y * rq.y), fma_r(rp.x, rq.y, rp.y * rq.x)};
+        // FP32: advance the phasor with the three-term recurrence
+        //   z_{m+1} = 2 cos(t) z_m - z_{m-1}   (2 FMA instead of a complex multiply),
+        // whose error grows like 1/|sin t|. When |sin t| < |cos t| the ramp is rotated by a
+        // quarter turn per sample (r -> j r, so |sin| >= 0.707) and the lane reads G
+        // pre-rotated by (-j)^m instead, which undoes it exactly.
+        bool quarter = false;
+        C zn = z;
+        R c2 = R(0);
+        if constexpr (sizeof(R) == 4) {
+          quarter = fabsf(r.y) < fabsf(r.x);
+          const C rk = quarter ? C{-r.y, r.x} : r;
+          c2 = R(2) * rk.x;
+          zn = {fma_r(z.x, rk.x, -z.y * rk.y), fma_r(z.x, rk.y, z.y * rk.x)};
+        }
         if (i + 1 < nf) {
           up = sm.U[(i + 1) * stride_u + iu_p];
           uq = sm.U[(i + 1) * stride_u + iu_q];
@@ -171,7 +197,7 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
           op = sm.off[(i + 1) * E + p];
           oq = sm.off[(i + 1) * E + P + q];
         }
-        const C *Gi = sm.G + i * sh.M_t + b * MB;
+        const C *Gi = (quarter ? sm.G1 : sm.G) + i * sh.M_t + b * MB;
         constexpr int kBlk = (MB < 8) ? MB : 8;
         C ga[kBlk], gb[kBlk];
 #pragma unroll
@@ -190,9 +216,15 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
             a.x = fma_r(-g.y, z.y, a.x);
             a.y = fma_r(g.x, z.y, a.y);
             a.y = fma_r(g.y, z.x, a.y);
-            const R zx = fma_r(z.x, r.x, -z.y * r.y);
-            z.y = fma_r(z.x, r.y, z.y * r.x);
-            z.x = zx;
+            if constexpr (sizeof(R) == 4) {
+              const C zz = {fma_r(c2, zn.x, -z.x), fma_r(c2, zn.y, -z.y)};
+              z = zn;
+              zn = zz;
+            } else {
+              const R zx = fma_r(z.x, r.x, -z.y * r.y);
+              z.y = fma_r(z.x, r.y, z.y * r.x);
+              z.x = zx;
+            }
           }
 #pragma unroll
           for (int j = 0; j < kBlk; ++j) ga[j] = gb[j];
@@ -274,7 +306,7 @@ static size_t smem_bytes(const EchoShape &sh) {
   b = (b + 15) & ~size_t(15);
   b += sizeof(Geo) * FT;
   b = (b + 15) & ~size_t(15);
-  const size_t tile = sizeof(C) * FT * sh.M_t + sizeof(C) * FT * sh.E * sh.B_w +
+  const size_t tile = 2 * sizeof(C) * FT * sh.M_t + sizeof(C) * FT * sh.E * sh.B_w +
                       sizeof(C) * FT * sh.E + sizeof(R) * FT * sh.E;
   // the output staging reuses the tile region from G on: O_w x min(MB, 16) values
   const size_t out_stage = sizeof(C) * sh.O_w * ((MB < 16) ? MB : 16);
