@@ -69,8 +69,10 @@ typedef struct {
   int32_t use_graph; /* batched call: capture the launches in a hipGraph and replay it  */
   int32_t persistent;/* batched call: one persistent facet-sum launch over a work queue  */
   int32_t timing;    /* record per-stage HIP events (read with rsim_last_timings)        */
-  int32_t tile_m;    /* facet-sum samples per thread (0 = autotuned/default; 8..64)       */
-  int32_t tile_f;    /* facets staged per LDS tile (0 = default; 4..32)                   */
+  int32_t tile_m;    /* facet-sum samples per thread (0 = autotuned/default)              */
+  int32_t tile_f;    /* facets staged per LDS tile (0 = default). Compiled (tile_m,      */
+                     /* tile_f): FP32 16x16 32x8 32x16 64x8 64x16, FP64 8x8 16x8; others  */
+                     /* fail with RSIM_EINVAL                                            */
   int32_t reserved;
 } rsim_opts;
 

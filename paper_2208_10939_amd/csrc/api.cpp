@@ -347,17 +347,28 @@ TunedShape pick_shape(const rsim_ctx *ctx, int precision, const rsim_opts &o) {
   return s;
 }
 
-EchoShape echo_shape(const rsim_ctx *ctx, const RadarConst &rc, int mb) {
+EchoShape echo_shape(const rsim_ctx *ctx, const RadarConst &rc, int mb, int max_threads = 512,
+                     int max_blocks = 1 << 30) {
   EchoShape sh{};
   sh.O = rc.P * rc.Q;
   sh.E = rc.P + rc.Q;
   sh.O_w = std::min(sh.O, 256);
   sh.o_tiles = (sh.O + sh.O_w - 1) / sh.O_w;
   const int blocks_needed = (rc.M + mb - 1) / mb;
-  sh.B_w = std::max(1, std::min(blocks_needed, 512 / sh.O_w));
+  sh.B_w = std::max(1, std::min({blocks_needed, max_threads / sh.O_w, max_blocks}));
   sh.M_t = sh.B_w * mb;
   sh.m_tiles = (rc.M + sh.M_t - 1) / sh.M_t;
+  sh.n_compute = (sh.O_w * sh.B_w + 63) / 64 * 64;
   sh.two_pi_slope = 2.0 * kPi * rc.slope;
+  return sh;
+}
+
+// Shape of the forward facet sum: at most kMaxComputeThreads accumulating threads (plus
+// the staging waves), and as many sample blocks as fit the LDS double buffer.
+EchoShape forward_shape(const rsim_ctx *ctx, const RadarConst &rc, int precision, int mb, int ft) {
+  EchoShape sh = echo_shape(ctx, rc, mb, kMaxComputeThreads);
+  while (sh.B_w > 1 && echo_smem_bytes(precision, mb, ft, sh) > ctx->max_lds)
+    sh = echo_shape(ctx, rc, mb, kMaxComputeThreads, sh.B_w - 1);
   return sh;
 }
 
@@ -562,7 +573,7 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
   const RadarConst rc = radar_const(ctx);
   const int precision = o.precision;
   const TunedShape ts = pick_shape(ctx, precision, o);
-  const EchoShape sh = echo_shape(ctx, rc, ts.mb);
+  const EchoShape sh = forward_shape(ctx, rc, precision, ts.mb, ts.ft);
   if (o.mask_mode == RSIM_MASK_COMPUTE) {
     stage_begin(ctx, timing, 0, s);
     for (auto &d : ds) HIP_TRY(ctx, launch_visibility(d, rc, s));
@@ -866,7 +877,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
   if (!echo_variant_exists(o.precision, ts.mb, ts.ft))
     return fail(ctx, RSIM_EINVAL, "no facet-sum variant with tile_m=%d tile_f=%d", ts.mb, ts.ft);
   if ((rc = need_device(ctx))) return rc;
-  const EchoShape sh = echo_shape(ctx, rcn, ts.mb);
+  const EchoShape sh = forward_shape(ctx, rcn, o.precision, ts.mb, ts.ft);
   if (echo_smem_bytes(o.precision, ts.mb, ts.ft, sh) > ctx->max_lds)
     return fail(ctx, RSIM_ERANGE, "facet-sum tile needs %zu bytes of LDS (max %zu)",
                 echo_smem_bytes(o.precision, ts.mb, ts.ft, sh), ctx->max_lds);
@@ -1117,7 +1128,7 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
   void *echo = nullptr;
   if ((rc = dev_alloc(ctx, &echo, 8 * cube * n_scenes))) return rc;
   struct Cand { int mb, ft; };
-  const Cand cands[] = {{16, 16}, {32, 8}, {32, 16}, {32, 32}, {64, 8}, {64, 16}, {64, 32}};
+  const Cand cands[] = {{16, 16}, {32, 8}, {32, 16}, {64, 8}, {64, 16}};
   float best = 1e30f;
   TunedShape best_s{32, 16};
   hipStream_t s = ctx->capture_stream;
@@ -1126,7 +1137,7 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
     o.tile_m = c.mb;
     o.tile_f = c.ft;
     o.timing = 1;
-    const EchoShape sh = echo_shape(ctx, rcn, c.mb);
+    const EchoShape sh = forward_shape(ctx, rcn, 0, c.mb, c.ft);
     if (echo_smem_bytes(0, c.mb, c.ft, sh) > ctx->max_lds) continue;
     float total = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {

@@ -12,134 +12,169 @@
 // the arrays here; it is applied as a short Taylor polynomial, exact to rounding).
 //
 // Work split (one item = chirp n x sample tile x channel tile): a workgroup holds
-// O_w channels x B_w sample blocks; thread (o, b) keeps MB consecutive samples of one
-// channel in registers and advances its phasor from sample to sample with one complex
-// multiply (phase linear in m under stop-and-hop). Per tile of FT lit facets the
-// workgroup stages through LDS, in FP64: facet geometry, element distances, phases
-// reduced to turns (the only FP64 arithmetic of the sum); then G_f(m) for the tile's
-// samples and each element's phasor at every block start. Block starts are re-seeded
-// from FP64 phases, so the recurrence never runs more than MB steps.
+// n_compute accumulating threads, thread (o, b) keeping MB consecutive samples of one
+// channel in registers, and two staging waves. The lit facets are taken in tiles of FT;
+// while the accumulating threads sum tile k from one LDS buffer, the staging waves fill
+// the other with tile k + 1, in FP64: facet geometry, element distances, phases reduced
+// to turns (the only FP64 arithmetic of the sum); then G_f(m) for the tile's samples and
+// each element's phasor at every block start. One workgroup barrier per tile hands the
+// buffers over. Block starts are re-seeded from FP64 phases, so a phasor recurrence
+// never runs more than MB steps.
 #include "echo_common.h"
 
 namespace rsim {
 
 template <typename R, int MB, int FT>
-struct EchoSmem {
+struct EchoLayout {
   using C = typename Cx<R>::T;
-  double *elem;  // [E][3]
-  Geo *geo;      // [FT]
-  C *G;          // [FT][M_t]
-  C *G1;         // [FT][M_t]: G (-j)^(m mod 4), for quarter-turn-rotated recurrences
-  C *U;          // [FT][E][B_w]
-  C *rat;        // [FT][E]
-  R *off;        // [FT][E]
+  static constexpr bool kRotated = sizeof(R) == 4;  // FP32 keeps G (-j)^m as well
+  size_t elem, geo, buf[2], G, G1, U, rat, off, total;
 
-  __device__ void carve(unsigned char *base, const EchoShape &sh) {
+  __host__ __device__ explicit EchoLayout(const EchoShape &sh) {
+    auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
     size_t b = 0;
-    elem = reinterpret_cast<double *>(base + b);
-    b += sizeof(double) * 3 * sh.E;
-    b = (b + 15) & ~size_t(15);
-    geo = reinterpret_cast<Geo *>(base + b);
-    b += sizeof(Geo) * FT;
-    b = (b + 15) & ~size_t(15);
-    G = reinterpret_cast<C *>(base + b);
-    b += sizeof(C) * FT * sh.M_t;
-    G1 = reinterpret_cast<C *>(base + b);
-    b += sizeof(C) * FT * sh.M_t;
-    U = reinterpret_cast<C *>(base + b);
-    b += sizeof(C) * FT * sh.E * sh.B_w;
-    rat = reinterpret_cast<C *>(base + b);
-    b += sizeof(C) * FT * sh.E;
-    off = reinterpret_cast<R *>(base + b);
+    elem = b;
+    b = up(b + sizeof(double) * 3 * sh.E);
+    geo = b;  // [2 staging waves][FT]
+    b = up(b + sizeof(Geo) * 2 * FT);
+    // offsets inside one tile buffer
+    size_t t = 0;
+    G = t;
+    t += sizeof(C) * FT * sh.M_t;
+    G1 = t;
+    t += kRotated ? sizeof(C) * FT * sh.M_t : 0;
+    U = t;
+    t += sizeof(C) * FT * sh.E * sh.B_w;
+    rat = t;
+    t += sizeof(C) * FT * sh.E;
+    off = t;
+    t = up(t + sizeof(R) * FT * sh.E);
+    buf[0] = b;
+    buf[1] = b + t;
+    // the output staging reuses the tile buffers: O_w x min(MB, 16) values
+    const size_t out_stage = sizeof(C) * sh.O_w * ((MB < 16) ? MB : 16);
+    total = b + (2 * t > out_stage ? 2 * t : out_stage);
   }
 };
 
 template <typename R, int MB, int FT>
-__device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
-                          EchoSmem<R, MB, FT> &sm, int n, int mt, int ot) {
+struct EchoTile {
   using C = typename Cx<R>::T;
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  const int P = rc.P, Q = rc.Q, E = sh.E;
-  const int ol = tid % sh.O_w;
-  const int b = tid / sh.O_w;
-  const int o = ot * sh.O_w + ol;
-  const bool o_ok = o < sh.O;
-  const int p = o_ok ? o / Q : 0;
-  const int q = o_ok ? o % Q : 0;
-  const int m_tile0 = mt * sh.M_t;
-  const int m_base = m_tile0 + b * MB;
-  const int32_t cnt = sc.vis_cnt[n];
-  const int32_t total = cnt + sc.n_points;
+  C *G;    // [FT][M_t]
+  C *G1;   // [FT][M_t]: G (-j)^(m mod 4), for quarter-turn-rotated recurrences (FP32)
+  C *U;    // [FT][E][B_w]
+  C *rat;  // [FT][E]
+  R *off;  // [FT][E]
+};
+
+template <typename R, int MB, int FT>
+struct EchoSmem {
+  using C = typename Cx<R>::T;
+  double *elem;  // [E][3]
+  Geo *geo;      // [2][FT]: one private copy per staging wave
+  unsigned char *buf0;
+  size_t buf_stride, oG, oG1, oU, orat, ooff;
+
+  __device__ void carve(unsigned char *base, const EchoShape &sh) {
+    const EchoLayout<R, MB, FT> L(sh);
+    elem = reinterpret_cast<double *>(base + L.elem);
+    geo = reinterpret_cast<Geo *>(base + L.geo);
+    buf0 = base + L.buf[0];
+    buf_stride = L.buf[1] - L.buf[0];
+    oG = L.G;
+    oG1 = L.G1;
+    oU = L.U;
+    orat = L.rat;
+    ooff = L.off;
+  }
+  // tile buffer k (0 or 1), by address arithmetic so no array of pointers is indexed
+  __device__ EchoTile<R, MB, FT> tile(int k) const {
+    unsigned char *t = buf0 + static_cast<size_t>(k) * buf_stride;
+    return {reinterpret_cast<C *>(t + oG), reinterpret_cast<C *>(t + oG1),
+            reinterpret_cast<C *>(t + oU), reinterpret_cast<C *>(t + orat),
+            reinterpret_cast<R *>(t + ooff)};
+  }
+};
+
+// Orders a wave's own LDS writes before its later LDS reads by other lanes.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Staging of one tile (entries t0 .. t0 + nf - 1 of chirp n) by the staging waves,
+// st = staging thread index in [0, kStagingThreads).
+template <typename R, int MB, int FT>
+__device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                           const EchoSmem<R, MB, FT> &sm, const EchoTile<R, MB, FT> &tl, int n,
+                           int32_t cnt, int32_t t0, int nf, int m_tile0, int st) {
+  using C = typename Cx<R>::T;
+  const int P = rc.P, E = sh.E;
   const double slope = rc.slope;
-
-  C acc[MB];
-#pragma unroll
-  for (int j = 0; j < MB; ++j) acc[j] = {R(0), R(0)};
-
-  for (int32_t t0 = 0; t0 < total; t0 += FT) {
-    const int nf = min(FT, total - t0);
-    __syncthreads();  // previous tile fully consumed
-    // stage A: facet / point geometry (FP64)
-    for (int i = tid; i < FT; i += nthr) {
-      if (i < nf)
-        entry_geometry(sc, rc, n, cnt, t0 + i, sm.geo[i]);
-      else
-        sm.geo[i].valid = 0;
+  // A: facet / point geometry (FP64). Each staging wave computes the whole tile into its
+  // own copy, so the reads below need no workgroup barrier.
+  Geo *geo = sm.geo + (st >> 6) * FT;
+  for (int i = st & 63; i < FT; i += 64) {
+    if (i < nf)
+      entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
+    else
+      geo[i].valid = 0;
+  }
+  wave_lds_sync();
+  // B1: per element distance, phases in FP64 reduced to turns
+  for (int task = st; task < FT * E; task += kStagingThreads) {
+    const int i = task / E, e = task % E;
+    const Geo &g = geo[i];
+    C *Ue = tl.U + (i * E + e) * sh.B_w;
+    if (!g.valid) {
+      for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = {R(0), R(0)};
+      tl.rat[i * E + e] = {R(1), R(0)};
+      tl.off[i * E + e] = R(0);
+      continue;
     }
-    __syncthreads();
-    // stage B1: per element distance, phases in FP64 reduced to turns
-    for (int task = tid; task < FT * E; task += nthr) {
-      const int i = task / E, e = task % E;
-      const Geo &g = sm.geo[i];
-      C *Ue = sm.U + (i * E + e) * sh.B_w;
-      if (!g.valid) {
-        for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = {R(0), R(0)};
-        sm.rat[i * E + e] = {R(1), R(0)};
-        sm.off[i * E + e] = R(0);
-        continue;
-      }
-      const double dx = sm.elem[3 * e + 0] - g.c[0];
-      const double dy = sm.elem[3 * e + 1] - g.c[1];
-      const double dz = sm.elem[3 * e + 2] - g.c[2];
-      const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
-      const double tau = Rn / kC0;
-      double psi0, offv;
-      if (e < P) {
-        const double d = tau - g.tref_t;
-        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
-               0.5 * slope * g.tref_t * g.tref_r;
-        offv = sh.two_pi_slope * d;
-      } else {
-        const double d = tau - g.tref_r;
-        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
-               0.5 * slope * g.tref_t * g.tref_r;
-        offv = d;
-      }
-      psi0 -= floor(psi0);
-      double delta = rc.df * tau;
-      delta -= floor(delta);
-      const R inv_r = static_cast<R>(1.0 / Rn);
-      for (int bb = 0; bb < sh.B_w; ++bb) {
-        const double m0 = static_cast<double>(m_tile0 + bb * MB);
-        Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
-      }
-      sm.rat[i * E + e] = phasor_m2pi<R>(delta, R(1));
-      sm.off[i * E + e] = static_cast<R>(offv);
+    const double dx = sm.elem[3 * e + 0] - g.c[0];
+    const double dy = sm.elem[3 * e + 1] - g.c[1];
+    const double dz = sm.elem[3 * e + 2] - g.c[2];
+    const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
+    const double tau = Rn / kC0;
+    double psi0, offv;
+    if (e < P) {
+      const double d = tau - g.tref_t;
+      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
+             0.5 * slope * g.tref_t * g.tref_r;
+      offv = sh.two_pi_slope * d;
+    } else {
+      const double d = tau - g.tref_r;
+      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
+             0.5 * slope * g.tref_t * g.tref_r;
+      offv = d;
     }
-    // stage B2: G_f(m) for the tile's samples
-    for (int task = tid; task < FT * sh.M_t; task += nthr) {
-      const int i = task / sh.M_t, j = task % sh.M_t;
-      const Geo &g = sm.geo[i];
-      C val = {R(0), R(0)};
-      if (g.valid) {
-        const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
-        const double s = fm / kC0;  // turns per metre
-        const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
-        const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
-        val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
-      }
-      sm.G[i * sh.M_t + j] = val;
+    psi0 -= floor(psi0);
+    double delta = rc.df * tau;
+    delta -= floor(delta);
+    const R inv_r = static_cast<R>(1.0 / Rn);
+    for (int bb = 0; bb < sh.B_w; ++bb) {
+      const double m0 = static_cast<double>(m_tile0 + bb * MB);
+      Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
+    }
+    tl.rat[i * E + e] = phasor_m2pi<R>(delta, R(1));
+    tl.off[i * E + e] = static_cast<R>(offv);
+  }
+  // B2: G_f(m) for the tile's samples
+  for (int task = st; task < FT * sh.M_t; task += kStagingThreads) {
+    const int i = task / sh.M_t, j = task % sh.M_t;
+    const Geo &g = geo[i];
+    C val = {R(0), R(0)};
+    if (g.valid) {
+      const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
+      const double s = fm / kC0;  // turns per metre
+      const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
+      const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
+      val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
+    }
+    tl.G[i * sh.M_t + j] = val;
+    if constexpr (EchoLayout<R, MB, FT>::kRotated) {
       // (-j)^(j mod 4): block starts are multiples of 4 samples
       C v1;
       switch (j & 3) {
@@ -148,101 +183,149 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
         case 2: v1 = {-val.x, -val.y}; break;
         default: v1 = {-val.y, val.x}; break;
       }
-      sm.G1[i * sh.M_t + j] = v1;
+      tl.G1[i * sh.M_t + j] = v1;
     }
-    __syncthreads();
-    // stage C: accumulate. Per sample: one complex multiply-accumulate (4 FMA) and
-    // one phasor step (2 MUL + 2 FMA). G is read from LDS in blocks of 8 samples,
-    // double-buffered in registers; the next facet's element phasors are prefetched.
-    if (o_ok) {
-      const int iu_p = p * sh.B_w + b, iu_q = (P + q) * sh.B_w + b;
-      const int stride_u = E * sh.B_w;
-      C up = sm.U[iu_p], uq = sm.U[iu_q];
-      C rp = sm.rat[p], rq = sm.rat[P + q];
-      R op = sm.off[p], oq = sm.off[P + q];
-      for (int i = 0; i < nf; ++i) {
-        const R eps = op * oq;
-        C z = {fma_r(up.x, uq.x, -up.y * uq.y), fma_r(up.x, uq.y, up.y * uq.x)};
-        if constexpr (sizeof(R) == 8) {
-          // exp(j eps) to fourth order (|eps| <= 1e-3 is enforced on the host)
-          const R e2 = eps * eps;
-          const C ce = {R(1) - e2 * (R(0.5) - e2 * R(1.0 / 24.0)),
-                        eps * (R(1) - e2 * R(1.0 / 6.0))};
-          z = {z.x * ce.x - z.y * ce.y, z.x * ce.y + z.y * ce.x};
-        } else {
-          // exp(j eps) ~ 1 + j eps: the host keeps |eps| <= 3e-4, so eps^2 / 2 stays
-          // below FP32 rounding
-          z = {fma_r(-eps, z.y, z.x), fma_r(eps, z.x, z.y)};
-        }
-        const C r = {fma_r(rp.x, rq.x, -rp.y * rq.y), fma_r(rp.x, rq.y, rp.y * rq.x)};
-        // FP32: advance the phasor with the three-term recurrence
-        //   z_{m+1} = 2 cos(t) z_m - z_{m-1}   (2 FMA instead of a complex multiply),
-        // whose error grows like 1/|sin t|. When |sin t| < |cos t| the ramp is rotated by a
-        // quarter turn per sample (r -> j r, so |sin| >= 0.707) and the lane reads G
-        // pre-rotated by (-j)^m instead, which undoes it exactly.
-        bool quarter = false;
-        C zn = z;
-        R c2 = R(0);
+  }
+}
+
+// Accumulation of one staged tile of nf entries into a thread's MB samples. Per sample:
+// one complex multiply-accumulate (4 FMA) and one phasor step. G is read from LDS in
+// blocks of 8 samples, double-buffered in registers; the next facet's element phasors
+// are prefetched.
+template <typename R, int MB, int FT>
+__device__ inline void sum_tile(const RadarConst &rc, const EchoShape &sh,
+                                const EchoTile<R, MB, FT> &tl, int nf, int p, int q, int b,
+                                typename Cx<R>::T (&acc)[MB]) {
+  using C = typename Cx<R>::T;
+  const int P = rc.P, E = sh.E;
+  const int iu_p = p * sh.B_w + b, iu_q = (P + q) * sh.B_w + b;
+  const int stride_u = E * sh.B_w;
+  C up = tl.U[iu_p], uq = tl.U[iu_q];
+  C rp = tl.rat[p], rq = tl.rat[P + q];
+  R op = tl.off[p], oq = tl.off[P + q];
+  for (int i = 0; i < nf; ++i) {
+    const R eps = op * oq;
+    C z = {fma_r(up.x, uq.x, -up.y * uq.y), fma_r(up.x, uq.y, up.y * uq.x)};
+    if constexpr (sizeof(R) == 8) {
+      // exp(j eps) to fourth order (|eps| <= 1e-3 is enforced on the host)
+      const R e2 = eps * eps;
+      const C ce = {R(1) - e2 * (R(0.5) - e2 * R(1.0 / 24.0)), eps * (R(1) - e2 * R(1.0 / 6.0))};
+      z = {z.x * ce.x - z.y * ce.y, z.x * ce.y + z.y * ce.x};
+    } else {
+      // exp(j eps) ~ 1 + j eps: the host keeps |eps| <= 3e-4, so eps^2 / 2 stays
+      // below FP32 rounding
+      z = {fma_r(-eps, z.y, z.x), fma_r(eps, z.x, z.y)};
+    }
+    const C r = {fma_r(rp.x, rq.x, -rp.y * rq.y), fma_r(rp.x, rq.y, rp.y * rq.x)};
+    // FP32: advance the phasor with the three-term recurrence
+    //   z_{m+1} = 2 cos(t) z_m - z_{m-1}   (2 FMA instead of a complex multiply),
+    // whose error grows like 1/|sin t|. When |sin t| < |cos t| the ramp is rotated by a
+    // quarter turn per sample (r -> j r, so |sin| >= 0.707) and the lane reads G
+    // pre-rotated by (-j)^m instead, which undoes it exactly.
+    bool quarter = false;
+    C zn = z;
+    R c2 = R(0);
+    if constexpr (sizeof(R) == 4) {
+      quarter = fabsf(r.y) < fabsf(r.x);
+      const C rk = quarter ? C{-r.y, r.x} : r;
+      c2 = R(2) * rk.x;
+      zn = {fma_r(z.x, rk.x, -z.y * rk.y), fma_r(z.x, rk.y, z.y * rk.x)};
+    }
+    if (i + 1 < nf) {
+      up = tl.U[(i + 1) * stride_u + iu_p];
+      uq = tl.U[(i + 1) * stride_u + iu_q];
+      rp = tl.rat[(i + 1) * E + p];
+      rq = tl.rat[(i + 1) * E + P + q];
+      op = tl.off[(i + 1) * E + p];
+      oq = tl.off[(i + 1) * E + P + q];
+    }
+    const C *Gi = (quarter ? tl.G1 : tl.G) + i * sh.M_t + b * MB;
+    constexpr int kBlk = (MB < 8) ? MB : 8;
+    C ga[kBlk], gb[kBlk];
+#pragma unroll
+    for (int j = 0; j < kBlk; ++j) ga[j] = Gi[j];
+#pragma unroll
+    for (int j0 = 0; j0 < MB; j0 += kBlk) {
+      if (j0 + kBlk < MB) {
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) gb[j] = Gi[j0 + kBlk + j];
+      }
+#pragma unroll
+      for (int j = 0; j < kBlk; ++j) {
+        const C g = ga[j];
+        C &a = acc[j0 + j];
+        a.x = fma_r(g.x, z.x, a.x);
+        a.x = fma_r(-g.y, z.y, a.x);
+        a.y = fma_r(g.x, z.y, a.y);
+        a.y = fma_r(g.y, z.x, a.y);
         if constexpr (sizeof(R) == 4) {
-          quarter = fabsf(r.y) < fabsf(r.x);
-          const C rk = quarter ? C{-r.y, r.x} : r;
-          c2 = R(2) * rk.x;
-          zn = {fma_r(z.x, rk.x, -z.y * rk.y), fma_r(z.x, rk.y, z.y * rk.x)};
-        }
-        if (i + 1 < nf) {
-          up = sm.U[(i + 1) * stride_u + iu_p];
-          uq = sm.U[(i + 1) * stride_u + iu_q];
-          rp = sm.rat[(i + 1) * E + p];
-          rq = sm.rat[(i + 1) * E + P + q];
-          op = sm.off[(i + 1) * E + p];
-          oq = sm.off[(i + 1) * E + P + q];
-        }
-        const C *Gi = (quarter ? sm.G1 : sm.G) + i * sh.M_t + b * MB;
-        constexpr int kBlk = (MB < 8) ? MB : 8;
-        C ga[kBlk], gb[kBlk];
-#pragma unroll
-        for (int j = 0; j < kBlk; ++j) ga[j] = Gi[j];
-#pragma unroll
-        for (int j0 = 0; j0 < MB; j0 += kBlk) {
-          if (j0 + kBlk < MB) {
-#pragma unroll
-            for (int j = 0; j < kBlk; ++j) gb[j] = Gi[j0 + kBlk + j];
-          }
-#pragma unroll
-          for (int j = 0; j < kBlk; ++j) {
-            const C g = ga[j];
-            C &a = acc[j0 + j];
-            a.x = fma_r(g.x, z.x, a.x);
-            a.x = fma_r(-g.y, z.y, a.x);
-            a.y = fma_r(g.x, z.y, a.y);
-            a.y = fma_r(g.y, z.x, a.y);
-            if constexpr (sizeof(R) == 4) {
-              const C zz = {fma_r(c2, zn.x, -z.x), fma_r(c2, zn.y, -z.y)};
-              z = zn;
-              zn = zz;
-            } else {
-              const R zx = fma_r(z.x, r.x, -z.y * r.y);
-              z.y = fma_r(z.x, r.y, z.y * r.x);
-              z.x = zx;
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < kBlk; ++j) ga[j] = gb[j];
+          const C zz = {fma_r(c2, zn.x, -z.x), fma_r(c2, zn.y, -z.y)};
+          z = zn;
+          zn = zz;
+        } else {
+          const R zx = fma_r(z.x, r.x, -z.y * r.y);
+          z.y = fma_r(z.x, r.y, z.y * r.x);
+          z.x = zx;
         }
       }
+#pragma unroll
+      for (int j = 0; j < kBlk; ++j) ga[j] = gb[j];
+    }
+  }
+}
+
+// One work item. Every thread of the workgroup reaches each barrier the same number of
+// times: the tile count depends only on the chirp's lit count.
+template <typename R, int MB, int FT>
+__device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                          EchoSmem<R, MB, FT> &sm, int n, int mt, int ot) {
+  using C = typename Cx<R>::T;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const bool staging = tid >= sh.n_compute;
+  const int st = tid - sh.n_compute;
+  const int Q = rc.Q;
+  const int ol = tid % sh.O_w;
+  const int b = tid / sh.O_w;
+  const int o = ot * sh.O_w + ol;
+  const bool o_ok = !staging && b < sh.B_w && o < sh.O;
+  const int p = o_ok ? o / Q : 0;
+  const int q = o_ok ? o % Q : 0;
+  const int m_tile0 = mt * sh.M_t;
+  const int32_t cnt = sc.vis_cnt[n];
+  const int32_t total = cnt + sc.n_points;
+  const int32_t n_tiles = (total + FT - 1) / FT;
+
+  C acc[MB];
+#pragma unroll
+  for (int j = 0; j < MB; ++j) acc[j] = {R(0), R(0)};
+
+  if (staging && n_tiles > 0) stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(0), n, cnt, 0,
+                                                    min(FT, total), m_tile0, st);
+  for (int32_t k = 0; k < n_tiles; ++k) {
+    // tile k is staged in buffer k & 1; buffer (k + 1) & 1 was consumed in step k - 1
+    __syncthreads();
+    const int cur = k & 1;
+    if (staging) {
+      const int32_t t1 = (k + 1) * FT;
+      if (t1 < total)
+        stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(cur ^ 1), n, cnt, t1, min(FT, total - t1),
+                              m_tile0, st);
+    } else if (o_ok) {
+      sum_tile<R, MB, FT>(rc, sh, sm.tile(cur), min(FT, total - k * FT), p, q, b, acc);
     }
   }
   // Store through LDS in chunks of kOut samples: each thread parks kOut accumulators,
   // then consecutive lanes write consecutive samples of one channel row, so a wave
   // writes whole 128-byte runs instead of one 8-byte value per row.
   constexpr int kOut = (MB < 16) ? MB : 16;
-  C *stage = sm.G;  // the host sizes LDS for O_w x kOut values here
+  C *stage = sm.tile(0).G;  // the layout reserves O_w x kOut values from here
   C *echo_out = static_cast<C *>(sc.echo);
   for (int bb = 0; bb < sh.B_w; ++bb) {
 #pragma unroll
     for (int jc = 0; jc < MB; jc += kOut) {
       __syncthreads();
-      if (b == bb) {
+      if (!staging && b == bb) {
 #pragma unroll
         for (int j = 0; j < kOut; ++j) stage[ol * kOut + j] = acc[jc + j];
       }
@@ -265,6 +348,7 @@ __global__ void __launch_bounds__(512) echo_kernel(DevScene sc, RadarConst rc, c
   EchoSmem<R, MB, FT> sm;
   sm.carve(echo_smem, sh);
   for (int i = threadIdx.x; i < 3 * sh.E; i += blockDim.x) sm.elem[i] = elem[i];
+  __syncthreads();
   const int per_chirp = sh.m_tiles * sh.o_tiles;
   const int n = blockIdx.x / per_chirp;
   const int r = blockIdx.x % per_chirp;
@@ -301,16 +385,7 @@ __global__ void reset_counter_kernel(int32_t *q) {
 
 template <typename R, int MB, int FT>
 static size_t smem_bytes(const EchoShape &sh) {
-  using C = typename Cx<R>::T;
-  size_t b = sizeof(double) * 3 * sh.E;
-  b = (b + 15) & ~size_t(15);
-  b += sizeof(Geo) * FT;
-  b = (b + 15) & ~size_t(15);
-  const size_t tile = 2 * sizeof(C) * FT * sh.M_t + sizeof(C) * FT * sh.E * sh.B_w +
-                      sizeof(C) * FT * sh.E + sizeof(R) * FT * sh.E;
-  // the output staging reuses the tile region from G on: O_w x min(MB, 16) values
-  const size_t out_stage = sizeof(C) * sh.O_w * ((MB < 16) ? MB : 16);
-  return b + (tile > out_stage ? tile : out_stage);
+  return EchoLayout<R, MB, FT>(sh).total;
 }
 
 // Host-side dispatch over the compiled (precision, MB, FT) variants.
@@ -323,7 +398,7 @@ template <typename R, int MB, int FT>
 static hipError_t launch_plain_t(const DevScene &sc, const RadarConst &rc, const double *elem,
                                  const EchoShape &sh, hipStream_t s) {
   const size_t lds = smem_bytes<R, MB, FT>(sh);
-  const int threads = sh.O_w * sh.B_w;
+  const int threads = sh.n_compute + kStagingThreads;
   const unsigned grid = static_cast<unsigned>(rc.N) * sh.m_tiles * sh.o_tiles;
   hipLaunchKernelGGL((echo_kernel<R, MB, FT>), dim3(grid), dim3(threads), lds, s, sc, rc, elem, sh);
   return hipGetLastError();
@@ -334,7 +409,7 @@ static hipError_t launch_persistent_t(const DevScene *scenes, const int4 *items,
                                       int32_t *queue, const RadarConst &rc, const double *elem,
                                       const EchoShape &sh, int n_groups, hipStream_t s) {
   const size_t lds = smem_bytes<R, MB, FT>(sh);
-  const int threads = sh.O_w * sh.B_w;
+  const int threads = sh.n_compute + kStagingThreads;
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
   hipLaunchKernelGGL((echo_persistent_kernel<R, MB, FT>), dim3(n_groups), dim3(threads), lds, s,
                      scenes, items, n_items, queue, rc, elem, sh);
@@ -346,20 +421,17 @@ static hipError_t occupancy_t(const EchoShape &sh, int *groups_per_cu) {
   const size_t lds = smem_bytes<R, MB, FT>(sh);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       groups_per_cu, reinterpret_cast<const void *>(echo_persistent_kernel<R, MB, FT>),
-      sh.O_w * sh.B_w, lds);
+      sh.n_compute + kStagingThreads, lds);
 }
 
 #define RSIM_ECHO_VARIANTS(X) \
   X(float, 16, 16)            \
   X(float, 32, 8)             \
   X(float, 32, 16)            \
-  X(float, 32, 32)            \
   X(float, 64, 8)             \
   X(float, 64, 16)            \
-  X(float, 64, 32)            \
   X(double, 8, 8)             \
-  X(double, 16, 8)            \
-  X(double, 32, 8)
+  X(double, 16, 8)
 
 #define RSIM_PREC_OF(R) (sizeof(R) == 8 ? 1 : 0)
 

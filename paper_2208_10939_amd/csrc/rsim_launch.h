@@ -10,11 +10,16 @@
 
 namespace rsim {
 
-// Facet-sum launch shape: a workgroup holds O_w channels x B_w blocks of MB samples.
+// Facet-sum launch shape: a workgroup holds O_w channels x B_w blocks of MB samples
+// (n_compute accumulating threads, O_w * B_w rounded up to whole waves; the forward
+// kernel adds two staging waves).
 struct EchoShape {
-  int32_t O, O_w, o_tiles, B_w, M_t, m_tiles, E, pad;
+  int32_t O, O_w, o_tiles, B_w, M_t, m_tiles, E, n_compute;
   double two_pi_slope;  // 2 pi mu
 };
+
+constexpr int kStagingThreads = 128;  // staging waves of the forward facet sum
+constexpr int kMaxComputeThreads = 384;  // + staging = 512 threads, 8 waves
 
 int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
               std::vector<BvhNode> &nodes_out, std::vector<float> &leaf_out);
