@@ -24,11 +24,143 @@
 
 namespace rsim {
 
+// FP32 path: the facet integral G_f(m) over one sample tile, with every phase reduced
+// in FP64 at the tile's first sample and advanced linearly in FP32 from there (the
+// spatial frequency s_m = f_m / c is linear in m, and so is every argument of Phi).
+// Nodes l, i, j as in phi_turns: (i, j) spans the widest gap. With nodes taken about
+// the centroid, the divided-difference form reads
+//   Phi = (f_j - f_i) / (2 pi s (b_j - b_i)),
+//   f_k = -j exp(j pi s (b_l + b_k)) sinc(pi s (b_k - b_l)),
+// and below the series gap the Taylor series about the mean applies as in phi_turns.
+struct alignas(16) GLin {
+  float gap, gap_i;          // rad: 2 pi s g_max (series below kSeriesGap)
+  float p1, p1_i, p2, p2_i;  // turns: s (b_l + b_j) / 2, s (b_l + b_i) / 2
+  float t1, t1_i, t2, t2_i;  // turns: s (b_j - b_l) / 2, s (b_i - b_l) / 2
+  float x1, x1_i, x2, x2_i;  // rad: pi s (b_j - b_l), pi s (b_i - b_l)
+  float w, w_i;              // rad: 2 pi s (b_j - b_i)
+  float b0, b0_i, b1, b1_i, b2, b2_i;  // rad: 2 pi s (b_k - mean)
+  float mp, mp_i;            // turns: s mean
+  float ar, ai;              // G = (ar + j ai) Phi
+  int32_t valid, pad0, pad1, pad2;
+};
+
+__device__ inline float centred_turns(double t) { return static_cast<float>(t - rint(t)); }
+
+// Coefficients for samples m = m_tile0 + j of the facet with geometry g.
+__device__ inline void make_glin(const Geo &g, const RadarConst &rc, int m_tile0, GLin &q) {
+  q.valid = g.valid;
+  if (!g.valid) return;
+  const double inv_c = 1.0 / kC0;
+  const double s0 = (rc.f0 + static_cast<double>(m_tile0) * rc.df) * inv_c;
+  const double ds = rc.df * inv_c;
+  const double mean = (g.beta[0] + g.beta[1] + g.beta[2]) * (1.0 / 3.0);
+  const double B0 = g.beta[0] - mean, B1 = g.beta[1] - mean, B2 = g.beta[2] - mean;
+  const double g12 = fabs(B1 - B2), g02 = fabs(B0 - B2), g01 = fabs(B0 - B1);
+  double bl, bi, bj, gmax;
+  if (g12 >= g02 && g12 >= g01) {
+    bl = B0; bi = B1; bj = B2; gmax = g12;
+  } else if (g02 >= g01) {
+    bl = B1; bi = B0; bj = B2; gmax = g02;
+  } else {
+    bl = B2; bi = B0; bj = B1; gmax = g01;
+  }
+  const double two_pi = 2.0 * kPi;
+  q.gap = static_cast<float>(two_pi * s0 * gmax);
+  q.gap_i = static_cast<float>(two_pi * ds * gmax);
+  // the sinc form on absolute nodes b + mean, so no separate mean phase
+  const double S1 = 0.5 * (bl + bj) + mean, S2 = 0.5 * (bl + bi) + mean;
+  q.p1 = centred_turns(s0 * S1);
+  q.p1_i = static_cast<float>(ds * S1);
+  q.p2 = centred_turns(s0 * S2);
+  q.p2_i = static_cast<float>(ds * S2);
+  const double d1 = bj - bl, d2 = bi - bl;
+  q.t1 = centred_turns(0.5 * s0 * d1);
+  q.t1_i = static_cast<float>(0.5 * ds * d1);
+  q.t2 = centred_turns(0.5 * s0 * d2);
+  q.t2_i = static_cast<float>(0.5 * ds * d2);
+  q.x1 = static_cast<float>(kPi * s0 * d1);
+  q.x1_i = static_cast<float>(kPi * ds * d1);
+  q.x2 = static_cast<float>(kPi * s0 * d2);
+  q.x2_i = static_cast<float>(kPi * ds * d2);
+  q.w = static_cast<float>(two_pi * s0 * (bj - bi));
+  q.w_i = static_cast<float>(two_pi * ds * (bj - bi));
+  q.b0 = static_cast<float>(two_pi * s0 * B0);
+  q.b0_i = static_cast<float>(two_pi * ds * B0);
+  q.b1 = static_cast<float>(two_pi * s0 * B1);
+  q.b1_i = static_cast<float>(two_pi * ds * B1);
+  q.b2 = static_cast<float>(two_pi * s0 * B2);
+  q.b2_i = static_cast<float>(two_pi * ds * B2);
+  q.mp = centred_turns(s0 * mean);
+  q.mp_i = static_cast<float>(ds * mean);
+  q.ar = static_cast<float>(g.amp_re);
+  q.ai = static_cast<float>(g.amp_im);
+}
+
+// sin(x) / x for x = x0 + j x_i (rad), t = t0 + j t_i = x / (2 pi) (turns, centred at
+// j = 0). Below |x| = 0.1 the even series to x^4 (error < x^6 / 5040 <= 2e-10 relative);
+// above, the hardware sine (absolute error ~1.3e-7) over x, relative error <= 1.3e-6.
+__device__ inline float sinc_lin(float x0, float x_i, float t0, float t_i, float jf) {
+  const float x = fmaf(jf, x_i, x0);
+  if (fabsf(x) < 0.1f) {
+    const float x2 = x * x;
+    return fmaf(x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+  }
+  float t = fmaf(jf, t_i, t0);
+  t -= rintf(t);
+  return __builtin_amdgcn_sinf(t) * __builtin_amdgcn_rcpf(x);
+}
+
+// G_f(m_tile0 + j)
+__device__ inline float2 g_lin(const GLin &q, int j) {
+  if (!q.valid) return {0.0f, 0.0f};
+  const float jf = static_cast<float>(j);
+  float2 phi;
+  if (fmaf(jf, q.gap_i, q.gap) < static_cast<float>(kSeriesGap)) {
+    const float b0 = fmaf(jf, q.b0_i, q.b0), b1 = fmaf(jf, q.b1_i, q.b1),
+                b2 = fmaf(jf, q.b2_i, q.b2);
+    const float e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
+    float hm3 = 0.0f, hm2 = 0.0f, hm1 = 1.0f;
+    float re = 0.5f, im = 0.0f, inv_fact = 0.5f;
+#pragma unroll
+    for (int n = 1; n <= EchoTraits<float>::kSeriesTerms; ++n) {
+      const float h = e1 * hm1 - e2 * hm2 + e3 * hm3;
+      hm3 = hm2;
+      hm2 = hm1;
+      hm1 = h;
+      inv_fact = inv_fact / static_cast<float>(n + 2);
+      const float term = h * inv_fact;
+      switch (n & 3) {
+        case 0: re += term; break;
+        case 1: im += term; break;
+        case 2: re -= term; break;
+        default: im -= term; break;
+      }
+    }
+    float t = fmaf(jf, q.mp_i, q.mp);
+    t -= rintf(t);
+    const float ms = __builtin_amdgcn_sinf(t), mc = __builtin_amdgcn_cosf(t);
+    phi = {re * mc - im * ms, re * ms + im * mc};
+  } else {
+    float t1 = fmaf(jf, q.p1_i, q.p1);
+    t1 -= rintf(t1);
+    float t2 = fmaf(jf, q.p2_i, q.p2);
+    t2 -= rintf(t2);
+    const float sc1 = sinc_lin(q.x1, q.x1_i, q.t1, q.t1_i, jf);
+    const float sc2 = sinc_lin(q.x2, q.x2_i, q.t2, q.t2_i, jf);
+    const float inv = __builtin_amdgcn_rcpf(fmaf(jf, q.w_i, q.w));
+    // f_k = -j exp(j 2 pi t_k) sinc_k = (sin, -cos) sinc_k
+    const float s1 = __builtin_amdgcn_sinf(t1) * sc1, c1 = __builtin_amdgcn_cosf(t1) * sc1;
+    const float s2 = __builtin_amdgcn_sinf(t2) * sc2, c2 = __builtin_amdgcn_cosf(t2) * sc2;
+    phi = {(s1 - s2) * inv, (c2 - c1) * inv};
+  }
+  return {q.ar * phi.x - q.ai * phi.y, q.ar * phi.y + q.ai * phi.x};
+}
+
 template <typename R, int MB, int FT>
 struct EchoLayout {
   using C = typename Cx<R>::T;
   static constexpr bool kRotated = sizeof(R) == 4;  // FP32 keeps G (-j)^m as well
-  size_t elem, geo, buf[2], G, G1, U, rat, off, total;
+  size_t elem, geo, glin, buf[2], G, G1, U, rat, off, total;
 
   __host__ __device__ explicit EchoLayout(const EchoShape &sh) {
     auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
@@ -37,6 +169,8 @@ struct EchoLayout {
     b = up(b + sizeof(double) * 3 * sh.E);
     geo = b;  // [2 staging waves][FT]
     b = up(b + sizeof(Geo) * 2 * FT);
+    glin = b;  // [2 staging waves][FT], FP32 path
+    b = up(b + (kRotated ? sizeof(GLin) * 2 * FT : 0));
     // offsets inside one tile buffer
     size_t t = 0;
     G = t;
@@ -72,6 +206,7 @@ struct EchoSmem {
   using C = typename Cx<R>::T;
   double *elem;  // [E][3]
   Geo *geo;      // [2][FT]: one private copy per staging wave
+  GLin *glin;    // [2][FT]: the same, FP32 path
   unsigned char *buf0;
   size_t buf_stride, oG, oG1, oU, orat, ooff;
 
@@ -79,6 +214,7 @@ struct EchoSmem {
     const EchoLayout<R, MB, FT> L(sh);
     elem = reinterpret_cast<double *>(base + L.elem);
     geo = reinterpret_cast<Geo *>(base + L.geo);
+    glin = reinterpret_cast<GLin *>(base + L.glin);
     buf0 = base + L.buf[0];
     buf_stride = L.buf[1] - L.buf[0];
     oG = L.G;
@@ -115,11 +251,13 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
   // A: facet / point geometry (FP64). Each staging wave computes the whole tile into its
   // own copy, so the reads below need no workgroup barrier.
   Geo *geo = sm.geo + (st >> 6) * FT;
+  GLin *glin = sm.glin + (st >> 6) * FT;
   for (int i = st & 63; i < FT; i += 64) {
     if (i < nf)
       entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
     else
       geo[i].valid = 0;
+    if constexpr (EchoLayout<R, MB, FT>::kRotated) make_glin(geo[i], rc, m_tile0, glin[i]);
   }
   wave_lds_sync();
   // B1: per element distance, phases in FP64 reduced to turns
@@ -137,7 +275,7 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
     const double dy = sm.elem[3 * e + 1] - g.c[1];
     const double dz = sm.elem[3 * e + 2] - g.c[2];
     const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
-    const double tau = Rn / kC0;
+    const double tau = Rn * (1.0 / kC0);
     double psi0, offv;
     if (e < P) {
       const double d = tau - g.tref_t;
@@ -153,7 +291,11 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
     psi0 -= floor(psi0);
     double delta = rc.df * tau;
     delta -= floor(delta);
-    const R inv_r = static_cast<R>(1.0 / Rn);
+    R inv_r;
+    if constexpr (sizeof(R) == 4)
+      inv_r = __builtin_amdgcn_rcpf(static_cast<float>(Rn));  // amplitude only: 1 ulp
+    else
+      inv_r = 1.0 / Rn;
     for (int bb = 0; bb < sh.B_w; ++bb) {
       const double m0 = static_cast<double>(m_tile0 + bb * MB);
       Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
@@ -164,14 +306,18 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
   // B2: G_f(m) for the tile's samples
   for (int task = st; task < FT * sh.M_t; task += kStagingThreads) {
     const int i = task / sh.M_t, j = task % sh.M_t;
-    const Geo &g = geo[i];
     C val = {R(0), R(0)};
-    if (g.valid) {
-      const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
-      const double s = fm / kC0;  // turns per metre
-      const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
-      const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
-      val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
+    if constexpr (EchoLayout<R, MB, FT>::kRotated) {
+      val = g_lin(glin[i], j);
+    } else {
+      const Geo &g = geo[i];
+      if (g.valid) {
+        const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
+        const double s = fm / kC0;  // turns per metre
+        const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
+        const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
+        val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
+      }
     }
     tl.G[i * sh.M_t + j] = val;
     if constexpr (EchoLayout<R, MB, FT>::kRotated) {
@@ -274,69 +420,81 @@ __device__ inline void sum_tile(const RadarConst &rc, const EchoShape &sh,
   }
 }
 
-// One work item. Every thread of the workgroup reaches each barrier the same number of
-// times: the tile count depends only on the chirp's lit count.
+// One work item. The staging waves and the accumulating waves run separate branches
+// (whole waves each, so the accumulators are not live in the staging code); both pass
+// the same sequence of workgroup barriers: one per tile, then two per output chunk.
+// The tile count depends only on the chirp's lit count.
 template <typename R, int MB, int FT>
 __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
                           EchoSmem<R, MB, FT> &sm, int n, int mt, int ot) {
   using C = typename Cx<R>::T;
+  constexpr int kOut = (MB < 16) ? MB : 16;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
-  const bool staging = tid >= sh.n_compute;
-  const int st = tid - sh.n_compute;
-  const int Q = rc.Q;
-  const int ol = tid % sh.O_w;
-  const int b = tid / sh.O_w;
-  const int o = ot * sh.O_w + ol;
-  const bool o_ok = !staging && b < sh.B_w && o < sh.O;
-  const int p = o_ok ? o / Q : 0;
-  const int q = o_ok ? o % Q : 0;
   const int m_tile0 = mt * sh.M_t;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t total = cnt + sc.n_points;
   const int32_t n_tiles = (total + FT - 1) / FT;
+  C *stage = sm.tile(0).G;  // output staging: the layout reserves O_w x kOut values here
+  C *echo_out = static_cast<C *>(sc.echo);
+  // Output in chunks of kOut samples: the accumulating threads park kOut values each in
+  // LDS, then consecutive lanes write consecutive samples of one channel row, so a wave
+  // writes whole 128-byte runs instead of one 8-byte value per row.
+  auto store_chunk = [&](int m0) {
+    for (int e = tid; e < sh.O_w * kOut; e += nthr) {
+      const int oo = ot * sh.O_w + e / kOut;
+      const int m = m0 + e % kOut;
+      if (oo < sh.O && m < rc.M)
+        echo_out[(static_cast<int64_t>(oo) * rc.N + n) * rc.M + m] = stage[e];
+    }
+  };
 
+  if (tid >= sh.n_compute) {
+    const int st = tid - sh.n_compute;
+    if (n_tiles > 0)
+      stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(0), n, cnt, 0, min(FT, total), m_tile0, st);
+    for (int32_t k = 0; k < n_tiles; ++k) {
+      // tile k is staged in buffer k & 1; buffer (k + 1) & 1 was consumed in step k - 1
+      __syncthreads();
+      const int32_t t1 = (k + 1) * FT;
+      if (t1 < total)
+        stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile((k & 1) ^ 1), n, cnt, t1,
+                              min(FT, total - t1), m_tile0, st);
+    }
+    for (int bb = 0; bb < sh.B_w; ++bb) {
+      for (int jc = 0; jc < MB; jc += kOut) {
+        __syncthreads();
+        __syncthreads();
+        store_chunk(m_tile0 + bb * MB + jc);
+      }
+    }
+    return;
+  }
+
+  const int Q = rc.Q;
+  const int ol = tid % sh.O_w;
+  const int b = tid / sh.O_w;
+  const int o = ot * sh.O_w + ol;
+  const bool o_ok = b < sh.B_w && o < sh.O;
+  const int p = o_ok ? o / Q : 0;
+  const int q = o_ok ? o % Q : 0;
   C acc[MB];
 #pragma unroll
   for (int j = 0; j < MB; ++j) acc[j] = {R(0), R(0)};
-
-  if (staging && n_tiles > 0) stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(0), n, cnt, 0,
-                                                    min(FT, total), m_tile0, st);
   for (int32_t k = 0; k < n_tiles; ++k) {
-    // tile k is staged in buffer k & 1; buffer (k + 1) & 1 was consumed in step k - 1
     __syncthreads();
-    const int cur = k & 1;
-    if (staging) {
-      const int32_t t1 = (k + 1) * FT;
-      if (t1 < total)
-        stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(cur ^ 1), n, cnt, t1, min(FT, total - t1),
-                              m_tile0, st);
-    } else if (o_ok) {
-      sum_tile<R, MB, FT>(rc, sh, sm.tile(cur), min(FT, total - k * FT), p, q, b, acc);
-    }
+    if (o_ok) sum_tile<R, MB, FT>(rc, sh, sm.tile(k & 1), min(FT, total - k * FT), p, q, b, acc);
   }
-  // Store through LDS in chunks of kOut samples: each thread parks kOut accumulators,
-  // then consecutive lanes write consecutive samples of one channel row, so a wave
-  // writes whole 128-byte runs instead of one 8-byte value per row.
-  constexpr int kOut = (MB < 16) ? MB : 16;
-  C *stage = sm.tile(0).G;  // the layout reserves O_w x kOut values from here
-  C *echo_out = static_cast<C *>(sc.echo);
   for (int bb = 0; bb < sh.B_w; ++bb) {
 #pragma unroll
     for (int jc = 0; jc < MB; jc += kOut) {
       __syncthreads();
-      if (!staging && b == bb) {
+      if (b == bb) {
 #pragma unroll
         for (int j = 0; j < kOut; ++j) stage[ol * kOut + j] = acc[jc + j];
       }
       __syncthreads();
-      const int m0 = m_tile0 + bb * MB + jc;
-      for (int e = tid; e < sh.O_w * kOut; e += nthr) {
-        const int oo = ot * sh.O_w + e / kOut;
-        const int m = m0 + e % kOut;
-        if (oo < sh.O && m < rc.M)
-          echo_out[(static_cast<int64_t>(oo) * rc.N + n) * rc.M + m] = stage[e];
-      }
+      store_chunk(m_tile0 + bb * MB + jc);
     }
   }
 }
