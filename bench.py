@@ -22,15 +22,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("facet·freq·channel·chirp evals/s + ms per RDM frame; "
           "fwd+bwd vs fwd, batched vs plain")
-# Per facet.freq.channel.chirp evaluation: one phasor step by the three-term recurrence
-# z_{m+1} = 2 cos(t) z_m - z_{m-1} (2 FMA = 4 FLOP) + one complex multiply-accumulate
-# (4 FMA = 8 FLOP).
-FLOP_PER_EVAL = 12
-# VALU FP32 FMA issue without packed-math instructions: 256 CU x 4 SIMD x 16 lanes x
-# 2 FLOP x 2.4 GHz. Packed FP32 (v_pk_fma_f32) would double it to the published
-# 157.3 TFLOP/s; this build keeps packed FP32 out of all device code.
-PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9
-PEAK_FP32_PACKED = 157.3e12
+# Algorithmic work per facet.freq.channel.chirp evaluation: one complex phasor step
+# (complex multiply, 6 FLOP) + one complex multiply-accumulate (8 FLOP).
+FLOP_PER_EVAL = 14
+# What the kernel executes per evaluation: the phasor step as the three-term recurrence
+# z_{m+1} = 2 cos(t) z_m - z_{m-1} (2 FMA = 4 FLOP) + the complex MAC (4 FMA = 8 FLOP).
+EXECUTED_FLOP_PER_EVAL = 12
+# Published FP32 vector peak of MI355X (256 CU x 2.4 GHz; reached with packed FP32).
+PEAK_FP32_VECTOR = 157.3e12
+# FP32 FMA issue without packed-math instructions, which this build keeps out of all
+# device code: 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.
+PEAK_FP32_NON_PACKED = 256 * 4 * 16 * 2 * 2.4e9
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "facet_sum_c2_traffic.json")
 
 
@@ -283,14 +285,16 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
-            "peak": PEAK_FP32_VALU / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VALU,
+            "frac": achieved / PEAK_FP32_VECTOR,
             "traffic": _traffic(evals_per_step),
             "kernel": "rsim::echo_kernel<float> (FP64 prep + facet integral + facet sum)",
             "flop_per_eval": FLOP_PER_EVAL,
             "evals_per_launch": evals_per_step,
-            "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
+            "executed_flop_per_eval": EXECUTED_FLOP_PER_EVAL,
+            "executed_frac_of_non_packed_fp32_peak":
+                EXECUTED_FLOP_PER_EVAL * evals_per_step / (fs_ms * 1e-3) / PEAK_FP32_NON_PACKED,
         },
     }
     if not args.no_extras:

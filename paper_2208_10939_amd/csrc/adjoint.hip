@@ -24,59 +24,62 @@ namespace {
 
 constexpr int kAdjVals = 8;  // grad_c (3), sum Re y, t0, t1, t2, pad
 
-// sinc(u) = sin u / u and its derivative (cos u - sinc u) / u at u = pi D, D in turns
-// (FP64, reduced before the FP32 trigonometry).
-__device__ inline float sinc_d(double D, float *sinc_out) {
-  const float u = static_cast<float>(kPi * D);
-  const float au = fabsf(u);
-  if (au < 0.05f) {
+// sinc(u) and sinc'(u) = (cos u - sinc u) / u at u = x0 + j x_i (rad), t = u / (2 pi)
+// (turns, centred at j = 0). Series below |u| = 0.3.
+__device__ inline float sinc_d_lin(float x0, float x_i, float t0, float t_i, float jf,
+                                   float *sinc_out) {
+  const float u = fmaf(jf, x_i, x0);
+  if (fabsf(u) < kSincSeries) {
     const float u2 = u * u;
-    *sinc_out = 1.0f - u2 * (1.0f / 6.0f) + u2 * u2 * (1.0f / 120.0f);
-    return u * (-1.0f / 3.0f + u2 * (1.0f / 30.0f - u2 * (1.0f / 840.0f)));
+    *sinc_out = sinc_series(u2);
+    return u * fmaf(u2, fmaf(u2, fmaf(u2, 1.0f / 45360.0f, -1.0f / 840.0f), 1.0f / 30.0f),
+                    -1.0f / 3.0f);
   }
-  float s, c;
-  sincospi_t(static_cast<float>(D - 2.0 * rint(0.5 * D)), &s, &c);
-  const float sc = s / u;
+  float t = fmaf(jf, t_i, t0);
+  t -= rintf(t);
+  const float r = __builtin_amdgcn_rcpf(u);
+  const float sc = __builtin_amdgcn_sinf(t) * r;
   *sinc_out = sc;
-  return (c - sc) / u;
+  return (__builtin_amdgcn_cosf(t) - sc) * r;
 }
 
-// Phi(a0,a1,a2) and dPhi/da_i (a in radians, given in turns A), FP32 results.
-__device__ void phi_grad_turns(double A0, double A1, double A2, float2 *phi, float2 dphi[3]) {
-  const double mean = (A0 + A1 + A2) / 3.0;
-  const double B[3] = {A0 - mean, A1 - mean, A2 - mean};
-  const double g12 = fabs(B[1] - B[2]), g02 = fabs(B[0] - B[2]), g01 = fabs(B[0] - B[1]);
-  int l, i, j;
-  double gmax;
-  if (g12 >= g02 && g12 >= g01) {
-    l = 0; i = 1; j = 2; gmax = g12;
-  } else if (g02 >= g01) {
-    l = 1; i = 0; j = 2; gmax = g02;
-  } else {
-    l = 2; i = 0; j = 1; gmax = g01;
+// G(m) = amp Phi and D_k(m) = amp k_m dPhi/da_k (k = triangle vertex; a_k = k_m b_k) at
+// sample m_tile0 + j, from the linear-phase coefficients of the forward facet integral.
+// Sinc form: with F(x, y) = -j exp(j (x + y) / 2) sinc((y - x) / 2),
+//   Phi = (F(a_l, a_j) - F(a_l, a_i)) / (a_j - a_i),
+//   dPhi/da_l = (F_x(a_l, a_j) - F_x(a_l, a_i)) / (a_j - a_i),
+//   dPhi/da_j = (F_y(a_l, a_j) - Phi) / (a_j - a_i),  dPhi/da_i = (Phi - F_y(a_l, a_i)) / (a_j - a_i),
+//   F_x = K (-sinc'/2 + j sinc/2),  F_y = K (sinc'/2 + j sinc/2),  K = -j exp(j (x + y) / 2).
+// Series form about the mean (Sec. 3.2): Phi_0 = sum_n j^n h_n(b) / (n+2)!,
+//   dPhi_0/db_k = sum_n j^(n+1) h_n(b, b_k) / (n+3)!, both turned by exp(j mean).
+__device__ inline void g_lin_grad(const GLin &q, int j, float2 &G, float2 D[3]) {
+  if (!q.valid) {
+    G = D[0] = D[1] = D[2] = make_float2(0.0f, 0.0f);
+    return;
   }
+  const float jf = static_cast<float>(j);
   float2 p0, d[3];
-  if (2.0 * kPi * gmax < kSeriesGap) {
-    // Phi_0 = sum_n j^n h_n(b)/(n+2)!,  dPhi_0/db_k = sum_n j^{n+1} h_n(b, b_k)/(n+3)!
-    const float b0 = static_cast<float>(2.0 * kPi * B[0]);
-    const float b1 = static_cast<float>(2.0 * kPi * B[1]);
-    const float b2 = static_cast<float>(2.0 * kPi * B[2]);
-    const float bk[3] = {b0, b1, b2};
-    const float e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
-    float h[10];
+  if (fmaf(jf, q.gap_i, q.gap) < static_cast<float>(kSeriesGap)) {
+    const float bk[3] = {fmaf(jf, q.b0_i, q.b0), fmaf(jf, q.b1_i, q.b1), fmaf(jf, q.b2_i, q.b2)};
+    const float e1 = bk[0] + bk[1] + bk[2];
+    const float e2 = bk[0] * bk[1] + bk[0] * bk[2] + bk[1] * bk[2];
+    const float e3 = bk[0] * bk[1] * bk[2];
+    float h[9];
     h[0] = 1.0f;
     float hm1 = 1.0f, hm2 = 0.0f, hm3 = 0.0f;
-    for (int n = 1; n < 10; ++n) {
+#pragma unroll
+    for (int n = 1; n < 9; ++n) {
       const float hn = e1 * hm1 - e2 * hm2 + e3 * hm3;
       hm3 = hm2;
       hm2 = hm1;
       hm1 = hn;
       h[n] = hn;
     }
-    float re = 0.0f, im = 0.0f, fact = 2.0f;  // (n+2)!
+    float re = 0.0f, im = 0.0f, inv_fact = 0.5f;  // 1 / (n+2)!
+#pragma unroll
     for (int n = 0; n <= 8; ++n) {
-      if (n > 0) fact *= static_cast<float>(n + 2);
-      const float term = h[n] / fact;
+      if (n > 0) inv_fact *= 1.0f / static_cast<float>(n + 2);
+      const float term = h[n] * inv_fact;
       switch (n & 3) {
         case 0: re += term; break;
         case 1: im += term; break;
@@ -85,15 +88,17 @@ __device__ void phi_grad_turns(double A0, double A1, double A2, float2 *phi, flo
       }
     }
     p0 = make_float2(re, im);
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float h4 = 1.0f, dre = 0.0f, dim = 0.0f, f3 = 6.0f;  // (n+3)!
+      float h4 = 1.0f, dre = 0.0f, dim = 0.0f, inv3 = 1.0f / 6.0f;  // 1 / (n+3)!
+#pragma unroll
       for (int n = 0; n <= 7; ++n) {
         if (n > 0) {
-          h4 = h[n] + bk[k] * h4;
-          f3 *= static_cast<float>(n + 3);
+          h4 = fmaf(bk[k], h4, h[n]);
+          inv3 *= 1.0f / static_cast<float>(n + 3);
         }
-        const float term = h4 / f3;
-        switch ((n + 1) & 3) {  // j^{n+1}
+        const float term = h4 * inv3;
+        switch ((n + 1) & 3) {  // j^(n+1)
           case 0: dre += term; break;
           case 1: dim += term; break;
           case 2: dre -= term; break;
@@ -102,37 +107,43 @@ __device__ void phi_grad_turns(double A0, double A1, double A2, float2 *phi, flo
       }
       d[k] = make_float2(dre, dim);
     }
+    float t = fmaf(jf, q.mp_i, q.mp);
+    t -= rintf(t);
+    const float ms = __builtin_amdgcn_sinf(t), mc = __builtin_amdgcn_cosf(t);
+    p0 = make_float2(p0.x * mc - p0.y * ms, p0.x * ms + p0.y * mc);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      d[k] = make_float2(d[k].x * mc - d[k].y * ms, d[k].x * ms + d[k].y * mc);
   } else {
-    // divided-difference form: Phi_0 = (F(b_l, b_j) - F(b_l, b_i)) / (b_j - b_i),
-    // F(x, y) = -j exp(j (x+y)/2) sinc((y-x)/2)
-    float2 F[2], Fx[2], Fy[2];
-    const int other[2] = {j, i};
-    for (int k = 0; k < 2; ++k) {
-      const double X = B[l], Y = B[other[k]];
-      const double S = X + Y;
-      float cs, sn;
-      sincospi_t(static_cast<float>(S - 2.0 * rint(0.5 * S)), &sn, &cs);
-      float sc;
-      const float scd = sinc_d(Y - X, &sc);
-      // K = -j exp(js) = (sn, -cs)
-      F[k] = make_float2(sn * sc, -cs * sc);
-      // dF/dx = K (-sinc'/2 + j sinc/2),  dF/dy = K (sinc'/2 + j sinc/2)
-      const float ax = -0.5f * scd, bx = 0.5f * sc;
-      const float ay = 0.5f * scd, by = 0.5f * sc;
-      Fx[k] = make_float2(sn * ax + cs * bx, sn * bx - cs * ax);
-      Fy[k] = make_float2(sn * ay + cs * by, sn * by - cs * ay);
-    }
-    const float inv = static_cast<float>(1.0 / (2.0 * kPi * (B[j] - B[i])));
-    p0 = make_float2((F[0].x - F[1].x) * inv, (F[0].y - F[1].y) * inv);
-    d[l] = make_float2((Fx[0].x - Fx[1].x) * inv, (Fx[0].y - Fx[1].y) * inv);
-    d[j] = make_float2((Fy[0].x - p0.x) * inv, (Fy[0].y - p0.y) * inv);
-    d[i] = make_float2((p0.x - Fy[1].x) * inv, (p0.y - Fy[1].y) * inv);
+    float t1 = fmaf(jf, q.p1_i, q.p1);
+    t1 -= rintf(t1);
+    float t2 = fmaf(jf, q.p2_i, q.p2);
+    t2 -= rintf(t2);
+    const float sn1 = __builtin_amdgcn_sinf(t1), cs1 = __builtin_amdgcn_cosf(t1);
+    const float sn2 = __builtin_amdgcn_sinf(t2), cs2 = __builtin_amdgcn_cosf(t2);
+    float sc1, sc2;
+    const float sd1 = sinc_d_lin(q.x1, q.x1_i, q.t1, q.t1_i, jf, &sc1);
+    const float sd2 = sinc_d_lin(q.x2, q.x2_i, q.t2, q.t2_i, jf, &sc2);
+    const float inv = __builtin_amdgcn_rcpf(fmaf(jf, q.w_i, q.w));
+    // K = (sn, -cs); F = K sinc; F_x = K (-sd/2 + j sc/2); F_y = K (sd/2 + j sc/2)
+    const float2 F1 = make_float2(sn1 * sc1, -cs1 * sc1), F2 = make_float2(sn2 * sc2, -cs2 * sc2);
+    const float2 F1x = make_float2(0.5f * (cs1 * sc1 - sn1 * sd1), 0.5f * (sn1 * sc1 + cs1 * sd1));
+    const float2 F2x = make_float2(0.5f * (cs2 * sc2 - sn2 * sd2), 0.5f * (sn2 * sc2 + cs2 * sd2));
+    const float2 F1y = make_float2(0.5f * (cs1 * sc1 + sn1 * sd1), 0.5f * (sn1 * sc1 - cs1 * sd1));
+    const float2 F2y = make_float2(0.5f * (cs2 * sc2 + sn2 * sd2), 0.5f * (sn2 * sc2 - cs2 * sd2));
+    p0 = make_float2((F1.x - F2.x) * inv, (F1.y - F2.y) * inv);
+    const float2 dl = make_float2((F1x.x - F2x.x) * inv, (F1x.y - F2x.y) * inv);
+    const float2 dj = make_float2((F1y.x - p0.x) * inv, (F1y.y - p0.y) * inv);
+    const float2 di = make_float2((p0.x - F2y.x) * inv, (p0.y - F2y.y) * inv);
+    // scatter to vertex order
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = (k == q.nl) ? dl : ((k == q.nj) ? dj : di);
   }
-  float ms, mc;
-  sincospi_t(static_cast<float>(2.0 * (mean - rint(mean))), &ms, &mc);
-  *phi = make_float2(p0.x * mc - p0.y * ms, p0.x * ms + p0.y * mc);
+  const float km = fmaf(jf, q.k_i, q.k);
+  G = make_float2(q.ar * p0.x - q.ai * p0.y, q.ar * p0.y + q.ai * p0.x);
+#pragma unroll
   for (int k = 0; k < 3; ++k)
-    dphi[k] = make_float2(d[k].x * mc - d[k].y * ms, d[k].x * ms + d[k].y * mc);
+    D[k] = make_float2(km * (q.ar * d[k].x - q.ai * d[k].y), km * (q.ar * d[k].y + q.ai * d[k].x));
 }
 
 struct AdjShape {
@@ -141,54 +152,175 @@ struct AdjShape {
   int32_t pad;
 };
 
+// LDS layout of the adjoint facet sum: shared tables, per-staging-wave geometry, the
+// per-wave channel sums of two tiles, and two tile buffers.
 template <int MB, int FT>
-struct AdjSmem {
-  double *elem;  // [E][3]
-  Geo *geo;      // [FT]
-  float4 *GD;    // [FT][M_t][2]: (G, D0), (D1, D2)
-  float2 *U;     // [FT][E][B_w]
-  float2 *rat;   // [FT][E]
-  float *off;    // [FT][E]
-  float4 *er;    // [FT][E]: unit vector centroid -> element (xyz), 1 / R (w)
-  float *tau;    // [FT][E]
-  float *red;    // [FT][waves][kAdjVals]
+struct AdjLayout {
+  size_t elem, geo, glin, red, buf[2], GD, U, rat, off, er, tau, total;
+  int waves;  // accumulating waves
 
-  __device__ void carve(unsigned char *base, const EchoShape &sh, int waves) {
+  __host__ __device__ explicit AdjLayout(const EchoShape &sh) {
+    auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
+    waves = sh.n_compute / 64;
     size_t b = 0;
-    auto take = [&](size_t bytes) {
-      b = (b + 15) & ~size_t(15);
-      unsigned char *p = base + b;
-      b += bytes;
-      return p;
-    };
-    elem = reinterpret_cast<double *>(take(sizeof(double) * 3 * sh.E));
-    geo = reinterpret_cast<Geo *>(take(sizeof(Geo) * FT));
-    GD = reinterpret_cast<float4 *>(take(sizeof(float4) * FT * 2 * sh.M_t));
-    U = reinterpret_cast<float2 *>(take(sizeof(float2) * FT * sh.E * sh.B_w));
-    rat = reinterpret_cast<float2 *>(take(sizeof(float2) * FT * sh.E));
-    off = reinterpret_cast<float *>(take(sizeof(float) * FT * sh.E));
-    er = reinterpret_cast<float4 *>(take(sizeof(float4) * FT * sh.E));
-    tau = reinterpret_cast<float *>(take(sizeof(float) * FT * sh.E));
-    red = reinterpret_cast<float *>(take(sizeof(float) * FT * waves * kAdjVals));
-  }
-  static size_t bytes(const EchoShape &sh, int waves) {
-    size_t b = 0;
-    auto take = [&](size_t bytes) {
-      b = (b + 15) & ~size_t(15);
-      b += bytes;
-    };
-    take(sizeof(double) * 3 * sh.E);
-    take(sizeof(Geo) * FT);
-    take(sizeof(float4) * FT * 2 * sh.M_t);
-    take(sizeof(float2) * FT * sh.E * sh.B_w);
-    take(sizeof(float2) * FT * sh.E);
-    take(sizeof(float) * FT * sh.E);
-    take(sizeof(float4) * FT * sh.E);
-    take(sizeof(float) * FT * sh.E);
-    take(sizeof(float) * FT * waves * kAdjVals);
-    return b;
+    elem = b;
+    b = up(b + sizeof(double) * 3 * sh.E);
+    geo = b;
+    b = up(b + sizeof(Geo) * 2 * FT);
+    glin = b;
+    b = up(b + sizeof(GLin) * 2 * FT);
+    red = b;  // [2][FT][waves][kAdjVals]
+    b = up(b + sizeof(float) * 2 * FT * waves * kAdjVals);
+    size_t t = 0;
+    GD = t;  // [FT][M_t][2] float4: (G, D0), (D1, D2)
+    t += sizeof(float4) * FT * 2 * sh.M_t;
+    U = t;  // [FT][E][B_w]
+    t += sizeof(float2) * FT * sh.E * sh.B_w;
+    rat = t;  // [FT][E]
+    t += sizeof(float2) * FT * sh.E;
+    er = t;  // [FT][E]: unit vector centroid -> element (xyz), 1 / R (w)
+    t += sizeof(float4) * FT * sh.E;
+    off = t;  // [FT][E]
+    t += sizeof(float) * FT * sh.E;
+    tau = t;  // [FT][E]
+    t = up(t + sizeof(float) * FT * sh.E);
+    buf[0] = b;
+    buf[1] = b + t;
+    total = b + 2 * t;
   }
 };
+
+struct AdjTile {
+  float4 *GD;
+  float2 *U, *rat;
+  float4 *er;
+  float *off, *tau;
+};
+
+template <int MB, int FT>
+struct AdjSmem {
+  double *elem;
+  Geo *geo;
+  GLin *glin;
+  float *red;
+  unsigned char *buf0;
+  size_t stride, oGD, oU, orat, oer, ooff, otau;
+  int waves;
+
+  __device__ void carve(unsigned char *base, const EchoShape &sh) {
+    const AdjLayout<MB, FT> L(sh);
+    elem = reinterpret_cast<double *>(base + L.elem);
+    geo = reinterpret_cast<Geo *>(base + L.geo);
+    glin = reinterpret_cast<GLin *>(base + L.glin);
+    red = reinterpret_cast<float *>(base + L.red);
+    buf0 = base + L.buf[0];
+    stride = L.buf[1] - L.buf[0];
+    oGD = L.GD;
+    oU = L.U;
+    orat = L.rat;
+    oer = L.er;
+    ooff = L.off;
+    otau = L.tau;
+    waves = L.waves;
+  }
+  __device__ AdjTile tile(int k) const {
+    unsigned char *t = buf0 + static_cast<size_t>(k) * stride;
+    return {reinterpret_cast<float4 *>(t + oGD), reinterpret_cast<float2 *>(t + oU),
+            reinterpret_cast<float2 *>(t + orat), reinterpret_cast<float4 *>(t + oer),
+            reinterpret_cast<float *>(t + ooff), reinterpret_cast<float *>(t + otau)};
+  }
+  __device__ float *red_buf(int k) const { return red + static_cast<size_t>(k) * FT * waves * kAdjVals; }
+};
+
+// Orders a wave's own LDS writes before its later LDS reads by other lanes.
+__device__ inline void wave_lds_sync_adj() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Staging of one tile (lit entries t0 .. t0 + nf - 1 of chirp n) by the staging waves.
+template <int MB, int FT>
+__device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                               const AdjSmem<MB, FT> &sm, const AdjTile &tl, int n, int32_t cnt,
+                               int32_t t0, int nf, int m_tile0, int st) {
+  const int P = rc.P, E = sh.E;
+  const double slope = rc.slope;
+  Geo *geo = sm.geo + (st >> 6) * FT;
+  GLin *glin = sm.glin + (st >> 6) * FT;
+  for (int i = st & 63; i < FT; i += 64) {
+    if (i < nf)
+      entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
+    else
+      geo[i].valid = 0;
+    make_glin(geo[i], rc, m_tile0, glin[i]);
+  }
+  wave_lds_sync_adj();
+  for (int task = st; task < FT * E; task += kStagingThreads) {
+    const int i = task / E, e = task % E;
+    const Geo &g = geo[i];
+    float2 *Ue = tl.U + (i * E + e) * sh.B_w;
+    if (!g.valid) {
+      for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = make_float2(0.0f, 0.0f);
+      tl.rat[i * E + e] = make_float2(1.0f, 0.0f);
+      tl.off[i * E + e] = 0.0f;
+      tl.er[i * E + e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      tl.tau[i * E + e] = 0.0f;
+      continue;
+    }
+    const double dx = sm.elem[3 * e + 0] - g.c[0];
+    const double dy = sm.elem[3 * e + 1] - g.c[1];
+    const double dz = sm.elem[3 * e + 2] - g.c[2];
+    const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
+    const double inv_rd = 1.0 / Rn;
+    const double tau = Rn * (1.0 / kC0);
+    double psi0, offv;
+    if (e < P) {
+      const double d = tau - g.tref_t;
+      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
+             0.5 * slope * g.tref_t * g.tref_r;
+      offv = sh.two_pi_slope * d;
+    } else {
+      const double d = tau - g.tref_r;
+      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
+             0.5 * slope * g.tref_t * g.tref_r;
+      offv = d;
+    }
+    psi0 -= floor(psi0);
+    double delta = rc.df * tau;
+    delta -= floor(delta);
+    const float inv_r = static_cast<float>(inv_rd);
+    for (int bb = 0; bb < sh.B_w; ++bb)
+      Ue[bb] = phasor_m2pi<float>(psi0 + static_cast<double>(m_tile0 + bb * MB) * delta, inv_r);
+    tl.rat[i * E + e] = phasor_m2pi<float>(delta, 1.0f);
+    tl.off[i * E + e] = static_cast<float>(offv);
+    tl.er[i * E + e] = make_float4(static_cast<float>(dx * inv_rd), static_cast<float>(dy * inv_rd),
+                                   static_cast<float>(dz * inv_rd), inv_r);
+    tl.tau[i * E + e] = static_cast<float>(tau);
+  }
+  for (int task = st; task < FT * sh.M_t; task += kStagingThreads) {
+    const int i = task / sh.M_t, j = task % sh.M_t;
+    float2 gv, dv[3];
+    g_lin_grad(glin[i], j, gv, dv);
+    float4 *dst = tl.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;
+    dst[0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
+    dst[1] = make_float4(dv[1].x, dv[1].y, dv[2].x, dv[2].y);
+  }
+}
+
+// Sums of a finished tile's per-wave channel sums (fixed wave order) into the
+// per-(chirp, facet, tile) partials, by the staging waves.
+template <int MB, int FT>
+__device__ void adj_flush(const AdjSmem<MB, FT> &sm, const float *red, float *partial, int64_t F,
+                          const EchoShape &sh, int n, int mt, int ot, int32_t t0, int nf, int st) {
+  for (int task = st; task < nf * 7; task += kStagingThreads) {
+    const int i = task / 7, k = task % 7;
+    float s = 0.0f;
+    for (int wv = 0; wv < sm.waves; ++wv) s += red[(i * sm.waves + wv) * kAdjVals + k];
+    const int64_t slot = ((static_cast<int64_t>(n) * F + t0 + i) * sh.m_tiles + mt) * sh.o_tiles + ot;
+    partial[slot * kAdjVals + k] = s;
+  }
+}
 
 // Sum over the 64 lanes of a wave: DPP moves inside each 16-lane row (no LDS round
 // trips), then the four row sums read out with readlane (the DPP row-broadcast
@@ -200,13 +332,8 @@ __device__ inline float dpp_add(float v) {
   return v + __builtin_bit_cast(float, t);
 }
 
-// DPP reads the registers of inactive lanes as they are, so it is used only when the
-// workgroup is made of whole waves; partial waves take the permute path.
-__device__ inline float wave_sum_partial(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
+// DPP reads the registers of inactive lanes as they are: every caller runs it with the
+// whole wave active.
 __device__ inline float wave_sum(float v) {
   v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
   v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]: quad sums
@@ -220,6 +347,10 @@ __device__ inline float wave_sum(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
+// One workgroup per (chirp, sample tile, channel tile): accumulating waves (thread (o, b)
+// holds conj(g) for MB samples of channel o in registers) and two staging waves, with
+// double-buffered tiles of FT lit facets as in the forward kernel. Both branches pass
+// the same barriers: one per tile and a final one.
 template <int MB, int FT>
 __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarConst rc,
                                                            const double *elem, AdjShape ash,
@@ -227,26 +358,48 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
                                                            float *partial) {
   extern __shared__ __align__(16) unsigned char adj_smem[];
   const EchoShape &sh = ash.sh;
-  const int waves = (blockDim.x + 63) / 64;
-  const bool whole_waves = (blockDim.x & 63) == 0;
   AdjSmem<MB, FT> sm;
-  sm.carve(adj_smem, sh, waves);
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  for (int i = tid; i < 3 * sh.E; i += nthr) sm.elem[i] = elem[i];
+  sm.carve(adj_smem, sh);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 3 * sh.E; i += blockDim.x) sm.elem[i] = elem[i];
+  __syncthreads();
   const int per_chirp = sh.m_tiles * sh.o_tiles;
   const int n = blockIdx.x / per_chirp;
   const int mt = (blockIdx.x % per_chirp) / sh.o_tiles;
   const int ot = blockIdx.x % sh.o_tiles;
+  const int m_tile0 = mt * sh.M_t;
+  const int32_t cnt = sc.vis_cnt[n];
+  const int32_t n_tiles = (cnt + FT - 1) / FT;
+
+  if (tid >= sh.n_compute) {
+    const int st = tid - sh.n_compute;
+    if (n_tiles > 0) adj_stage_tile<MB, FT>(sc, rc, sh, sm, sm.tile(0), n, cnt, 0, min(FT, cnt), m_tile0, st);
+    for (int32_t k = 0; k < n_tiles; ++k) {
+      __syncthreads();
+      if (k > 0)
+        adj_flush<MB, FT>(sm, sm.red_buf((k - 1) & 1), partial, ash.F, sh, n, mt, ot, (k - 1) * FT,
+                          min(FT, cnt - (k - 1) * FT), st);
+      const int32_t t1 = (k + 1) * FT;
+      if (t1 < cnt)
+        adj_stage_tile<MB, FT>(sc, rc, sh, sm, sm.tile((k & 1) ^ 1), n, cnt, t1, min(FT, cnt - t1),
+                               m_tile0, st);
+    }
+    __syncthreads();
+    if (n_tiles > 0)
+      adj_flush<MB, FT>(sm, sm.red_buf((n_tiles - 1) & 1), partial, ash.F, sh, n, mt, ot,
+                        (n_tiles - 1) * FT, min(FT, cnt - (n_tiles - 1) * FT), st);
+    return;
+  }
+
   const int P = rc.P, Q = rc.Q, E = sh.E;
   const int ol = tid % sh.O_w, b = tid / sh.O_w;
   const int o = ot * sh.O_w + ol;
-  const bool o_ok = o < sh.O;
+  const bool o_ok = b < sh.B_w && o < sh.O;
   const int p = o_ok ? o / Q : 0, q = o_ok ? o % Q : 0;
-  const int m_tile0 = mt * sh.M_t;
   const int m_base = m_tile0 + b * MB;
-  const int32_t cnt = sc.vis_cnt[n];
   const double slope = rc.slope;
   const float kf0 = static_cast<float>(2.0 * kPi / kC0);
+  const int wv = tid >> 6;
 
   // conj(g) for this thread's samples
   float2 gq[MB];
@@ -260,90 +413,23 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
     }
   }
 
-  for (int32_t t0 = 0; t0 < cnt; t0 += FT) {
-    const int nf = min(FT, cnt - t0);
+  for (int32_t kt = 0; kt < n_tiles; ++kt) {
     __syncthreads();
-    for (int i = tid; i < FT; i += nthr) {
-      if (i < nf)
-        entry_geometry(sc, rc, n, cnt, t0 + i, sm.geo[i]);
-      else
-        sm.geo[i].valid = 0;
-    }
-    __syncthreads();
-    for (int task = tid; task < FT * E; task += nthr) {
-      const int i = task / E, e = task % E;
-      const Geo &g = sm.geo[i];
-      float2 *Ue = sm.U + (i * E + e) * sh.B_w;
-      if (!g.valid) {
-        for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = make_float2(0.0f, 0.0f);
-        sm.rat[i * E + e] = make_float2(1.0f, 0.0f);
-        sm.off[i * E + e] = 0.0f;
-        sm.er[i * E + e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        sm.tau[i * E + e] = 0.0f;
-        continue;
-      }
-      const double dx = sm.elem[3 * e + 0] - g.c[0];
-      const double dy = sm.elem[3 * e + 1] - g.c[1];
-      const double dz = sm.elem[3 * e + 2] - g.c[2];
-      const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
-      const double tau = Rn / kC0;
-      double psi0, offv;
-      if (e < P) {
-        const double d = tau - g.tref_t;
-        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
-               0.5 * slope * g.tref_t * g.tref_r;
-        offv = sh.two_pi_slope * d;
-      } else {
-        const double d = tau - g.tref_r;
-        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
-               0.5 * slope * g.tref_t * g.tref_r;
-        offv = d;
-      }
-      psi0 -= floor(psi0);
-      double delta = rc.df * tau;
-      delta -= floor(delta);
-      const float inv_r = static_cast<float>(1.0 / Rn);
-      for (int bb = 0; bb < sh.B_w; ++bb)
-        Ue[bb] = phasor_m2pi<float>(psi0 + static_cast<double>(m_tile0 + bb * MB) * delta, inv_r);
-      sm.rat[i * E + e] = phasor_m2pi<float>(delta, 1.0f);
-      sm.off[i * E + e] = static_cast<float>(offv);
-      sm.er[i * E + e] = make_float4(static_cast<float>(dx / Rn), static_cast<float>(dy / Rn),
-                                     static_cast<float>(dz / Rn), inv_r);
-      sm.tau[i * E + e] = static_cast<float>(tau);
-    }
-    for (int task = tid; task < FT * sh.M_t; task += nthr) {
-      const int i = task / sh.M_t, j = task % sh.M_t;
-      const Geo &g = sm.geo[i];
-      float2 gv = make_float2(0.0f, 0.0f), dv[3] = {gv, gv, gv};
-      if (g.valid) {
-        const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
-        const double s = fm / kC0;
-        float2 ph, dph[3];
-        phi_grad_turns(s * g.beta[0], s * g.beta[1], s * g.beta[2], &ph, dph);
-        const float ar = static_cast<float>(g.amp_re), ai = static_cast<float>(g.amp_im);
-        gv = make_float2(ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x);
-        const float km = static_cast<float>(2.0 * kPi * s);
-        for (int k = 0; k < 3; ++k)
-          dv[k] = make_float2(km * (ar * dph[k].x - ai * dph[k].y),
-                              km * (ar * dph[k].y + ai * dph[k].x));
-      }
-      float4 *dst = sm.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;
-      dst[0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
-      dst[1] = make_float4(dv[1].x, dv[1].y, dv[2].x, dv[2].y);
-    }
-    __syncthreads();
+    const AdjTile tl = sm.tile(kt & 1);
+    float *red = sm.red_buf(kt & 1);
+    const int nf = min(FT, cnt - kt * FT);
     for (int i = 0; i < nf; ++i) {
-      float v[kAdjVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+      float v[7] = {0, 0, 0, 0, 0, 0, 0};
       if (o_ok) {
-        const float2 up = sm.U[(i * E + p) * sh.B_w + b];
-        const float2 uq = sm.U[(i * E + P + q) * sh.B_w + b];
-        const float2 rp = sm.rat[i * E + p], rq = sm.rat[i * E + P + q];
-        const float eps = sm.off[i * E + p] * sm.off[i * E + P + q];
-        float2 z = make_float2(up.x * uq.x - up.y * uq.y, up.x * uq.y + up.y * uq.x);
-        z = make_float2(z.x - eps * z.y, z.y + eps * z.x);
-        const float2 r = make_float2(rp.x * rq.x - rp.y * rq.y, rp.x * rq.y + rp.y * rq.x);
+        const float2 up = tl.U[(i * E + p) * sh.B_w + b];
+        const float2 uq = tl.U[(i * E + P + q) * sh.B_w + b];
+        const float2 rp = tl.rat[i * E + p], rq = tl.rat[i * E + P + q];
+        const float eps = tl.off[i * E + p] * tl.off[i * E + P + q];
+        float2 z = make_float2(fma_r(up.x, uq.x, -up.y * uq.y), fma_r(up.x, uq.y, up.y * uq.x));
+        z = make_float2(fma_r(-eps, z.y, z.x), fma_r(eps, z.x, z.y));
+        const float2 r = make_float2(fma_r(rp.x, rq.x, -rp.y * rq.y), fma_r(rp.x, rq.y, rp.y * rq.x));
         // per sample: (G, D0) and (D1, D2) as two 16-byte LDS reads, a block ahead
-        const float4 *gd = sm.GD + (static_cast<int64_t>(i) * sh.M_t + b * MB) * 2;
+        const float4 *gd = tl.GD + (static_cast<int64_t>(i) * sh.M_t + b * MB) * 2;
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
         constexpr int kB = 2;
         float4 ca[2 * kB], cb[2 * kB];
@@ -365,7 +451,7 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
             const float yy = fma_r(g0.x, w.y, g0.y * w.x);
             s0 += yx;
             s1 += yy;
-            s2 = fma_r(static_cast<float>(m_base + j), yy, s2);
+            s2 = fma_r(static_cast<float>(j), yy, s2);
             a0 = fma_r(g0.z, w.x, fma_r(-g0.w, w.y, a0));
             a1 = fma_r(g1.x, w.x, fma_r(-g1.y, w.y, a1));
             a2 = fma_r(g1.z, w.x, fma_r(-g1.w, w.y, a2));
@@ -376,11 +462,13 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
 #pragma unroll
           for (int u = 0; u < 2 * kB; ++u) ca[u] = cb[u];
         }
+        // sum_m m Im(y) with m counted from the block start; shift to absolute m
+        s2 = fma_r(static_cast<float>(m_base), s1, s2);
         // dL/dR_p and dL/dR_q of this channel, then onto the centroid: dR/dc = -e_hat
-        const float tpq = sm.tau[i * E + p] + sm.tau[i * E + P + q];
+        const float tpq = tl.tau[i * E + p] + tl.tau[i * E + P + q];
         const float f0mu = static_cast<float>(rc.f0 - slope * static_cast<double>(tpq));
         const float kap = kf0 * (f0mu * s1 + static_cast<float>(rc.df) * s2);
-        const float4 ep = sm.er[i * E + p], eq = sm.er[i * E + P + q];
+        const float4 ep = tl.er[i * E + p], eq = tl.er[i * E + P + q];
         const float cp = kap - s0 * ep.w, cq = kap - s0 * eq.w;
         v[0] = -(cp * ep.x + cq * eq.x);
         v[1] = -(cp * ep.y + cq * eq.y);
@@ -390,22 +478,15 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
         v[5] = a1;
         v[6] = a2;
       }
-      const int wv = tid >> 6;
+      // every lane of the (whole) wave takes part: DPP reads all lanes
 #pragma unroll
       for (int k = 0; k < 7; ++k) {
-        const float s = whole_waves ? wave_sum(v[k]) : wave_sum_partial(v[k]);
-        if ((tid & 63) == 0) sm.red[(i * waves + wv) * kAdjVals + k] = s;
+        const float s = wave_sum(v[k]);
+        if ((tid & 63) == 0) red[(i * sm.waves + wv) * kAdjVals + k] = s;
       }
     }
-    __syncthreads();
-    for (int task = tid; task < nf * 7; task += nthr) {
-      const int i = task / 7, k = task % 7;
-      float s = 0.0f;
-      for (int wv = 0; wv < waves; ++wv) s += sm.red[(i * waves + wv) * kAdjVals + k];
-      const int64_t slot = ((static_cast<int64_t>(n) * ash.F + t0 + i) * sh.m_tiles + mt) * sh.o_tiles + ot;
-      partial[slot * kAdjVals + k] = s;
-    }
   }
+  __syncthreads();
 }
 
 // Per lit (chirp, facet): sum the partials and apply the chain rule to the three
@@ -564,8 +645,8 @@ __global__ void __launch_bounds__(256) velocity_reduce_kernel(const double *vpar
 
 }  // namespace
 
-constexpr int kAdjMB = 32;
-constexpr int kAdjFT = 16;
+constexpr int kAdjMB = 64;
+constexpr int kAdjFT = 8;
 
 size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F) {
   return static_cast<size_t>(N) * F * sh.m_tiles * sh.o_tiles * kAdjVals;
@@ -573,16 +654,13 @@ size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F) {
 
 int adjoint_tile_m() { return kAdjMB; }
 
-size_t adjoint_smem_bytes(const EchoShape &sh) {
-  const int waves = (sh.O_w * sh.B_w + 63) / 64;
-  return AdjSmem<kAdjMB, kAdjFT>::bytes(sh, waves);
-}
+size_t adjoint_smem_bytes(const EchoShape &sh) { return AdjLayout<kAdjMB, kAdjFT>(sh).total; }
 
 hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
                           hipStream_t s) {
   AdjShape ash{sh, static_cast<int32_t>(sc.n_facets), 0};
-  const int threads = sh.O_w * sh.B_w;
+  const int threads = sh.n_compute + kStagingThreads;
   const int64_t gx_n = static_cast<int64_t>(rc.N) * sc.n_facets * 9;
   hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, gxw, gx_n);
   if (sc.n_facets == 0) return hipGetLastError();

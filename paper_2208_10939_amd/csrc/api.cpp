@@ -951,7 +951,9 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   if ((rc = need_device(ctx))) return rc;
   SceneRec &sc = ctx->scenes[scene_id];
   if ((rc = ensure_scene_device(ctx, sc))) return rc;
-  const EchoShape sh = echo_shape(ctx, rcn, adjoint_tile_m());
+  EchoShape sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads);
+  while (sh.B_w > 1 && adjoint_smem_bytes(sh) > ctx->max_lds)
+    sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads, sh.B_w - 1);
   if (adjoint_smem_bytes(sh) > ctx->max_lds)
     return fail(ctx, RSIM_ERANGE, "adjoint tile needs %zu bytes of LDS", adjoint_smem_bytes(sh));
   const int64_t F = sc.n_facets, N = rcn.N;

@@ -24,92 +24,6 @@
 
 namespace rsim {
 
-// FP32 path: the facet integral G_f(m) over one sample tile, with every phase reduced
-// in FP64 at the tile's first sample and advanced linearly in FP32 from there (the
-// spatial frequency s_m = f_m / c is linear in m, and so is every argument of Phi).
-// Nodes l, i, j as in phi_turns: (i, j) spans the widest gap. With nodes taken about
-// the centroid, the divided-difference form reads
-//   Phi = (f_j - f_i) / (2 pi s (b_j - b_i)),
-//   f_k = -j exp(j pi s (b_l + b_k)) sinc(pi s (b_k - b_l)),
-// and below the series gap the Taylor series about the mean applies as in phi_turns.
-struct alignas(16) GLin {
-  float gap, gap_i;          // rad: 2 pi s g_max (series below kSeriesGap)
-  float p1, p1_i, p2, p2_i;  // turns: s (b_l + b_j) / 2, s (b_l + b_i) / 2
-  float t1, t1_i, t2, t2_i;  // turns: s (b_j - b_l) / 2, s (b_i - b_l) / 2
-  float x1, x1_i, x2, x2_i;  // rad: pi s (b_j - b_l), pi s (b_i - b_l)
-  float w, w_i;              // rad: 2 pi s (b_j - b_i)
-  float b0, b0_i, b1, b1_i, b2, b2_i;  // rad: 2 pi s (b_k - mean)
-  float mp, mp_i;            // turns: s mean
-  float ar, ai;              // G = (ar + j ai) Phi
-  int32_t valid, pad0, pad1, pad2;
-};
-
-__device__ inline float centred_turns(double t) { return static_cast<float>(t - rint(t)); }
-
-// Coefficients for samples m = m_tile0 + j of the facet with geometry g.
-__device__ inline void make_glin(const Geo &g, const RadarConst &rc, int m_tile0, GLin &q) {
-  q.valid = g.valid;
-  if (!g.valid) return;
-  const double inv_c = 1.0 / kC0;
-  const double s0 = (rc.f0 + static_cast<double>(m_tile0) * rc.df) * inv_c;
-  const double ds = rc.df * inv_c;
-  const double mean = (g.beta[0] + g.beta[1] + g.beta[2]) * (1.0 / 3.0);
-  const double B0 = g.beta[0] - mean, B1 = g.beta[1] - mean, B2 = g.beta[2] - mean;
-  const double g12 = fabs(B1 - B2), g02 = fabs(B0 - B2), g01 = fabs(B0 - B1);
-  double bl, bi, bj, gmax;
-  if (g12 >= g02 && g12 >= g01) {
-    bl = B0; bi = B1; bj = B2; gmax = g12;
-  } else if (g02 >= g01) {
-    bl = B1; bi = B0; bj = B2; gmax = g02;
-  } else {
-    bl = B2; bi = B0; bj = B1; gmax = g01;
-  }
-  const double two_pi = 2.0 * kPi;
-  q.gap = static_cast<float>(two_pi * s0 * gmax);
-  q.gap_i = static_cast<float>(two_pi * ds * gmax);
-  // the sinc form on absolute nodes b + mean, so no separate mean phase
-  const double S1 = 0.5 * (bl + bj) + mean, S2 = 0.5 * (bl + bi) + mean;
-  q.p1 = centred_turns(s0 * S1);
-  q.p1_i = static_cast<float>(ds * S1);
-  q.p2 = centred_turns(s0 * S2);
-  q.p2_i = static_cast<float>(ds * S2);
-  const double d1 = bj - bl, d2 = bi - bl;
-  q.t1 = centred_turns(0.5 * s0 * d1);
-  q.t1_i = static_cast<float>(0.5 * ds * d1);
-  q.t2 = centred_turns(0.5 * s0 * d2);
-  q.t2_i = static_cast<float>(0.5 * ds * d2);
-  q.x1 = static_cast<float>(kPi * s0 * d1);
-  q.x1_i = static_cast<float>(kPi * ds * d1);
-  q.x2 = static_cast<float>(kPi * s0 * d2);
-  q.x2_i = static_cast<float>(kPi * ds * d2);
-  q.w = static_cast<float>(two_pi * s0 * (bj - bi));
-  q.w_i = static_cast<float>(two_pi * ds * (bj - bi));
-  q.b0 = static_cast<float>(two_pi * s0 * B0);
-  q.b0_i = static_cast<float>(two_pi * ds * B0);
-  q.b1 = static_cast<float>(two_pi * s0 * B1);
-  q.b1_i = static_cast<float>(two_pi * ds * B1);
-  q.b2 = static_cast<float>(two_pi * s0 * B2);
-  q.b2_i = static_cast<float>(two_pi * ds * B2);
-  q.mp = centred_turns(s0 * mean);
-  q.mp_i = static_cast<float>(ds * mean);
-  q.ar = static_cast<float>(g.amp_re);
-  q.ai = static_cast<float>(g.amp_im);
-}
-
-// sin(x) / x for x = x0 + j x_i (rad), t = t0 + j t_i = x / (2 pi) (turns, centred at
-// j = 0). Below |x| = 0.1 the even series to x^4 (error < x^6 / 5040 <= 2e-10 relative);
-// above, the hardware sine (absolute error ~1.3e-7) over x, relative error <= 1.3e-6.
-__device__ inline float sinc_lin(float x0, float x_i, float t0, float t_i, float jf) {
-  const float x = fmaf(jf, x_i, x0);
-  if (fabsf(x) < 0.1f) {
-    const float x2 = x * x;
-    return fmaf(x2, fmaf(x2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
-  }
-  float t = fmaf(jf, t_i, t0);
-  t -= rintf(t);
-  return __builtin_amdgcn_sinf(t) * __builtin_amdgcn_rcpf(x);
-}
-
 // G_f(m_tile0 + j)
 __device__ inline float2 g_lin(const GLin &q, int j) {
   if (!q.valid) return {0.0f, 0.0f};
