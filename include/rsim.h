@@ -52,7 +52,7 @@ typedef struct rsim_ctx rsim_ctx;
 
 /* FMCW waveform (eq. (8), Section 4.1). Sample m of chirp n is taken at frequency
  * f_m = f0 + m * slope / fs and chirp start time t_n = n * chirp_period.
- * n_samples (M) and n_chirps (N) in 1..4096; rsim_form_rdm needs powers of two. */
+ * n_samples (M) and n_chirps (N) in 1..4096; the RDM calls need lengths 2^a 3^b. */
 typedef struct {
   double f0_hz;
   double slope_hz_per_s;
@@ -171,7 +171,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
  *   echo  DEVICE [n_cubes][O][N][M] complex64 (complex128 with RSIM_FP64)
  *   rdm   DEVICE [n_cubes][O][N][M] float32 (float64 with RSIM_FP64), row = Doppler
  *   y_opt DEVICE or NULL, Y in the echo's complex type and layout.
- * ERANGE unless M and N are powers of two in 2..4096. */
+ * ERANGE unless M and N are of the form 2^a 3^b in 2..4096 (mixed radix-2/3 FFT). */
 int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm,
                       void *y_opt, void *hip_stream, const rsim_opts *opts);
 

@@ -199,7 +199,13 @@ bool finite_all(const double *p, size_t n) {
   return true;
 }
 
-bool is_pow2(int v) { return v >= 2 && (v & (v - 1)) == 0; }
+// FFT lengths of the range and Doppler transforms: 2^a 3^b in 2..4096
+bool fft_size_ok(int v) {
+  if (v < 2 || v > 4096) return false;
+  while (v % 2 == 0) v /= 2;
+  while (v % 3 == 0) v /= 3;
+  return v == 1;
+}
 
 int32_t need_device(rsim_ctx *ctx) {
   if (ctx->host_only) return fail(ctx, RSIM_EDEVICE, "host-only context: no device calls");
@@ -376,11 +382,11 @@ void *twiddles(rsim_ctx *ctx, int L, int precision, int32_t *status) {
   auto key = std::make_pair(L, precision);
   auto it = ctx->twiddles.find(key);
   if (it != ctx->twiddles.end()) return it->second;
-  const int half = std::max(1, L / 2);
+  const int full = std::max(1, L);
   void *p = nullptr;
   if (precision) {
-    std::vector<double> t(2 * half);
-    for (int i = 0; i < half; ++i) {
+    std::vector<double> t(2 * full);
+    for (int i = 0; i < full; ++i) {
       t[2 * i] = std::cos(2.0 * kPi * i / L);
       t[2 * i + 1] = -std::sin(2.0 * kPi * i / L);
     }
@@ -388,8 +394,8 @@ void *twiddles(rsim_ctx *ctx, int L, int precision, int32_t *status) {
     *status = upload(ctx, &d, t.data(), t.size());
     p = d;
   } else {
-    std::vector<float> t(2 * half);
-    for (int i = 0; i < half; ++i) {
+    std::vector<float> t(2 * full);
+    for (int i = 0; i < full; ++i) {
       t[2 * i] = static_cast<float>(std::cos(2.0 * kPi * i / L));
       t[2 * i + 1] = static_cast<float>(-std::sin(2.0 * kPi * i / L));
     }
@@ -1017,8 +1023,8 @@ int32_t rsim_rdm_backward(rsim_ctx *ctx, const float *grad_rdm, const void *y, i
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
-  if (!is_pow2(M) || !is_pow2(N))
-    return fail(ctx, RSIM_ERANGE, "rsim_rdm_backward: M and N must be powers of two");
+  if (!fft_size_ok(M) || !fft_size_ok(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_rdm_backward: M and N must be 2^a 3^b in 2..4096");
   if ((rc = need_device(ctx))) return rc;
   const int64_t O = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3);
   const int64_t planes = O * n_cubes;
@@ -1047,8 +1053,8 @@ int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rd
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
-  if (!is_pow2(M) || !is_pow2(N))
-    return fail(ctx, RSIM_ERANGE, "rsim_form_rdm: M=%d and N=%d must be powers of two in 2..4096", M, N);
+  if (!fft_size_ok(M) || !fft_size_ok(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_form_rdm: M=%d and N=%d must be 2^a 3^b in 2..4096", M, N);
   if ((rc = need_device(ctx))) return rc;
   const int precision = o.precision ? 1 : 0;
   const size_t csize = precision ? 16 : 8;
@@ -1082,8 +1088,8 @@ int32_t rsim_rdm_adjoint(rsim_ctx *ctx, const void *grad_y, int32_t n_cubes, voi
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
-  if (!is_pow2(M) || !is_pow2(N))
-    return fail(ctx, RSIM_ERANGE, "rsim_rdm_adjoint: M and N must be powers of two");
+  if (!fft_size_ok(M) || !fft_size_ok(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_rdm_adjoint: M and N must be 2^a 3^b in 2..4096");
   if ((rc = need_device(ctx))) return rc;
   const int64_t O = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3);
   const int64_t planes = O * n_cubes;

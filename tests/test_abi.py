@@ -102,10 +102,13 @@ def test_validation_codes_host_only():
     ctx.set_array(arr.tx * 0 + np.array([[-50.0, 0, 6], [50.0, 0, 6]]).repeat(6, 0),
                   arr.rx * 0 + np.array([[-50.0, 0, 6], [50.0, 0, 6]]).repeat(8, 0))
     assert L.rsim_synthesize(ctx._h, ids, 1, echo, None, None, ctypes.byref(o)) == rsim.RSIM_ERANGE
-    # RDM needs powers of two
+    # the RDM transforms take lengths 2^a 3^b: 320 = 2^6 5 is refused before any device
+    # work, 384 = 2^7 3 passes the size check and stops at the missing device
     ctx.set_array(arr.tx, arr.rx)
-    ctx.set_waveform(scenes.paper_waveform(384, 8))
+    ctx.set_waveform(scenes.paper_waveform(320, 8))
     assert L.rsim_form_rdm(ctx._h, echo, 1, echo, None, None, ctypes.byref(o)) == rsim.RSIM_ERANGE
+    ctx.set_waveform(scenes.paper_waveform(384, 48))
+    assert L.rsim_form_rdm(ctx._h, echo, 1, echo, None, None, ctypes.byref(o)) == rsim.RSIM_EDEVICE
     ctx.close()
 
 

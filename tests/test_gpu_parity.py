@@ -125,12 +125,29 @@ def test_small_intersection_fp32_and_rdm(sim_mod):
     assert err <= 2 * FP32_TOL
 
 
+def test_experiment2_waveform_384_samples(sim_mod):
+    """The paper's second experiment waveform (384 samples per chirp; Table 2) end to end
+    on a small vehicle scene: echo and RDM against the oracle (radix-3 range FFT, and a
+    Doppler length of 12 = 2^2 3)."""
+    _log("case experiment-2 waveform M=384 N=12, 1.5k-triangle vehicle")
+    base = scenes.small_single(n_samples=384, n_chirps=12)
+    sim, H, Ho = _check_mask_then_echo(sim_mod, base, 0, FP32_TOL)
+    rdm = sim.form_rdm(H).cpu().numpy()[0]
+    Po, _ = oracle.rdm_from_echo(Ho)
+    err = rel_rms(rdm, Po)
+    _log(f"  rdm rel_rms={err:.3e}")
+    assert err <= 2 * FP32_TOL
+
+
 @pytest.mark.parametrize("precision", [0, 1])
-def test_rdm_fft_against_numpy(sim_mod, precision):
-    """Range/Doppler FFTs and the RDM on a seeded random cube vs numpy.fft (FP64)."""
+@pytest.mark.parametrize("M,N", [(256, 64), (384, 48), (162, 6)])
+def test_rdm_fft_against_numpy(sim_mod, precision, M, N):
+    """Range/Doppler FFTs and the RDM on a seeded random cube vs numpy.fft (FP64), at
+    power-of-two lengths and at mixed radix-2/3 lengths (384 samples is the paper's
+    second experiment; 162 = 2 x 3^4)."""
     import torch
-    _log(f"case rdm_fft precision={precision}")
-    wf = scenes.paper_waveform(256, 64)
+    _log(f"case rdm_fft precision={precision} M={M} N={N}")
+    wf = scenes.paper_waveform(M, N)
     arr = scenes.sparse_mimo_12x16(wf, 1)
     sim = sim_mod.Simulator([scenes.point_scene([20.0], [1.0])], wf, arr)
     rng = np.random.default_rng(7)
@@ -147,11 +164,12 @@ def test_rdm_fft_against_numpy(sim_mod, precision):
     assert e1 <= tol and e2 <= 2 * tol
 
 
-def test_rdm_adjoint_identity(sim_mod):
+@pytest.mark.parametrize("M,N", [(128, 32), (96, 12)])
+def test_rdm_adjoint_identity(sim_mod, M, N):
     """<A x, g> = <x, A^H g> (real inner product) for the linear map x -> Y."""
     import torch
-    _log("case rdm_adjoint")
-    wf = scenes.paper_waveform(128, 32)
+    _log(f"case rdm_adjoint M={M} N={N}")
+    wf = scenes.paper_waveform(M, N)
     arr = scenes.ula_1tx4rx(wf)
     sim = sim_mod.Simulator([scenes.point_scene([20.0], [1.0])], wf, arr)
     rng = np.random.default_rng(3)
