@@ -212,6 +212,65 @@ int32_t rsim_rdm_backward(rsim_ctx *ctx, const float *grad_rdm, const void *y, i
 int32_t rsim_rdm_adjoint(rsim_ctx *ctx, const void *grad_y, int32_t n_cubes,
                          void *grad_echo, void *hip_stream);
 
+/* ---- detection, point cloud, noise ------------------------------------------------- */
+
+/* CA-CFAR and angle-FFT settings (Section 3.3; the paper leaves window sizes and the
+ * threshold open, so they are parameters). Around each cell under test: guard cells
+ * on each side (Doppler rows, range bins), then training cells on each side beyond
+ * them; noise = mean power over the training ring, both axes periodic. A cell is
+ * detected when its power exceeds scale x noise. The angle FFT runs over the virtual
+ * array on its half-wavelength grid, zero-padded to na_x x na_z. */
+typedef struct {
+  int32_t guard_doppler, guard_range;
+  int32_t train_doppler, train_range;
+  float scale;       /* threshold factor on the training mean, > 0                      */
+  int32_t na_x;      /* angle FFT length along x, 2^a 3^b; 0 = smallest >= 2 x extent    */
+  int32_t na_z;      /* along z; 0 = as na_x (1 when the virtual array is one row)       */
+  int32_t max_points;/* points written per cube, >= 1                                    */
+} rsim_cfar_opts;
+
+/* One detected range-Doppler cell and its point. */
+typedef struct {
+  int32_t row, bin;           /* Doppler row (zero Doppler at row N/2) and range bin     */
+  float power, noise;         /* channel-integrated power and the CFAR noise estimate   */
+  float range_m;              /* eq. (4): bin x c / (2 B)                                */
+  float velocity_mps;         /* eq. (5): (row - N/2) x lambda_c / (2 N T_c), + receding */
+  float u, w;                 /* direction cosines along x and z from the angle peak     */
+  float x, y, z;              /* point: phase-centre midpoint + range (u, sqrt(1-u^2-w^2), w) */
+  float angle_power;          /* |angle spectrum|^2 at the peak                          */
+  int32_t kx, kz;             /* signed angle bins of the peak                           */
+  int32_t reserved[2];
+} rsim_point;
+
+/* Detection and point cloud of n_cubes RDM frames (Section 3.3; eq. (6)): the channel-
+ * integrated map P[n][m] = sum_o rdm[o][n][m], CA-CFAR on P, then for each detected
+ * cell (row-major order) the 2-D angle FFT of Y over the virtual-array grid, whose
+ * first maximum gives u = -2 kx / na_x, w = -2 kz / na_z (Y comes from the beat signal
+ * conj(H), so a target in direction d carries phases exp(-j k d . v) across the
+ * virtual elements v = tx_p + rx_q).
+ *   rdm        DEVICE [n_cubes][O][N][M] float32 (rsim_form_rdm, FP32)
+ *   y          DEVICE [n_cubes][O][N][M] complex64 (rsim_form_rdm's y_opt)
+ *   det_mask   DEVICE [n_cubes][N][M] uint8 or NULL: 1 = detected
+ *   noise_map  DEVICE [n_cubes][N][M] float32 or NULL: CFAR noise estimate
+ *   points     DEVICE [n_cubes][max_points] rsim_point: the first max_points detections
+ *   n_points   DEVICE [n_cubes] int32: number of detections (may exceed max_points)
+ * EINVAL for bad settings; ERANGE when the window does not fit the map (2 (guard +
+ * train) + 1 > N or M), when the virtual elements are not on a half-wavelength grid
+ * in one x-z plane, or when an angle length is not 2^a 3^b or exceeds the LDS. */
+int32_t rsim_detect(rsim_ctx *ctx, const float *rdm, const void *y, int32_t n_cubes,
+                    const rsim_cfar_opts *opts, uint8_t *det_mask, float *noise_map,
+                    rsim_point *points, int32_t *n_points, void *hip_stream);
+
+/* Adds complex white Gaussian noise at snr_db to n_cubes echo cubes in place (Section
+ * 3.2): sigma^2 = mean |H|^2 of the cube / 10^(snr_db / 10), each part variance
+ * sigma^2 / 2. Normals from Philox4x32-10 (counter = element index lo, hi, cube, 0;
+ * key = seed lo, hi) through Box-Muller in FP64, so a given seed gives the same noise
+ * on any device.
+ *   echo DEVICE [n_cubes][O][N][M] complex64 (complex128 with opts->precision =
+ *   RSIM_FP64); opts may be NULL. */
+int32_t rsim_add_noise(rsim_ctx *ctx, void *echo, int32_t n_cubes, double snr_db,
+                       uint64_t seed, void *hip_stream, const rsim_opts *opts);
+
 /* ---- tuning ------------------------------------------------------------------------- */
 
 /* Time the facet-sum tile shapes on the given scenes and keep the fastest as the

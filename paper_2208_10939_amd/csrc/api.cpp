@@ -125,6 +125,14 @@ struct rsim_ctx {
   size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0;
   BatchTables batch;  // persistent launches outside graphs
   GraphCache graph;
+  // detection and noise work buffers (grow only)
+  void *det_P = nullptr, *det_mask = nullptr, *det_noise = nullptr, *det_list = nullptr;
+  size_t det_P_n = 0, det_mask_n = 0, det_noise_n = 0, det_list_n = 0;
+  int32_t *det_nodes = nullptr;             // node position, CSR offsets, channels
+  size_t det_nodes_n = 0;
+  std::vector<int32_t> det_nodes_host;      // uploaded contents
+  double *noise_part = nullptr;
+  size_t noise_part_n = 0;
 };
 
 namespace {
@@ -175,6 +183,17 @@ void dev_free(rsim_ctx *ctx, void *p) {
     ctx->allocs.erase(it);
   }
   (void)hipFree(p);
+}
+
+// Grow-only device buffer: reallocates (contents lost) when fewer than `bytes` are held.
+int32_t grow_bytes(rsim_ctx *ctx, void **p, size_t *cap, size_t bytes) {
+  if (*cap >= bytes && *p) return RSIM_OK;
+  dev_free(ctx, *p);
+  *p = nullptr;
+  *cap = 0;
+  int32_t rc = dev_alloc(ctx, p, std::max<size_t>(bytes, 64));
+  if (!rc) *cap = std::max<size_t>(bytes, 64);
+  return rc;
 }
 
 template <typename T>
@@ -1120,6 +1139,159 @@ int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages) {
     ms[k] = v;
   }
   ctx->timing_pending = false;
+  return RSIM_OK;
+}
+
+int32_t rsim_detect(rsim_ctx *ctx, const float *rdm, const void *y, int32_t n_cubes,
+                    const rsim_cfar_opts *opts, uint8_t *det_mask, float *noise_map,
+                    rsim_point *points, int32_t *n_points, void *hip_stream) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!rdm || !y || !opts || !points || !n_points || n_cubes < 1)
+    return fail(ctx, RSIM_EINVAL, "rsim_detect: need rdm, y, opts, points, n_points, n_cubes >= 1");
+  const rsim_cfar_opts o = *opts;
+  if (o.guard_doppler < 0 || o.guard_range < 0 || o.train_doppler < 0 || o.train_range < 0 ||
+      o.train_doppler + o.train_range < 1 || !(o.scale > 0.0f) || !std::isfinite(o.scale) ||
+      o.max_points < 1 || o.na_x < 0 || o.na_z < 0)
+    return fail(ctx, RSIM_EINVAL, "rsim_detect: bad CFAR settings");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
+  const int hd = o.guard_doppler + o.train_doppler, hr = o.guard_range + o.train_range;
+  if (2 * hd + 1 > N || 2 * hr + 1 > M)
+    return fail(ctx, RSIM_ERANGE, "rsim_detect: CFAR window %dx%d exceeds the %dx%d map",
+                2 * hd + 1, 2 * hr + 1, N, M);
+  // virtual elements tx_p + rx_q on the half-wavelength grid of the x-z plane
+  const double df = ctx->wf.slope_hz_per_s / ctx->wf.fs_hz;
+  const double lam_c = kC0 / (ctx->wf.f0_hz + 0.5 * M * df);
+  const double d = 0.5 * lam_c;
+  const int P = static_cast<int>(ctx->tx.size() / 3), Q = static_cast<int>(ctx->rx.size() / 3);
+  const int O = P * Q;
+  std::vector<double> vx(O), vy(O), vz(O);
+  for (int p = 0; p < P; ++p)
+    for (int q = 0; q < Q; ++q) {
+      vx[p * Q + q] = ctx->tx[3 * p + 0] + ctx->rx[3 * q + 0];
+      vy[p * Q + q] = ctx->tx[3 * p + 1] + ctx->rx[3 * q + 1];
+      vz[p * Q + q] = ctx->tx[3 * p + 2] + ctx->rx[3 * q + 2];
+    }
+  const double x0 = *std::min_element(vx.begin(), vx.end());
+  const double z0 = *std::min_element(vz.begin(), vz.end());
+  const double y_lo = *std::min_element(vy.begin(), vy.end());
+  const double y_hi = *std::max_element(vy.begin(), vy.end());
+  if (y_hi - y_lo > 1e-9)
+    return fail(ctx, RSIM_ERANGE, "rsim_detect: virtual elements are not in one x-z plane");
+  std::vector<int> ix(O), iz(O);
+  int nx = 0, nz = 0;
+  for (int k = 0; k < O; ++k) {
+    const double gx = (vx[k] - x0) / d, gz = (vz[k] - z0) / d;
+    ix[k] = static_cast<int>(std::lround(gx));
+    iz[k] = static_cast<int>(std::lround(gz));
+    if (std::fabs(gx - ix[k]) > 1e-6 || std::fabs(gz - iz[k]) > 1e-6)
+      return fail(ctx, RSIM_ERANGE, "rsim_detect: virtual elements are not on a half-wavelength grid");
+    nx = std::max(nx, ix[k] + 1);
+    nz = std::max(nz, iz[k] + 1);
+  }
+  auto smallest_fft = [](int n) {
+    int best = 1 << 30;
+    for (long p2 = 1; p2 < 4L * n + 4; p2 *= 2)
+      for (long p = p2; p < 4L * n + 4; p *= 3)
+        if (p >= n && p < best) best = static_cast<int>(p);
+    return best;
+  };
+  const int na_x = o.na_x ? o.na_x : smallest_fft(2 * nx);
+  const int na_z = o.na_z ? o.na_z : (nz == 1 ? 1 : smallest_fft(2 * nz));
+  if (!fft_size_ok(na_x) || na_x < nx || (na_z != 1 && !fft_size_ok(na_z)) || na_z < nz)
+    return fail(ctx, RSIM_ERANGE, "rsim_detect: angle lengths %dx%d must be 2^a 3^b covering the "
+                "%dx%d virtual grid", na_x, na_z, nx, nz);
+  if ((rc = need_device(ctx))) return rc;
+  if (cfar_smem_bytes(o.guard_doppler, o.guard_range, o.train_doppler, o.train_range) > ctx->max_lds)
+    return fail(ctx, RSIM_ERANGE, "rsim_detect: CFAR window too large for LDS");
+  if (angle_smem_bytes(na_x, na_z) + 4096 > ctx->max_lds)
+    return fail(ctx, RSIM_ERANGE, "rsim_detect: angle grid %dx%d too large for LDS", na_x, na_z);
+  // grid nodes in ascending position, each with its channels in channel order
+  std::vector<int> order(O);
+  for (int k = 0; k < O; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return iz[a] * na_x + ix[a] < iz[b] * na_x + ix[b];
+  });
+  std::vector<int32_t> pos, off, ch;
+  for (int k = 0; k < O; ++k) {
+    const int g = iz[order[k]] * na_x + ix[order[k]];
+    if (pos.empty() || pos.back() != g) {
+      pos.push_back(g);
+      off.push_back(k);
+    }
+    ch.push_back(order[k]);
+  }
+  off.push_back(O);
+  const int n_nodes = static_cast<int>(pos.size());
+  std::vector<int32_t> tables;
+  tables.insert(tables.end(), pos.begin(), pos.end());
+  tables.insert(tables.end(), off.begin(), off.end());
+  tables.insert(tables.end(), ch.begin(), ch.end());
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (tables != ctx->det_nodes_host) {
+    HIP_TRY(ctx, hipStreamSynchronize(s));  // an earlier call may still read the tables
+    void *pn = ctx->det_nodes;
+    if ((rc = grow_bytes(ctx, &pn, &ctx->det_nodes_n, sizeof(int32_t) * tables.size()))) return rc;
+    ctx->det_nodes = static_cast<int32_t *>(pn);
+    HIP_TRY(ctx, hipMemcpy(ctx->det_nodes, tables.data(), sizeof(int32_t) * tables.size(),
+                           hipMemcpyHostToDevice));
+    ctx->det_nodes_host = tables;
+  }
+  const int64_t cells = static_cast<int64_t>(n_cubes) * N * M;
+  if ((rc = grow_bytes(ctx, &ctx->det_P, &ctx->det_P_n, sizeof(float) * cells))) return rc;
+  if (!det_mask) {
+    if ((rc = grow_bytes(ctx, &ctx->det_mask, &ctx->det_mask_n, cells))) return rc;
+    det_mask = static_cast<uint8_t *>(ctx->det_mask);
+  }
+  if (!noise_map) {
+    if ((rc = grow_bytes(ctx, &ctx->det_noise, &ctx->det_noise_n, sizeof(float) * cells))) return rc;
+    noise_map = static_cast<float *>(ctx->det_noise);
+  }
+  if ((rc = grow_bytes(ctx, &ctx->det_list, &ctx->det_list_n,
+                       sizeof(int32_t) * static_cast<size_t>(n_cubes) * o.max_points)))
+    return rc;
+  void *tw_x = twiddles(ctx, na_x, 0, &rc);
+  if (rc) return rc;
+  void *tw_z = na_z > 1 ? twiddles(ctx, na_z, 0, &rc) : tw_x;
+  if (rc) return rc;
+  double c_ref[3];
+  for (int k = 0; k < 3; ++k) {
+    double a = 0.0, b = 0.0;
+    for (int p = 0; p < P; ++p) a += ctx->tx[3 * p + k];
+    for (int q = 0; q < Q; ++q) b += ctx->rx[3 * q + k];
+    c_ref[k] = 0.5 * (a / P + b / Q);
+  }
+  const double range_res = kC0 / (2.0 * M * df);
+  const double vel_res = lam_c / (2.0 * N * ctx->wf.chirp_period_s);
+  const int32_t *nodes = ctx->det_nodes;
+  HIP_TRY(ctx, launch_detect(rdm, y, n_cubes, O, N, M, o.guard_doppler, o.guard_range,
+                             o.train_doppler, o.train_range, o.scale, na_x, na_z, o.max_points,
+                             range_res, vel_res, c_ref, nodes, nodes + n_nodes,
+                             nodes + 2 * n_nodes + 1, n_nodes, tw_x, tw_z,
+                             static_cast<float *>(ctx->det_P), det_mask, noise_map,
+                             static_cast<int32_t *>(ctx->det_list), n_points, points, s));
+  return RSIM_OK;
+}
+
+int32_t rsim_add_noise(rsim_ctx *ctx, void *echo, int32_t n_cubes, double snr_db, uint64_t seed,
+                       void *hip_stream, const rsim_opts *opts) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!echo || n_cubes < 1 || !std::isfinite(snr_db))
+    return fail(ctx, RSIM_EINVAL, "rsim_add_noise: need echo, n_cubes >= 1 and a finite SNR");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  if ((rc = need_device(ctx))) return rc;
+  const int precision = (opts && opts->precision) ? 1 : 0;
+  const int64_t n = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3) *
+                    ctx->wf.n_chirps * ctx->wf.n_samples;
+  void *part = ctx->noise_part;
+  const size_t need = sizeof(double) * static_cast<size_t>(n_cubes) * (noise_partials_per_cube() + 1);
+  if ((rc = grow_bytes(ctx, &part, &ctx->noise_part_n, need))) return rc;
+  ctx->noise_part = static_cast<double *>(part);
+  double *scale = ctx->noise_part + static_cast<size_t>(n_cubes) * noise_partials_per_cube();
+  HIP_TRY(ctx, launch_add_noise(precision, echo, n, n_cubes, snr_db, seed, ctx->noise_part, scale,
+                                static_cast<hipStream_t>(hip_stream)));
   return RSIM_OK;
 }
 

@@ -44,6 +44,20 @@ hipError_t launch_doppler_fft(int precision, const void *in, void *y_out, void *
                               int64_t planes, int N, int M, int mode, const void *tw,
                               hipStream_t s, const void *gp = nullptr);
 
+// detection stage and white Gaussian noise
+size_t cfar_smem_bytes(int gd, int gr, int td, int tr);
+size_t angle_smem_bytes(int na_x, int na_z);
+hipError_t launch_detect(const float *rdm, const void *y, int64_t cubes, int O, int N, int M,
+                         int gd, int gr, int td, int tr, float scale, int na_x, int na_z,
+                         int max_points, double range_res, double vel_res, const double *c_ref,
+                         const int32_t *node_pos, const int32_t *node_off,
+                         const int32_t *node_ch, int n_nodes, const void *tw_x, const void *tw_z,
+                         float *P, uint8_t *det, float *noise, int32_t *list, int32_t *count,
+                         void *points, hipStream_t s);
+hipError_t launch_add_noise(int precision, void *echo, int64_t n, int64_t cubes, double snr_db,
+                            uint64_t seed, double *part, double *scale, hipStream_t s);
+int noise_partials_per_cube();
+
 // adjoint of the facet sum (FP32): partial sums per (chirp, lit facet, tile), then
 // per-facet world-vertex gradients gxw [N][F][9]
 size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F);

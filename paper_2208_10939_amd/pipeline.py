@@ -8,7 +8,8 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from .rsim import Context, RSIM_FP32_PHASE64, RSIM_FP64, RSIM_MASK_COMPUTE, RSIM_MASK_INPUT
+from .rsim import (Context, POINT_DTYPE, RSIM_FP32_PHASE64, RSIM_FP64, RSIM_MASK_COMPUTE,
+                   RSIM_MASK_INPUT)
 
 
 def pack_mask(mask: np.ndarray) -> np.ndarray:
@@ -68,6 +69,38 @@ class Simulator:
         y = torch.empty_like(echo) if want_y else None
         self.ctx.form_rdm(echo, rdm, y, n_cubes=n_cubes, precision=precision, **kw)
         return (rdm, y) if want_y else rdm
+
+    def detect(self, rdm, y, max_points: int = 256, guard=(1, 1), train=(2, 4),
+               scale: float = 10.0, na_x: int = 0, na_z: int = 0, want_maps: bool = False):
+        """CA-CFAR on the channel-integrated RDM and the angle FFT of each detected cell
+        (FP32 RDM and Y from form_rdm). Returns (points, counts[, det_mask, noise_map]):
+        points a device uint8 tensor [n_cubes, max_points, 64] of Point records
+        (points_numpy() decodes them), counts int32 [n_cubes]."""
+        n_cubes = rdm.shape[0]
+        pts = torch.zeros((n_cubes, max_points, 64), dtype=torch.uint8, device=self.dev)
+        cnt = torch.zeros((n_cubes,), dtype=torch.int32, device=self.dev)
+        det = noise = None
+        if want_maps:
+            det = torch.zeros((n_cubes, self.wf.n_chirps, self.wf.n_samples), dtype=torch.uint8,
+                              device=self.dev)
+            noise = torch.zeros((n_cubes, self.wf.n_chirps, self.wf.n_samples),
+                                dtype=torch.float32, device=self.dev)
+        self.ctx.detect(rdm, y, pts, cnt, n_cubes=n_cubes, det_mask=det, noise_map=noise,
+                        guard=guard, train=train, scale=scale, na_x=na_x, na_z=na_z)
+        return (pts, cnt, det, noise) if want_maps else (pts, cnt)
+
+    @staticmethod
+    def points_numpy(points, counts):
+        """Per cube, a structured numpy array of the written Point records."""
+        raw = points.cpu().numpy()
+        c = counts.cpu().numpy()
+        return [raw[i, :min(int(c[i]), raw.shape[1])].copy().view(POINT_DTYPE).reshape(-1)
+                for i in range(raw.shape[0])]
+
+    def add_noise(self, echo, snr_db: float, seed: int, precision=RSIM_FP32_PHASE64):
+        """White Gaussian noise at snr_db added in place to each cube of `echo`."""
+        self.ctx.add_noise(echo, snr_db, seed, n_cubes=echo.shape[0], precision=precision)
+        return echo
 
     def masks_numpy(self, mask_tensor, which: Optional[Sequence[int]] = None):
         """Split a device mask buffer into per-scene [N, F] bool arrays."""

@@ -33,7 +33,7 @@ EXPORTS = (
     "rsim_scene_info", "rsim_set_waveform", "rsim_set_array", "rsim_synthesize",
     "rsim_form_rdm", "rsim_last_timings", "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
-    "rsim_rdm_backward",
+    "rsim_rdm_backward", "rsim_detect", "rsim_add_noise",
 )
 
 
@@ -55,6 +55,28 @@ class Opts(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_f", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
+
+class CfarOpts(ctypes.Structure):
+    _fields_ = [("guard_doppler", ctypes.c_int32), ("guard_range", ctypes.c_int32),
+                ("train_doppler", ctypes.c_int32), ("train_range", ctypes.c_int32),
+                ("scale", ctypes.c_float), ("na_x", ctypes.c_int32), ("na_z", ctypes.c_int32),
+                ("max_points", ctypes.c_int32)]
+
+
+class Point(ctypes.Structure):
+    _fields_ = [("row", ctypes.c_int32), ("bin", ctypes.c_int32), ("power", ctypes.c_float),
+                ("noise", ctypes.c_float), ("range_m", ctypes.c_float),
+                ("velocity_mps", ctypes.c_float), ("u", ctypes.c_float), ("w", ctypes.c_float),
+                ("x", ctypes.c_float), ("y", ctypes.c_float), ("z", ctypes.c_float),
+                ("angle_power", ctypes.c_float), ("kx", ctypes.c_int32), ("kz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+# numpy view of an array of Point records (64 bytes each)
+POINT_DTYPE = np.dtype([("row", "<i4"), ("bin", "<i4"), ("power", "<f4"), ("noise", "<f4"),
+                        ("range_m", "<f4"), ("velocity_mps", "<f4"), ("u", "<f4"), ("w", "<f4"),
+                        ("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("angle_power", "<f4"),
+                        ("kx", "<i4"), ("kz", "<i4"), ("reserved", "<i4", (2,))])
 
 _lib = None
 
@@ -93,6 +115,8 @@ def lib() -> ctypes.CDLL:
         "rsim_update_mesh": ([vp, i32, vp, i64], i32),
         "rsim_set_instance_motion": ([vp, i32, i32, dp, dp], i32),
         "rsim_rdm_backward": ([vp, vp, vp, i32, vp, vp], i32),
+        "rsim_detect": ([vp, vp, vp, i32, ctypes.POINTER(CfarOpts), vp, vp, vp, vp, vp], i32),
+        "rsim_add_noise": ([vp, vp, i32, ctypes.c_double, u64, vp, ctypes.POINTER(Opts)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -267,6 +291,24 @@ class Context:
         arr = (ctypes.c_void_p * max(1, len(grad_verts)))(*[_ptr(g) for g in grad_verts])
         self._check(self._L.rsim_backward(self._h, int(scene), _ptr(grad_echo), _ptr(mask), arr,
                                           len(grad_verts), _ptr(grad_vel), _stream(stream)))
+
+    def detect(self, rdm, y, points, n_points, n_cubes: int = 1, det_mask=None, noise_map=None,
+               guard=(1, 1), train=(2, 4), scale: float = 10.0, na_x: int = 0, na_z: int = 0,
+               stream=None):
+        """CA-CFAR + angle FFT into `points` (uint8 device tensor of n_cubes x max_points
+        x 64 bytes) and `n_points` (int32 device tensor [n_cubes])."""
+        max_points = points.numel() // (64 * int(n_cubes))
+        o = CfarOpts(int(guard[0]), int(guard[1]), int(train[0]), int(train[1]), float(scale),
+                     int(na_x), int(na_z), int(max_points))
+        self._check(self._L.rsim_detect(self._h, _ptr(rdm), _ptr(y), int(n_cubes), ctypes.byref(o),
+                                        _ptr(det_mask), _ptr(noise_map), _ptr(points),
+                                        _ptr(n_points), _stream(stream)))
+
+    def add_noise(self, echo, snr_db: float, seed: int, n_cubes: int = 1, stream=None, **kw):
+        o = self.opts(**kw)
+        self._check(self._L.rsim_add_noise(self._h, _ptr(echo), int(n_cubes), float(snr_db),
+                                           int(seed) & 0xFFFFFFFFFFFFFFFF, _stream(stream),
+                                           ctypes.byref(o)))
 
     def last_timings(self) -> dict:
         buf = (ctypes.c_float * N_STAGES)()

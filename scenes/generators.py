@@ -490,3 +490,24 @@ def plate_scene(a, b, n_a, n_b, distance, tilt_rad=0.0, centre=RADAR_POS) -> Sce
     pos0 = np.asarray(centre, np.float64) + np.array([0.0, distance, 0.0])
     inst = Instance(mesh=0, rot=rot, pos0=pos0, vel=np.zeros(3))
     return Scene(meshes=[mesh], instances=[inst])
+
+
+# ----------------------------------------------------------------------------------
+# synthetic range-Doppler cubes for the detection stage
+# ----------------------------------------------------------------------------------
+
+def synthetic_y_cube(arr: RadarArray, wf: Waveform, seed: int, targets, noise_sigma: float = 1.0):
+    """Seeded complex cube Y[O, N, M] standing in for the Doppler-FFT output: circular
+    complex Gaussian noise of standard deviation noise_sigma per element plus, for each
+    target (row, bin, amplitude, u, w), a plane wave over the virtual array at that cell,
+    amplitude * exp(-j 2 pi (u x + w z) / lambda_c) with (x, z) the virtual element
+    positions tx_p + rx_q. Returns complex64."""
+    rng = np.random.default_rng(seed)
+    O = arr.n_channels
+    N, M = wf.n_chirps, wf.n_samples
+    Y = (rng.normal(size=(O, N, M)) + 1j * rng.normal(size=(O, N, M))) * (noise_sigma / np.sqrt(2.0))
+    lam = _band_centre_wavelength(wf)
+    v = (arr.tx[:, None, :] + arr.rx[None, :, :]).reshape(-1, 3)
+    for row, col, amp, u, w in targets:
+        Y[:, row, col] += amp * np.exp(-2j * np.pi * (u * v[:, 0] + w * v[:, 2]) / lam)
+    return Y.astype(np.complex64)

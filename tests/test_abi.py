@@ -121,3 +121,38 @@ def test_bvh_build_on_large_mesh_host_only():
     v = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32)
     ctx.load_mesh(v, np.array([[0, 1, 2]], np.int32))
     ctx.close()
+
+
+def test_detect_and_noise_validation_host_only():
+    """Argument checks of rsim_detect / rsim_add_noise before any device work."""
+    assert ctypes.sizeof(rsim.Point) == 64 and ctypes.sizeof(rsim.CfarOpts) == 32
+    assert rsim.POINT_DTYPE.itemsize == 64
+    ctx = _host_ctx()
+    L = ctx._L
+    wf = scenes.paper_waveform(64, 16)
+    arr = scenes.sparse_mimo_12x16(wf, 2)
+    ctx.set_waveform(wf)
+    ctx.set_array(arr.tx, arr.rx)
+    dummy = ctypes.c_void_p(1)
+    o = rsim.CfarOpts(1, 1, 2, 4, 10.0, 0, 0, 16)
+
+    def det(opts):
+        return L.rsim_detect(ctx._h, dummy, dummy, 1, ctypes.byref(opts), None, None, dummy,
+                             dummy, None)
+
+    assert det(rsim.CfarOpts(1, 1, 0, 0, 10.0, 0, 0, 16)) == rsim.RSIM_EINVAL  # no training
+    assert det(rsim.CfarOpts(1, 1, 2, 4, 0.0, 0, 0, 16)) == rsim.RSIM_EINVAL  # scale
+    assert det(rsim.CfarOpts(1, 1, 2, 4, 10.0, 0, 0, 0)) == rsim.RSIM_EINVAL  # max_points
+    assert det(rsim.CfarOpts(4, 1, 6, 4, 10.0, 0, 0, 16)) == rsim.RSIM_ERANGE  # 21 rows > N=16
+    assert det(rsim.CfarOpts(1, 1, 2, 4, 10.0, 100, 0, 16)) == rsim.RSIM_ERANGE  # 100 = 4 * 25
+    assert det(o) == rsim.RSIM_EDEVICE
+    # an array off the half-wavelength grid
+    ctx.set_array(arr.tx + np.array([0.3e-3, 0.0, 0.0]) * np.arange(12)[:, None], arr.rx)
+    assert det(o) == rsim.RSIM_ERANGE
+    assert b"grid" in L.rsim_last_error(ctx._h)
+    ctx.set_array(arr.tx, arr.rx)
+    assert L.rsim_add_noise(ctx._h, None, 1, 10.0, 1, None, None) == rsim.RSIM_EINVAL
+    assert L.rsim_add_noise(ctx._h, dummy, 1, float("nan"), 1, None, None) == rsim.RSIM_EINVAL
+    assert L.rsim_add_noise(ctx._h, dummy, 1, 10.0, 1, None, None) == rsim.RSIM_EDEVICE
+    ctx.close()
+

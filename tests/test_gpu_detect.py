@@ -1,0 +1,183 @@
+"""GPU parity of the detection stage (CA-CFAR, angle FFT, point cloud; Section 3.3 and
+eq. (6)) and of the white Gaussian noise (Section 3.2), through the C ABI, against the
+FP64 oracle on the same seeded inputs. Detection decisions are compared wherever the
+oracle's decision is clear of the threshold (|P / (scale * noise) - 1| > 1e-4, and for
+the angle peak a runner-up more than 1e-4 below the maximum); there both sides must
+agree exactly, elsewhere either answer is correct."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import detect, noise
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-4
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    import torch  # noqa: F401
+    from paper_2208_10939_amd import pipeline
+    return pipeline
+
+
+def _oracle_points(P, Y, wf, arr, guard, train, scale, na_x=0, na_z=0):
+    """Oracle detections plus the ambiguity flags of each decision."""
+    Pi = detect.integrate(P)
+    det, nmap, _ = detect.ca_cfar(Pi, guard, train, scale)
+    ratio = Pi / (scale * nmap)
+    amb_det = np.abs(ratio - 1.0) <= MARGIN
+    pts = detect.point_cloud(P, Y, wf, arr, guard, train, scale, na_x, na_z)
+    ix, iz, nx, nz, _ = detect.virtual_grid(arr, wf)
+    na_x = na_x or detect._fft_len(2 * nx)
+    na_z = na_z or (1 if nz == 1 else detect._fft_len(2 * nz))
+    for p in pts:
+        A = detect.angle_spectrum(Y[:, p["row"], p["bin"]], ix, iz, na_x, na_z).ravel()
+        top2 = np.sort(A)[-2:]
+        p["amb_angle"] = top2[1] - top2[0] <= MARGIN * top2[1]
+    return det, nmap, amb_det, pts
+
+
+def _compare(gpu_pts, gcount, det_g, noise_g, det_o, noise_o, amb_det, opts, max_points,
+             tol=1e-5):
+    """tol: relative tolerance on powers and noise levels (1e-5 when both sides read the
+    same map; the RDM's 2e-4 when each side forms its own)."""
+    clear = ~amb_det
+    assert np.array_equal(det_g[clear], det_o[clear]), \
+        f"{int((det_g[clear] != det_o[clear]).sum())} clear CFAR decisions differ"
+    nz = noise_o > 0
+    rel = np.max(np.abs(noise_g[nz] - noise_o[nz]) / noise_o[nz])
+    assert rel <= tol, rel
+    assert gcount == int(det_g.sum())
+    # the listed points are the first max_points GPU detections in row-major order
+    cells = np.flatnonzero(det_g.ravel())[:max_points]
+    assert np.array_equal(gpu_pts["row"] * det_g.shape[1] + gpu_pts["bin"], cells)
+    by_cell = {(p["row"], p["bin"]): p for p in opts}
+    checked = 0
+    for g in gpu_pts:
+        p = by_cell.get((int(g["row"]), int(g["bin"])))
+        if p is None:
+            continue  # an ambiguous detection the oracle did not take
+        assert g["power"] == pytest.approx(p["power"], rel=tol)
+        assert g["noise"] == pytest.approx(p["noise"], rel=tol)
+        assert g["range_m"] == pytest.approx(p["range"], rel=1e-6, abs=1e-6)
+        assert g["velocity_mps"] == pytest.approx(p["velocity"], rel=1e-6, abs=1e-6)
+        if p["amb_angle"]:
+            continue
+        assert (int(g["kx"]), int(g["kz"])) == (p["kx"], p["kz"])
+        assert g["u"] == pytest.approx(p["u"], abs=1e-7)
+        assert g["w"] == pytest.approx(p["w"], abs=1e-7)
+        assert np.allclose([g["x"], g["y"], g["z"]], p["xyz"], rtol=0, atol=1e-4)
+        checked += 1
+    return checked
+
+
+@pytest.mark.parametrize("array,scale,max_points", [("mimo", 8.0, 64), ("ula", 8.0, 64),
+                                                     ("ula", 2.5, 8)])
+def test_cfar_and_angle_on_synthetic_cubes(sim_mod, array, scale, max_points):
+    """Seeded Y cubes (noise + plane waves planted at known cells and directions) for
+    the 12x16 sparse MIMO array and the 1Tx4Rx line array; P = |Y|^2 in FP32 feeds both
+    sides. Two cubes per call (the second with other targets), ragged map tiles; the low
+    threshold on the 4-channel array gives many noise detections, more than max_points."""
+    import torch
+    wf = scenes.paper_waveform(96, 40)
+    arr = scenes.sparse_mimo_12x16(wf, 2) if array == "mimo" else scenes.ula_1tx4rx(wf)
+    targets = [[(3, 10, 6.0, 0.2, -0.3), (20, 50, 5.0, -0.45, 0.1), (39, 95, 8.0, 0.0, 0.0),
+                (21, 51, 6.0, 0.6, 0.3)],
+               [(0, 0, 5.0, -0.1, 0.2), (25, 70, 10.0, 0.33, -0.5)]]
+    Ys = [scenes.synthetic_y_cube(arr, wf, 40 + k, t) for k, t in enumerate(targets)]
+    Y = np.stack(Ys)
+    P = (np.abs(Y.astype(np.complex128)) ** 2).astype(np.float32)
+    guard, train = (1, 2), (2, 4)
+    sim = sim_mod.Simulator([scenes.point_scene([20.0], [1.0])], wf, arr)
+    pts, cnt, det, nmap = sim.detect(torch.from_numpy(P).cuda(), torch.from_numpy(Y).cuda(),
+                                     max_points=max_points, guard=guard, train=train, scale=scale,
+                                     want_maps=True)
+    gp = sim.points_numpy(pts, cnt)
+    det = det.cpu().numpy().astype(bool)
+    nmap = nmap.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    for k in range(2):
+        det_o, noise_o, amb, opts = _oracle_points(P[k].astype(np.float64),
+                                                   Y[k].astype(np.complex128), wf, arr, guard,
+                                                   train, scale)
+        n = _compare(gp[k], int(cnt[k]), det[k], nmap[k], det_o, noise_o, amb, opts, max_points)
+        _log(f"  {array} cube {k}: detections gpu={int(cnt[k])} oracle={int(det_o.sum())} "
+             f"ambiguous={int(amb.sum())} angle-checked={n}")
+        for row, col, amp, u, w in targets[k]:
+            assert det[k][row, col], f"planted target {(row, col)} not detected"
+        assert n >= 1
+
+
+def test_detection_end_to_end_point_scatterers(sim_mod):
+    """Point scatterers plus white noise at 0 dB per sample (the same seeded noise on
+    both sides) through the whole GPU chain (echo, noise, RDM, detection) and through the
+    oracle's chain: detections and points agree, and the strongest point near each
+    scatterer sits within one range, Doppler and angle cell of it."""
+    wf = scenes.paper_waveform(128, 32)
+    arr = scenes.sparse_mimo_12x16(wf, seed=2)
+    pos = np.array([[4.0, 20.0, -6.0], [-8.0, 35.0, 2.0]])
+    vel = np.array([[0.0, 2.0, 0.0], [1.0, -4.0, 0.0]])
+    sc = scenes.Scene(meshes=[], instances=[],
+                      points=scenes.Points(pos0=pos, vel=vel, amp=np.array([1.0 + 0j, 0.7j])))
+    sim = sim_mod.Simulator([sc], wf, arr)
+    H = sim.synthesize()
+    sim.add_noise(H, 0.0, seed=77)
+    rdm, Y = sim.form_rdm(H, want_y=True)
+    guard, train, scale = (2, 2), (3, 6), 20.0
+    pts, cnt, det, nmap = sim.detect(rdm, Y, max_points=128, guard=guard, train=train,
+                                     scale=scale, want_maps=True)
+    gp = sim.points_numpy(pts, cnt)[0]
+    Ho = noise.add_awgn(oracle.synthesize(sc, wf, arr), 0.0, seed=77)
+    Po, Yo = oracle.rdm_from_echo(Ho)
+    det_o, noise_o, amb, opts = _oracle_points(Po, Yo, wf, arr, guard, train, scale)
+    # each side forms its own RDM (bar 2e-4): widen the clear-decision margin to match
+    Pi = detect.integrate(Po)
+    amb |= np.abs(Pi / (scale * noise_o) - 1.0) <= 1e-3
+    n = _compare(gp, int(cnt.cpu().numpy()[0]), det.cpu().numpy()[0].astype(bool),
+                 nmap.cpu().numpy()[0], det_o, noise_o, amb, opts, 128, tol=2e-4)
+    _log(f"  detections gpu={int(cnt.cpu().numpy()[0])} oracle={int(det_o.sum())} "
+         f"angle-checked={n}")
+    c_ref = 0.5 * (arr.tx.mean(0) + arr.rx.mean(0))
+    d = oracle.derived(wf)
+    for k in range(2):
+        r = np.linalg.norm(pos[k] - c_ref)
+        near = [g for g in gp if abs(g["range_m"] - r) <= d["range_resolution"]]
+        assert near, f"scatterer {k} not detected"
+        best = max(near, key=lambda g: g["power"])
+        dv = (pos[k] - c_ref) / r
+        assert abs(best["velocity_mps"] - vel[k] @ dv) <= d["velocity_resolution"]
+        assert abs(best["u"] - dv[0]) <= 0.02
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_awgn_matches_oracle(sim_mod, precision):
+    """Philox4x32-10 + Box-Muller noise at 5 dB SNR on two seeded cubes, elementwise
+    against the oracle; the same seed gives the same noise."""
+    import torch
+    wf = scenes.paper_waveform(64, 8)
+    arr = scenes.sparse_mimo_12x16(wf, 1)
+    sim = sim_mod.Simulator([scenes.point_scene([20.0], [1.0])], wf, arr)
+    rng = np.random.default_rng(21)
+    H = rng.normal(size=(2, sim.O, 8, 64)) + 1j * rng.normal(size=(2, sim.O, 8, 64))
+    dt = torch.complex128 if precision else torch.complex64
+    Hin = H if precision else H.astype(np.complex64).astype(np.complex128)
+    Ho = noise.add_awgn(Hin, 5.0, seed=0x1234_5678_9ABC)
+    Ht = torch.from_numpy(Hin).to(dt).cuda()
+    sim.add_noise(Ht, 5.0, 0x1234_5678_9ABC, precision=precision)
+    Hg = Ht.cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(Hg - Ho)) / np.sqrt(np.mean(np.abs(Ho - Hin) ** 2))
+    _log(f"  precision={precision} max |gpu - oracle| / noise rms = {err:.3e}")
+    assert err <= (1e-12 if precision else 2e-6)
+    Ht2 = torch.from_numpy(Hin).to(dt).cuda()
+    sim.add_noise(Ht2, 5.0, 0x1234_5678_9ABC, precision=precision)
+    assert torch.equal(Ht, Ht2)
