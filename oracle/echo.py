@@ -18,6 +18,10 @@ Readings where the paper is silent or garbled:
     and Rx elements. For a flat plate at normal incidence |a|^2 equals eq. (7)
     with sigma = 4 pi A^2 / lambda^2 (the lambda factors cancel since lambda k = 2 pi).
   * Stop-and-hop: the geometry of chirp n is frozen at t_n = n T_c (eq. (12) per chirp).
+    Optionally (intra_chirp=True) the propagation delay of eqs. (12)-(13) is taken at
+    each sample time t_n + m / fs: the facet centroid (or point) moves with its velocity
+    within the chirp; the amplitude, the facet integral and the lit set stay at t_n
+    (eq. (13) holds P sigma constant while tau(t) varies).
   * The response carries exp(-j 2 pi (f_m tau - mu tau^2 / 2)), tau = (R_t + R_r)/c,
     so that conj(H) at sample m equals eq. (13) for a point target (beat = conj(H)).
   * Point scatterers: amplitude s / (4 pi R_t R_r) with a constant complex s (m^2)
@@ -42,9 +46,18 @@ def _phase_turns(freqs, tau, slope):
     return ph - np.floor(ph)
 
 
-def facet_terms(tri: np.ndarray, wf, array, freqs: np.ndarray, channels):
+def _moving_distances(elems, c, vel, dt):
+    """|e - (c_f + v_f dt_m)| for elements [E,3], centroids [F,3], velocities [F,3] and
+    sample times dt [M_sel]: returns [F, E, M_sel]."""
+    pos = c[:, None, :] + vel[:, None, :] * dt[None, :, None]  # [F, M, 3]
+    return np.linalg.norm(elems[None, :, None, :] - pos[:, None, :, :], axis=3)
+
+
+def facet_terms(tri: np.ndarray, wf, array, freqs: np.ndarray, channels, vel=None, dt=None):
     """Sum over the given world triangles [F,3,3] of the facet terms for the
-    selected channels (list of (p, q)) and frequencies: returns [len(channels), M_sel]."""
+    selected channels (list of (p, q)) and frequencies: returns [len(channels), M_sel].
+    With vel [F,3] and dt [M_sel] (seconds after t_n) the delay is taken at the sample
+    times; amplitude and facet integral stay at t_n."""
     tx = np.asarray(array.tx, np.float64)
     rx = np.asarray(array.rx, np.float64)
     tx_c, rx_c = tx.mean(axis=0), rx.mean(axis=0)
@@ -63,16 +76,25 @@ def facet_terms(tri: np.ndarray, wf, array, freqs: np.ndarray, channels):
     integ = facet_integral(k[None, :], beta[:, None, :], area[:, None])  # [F, M]
     rt = np.linalg.norm(tx[None, :, :] - c[:, None, :], axis=2)  # [F, P]
     rr = np.linalg.norm(rx[None, :, :] - c[:, None, :], axis=2)  # [F, Q]
+    if vel is not None:
+        rt_m = _moving_distances(tx, c, vel, dt)  # [F, P, M]
+        rr_m = _moving_distances(rx, c, vel, dt)
     for ci, (p, q) in enumerate(channels):
-        tau = (rt[:, p] + rr[:, q]) / C0
         amp = 1j * obl / (4.0 * np.pi * rt[:, p] * rr[:, q])
-        ph = _phase_turns(freqs, tau, wf.slope)
+        if vel is None:
+            ph = _phase_turns(freqs, (rt[:, p] + rr[:, q]) / C0, wf.slope)
+        else:
+            tau = (rt_m[:, p, :] + rr_m[:, q, :]) / C0  # [F, M]
+            ph = freqs[None, :] * tau - 0.5 * wf.slope * tau * tau
+            ph -= np.floor(ph)
         out[ci] = np.sum(amp[:, None] * integ * np.exp(-2j * np.pi * ph), axis=0)
     return out
 
 
-def point_terms(pos: np.ndarray, amp: np.ndarray, wf, array, freqs, channels):
-    """Sum of point-scatterer terms s / (4 pi R_t R_r) exp(-j 2 pi (f tau - mu tau^2/2))."""
+def point_terms(pos: np.ndarray, amp: np.ndarray, wf, array, freqs, channels, vel=None,
+                dt=None):
+    """Sum of point-scatterer terms s / (4 pi R_t R_r) exp(-j 2 pi (f tau - mu tau^2/2));
+    with vel and dt the delay is taken at the sample times (amplitude at t_n)."""
     tx = np.asarray(array.tx, np.float64)
     rx = np.asarray(array.rx, np.float64)
     out = np.zeros((len(channels), freqs.size), np.complex128)
@@ -80,22 +102,30 @@ def point_terms(pos: np.ndarray, amp: np.ndarray, wf, array, freqs, channels):
         return out
     rt = np.linalg.norm(tx[None, :, :] - pos[:, None, :], axis=2)
     rr = np.linalg.norm(rx[None, :, :] - pos[:, None, :], axis=2)
+    if vel is not None:
+        rt_m = _moving_distances(tx, pos, vel, dt)
+        rr_m = _moving_distances(rx, pos, vel, dt)
     for ci, (p, q) in enumerate(channels):
-        tau = (rt[:, p] + rr[:, q]) / C0
         a = amp / (4.0 * np.pi * rt[:, p] * rr[:, q])
-        ph = _phase_turns(freqs, tau, wf.slope)
+        if vel is None:
+            ph = _phase_turns(freqs, (rt[:, p] + rr[:, q]) / C0, wf.slope)
+        else:
+            tau = (rt_m[:, p, :] + rr_m[:, q, :]) / C0
+            ph = freqs[None, :] * tau - 0.5 * wf.slope * tau * tau
+            ph -= np.floor(ph)
         out[ci] = np.sum(a[:, None] * np.exp(-2j * np.pi * ph), axis=0)
     return out
 
 
 def synthesize(scene, wf, array, mask=None, chirps=None, channels=None, samples=None,
-               chunk: int = 2048, return_mask: bool = False):
+               chunk: int = 2048, return_mask: bool = False, intra_chirp: bool = False):
     """Echo frequency response H[o, n, m] (complex128) of a scene.
 
     mask: optional lit-facet mask [n_chirps_total, F] (bool) to use instead of the
     brute-force visibility; chirps / channels / samples: optional index subsets
     (channels as flat indices o = p Q + q). Returns H[len(channels), len(chirps),
-    len(samples)] (and the per-chirp masks used when return_mask)."""
+    len(samples)] (and the per-chirp masks used when return_mask). intra_chirp: delay at
+    each sample time t_n + m / fs instead of t_n."""
     P, Q = array.tx.shape[0], array.rx.shape[0]
     chirps = np.arange(wf.n_chirps) if chirps is None else np.asarray(chirps)
     channels = np.arange(P * Q) if channels is None else np.asarray(channels)
@@ -105,9 +135,12 @@ def synthesize(scene, wf, array, mask=None, chirps=None, channels=None, samples=
     freqs = wf.f0 + df * samples.astype(np.float64)
     H = np.zeros((channels.size, chirps.size, samples.size), np.complex128)
     used = []
+    dt = samples.astype(np.float64) / wf.fs if intra_chirp else None
     for ni, n in enumerate(chirps):
         t = float(n) * wf.chirp_period
-        tri, _, _ = world_triangles(scene, t)
+        tri, inst_of, _ = world_triangles(scene, t)
+        fvel = (np.array([scene.instances[i].vel for i in inst_of], np.float64).reshape(-1, 3)
+                if intra_chirp else None)
         if mask is None:
             lit, _ = visibility(scene, array, wf, chirps=[n])
             lit = lit[0]
@@ -116,10 +149,13 @@ def synthesize(scene, wf, array, mask=None, chirps=None, channels=None, samples=
         used.append(lit)
         idx = np.nonzero(lit)[0]
         for s0 in range(0, idx.size, chunk):
-            H[:, ni, :] += facet_terms(tri[idx[s0:s0 + chunk]], wf, array, freqs, pq)
+            sel = idx[s0:s0 + chunk]
+            H[:, ni, :] += facet_terms(tri[sel], wf, array, freqs, pq,
+                                       vel=None if fvel is None else fvel[sel], dt=dt)
         if scene.points is not None and scene.points.n:
             H[:, ni, :] += point_terms(point_positions(scene, t), scene.points.amp, wf,
-                                       array, freqs, pq)
+                                       array, freqs, pq,
+                                       vel=scene.points.vel if intra_chirp else None, dt=dt)
     if return_mask:
         return H, np.array(used)
     return H

@@ -179,3 +179,45 @@ def test_zero_area_triangle_is_inert():
     H1, mask = oracle.synthesize(Scene([Mesh(verts, tris)], [inst]), wf, arr, return_mask=True)
     assert not mask[:, -1].any()
     assert np.max(np.abs(H1 - H0)) == 0.0
+
+
+def test_intra_chirp_delay_equals_eq12_eq13():
+    """Delay at each sample time: a point moving radially away from a monostatic element
+    has tau(t) = 2 (R0 + v t) / c (eq. (12)) with t = t_n + m / fs, and the beat sample
+    conj(H) is eq. (13) with that tau; the amplitude stays at the chirp start."""
+    wf = scenes.paper_waveform(64, 3)
+    e = scenes.RADAR_POS.astype(np.float64)
+    arr = RadarArray(tx=e[None].copy(), rx=e[None].copy())
+    u = np.array([0.3, 0.9, -0.2])
+    u /= np.linalg.norm(u)
+    R0, v = 23.0, 14.0
+    sc = Scene(meshes=[], instances=[],
+               points=scenes.Points(pos0=(e + R0 * u)[None], vel=(v * u)[None],
+                                    amp=np.array([2.0 + 1.0j])))
+    H = oracle.synthesize(sc, wf, arr, intra_chirp=True)[0]
+    c = 299792458.0
+    m = np.arange(wf.n_samples)
+    fm = wf.f0 + m * wf.slope / wf.fs
+    for n in range(wf.n_chirps):
+        tn = n * wf.chirp_period
+        tau = 2.0 * (R0 + v * (tn + m / wf.fs)) / c
+        Rn = R0 + v * tn
+        expect = (2.0 + 1.0j) / (4 * np.pi * Rn * Rn) * np.exp(
+            -2j * np.pi * (fm * tau - 0.5 * wf.slope * tau * tau))
+        assert np.max(np.abs(H[n] - expect)) <= 1e-9 * np.max(np.abs(expect))
+    # and it differs from stop-and-hop by the Doppler phase accrued within the chirp
+    Hs = oracle.synthesize(sc, wf, arr)[0]
+    drift = np.angle(H[0, -1] / Hs[0, -1])
+    expect_drift = -2 * np.pi * fm[-1] * 2 * v * ((wf.n_samples - 1) / wf.fs) / c
+    assert np.angle(np.exp(1j * (drift - expect_drift))) == pytest.approx(0.0, abs=1e-3)
+
+
+def test_intra_chirp_static_scene_equals_stop_and_hop():
+    """Without motion the intra-chirp delay changes nothing."""
+    cfg = scenes.small_single(n_tris=300, n_samples=32, n_chirps=2)
+    sc = cfg.scenes[0]
+    still = Scene(meshes=sc.meshes, instances=[Instance(i.mesh, i.rot, i.pos0, 0.0 * i.vel)
+                                               for i in sc.instances])
+    a = oracle.synthesize(still, cfg.waveform, cfg.array, channels=[0, 77, 191])
+    b = oracle.synthesize(still, cfg.waveform, cfg.array, channels=[0, 77, 191], intra_chirp=True)
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
