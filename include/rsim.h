@@ -73,7 +73,10 @@ typedef struct {
   int32_t tile_f;    /* facets staged per LDS tile (0 = default). Compiled (tile_m,      */
                      /* tile_f): FP32 16x16 32x8 32x16 64x8 64x16, FP64 8x8 16x8; others  */
                      /* fail with RSIM_EINVAL                                            */
-  int32_t reserved;
+  int32_t intra_chirp; /* 0: stop-and-hop, geometry and delay frozen at t_n (default).   */
+                     /* 1: the propagation delay of eq. (12) taken at each sample time  */
+                     /* t_n + m / fs (range-Doppler coupling within a chirp); amplitude, */
+                     /* facet integral and lit set stay at t_n. FP32 sum only.          */
 } rsim_opts;
 
 /* ---- context ---------------------------------------------------------------------- */

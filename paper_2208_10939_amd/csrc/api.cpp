@@ -595,7 +595,8 @@ int32_t prepare_batch(rsim_ctx *ctx, BatchTables &bt, const std::vector<int32_t>
 // Enqueue visibility + compaction + facet sum (kernels only; capturable).
 int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const BatchTables *bt,
                           hipStream_t s, const rsim_opts &o, bool timing) {
-  const RadarConst rc = radar_const(ctx);
+  RadarConst rc = radar_const(ctx);
+  rc.intra = o.intra_chirp ? 1 : 0;
   const int precision = o.precision;
   const TunedShape ts = pick_shape(ctx, precision, o);
   const EchoShape sh = forward_shape(ctx, rc, precision, ts.mb, ts.ft);
@@ -884,6 +885,11 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: unknown mask mode %d", o.mask_mode);
   if (o.mask_mode == RSIM_MASK_INPUT && !vis_mask)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: RSIM_MASK_INPUT needs vis_mask");
+  if (o.intra_chirp != 0 && o.intra_chirp != 1)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: intra_chirp must be 0 or 1");
+  if (o.intra_chirp && o.precision == RSIM_FP64)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the intra-chirp delay is implemented in the "
+                "FP32 sum only");
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   std::vector<int32_t> ids(scene_ids, scene_ids + n_scenes);

@@ -94,7 +94,7 @@ struct EchoLayout {
     U = t;
     t += sizeof(C) * FT * sh.E * sh.B_w;
     rat = t;
-    t += sizeof(C) * FT * sh.E;
+    t += sizeof(C) * FT * sh.E * sh.B_w;
     off = t;
     t = up(t + sizeof(R) * FT * sh.E);
     buf[0] = b;
@@ -111,7 +111,7 @@ struct EchoTile {
   C *G;    // [FT][M_t]
   C *G1;   // [FT][M_t]: G (-j)^(m mod 4), for quarter-turn-rotated recurrences (FP32)
   C *U;    // [FT][E][B_w]
-  C *rat;  // [FT][E]
+  C *rat;  // [FT][E][B_w]: per-sample phasor step of each block
   R *off;  // [FT][E]
 };
 
@@ -146,6 +146,41 @@ struct EchoSmem {
   }
 };
 
+// Delay of element `el` from the facet centroid moved to sample time t_n + m / fs.
+__device__ inline double moving_delay(const Geo &g, const double *el, double t) {
+  const double dx = el[0] - (g.c[0] + g.vel[0] * t);
+  const double dy = el[1] - (g.c[1] + g.vel[1] * t);
+  const double dz = el[2] - (g.c[2] + g.vel[2] * t);
+  return sqrt(dx * dx + dy * dy + dz * dz) * (1.0 / kC0);
+}
+
+// Element part of the phase (turns, unreduced) at sample m with the delay taken at the
+// sample time: f_m tau - slope tau^2 / 2 - slope tau_ref,other (tau - tau_ref,self)
+// - slope tau_ref,t tau_ref,r / 2, the same split as the stop-and-hop phases.
+__device__ inline double element_phase(const Geo &g, const RadarConst &rc, const double *el,
+                                       bool tx, int m) {
+  const double tau = moving_delay(g, el, m / rc.fs);
+  const double fm = rc.f0 + m * rc.df;
+  const double d = tau - (tx ? g.tref_t : g.tref_r);
+  return fm * tau - 0.5 * rc.slope * tau * tau - rc.slope * (tx ? g.tref_r : g.tref_t) * d -
+         0.5 * rc.slope * g.tref_t * g.tref_r;
+}
+
+// Quadratic coefficient (turns per sample^2) of the phase-centre path's phase
+// f_m tau - slope tau^2 / 2 with the delay at the sample time, from a second difference
+// over one block: the phase leaves the chord of a block by q j (j - MB).
+__device__ inline double chord_curvature(const Geo &g, const RadarConst &rc, int m0, int mb) {
+  const int h = mb / 2;
+  double ph[3];
+  for (int k = 0; k < 3; ++k) {
+    const int m = m0 + k * h;
+    const double t = m / rc.fs;
+    const double tau = moving_delay(g, rc.tx_c, t) + moving_delay(g, rc.rx_c, t);
+    ph[k] = (rc.f0 + m * rc.df) * tau - 0.5 * rc.slope * tau * tau;
+  }
+  return (ph[2] - 2.0 * ph[1] + ph[0]) / (2.0 * h * h);
+}
+
 // Orders a wave's own LDS writes before its later LDS reads by other lanes.
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -171,7 +206,10 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
       entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
     else
       geo[i].valid = 0;
-    if constexpr (EchoLayout<R, MB, FT>::kRotated) make_glin(geo[i], rc, m_tile0, glin[i]);
+    if constexpr (EchoLayout<R, MB, FT>::kRotated) {
+      make_glin(geo[i], rc, m_tile0, glin[i]);
+      if (rc.intra && geo[i].valid) glin[i].quad = static_cast<float>(chord_curvature(geo[i], rc, m_tile0, MB));
+    }
   }
   wave_lds_sync();
   // B1: per element distance, phases in FP64 reduced to turns
@@ -179,9 +217,12 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
     const int i = task / E, e = task % E;
     const Geo &g = geo[i];
     C *Ue = tl.U + (i * E + e) * sh.B_w;
+    C *re = tl.rat + (i * E + e) * sh.B_w;
     if (!g.valid) {
-      for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = {R(0), R(0)};
-      tl.rat[i * E + e] = {R(1), R(0)};
+      for (int bb = 0; bb < sh.B_w; ++bb) {
+        Ue[bb] = {R(0), R(0)};
+        re[bb] = {R(1), R(0)};
+      }
       tl.off[i * E + e] = R(0);
       continue;
     }
@@ -210,11 +251,24 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
       inv_r = __builtin_amdgcn_rcpf(static_cast<float>(Rn));  // amplitude only: 1 ulp
     else
       inv_r = 1.0 / Rn;
-    for (int bb = 0; bb < sh.B_w; ++bb) {
-      const double m0 = static_cast<double>(m_tile0 + bb * MB);
-      Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
+    if (!rc.intra) {
+      const C step = phasor_m2pi<R>(delta, R(1));
+      for (int bb = 0; bb < sh.B_w; ++bb) {
+        const double m0 = static_cast<double>(m_tile0 + bb * MB);
+        Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
+        re[bb] = step;
+      }
+    } else {
+      // delay at each sample time t_n + m / fs: exact FP64 phases at both ends of each
+      // block; the block runs along their chord (the curvature goes into G)
+      for (int bb = 0; bb < sh.B_w; ++bb) {
+        const int ma = m_tile0 + bb * MB;
+        const double pa = element_phase(g, rc, sm.elem + 3 * e, e < P, ma);
+        const double pb = element_phase(g, rc, sm.elem + 3 * e, e < P, ma + MB);
+        Ue[bb] = phasor_m2pi<R>(pa - floor(pa), inv_r);
+        re[bb] = phasor_m2pi<R>((pb - pa) * (1.0 / MB), R(1));
+      }
     }
-    tl.rat[i * E + e] = phasor_m2pi<R>(delta, R(1));
     tl.off[i * E + e] = static_cast<R>(offv);
   }
   // B2: G_f(m) for the tile's samples
@@ -223,6 +277,13 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
     C val = {R(0), R(0)};
     if constexpr (EchoLayout<R, MB, FT>::kRotated) {
       val = g_lin(glin[i], j);
+      if (rc.intra) {
+        // deviation of the phase from its chord over the block: exp(-j 2 pi q jj (jj - MB))
+        // to first order (|2 pi q jj (jj - MB)| <= ~2e-4 rad)
+        const int jj = j % MB;
+        const float x = 6.283185307179586f * glin[i].quad * static_cast<float>(jj * (jj - MB));
+        val = {fma_r(val.y, x, val.x), fma_r(-val.x, x, val.y)};
+      }
     } else {
       const Geo &g = geo[i];
       if (g.valid) {
@@ -261,7 +322,7 @@ __device__ inline void sum_tile(const RadarConst &rc, const EchoShape &sh,
   const int iu_p = p * sh.B_w + b, iu_q = (P + q) * sh.B_w + b;
   const int stride_u = E * sh.B_w;
   C up = tl.U[iu_p], uq = tl.U[iu_q];
-  C rp = tl.rat[p], rq = tl.rat[P + q];
+  C rp = tl.rat[iu_p], rq = tl.rat[iu_q];
   R op = tl.off[p], oq = tl.off[P + q];
   for (int i = 0; i < nf; ++i) {
     const R eps = op * oq;
@@ -294,8 +355,8 @@ __device__ inline void sum_tile(const RadarConst &rc, const EchoShape &sh,
     if (i + 1 < nf) {
       up = tl.U[(i + 1) * stride_u + iu_p];
       uq = tl.U[(i + 1) * stride_u + iu_q];
-      rp = tl.rat[(i + 1) * E + p];
-      rq = tl.rat[(i + 1) * E + P + q];
+      rp = tl.rat[(i + 1) * stride_u + iu_p];
+      rq = tl.rat[(i + 1) * stride_u + iu_q];
       op = tl.off[(i + 1) * E + p];
       oq = tl.off[(i + 1) * E + P + q];
     }

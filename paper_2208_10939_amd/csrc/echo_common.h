@@ -35,6 +35,7 @@ struct alignas(8) Geo {
   double tref_t, tref_r;
   double beta[3];     // w . (x_i - c), metres
   double amp_re, amp_im;  // G = amp * Phi
+  double vel[3];      // world velocity of the facet or point
   int32_t valid, pad;
 };
 
@@ -149,6 +150,7 @@ struct alignas(16) GLin {
   float mp, mp_i;            // turns: s mean
   float ar, ai;              // G = (ar + j ai) Phi
   float k, k_i;              // rad per metre: 2 pi s (k_m of the wavenumber)
+  float quad;                // turns per sample^2 of the delay's motion within a chirp
   int32_t valid;
   int32_t nl, ni, nj;  // vertex index of node l, i, j
 };
@@ -208,6 +210,7 @@ __device__ inline void make_glin(const Geo &g, const RadarConst &rc, int m_tile0
   q.ai = static_cast<float>(g.amp_im);
   q.k = static_cast<float>(two_pi * s0);
   q.k_i = static_cast<float>(two_pi * ds);
+  q.quad = 0.0f;
 }
 
 // sin(x) / x for x = x0 + j x_i (rad), t = t0 + j t_i = x / (2 pi) (turns, centred at
@@ -285,6 +288,7 @@ __device__ void entry_geometry(const DevScene &sc, const RadarConst &rc, int n, 
     g.amp_im = obl * 0.5 * two_area / (2.0 * kPi);
     g.tref_t = rt * inv_c;
     g.tref_r = rr * inv_c;
+    for (int k = 0; k < 3; ++k) g.vel[k] = I.vel[k];
     g.valid = two_area > 0.0;
   } else {
     const int32_t k = item - cnt;
@@ -300,6 +304,7 @@ __device__ void entry_geometry(const DevScene &sc, const RadarConst &rc, int n, 
     // Phi(0,0,0) = 1/2, so G = s / (4 pi) with amp = s / (2 pi)
     g.amp_re = sc.pt_amp[2 * k + 0] / (2.0 * kPi);
     g.amp_im = sc.pt_amp[2 * k + 1] / (2.0 * kPi);
+    for (int d = 0; d < 3; ++d) g.vel[d] = sc.pt_vel[3 * k + d];
     g.valid = 1;
   }
   g.c[0] = c[0];

@@ -52,6 +52,8 @@ struct RadarConst {
   double f0, slope, fs, df, tc;  // df = slope / fs
   double tx_c[3], rx_c[3];       // phase centres (element means)
   int32_t M, N, P, Q;
+  int32_t intra;  // 1: propagation delay at each sample time within the chirp
+  int32_t pad;
 };
 
 // Per-scene device view used by the visibility, compaction and echo kernels.

@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("mask_mode", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("tile_m", ctypes.c_int32),
-                ("tile_f", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_f", ctypes.c_int32), ("intra_chirp", ctypes.c_int32)]
 
 
 class CfarOpts(ctypes.Structure):
@@ -264,9 +264,9 @@ class Context:
     # ---- echo / RDM --------------------------------------------------------------
     @staticmethod
     def opts(precision=RSIM_FP32_PHASE64, mask_mode=RSIM_MASK_COMPUTE, use_graph=False,
-             persistent=False, timing=False, tile_m=0, tile_f=0) -> Opts:
+             persistent=False, timing=False, tile_m=0, tile_f=0, intra_chirp=False) -> Opts:
         return Opts(int(precision), int(mask_mode), int(bool(use_graph)), int(bool(persistent)),
-                    int(bool(timing)), int(tile_m), int(tile_f), 0)
+                    int(bool(timing)), int(tile_m), int(tile_f), int(bool(intra_chirp)))
 
     def synthesize(self, scene_ids: Sequence[int], echo, mask=None, stream=None, **kw):
         ids = (ctypes.c_int32 * len(scene_ids))(*[int(s) for s in scene_ids])

@@ -92,6 +92,11 @@ def test_validation_codes_host_only():
     ctx.set_array(arr.tx, arr.rx)
     bad_ids = (ctypes.c_int32 * 1)(sid + 7)
     assert L.rsim_synthesize(ctx._h, bad_ids, 1, echo, None, None, ctypes.byref(o)) == rsim.RSIM_EINVAL
+    # the intra-chirp delay is an FP32-sum option; other values are refused
+    o_intra = rsim.Opts(precision=rsim.RSIM_FP64, intra_chirp=1)
+    assert L.rsim_synthesize(ctx._h, ids, 1, echo, None, None, ctypes.byref(o_intra)) == rsim.RSIM_EINVAL
+    o_bad = rsim.Opts(intra_chirp=2)
+    assert L.rsim_synthesize(ctx._h, ids, 1, echo, None, None, ctypes.byref(o_bad)) == rsim.RSIM_EINVAL
     # RSIM_MASK_INPUT without a mask
     o_in = rsim.Opts(mask_mode=rsim.RSIM_MASK_INPUT)
     assert L.rsim_synthesize(ctx._h, ids, 1, echo, None, None, ctypes.byref(o_in)) == rsim.RSIM_EINVAL
