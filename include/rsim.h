@@ -148,6 +148,22 @@ int32_t rsim_set_waveform(rsim_ctx *ctx, const rsim_waveform *wf);
 int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx,
                        const double *rx_xyz, int32_t n_rx);
 
+/* Ground double bounce (Section 2.2: forward and backward rays joined after
+ * reflections). enable = 1 adds the paths that reflect once on the flat road plane
+ * z = z_ground on the transmit side, on the receive side, or on both, by the image
+ * method: each is the single-bounce facet term with mirrored elements, times gamma
+ * (complex reflection coefficient; -1 for a perfectly conducting plane) per bounce.
+ * A facet takes a reflected side when its centroid lies above the plane, it faces the
+ * mirrored phase centre, and both legs (centroid -> specular point -> phase centre) are
+ * clear; instances lying in the plane (the road surface) do not block those legs.
+ * While enabled, rsim_synthesize's vis_mask holds 4 mask sets per scene (path types
+ * 0: direct, 1: Tx side reflected, 2: Rx side reflected, 3: both; type-major), the
+ * persistent form is refused (EINVAL) and rsim_backward returns ESTATE.
+ * ERANGE if an array element does not lie above the plane. Point scatterers take all
+ * four paths. */
+int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double gamma_re,
+                        double gamma_im);
+
 /* ---- echo and RDM ------------------------------------------------------------------ */
 
 /* Echo frequency response H (Sections 2.2, 3.2; eqs. (7), (9)-(13)) of each scene:

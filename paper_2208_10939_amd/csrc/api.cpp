@@ -56,6 +56,7 @@ struct SceneRec {
   double *d_pt = nullptr;  // pos [n][3], vel [n][3], amp [n][2]
   // work buffers sized for (N, F)
   int32_t buf_N = -1;
+  int32_t buf_types = 0;  // path types the mask buffer holds (1, or 4 with the ground bounce)
   uint32_t *d_mask = nullptr;
   int32_t *d_vis_idx = nullptr;
   int32_t *d_vis_cnt = nullptr;
@@ -133,6 +134,11 @@ struct rsim_ctx {
   std::vector<int32_t> det_nodes_host;      // uploaded contents
   double *noise_part = nullptr;
   size_t noise_part_n = 0;
+  // ground plane of the reflected paths (rsim_set_ground)
+  bool ground = false;
+  double z_ground = 0.0, gamma_re = -1.0, gamma_im = 0.0;
+  double *d_elem_img = nullptr;  // [3][E][3]: elements of path types 1..3 (images)
+  uint64_t elem_img_version = 0;
 };
 
 namespace {
@@ -243,6 +249,8 @@ RadarConst radar_const(const rsim_ctx *ctx) {
   rc.N = ctx->wf.n_chirps;
   rc.P = static_cast<int32_t>(ctx->tx.size() / 3);
   rc.Q = static_cast<int32_t>(ctx->rx.size() / 3);
+  rc.bounce = ctx->ground ? 1 : 0;
+  rc.z_ground = ctx->z_ground;
   for (int k = 0; k < 3; ++k) {
     double st = 0, sr = 0;
     for (int p = 0; p < rc.P; ++p) st += ctx->tx[3 * p + k];
@@ -304,6 +312,16 @@ int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
       d.facet_base = base;
       d.n_tris = static_cast<int32_t>(m.tris.size() / 3);
       d.has_bvh = m.depth >= 0 ? 1 : 0;
+      // in the ground plane: every world vertex within 1e-6 m of it at t = 0, and no
+      // vertical motion
+      bool flat = !m.verts.empty() && r.vel[2] == 0.0;
+      for (size_t v = 0; flat && v < m.verts.size() / 3; ++v) {
+        const double z = r.rot[6] * m.verts[3 * v] + r.rot[7] * m.verts[3 * v + 1] +
+                         r.rot[8] * m.verts[3 * v + 2] + r.pos0[2];
+        flat = std::fabs(z - ctx->z_ground) <= 1e-6;
+      }
+      d.in_plane = flat ? 1 : 0;
+      d.pad = 0;
       base += d.n_tris;
     }
     sc.n_facets = base;
@@ -321,7 +339,8 @@ int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
     sc.dirty = false;
     sc.buf_N = -1;
   }
-  if (sc.buf_N != N) {
+  const int types = ctx->ground ? 4 : 1;
+  if (sc.buf_N != N || sc.buf_types != types) {
     dev_free(ctx, sc.d_mask);
     dev_free(ctx, sc.d_vis_idx);
     dev_free(ctx, sc.d_vis_cnt);
@@ -331,13 +350,14 @@ int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
     const int64_t words = (sc.n_facets + 31) / 32;
     int32_t rc;
     if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_mask),
-                        sizeof(uint32_t) * std::max<int64_t>(1, words) * N)))
+                        sizeof(uint32_t) * std::max<int64_t>(1, words) * N * types)))
       return rc;
     if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_vis_idx),
                         sizeof(int32_t) * std::max<int64_t>(1, sc.n_facets) * N)))
       return rc;
     if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_vis_cnt), sizeof(int32_t) * N))) return rc;
     sc.buf_N = N;
+    sc.buf_types = types;
   }
   return RSIM_OK;
 }
@@ -533,7 +553,7 @@ std::vector<DevScene> scene_views(rsim_ctx *ctx, const std::vector<int32_t> &ids
   for (size_t i = 0; i < ids.size(); ++i) {
     SceneRec &sc = ctx->scenes[ids[i]];
     uint32_t *mask = vis_mask ? vis_mask + mask_off : sc.d_mask;
-    mask_off += static_cast<int64_t>(rc.N) * ((sc.n_facets + 31) / 32);
+    mask_off += static_cast<int64_t>(ctx->ground ? 4 : 1) * rc.N * ((sc.n_facets + 31) / 32);
     ds[i] = dev_scene(sc, mask, static_cast<char *>(echo) + i * cube * csize);
   }
   return ds;
@@ -605,21 +625,78 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     for (auto &d : ds) HIP_TRY(ctx, launch_visibility(d, rc, s));
     stage_end(ctx, timing, 0, s);
   }
-  stage_begin(ctx, timing, 1, s);
-  for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, rc.N, s));
-  stage_end(ctx, timing, 1, s);
+  if (!ctx->ground) {
+    stage_begin(ctx, timing, 1, s);
+    for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, rc.N, s));
+    stage_end(ctx, timing, 1, s);
+    stage_begin(ctx, timing, 2, s);
+    if (bt) {
+      int per_cu = 0;
+      HIP_TRY(ctx, echo_occupancy(precision, ts.mb, ts.ft, sh, &per_cu));
+      const int groups = std::max(1, per_cu) * ctx->cu_count;
+      HIP_TRY(ctx, launch_echo_persistent(precision, ts.mb, ts.ft, bt->d_scenes, bt->d_items,
+                                          bt->n_items, bt->d_queue, rc, ctx->d_elem, sh, groups, s));
+    } else {
+      for (auto &d : ds)
+        HIP_TRY(ctx, launch_echo_plain(precision, ts.mb, ts.ft, d, rc, ctx->d_elem, sh, s));
+    }
+    stage_end(ctx, timing, 2, s);
+    return RSIM_OK;
+  }
+  // ground bounce: the four path types in turn, each its own mask set, elements
+  // (images for the reflected sides) and factor gamma per bounce, summed into the echo
+  const int E = rc.P + rc.Q;
   stage_begin(ctx, timing, 2, s);
-  if (bt) {
-    int per_cu = 0;
-    HIP_TRY(ctx, echo_occupancy(precision, ts.mb, ts.ft, sh, &per_cu));
-    const int groups = std::max(1, per_cu) * ctx->cu_count;
-    HIP_TRY(ctx, launch_echo_persistent(precision, ts.mb, ts.ft, bt->d_scenes, bt->d_items,
-                                        bt->n_items, bt->d_queue, rc, ctx->d_elem, sh, groups, s));
-  } else {
-    for (auto &d : ds)
-      HIP_TRY(ctx, launch_echo_plain(precision, ts.mb, ts.ft, d, rc, ctx->d_elem, sh, s));
+  for (int k = 0; k < 4; ++k) {
+    RadarConst rk = rc;
+    if (k & 1) rk.tx_c[2] = 2.0 * ctx->z_ground - rc.tx_c[2];
+    if (k >> 1) rk.rx_c[2] = 2.0 * ctx->z_ground - rc.rx_c[2];
+    const double *elem = k ? ctx->d_elem_img + static_cast<size_t>(k - 1) * 3 * E : ctx->d_elem;
+    EchoShape sk = sh;
+    sk.accumulate = k ? 1 : 0;
+    double gr = 1.0, gi = 0.0;
+    for (int b = 0; b < ((k & 1) + (k >> 1)); ++b) {
+      const double t = gr * ctx->gamma_re - gi * ctx->gamma_im;
+      gi = gr * ctx->gamma_im + gi * ctx->gamma_re;
+      gr = t;
+    }
+    sk.gamma_re = gr;
+    sk.gamma_im = gi;
+    for (const DevScene &d : ds) {
+      DevScene dk = d;
+      dk.mask = d.mask + static_cast<int64_t>(k) * rc.N * d.mask_words;
+      HIP_TRY(ctx, launch_compact(dk, rc.N, s));
+      HIP_TRY(ctx, launch_echo_plain(precision, ts.mb, ts.ft, dk, rk, elem, sk, s));
+    }
   }
   stage_end(ctx, timing, 2, s);
+  return RSIM_OK;
+}
+
+// Element positions of path types 1..3 (Tx images; Rx images; both) on the device.
+int32_t ensure_elem_images(rsim_ctx *ctx) {
+  if (ctx->d_elem_img && ctx->elem_img_version == ctx->version) return RSIM_OK;
+  const size_t E = (ctx->tx.size() + ctx->rx.size()) / 3;
+  std::vector<double> e(3 * 3 * E);
+  for (int k = 1; k < 4; ++k) {
+    double *dst = e.data() + (k - 1) * 3 * E;
+    size_t j = 0;
+    for (size_t p = 0; p < ctx->tx.size() / 3; ++p, ++j) {
+      dst[3 * j] = ctx->tx[3 * p];
+      dst[3 * j + 1] = ctx->tx[3 * p + 1];
+      dst[3 * j + 2] = (k & 1) ? 2.0 * ctx->z_ground - ctx->tx[3 * p + 2] : ctx->tx[3 * p + 2];
+    }
+    for (size_t q = 0; q < ctx->rx.size() / 3; ++q, ++j) {
+      dst[3 * j] = ctx->rx[3 * q];
+      dst[3 * j + 1] = ctx->rx[3 * q + 1];
+      dst[3 * j + 2] = (k >> 1) ? 2.0 * ctx->z_ground - ctx->rx[3 * q + 2] : ctx->rx[3 * q + 2];
+    }
+  }
+  dev_free(ctx, ctx->d_elem_img);
+  ctx->d_elem_img = nullptr;
+  int32_t rc = upload(ctx, &ctx->d_elem_img, e.data(), e.size());
+  if (rc) return rc;
+  ctx->elem_img_version = ctx->version;
   return RSIM_OK;
 }
 
@@ -856,6 +933,14 @@ int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx, const 
     return fail(ctx, RSIM_ERANGE, "rsim_set_array: 1..64 Tx and 1..64 Rx elements");
   if (!finite_all(tx_xyz, 3 * n_tx) || !finite_all(rx_xyz, 3 * n_rx))
     return fail(ctx, RSIM_EINVAL, "rsim_set_array: non-finite position");
+  if (ctx->ground) {
+    for (int32_t k = 0; k < n_tx; ++k)
+      if (!(tx_xyz[3 * k + 2] > ctx->z_ground))
+        return fail(ctx, RSIM_ERANGE, "rsim_set_array: elements must lie above the ground plane");
+    for (int32_t k = 0; k < n_rx; ++k)
+      if (!(rx_xyz[3 * k + 2] > ctx->z_ground))
+        return fail(ctx, RSIM_ERANGE, "rsim_set_array: elements must lie above the ground plane");
+  }
   ctx->tx.assign(tx_xyz, tx_xyz + 3 * n_tx);
   ctx->rx.assign(rx_xyz, rx_xyz + 3 * n_rx);
   if (!ctx->host_only) {
@@ -868,6 +953,29 @@ int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx, const 
     if ((rc = upload(ctx, &ctx->d_elem, e.data(), e.size()))) return rc;
   }
   ctx->have_arr = true;
+  ctx->version++;
+  return RSIM_OK;
+}
+
+int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double gamma_re,
+                        double gamma_im) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if ((enable != 0 && enable != 1) || !std::isfinite(z_ground) || !std::isfinite(gamma_re) ||
+      !std::isfinite(gamma_im))
+    return fail(ctx, RSIM_EINVAL, "rsim_set_ground: enable 0/1 and finite plane and gamma");
+  if (enable && ctx->have_arr) {
+    for (size_t k = 2; k < ctx->tx.size(); k += 3)
+      if (!(ctx->tx[k] > z_ground))
+        return fail(ctx, RSIM_ERANGE, "rsim_set_ground: array elements must lie above the plane");
+    for (size_t k = 2; k < ctx->rx.size(); k += 3)
+      if (!(ctx->rx[k] > z_ground))
+        return fail(ctx, RSIM_ERANGE, "rsim_set_ground: array elements must lie above the plane");
+  }
+  ctx->ground = enable != 0;
+  ctx->z_ground = z_ground;
+  ctx->gamma_re = gamma_re;
+  ctx->gamma_im = gamma_im;
+  for (SceneRec &sc : ctx->scenes) sc.dirty = true;  // instance in-plane flags
   ctx->version++;
   return RSIM_OK;
 }
@@ -890,6 +998,9 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
   if (o.intra_chirp && o.precision == RSIM_FP64)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the intra-chirp delay is implemented in the "
                 "FP32 sum only");
+  if (ctx->ground && o.persistent)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the ground bounce runs with plain launches "
+                "(persistent = 0)");
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   std::vector<int32_t> ids(scene_ids, scene_ids + n_scenes);
@@ -914,6 +1025,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
                 echo_smem_bytes(o.precision, ts.mb, ts.ft, sh), ctx->max_lds);
   for (int32_t id : ids)
     if ((rc = ensure_scene_device(ctx, ctx->scenes[id]))) return rc;
+  if (ctx->ground && (rc = ensure_elem_images(ctx))) return rc;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const bool timing = o.timing != 0;
   timing_reset(ctx, timing);
@@ -976,6 +1088,9 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   if ((rc = check_scene(ctx, scene_id))) return rc;
+  if (ctx->ground)
+    return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path; "
+                "disable the ground bounce (rsim_set_ground) first");
   const RadarConst rcn = radar_const(ctx);
   if (cross_term_bound(ctx, rcn) > 3e-4)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: array aperture too large for the FP32 sum");

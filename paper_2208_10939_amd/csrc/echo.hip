@@ -419,8 +419,17 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
     for (int e = tid; e < sh.O_w * kOut; e += nthr) {
       const int oo = ot * sh.O_w + e / kOut;
       const int m = m0 + e % kOut;
-      if (oo < sh.O && m < rc.M)
-        echo_out[(static_cast<int64_t>(oo) * rc.N + n) * rc.M + m] = stage[e];
+      if (oo < sh.O && m < rc.M) {
+        C *dst = echo_out + (static_cast<int64_t>(oo) * rc.N + n) * rc.M + m;
+        if (!sh.accumulate) {
+          *dst = stage[e];
+        } else {
+          // a further path type of the same echo: dst += gamma x value
+          const C v = stage[e], d = *dst;
+          const R gr = static_cast<R>(sh.gamma_re), gi = static_cast<R>(sh.gamma_im);
+          *dst = {d.x + (gr * v.x - gi * v.y), d.y + (gr * v.y + gi * v.x)};
+        }
+      }
     }
   };
 

@@ -45,6 +45,8 @@ struct DevInstance {
   int64_t facet_base;           // scene-global index of this instance's triangle 0
   int32_t n_tris;
   int32_t has_bvh;              // 0 if the mesh has no non-degenerate triangle
+  int32_t in_plane;             // 1: lies in the reflecting ground plane (never blocks legs ending on it)
+  int32_t pad;
 };
 
 // Radar constants passed by value.
@@ -52,8 +54,9 @@ struct RadarConst {
   double f0, slope, fs, df, tc;  // df = slope / fs
   double tx_c[3], rx_c[3];       // phase centres (element means)
   int32_t M, N, P, Q;
-  int32_t intra;  // 1: propagation delay at each sample time within the chirp
-  int32_t pad;
+  int32_t intra;   // 1: propagation delay at each sample time within the chirp
+  int32_t bounce;  // 1: visibility also of the ground-reflected paths (four mask sets)
+  double z_ground; // height of the reflecting ground plane
 };
 
 // Per-scene device view used by the visibility, compaction and echo kernels.

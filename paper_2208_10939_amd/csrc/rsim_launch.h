@@ -16,6 +16,9 @@ namespace rsim {
 struct EchoShape {
   int32_t O, O_w, o_tiles, B_w, M_t, m_tiles, E, n_compute;
   double two_pi_slope;  // 2 pi mu
+  int32_t accumulate;   // 0: write the echo; 1: add gamma x (this path's echo) to it
+  int32_t pad;
+  double gamma_re, gamma_im;
 };
 
 constexpr int kStagingThreads = 128;  // staging waves of the forward facet sum

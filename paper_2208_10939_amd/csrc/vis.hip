@@ -116,11 +116,12 @@ __device__ bool blas_occluded(const BvhNode *nodes, const float4 *leaf, float ox
 // (triangle `self_local` of instance `self_inst` excluded)?
 __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
                                 const double s[3], int self_inst, int32_t self_local,
-                                int32_t *stack, int stride) {
+                                int32_t *stack, int stride, bool skip_plane = false) {
   double d[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
   for (int j = 0; j < sc.n_inst; ++j) {
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
+    if (skip_plane && I.in_plane) continue;  // the road surface under a reflected leg
     double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
     // world-space slab test against the instance box (FP64, conservative box)
     double tn = 0.0, tf = 1.0;
@@ -151,6 +152,25 @@ __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
   return false;
 }
 
+// One side (phase centre E, facing value fe = n . (E - c)) of a facet: *direct when it
+// faces E and centroid -> E is clear; *reflected when the centroid lies above the ground
+// plane, the facet faces the image E' and both legs centroid -> S -> E are clear, S the
+// specular point (the road surface is skipped for these legs).
+__device__ void reflected_sides(const DevScene &sc, const RadarConst &rc, double t,
+                                const double c[3], const double n[3], const double E[3], double fe,
+                                int ii, int32_t lt, int32_t *stk, bool *direct, bool *refl) {
+  *direct = fe > 0.0 && !segment_blocked(sc, t, c, E, ii, lt, stk, blockDim.x);
+  *refl = false;
+  if (!(c[2] > rc.z_ground)) return;
+  const double ez = 2.0 * rc.z_ground - E[2];  // image height
+  const double fi = n[0] * (E[0] - c[0]) + n[1] * (E[1] - c[1]) + n[2] * (ez - c[2]);
+  if (!(fi > 0.0)) return;
+  const double a = (c[2] - rc.z_ground) / (c[2] - ez);
+  const double S[3] = {c[0] + a * (E[0] - c[0]), c[1] + a * (E[1] - c[1]), rc.z_ground};
+  *refl = !segment_blocked(sc, t, c, S, ii, lt, stk, blockDim.x, true) &&
+          !segment_blocked(sc, t, S, E, -1, -1, stk, blockDim.x, true);
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(128) vis_kernel(DevScene sc, RadarConst rc) {
@@ -159,6 +179,7 @@ __global__ void __launch_bounds__(128) vis_kernel(DevScene sc, RadarConst rc) {
   const int n = blockIdx.y;
   const double t = n * rc.tc;
   bool lit = false;
+  bool lit4[4] = {false, false, false, false};
   if (f < sc.n_facets) {
     const int ii = find_instance(sc.inst, sc.n_inst, f);
     const DevInstance &I = sc.inst[ii];
@@ -183,18 +204,36 @@ __global__ void __launch_bounds__(128) vis_kernel(DevScene sc, RadarConst rc) {
     bool nonzero = (nx != 0.0 || ny != 0.0 || nz != 0.0);
     double ft = nx * (rc.tx_c[0] - c[0]) + ny * (rc.tx_c[1] - c[1]) + nz * (rc.tx_c[2] - c[2]);
     double fr = nx * (rc.rx_c[0] - c[0]) + ny * (rc.rx_c[1] - c[1]) + nz * (rc.rx_c[2] - c[2]);
-    if (nonzero && ft > 0.0 && fr > 0.0) {
-      int32_t *stk = vis_stack + threadIdx.x;
-      lit = !segment_blocked(sc, t, c, rc.tx_c, ii, lt, stk, blockDim.x) &&
-            !segment_blocked(sc, t, c, rc.rx_c, ii, lt, stk, blockDim.x);
+    int32_t *stk = vis_stack + threadIdx.x;
+    if (!rc.bounce) {
+      if (nonzero && ft > 0.0 && fr > 0.0) {
+        lit = !segment_blocked(sc, t, c, rc.tx_c, ii, lt, stk, blockDim.x) &&
+              !segment_blocked(sc, t, c, rc.rx_c, ii, lt, stk, blockDim.x);
+      }
+    } else if (nonzero) {
+      // per side: direct (faces E, centroid -> E clear) and reflected on the ground plane;
+      // path type k takes the transmit side (k & 1) and the receive side (k >> 1)
+      const double nv[3] = {nx, ny, nz};
+      bool dt, it, dr, ir;
+      reflected_sides(sc, rc, t, c, nv, rc.tx_c, ft, ii, lt, stk, &dt, &it);
+      reflected_sides(sc, rc, t, c, nv, rc.rx_c, fr, ii, lt, stk, &dr, &ir);
+      lit4[0] = dt && dr;
+      lit4[1] = it && dr;
+      lit4[2] = dt && ir;
+      lit4[3] = it && ir;
     }
   }
-  const unsigned long long bits = __ballot(lit);
-  if ((threadIdx.x & 63) == 0) {
-    const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 5;
-    uint32_t *row = sc.mask + static_cast<int64_t>(n) * sc.mask_words;
-    if (w < sc.mask_words) row[w] = static_cast<uint32_t>(bits);
-    if (w + 1 < sc.mask_words) row[w + 1] = static_cast<uint32_t>(bits >> 32);
+  const int types = rc.bounce ? 4 : 1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k >= types) break;
+    const unsigned long long bits = __ballot(rc.bounce ? lit4[k] : lit);
+    if ((threadIdx.x & 63) == 0) {
+      const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 5;
+      uint32_t *row = sc.mask + (static_cast<int64_t>(k) * rc.N + n) * sc.mask_words;
+      if (w < sc.mask_words) row[w] = static_cast<uint32_t>(bits);
+      if (w + 1 < sc.mask_words) row[w + 1] = static_cast<uint32_t>(bits >> 32);
+    }
   }
 }
 

@@ -48,9 +48,15 @@ class Simulator:
         return torch.empty((n_scenes, self.O, self.wf.n_chirps, self.wf.n_samples), dtype=dt,
                            device=self.dev)
 
+    def set_ground(self, enable: bool, z_ground: float = 0.0, gamma: complex = -1.0):
+        """Ground double bounce on/off; while on, masks hold four path types per scene."""
+        self.ctx.set_ground(enable, z_ground, gamma)
+        self.mask_types = 4 if enable else 1
+
     def mask_buffer(self, which: Optional[Sequence[int]] = None):
         which = range(len(self.scene_ids)) if which is None else which
-        total = sum(self.wf.n_chirps * self.mask_words[i] for i in which)
+        types = getattr(self, "mask_types", 1)
+        total = sum(types * self.wf.n_chirps * self.mask_words[i] for i in which)
         return torch.zeros(max(1, total), dtype=torch.int32, device=self.dev)
 
     def synthesize(self, which: Optional[Sequence[int]] = None, precision=RSIM_FP32_PHASE64,

@@ -33,7 +33,7 @@ EXPORTS = (
     "rsim_scene_info", "rsim_set_waveform", "rsim_set_array", "rsim_synthesize",
     "rsim_form_rdm", "rsim_last_timings", "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
-    "rsim_rdm_backward", "rsim_detect", "rsim_add_noise",
+    "rsim_rdm_backward", "rsim_detect", "rsim_add_noise", "rsim_set_ground",
 )
 
 
@@ -117,6 +117,7 @@ def lib() -> ctypes.CDLL:
         "rsim_rdm_backward": ([vp, vp, vp, i32, vp, vp], i32),
         "rsim_detect": ([vp, vp, vp, i32, ctypes.POINTER(CfarOpts), vp, vp, vp, vp, vp], i32),
         "rsim_add_noise": ([vp, vp, i32, ctypes.c_double, u64, vp, ctypes.POINTER(Opts)], i32),
+        "rsim_set_ground": ([vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -256,6 +257,11 @@ class Context:
         r = np.ascontiguousarray(rx, np.float64).reshape(-1, 3)
         self._check(self._L.rsim_set_array(self._h, _dptr(t), t.shape[0], _dptr(r), r.shape[0]))
         self.n_tx, self.n_rx = t.shape[0], r.shape[0]
+
+    def set_ground(self, enable: bool, z_ground: float = 0.0, gamma: complex = -1.0):
+        g = complex(gamma)
+        self._check(self._L.rsim_set_ground(self._h, int(bool(enable)), float(z_ground), g.real,
+                                            g.imag))
 
     @property
     def n_channels(self) -> int:
