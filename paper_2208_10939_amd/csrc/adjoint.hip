@@ -166,9 +166,9 @@ struct AdjLayout {
     elem = b;
     b = up(b + sizeof(double) * 3 * sh.E);
     geo = b;
-    b = up(b + sizeof(Geo) * 2 * FT);
+    b = up(b + sizeof(Geo) * FT);
     glin = b;
-    b = up(b + sizeof(GLin) * 2 * FT);
+    b = up(b + sizeof(GLin) * FT);
     red = b;  // [2][FT][waves][kAdjVals]
     b = up(b + sizeof(float) * 2 * FT * waves * kAdjVals);
     size_t t = 0;
@@ -246,9 +246,13 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
                                int32_t t0, int nf, int m_tile0, int st) {
   const int P = rc.P, E = sh.E;
   const double slope = rc.slope;
-  Geo *geo = sm.geo + (st >> 6) * FT;
-  GLin *glin = sm.glin + (st >> 6) * FT;
-  for (int i = st & 63; i < FT; i += 64) {
+  // each staging wave takes half of the tile's facets through all steps
+  constexpr int kHalf = FT / 2;
+  static_assert(FT % 2 == 0 && kHalf <= 64, "two staging waves split the tile");
+  const int lane = st & 63, i0 = (st >> 6) * kHalf;
+  Geo *geo = sm.geo;
+  GLin *glin = sm.glin;
+  for (int i = i0 + lane; i < i0 + kHalf && lane < kHalf; i += 64) {
     if (i < nf)
       entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
     else
@@ -256,8 +260,8 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
     make_glin(geo[i], rc, m_tile0, glin[i]);
   }
   wave_lds_sync_adj();
-  for (int task = st; task < FT * E; task += kStagingThreads) {
-    const int i = task / E, e = task % E;
+  for (int task = lane; task < kHalf * E; task += 64) {
+    const int i = i0 + task / E, e = task % E;
     const Geo &g = geo[i];
     float2 *Ue = tl.U + (i * E + e) * sh.B_w;
     if (!g.valid) {
@@ -298,8 +302,8 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
                                    static_cast<float>(dz * inv_rd), inv_r);
     tl.tau[i * E + e] = static_cast<float>(tau);
   }
-  for (int task = st; task < FT * sh.M_t; task += kStagingThreads) {
-    const int i = task / sh.M_t, j = task % sh.M_t;
+  for (int task = lane; task < kHalf * sh.M_t; task += 64) {
+    const int i = i0 + task / sh.M_t, j = task % sh.M_t;
     float2 gv, dv[3];
     g_lin_grad(glin[i], j, gv, dv);
     float4 *dst = tl.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;

@@ -81,10 +81,10 @@ struct EchoLayout {
     size_t b = 0;
     elem = b;
     b = up(b + sizeof(double) * 3 * sh.E);
-    geo = b;  // [2 staging waves][FT]
-    b = up(b + sizeof(Geo) * 2 * FT);
-    glin = b;  // [2 staging waves][FT], FP32 path
-    b = up(b + (kRotated ? sizeof(GLin) * 2 * FT : 0));
+    geo = b;  // [FT]
+    b = up(b + sizeof(Geo) * FT);
+    glin = b;  // [FT], FP32 path
+    b = up(b + (kRotated ? sizeof(GLin) * FT : 0));
     // offsets inside one tile buffer
     size_t t = 0;
     G = t;
@@ -110,8 +110,8 @@ struct EchoTile {
   using C = typename Cx<R>::T;
   C *G;    // [FT][M_t]
   C *G1;   // [FT][M_t]: G (-j)^(m mod 4), for quarter-turn-rotated recurrences (FP32)
-  C *U;    // [FT][E][B_w]
-  C *rat;  // [FT][E][B_w]: per-sample phasor step of each block
+  C *U;    // [B_w][FT][E]
+  C *rat;  // [B_w][FT][E]: per-sample phasor step of each block
   R *off;  // [FT][E]
 };
 
@@ -119,8 +119,8 @@ template <typename R, int MB, int FT>
 struct EchoSmem {
   using C = typename Cx<R>::T;
   double *elem;  // [E][3]
-  Geo *geo;      // [2][FT]: one private copy per staging wave
-  GLin *glin;    // [2][FT]: the same, FP32 path
+  Geo *geo;      // [FT]: entry i written and read by the staging wave that owns it
+  GLin *glin;    // [FT]: the same, FP32 path
   unsigned char *buf0;
   size_t buf_stride, oG, oG1, oU, orat, ooff;
 
@@ -197,11 +197,15 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
   using C = typename Cx<R>::T;
   const int P = rc.P, E = sh.E;
   const double slope = rc.slope;
-  // A: facet / point geometry (FP64). Each staging wave computes the whole tile into its
-  // own copy, so the reads below need no workgroup barrier.
-  Geo *geo = sm.geo + (st >> 6) * FT;
-  GLin *glin = sm.glin + (st >> 6) * FT;
-  for (int i = st & 63; i < FT; i += 64) {
+  // Each staging wave takes half of the tile's entries through all three steps, so the
+  // geometry it reads back was written by itself and needs no workgroup barrier.
+  constexpr int kHalf = FT / 2;
+  static_assert(FT % 2 == 0 && kHalf <= 64, "two staging waves split the tile");
+  const int lane = st & 63, i0 = (st >> 6) * kHalf;
+  Geo *geo = sm.geo;
+  GLin *glin = sm.glin;
+  // A: facet / point geometry (FP64)
+  for (int i = i0 + lane; i < i0 + kHalf && lane < kHalf; i += 64) {
     if (i < nf)
       entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
     else
@@ -213,15 +217,18 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
   }
   wave_lds_sync();
   // B1: per element distance, phases in FP64 reduced to turns
-  for (int task = st; task < FT * E; task += kStagingThreads) {
-    const int i = task / E, e = task % E;
+  for (int task = lane; task < kHalf * E; task += 64) {
+    const int i = i0 + task / E, e = task % E;
     const Geo &g = geo[i];
-    C *Ue = tl.U + (i * E + e) * sh.B_w;
-    C *re = tl.rat + (i * E + e) * sh.B_w;
+    // block-major [B_w][FT][E]: the lanes of a wave (consecutive channels) then read
+    // consecutive Rx elements of one block
+    C *Ue = tl.U + i * E + e;
+    C *re = tl.rat + i * E + e;
+    const int bstride = FT * E;
     if (!g.valid) {
       for (int bb = 0; bb < sh.B_w; ++bb) {
-        Ue[bb] = {R(0), R(0)};
-        re[bb] = {R(1), R(0)};
+        Ue[bb * bstride] = {R(0), R(0)};
+        re[bb * bstride] = {R(1), R(0)};
       }
       tl.off[i * E + e] = R(0);
       continue;
@@ -255,8 +262,8 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
       const C step = phasor_m2pi<R>(delta, R(1));
       for (int bb = 0; bb < sh.B_w; ++bb) {
         const double m0 = static_cast<double>(m_tile0 + bb * MB);
-        Ue[bb] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
-        re[bb] = step;
+        Ue[bb * bstride] = phasor_m2pi<R>(psi0 + m0 * delta, inv_r);
+        re[bb * bstride] = step;
       }
     } else {
       // delay at each sample time t_n + m / fs: exact FP64 phases at both ends of each
@@ -265,15 +272,15 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
         const int ma = m_tile0 + bb * MB;
         const double pa = element_phase(g, rc, sm.elem + 3 * e, e < P, ma);
         const double pb = element_phase(g, rc, sm.elem + 3 * e, e < P, ma + MB);
-        Ue[bb] = phasor_m2pi<R>(pa - floor(pa), inv_r);
-        re[bb] = phasor_m2pi<R>((pb - pa) * (1.0 / MB), R(1));
+        Ue[bb * bstride] = phasor_m2pi<R>(pa - floor(pa), inv_r);
+        re[bb * bstride] = phasor_m2pi<R>((pb - pa) * (1.0 / MB), R(1));
       }
     }
     tl.off[i * E + e] = static_cast<R>(offv);
   }
   // B2: G_f(m) for the tile's samples
-  for (int task = st; task < FT * sh.M_t; task += kStagingThreads) {
-    const int i = task / sh.M_t, j = task % sh.M_t;
+  for (int task = lane; task < kHalf * sh.M_t; task += 64) {
+    const int i = i0 + task / sh.M_t, j = task % sh.M_t;
     C val = {R(0), R(0)};
     if constexpr (EchoLayout<R, MB, FT>::kRotated) {
       val = g_lin(glin[i], j);
@@ -319,8 +326,8 @@ __device__ inline void sum_tile(const RadarConst &rc, const EchoShape &sh,
                                 typename Cx<R>::T (&acc)[MB]) {
   using C = typename Cx<R>::T;
   const int P = rc.P, E = sh.E;
-  const int iu_p = p * sh.B_w + b, iu_q = (P + q) * sh.B_w + b;
-  const int stride_u = E * sh.B_w;
+  const int iu_p = b * FT * E + p, iu_q = b * FT * E + P + q;
+  const int stride_u = E;
   C up = tl.U[iu_p], uq = tl.U[iu_q];
   C rp = tl.rat[iu_p], rq = tl.rat[iu_q];
   R op = tl.off[p], oq = tl.off[P + q];

@@ -264,7 +264,7 @@ __device__ void entry_geometry(const DevScene &sc, const RadarConst &rc, int n, 
     }
     double e1[3], e2[3];
     for (int k = 0; k < 3; ++k) {
-      c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
+      c[k] = (x[0][k] + x[1][k] + x[2][k]) * (1.0 / 3.0);
       e1[k] = x[1][k] - x[0][k];
       e2[k] = x[2][k] - x[0][k];
     }
@@ -278,14 +278,16 @@ __device__ void entry_geometry(const DevScene &sc, const RadarConst &rc, int n, 
     }
     const double rt = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
     const double rr = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
+    const double irt = 1.0 / rt, irr = 1.0 / rr;
     double w[3];
-    for (int k = 0; k < 3; ++k) w[k] = ut[k] / rt + ur[k] / rr;
-    const double obl = 0.5 * (nv[0] * w[0] + nv[1] * w[1] + nv[2] * w[2]) / two_area;
+    for (int k = 0; k < 3; ++k) w[k] = ut[k] * irt + ur[k] * irr;
+    // o = n . w / 2 with n = nv / |nv|; G = j o A Phi / (2 pi), A = |nv| / 2, so
+    // o A = (nv . w) / 4 and no division by the area is needed
+    const double nw = nv[0] * w[0] + nv[1] * w[1] + nv[2] * w[2];
     for (int v = 0; v < 3; ++v)
       g.beta[v] = w[0] * (x[v][0] - c[0]) + w[1] * (x[v][1] - c[1]) + w[2] * (x[v][2] - c[2]);
-    // G = j o A Phi / (2 pi), A = two_area / 2
     g.amp_re = 0.0;
-    g.amp_im = obl * 0.5 * two_area / (2.0 * kPi);
+    g.amp_im = two_area > 0.0 ? nw * (0.25 / (2.0 * kPi)) : 0.0;
     g.tref_t = rt * inv_c;
     g.tref_r = rr * inv_c;
     for (int k = 0; k < 3; ++k) g.vel[k] = I.vel[k];
