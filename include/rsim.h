@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define RSIM_ABI_VERSION 1
+#define RSIM_ABI_VERSION 2
 
 /* status codes */
 #define RSIM_OK 0
@@ -43,6 +43,14 @@ extern "C" {
 /* precision of rsim_synthesize / rsim_form_rdm */
 #define RSIM_FP32_PHASE64 0 /* FP64 geometry and phase reduction, FP32 sum; complex64 */
 #define RSIM_FP64 1         /* FP64 throughout; complex128 echo                       */
+
+/* facet-sum kernel of rsim_synthesize (FP32 sum) */
+#define RSIM_KERNEL_AUTO 0   /* the faster of the two for this array and waveform as timed by */
+                             /* rsim_autotune; the vector units until it has run               */
+#define RSIM_KERNEL_VECTOR 1 /* vector units: full phase factorisation incl. the cross term   */
+#define RSIM_KERNEL_MATRIX 2 /* matrix cores: separable Tx x Rx contraction per sample, which  */
+                             /* drops the Tx-Rx cross term; eligible when |2 pi slope d_p e_q| */
+                             /* <= 1e-5 rad, P <= 12 and Q <= 16                               */
 
 /* visibility-mask mode */
 #define RSIM_MASK_COMPUTE 0 /* compute the lit-facet mask; write it to vis_mask if given */
@@ -77,6 +85,10 @@ typedef struct {
                      /* 1: the propagation delay of eq. (12) taken at each sample time  */
                      /* t_n + m / fs (range-Doppler coupling within a chirp); amplitude, */
                      /* facet integral and lit set stay at t_n. FP32 sum only.          */
+  int32_t kernel;    /* RSIM_KERNEL_AUTO (default), RSIM_KERNEL_VECTOR or RSIM_KERNEL_MATRIX; */
+                     /* MATRIX on an ineligible array or with RSIM_FP64 fails with ERANGE /  */
+                     /* EINVAL; AUTO falls back to VECTOR there                             */
+  int32_t reserved[3];
 } rsim_opts;
 
 /* ---- context ---------------------------------------------------------------------- */
@@ -292,7 +304,8 @@ int32_t rsim_add_noise(rsim_ctx *ctx, void *echo, int32_t n_cubes, double snr_db
 
 /* ---- tuning ------------------------------------------------------------------------- */
 
-/* Time the facet-sum tile shapes on the given scenes and keep the fastest as the
+/* Time the facet-sum tile shapes (and the matrix-core kernel where the array allows it)
+ * on the given scenes and keep the fastest as the
  * default for this (M, O, precision); optionally append it to a JSON-lines cache
  * file (cache_json_path may be NULL). Synchronous. */
 int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,

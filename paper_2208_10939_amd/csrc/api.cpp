@@ -64,6 +64,7 @@ struct SceneRec {
 
 struct TunedShape {
   int mb, ft;
+  int kernel;  // RSIM_KERNEL_VECTOR or RSIM_KERNEL_MATRIX (0: not tuned: vector units)
 };
 
 // Device-side tables of one batched call: scene views and the longest-first work
@@ -384,7 +385,7 @@ TunedShape pick_shape(const rsim_ctx *ctx, int precision, const rsim_opts &o) {
   const int M = ctx->wf.n_samples;
   const int O = static_cast<int>(ctx->tx.size() / 3 * ctx->rx.size() / 3);
   // defaults from a tile sweep on MI355X (c2 workload); rsim_autotune refines them
-  TunedShape s = precision ? TunedShape{16, 8} : TunedShape{64, 16};
+  TunedShape s = precision ? TunedShape{16, 8, 0} : TunedShape{64, 16, 0};
   auto it = ctx->tuned.find(std::make_tuple(M, O, precision));
   if (it != ctx->tuned.end()) s = it->second;
   if (o.tile_m) s.mb = o.tile_m;
@@ -415,6 +416,65 @@ EchoShape forward_shape(const rsim_ctx *ctx, const RadarConst &rc, int precision
   while (sh.B_w > 1 && echo_smem_bytes(precision, mb, ft, sh) > ctx->max_lds)
     sh = echo_shape(ctx, rc, mb, kMaxComputeThreads, sh.B_w - 1);
   return sh;
+}
+
+// Largest cross-term phase the matrix-core sum may drop: each term then carries a relative
+// error below 1e-5, an order of magnitude under the FP32 sum's tolerance.
+constexpr double kMatrixCrossLimit = 1e-5;
+
+// Why the matrix-core facet sum cannot run for this array and precision (nullptr: it can).
+const char *matrix_ineligible(const rsim_ctx *ctx, const RadarConst &rc, int precision) {
+  int pt = 0, qt = 0;
+  if (precision != RSIM_FP32_PHASE64) return "the matrix-core facet sum is FP32 only";
+  if (!mfma_variant(rc.P, rc.Q, &pt, &qt)) return "the matrix-core facet sum needs P <= 12, Q <= 16";
+  if (cross_term_bound(ctx, rc) > kMatrixCrossLimit)
+    return "array aperture too large to drop the Tx-Rx cross term on the matrix cores";
+  return nullptr;
+}
+
+// Shape of the matrix-core facet sum: all O channels and 128 samples per workgroup.
+EchoShape matrix_shape(const RadarConst &rc) {
+  EchoShape sh{};
+  sh.O = rc.P * rc.Q;
+  sh.E = rc.P + rc.Q;
+  sh.O_w = sh.O;
+  sh.o_tiles = 1;
+  sh.M_t = mfma_tile_samples();
+  sh.B_w = 1;
+  sh.m_tiles = (rc.M + sh.M_t - 1) / sh.M_t;
+  sh.n_compute = 512;
+  sh.two_pi_slope = 2.0 * kPi * rc.slope;
+  int pt = 1, qt = 1;
+  mfma_variant(rc.P, rc.Q, &pt, &qt);
+  sh.slots_tx = 4 * pt;
+  sh.slots = 4 * (pt + qt);
+  return sh;
+}
+
+// Kernel, tiles and shape of one rsim_synthesize call.
+struct SumPlan {
+  bool matrix = false;
+  TunedShape ts{};
+  EchoShape sh{};
+  int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
+};
+
+SumPlan plan_sum(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o) {
+  SumPlan pl;
+  pl.ts = pick_shape(ctx, o.precision, o);
+  const bool eligible = matrix_ineligible(ctx, rc, o.precision) == nullptr;
+  if (o.kernel == RSIM_KERNEL_MATRIX)
+    pl.matrix = true;
+  else if (o.kernel == RSIM_KERNEL_AUTO)  // the autotuned choice; vector units by default
+    pl.matrix = eligible && pl.ts.kernel == RSIM_KERNEL_MATRIX && !o.tile_m && !o.tile_f;
+  if (pl.matrix) {
+    pl.sh = matrix_shape(rc);
+    pl.batch_key = 0;
+  } else {
+    pl.sh = forward_shape(ctx, rc, o.precision, pl.ts.mb, pl.ts.ft);
+    pl.batch_key = pl.ts.mb;
+  }
+  return pl;
 }
 
 void *twiddles(rsim_ctx *ctx, int L, int precision, int32_t *status) {
@@ -618,8 +678,14 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
   RadarConst rc = radar_const(ctx);
   rc.intra = o.intra_chirp ? 1 : 0;
   const int precision = o.precision;
-  const TunedShape ts = pick_shape(ctx, precision, o);
-  const EchoShape sh = forward_shape(ctx, rc, precision, ts.mb, ts.ft);
+  const SumPlan pl = plan_sum(ctx, rc, o);
+  const TunedShape ts = pl.ts;
+  const EchoShape sh = pl.sh;
+  auto sum_plain = [&](const DevScene &d, const RadarConst &r, const double *elem,
+                       const EchoShape &shk) {
+    return pl.matrix ? launch_echo_mfma(d, r, elem, shk, s)
+                     : launch_echo_plain(precision, ts.mb, ts.ft, d, r, elem, shk, s);
+  };
   if (o.mask_mode == RSIM_MASK_COMPUTE) {
     stage_begin(ctx, timing, 0, s);
     for (auto &d : ds) HIP_TRY(ctx, launch_visibility(d, rc, s));
@@ -630,15 +696,20 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, rc.N, s));
     stage_end(ctx, timing, 1, s);
     stage_begin(ctx, timing, 2, s);
-    if (bt) {
+    if (bt && pl.matrix) {
+      int per_cu = 0;
+      HIP_TRY(ctx, mfma_occupancy(rc.P, rc.Q, sh, &per_cu));
+      const int groups = std::max(1, per_cu) * ctx->cu_count;
+      HIP_TRY(ctx, launch_echo_mfma_persistent(bt->d_scenes, bt->d_items, bt->n_items, bt->d_queue,
+                                               rc, ctx->d_elem, sh, groups, s));
+    } else if (bt) {
       int per_cu = 0;
       HIP_TRY(ctx, echo_occupancy(precision, ts.mb, ts.ft, sh, &per_cu));
       const int groups = std::max(1, per_cu) * ctx->cu_count;
       HIP_TRY(ctx, launch_echo_persistent(precision, ts.mb, ts.ft, bt->d_scenes, bt->d_items,
                                           bt->n_items, bt->d_queue, rc, ctx->d_elem, sh, groups, s));
     } else {
-      for (auto &d : ds)
-        HIP_TRY(ctx, launch_echo_plain(precision, ts.mb, ts.ft, d, rc, ctx->d_elem, sh, s));
+      for (auto &d : ds) HIP_TRY(ctx, sum_plain(d, rc, ctx->d_elem, sh));
     }
     stage_end(ctx, timing, 2, s);
     return RSIM_OK;
@@ -666,7 +737,7 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
       DevScene dk = d;
       dk.mask = d.mask + static_cast<int64_t>(k) * rc.N * d.mask_words;
       HIP_TRY(ctx, launch_compact(dk, rc.N, s));
-      HIP_TRY(ctx, launch_echo_plain(precision, ts.mb, ts.ft, dk, rk, elem, sk, s));
+      HIP_TRY(ctx, sum_plain(dk, rk, elem, sk));
     }
   }
   stage_end(ctx, timing, 2, s);
@@ -998,6 +1069,10 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
   if (o.intra_chirp && o.precision == RSIM_FP64)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the intra-chirp delay is implemented in the "
                 "FP32 sum only");
+  if (o.kernel < RSIM_KERNEL_AUTO || o.kernel > RSIM_KERNEL_MATRIX)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: unknown kernel %d", o.kernel);
+  if (o.kernel == RSIM_KERNEL_MATRIX && o.precision != RSIM_FP32_PHASE64)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the matrix-core facet sum is FP32 only");
   if (ctx->ground && o.persistent)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the ground bounce runs with plain launches "
                 "(persistent = 0)");
@@ -1015,14 +1090,20 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     return fail(ctx, RSIM_ERANGE,
                 "array aperture too large: |2 pi slope d_p e_q| may reach %.3g rad (limit %.1g)",
                 eps, eps_limit);
-  const TunedShape ts = pick_shape(ctx, o.precision, o);
-  if (!echo_variant_exists(o.precision, ts.mb, ts.ft))
+  if (o.kernel == RSIM_KERNEL_MATRIX) {
+    if (const char *why = matrix_ineligible(ctx, rcn, o.precision))
+      return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
+  }
+  const SumPlan pl = plan_sum(ctx, rcn, o);
+  const TunedShape ts = pl.ts;
+  if (!pl.matrix && !echo_variant_exists(o.precision, ts.mb, ts.ft))
     return fail(ctx, RSIM_EINVAL, "no facet-sum variant with tile_m=%d tile_f=%d", ts.mb, ts.ft);
   if ((rc = need_device(ctx))) return rc;
-  const EchoShape sh = forward_shape(ctx, rcn, o.precision, ts.mb, ts.ft);
-  if (echo_smem_bytes(o.precision, ts.mb, ts.ft, sh) > ctx->max_lds)
-    return fail(ctx, RSIM_ERANGE, "facet-sum tile needs %zu bytes of LDS (max %zu)",
-                echo_smem_bytes(o.precision, ts.mb, ts.ft, sh), ctx->max_lds);
+  const EchoShape sh = pl.sh;
+  const size_t lds = pl.matrix ? mfma_smem_bytes(sh) : echo_smem_bytes(o.precision, ts.mb, ts.ft, sh);
+  if (lds > ctx->max_lds)
+    return fail(ctx, RSIM_ERANGE, "facet-sum tile needs %zu bytes of LDS (max %zu)", lds,
+                ctx->max_lds);
   for (int32_t id : ids)
     if ((rc = ensure_scene_device(ctx, ctx->scenes[id]))) return rc;
   if (ctx->ground && (rc = ensure_elem_images(ctx))) return rc;
@@ -1043,7 +1124,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       g.graph = nullptr;
       g.valid = false;
       if (o.persistent &&
-          (rc = prepare_batch(ctx, g.tables, ids, ds, echo, vis_mask, o.precision, ts.mb, sh, s)))
+          (rc = prepare_batch(ctx, g.tables, ids, ds, echo, vis_mask, o.precision, pl.batch_key,
+                              sh, s)))
         return rc;
       HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed));
       int32_t rc2 = enqueue_synthesis(ctx, ds, o.persistent ? &g.tables : nullptr,
@@ -1074,7 +1156,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     return RSIM_OK;
   }
   if (o.persistent &&
-      (rc = prepare_batch(ctx, ctx->batch, ids, ds, echo, vis_mask, o.precision, ts.mb, sh, s)))
+      (rc = prepare_batch(ctx, ctx->batch, ids, ds, echo, vis_mask, o.precision, pl.batch_key, sh,
+                          s)))
     return rc;
   return enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing);
 }
@@ -1428,18 +1511,26 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
   const int64_t cube = static_cast<int64_t>(O) * rcn.N * rcn.M;
   void *echo = nullptr;
   if ((rc = dev_alloc(ctx, &echo, 8 * cube * n_scenes))) return rc;
+  // vector-unit tiles, then the matrix cores where the array allows them (mb = 0)
   struct Cand { int mb, ft; };
-  const Cand cands[] = {{16, 16}, {32, 8}, {32, 16}, {64, 8}, {64, 16}};
+  std::vector<Cand> cands = {{16, 16}, {32, 8}, {32, 16}, {64, 8}, {64, 16}};
+  if (!matrix_ineligible(ctx, rcn, RSIM_FP32_PHASE64)) cands.push_back({0, 0});
   float best = 1e30f;
-  TunedShape best_s{32, 16};
+  TunedShape best_s{32, 16, RSIM_KERNEL_VECTOR};
   hipStream_t s = ctx->capture_stream;
   for (const Cand &c : cands) {
     rsim_opts o{};
-    o.tile_m = c.mb;
-    o.tile_f = c.ft;
     o.timing = 1;
-    const EchoShape sh = forward_shape(ctx, rcn, 0, c.mb, c.ft);
-    if (echo_smem_bytes(0, c.mb, c.ft, sh) > ctx->max_lds) continue;
+    if (c.mb) {
+      o.tile_m = c.mb;
+      o.tile_f = c.ft;
+      o.kernel = RSIM_KERNEL_VECTOR;
+      const EchoShape sh = forward_shape(ctx, rcn, 0, c.mb, c.ft);
+      if (echo_smem_bytes(0, c.mb, c.ft, sh) > ctx->max_lds) continue;
+    } else {
+      o.kernel = RSIM_KERNEL_MATRIX;
+      if (mfma_smem_bytes(matrix_shape(rcn)) > ctx->max_lds) continue;
+    }
     float total = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
       if ((rc = rsim_synthesize(ctx, scene_ids, n_scenes, echo, nullptr, s, &o))) {
@@ -1455,7 +1546,10 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
     }
     if (total < best) {
       best = total;
-      best_s = TunedShape{c.mb, c.ft};
+      if (c.mb)
+        best_s = TunedShape{c.mb, c.ft, RSIM_KERNEL_VECTOR};
+      else
+        best_s.kernel = RSIM_KERNEL_MATRIX;  // keeps the best vector tiles for opts.kernel = 1
     }
   }
   dev_free(ctx, echo);
@@ -1465,7 +1559,9 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
     std::ofstream f(cache_json_path, std::ios::app);
     if (!f) return fail(ctx, RSIM_EINVAL, "cannot open %s", cache_json_path);
     f << "{\"arch\": \"gfx950\", \"M\": " << rcn.M << ", \"O\": " << O
-      << ", \"precision\": \"fp32\", \"tile_m\": " << best_s.mb << ", \"tile_f\": " << best_s.ft
+      << ", \"precision\": \"fp32\", \"kernel\": \""
+      << (best_s.kernel == RSIM_KERNEL_MATRIX ? "matrix" : "vector")
+      << "\", \"tile_m\": " << best_s.mb << ", \"tile_f\": " << best_s.ft
       << ", \"facet_sum_ms\": " << best / 2 << "}\n";
   }
   return RSIM_OK;

@@ -231,6 +231,87 @@ __device__ inline float sinc_lin(float x0, float x_i, float t0, float t_i, float
   return __builtin_amdgcn_sinf(t) * __builtin_amdgcn_rcpf(x);
 }
 
+// G_f(m_tile0 + j)
+__device__ inline float2 g_lin(const GLin &q, int j) {
+  if (!q.valid) return {0.0f, 0.0f};
+  const float jf = static_cast<float>(j);
+  float2 phi;
+  if (fmaf(jf, q.gap_i, q.gap) < static_cast<float>(kSeriesGap)) {
+    const float b0 = fmaf(jf, q.b0_i, q.b0), b1 = fmaf(jf, q.b1_i, q.b1),
+                b2 = fmaf(jf, q.b2_i, q.b2);
+    const float e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
+    float hm3 = 0.0f, hm2 = 0.0f, hm1 = 1.0f;
+    float re = 0.5f, im = 0.0f, inv_fact = 0.5f;
+#pragma unroll
+    for (int n = 1; n <= EchoTraits<float>::kSeriesTerms; ++n) {
+      const float h = e1 * hm1 - e2 * hm2 + e3 * hm3;
+      hm3 = hm2;
+      hm2 = hm1;
+      hm1 = h;
+      inv_fact = inv_fact / static_cast<float>(n + 2);
+      const float term = h * inv_fact;
+      switch (n & 3) {
+        case 0: re += term; break;
+        case 1: im += term; break;
+        case 2: re -= term; break;
+        default: im -= term; break;
+      }
+    }
+    float t = fmaf(jf, q.mp_i, q.mp);
+    t -= rintf(t);
+    const float ms = __builtin_amdgcn_sinf(t), mc = __builtin_amdgcn_cosf(t);
+    phi = {re * mc - im * ms, re * ms + im * mc};
+  } else {
+    float t1 = fmaf(jf, q.p1_i, q.p1);
+    t1 -= rintf(t1);
+    float t2 = fmaf(jf, q.p2_i, q.p2);
+    t2 -= rintf(t2);
+    const float sc1 = sinc_lin(q.x1, q.x1_i, q.t1, q.t1_i, jf);
+    const float sc2 = sinc_lin(q.x2, q.x2_i, q.t2, q.t2_i, jf);
+    const float inv = __builtin_amdgcn_rcpf(fmaf(jf, q.w_i, q.w));
+    // f_k = -j exp(j 2 pi t_k) sinc_k = (sin, -cos) sinc_k
+    const float s1 = __builtin_amdgcn_sinf(t1) * sc1, c1 = __builtin_amdgcn_cosf(t1) * sc1;
+    const float s2 = __builtin_amdgcn_sinf(t2) * sc2, c2 = __builtin_amdgcn_cosf(t2) * sc2;
+    phi = {(s1 - s2) * inv, (c2 - c1) * inv};
+  }
+  return {q.ar * phi.x - q.ai * phi.y, q.ar * phi.y + q.ai * phi.x};
+}
+
+// Delay of element `el` from the facet centroid moved to sample time t_n + m / fs.
+__device__ inline double moving_delay(const Geo &g, const double *el, double t) {
+  const double dx = el[0] - (g.c[0] + g.vel[0] * t);
+  const double dy = el[1] - (g.c[1] + g.vel[1] * t);
+  const double dz = el[2] - (g.c[2] + g.vel[2] * t);
+  return sqrt(dx * dx + dy * dy + dz * dz) * (1.0 / kC0);
+}
+
+// Element part of the phase (turns, unreduced) at sample m with the delay taken at the
+// sample time: f_m tau - slope tau^2 / 2 - slope tau_ref,other (tau - tau_ref,self)
+// - slope tau_ref,t tau_ref,r / 2, the same split as the stop-and-hop phases.
+__device__ inline double element_phase(const Geo &g, const RadarConst &rc, const double *el,
+                                       bool tx, int m) {
+  const double tau = moving_delay(g, el, m / rc.fs);
+  const double fm = rc.f0 + m * rc.df;
+  const double d = tau - (tx ? g.tref_t : g.tref_r);
+  return fm * tau - 0.5 * rc.slope * tau * tau - rc.slope * (tx ? g.tref_r : g.tref_t) * d -
+         0.5 * rc.slope * g.tref_t * g.tref_r;
+}
+
+// Quadratic coefficient (turns per sample^2) of the phase-centre path's phase
+// f_m tau - slope tau^2 / 2 with the delay at the sample time, from a second difference
+// over one block: the phase leaves the chord of a block by q j (j - MB).
+__device__ inline double chord_curvature(const Geo &g, const RadarConst &rc, int m0, int mb) {
+  const int h = mb / 2;
+  double ph[3];
+  for (int k = 0; k < 3; ++k) {
+    const int m = m0 + k * h;
+    const double t = m / rc.fs;
+    const double tau = moving_delay(g, rc.tx_c, t) + moving_delay(g, rc.rx_c, t);
+    ph[k] = (rc.f0 + m * rc.df) * tau - 0.5 * rc.slope * tau * tau;
+  }
+  return (ph[2] - 2.0 * ph[1] + ph[0]) / (2.0 * h * h);
+}
+
 __device__ inline int find_inst(const DevInstance *inst, int n_inst, int64_t f) {
   int lo = 0, hi = n_inst - 1;
   while (lo < hi) {

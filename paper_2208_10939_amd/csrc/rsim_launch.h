@@ -19,6 +19,7 @@ struct EchoShape {
   int32_t accumulate;   // 0: write the echo; 1: add gamma x (this path's echo) to it
   int32_t pad;
   double gamma_re, gamma_im;
+  int32_t slots_tx, slots;  // matrix-core sum: element slots per facet (Tx first, padded)
 };
 
 constexpr int kStagingThreads = 128;  // staging waves of the forward facet sum
@@ -40,6 +41,18 @@ hipError_t launch_echo_persistent(int precision, int mb, int ft, const DevScene 
 hipError_t echo_occupancy(int precision, int mb, int ft, const EchoShape &sh, int *groups_per_cu);
 bool echo_variant_exists(int precision, int mb, int ft);
 size_t echo_smem_bytes(int precision, int mb, int ft, const EchoShape &sh);
+
+// facet sum on the matrix cores (FP32, separable Tx x Rx form without the cross term):
+// one workgroup per (chirp, 128-sample tile)
+bool mfma_variant(int P, int Q, int *pt, int *qt);
+size_t mfma_smem_bytes(const EchoShape &sh);
+int mfma_tile_samples();
+hipError_t launch_echo_mfma(const DevScene &sc, const RadarConst &rc, const double *elem,
+                            const EchoShape &sh, hipStream_t s);
+hipError_t launch_echo_mfma_persistent(const DevScene *scenes, const int4 *items, int32_t n_items,
+                                       int32_t *queue, const RadarConst &rc, const double *elem,
+                                       const EchoShape &sh, int n_groups, hipStream_t s);
+hipError_t mfma_occupancy(int P, int Q, const EchoShape &sh, int *groups_per_cu);
 
 hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t rows, int M,
                             int conj_in, const void *tw, hipStream_t s);

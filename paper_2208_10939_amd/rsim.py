@@ -23,6 +23,10 @@ RSIM_FP32_PHASE64 = 0
 RSIM_FP64 = 1
 RSIM_MASK_COMPUTE = 0
 RSIM_MASK_INPUT = 1
+RSIM_KERNEL_AUTO = 0
+RSIM_KERNEL_VECTOR = 1
+RSIM_KERNEL_MATRIX = 2
+ABI_VERSION = 2
 N_STAGES = 8
 STAGES = ("visibility", "compaction", "facet_sum", "range_fft", "doppler_rdm",
           "adjoint_facet_sum", "adjoint_fft", "vertex_gather")
@@ -53,7 +57,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("mask_mode", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("tile_m", ctypes.c_int32),
-                ("tile_f", ctypes.c_int32), ("intra_chirp", ctypes.c_int32)]
+                ("tile_f", ctypes.c_int32), ("intra_chirp", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class CfarOpts(ctypes.Structure):
@@ -123,6 +128,9 @@ def lib() -> ctypes.CDLL:
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
+    if L.rsim_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {L.rsim_abi_version()}, the binding "
+                           f"expects {ABI_VERSION}: rebuild it")
     _lib = L
     return L
 
@@ -270,9 +278,11 @@ class Context:
     # ---- echo / RDM --------------------------------------------------------------
     @staticmethod
     def opts(precision=RSIM_FP32_PHASE64, mask_mode=RSIM_MASK_COMPUTE, use_graph=False,
-             persistent=False, timing=False, tile_m=0, tile_f=0, intra_chirp=False) -> Opts:
+             persistent=False, timing=False, tile_m=0, tile_f=0, intra_chirp=False,
+             kernel=RSIM_KERNEL_AUTO) -> Opts:
         return Opts(int(precision), int(mask_mode), int(bool(use_graph)), int(bool(persistent)),
-                    int(bool(timing)), int(tile_m), int(tile_f), int(bool(intra_chirp)))
+                    int(bool(timing)), int(tile_m), int(tile_f), int(bool(intra_chirp)),
+                    int(kernel))
 
     def synthesize(self, scene_ids: Sequence[int], echo, mask=None, stream=None, **kw):
         ids = (ctypes.c_int32 * len(scene_ids))(*[int(s) for s in scene_ids])

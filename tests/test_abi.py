@@ -30,7 +30,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(rsim.EXPORTS)
-    assert L.rsim_abi_version() == 1
+    assert L.rsim_abi_version() == rsim.ABI_VERSION == 2
 
 
 def test_create_without_device_reports_edevice():
@@ -131,6 +131,7 @@ def test_bvh_build_on_large_mesh_host_only():
 def test_detect_and_noise_validation_host_only():
     """Argument checks of rsim_detect / rsim_add_noise before any device work."""
     assert ctypes.sizeof(rsim.Point) == 64 and ctypes.sizeof(rsim.CfarOpts) == 32
+    assert ctypes.sizeof(rsim.Opts) == 48
     assert rsim.POINT_DTYPE.itemsize == 64
     ctx = _host_ctx()
     L = ctx._L

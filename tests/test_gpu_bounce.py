@@ -27,14 +27,14 @@ def rel_rms(a, b):
     return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
 
 
-def _run(cfg, precision, gamma=-1.0, z_g=0.0):
+def _run(cfg, precision, gamma=-1.0, z_g=0.0, kernel=0):
     import torch
     from paper_2208_10939_amd.pipeline import Simulator
     sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
     sim = Simulator([sc], wf, arr)
     sim.set_ground(True, z_g, gamma)
     mask = sim.mask_buffer()
-    sim.synthesize(precision=precision, mask=mask)
+    sim.synthesize(precision=precision, mask=mask, kernel=kernel)
     F, N = sim.n_facets[0], wf.n_chirps
     words = sim.mask_words[0]
     raw = mask.cpu().numpy().view("<u4").reshape(4, N, words)
@@ -44,7 +44,8 @@ def _run(cfg, precision, gamma=-1.0, z_g=0.0):
     assert not (mism & ~amb).any(), f"{int((mism & ~amb).sum())} unambiguous mask mismatches"
     packed = np.concatenate([pack_mask(om[k]).reshape(-1) for k in range(4)])
     m_in = torch.from_numpy(packed.view(np.int32).copy()).cuda()
-    H = sim.synthesize(precision=precision, mask=m_in, mask_mode=1).cpu().numpy()[0]
+    H = sim.synthesize(precision=precision, mask=m_in, mask_mode=1,
+                       kernel=kernel).cpu().numpy()[0]
     Ho = bounce.synthesize_bounce(sc, wf, arr, z_g=z_g, gamma=gamma, masks=om)
     Hd = oracle.synthesize(sc, wf, arr, mask=om[0])
     err = rel_rms(H, Ho)
@@ -54,11 +55,11 @@ def _run(cfg, precision, gamma=-1.0, z_g=0.0):
     return err
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_bounce_vehicle(precision):
-    _log(f"case ground bounce, 1.5k-triangle vehicle, precision={precision}")
+@pytest.mark.parametrize("precision,kernel", [(0, 1), (0, 2), (1, 0)])
+def test_bounce_vehicle(precision, kernel):
+    _log(f"case ground bounce, 1.5k-triangle vehicle, precision={precision} kernel={kernel}")
     cfg = scenes.small_single(n_samples=64, n_chirps=2)
-    err = _run(cfg, precision, gamma=-0.9 + 0.2j)
+    err = _run(cfg, precision, gamma=-0.9 + 0.2j, kernel=kernel)
     assert err <= (FP64_TOL if precision else FP32_TOL)
 
 

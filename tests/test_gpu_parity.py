@@ -191,22 +191,22 @@ def test_rdm_adjoint_identity(sim_mod, M, N):
 
 
 def test_batched_persistent_equals_plain(sim_mod):
-    _log("case batched (4 scenes, persistent + graph) vs plain")
+    _log("case batched (4 scenes, persistent + graph) vs plain, vector-unit kernel")
     wf = scenes.paper_waveform(64, 4)
     arr = scenes.sparse_mimo_12x16(wf, 4)
     scs = [scenes.intersection_scene(400 + i, n_vehicles=1 + i, per_vehicle=300 + 200 * i,
                                      with_ground=False) for i in range(4)]
     sim = sim_mod.Simulator(scs, wf, arr)
-    plain = sim.synthesize()
+    plain = sim.synthesize(kernel=1)
     for i in range(4):
-        one = sim.synthesize(which=[i])
+        one = sim.synthesize(which=[i], kernel=1)
         assert np.array_equal(one.cpu().numpy()[0], plain.cpu().numpy()[i])
-    pers = sim.synthesize(persistent=True)
+    pers = sim.synthesize(persistent=True, kernel=1)
     assert np.array_equal(pers.cpu().numpy(), plain.cpu().numpy())
     buf = sim.echo_buffer(4)
     for rep in range(3):
         buf.zero_()
-        sim.synthesize(echo=buf, persistent=True, use_graph=True)
+        sim.synthesize(echo=buf, persistent=True, use_graph=True, kernel=1)
         assert np.array_equal(buf.cpu().numpy(), plain.cpu().numpy()), f"replay {rep}"
     Ho = oracle.synthesize(scs[2], wf, arr)
     err = rel_rms(plain.cpu().numpy()[2], Ho)
@@ -215,7 +215,8 @@ def test_batched_persistent_equals_plain(sim_mod):
 
 
 def test_intra_chirp_delay_fp32(sim_mod):
-    """Delay at each sample time (range-Doppler coupling within the chirp), FP32 sum:
+    """Delay at each sample time (range-Doppler coupling within the chirp), FP32 sum on
+    the vector units:
     fast point targets and a moving vehicle against the oracle's reading; the result
     differs from stop-and-hop by far more than the tolerance."""
     import torch
@@ -225,7 +226,7 @@ def test_intra_chirp_delay_fp32(sim_mod):
     sc = scenes.point_scene([14.0, 31.0, 52.0], [15.0, -12.0, 13.0],
                             amps=[1.0, 0.5 - 0.2j, 2j], az_deg=[-25.0, 8.0, 30.0])
     sim = sim_mod.Simulator([sc], wf, arr)
-    H = sim.synthesize(intra_chirp=True).cpu().numpy()[0]
+    H = sim.synthesize(intra_chirp=True, kernel=1).cpu().numpy()[0]
     Ho = oracle.synthesize(sc, wf, arr, intra_chirp=True)
     Hs = oracle.synthesize(sc, wf, arr)
     err, moved = rel_rms(H, Ho), rel_rms(Hs, Ho)
@@ -236,7 +237,7 @@ def test_intra_chirp_delay_fp32(sim_mod):
     sim = sim_mod.Simulator([sc], wf, arr)
     omask, amb = oracle.visibility(sc, arr, wf)
     H = sim.synthesize(mask=sim.mask_from_numpy([omask]), mask_mode=1,
-                       intra_chirp=True).cpu().numpy()[0]
+                       intra_chirp=True, kernel=1).cpu().numpy()[0]
     Ho = oracle.synthesize(sc, wf, arr, mask=omask, intra_chirp=True)
     err = rel_rms(H, Ho)
     _log(f"  vehicle: speed {np.linalg.norm(sc.instances[0].vel):.1f} m/s rel_rms={err:.3e}")
