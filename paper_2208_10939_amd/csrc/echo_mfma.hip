@@ -29,6 +29,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kMfmaWaves = 8;          // accumulating waves, 16 samples each
 constexpr int kMfmaTile = 16 * kMfmaWaves;  // samples per workgroup
 constexpr int kMfmaBlk = 16;           // samples per phase block (one wave)
+constexpr double kBlkMid = 7.5;        // block centre, where the staged phase is taken
+constexpr int kMfmaStagingWaves = 4;  // one per SIMD, beside two accumulating waves
+constexpr int kMfmaThreads = (kMfmaWaves + kMfmaStagingWaves) * 64;
 
 template <int FT>
 struct MfmaLayout {
@@ -45,7 +48,7 @@ struct MfmaLayout {
     size_t t = 0;
     G = t;  // [FT][kMfmaTile] float2
     t += sizeof(float2) * FT * kMfmaTile;
-    EP = t;  // [kMfmaWaves][FT][slots] float2: (phase at the block start, step) in turns
+    EP = t;  // [kMfmaWaves][FT][slots] float2: (phase at the block centre, step) in turns
     t += sizeof(float2) * kMfmaWaves * FT * sh.slots;
     IR = t;  // [FT][slots] float: 1 / R
     t = up(t + sizeof(float) * FT * sh.slots);
@@ -87,15 +90,15 @@ __device__ inline void mfma_lds_sync() {
 __device__ inline float centred(double t) { return static_cast<float>(t - rint(t)); }
 
 // Staging of one tile (entries t0 .. t0 + nf - 1 of chirp n) into buffer k; each of the
-// two staging waves takes half of the entries through all steps. Element e has slot e
+// staging waves takes its share of the entries through all steps. Element e has slot e
 // (Tx) or slots_tx + e - P (Rx) in a facet's row of sh.slots; the padding slots are
 // never written (they feed only product rows and columns that are never stored).
 template <int FT>
 __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
                            const MfmaSmem<FT> &sm, int k, int n, int32_t cnt, int32_t t0, int nf,
                            int m_tile0, int st) {
-  constexpr int kHalf = FT / 2;
-  static_assert(FT % 2 == 0 && kHalf <= 64, "two staging waves split the tile");
+  constexpr int kHalf = FT / kMfmaStagingWaves;  // entries per staging wave
+  static_assert(FT % kMfmaStagingWaves == 0 && kHalf <= 64, "staging waves split the tile");
   const int P = rc.P, E = sh.E;
   const int lane = st & 63, i0 = (st >> 6) * kHalf;
   const double slope = rc.slope;
@@ -146,14 +149,15 @@ __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoS
       const float dstep = centred(delta);
       for (int b = 0; b < kMfmaWaves; ++b) {
         const double m0 = static_cast<double>(m_tile0 + b * kMfmaBlk);
-        EP[(b * FT + i) * S + slot] = make_float2(centred(psi0 + m0 * delta), dstep);
+        EP[(b * FT + i) * S + slot] = make_float2(centred(psi0 + (m0 + kBlkMid) * delta), dstep);
       }
     } else {
       for (int b = 0; b < kMfmaWaves; ++b) {
         const int ma = m_tile0 + b * kMfmaBlk;
         const double pa = element_phase(g, rc, sm.elem + 3 * e, e < P, ma);
         const double pb = element_phase(g, rc, sm.elem + 3 * e, e < P, ma + kMfmaBlk);
-        EP[(b * FT + i) * S + slot] = make_float2(centred(pa), centred((pb - pa) * (1.0 / kMfmaBlk)));
+        const double step = (pb - pa) * (1.0 / kMfmaBlk);
+        EP[(b * FT + i) * S + slot] = make_float2(centred(pa + kBlkMid * step), centred(step));
       }
     }
   }
@@ -171,33 +175,56 @@ __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoS
 }
 
 // exp(-j 2 pi (phi0 + s step)) * ir
+// exp(-j 2 pi (phi_c + s step)) / R for a sample s - 7.5 samples from the block centre
+// (|t| <= 4.25 turns: the hardware sine and cosine take it unreduced, and its FP32
+// rounding stays below 2.4e-7 turns)
 __device__ inline float2 elem_phasor(float2 ep, float s, float ir) {
-  float t = fmaf(s, ep.y, ep.x);
-  t -= rintf(t);
+  const float t = fmaf(s, ep.y, ep.x);
   return make_float2(__builtin_amdgcn_cosf(t) * ir, -__builtin_amdgcn_sinf(t) * ir);
 }
 
-// Operands of facet i for this lane (sample mj, slot l of each group of four): A = G T_p
-// / R_p for its Tx slots p = 4a + l, B = T_q / R_q for its Rx slots 4 PT + 4b + l. Rows of
-// padding slots hold whatever the LDS holds; they reach only products that are never
-// stored.
+// LDS values behind the operands of one facet for this lane (sample mj, slot l of each
+// group of four): G at its sample, and (phase, step) and 1 / R of its Tx slots 4a + l and
+// Rx slots 4 PT + 4b + l. Padding slots hold whatever the LDS holds; they reach only
+// products that are never stored.
 template <int PT, int QT>
-__device__ inline void mfma_operands(const float2 *G, const float2 *EP, const float *IR, int i,
-                                     int mj, int l, float sf, float (&ar)[PT], float (&ai)[PT],
-                                     float (&br)[QT], float (&bi)[QT]) {
+struct MfmaRaw {
+  float2 g, et[PT], er[QT];
+  float it[PT], ir[QT];
+};
+
+template <int PT, int QT>
+__device__ inline void mfma_load(const float2 *G, const float2 *EP, const float *IR, int i, int mj,
+                                 int l, MfmaRaw<PT, QT> &r) {
   constexpr int kSlots = 4 * (PT + QT);
-  const float2 g = G[i * kMfmaTile + mj];
+  r.g = G[i * kMfmaTile + mj];
   const float2 *ep = EP + i * kSlots + l;
   const float *ir = IR + i * kSlots + l;
 #pragma unroll
   for (int a = 0; a < PT; ++a) {
-    const float2 t = elem_phasor(ep[4 * a], sf, ir[4 * a]);
-    ar[a] = g.x * t.x - g.y * t.y;
-    ai[a] = g.x * t.y + g.y * t.x;
+    r.et[a] = ep[4 * a];
+    r.it[a] = ir[4 * a];
   }
 #pragma unroll
   for (int b = 0; b < QT; ++b) {
-    const float2 t = elem_phasor(ep[4 * (PT + b)], sf, ir[4 * (PT + b)]);
+    r.er[b] = ep[4 * (PT + b)];
+    r.ir[b] = ir[4 * (PT + b)];
+  }
+}
+
+// Operands A = G T_p / R_p (Tx) and B = T_q / R_q (Rx) at sample offset sf in the block.
+template <int PT, int QT>
+__device__ inline void mfma_form(const MfmaRaw<PT, QT> &r, float sf, float (&ar)[PT],
+                                 float (&ai)[PT], float (&br)[QT], float (&bi)[QT]) {
+#pragma unroll
+  for (int a = 0; a < PT; ++a) {
+    const float2 t = elem_phasor(r.et[a], sf, r.it[a]);
+    ar[a] = r.g.x * t.x - r.g.y * t.y;
+    ai[a] = r.g.x * t.y + r.g.y * t.x;
+  }
+#pragma unroll
+  for (int b = 0; b < QT; ++b) {
+    const float2 t = elem_phasor(r.er[b], sf, r.ir[b]);
     br[b] = t.x;
     bi[b] = t.y;
   }
@@ -264,7 +291,7 @@ __device__ void mfma_compute_item(const DevScene &sc, const RadarConst &rc, cons
   const int w = tid >> 6, lane = tid & 63;
   const int s = lane >> 2, l = lane & 3;  // block (sample) and row/column within it
   const int mj = w * kMfmaBlk + s;        // sample within the tile
-  const float sf = static_cast<float>(s);
+  const float sf = static_cast<float>(s) - static_cast<float>(kBlkMid);  // from the block centre
   v4f acr[PT][QT], aci[PT][QT];
 #pragma unroll
   for (int a = 0; a < PT; ++a)
@@ -280,24 +307,20 @@ __device__ void mfma_compute_item(const DevScene &sc, const RadarConst &rc, cons
     const float2 *EP = sm.EP(buf) + w * FT * (4 * (PT + QT));
     const float *IR = sm.IR(buf);
     const int nf = min(FT, total - k * FT);  // >= 1
-    // software pipeline: the operands of facet i + 1 (LDS reads, phasors) are formed
-    // while the MFMAs of facet i run
+    // Software pipeline: the LDS reads of facet i + 1 are in flight while the MFMAs of
+    // facet i run; its operands are formed after them. Scheduling barriers keep the
+    // MFMAs in one group and the vector work in another (interleaving the two within a
+    // wave costs issue cycles on this hardware).
     float ar[PT], ai[PT], br[QT], bi[QT];
-    mfma_operands<PT, QT>(G, EP, IR, 0, mj, l, sf, ar, ai, br, bi);
+    MfmaRaw<PT, QT> raw;
+    mfma_load<PT, QT>(G, EP, IR, 0, mj, l, raw);
+    mfma_form<PT, QT>(raw, sf, ar, ai, br, bi);
     for (int i = 1; i < nf; ++i) {
-      float ar2[PT], ai2[PT], br2[QT], bi2[QT];
-      mfma_operands<PT, QT>(G, EP, IR, i, mj, l, sf, ar2, ai2, br2, bi2);
+      mfma_load<PT, QT>(G, EP, IR, i, mj, l, raw);
+      __builtin_amdgcn_sched_barrier(0);
       mfma_accumulate<PT, QT>(acr, aci, ar, ai, br, bi);
-#pragma unroll
-      for (int a = 0; a < PT; ++a) {
-        ar[a] = ar2[a];
-        ai[a] = ai2[a];
-      }
-#pragma unroll
-      for (int b = 0; b < QT; ++b) {
-        br[b] = br2[b];
-        bi[b] = bi2[b];
-      }
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_form<PT, QT>(raw, sf, ar, ai, br, bi);
     }
     mfma_accumulate<PT, QT>(acr, aci, ar, ai, br, bi);
   }
@@ -336,7 +359,7 @@ __device__ void mfma_compute_item(const DevScene &sc, const RadarConst &rc, cons
 }
 
 template <int PT, int QT, int FT>
-__global__ void __launch_bounds__(640) echo_mfma_kernel(DevScene sc, RadarConst rc,
+__global__ void __launch_bounds__(kMfmaThreads) echo_mfma_kernel(DevScene sc, RadarConst rc,
                                                         const double *elem, EchoShape sh) {
   extern __shared__ __align__(16) unsigned char mfma_smem[];
   MfmaSmem<FT> sm;
@@ -355,7 +378,7 @@ __global__ void __launch_bounds__(640) echo_mfma_kernel(DevScene sc, RadarConst 
 // role runs its own loop (so that neither holds the other's values); both pass the same
 // barriers per item.
 template <int PT, int QT, int FT>
-__global__ void __launch_bounds__(640) echo_mfma_persistent_kernel(
+__global__ void __launch_bounds__(kMfmaThreads) echo_mfma_persistent_kernel(
     const DevScene *scenes, const int4 *items, int32_t n_items, int32_t *queue, RadarConst rc,
     const double *elem, EchoShape sh) {
   extern __shared__ __align__(16) unsigned char mfma_smem[];
@@ -423,7 +446,7 @@ hipError_t launch_echo_mfma(const DevScene &sc, const RadarConst &rc, const doub
   if (sh.slots_tx != 4 * pt || sh.slots != 4 * (pt + qt)) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>(rc.N) * sh.m_tiles;
   const size_t lds = mfma_smem_bytes(sh);
-  const int threads = kMfmaWaves * 64 + kStagingThreads;
+  const int threads = kMfmaThreads;
 #define X(PT, QT)                                                                            \
   if (pt == PT && qt == QT) {                                                                \
     hipLaunchKernelGGL((echo_mfma_kernel<PT, QT, kMfmaFT>), dim3(grid), dim3(threads), lds, s, \
@@ -442,7 +465,7 @@ hipError_t launch_echo_mfma_persistent(const DevScene *scenes, const int4 *items
   if (!mfma_variant(rc.P, rc.Q, &pt, &qt)) return hipErrorInvalidValue;
   if (sh.slots_tx != 4 * pt || sh.slots != 4 * (pt + qt)) return hipErrorInvalidValue;
   const size_t lds = mfma_smem_bytes(sh);
-  const int threads = kMfmaWaves * 64 + kStagingThreads;
+  const int threads = kMfmaThreads;
   hipLaunchKernelGGL(mfma_reset_counter_kernel, dim3(1), dim3(64), 0, s, queue);
 #define X(PT, QT)                                                                           \
   if (pt == PT && qt == QT) {                                                               \
@@ -460,7 +483,7 @@ hipError_t mfma_occupancy(int P, int Q, const EchoShape &sh, int *groups_per_cu)
   if (!mfma_variant(P, Q, &pt, &qt)) return hipErrorInvalidValue;
   if (sh.slots_tx != 4 * pt || sh.slots != 4 * (pt + qt)) return hipErrorInvalidValue;
   const size_t lds = mfma_smem_bytes(sh);
-  const int threads = kMfmaWaves * 64 + kStagingThreads;
+  const int threads = kMfmaThreads;
 #define X(PT, QT)                                                                       \
   if (pt == PT && qt == QT)                                                             \
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
