@@ -7,6 +7,7 @@ compaction + facet sum + range FFT + Doppler FFT/RDM of one frame; inputs reside
 in device memory. Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--calib-copy MiB]
+                  [--kernel auto|vector|matrix] [--tile-m T --tile-f F]
 """
 from __future__ import annotations
 
@@ -30,35 +31,81 @@ FLOP_PER_EVAL = 14
 EXECUTED_FLOP_PER_EVAL = 12
 # Published FP32 vector peak of MI355X (256 CU x 2.4 GHz; reached with packed FP32).
 PEAK_FP32_VECTOR = 157.3e12
+# Published dense FP32 matrix-core (MFMA) peak of MI355X.
+PEAK_FP32_MFMA = 157.3e12
+# What the matrix-core kernel executes per evaluation on the matrix cores: the complex
+# multiply-accumulate as four real rank-1 MFMA updates (4 MAC = 8 FLOP); the phasors
+# (one per Tx and per Rx element, not per channel) run on the vector units.
+MFMA_FLOP_PER_EVAL = 8
 # FP32 FMA issue without packed-math instructions, which this build keeps out of all
 # device code: 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.
 PEAK_FP32_NON_PACKED = 256 * 4 * 16 * 2 * 2.4e9
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "facet_sum_c2_traffic.json")
+PROFILE_TRAFFIC = {"vector": os.path.join(ROOT, "profiles", "facet_sum_c2_traffic.json"),
+                   "matrix": os.path.join(ROOT, "profiles", "facet_sum_mfma_c2_traffic.json")}
+KERNEL_SOURCES = {"vector": ("echo.hip", "echo_common.h"),
+                  "matrix": ("echo_mfma.hip", "echo_common.h")}
+KERNEL_CODES = {"auto": 0, "vector": 1, "matrix": 2}
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def _src_hash():
+def _src_hash(kernel="vector"):
     h = hashlib.sha256()
-    for f in ("echo.hip", "echo_common.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2208_10939_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(evals_per_launch):
+def _traffic(kernel):
     """HBM bytes per facet-sum launch from the committed counter summary, if it was
     taken on the current kernel source."""
     try:
-        with open(PROFILE_TRAFFIC) as f:
+        with open(PROFILE_TRAFFIC[kernel]) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("echo_hip_sha256_16") != _src_hash():
+    if d.get("echo_hip_sha256_16") != _src_hash(kernel):
         return None
     return d.get("bytes_per_launch")
+
+
+def roofline(kernel, achieved, evals, fs_ms):
+    """Roofline object of the facet-sum kernel: algorithmic FLOP (FLOP_PER_EVAL per
+    evaluation) per launch over the launch's measured duration, against the published
+    FP32 peak of the units the kernel runs on."""
+    rate = evals / (fs_ms * 1e-3)
+    if kernel == "matrix":
+        return {
+            "bound": "mfma",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_MFMA / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_MFMA,
+            "traffic": _traffic("matrix"),
+            "kernel": "rsim::echo_mfma_kernel<3, 4, 16> (FP64 prep + facet integral + "
+                      "separable Tx x Rx contraction on v_mfma_f32_4x4x1f32)",
+            "flop_per_eval": FLOP_PER_EVAL,
+            "evals_per_launch": evals,
+            "executed_mfma_flop_per_eval": MFMA_FLOP_PER_EVAL,
+            "mfma_utilisation": MFMA_FLOP_PER_EVAL * rate / PEAK_FP32_MFMA,
+        }
+    return {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP32_VECTOR / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_VECTOR,
+        "traffic": _traffic("vector"),
+        "kernel": "rsim::echo_kernel<float> (FP64 prep + facet integral + facet sum)",
+        "flop_per_eval": FLOP_PER_EVAL,
+        "evals_per_launch": evals,
+        "executed_flop_per_eval": EXECUTED_FLOP_PER_EVAL,
+        "executed_frac_of_non_packed_fp32_peak":
+            EXECUTED_FLOP_PER_EVAL * rate / PEAK_FP32_NON_PACKED,
+    }
 
 
 def cpu_baseline(cfg, channels=32):
@@ -196,6 +243,8 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--tile-f", type=int, default=0)
+    ap.add_argument("--kernel", choices=("auto", "vector", "matrix"), default="auto",
+                    help="facet-sum kernel (auto: the autotuner's choice)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -220,14 +269,14 @@ def main():
     echo = sim.echo_buffer(1)
     mask = sim.mask_buffer()
     rdm = torch.empty(echo.shape, dtype=torch.float32, device="cuda")
-    kw = dict(tile_m=args.tile_m, tile_f=args.tile_f)
+    kw = dict(tile_m=args.tile_m, tile_f=args.tile_f, kernel=KERNEL_CODES[args.kernel])
 
     def step(timing):
         sim.ctx.synthesize([sim.scene_ids[0]], echo, mask, timing=timing, **kw)
         sim.ctx.form_rdm(echo, rdm, None, n_cubes=1, timing=timing)
 
     tuned = None
-    if not (args.tile_m or args.tile_f):
+    if not (args.tile_m or args.tile_f) and args.kernel == "auto":
         # tile shapes from the library's autotuner, timed on this workload
         import tempfile
         fd, tune_path = tempfile.mkstemp(suffix=".jsonl")
@@ -236,7 +285,10 @@ def main():
         with open(tune_path) as f:
             tuned = json.loads(f.read().strip().splitlines()[-1])
         os.remove(tune_path)
-        _log(f"bench: autotuned facet-sum tile {tuned['tile_m']} x {tuned['tile_f']}")
+        _log(f"bench: autotuned facet-sum kernel {tuned['kernel']}, vector tile "
+             f"{tuned['tile_m']} x {tuned['tile_f']}")
+    kernel = (tuned["kernel"] if tuned else
+              ("vector" if args.kernel == "auto" else args.kernel))
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -279,23 +331,11 @@ def main():
                    "triangles": int(sc.n_tris), "channels": int(arr.n_channels),
                    "samples": int(wf.n_samples), "chirps": int(wf.n_chirps),
                    "lit_facets_per_chirp": float(lit.mean()), "seed": cfg.seed,
+                   "facet_sum_kernel": kernel,
                    "facet_sum_tile": (tuned if tuned else
                                       {"tile_m": args.tile_m, "tile_f": args.tile_f})},
         "stage_ms": stage_avg,
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR,
-            "traffic": _traffic(evals_per_step),
-            "kernel": "rsim::echo_kernel<float> (FP64 prep + facet integral + facet sum)",
-            "flop_per_eval": FLOP_PER_EVAL,
-            "evals_per_launch": evals_per_step,
-            "executed_flop_per_eval": EXECUTED_FLOP_PER_EVAL,
-            "executed_frac_of_non_packed_fp32_peak":
-                EXECUTED_FLOP_PER_EVAL * evals_per_step / (fs_ms * 1e-3) / PEAK_FP32_NON_PACKED,
-        },
+        "roofline": roofline(kernel, achieved, evals_per_step, fs_ms),
     }
     if not args.no_extras:
         _log("bench: forward + backward")

@@ -30,7 +30,7 @@ struct EchoTraits<double> {
 };
 constexpr double kSeriesGap = 0.5;  // radians: series below, divided-difference form above
 
-struct alignas(8) Geo {
+struct alignas(16) Geo {
   double c[3];        // centroid (world) at t_n
   double tref_t, tref_r;
   double beta[3];     // w . (x_i - c), metres

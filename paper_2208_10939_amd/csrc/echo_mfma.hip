@@ -89,6 +89,20 @@ __device__ inline void mfma_lds_sync() {
 
 __device__ inline float centred(double t) { return static_cast<float>(t - rint(t)); }
 
+// A copy of an LDS record in registers, read as whole 16-byte words in one batch.
+template <typename T>
+__device__ inline T lds_copy(const T &src) {
+  static_assert(sizeof(T) % 16 == 0 && alignof(T) >= 16, "16-byte records");
+  constexpr int kWords = sizeof(T) / 16;
+  float4 w[kWords];
+  const float4 *p = reinterpret_cast<const float4 *>(&src);
+#pragma unroll
+  for (int k = 0; k < kWords; ++k) w[k] = p[k];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
 // Staging of one tile (entries t0 .. t0 + nf - 1 of chirp n) into buffer k; each of the
 // staging waves takes its share of the entries through all steps. Element e has slot e
 // (Tx) or slots_tx + e - P (Rx) in a facet's row of sh.slots; the padding slots are
@@ -120,7 +134,7 @@ __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoS
     const int i = i0 + task / E, e = task % E;
     const int slot = e < P ? e : sh.slots_tx + (e - P);  // Tx slots, then Rx slots
     const int S = sh.slots;
-    const Geo &g = sm.geo[i];
+    const Geo g = lds_copy(sm.geo[i]);  // one batch of LDS reads
     if (!g.valid) {
       for (int b = 0; b < kMfmaWaves; ++b) EP[(b * FT + i) * S + slot] = make_float2(0.0f, 0.0f);
       IR[i * S + slot] = 0.0f;
@@ -133,16 +147,11 @@ __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoS
     IR[i * S + slot] = static_cast<float>(1.0 / Rn);
     if (!rc.intra) {
       const double tau = Rn * (1.0 / kC0);
-      double psi0;
-      if (e < P) {
-        const double d = tau - g.tref_t;
-        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
-               0.5 * slope * g.tref_t * g.tref_r;
-      } else {
-        const double d = tau - g.tref_r;
-        psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
-               0.5 * slope * g.tref_t * g.tref_r;
-      }
+      // Tx element: reference delay of its own side tref_t, of the other side tref_r
+      const bool tx = e < P;
+      const double t_self = tx ? g.tref_t : g.tref_r, t_other = tx ? g.tref_r : g.tref_t;
+      double psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * t_other * (tau - t_self) -
+                    0.5 * slope * g.tref_t * g.tref_r;
       psi0 -= floor(psi0);
       double delta = rc.df * tau;
       delta -= floor(delta);
@@ -161,16 +170,21 @@ __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoS
       }
     }
   }
-  // G_f(m) for the tile's samples
-  for (int task = lane; task < kHalf * kMfmaTile; task += 64) {
-    const int i = i0 + task / kMfmaTile, j = task % kMfmaTile;
-    float2 val = g_lin(sm.glin[i], j);
-    if (rc.intra) {
-      const int jj = j % kMfmaBlk;
-      const float x = 6.283185307179586f * sm.glin[i].quad * static_cast<float>(jj * (jj - kMfmaBlk));
-      val = make_float2(fmaf(val.y, x, val.x), fmaf(-val.x, x, val.y));
+  // G_f(m) for the tile's samples: one facet at a time, its coefficients read from LDS
+  // into registers once (in one batch) rather than field by field inside the branches
+  static_assert(kMfmaTile % 64 == 0, "whole waves per facet");
+  for (int ii = 0; ii < kHalf; ++ii) {
+    const int i = i0 + ii;
+    const GLin q = lds_copy(sm.glin[i]);
+    for (int j = lane; j < kMfmaTile; j += 64) {
+      float2 val = g_lin(q, j);
+      if (rc.intra) {
+        const int jj = j % kMfmaBlk;
+        const float x = 6.283185307179586f * q.quad * static_cast<float>(jj * (jj - kMfmaBlk));
+        val = make_float2(fmaf(val.y, x, val.x), fmaf(-val.x, x, val.y));
+      }
+      G[i * kMfmaTile + j] = val;
     }
-    G[i * kMfmaTile + j] = val;
   }
 }
 
