@@ -177,16 +177,40 @@ def measure_fwd_bwd(sim, reps=3):
             "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
 
 
-def measure_batched(n_scenes=8, reps=3):
+def measure_other_kernel(sim, echo, mask, kernel, evals, reps=5):
+    """Facet-sum time and roofline of the kernel the autotuner did not pick, on the same
+    frame (median of `reps` launches after one warm-up; results compared with the main
+    kernel's to the FP32 bar)."""
+    import numpy as np
+    import torch
+    ref = echo.clone()
+    kc = KERNEL_CODES[kernel]
+    buf = torch.empty_like(echo)
+    sim.ctx.synthesize([sim.scene_ids[0]], buf, mask, kernel=kc)
+    ts = []
+    for _ in range(reps):
+        sim.ctx.synthesize([sim.scene_ids[0]], buf, mask, timing=True, kernel=kc)
+        ts.append(sim.ctx.last_timings()["facet_sum"])
+    torch.cuda.synchronize()
+    fs = float(np.median(ts))
+    d = (buf - ref).abs().pow(2).sum().sqrt() / ref.abs().pow(2).sum().sqrt()
+    return {"kernel": kernel, "facet_sum_ms": fs,
+            "roofline": roofline(kernel, FLOP_PER_EVAL * evals / (fs * 1e-3), evals, fs),
+            "rel_rms_vs_main": float(d)}
+
+
+def measure_batched(n_scenes=8, reps=3, kernel="vector"):
     """A slice of the 64-scene batched workload (seeds 400...): one persistent,
     graph-captured launch over all scenes vs one plain launch per scene (equal
-    accuracy: the per-scene results are bit-identical, checked here)."""
+    accuracy: the per-scene results are bit-identical, checked here), with the
+    facet-sum kernel of the main measurement."""
     import numpy as np
     import torch
     import scenes
     from paper_2208_10939_amd.pipeline import Simulator
     cfg = scenes.c4(n_scenes=n_scenes)
     sim = Simulator(cfg.scenes, cfg.waveform, cfg.array)
+    kc = KERNEL_CODES[kernel]
     n = len(cfg.scenes)
     plain = sim.echo_buffer(n)
     batched = sim.echo_buffer(n)
@@ -194,10 +218,11 @@ def measure_batched(n_scenes=8, reps=3):
 
     def run_plain():
         for i in range(n):
-            sim.ctx.synthesize([sim.scene_ids[i]], plain[i:i + 1], None)
+            sim.ctx.synthesize([sim.scene_ids[i]], plain[i:i + 1], None, kernel=kc)
 
     def run_batched():
-        sim.ctx.synthesize(sim.scene_ids, batched, mask, persistent=True, use_graph=True)
+        sim.ctx.synthesize(sim.scene_ids, batched, mask, persistent=True, use_graph=True,
+                           kernel=kc)
 
     times = {}
     for name, fn in (("plain", run_plain), ("batched", run_batched)):
@@ -213,7 +238,7 @@ def measure_batched(n_scenes=8, reps=3):
     lit = sum(int(m.sum()) for m in sim.masks_numpy(mask))
     evals = lit * cfg.waveform.n_samples * cfg.array.n_channels
     same = bool(torch.equal(plain, batched))
-    return {"scenes": n, "triangles": int(sum(s.n_tris for s in cfg.scenes)),
+    return {"scenes": n, "triangles": int(sum(s.n_tris for s in cfg.scenes)), "kernel": kernel,
             "plain_ms": times["plain"], "batched_ms": times["batched"],
             "plain_evals_per_s": evals / (times["plain"] * 1e-3),
             "batched_evals_per_s": evals / (times["batched"] * 1e-3),
@@ -338,10 +363,13 @@ def main():
         "roofline": roofline(kernel, achieved, evals_per_step, fs_ms),
     }
     if not args.no_extras:
+        other = "vector" if kernel == "matrix" else "matrix"
+        _log(f"bench: the {other} kernel's facet sum on the same frame")
+        out["other_kernel"] = measure_other_kernel(sim, echo, mask, other, evals_per_step)
         _log("bench: forward + backward")
         out["fwd_bwd"] = measure_fwd_bwd(sim)
         _log("bench: batched vs plain (8 scenes of the 64-scene workload)")
-        out["batched_vs_plain"] = measure_batched()
+        out["batched_vs_plain"] = measure_batched(kernel=kernel)
     if not args.no_cpu:
         _log("bench: timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -262,7 +262,7 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
   wave_lds_sync_adj();
   for (int task = lane; task < kHalf * E; task += 64) {
     const int i = i0 + task / E, e = task % E;
-    const Geo &g = geo[i];
+    const Geo g = lds_copy(geo[i]);  // one batch of LDS reads
     float2 *Ue = tl.U + (i * E + e) * sh.B_w;
     if (!g.valid) {
       for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = make_float2(0.0f, 0.0f);
@@ -278,18 +278,13 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
     const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
     const double inv_rd = 1.0 / Rn;
     const double tau = Rn * (1.0 / kC0);
-    double psi0, offv;
-    if (e < P) {
-      const double d = tau - g.tref_t;
-      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
-             0.5 * slope * g.tref_t * g.tref_r;
-      offv = sh.two_pi_slope * d;
-    } else {
-      const double d = tau - g.tref_r;
-      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
-             0.5 * slope * g.tref_t * g.tref_r;
-      offv = d;
-    }
+    // Tx element: reference delay of its own side tref_t, of the other side tref_r
+    const bool tx = e < P;
+    const double t_self = tx ? g.tref_t : g.tref_r, t_other = tx ? g.tref_r : g.tref_t;
+    const double d = tau - t_self;
+    double psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * t_other * d -
+                  0.5 * slope * g.tref_t * g.tref_r;
+    const double offv = tx ? sh.two_pi_slope * d : d;
     psi0 -= floor(psi0);
     double delta = rc.df * tau;
     delta -= floor(delta);
@@ -302,13 +297,18 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
                                    static_cast<float>(dz * inv_rd), inv_r);
     tl.tau[i * E + e] = static_cast<float>(tau);
   }
-  for (int task = lane; task < kHalf * sh.M_t; task += 64) {
-    const int i = i0 + task / sh.M_t, j = task % sh.M_t;
-    float2 gv, dv[3];
-    g_lin_grad(glin[i], j, gv, dv);
-    float4 *dst = tl.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;
-    dst[0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
-    dst[1] = make_float4(dv[1].x, dv[1].y, dv[2].x, dv[2].y);
+  // G and its node derivatives, one facet at a time: its record is read from LDS into
+  // registers once (in one batch), not field by field inside the branches
+  for (int ii = 0; ii < kHalf; ++ii) {
+    const int i = i0 + ii;
+    const GLin q = lds_copy(glin[i]);
+    for (int j = lane; j < sh.M_t; j += 64) {
+      float2 gv, dv[3];
+      g_lin_grad(q, j, gv, dv);
+      float4 *dst = tl.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;
+      dst[0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
+      dst[1] = make_float4(dv[1].x, dv[1].y, dv[2].x, dv[2].y);
+    }
   }
 }
 

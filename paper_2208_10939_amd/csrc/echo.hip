@@ -138,7 +138,7 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
   // B1: per element distance, phases in FP64 reduced to turns
   for (int task = lane; task < kHalf * E; task += 64) {
     const int i = i0 + task / E, e = task % E;
-    const Geo &g = geo[i];
+    const Geo g = lds_copy(geo[i]);  // one batch of LDS reads
     // block-major [B_w][FT][E]: the lanes of a wave (consecutive channels) then read
     // consecutive Rx elements of one block
     C *Ue = tl.U + i * E + e;
@@ -157,18 +157,13 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
     const double dz = sm.elem[3 * e + 2] - g.c[2];
     const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
     const double tau = Rn * (1.0 / kC0);
-    double psi0, offv;
-    if (e < P) {
-      const double d = tau - g.tref_t;
-      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_r * d -
-             0.5 * slope * g.tref_t * g.tref_r;
-      offv = sh.two_pi_slope * d;
-    } else {
-      const double d = tau - g.tref_r;
-      psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * g.tref_t * d -
-             0.5 * slope * g.tref_t * g.tref_r;
-      offv = d;
-    }
+    // Tx element: reference delay of its own side tref_t, of the other side tref_r
+    const bool tx = e < P;
+    const double t_self = tx ? g.tref_t : g.tref_r, t_other = tx ? g.tref_r : g.tref_t;
+    const double d = tau - t_self;
+    double psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * t_other * d -
+                  0.5 * slope * g.tref_t * g.tref_r;
+    const double offv = tx ? sh.two_pi_slope * d : d;
     psi0 -= floor(psi0);
     double delta = rc.df * tau;
     delta -= floor(delta);
@@ -197,40 +192,48 @@ __device__ void stage_tile(const DevScene &sc, const RadarConst &rc, const EchoS
     }
     tl.off[i * E + e] = static_cast<R>(offv);
   }
-  // B2: G_f(m) for the tile's samples
-  for (int task = lane; task < kHalf * sh.M_t; task += 64) {
-    const int i = i0 + task / sh.M_t, j = task % sh.M_t;
-    C val = {R(0), R(0)};
-    if constexpr (EchoLayout<R, MB, FT>::kRotated) {
-      val = g_lin(glin[i], j);
-      if (rc.intra) {
-        // deviation of the phase from its chord over the block: exp(-j 2 pi q jj (jj - MB))
-        // to first order (|2 pi q jj (jj - MB)| <= ~2e-4 rad)
-        const int jj = j % MB;
-        const float x = 6.283185307179586f * glin[i].quad * static_cast<float>(jj * (jj - MB));
-        val = {fma_r(val.y, x, val.x), fma_r(-val.x, x, val.y)};
+  // B2: G_f(m) for the tile's samples, one entry at a time: its record is read from LDS
+  // into registers once (in one batch), not field by field inside the branches
+  for (int ii = 0; ii < kHalf; ++ii) {
+    const int i = i0 + ii;
+    GLin q{};
+    Geo g{};
+    if constexpr (EchoLayout<R, MB, FT>::kRotated)
+      q = lds_copy(glin[i]);
+    else
+      g = lds_copy(geo[i]);
+    for (int j = lane; j < sh.M_t; j += 64) {
+      C val = {R(0), R(0)};
+      if constexpr (EchoLayout<R, MB, FT>::kRotated) {
+        val = g_lin(q, j);
+        if (rc.intra) {
+          // deviation of the phase from its chord over the block:
+          // exp(-j 2 pi q jj (jj - MB)) to first order (|2 pi q jj (jj - MB)| <= ~2e-4 rad)
+          const int jj = j % MB;
+          const float x = 6.283185307179586f * q.quad * static_cast<float>(jj * (jj - MB));
+          val = {fma_r(val.y, x, val.x), fma_r(-val.x, x, val.y)};
+        }
+      } else {
+        if (g.valid) {
+          const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
+          const double s = fm / kC0;  // turns per metre
+          const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
+          const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
+          val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
+        }
       }
-    } else {
-      const Geo &g = geo[i];
-      if (g.valid) {
-        const double fm = rc.f0 + static_cast<double>(m_tile0 + j) * rc.df;
-        const double s = fm / kC0;  // turns per metre
-        const C ph = phi_turns<R>(s * g.beta[0], s * g.beta[1], s * g.beta[2]);
-        const R ar = static_cast<R>(g.amp_re), ai = static_cast<R>(g.amp_im);
-        val = {ar * ph.x - ai * ph.y, ar * ph.y + ai * ph.x};
+      tl.G[i * sh.M_t + j] = val;
+      if constexpr (EchoLayout<R, MB, FT>::kRotated) {
+        // (-j)^(j mod 4): block starts are multiples of 4 samples
+        C v1;
+        switch (j & 3) {
+          case 0: v1 = val; break;
+          case 1: v1 = {val.y, -val.x}; break;
+          case 2: v1 = {-val.x, -val.y}; break;
+          default: v1 = {-val.y, val.x}; break;
+        }
+        tl.G1[i * sh.M_t + j] = v1;
       }
-    }
-    tl.G[i * sh.M_t + j] = val;
-    if constexpr (EchoLayout<R, MB, FT>::kRotated) {
-      // (-j)^(j mod 4): block starts are multiples of 4 samples
-      C v1;
-      switch (j & 3) {
-        case 0: v1 = val; break;
-        case 1: v1 = {val.y, -val.x}; break;
-        case 2: v1 = {-val.x, -val.y}; break;
-        default: v1 = {-val.y, val.x}; break;
-      }
-      tl.G1[i * sh.M_t + j] = v1;
     }
   }
 }
@@ -325,62 +328,76 @@ __device__ inline void sum_tile(const RadarConst &rc, const EchoShape &sh,
 // (whole waves each, so the accumulators are not live in the staging code); both pass
 // the same sequence of workgroup barriers: one per tile, then two per output chunk.
 // The tile count depends only on the chirp's lit count.
-template <typename R, int MB, int FT>
-__device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
-                          EchoSmem<R, MB, FT> &sm, int n, int mt, int ot) {
+// Output of one work item in chunks of kOut samples: the accumulating threads park kOut
+// values each in LDS, then consecutive lanes write consecutive samples of one channel
+// row, so a wave writes whole 128-byte runs instead of one 8-byte value per row.
+template <typename R, int MB>
+__device__ inline void store_chunk(const RadarConst &rc, const EchoShape &sh,
+                                   const typename Cx<R>::T *stage, typename Cx<R>::T *echo_out,
+                                   int n, int ot, int m0) {
   using C = typename Cx<R>::T;
   constexpr int kOut = (MB < 16) ? MB : 16;
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
+  for (int e = threadIdx.x; e < sh.O_w * kOut; e += blockDim.x) {
+    const int oo = ot * sh.O_w + e / kOut;
+    const int m = m0 + e % kOut;
+    if (oo < sh.O && m < rc.M) {
+      C *dst = echo_out + (static_cast<int64_t>(oo) * rc.N + n) * rc.M + m;
+      if (!sh.accumulate) {
+        *dst = stage[e];
+      } else {
+        // a further path type of the same echo: dst += gamma x value
+        const C v = stage[e], d = *dst;
+        const R gr = static_cast<R>(sh.gamma_re), gi = static_cast<R>(sh.gamma_im);
+        *dst = {d.x + (gr * v.x - gi * v.y), d.y + (gr * v.y + gi * v.x)};
+      }
+    }
+  }
+}
+
+// One work item (chirp n, sample tile mt, channel tile ot), split in its two roles. The
+// staging waves and the accumulating waves pass the same barriers: one per tile, then
+// two per output chunk.
+template <typename R, int MB, int FT>
+__device__ void echo_stage_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                                EchoSmem<R, MB, FT> &sm, int n, int mt, int ot, int st) {
+  using C = typename Cx<R>::T;
+  constexpr int kOut = (MB < 16) ? MB : 16;
   const int m_tile0 = mt * sh.M_t;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t total = cnt + sc.n_points;
   const int32_t n_tiles = (total + FT - 1) / FT;
-  C *stage = sm.tile(0).G;  // output staging: the layout reserves O_w x kOut values here
+  const C *stage = sm.tile(0).G;  // output staging: the layout reserves O_w x kOut values here
   C *echo_out = static_cast<C *>(sc.echo);
-  // Output in chunks of kOut samples: the accumulating threads park kOut values each in
-  // LDS, then consecutive lanes write consecutive samples of one channel row, so a wave
-  // writes whole 128-byte runs instead of one 8-byte value per row.
-  auto store_chunk = [&](int m0) {
-    for (int e = tid; e < sh.O_w * kOut; e += nthr) {
-      const int oo = ot * sh.O_w + e / kOut;
-      const int m = m0 + e % kOut;
-      if (oo < sh.O && m < rc.M) {
-        C *dst = echo_out + (static_cast<int64_t>(oo) * rc.N + n) * rc.M + m;
-        if (!sh.accumulate) {
-          *dst = stage[e];
-        } else {
-          // a further path type of the same echo: dst += gamma x value
-          const C v = stage[e], d = *dst;
-          const R gr = static_cast<R>(sh.gamma_re), gi = static_cast<R>(sh.gamma_im);
-          *dst = {d.x + (gr * v.x - gi * v.y), d.y + (gr * v.y + gi * v.x)};
-        }
-      }
-    }
-  };
-
-  if (tid >= sh.n_compute) {
-    const int st = tid - sh.n_compute;
-    if (n_tiles > 0)
-      stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(0), n, cnt, 0, min(FT, total), m_tile0, st);
-    for (int32_t k = 0; k < n_tiles; ++k) {
-      // tile k is staged in buffer k & 1; buffer (k + 1) & 1 was consumed in step k - 1
-      __syncthreads();
-      const int32_t t1 = (k + 1) * FT;
-      if (t1 < total)
-        stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile((k & 1) ^ 1), n, cnt, t1,
-                              min(FT, total - t1), m_tile0, st);
-    }
-    for (int bb = 0; bb < sh.B_w; ++bb) {
-      for (int jc = 0; jc < MB; jc += kOut) {
-        __syncthreads();
-        __syncthreads();
-        store_chunk(m_tile0 + bb * MB + jc);
-      }
-    }
-    return;
+  if (n_tiles > 0)
+    stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile(0), n, cnt, 0, min(FT, total), m_tile0, st);
+  for (int32_t k = 0; k < n_tiles; ++k) {
+    // tile k is staged in buffer k & 1; buffer (k + 1) & 1 was consumed in step k - 1
+    __syncthreads();
+    const int32_t t1 = (k + 1) * FT;
+    if (t1 < total)
+      stage_tile<R, MB, FT>(sc, rc, sh, sm, sm.tile((k & 1) ^ 1), n, cnt, t1,
+                            min(FT, total - t1), m_tile0, st);
   }
+  for (int bb = 0; bb < sh.B_w; ++bb) {
+    for (int jc = 0; jc < MB; jc += kOut) {
+      __syncthreads();
+      __syncthreads();
+      store_chunk<R, MB>(rc, sh, stage, echo_out, n, ot, m_tile0 + bb * MB + jc);
+    }
+  }
+}
 
+template <typename R, int MB, int FT>
+__device__ void echo_compute_item(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                                  EchoSmem<R, MB, FT> &sm, int n, int mt, int ot) {
+  using C = typename Cx<R>::T;
+  constexpr int kOut = (MB < 16) ? MB : 16;
+  const int tid = threadIdx.x;
+  const int m_tile0 = mt * sh.M_t;
+  const int32_t total = sc.vis_cnt[n] + sc.n_points;
+  const int32_t n_tiles = (total + FT - 1) / FT;
+  C *stage = sm.tile(0).G;
+  C *echo_out = static_cast<C *>(sc.echo);
   const int Q = rc.Q;
   const int ol = tid % sh.O_w;
   const int b = tid / sh.O_w;
@@ -404,7 +421,7 @@ __device__ void echo_item(const DevScene &sc, const RadarConst &rc, const EchoSh
         for (int j = 0; j < kOut; ++j) stage[ol * kOut + j] = acc[jc + j];
       }
       __syncthreads();
-      store_chunk(m_tile0 + bb * MB + jc);
+      store_chunk<R, MB>(rc, sh, stage, echo_out, n, ot, m_tile0 + bb * MB + jc);
     }
   }
 }
@@ -420,7 +437,11 @@ __global__ void __launch_bounds__(512) echo_kernel(DevScene sc, RadarConst rc, c
   const int per_chirp = sh.m_tiles * sh.o_tiles;
   const int n = blockIdx.x / per_chirp;
   const int r = blockIdx.x % per_chirp;
-  echo_item<R, MB, FT>(sc, rc, sh, sm, n, r / sh.o_tiles, r % sh.o_tiles);
+  if (threadIdx.x >= sh.n_compute)
+    echo_stage_item<R, MB, FT>(sc, rc, sh, sm, n, r / sh.o_tiles, r % sh.o_tiles,
+                               threadIdx.x - sh.n_compute);
+  else
+    echo_compute_item<R, MB, FT>(sc, rc, sh, sm, n, r / sh.o_tiles, r % sh.o_tiles);
 }
 
 // Persistent form: a grid sized to the machine drains a queue of work items
@@ -435,15 +456,28 @@ __global__ void __launch_bounds__(512) echo_persistent_kernel(const DevScene *sc
   EchoSmem<R, MB, FT> sm;
   sm.carve(echo_smem, sh);
   for (int i = threadIdx.x; i < 3 * sh.E; i += blockDim.x) sm.elem[i] = elem[i];
-  while (true) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
-    __syncthreads();
-    const int32_t it = s_item;
-    if (it >= n_items) break;  // every workgroup reaches this once the queue is drained
-    const int4 w = items[it];
-    const DevScene sc = scenes[w.x];
-    echo_item<R, MB, FT>(sc, rc, sh, sm, w.y, w.z, w.w);
+  // each role runs its own loop (so that neither holds the other's values); both pass the
+  // same barriers per item
+  if (threadIdx.x >= sh.n_compute) {
+    const int st = threadIdx.x - sh.n_compute;
+    while (true) {
+      __syncthreads();
+      if (st == 0) s_item = atomicAdd(queue, 1);
+      __syncthreads();
+      const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+      if (it >= n_items) break;  // every workgroup reaches this once the queue is drained
+      const int4 w = items[it];
+      echo_stage_item<R, MB, FT>(scenes[w.x], rc, sh, sm, w.y, w.z, w.w, st);
+    }
+  } else {
+    while (true) {
+      __syncthreads();
+      __syncthreads();
+      const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+      if (it >= n_items) break;
+      const int4 w = items[it];
+      echo_compute_item<R, MB, FT>(scenes[w.x], rc, sh, sm, w.y, w.z, w.w);
+    }
   }
 }
 

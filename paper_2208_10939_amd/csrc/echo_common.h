@@ -39,6 +39,20 @@ struct alignas(16) Geo {
   int32_t valid, pad;
 };
 
+// A copy of an LDS record in registers, read as whole 16-byte words in one batch.
+template <typename T>
+__device__ inline T lds_copy(const T &src) {
+  static_assert(sizeof(T) % 16 == 0 && alignof(T) >= 16, "16-byte records");
+  constexpr int kWords = sizeof(T) / 16;
+  float4 w[kWords];
+  const float4 *p = reinterpret_cast<const float4 *>(&src);
+#pragma unroll
+  for (int k = 0; k < kWords; ++k) w[k] = p[k];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
 __device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 

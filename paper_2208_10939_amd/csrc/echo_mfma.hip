@@ -13,13 +13,16 @@
 // (block k = lanes 4k..4k+3: A lane 4k+i is row i, B lane 4k+j is column j, result
 // register i of lane 4k+j is element (i, j)). Here block k = sample m_w + k, rows = 4 Tx
 // elements of a Tx tile, columns = 4 Rx elements of an Rx tile. Per facet a lane
-// evaluates its PT Tx and QT Rx element phasors at its sample (one FMA on FP32 phases
-// reduced per 16-sample block in FP64, hardware sine/cosine), multiplies the Tx ones by
-// G_f(m), and the wave issues 4 MFMAs per (Tx tile, Rx tile) for the complex product:
-//   Re += Ar Br + Ai (-Bi),  Im += Ar Bi + Ai Br.
+// evaluates its PT Tx and QT Rx element phasors at its sample (one FMA on an FP32 phase
+// taken at the block centre after an FP64 reduction, hardware sine/cosine), multiplies
+// the Tx ones by G_f(m), and the wave issues 4 MFMAs per (Tx tile, Rx tile) for the
+// complex product:
+//   Re += Ar Br + (-Ai) Bi,  Im += Ai Br + Ar Bi.
 // A workgroup covers one chirp and 128 samples with eight accumulating waves (16 samples
-// each) and two staging waves that fill double-buffered LDS tiles of FT facets (FP64
-// geometry, element phases per block, G(m)), as in the VALU kernel.
+// each) and four staging waves (one per SIMD) that fill double-buffered LDS tiles of FT
+// facets (FP64 geometry, element phases per block, G(m)), as in the VALU kernel. MFMAs
+// and vector instructions of one wave are issued in separate groups: interleaved, they
+// cost extra issue cycles on this GPU.
 #include "echo_common.h"
 
 namespace rsim {
@@ -89,20 +92,6 @@ __device__ inline void mfma_lds_sync() {
 
 __device__ inline float centred(double t) { return static_cast<float>(t - rint(t)); }
 
-// A copy of an LDS record in registers, read as whole 16-byte words in one batch.
-template <typename T>
-__device__ inline T lds_copy(const T &src) {
-  static_assert(sizeof(T) % 16 == 0 && alignof(T) >= 16, "16-byte records");
-  constexpr int kWords = sizeof(T) / 16;
-  float4 w[kWords];
-  const float4 *p = reinterpret_cast<const float4 *>(&src);
-#pragma unroll
-  for (int k = 0; k < kWords; ++k) w[k] = p[k];
-  T out;
-  __builtin_memcpy(&out, w, sizeof(T));
-  return out;
-}
-
 // Staging of one tile (entries t0 .. t0 + nf - 1 of chirp n) into buffer k; each of the
 // staging waves takes its share of the entries through all steps. Element e has slot e
 // (Tx) or slots_tx + e - P (Rx) in a facet's row of sh.slots; the padding slots are
@@ -144,7 +133,7 @@ __device__ void mfma_stage(const DevScene &sc, const RadarConst &rc, const EchoS
     const double dy = sm.elem[3 * e + 1] - g.c[1];
     const double dz = sm.elem[3 * e + 2] - g.c[2];
     const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
-    IR[i * S + slot] = static_cast<float>(1.0 / Rn);
+    IR[i * S + slot] = __builtin_amdgcn_rcpf(static_cast<float>(Rn));  // amplitude only: 1 ulp
     if (!rc.intra) {
       const double tau = Rn * (1.0 / kC0);
       // Tx element: reference delay of its own side tref_t, of the other side tref_r
