@@ -49,6 +49,8 @@ def _sampled_parity(sim, sc, wf, arr, chirps, channels, samples, scene_index=0, 
 
 
 def test_single_vehicle_50k_full_size():
+    """Both facet-sum kernels (the bench times the autotuner's pick, the other one is
+    reported beside it) against the same oracle samples."""
     import torch
     from paper_2208_10939_amd.pipeline import Simulator
     _log("case 50k-triangle vehicle, 192 ch x 256 x 128 (bench launch configuration)")
@@ -57,7 +59,8 @@ def test_single_vehicle_50k_full_size():
     sim = Simulator([sc], wf, arr)
     mask = sim.mask_buffer()
     sim.last_mask = mask
-    Ht = sim.synthesize(mask=mask)
+    Ht = sim.synthesize(mask=mask, kernel=1)
+    Hm = sim.synthesize(mask=mask, kernel=2).cpu().numpy()[0]
     rdm = sim.form_rdm(Ht)
     torch.cuda.synchronize()
     H = Ht.cpu().numpy()[0]
@@ -66,8 +69,16 @@ def test_single_vehicle_50k_full_size():
     channels = np.array([0, 37, 95, 128, 160, 191])
     err, om, amb = _sampled_parity(sim, sc, wf, arr, chirps, channels, np.arange(256), echo=H,
                                    gmask_rows=gm)
-    _log(f"  lit={om.sum(1)} ambiguous={amb.sum()} echo rel_rms={err:.3e}")
+    _log(f"  lit={om.sum(1)} ambiguous={amb.sum()} vector-unit echo rel_rms={err:.3e}")
     assert err <= TOL
+    if not (gm != om).any():  # same lit sets: the matrix-core echo against the same samples
+        mask_all = np.zeros((wf.n_chirps, om.shape[1]), bool)
+        mask_all[np.asarray(chirps)] = om
+        Ho = oracle.synthesize(sc, wf, arr, mask=mask_all, chirps=chirps, channels=channels,
+                               samples=np.arange(256))
+        errm = rel_rms(Hm[np.ix_(channels, chirps, np.arange(256))], Ho)
+        _log(f"  matrix-core echo rel_rms={errm:.3e}")
+        assert errm <= TOL
     # Parseval over every chirp and channel of the RDM (no window, unnormalised FFTs)
     P = rdm.double().sum().item()
     E = (Ht.abs().double() ** 2).sum().item() * wf.n_samples * wf.n_chirps
@@ -102,13 +113,14 @@ def test_batched_64_scenes_equals_plain_and_oracle():
     sim = Simulator(cfg.scenes, wf, arr)
     n = len(cfg.scenes)
     mask = sim.mask_buffer()
-    batched = sim.synthesize(mask=mask, persistent=True, use_graph=True)
-    torch.cuda.synchronize()
-    same = True
-    for i in range(n):
-        one = sim.synthesize([i])
-        same &= bool(torch.equal(one[0], batched[i]))
-    assert same
+    for kernel in (1, 2):  # vector units, then matrix cores (kept in `batched`)
+        batched = sim.synthesize(mask=mask, persistent=True, use_graph=True, kernel=kernel)
+        torch.cuda.synchronize()
+        same = True
+        for i in range(n):
+            one = sim.synthesize([i], kernel=kernel)
+            same &= bool(torch.equal(one[0], batched[i]))
+        assert same, f"kernel {kernel}: persistent and plain differ"
     masks = sim.masks_numpy(mask)
     for i in (int(np.argmin([s.n_tris for s in cfg.scenes])), 7):
         sc = cfg.scenes[i]
