@@ -152,6 +152,131 @@ __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
   return false;
 }
 
+// Any triangle of the leaf hit by o + t d1 or o + t d2, t in [kTEps, 1 - kTEps]?
+__device__ inline bool leaf_hit2(const float4 *leaf, int32_t ref, float ox, float oy, float oz,
+                                 const float d[2][3], int32_t skip) {
+  uint32_t code = static_cast<uint32_t>(-ref - 1);
+  uint32_t first = code >> 4, count = code & 15u;
+  for (uint32_t k = 0; k < count; ++k) {
+    const float4 a = leaf[3 * (first + k) + 0];
+    const float4 b = leaf[3 * (first + k) + 1];
+    const float4 c = leaf[3 * (first + k) + 2];
+    if (__float_as_int(c.y) == skip) continue;
+    const float e1x = a.w, e1y = b.x, e1z = b.y;
+    const float e2x = b.z, e2y = b.w, e2z = c.x;
+    const float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
+    const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const float dx = d[r][0], dy = d[r][1], dz = d[r][2];
+      const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+      const float det = e1x * px + e1y * py + e1z * pz;
+      if (det == 0.0f) continue;
+      const float inv = 1.0f / det;
+      const float u = (sx * px + sy * py + sz * pz) * inv;
+      if (!(u >= 0.0f && u <= 1.0f)) continue;
+      const float v = (dx * qx + dy * qy + dz * qz) * inv;
+      if (!(v >= 0.0f && u + v <= 1.0f)) continue;
+      const float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+      if (t >= kTEps && t <= 1.0f - kTEps) return true;
+    }
+  }
+  return false;
+}
+
+// Any-hit traversal of one BLAS for the two body-frame segments o -> o + d1 and
+// o -> o + d2 together: a node is entered when either segment meets its box, so the two
+// nearly parallel shadow rays of a facet share every node fetch.
+__device__ bool blas_occluded2(const BvhNode *nodes, const float4 *leaf, float ox, float oy,
+                               float oz, const float d[2][3], int32_t skip, int32_t *stack,
+                               int stride) {
+  float inv[2][3];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k) inv[r][k] = safe_inv(d[r][k]);
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const BvhNode nd = nodes[node];
+    const bool h0 = box_hit(nd.lo0, nd.hi0, ox, oy, oz, inv[0][0], inv[0][1], inv[0][2]) ||
+                    box_hit(nd.lo0, nd.hi0, ox, oy, oz, inv[1][0], inv[1][1], inv[1][2]);
+    const bool h1 = box_hit(nd.lo1, nd.hi1, ox, oy, oz, inv[0][0], inv[0][1], inv[0][2]) ||
+                    box_hit(nd.lo1, nd.hi1, ox, oy, oz, inv[1][0], inv[1][1], inv[1][2]);
+    int32_t next = -1;
+    if (h0) {
+      if (nd.c0 < 0) {
+        if (leaf_hit2(leaf, nd.c0, ox, oy, oz, d, skip)) return true;
+      } else {
+        next = nd.c0;
+      }
+    }
+    if (h1) {
+      if (nd.c1 < 0) {
+        if (leaf_hit2(leaf, nd.c1, ox, oy, oz, d, skip)) return true;
+      } else if (next >= 0) {
+        stack[sp * stride] = nd.c1;  // depth <= kBvhMaxDepth < kBvhStack
+        ++sp;
+      } else {
+        next = nd.c1;
+      }
+    }
+    if (next < 0) {
+      if (sp == 0) return false;
+      --sp;
+      next = stack[sp * stride];
+    }
+    node = next;
+  }
+}
+
+// Is either world segment c -> s1 or c -> s2 blocked by a triangle of the scene at time t
+// (triangle `self_local` of instance `self_inst` excluded)? Same decisions as two calls
+// of segment_blocked joined by "or".
+__device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], const double s1[3],
+                             const double s2[3], int self_inst, int32_t self_local,
+                             int32_t *stack, int stride) {
+  const double dw[2][3] = {{s1[0] - c[0], s1[1] - c[1], s1[2] - c[2]},
+                           {s2[0] - c[0], s2[1] - c[1], s2[2] - c[2]}};
+  for (int j = 0; j < sc.n_inst; ++j) {
+    const DevInstance &I = sc.inst[j];
+    if (!I.has_bvh) continue;
+    double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
+    // world-space slab test of each segment against the instance box (FP64)
+    bool any = false;
+    for (int r = 0; r < 2; ++r) {
+      double tn = 0.0, tf = 1.0;
+      bool miss = false;
+      for (int k = 0; k < 3; ++k) {
+        double lo = I.box_lo[k] + p[k], hi = I.box_hi[k] + p[k];
+        if (dw[r][k] == 0.0) {
+          if (c[k] < lo || c[k] > hi) miss = true;
+          continue;
+        }
+        double a = (lo - c[k]) / dw[r][k], b = (hi - c[k]) / dw[r][k];
+        tn = fmax(tn, fmin(a, b));
+        tf = fmin(tf, fmax(a, b));
+      }
+      any = any || !(miss || tn > tf);
+    }
+    if (!any) continue;
+    // body frame: x_body = R^T (x - p)
+    const double *R = I.rot;
+    double q0 = c[0] - p[0], q1 = c[1] - p[1], q2 = c[2] - p[2];
+    float ox = static_cast<float>(R[0] * q0 + R[3] * q1 + R[6] * q2);
+    float oy = static_cast<float>(R[1] * q0 + R[4] * q1 + R[7] * q2);
+    float oz = static_cast<float>(R[2] * q0 + R[5] * q1 + R[8] * q2);
+    float d[2][3];
+    for (int r = 0; r < 2; ++r) {
+      d[r][0] = static_cast<float>(R[0] * dw[r][0] + R[3] * dw[r][1] + R[6] * dw[r][2]);
+      d[r][1] = static_cast<float>(R[1] * dw[r][0] + R[4] * dw[r][1] + R[7] * dw[r][2]);
+      d[r][2] = static_cast<float>(R[2] * dw[r][0] + R[5] * dw[r][1] + R[8] * dw[r][2]);
+    }
+    int32_t skip = (j == self_inst) ? self_local : -1;
+    if (blas_occluded2(I.nodes, I.leaf, ox, oy, oz, d, skip, stack, stride)) return true;
+  }
+  return false;
+}
+
 // One side (phase centre E, facing value fe = n . (E - c)) of a facet: *direct when it
 // faces E and centroid -> E is clear; *reflected when the centroid lies above the ground
 // plane, the facet faces the image E' and both legs centroid -> S -> E are clear, S the
@@ -206,10 +331,8 @@ __global__ void __launch_bounds__(128) vis_kernel(DevScene sc, RadarConst rc) {
     double fr = nx * (rc.rx_c[0] - c[0]) + ny * (rc.rx_c[1] - c[1]) + nz * (rc.rx_c[2] - c[2]);
     int32_t *stk = vis_stack + threadIdx.x;
     if (!rc.bounce) {
-      if (nonzero && ft > 0.0 && fr > 0.0) {
-        lit = !segment_blocked(sc, t, c, rc.tx_c, ii, lt, stk, blockDim.x) &&
-              !segment_blocked(sc, t, c, rc.rx_c, ii, lt, stk, blockDim.x);
-      }
+      if (nonzero && ft > 0.0 && fr > 0.0)
+        lit = !pair_blocked(sc, t, c, rc.tx_c, rc.rx_c, ii, lt, stk, blockDim.x);
     } else if (nonzero) {
       // per side: direct (faces E, centroid -> E clear) and reflected on the ground plane;
       // path type k takes the transmit side (k & 1) and the receive side (k >> 1)
