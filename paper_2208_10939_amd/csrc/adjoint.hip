@@ -10,7 +10,7 @@
 //   dL/do     = sum Re(y) / o,            dL/dA = sum Re(y) / A,
 //   dL/db_i   = sum Re(D_i w),  D_i = j o A k_m dPhi/da_i / (2 pi),
 //   dL/dR_p   = sum_q,m [ (2 pi / c)(f_m - slope tau) Im y - Re y / R_p ]  (same for R_q).
-// The adjoint facet-sum kernel forms these sums (21 VALU ops per evaluation) and
+// The adjoint facet-sum kernel forms these sums (20 VALU ops per evaluation) and
 // reduces them over its channels with wave shuffles in a fixed order; a second
 // kernel applies the FP64 chain rule from (o, A, b, centroid) to the three world
 // vertices; a third gathers per-vertex gradients through a vertex -> (triangle,
@@ -451,9 +451,9 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
             const float4 g0 = ca[2 * jj], g1 = ca[2 * jj + 1];  // (G, D0), (D1, D2)
             const float2 w = make_float2(fma_r(gq[j].x, z.x, -gq[j].y * z.y),
                                          fma_r(gq[j].x, z.y, gq[j].y * z.x));
-            const float yx = fma_r(g0.x, w.x, -g0.y * w.y);
+            // Re y straight into its sum (two FMAs); Im y is kept for the two sums it feeds
+            s0 = fma_r(g0.x, w.x, fma_r(-g0.y, w.y, s0));
             const float yy = fma_r(g0.x, w.y, g0.y * w.x);
-            s0 += yx;
             s1 += yy;
             s2 = fma_r(static_cast<float>(j), yy, s2);
             a0 = fma_r(g0.z, w.x, fma_r(-g0.w, w.y, a0));
