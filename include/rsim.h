@@ -229,6 +229,15 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                       const uint32_t *vis_mask, float *const *grad_verts, int32_t n_meshes,
                       double *grad_vel, void *hip_stream);
 
+/* Facet-sum kernel of rsim_backward (Sections 2.2, 3.2; eqs. (7), (9)-(13), differentiated):
+ * RSIM_KERNEL_AUTO (default) takes the matrix cores when the array allows them (the same
+ * eligibility as rsim_opts.kernel: |2 pi slope d_p e_q| <= 1e-5 rad, P <= 12, Q <= 16) and
+ * the vector units otherwise; RSIM_KERNEL_VECTOR always the vector units;
+ * RSIM_KERNEL_MATRIX the matrix cores, rsim_backward then failing with ERANGE on an
+ * ineligible array. EINVAL for another value. Both give the same gradients to FP32
+ * rounding and the dropped cross term (relative <= 1e-5). */
+int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel);
+
 /* Gradient of L with respect to the echo given dL/dP of the power RDM P = |Y|^2 and
  * the Y of the forward call (FP32): dL/dY = 2 (dL/dP) Y, then the adjoint of the
  * Doppler and range transforms (Section 3.3).

@@ -121,6 +121,7 @@ struct rsim_ctx {
   int cu_count = 0;
   size_t max_lds = 0;
   std::map<std::tuple<int, int, int>, TunedShape> tuned;  // (M, O, precision) -> shape
+  int32_t bwd_kernel = RSIM_KERNEL_AUTO;  // facet-sum kernel of rsim_backward
   // adjoint work buffers
   float *adj_partial = nullptr, *adj_gxw = nullptr;
   double *adj_vpart = nullptr;
@@ -1051,6 +1052,14 @@ int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double g
   return RSIM_OK;
 }
 
+int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (kernel < RSIM_KERNEL_AUTO || kernel > RSIM_KERNEL_MATRIX)
+    return fail(ctx, RSIM_EINVAL, "rsim_set_backward_kernel: unknown kernel %d", kernel);
+  ctx->bwd_kernel = kernel;
+  return RSIM_OK;
+}
+
 int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes, void *echo,
                         uint32_t *vis_mask, void *hip_stream, const rsim_opts *opts) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
@@ -1180,11 +1189,30 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   if ((rc = need_device(ctx))) return rc;
   SceneRec &sc = ctx->scenes[scene_id];
   if ((rc = ensure_scene_device(ctx, sc))) return rc;
-  EchoShape sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads);
-  while (sh.B_w > 1 && adjoint_smem_bytes(sh) > ctx->max_lds)
-    sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads, sh.B_w - 1);
-  if (adjoint_smem_bytes(sh) > ctx->max_lds)
-    return fail(ctx, RSIM_ERANGE, "adjoint tile needs %zu bytes of LDS", adjoint_smem_bytes(sh));
+  // matrix cores when the array allows them (unless the vector units are asked for)
+  const char *why = matrix_ineligible(ctx, rcn, RSIM_FP32_PHASE64);
+  if (ctx->bwd_kernel == RSIM_KERNEL_MATRIX && why)
+    return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", why);
+  const bool matrix = !why && ctx->bwd_kernel != RSIM_KERNEL_VECTOR &&
+                      adjoint_mfma_smem_bytes(rcn.P, rcn.Q, rcn.P + rcn.Q) <= ctx->max_lds;
+  EchoShape sh{};
+  if (matrix) {
+    sh.O = rcn.P * rcn.Q;
+    sh.E = rcn.P + rcn.Q;
+    sh.O_w = sh.O;
+    sh.o_tiles = 1;
+    sh.B_w = 1;
+    sh.M_t = adjoint_mfma_tile_m();
+    sh.m_tiles = (rcn.M + sh.M_t - 1) / sh.M_t;
+    sh.n_compute = 256;
+    sh.two_pi_slope = 2.0 * kPi * rcn.slope;
+  } else {
+    sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads);
+    while (sh.B_w > 1 && adjoint_smem_bytes(sh) > ctx->max_lds)
+      sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads, sh.B_w - 1);
+    if (adjoint_smem_bytes(sh) > ctx->max_lds)
+      return fail(ctx, RSIM_ERANGE, "adjoint tile needs %zu bytes of LDS", adjoint_smem_bytes(sh));
+  }
   const int64_t F = sc.n_facets, N = rcn.N;
   size_t vmax = 1;
   for (const InstRec &r : sc.inst) vmax = std::max(vmax, ctx->meshes[r.mesh].verts.size() / 3);
@@ -1214,7 +1242,12 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   const bool timing = ctx->timing_pending;
   HIP_TRY(ctx, launch_compact(d, rcn.N, s));
   stage_begin(ctx, timing, 5, s);
-  HIP_TRY(ctx, launch_adjoint(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial, ctx->adj_gxw, s));
+  if (matrix)
+    HIP_TRY(ctx, launch_adjoint_mfma(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial,
+                                     ctx->adj_gxw, s));
+  else
+    HIP_TRY(ctx, launch_adjoint(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial,
+                                ctx->adj_gxw, s));
   stage_end(ctx, timing, 5, s);
   stage_begin(ctx, timing, 7, s);
   for (size_t i = 0; i < sc.inst.size(); ++i) {

@@ -79,6 +79,13 @@ int noise_partials_per_cube();
 size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F);
 size_t adjoint_smem_bytes(const EchoShape &sh);
 int adjoint_tile_m();
+// adjoint on the matrix cores (FP32, separable form): one workgroup per (chirp,
+// 64-sample tile); EchoShape with o_tiles = 1 and m_tiles = ceil(M / 64)
+int adjoint_mfma_tile_m();
+size_t adjoint_mfma_smem_bytes(int P, int Q, int E);
+hipError_t launch_adjoint_mfma(const DevScene &sc, const RadarConst &rc, const double *elem,
+                               const EchoShape &sh, const void *grad_echo, float *partial,
+                               float *gxw, hipStream_t s);
 hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
                           hipStream_t s);

@@ -38,6 +38,7 @@ EXPORTS = (
     "rsim_form_rdm", "rsim_last_timings", "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
     "rsim_rdm_backward", "rsim_detect", "rsim_add_noise", "rsim_set_ground",
+    "rsim_set_backward_kernel",
 )
 
 
@@ -123,6 +124,7 @@ def lib() -> ctypes.CDLL:
         "rsim_detect": ([vp, vp, vp, i32, ctypes.POINTER(CfarOpts), vp, vp, vp, vp, vp], i32),
         "rsim_add_noise": ([vp, vp, i32, ctypes.c_double, u64, vp, ctypes.POINTER(Opts)], i32),
         "rsim_set_ground": ([vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
+        "rsim_set_backward_kernel": ([vp, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -270,6 +272,9 @@ class Context:
         g = complex(gamma)
         self._check(self._L.rsim_set_ground(self._h, int(bool(enable)), float(z_ground), g.real,
                                             g.imag))
+
+    def set_backward_kernel(self, kernel: int = RSIM_KERNEL_AUTO):
+        self._check(self._L.rsim_set_backward_kernel(self._h, int(kernel)))
 
     @property
     def n_channels(self) -> int:
