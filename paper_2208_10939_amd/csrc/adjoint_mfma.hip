@@ -20,13 +20,13 @@
 // vector-unit adjoint taken with the other side at its reference delay (a relative change
 // of slope |tau_q - tau_ref| / f0 ~ 1e-7).
 //
-// Layout: a workgroup covers one chirp and 64 samples: four accumulating waves (wave w:
-// samples 16w .. 16w+15) and four staging waves; conj(g) of the tile sits in LDS for the
-// whole item. Tiles of four lit facets, double-buffered. Per tile, lane (s, l) of a wave
-// takes facet l at sample s: its 4 PT Tx and 4 QT Rx phasors are the MFMA B operands,
-// conj(g) rows (X) or columns (Y) the A operands read from LDS, so that
-// v_mfma_f32_4x4x1f32 block s holds the outer products of 4 channel rows and 4 facets,
-// and after the K loop lane (s, l) holds X_p (or Y_q) of its facet at its sample.
+// Layout: a workgroup covers one chirp and 64 samples: eight accumulating waves (wave w:
+// samples 8w .. 8w+7, two per SIMD) and four staging waves; conj(g) of the tile sits in
+// LDS for the whole item. Tiles of eight lit facets, double-buffered. Per tile, MFMA block
+// b = (sample s = b mod 8, facet group b / 8) of a wave: lane (b, l) takes facet
+// 4 (b / 8) + l at sample s. Its 4 PT Tx and 4 QT Rx phasors are the MFMA B operands,
+// conj(g) rows (X) or columns (Y) the A operands read from LDS, so that after the K loop
+// lane (b, l) holds X_p (or Y_q) of its facet at its sample.
 #include "adjoint_common.h"
 
 namespace rsim {
@@ -35,19 +35,20 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kAmWaves = 4;                 // accumulating waves, 16 samples each
-constexpr int kAmBlk = 16;                  // samples per wave
+constexpr int kAmWaves = 8;                 // accumulating waves, 8 samples each
+constexpr int kAmBlk = 8;                   // samples per wave
 constexpr int kAmTile = kAmWaves * kAmBlk;  // samples per workgroup
-constexpr int kAmStaging = 4;               // staging waves, one facet each
-constexpr int kAmFT = 4;                    // facets per tile (one per lane column)
+constexpr int kAmFT = 8;                    // facets per tile: two groups of four columns
+constexpr int kAmStaging = 4;               // staging waves, two facets each
 constexpr int kAmThreads = (kAmWaves + kAmStaging) * 64;
-constexpr double kAmMid = 7.5;              // block centre, where staged phases are taken
+constexpr double kAmMid = 31.5;             // tile centre, where staged phases are taken
 
-// LDS: elem | conj(g) [w][4PT][row] (row = 16 (4QT) + 16 float2: the padding moves each p
-// row by 32 banks) | red [2][FT][waves][kAdjVals] | two tile buffers.
+// LDS: elem | conj(g) [w][4PT][row] (row = 8 (4QT) + 8 float2: each p row starts 16 banks
+// after the previous one, so the four rows or columns a read touches fall in distinct
+// banks) | red [2][FT][waves][kAdjVals] | two tile buffers.
 template <int PT, int QT>
 struct AmLayout {
-  static constexpr int kRow = 16 * 4 * QT + 16;  // float2 per p row
+  static constexpr int kRow = kAmBlk * 4 * QT + 8;  // float2 per p row
   static constexpr int kSlots = 4 * (PT + QT);
   size_t elem, gc, red, buf[2], geo, glin, EP, EC, KC, GD, total;
   __host__ __device__ explicit AmLayout(int E) {
@@ -64,8 +65,8 @@ struct AmLayout {
     t = up(t + sizeof(Geo) * kAmFT);
     glin = t;
     t = up(t + sizeof(GLin) * kAmFT);
-    EP = t;  // [kAmWaves][FT][slots] float2: phase at the block centre, step (turns)
-    t = up(t + sizeof(float2) * kAmWaves * kAmFT * kSlots);
+    EP = t;  // [FT][slots] float2: phase at the tile centre, step (turns)
+    t = up(t + sizeof(float2) * kAmFT * kSlots);
     EC = t;  // [FT][slots] float4: unit vector centroid -> element, 1 / R
     t = up(t + sizeof(float4) * kAmFT * kSlots);
     KC = t;  // [FT][slots] float: k0 (f0 - slope (tau_e + tau_ref,other))
@@ -112,17 +113,20 @@ struct AmSmem {
 __device__ inline float am_centred(double t) { return static_cast<float>(t - rint(t)); }
 
 // Staging of tile entries t0 .. t0 + nf - 1 of chirp n into buffer k: staging wave sw
-// takes facet sw through geometry, element data and G, D_k. Padding slots (and absent
-// facets) get zeros, so that every phasor built from them is zero.
+// takes facets 2 sw and 2 sw + 1 through geometry, element data and G, D_k. Padding slots
+// (and absent facets) get zeros, so that every phasor built from them is zero.
 template <int PT, int QT>
 __device__ void am_stage(const DevScene &sc, const RadarConst &rc, const AmSmem<PT, QT> &sm, int k,
                          int n, int32_t cnt, int32_t t0, int nf, int m_tile0, int st) {
   constexpr int kSlots = 4 * (PT + QT);
-  const int lane = st & 63, i = st >> 6;  // facet of this staging wave
+  constexpr int kPer = kAmFT / kAmStaging;  // facets per staging wave
+  static_assert(kPer * kSlots <= 64, "one pass over a wave's element slots");
+  const int lane = st & 63, i0 = (st >> 6) * kPer;
   const int P = rc.P, Q = rc.Q;
   Geo *geo = sm.geo(k);
   GLin *glin = sm.glin(k);
-  if (lane == 0) {
+  if (lane < kPer) {
+    const int i = i0 + lane;
     if (i < nf)
       entry_geometry(sc, rc, n, cnt, t0 + i, geo[i]);
     else
@@ -132,46 +136,45 @@ __device__ void am_stage(const DevScene &sc, const RadarConst &rc, const AmSmem<
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  const Geo g = lds_copy(geo[i]);
-  const GLin q = lds_copy(glin[i]);
   float2 *EP = sm.EP(k);
   float4 *EC = sm.EC(k);
   float *KC = sm.KC(k);
   const double slope = rc.slope;
   const double k0 = 2.0 * kPi / kC0;
-  for (int slot = lane; slot < kSlots; slot += 64) {
+  if (lane < kPer * kSlots) {
+    const int i = i0 + lane / kSlots, slot = lane % kSlots;
+    const Geo g = lds_copy(geo[i]);
     const bool tx = slot < 4 * PT;
     const int e = tx ? slot : P + (slot - 4 * PT);  // element of the slot
     const bool real = tx ? (slot < P) : (slot - 4 * PT < Q);
     if (!g.valid || !real) {
-      for (int b = 0; b < kAmWaves; ++b) EP[(b * kAmFT + i) * kSlots + slot] = make_float2(0.0f, 0.0f);
+      EP[i * kSlots + slot] = make_float2(0.0f, 0.0f);
       EC[i * kSlots + slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       KC[i * kSlots + slot] = 0.0f;
-      continue;
+    } else {
+      const double dx = sm.elem[3 * e + 0] - g.c[0];
+      const double dy = sm.elem[3 * e + 1] - g.c[1];
+      const double dz = sm.elem[3 * e + 2] - g.c[2];
+      const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
+      const double inv = 1.0 / Rn;
+      const double tau = Rn * (1.0 / kC0);
+      const double t_self = tx ? g.tref_t : g.tref_r, t_other = tx ? g.tref_r : g.tref_t;
+      double psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * t_other * (tau - t_self) -
+                    0.5 * slope * g.tref_t * g.tref_r;
+      psi0 -= floor(psi0);
+      double delta = rc.df * tau;
+      delta -= floor(delta);
+      const double mc = static_cast<double>(m_tile0) + kAmMid;
+      EP[i * kSlots + slot] = make_float2(am_centred(psi0 + mc * delta), am_centred(delta));
+      EC[i * kSlots + slot] = make_float4(static_cast<float>(dx * inv), static_cast<float>(dy * inv),
+                                          static_cast<float>(dz * inv), static_cast<float>(inv));
+      KC[i * kSlots + slot] = static_cast<float>(k0 * (rc.f0 - slope * (tau + t_other)));
     }
-    const double dx = sm.elem[3 * e + 0] - g.c[0];
-    const double dy = sm.elem[3 * e + 1] - g.c[1];
-    const double dz = sm.elem[3 * e + 2] - g.c[2];
-    const double Rn = sqrt(dx * dx + dy * dy + dz * dz);
-    const double inv = 1.0 / Rn;
-    const double tau = Rn * (1.0 / kC0);
-    const double t_self = tx ? g.tref_t : g.tref_r, t_other = tx ? g.tref_r : g.tref_t;
-    double psi0 = rc.f0 * tau - 0.5 * slope * tau * tau - slope * t_other * (tau - t_self) -
-                  0.5 * slope * g.tref_t * g.tref_r;
-    psi0 -= floor(psi0);
-    double delta = rc.df * tau;
-    delta -= floor(delta);
-    const float dstep = am_centred(delta);
-    for (int b = 0; b < kAmWaves; ++b) {
-      const double mc = static_cast<double>(m_tile0 + b * kAmBlk) + kAmMid;
-      EP[(b * kAmFT + i) * kSlots + slot] = make_float2(am_centred(psi0 + mc * delta), dstep);
-    }
-    EC[i * kSlots + slot] = make_float4(static_cast<float>(dx * inv), static_cast<float>(dy * inv),
-                                        static_cast<float>(dz * inv), static_cast<float>(inv));
-    KC[i * kSlots + slot] = static_cast<float>(k0 * (rc.f0 - slope * (tau + t_other)));
   }
   float4 *GD = sm.GD(k);
-  for (int j = lane; j < kAmTile; j += 64) {
+  for (int t = lane; t < kPer * kAmTile; t += 64) {
+    const int i = i0 + t / kAmTile, j = t % kAmTile;
+    const GLin q = lds_copy(glin[i]);
     float2 gv, dv[3];
     g_lin_grad(q, j, gv, dv);
     GD[(i * kAmTile + j) * 2 + 0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
@@ -192,18 +195,27 @@ __device__ inline void am_flush(const float *red, float *partial, int64_t F, int
   }
 }
 
-// exp(-j 2 pi (phi_c + s step)) / R at s samples from the block centre
+// exp(-j 2 pi (phi_c + s step)) / R at s samples from the tile centre (|s| <= 31.5: FP32
+// rounding of the phase <= 1e-6 turns, well inside the adjoint's tolerance)
 __device__ inline float2 am_phasor(float2 ep, float s, float ir) {
   const float t = fmaf(s, ep.y, ep.x);
   return make_float2(__builtin_amdgcn_cosf(t) * ir, -__builtin_amdgcn_sinf(t) * ir);
 }
 
-// Sum over the 16 lanes 4s + l (s = 0..15) that share l; every lane gets its group's sum.
+// Sum over the 8 lanes 4 (s + 8 fg) + l (s = 0..7) that share the facet (fg, l); every
+// lane gets its group's sum.
+// (ds_swizzle in bit-mask mode, lane ^ m within 32-lane halves: no address registers)
+template <int kXor>
+__device__ inline float swz_xor(float v) {
+  constexpr int kPattern = 0x1F | (kXor << 10);  // and 0x1F, or 0, xor kXor
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), kPattern));
+}
+
 __device__ inline float sum_over_samples(float v) {
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
+  v += swz_xor<4>(v);
+  v += swz_xor<8>(v);
+  v += swz_xor<16>(v);
   return v;
 }
 
@@ -232,7 +244,7 @@ __global__ void __launch_bounds__(kAmThreads) adjoint_mfma_kernel(DevScene sc, R
     const int q = c / kAmBlk, s = c % kAmBlk;
     const int m = m_tile0 + w * kAmBlk + s;
     float2 v = make_float2(0.0f, 0.0f);
-    if (p < P && q < Q && c < 16 * 4 * QT && m < M) {
+    if (p < P && q < Q && c < kAmBlk * 4 * QT && m < M) {
       const float2 gv = grad_echo[(static_cast<int64_t>(p * Q + q) * N + n) * M + m];
       v = make_float2(gv.x, -gv.y);
     }
@@ -262,56 +274,57 @@ __global__ void __launch_bounds__(kAmThreads) adjoint_mfma_kernel(DevScene sc, R
     return;
   }
 
-  const int w = tid >> 6, lane = tid & 63;
-  const int s = lane >> 2, l = lane & 3;  // sample in the wave's block; facet column
-  const float sf = static_cast<float>(s) - static_cast<float>(kAmMid);
-  const float mabs = static_cast<float>(m_tile0 + w * kAmBlk + s);
   const float kdf = static_cast<float>(2.0 * kPi / kC0 * rc.df);
-  const float2 *gcw = sm.gc + static_cast<size_t>(w) * 4 * PT * kRow;
   for (int32_t kt = 0; kt < n_tiles; ++kt) {
     __syncthreads();
+    // The lane's indices and addresses are formed here, per tile, from a thread id passed
+    // through an empty asm: hoisted out of the loop they would be held (and spilled)
+    // across it at three waves per SIMD.
+    int lt = tid;
+    asm volatile("" : "+v"(lt));
+    const int w = lt >> 6, lane = lt & 63;
+    const int blk = lane >> 2, l = lane & 3;  // MFMA block; row / column within it
+    const int s = blk % kAmBlk, fi = 4 * (blk / kAmBlk) + l;  // sample in the wave; facet
+    const int mw = w * kAmBlk + s;                            // sample in the tile
+    const float sf = static_cast<float>(mw) - static_cast<float>(kAmMid);
+    const float mabs = static_cast<float>(m_tile0 + mw);
+    const float2 *gcw = sm.gc + static_cast<size_t>(w) * 4 * PT * kRow;
     const int buf = kt & 1;
-    const float2 *EP = sm.EP(buf) + (w * kAmFT + l) * kSlots;
-    const float4 *EC = sm.EC(buf) + l * kSlots;
-    const float *KC = sm.KC(buf) + l * kSlots;
+    const float2 *EP = sm.EP(buf) + fi * kSlots;
+    const float4 *EC = sm.EC(buf) + fi * kSlots;
+    const float *KC = sm.KC(buf) + fi * kSlots;
     // phasors of this lane's facet at its sample: Tx slots 0 .. 4PT-1, Rx slots after
+    // Phases in this order (scheduling barriers between them, and every four elements
+    // inside, bound what the compiler keeps live at three waves per SIMD): Rx phasors, the
+    // X contraction, Tx phasors, the Tx-side sums, the Y contraction, the Rx-side sums.
     float ar[4 * PT], ai[4 * PT], br[4 * QT], bi[4 * QT];
-#pragma unroll
-    for (int p = 0; p < 4 * PT; ++p) {
-      const float2 t = am_phasor(EP[p], sf, EC[p].w);
-      ar[p] = t.x;
-      ai[p] = t.y;
-    }
 #pragma unroll
     for (int q = 0; q < 4 * QT; ++q) {
       const float2 t = am_phasor(EP[4 * PT + q], sf, EC[4 * PT + q].w);
       br[q] = t.x;
       bi[q] = t.y;
+      if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     }
-    const float4 *gd = sm.GD(buf) + (l * kAmTile + w * kAmBlk + s) * 2;
-    const float4 g0 = gd[0], g1 = gd[1];  // (G, D0), (D1, D2)
     const float kmf = kdf * mabs;
     float v[7] = {0, 0, 0, 0, 0, 0, 0};
     float wr = 0.0f, wi = 0.0f;
+    float4 g0, g1;  // (G, D0), (D1, D2) of this facet and sample
     {
-      // X_p = sum_q conj(g)[p, q] B_q: A operand conj(g)[4a + l, q] (row l of block s);
-      // lane (s, l) register r of tile a then holds X[4a + r] of facet l at sample s
+      // X_p = sum_q conj(g)[p, q] B_q: A operand conj(g)[4a + l, q] (row l of block b, at
+      // the block's sample); lane (b, l) register r of tile a then holds X[4a + r] of its facet
       v4f xr[PT], xi[PT];
 #pragma unroll
       for (int a = 0; a < PT; ++a) {
         xr[a] = v4f{0.f, 0.f, 0.f, 0.f};
         xi[a] = v4f{0.f, 0.f, 0.f, 0.f};
       }
-      float nbi[4 * QT];  // negated ahead, so that the MFMA groups hold no vector work
-#pragma unroll
-      for (int q = 0; q < 4 * QT; ++q) nbi[q] = -bi[q];
       // conj(g) operands one step ahead of the MFMAs that use them (LDS latency)
       float2 gn[PT];
 #pragma unroll
       for (int a = 0; a < PT; ++a) gn[a] = gcw[(4 * a + l) * kRow + s];
 #pragma unroll
       for (int q = 0; q < 4 * QT; ++q) {
-        const float nb = nbi[q];
+        const float nb = -bi[q];
         float2 g[PT];
 #pragma unroll
         for (int a = 0; a < PT; ++a) {
@@ -335,6 +348,16 @@ __global__ void __launch_bounds__(kAmThreads) adjoint_mfma_kernel(DevScene sc, R
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
+      for (int p = 0; p < 4 * PT; ++p) {
+        const float2 t = am_phasor(EP[p], sf, EC[p].w);
+        ar[p] = t.x;
+        ai[p] = t.y;
+        if (p % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+      const float4 *gd = sm.GD(buf) + (fi * kAmTile + mw) * 2;
+      g0 = gd[0];
+      g1 = gd[1];
+#pragma unroll
       for (int a = 0; a < PT; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -350,25 +373,23 @@ __global__ void __launch_bounds__(kAmThreads) adjoint_mfma_kernel(DevScene sc, R
           v[0] = fmaf(-c, e.x, v[0]);
           v[1] = fmaf(-c, e.y, v[1]);
           v[2] = fmaf(-c, e.z, v[2]);
+          if (r == 3) __builtin_amdgcn_sched_barrier(0);
         }
     }
     {
-      // Y_q = sum_p conj(g)[p, q] A_p: A operand conj(g)[p, 4b + l] (row l of block s)
+      // Y_q = sum_p conj(g)[p, q] A_p: A operand conj(g)[p, 4b + l] (row l of the block)
       v4f yr[QT], yi[QT];
 #pragma unroll
       for (int b = 0; b < QT; ++b) {
         yr[b] = v4f{0.f, 0.f, 0.f, 0.f};
         yi[b] = v4f{0.f, 0.f, 0.f, 0.f};
       }
-      float nai[4 * PT];
-#pragma unroll
-      for (int p = 0; p < 4 * PT; ++p) nai[p] = -ai[p];
       float2 gn[QT];
 #pragma unroll
       for (int b = 0; b < QT; ++b) gn[b] = gcw[(4 * b + l) * kAmBlk + s];
 #pragma unroll
       for (int p = 0; p < 4 * PT; ++p) {
-        const float na = nai[p];
+        const float na = -ai[p];
         float2 g[QT];
 #pragma unroll
         for (int b = 0; b < QT; ++b) {
@@ -402,18 +423,19 @@ __global__ void __launch_bounds__(kAmThreads) adjoint_mfma_kernel(DevScene sc, R
           v[0] = fmaf(-c, e.x, v[0]);
           v[1] = fmaf(-c, e.y, v[1]);
           v[2] = fmaf(-c, e.z, v[2]);
+          if (r == 3) __builtin_amdgcn_sched_barrier(0);
         }
     }
     v[3] = g0.x * wr - g0.y * wi;  // Re(G W)
     v[4] = g0.z * wr - g0.w * wi;  // Re(D_k W)
     v[5] = g1.x * wr - g1.y * wi;
     v[6] = g1.z * wr - g1.w * wi;
-    // sums over the wave's 16 samples (every lane takes part), lane (0, l) records them
+    // sums over the wave's 8 samples (every lane takes part); the lanes of sample 0 record them
     float *red = sm.red_buf(buf);
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
       const float tot = sum_over_samples(v[k]);
-      if (s == 0) red[(l * kAmWaves + w) * kAdjVals + k] = tot;
+      if (s == 0) red[(fi * kAmWaves + w) * kAdjVals + k] = tot;
     }
   }
   __syncthreads();
