@@ -465,31 +465,40 @@ __global__ void fill_zero_kernel(float *p, int64_t n) {
     p[i] = 0.0f;
 }
 
-// One instance: per body vertex, gather sum over chirps and incident (triangle,
-// corner) of the world gradients, rotate to the body frame and accumulate into gv;
-// vpart[v] = sum_n t_n (world gradient of v at chirp n) for the velocity gradient.
+// Per facet and component: the sum over chirps of the world-vertex gradients and of t_n
+// times them (FP64, chirp order): gsum[f * 9 + c], gtsum[f * 9 + c]. Consecutive threads
+// read consecutive components of one chirp's row.
+__global__ void __launch_bounds__(256) facet_chirp_sum_kernel(const float *gxw, int64_t n_facets,
+                                                              int N, double tc, double *gsum,
+                                                              double *gtsum) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n_facets * 9) return;
+  double g = 0.0, gt = 0.0;
+  for (int n = 0; n < N; ++n) {
+    const double v = gxw[static_cast<int64_t>(n) * n_facets * 9 + idx];
+    g += v;
+    gt += (n * tc) * v;
+  }
+  gsum[idx] = g;
+  gtsum[idx] = gt;
+}
+
+// One instance: per body vertex, gather over incident (triangle, corner) the chirp-summed
+// world gradients, rotate to the body frame and accumulate into gv; vpart[v] = sum over
+// chirps of t_n (world gradient of v at chirp n) for the velocity gradient.
 __global__ void __launch_bounds__(256) vertex_gather_kernel(
-    const float *gxw, int64_t n_facets, int N, double tc, const double *rot,
-    int64_t facet_base, const int32_t *csr_off, const int32_t *csr_ent, int32_t n_verts,
-    float *gv, double *vpart) {
+    const double *gsum, const double *gtsum, const double *rot, int64_t facet_base,
+    const int32_t *csr_off, const int32_t *csr_ent, int32_t n_verts, float *gv, double *vpart) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n_verts) return;
   double g[3] = {0, 0, 0}, gt[3] = {0, 0, 0};
   const int32_t b = csr_off[v], e = csr_off[v + 1];
-  for (int n = 0; n < N; ++n) {
-    double gn[3] = {0, 0, 0};
-    for (int32_t k = b; k < e; ++k) {
-      const int32_t ent = csr_ent[k];  // triangle * 3 + corner
-      const float *src = gxw + (static_cast<int64_t>(n) * n_facets + facet_base + ent / 3) * 9 +
-                         3 * (ent % 3);
-      gn[0] += src[0];
-      gn[1] += src[1];
-      gn[2] += src[2];
-    }
-    const double tn = n * tc;
-    for (int k = 0; k < 3; ++k) {
-      g[k] += gn[k];
-      gt[k] += tn * gn[k];
+  for (int32_t k = b; k < e; ++k) {
+    const int32_t ent = csr_ent[k];  // triangle * 3 + corner
+    const int64_t o = (facet_base + ent / 3) * 9 + 3 * (ent % 3);
+    for (int c = 0; c < 3; ++c) {
+      g[c] += gsum[o + c];
+      gt[c] += gtsum[o + c];
     }
   }
   // body gradient = R^T (world gradient)
@@ -559,13 +568,23 @@ hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double
   return launch_adjoint_finish(sc, rc, sh, partial, gxw, s);
 }
 
-hipError_t launch_vertex_gather(const float *gxw, int64_t n_facets, int N, double tc,
-                                const double *rot_dev, int64_t facet_base, const int32_t *csr_off,
-                                const int32_t *csr_ent, int32_t n_verts, float *gv, double *vpart,
-                                double *vel_out, hipStream_t s) {
+hipError_t launch_facet_chirp_sum(const float *gxw, int64_t n_facets, int N, double tc,
+                                  double *gsum, double *gtsum, hipStream_t s) {
+  if (n_facets > 0) {
+    const int64_t n = n_facets * 9;
+    hipLaunchKernelGGL(facet_chirp_sum_kernel, dim3(static_cast<unsigned>((n + 255) / 256)),
+                       dim3(256), 0, s, gxw, n_facets, N, tc, gsum, gtsum);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vertex_gather(const double *gsum, const double *gtsum, const double *rot_dev,
+                                int64_t facet_base, const int32_t *csr_off, const int32_t *csr_ent,
+                                int32_t n_verts, float *gv, double *vpart, double *vel_out,
+                                hipStream_t s) {
   if (n_verts > 0) {
-    hipLaunchKernelGGL(vertex_gather_kernel, dim3((n_verts + 255) / 256), dim3(256), 0, s, gxw,
-                       n_facets, N, tc, rot_dev, facet_base, csr_off, csr_ent, n_verts, gv, vpart);
+    hipLaunchKernelGGL(vertex_gather_kernel, dim3((n_verts + 255) / 256), dim3(256), 0, s, gsum,
+                       gtsum, rot_dev, facet_base, csr_off, csr_ent, n_verts, gv, vpart);
   }
   hipLaunchKernelGGL(velocity_reduce_kernel, dim3(1), dim3(256), 0, s, vpart, n_verts, vel_out);
   return hipGetLastError();

@@ -124,8 +124,8 @@ struct rsim_ctx {
   int32_t bwd_kernel = RSIM_KERNEL_AUTO;  // facet-sum kernel of rsim_backward
   // adjoint work buffers
   float *adj_partial = nullptr, *adj_gxw = nullptr;
-  double *adj_vpart = nullptr;
-  size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0;
+  double *adj_vpart = nullptr, *adj_gsum = nullptr;  // gsum: [2][F][9] (plain, t_n-weighted)
+  size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0, adj_gsum_n = 0;
   BatchTables batch;  // persistent launches outside graphs
   GraphCache graph;
   // detection and noise work buffers (grow only)
@@ -1229,6 +1229,15 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                    std::max<size_t>(1, adjoint_partial_floats(sh, N, F)))))
     return rc;
   if ((rc = grow_f(ctx->adj_gxw, ctx->adj_gxw_n, std::max<size_t>(1, N * F * 9)))) return rc;
+  if (ctx->adj_gsum_n < static_cast<size_t>(2 * 9 * std::max<int64_t>(1, F))) {
+    dev_free(ctx, ctx->adj_gsum);
+    ctx->adj_gsum = nullptr;
+    ctx->adj_gsum_n = 0;
+    const size_t need = 2 * 9 * static_cast<size_t>(std::max<int64_t>(1, F));
+    if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&ctx->adj_gsum), sizeof(double) * need)))
+      return rc;
+    ctx->adj_gsum_n = need;
+  }
   if (ctx->adj_vpart_n < 3 * vmax) {
     dev_free(ctx, ctx->adj_vpart);
     ctx->adj_vpart = nullptr;
@@ -1250,6 +1259,8 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                                 ctx->adj_gxw, s));
   stage_end(ctx, timing, 5, s);
   stage_begin(ctx, timing, 7, s);
+  double *gsum = ctx->adj_gsum, *gtsum = ctx->adj_gsum + 9 * F;
+  HIP_TRY(ctx, launch_facet_chirp_sum(ctx->adj_gxw, F, rcn.N, rcn.tc, gsum, gtsum, s));
   for (size_t i = 0; i < sc.inst.size(); ++i) {
     const InstRec &r = sc.inst[i];
     const MeshRec &m = ctx->meshes[r.mesh];
@@ -1263,8 +1274,8 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
       for (size_t k = 0; k < i; ++k) b += static_cast<int64_t>(ctx->meshes[sc.inst[k].mesh].tris.size() / 3);
       return b;
     }();
-    HIP_TRY(ctx, launch_vertex_gather(ctx->adj_gxw, F, rcn.N, rcn.tc, rot_dev, base, m.d_csr_off,
-                                      m.d_csr_ent, static_cast<int32_t>(m.verts.size() / 3), gv,
+    HIP_TRY(ctx, launch_vertex_gather(gsum, gtsum, rot_dev, base, m.d_csr_off, m.d_csr_ent,
+                                      static_cast<int32_t>(m.verts.size() / 3), gv,
                                       ctx->adj_vpart, vel_out, s));
   }
   stage_end(ctx, timing, 7, s);

@@ -89,9 +89,12 @@ hipError_t launch_adjoint_mfma(const DevScene &sc, const RadarConst &rc, const d
 hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
                           hipStream_t s);
-hipError_t launch_vertex_gather(const float *gxw, int64_t n_facets, int N, double tc,
-                                const double *rot_dev, int64_t facet_base, const int32_t *csr_off,
-                                const int32_t *csr_ent, int32_t n_verts, float *gv, double *vpart,
-                                double *vel_out, hipStream_t s);
+// world-vertex gradients [N][F][9] -> per-facet sums over chirps, plain and t_n-weighted
+hipError_t launch_facet_chirp_sum(const float *gxw, int64_t n_facets, int N, double tc,
+                                  double *gsum, double *gtsum, hipStream_t s);
+hipError_t launch_vertex_gather(const double *gsum, const double *gtsum, const double *rot_dev,
+                                int64_t facet_base, const int32_t *csr_off, const int32_t *csr_ent,
+                                int32_t n_verts, float *gv, double *vpart, double *vel_out,
+                                hipStream_t s);
 
 }  // namespace rsim
