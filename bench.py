@@ -7,7 +7,7 @@ compaction + facet sum + range FFT + Doppler FFT/RDM of one frame; inputs reside
 in device memory. Prints ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--calib-copy MiB]
-                  [--kernel auto|vector|matrix] [--tile-m T --tile-f F]
+                  [--kernel auto|vector|matrix|nufft] [--tile-m T --tile-f F]
 """
 from __future__ import annotations
 
@@ -40,11 +40,32 @@ MFMA_FLOP_PER_EVAL = 8
 # FP32 FMA issue without packed-math instructions, which this build keeps out of all
 # device code: 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.
 PEAK_FP32_NON_PACKED = 256 * 4 * 16 * 2 * 2.4e9
+# NUFFT facet sum (type-1 non-uniform FFT over the sample index): spread width (grid
+# cells) and Taylor terms on this workload (facet spread bound 0.27 cells <= 0.35).
+NUFFT_WIDTH = 12
+NUFFT_ORDER = 5
+
+
+def nufft_flop(units, cubes_rows, ng, M):
+    """Algorithmic FLOP of the NUFFT facet sum: per (lit entry, channel, chirp) unit the
+    coefficient scaling (R complex products, 6 R), the two FP64 distances and the phase
+    (30), and per grid cell of the spread the Horner polynomial (R - 1 complex-by-real
+    steps, 4 (R - 1)), the Gaussian weight (3), the weighting (2) and the accumulation
+    (2); per (channel, chirp) row an n_g-point FFT (5 n_g log2 n_g) and the
+    deconvolution of M samples (2 M)."""
+    import math
+    R, W = NUFFT_ORDER, NUFFT_WIDTH
+    per_unit = 6 * R + 30 + W * (4 * (R - 1) + 7)
+    return units * per_unit + cubes_rows * (5 * ng * math.log2(ng) + 2 * M)
+
+
 PROFILE_TRAFFIC = {"vector": os.path.join(ROOT, "profiles", "facet_sum_c2_traffic.json"),
-                   "matrix": os.path.join(ROOT, "profiles", "facet_sum_mfma_c2_traffic.json")}
+                   "matrix": os.path.join(ROOT, "profiles", "facet_sum_mfma_c2_traffic.json"),
+                   "nufft": os.path.join(ROOT, "profiles", "facet_sum_nufft_c2_traffic.json")}
 KERNEL_SOURCES = {"vector": ("echo.hip", "echo_common.h"),
-                  "matrix": ("echo_mfma.hip", "echo_common.h")}
-KERNEL_CODES = {"auto": 0, "vector": 1, "matrix": 2}
+                  "matrix": ("echo_mfma.hip", "echo_common.h"),
+                  "nufft": ("nufft.hip", "echo_common.h", "fft_common.h")}
+KERNEL_CODES = {"auto": 0, "vector": 1, "matrix": 2, "nufft": 3}
 
 
 def _log(msg):
@@ -72,11 +93,32 @@ def _traffic(kernel):
     return d.get("bytes_per_launch")
 
 
-def roofline(kernel, achieved, evals, fs_ms):
-    """Roofline object of the facet-sum kernel: algorithmic FLOP (FLOP_PER_EVAL per
-    evaluation) per launch over the launch's measured duration, against the published
-    FP32 peak of the units the kernel runs on."""
+def roofline(kernel, evals, fs_ms, shape=None):
+    """Roofline object of the facet-sum kernel: algorithmic FLOP per launch (direct sums:
+    FLOP_PER_EVAL per evaluation; NUFFT: nufft_flop) over the launch's measured duration,
+    against the published FP32 peak of the units the kernel runs on."""
     rate = evals / (fs_ms * 1e-3)
+    achieved = FLOP_PER_EVAL * rate
+    if kernel == "nufft":
+        O, N, M = shape
+        ng = 2 * M  # 2^a 3^b already for M = 256
+        flop = nufft_flop(evals // M, O * N, ng, M)
+        ach = flop / (fs_ms * 1e-3)
+        return {
+            "bound": "alu",
+            "achieved": ach / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP32_VECTOR,
+            "traffic": _traffic("nufft"),
+            "kernel": "rsim::nufft_prep_kernel<5> + nufft_sort_kernel<5> + nufft_spread_kernel<5> + nufft_fft_kernel (Gaussian "
+                      "spread in registers + in-LDS FFT + deconvolution)",
+            "flop_per_launch": flop,
+            "units_per_launch": evals // M,
+            "flop_per_unit": 6 * NUFFT_ORDER + 30 + NUFFT_WIDTH * (4 * (NUFFT_ORDER - 1) + 7),
+            "frac_of_non_packed_fp32_peak": ach / PEAK_FP32_NON_PACKED,
+            "direct_sum_equivalent_tflops": achieved / 1e12,
+        }
     if kernel == "matrix":
         return {
             "bound": "mfma",
@@ -194,8 +236,9 @@ def measure_other_kernel(sim, echo, mask, kernel, evals, reps=5):
     torch.cuda.synchronize()
     fs = float(np.median(ts))
     d = (buf - ref).abs().pow(2).sum().sqrt() / ref.abs().pow(2).sum().sqrt()
+    wf = sim.wf
     return {"kernel": kernel, "facet_sum_ms": fs,
-            "roofline": roofline(kernel, FLOP_PER_EVAL * evals / (fs * 1e-3), evals, fs),
+            "roofline": roofline(kernel, evals, fs, (sim.O, wf.n_chirps, wf.n_samples)),
             "rel_rms_vs_main": float(d)}
 
 
@@ -268,7 +311,7 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--tile-f", type=int, default=0)
-    ap.add_argument("--kernel", choices=("auto", "vector", "matrix"), default="auto",
+    ap.add_argument("--kernel", choices=("auto", "vector", "matrix", "nufft"), default="auto",
                     help="facet-sum kernel (auto: the autotuner's choice)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -360,12 +403,17 @@ def main():
                    "facet_sum_tile": (tuned if tuned else
                                       {"tile_m": args.tile_m, "tile_f": args.tile_f})},
         "stage_ms": stage_avg,
-        "roofline": roofline(kernel, achieved, evals_per_step, fs_ms),
+        "roofline": roofline(kernel, evals_per_step, fs_ms,
+                             (arr.n_channels, wf.n_chirps, wf.n_samples)),
     }
     if not args.no_extras:
-        other = "vector" if kernel == "matrix" else "matrix"
-        _log(f"bench: the {other} kernel's facet sum on the same frame")
-        out["other_kernel"] = measure_other_kernel(sim, echo, mask, other, evals_per_step)
+        out["other_kernels"] = []
+        for other in ("nufft", "matrix", "vector"):
+            if other == kernel:
+                continue
+            _log(f"bench: the {other} kernel's facet sum on the same frame")
+            out["other_kernels"].append(
+                measure_other_kernel(sim, echo, mask, other, evals_per_step))
         _log("bench: forward + backward")
         out["fwd_bwd"] = measure_fwd_bwd(sim)
         _log("bench: batched vs plain (8 scenes of the 64-scene workload)")

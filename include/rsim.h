@@ -45,12 +45,23 @@ extern "C" {
 #define RSIM_FP64 1         /* FP64 throughout; complex128 echo                       */
 
 /* facet-sum kernel of rsim_synthesize (FP32 sum) */
-#define RSIM_KERNEL_AUTO 0   /* the faster of the two for this array and waveform as timed by */
-                             /* rsim_autotune; the vector units until it has run               */
+#define RSIM_KERNEL_AUTO 0   /* the fastest eligible kernel for this array and waveform as    */
+                             /* timed by rsim_autotune; the vector units until it has run      */
 #define RSIM_KERNEL_VECTOR 1 /* vector units: full phase factorisation incl. the cross term   */
 #define RSIM_KERNEL_MATRIX 2 /* matrix cores: separable Tx x Rx contraction per sample, which  */
                              /* drops the Tx-Rx cross term; eligible when |2 pi slope d_p e_q| */
                              /* <= 1e-5 rad, P <= 12 and Q <= 16                               */
+#define RSIM_KERNEL_NUFFT 3  /* type-1 non-uniform FFT over the sample index: each facet's    */
+                             /* divided-difference integral spread onto a 2x-oversampled grid  */
+                             /* per channel with a Taylor-expanded Gaussian, then an FFT and   */
+                             /* deconvolution (relative error ~1e-5 or below). Exact per-      */
+                             /* channel distances (no cross-term approximation). Eligible for  */
+                             /* stop-and-hop without the ground bounce, and when every facet   */
+                             /* spans at most 1.5 grid cells: 2 r_max df n_g / c <= 1.5, r_max */
+                             /* the largest vertex-to-centroid distance of the scenes' meshes, */
+                             /* n_g the smallest 2^a 3^b >= 2M (32 <= n_g <= 2048), and when   */
+                             /* every channel's path stays within 2.5 grid cells of the phase- */
+                             /* centre path (array aperture).                                  */
 
 /* visibility-mask mode */
 #define RSIM_MASK_COMPUTE 0 /* compute the lit-facet mask; write it to vis_mask if given */
@@ -85,9 +96,9 @@ typedef struct {
                      /* 1: the propagation delay of eq. (12) taken at each sample time  */
                      /* t_n + m / fs (range-Doppler coupling within a chirp); amplitude, */
                      /* facet integral and lit set stay at t_n. FP32 sum only.          */
-  int32_t kernel;    /* RSIM_KERNEL_AUTO (default), RSIM_KERNEL_VECTOR or RSIM_KERNEL_MATRIX; */
-                     /* MATRIX on an ineligible array or with RSIM_FP64 fails with ERANGE /  */
-                     /* EINVAL; AUTO falls back to VECTOR there                             */
+  int32_t kernel;    /* RSIM_KERNEL_AUTO (default), _VECTOR, _MATRIX or _NUFFT; MATRIX or   */
+                     /* NUFFT where ineligible fails with ERANGE (with RSIM_FP64: EINVAL);  */
+                     /* AUTO falls back to VECTOR there                                     */
   int32_t reserved[3];
 } rsim_opts;
 
@@ -313,7 +324,7 @@ int32_t rsim_add_noise(rsim_ctx *ctx, void *echo, int32_t n_cubes, double snr_db
 
 /* ---- tuning ------------------------------------------------------------------------- */
 
-/* Time the facet-sum tile shapes (and the matrix-core kernel where the array allows it)
+/* Time the facet-sum tile shapes (and the matrix-core and NUFFT kernels where eligible)
  * on the given scenes and keep the fastest as the
  * default for this (M, O, precision); optionally append it to a JSON-lines cache
  * file (cache_json_path may be NULL). Synchronous. */

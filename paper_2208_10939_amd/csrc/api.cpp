@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -34,6 +35,7 @@ struct MeshRec {
   std::vector<float> verts;
   std::vector<int32_t> tris;
   double box_lo[3], box_hi[3];  // body bounding box
+  double r_max = 0.0;           // largest vertex-to-centroid distance of any triangle
   int depth = -1;
   int64_t n_nodes = 0, n_leaf = 0;
   void *d_verts = nullptr, *d_tris = nullptr, *d_nodes = nullptr, *d_leaf = nullptr;
@@ -64,7 +66,7 @@ struct SceneRec {
 
 struct TunedShape {
   int mb, ft;
-  int kernel;  // RSIM_KERNEL_VECTOR or RSIM_KERNEL_MATRIX (0: not tuned: vector units)
+  int kernel;  // RSIM_KERNEL_VECTOR, _MATRIX or _NUFFT (0: not tuned: vector units)
 };
 
 // Device-side tables of one batched call: scene views and the longest-first work
@@ -125,6 +127,11 @@ struct rsim_ctx {
   // adjoint work buffers
   float *adj_partial = nullptr, *adj_gxw = nullptr;
   double *adj_vpart = nullptr, *adj_gsum = nullptr;  // gsum: [2][F][9] (plain, t_n-weighted)
+  // NUFFT facet sum work buffer (records, keys, order, cell counts, grids) and the layout
+  // its count and grid regions were last cleared for
+  void *nu_buf = nullptr;
+  size_t nu_buf_bytes = 0;
+  std::array<int64_t, 5> nu_layout{};
   size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0, adj_gsum_n = 0;
   BatchTables batch;  // persistent launches outside graphs
   GraphCache graph;
@@ -452,18 +459,113 @@ EchoShape matrix_shape(const RadarConst &rc) {
   return sh;
 }
 
+// NUFFT facet sum: largest facet spread on the grid (cells) and grid length.
+constexpr double kNuMaxSpread = 1.5;
+constexpr int kNuMaxGrid = 2048;
+constexpr size_t kNuRecBudget = size_t(4) << 30;  // work buffer: chirps per launch cap
+
+int smooth_at_least(int n) {  // smallest 2^a 3^b >= n
+  int best = 1 << 30;
+  for (int64_t p3 = 1; p3 < (int64_t(1) << 31); p3 *= 3)
+    for (int64_t v = p3; v < (int64_t(1) << 31); v *= 2)
+      if (v >= n) {
+        best = std::min<int64_t>(best, v);
+        break;
+      }
+  return best;
+}
+
+double scenes_rmax(const rsim_ctx *ctx, const std::vector<int32_t> &ids) {
+  double r = 0.0;
+  for (int32_t id : ids)
+    for (const InstRec &i : ctx->scenes[id].inst) r = std::max(r, ctx->meshes[i.mesh].r_max);
+  return r;
+}
+
+// Why the NUFFT facet sum cannot run (nullptr: it can, and *ns holds its shape without
+// the chirp chunk and record stride).
+const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o,
+                             double r_max, NuShape *ns) {
+  if (o.precision != RSIM_FP32_PHASE64) return "the NUFFT facet sum is FP32 only";
+  if (o.intra_chirp) return "the NUFFT facet sum is stop-and-hop only";
+  if (ctx->ground) return "the NUFFT facet sum covers the single-bounce path only";
+  const int ng = smooth_at_least(2 * rc.M);
+  if (ng > kNuMaxGrid) return "the NUFFT facet sum needs 2M <= 2048";
+  if (ng < 32) return "the NUFFT facet sum needs M >= 16";
+  const double kappa = rc.df * ng / kC0;
+  const double spread = 2.0 * r_max * kappa;
+  if (spread > kNuMaxSpread) return "facets span more than 1.5 NUFFT grid cells";
+  // every channel's grid position lies within chan_cells of the phase-centre path's
+  double et = 0.0, er = 0.0;
+  for (int p = 0; p < rc.P; ++p) {
+    double d = 0.0;
+    for (int k = 0; k < 3; ++k) d += (ctx->tx[3 * p + k] - rc.tx_c[k]) * (ctx->tx[3 * p + k] - rc.tx_c[k]);
+    et = std::max(et, std::sqrt(d));
+  }
+  for (int q = 0; q < rc.Q; ++q) {
+    double d = 0.0;
+    for (int k = 0; k < 3; ++k) d += (ctx->rx[3 * q + k] - rc.rx_c[k]) * (ctx->rx[3 * q + k] - rc.rx_c[k]);
+    er = std::max(er, std::sqrt(d));
+  }
+  // the register window of the spread holds every channel's cells while the sorted
+  // phase-centre positions advance: 2 d <= window - width - 3
+  const double chan_d = kappa * (et + er);
+  if (2.0 * chan_d > nufft_window_cells() - kNuWidth - 3)
+    return "array aperture too wide for the NUFFT register window";
+  NuShape s{};
+  s.ng = ng;
+  s.ld = ng + 1;
+  s.order = spread <= 0.35 ? 5 : spread <= 0.8 ? 7 : 10;
+  s.cb = 0;
+  for (int cb = 16; cb >= 1 && !s.cb; --cb) {  // two workgroups per CU where possible
+    NuShape t = s;
+    t.cb = cb;
+    if (nufft_smem_bytes(t) <= ctx->max_lds / 2) s.cb = cb;
+  }
+  if (!s.cb) s.cb = 1;
+  const int O = rc.P * rc.Q;
+  s.cb = std::min(s.cb, O);
+  s.groups = (O + s.cb - 1) / s.cb;
+  s.fc = rc.f0 + (rc.M / 2) * rc.df;
+  s.kc = 2.0 * kPi * s.fc / kC0;
+  s.cells_per_s = rc.df * ng;
+  s.kappa = kappa;
+  s.sigma = kNuSigma;
+  s.chan_d = chan_d;
+  s.spread_groups = (O + 63) / 64;
+  s.n0 = 0;
+  s.n_chirps = rc.N;
+  *ns = s;
+  return nullptr;
+}
+
 // Kernel, tiles and shape of one rsim_synthesize call.
 struct SumPlan {
   bool matrix = false;
+  bool nufft = false;
   TunedShape ts{};
   EchoShape sh{};
+  NuShape ns{};         // NUFFT: shape; n_chirps = chirps per launch
+  NuBuffers nb{};       // NUFFT: work buffers
+  const void *tw = nullptr;  // NUFFT: twiddles of the grid length
   int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
 };
 
-SumPlan plan_sum(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o) {
+SumPlan plan_sum(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o, double r_max) {
   SumPlan pl;
   pl.ts = pick_shape(ctx, o.precision, o);
   const bool eligible = matrix_ineligible(ctx, rc, o.precision) == nullptr;
+  NuShape ns{};
+  const bool nu_ok = nufft_ineligible(ctx, rc, o, r_max, &ns) == nullptr;
+  if (o.kernel == RSIM_KERNEL_NUFFT || (o.kernel == RSIM_KERNEL_AUTO && nu_ok &&
+                                        pl.ts.kernel == RSIM_KERNEL_NUFFT && !o.tile_m &&
+                                        !o.tile_f)) {
+    pl.nufft = true;
+    pl.ns = ns;
+    pl.sh = echo_shape(ctx, rc, 64);
+    pl.batch_key = -1;
+    return pl;
+  }
   if (o.kernel == RSIM_KERNEL_MATRIX)
     pl.matrix = true;
   else if (o.kernel == RSIM_KERNEL_AUTO)  // the autotuned choice; vector units by default
@@ -558,6 +660,20 @@ int32_t index_mesh(rsim_ctx *ctx, MeshRec &m, bool first_time) {
       if (first || v[k] > m.box_hi[k]) m.box_hi[k] = v[k];
     }
     first = false;
+  }
+  m.r_max = 0.0;
+  for (int64_t t = 0; t < n_tris; ++t) {
+    double x[3][3], c[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < 3; ++v)
+      for (int k = 0; k < 3; ++k) {
+        x[v][k] = m.verts[3 * static_cast<int64_t>(m.tris[3 * t + v]) + k];
+        c[k] += x[v][k] / 3.0;
+      }
+    for (int v = 0; v < 3; ++v) {
+      double d = 0.0;
+      for (int k = 0; k < 3; ++k) d += (x[v][k] - c[k]) * (x[v][k] - c[k]);
+      m.r_max = std::max(m.r_max, std::sqrt(d));
+    }
   }
   std::vector<BvhNode> nodes;
   std::vector<float> leaf;
@@ -675,11 +791,10 @@ int32_t prepare_batch(rsim_ctx *ctx, BatchTables &bt, const std::vector<int32_t>
 
 // Enqueue visibility + compaction + facet sum (kernels only; capturable).
 int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const BatchTables *bt,
-                          hipStream_t s, const rsim_opts &o, bool timing) {
+                          hipStream_t s, const rsim_opts &o, bool timing, const SumPlan &pl) {
   RadarConst rc = radar_const(ctx);
   rc.intra = o.intra_chirp ? 1 : 0;
   const int precision = o.precision;
-  const SumPlan pl = plan_sum(ctx, rc, o);
   const TunedShape ts = pl.ts;
   const EchoShape sh = pl.sh;
   auto sum_plain = [&](const DevScene &d, const RadarConst &r, const double *elem,
@@ -697,7 +812,20 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, rc.N, s));
     stage_end(ctx, timing, 1, s);
     stage_begin(ctx, timing, 2, s);
-    if (bt && pl.matrix) {
+    if (pl.nufft) {
+      // per scene, in chirp chunks that fit the record buffer (batched calls included)
+      for (const DevScene &d : ds) {
+        NuShape ns = pl.ns;
+        ns.rec_stride = d.n_facets + d.n_points;
+        for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
+          ns.n0 = n0;
+          ns.n_chirps = std::min(pl.ns.n_chirps, rc.N - n0);
+          ns.runs = static_cast<int32_t>((ns.rec_stride + nufft_run_length() - 1) /
+                                         nufft_run_length());
+          HIP_TRY(ctx, launch_nufft(d, rc, ctx->d_elem, ns, pl.nb, pl.tw, s));
+        }
+      }
+    } else if (bt && pl.matrix) {
       int per_cu = 0;
       HIP_TRY(ctx, mfma_occupancy(rc.P, rc.Q, sh, &per_cu));
       const int groups = std::max(1, per_cu) * ctx->cu_count;
@@ -1078,10 +1206,12 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
   if (o.intra_chirp && o.precision == RSIM_FP64)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the intra-chirp delay is implemented in the "
                 "FP32 sum only");
-  if (o.kernel < RSIM_KERNEL_AUTO || o.kernel > RSIM_KERNEL_MATRIX)
+  if (o.kernel < RSIM_KERNEL_AUTO || o.kernel > RSIM_KERNEL_NUFFT)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: unknown kernel %d", o.kernel);
   if (o.kernel == RSIM_KERNEL_MATRIX && o.precision != RSIM_FP32_PHASE64)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the matrix-core facet sum is FP32 only");
+  if (o.kernel == RSIM_KERNEL_NUFFT && o.precision != RSIM_FP32_PHASE64)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the NUFFT facet sum is FP32 only");
   if (ctx->ground && o.persistent)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the ground bounce runs with plain launches "
                 "(persistent = 0)");
@@ -1103,13 +1233,65 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     if (const char *why = matrix_ineligible(ctx, rcn, o.precision))
       return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
   }
-  const SumPlan pl = plan_sum(ctx, rcn, o);
+  const double r_max = scenes_rmax(ctx, ids);
+  if (o.kernel == RSIM_KERNEL_NUFFT) {
+    NuShape tmp{};
+    if (const char *why = nufft_ineligible(ctx, rcn, o, r_max, &tmp))
+      return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
+  }
+  SumPlan pl = plan_sum(ctx, rcn, o, r_max);
   const TunedShape ts = pl.ts;
-  if (!pl.matrix && !echo_variant_exists(o.precision, ts.mb, ts.ft))
+  if (!pl.matrix && !pl.nufft && !echo_variant_exists(o.precision, ts.mb, ts.ft))
     return fail(ctx, RSIM_EINVAL, "no facet-sum variant with tile_m=%d tile_f=%d", ts.mb, ts.ft);
   if ((rc = need_device(ctx))) return rc;
+  if (pl.nufft) {
+    // twiddles of the grid length and the record buffer (both before any capture);
+    // a reallocated buffer invalidates captured graphs
+    pl.tw = twiddles(ctx, pl.ns.ng, 0, &rc);
+    if (rc) return rc;
+    int64_t stride = 0;
+    for (int32_t id : ids)
+      stride = std::max<int64_t>(stride, ctx->scenes[id].n_facets +
+                                             static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
+    stride = std::max<int64_t>(stride, 1);
+    const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q, ng = pl.ns.ng;
+    const size_t rec_b = nufft_record_bytes(pl.ns.order);
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t per_chirp = stride * (rec_b + 8) + O * ng * 8;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
+    const size_t off_pos = al(chunk * stride * 4);
+    const size_t off_srec = off_pos + al(chunk * stride * 4);
+    const size_t off_grid = off_srec + al(chunk * stride * rec_b);
+    const size_t total = off_grid + chunk * O * ng * 8;
+    const std::array<int64_t, 5> layout{stride, chunk, O, ng, static_cast<int64_t>(rec_b)};
+    bool clear = layout != ctx->nu_layout;
+    if (ctx->nu_buf_bytes < total) {
+      HIP_TRY(ctx, hipDeviceSynchronize());  // earlier launches may still use the buffer
+      dev_free(ctx, ctx->nu_buf);
+      ctx->nu_buf = nullptr;
+      ctx->nu_buf_bytes = 0;
+      ctx->nu_layout = {};
+      if ((rc = dev_alloc(ctx, &ctx->nu_buf, total))) return rc;
+      ctx->nu_buf_bytes = total;
+      clear = true;
+    }
+    char *b = static_cast<char *>(ctx->nu_buf);
+    pl.nb = NuBuffers{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
+                      b + off_srec, reinterpret_cast<float2 *>(b + off_grid)};
+    pl.ns.n_chirps = static_cast<int32_t>(chunk);
+    if (clear) {
+      // the kernels leave the grids zero; a new layout starts from zero (on the
+      // caller's stream, ahead of any launch or graph replay of this call)
+      hipStream_t s0 = static_cast<hipStream_t>(hip_stream);
+      HIP_TRY(ctx, launch_fill_zero(reinterpret_cast<float *>(pl.nb.grid), chunk * O * ng * 2, s0));
+      ctx->nu_layout = layout;
+      ctx->version++;  // captured graphs hold the old pointers
+    }
+  }
   const EchoShape sh = pl.sh;
-  const size_t lds = pl.matrix ? mfma_smem_bytes(sh) : echo_smem_bytes(o.precision, ts.mb, ts.ft, sh);
+  const size_t lds = pl.nufft    ? nufft_smem_bytes(pl.ns)
+                     : pl.matrix ? mfma_smem_bytes(sh)
+                                 : echo_smem_bytes(o.precision, ts.mb, ts.ft, sh);
   if (lds > ctx->max_lds)
     return fail(ctx, RSIM_ERANGE, "facet-sum tile needs %zu bytes of LDS (max %zu)", lds,
                 ctx->max_lds);
@@ -1138,7 +1320,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
         return rc;
       HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed));
       int32_t rc2 = enqueue_synthesis(ctx, ds, o.persistent ? &g.tables : nullptr,
-                                      ctx->capture_stream, o, false);
+                                      ctx->capture_stream, o, false, pl);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
       if (rc2) {
@@ -1168,7 +1350,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       (rc = prepare_batch(ctx, ctx->batch, ids, ds, echo, vis_mask, o.precision, pl.batch_key, sh,
                           s)))
     return rc;
-  return enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing);
+  return enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing, pl);
 }
 
 int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
@@ -1555,25 +1737,39 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
   const int64_t cube = static_cast<int64_t>(O) * rcn.N * rcn.M;
   void *echo = nullptr;
   if ((rc = dev_alloc(ctx, &echo, 8 * cube * n_scenes))) return rc;
-  // vector-unit tiles, then the matrix cores where the array allows them (mb = 0)
+  // vector-unit tiles, then the matrix cores where the array allows them (mb = 0) and
+  // the NUFFT where the scenes allow it (mb = -1)
   struct Cand { int mb, ft; };
   std::vector<Cand> cands = {{16, 16}, {32, 8}, {32, 16}, {64, 8}, {64, 16}};
   if (!matrix_ineligible(ctx, rcn, RSIM_FP32_PHASE64)) cands.push_back({0, 0});
+  {
+    rsim_opts probe{};
+    NuShape ns{};
+    const std::vector<int32_t> ids(scene_ids, scene_ids + n_scenes);
+    for (int32_t id : ids)
+      if ((rc = check_scene(ctx, id))) {
+        dev_free(ctx, echo);
+        return rc;
+      }
+    if (!nufft_ineligible(ctx, rcn, probe, scenes_rmax(ctx, ids), &ns)) cands.push_back({-1, 0});
+  }
   float best = 1e30f;
   TunedShape best_s{32, 16, RSIM_KERNEL_VECTOR};
   hipStream_t s = ctx->capture_stream;
   for (const Cand &c : cands) {
     rsim_opts o{};
     o.timing = 1;
-    if (c.mb) {
+    if (c.mb > 0) {
       o.tile_m = c.mb;
       o.tile_f = c.ft;
       o.kernel = RSIM_KERNEL_VECTOR;
       const EchoShape sh = forward_shape(ctx, rcn, 0, c.mb, c.ft);
       if (echo_smem_bytes(0, c.mb, c.ft, sh) > ctx->max_lds) continue;
-    } else {
+    } else if (c.mb == 0) {
       o.kernel = RSIM_KERNEL_MATRIX;
       if (mfma_smem_bytes(matrix_shape(rcn)) > ctx->max_lds) continue;
+    } else {
+      o.kernel = RSIM_KERNEL_NUFFT;
     }
     float total = 0.0f;
     for (int rep = 0; rep < 3; ++rep) {
@@ -1590,10 +1786,10 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
     }
     if (total < best) {
       best = total;
-      if (c.mb)
+      if (c.mb > 0)
         best_s = TunedShape{c.mb, c.ft, RSIM_KERNEL_VECTOR};
-      else
-        best_s.kernel = RSIM_KERNEL_MATRIX;  // keeps the best vector tiles for opts.kernel = 1
+      else  // keeps the best vector tiles for opts.kernel = 1
+        best_s.kernel = c.mb == 0 ? RSIM_KERNEL_MATRIX : RSIM_KERNEL_NUFFT;
     }
   }
   dev_free(ctx, echo);
@@ -1604,7 +1800,9 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
     if (!f) return fail(ctx, RSIM_EINVAL, "cannot open %s", cache_json_path);
     f << "{\"arch\": \"gfx950\", \"M\": " << rcn.M << ", \"O\": " << O
       << ", \"precision\": \"fp32\", \"kernel\": \""
-      << (best_s.kernel == RSIM_KERNEL_MATRIX ? "matrix" : "vector")
+      << (best_s.kernel == RSIM_KERNEL_MATRIX  ? "matrix"
+          : best_s.kernel == RSIM_KERNEL_NUFFT ? "nufft"
+                                               : "vector")
       << "\", \"tile_m\": " << best_s.mb << ", \"tile_f\": " << best_s.ft
       << ", \"facet_sum_ms\": " << best / 2 << "}\n";
   }

@@ -1,0 +1,495 @@
+// Facet sum as a type-1 non-uniform FFT over the sample index (stop-and-hop, FP32 with
+// FP64 geometry and phases). Same result as the direct sum of Sections 2.2 and 3.2,
+// eqs. (7)-(13), within the spread kernel's error.
+//
+// With the closed-form facet integral written as a divided difference, the term of a
+// lit facet (or point) for channel (p, q) at sample m = m' + M/2 is
+//   T(m) = -amp / (R_t R_r k_m^2) exp(-j 2 pi (f_c tau - mu tau^2 / 2))
+//          DD2_beta[ exp(j k_c beta) exp(-j m' dk (L - beta)) ](beta_0, beta_1, beta_2),
+// with L = R_t + R_r, tau = L / c, f_c = f0 + (M/2) df, k = 2 pi f / c, dk = 2 pi df / c
+// and DD2 the second divided difference over the facet's node offsets beta_v. For every
+// channel the sum over facets is therefore a type-1 transform of sources at path lengths
+// L - beta onto the modes m'. Each source set is spread onto a periodic grid of n_g >= 2M
+// cells with a Gaussian psi(x) = exp(-x^2 / (2 s^2)); the grid position of path length L
+// is x = kappa L with kappa = df n_g / c cells per metre. Expanding psi(l - x_L + kappa
+// beta) in beta turns the facet's spread into
+//   Q(p, q) psi(l - x_L) sum_k b_k (l - x_L)^k,
+//   b_k = -amp / (k_c^2 s^k) sum_{r >= k} D_r (-kappa / s)^r / r! He_{r,k},
+//   D_r = DD2[beta^r exp(j k_c beta)] (Leibniz rule over the stable divided
+//         differences of exp(j k_c beta); He_{r,k} the coefficients of He_r(y)),
+// where only Q = exp(-j 2 pi (f_c tau - mu tau^2/2)) / (R_t R_r) and x_L depend on the
+// channel. A forward FFT of each channel's grid then gives
+//   H(m' + M/2) = U(m') k_c^2 / (k_m^2 psi_hat(2 pi m' / n_g)),
+//   psi_hat(w) = s sqrt(2 pi) exp(-s^2 w^2 / 2).
+//
+// Channel (p, q) differs from the phase-centre path (centres t_c, r_c of the Tx and Rx
+// elements) only through dL = (R_tp - R_tc) + (R_rq - R_rc), a few centimetres. With
+// u the unit vector from t_c to the centroid, a = t_p - t_c and s = u.a, exactly
+//   R_tp - R_tc = -s + e,   e (2 R_tc - 2 s + e) = |a|^2 - s^2 =: h,
+// so e = h / D (1 - h / D^2 + ...) with D = 2 R_tc - 2 s (the next term is below
+// e (h / D^2)^2). s is formed in FP64 and its phase g1 s reduced in FP64; e and the rest
+// in FP32. The phase-centre path itself (delay, reduced phase, grid cell) is FP64, once
+// per entry:
+//   f_c tau - mu tau^2 / 2 = [same at tau_c] + dL g1 - mu dL^2 / (2 c^2),
+//   g1 = (f_c - mu tau_c) / c.
+//
+// Five kernels per chunk of chirps:
+//   key     per (chirp, lit facet or point): grid cell of the phase-centre path;
+//   count   per chirp: counting sort by cell in LDS, giving each entry its position in
+//           cell order (order within a cell is that of the LDS counter, so sums are
+//           reproducible to FP32 rounding only);
+//   prep    per entry: b_k and the phase-centre path (FP64 work, stored as FP32
+//           offsets, reduced phase and grid cell), written at the sorted position;
+//   spread  one wave per (chirp, 64 channels, run of kNuSeg sorted records): each lane
+//           (channel) accumulates a window of kNuSlots cells in registers, with Gaussian
+//           weights from a product recurrence, and adds it to the global grid
+//           [chirp][channel][n_g] only when the sorted positions leave the window (and at
+//           the end of the run);
+//   fft     per (chirp, group of channels): grid rows into LDS (rows zeroed behind),
+//           in-LDS Stockham FFT, deconvolution, echo samples.
+#include "adjoint_common.h"
+#include "echo_common.h"
+#include "fft_common.h"
+
+namespace rsim {
+
+constexpr int kNuFftThreads = 512;
+constexpr int kNuFftSeq = 2;   // channel grids per FFT pass group (the work buffer)
+constexpr int kNuMaxOrder = 10;
+constexpr int kNuSeg = 256;    // sorted records per spread wave
+constexpr int kNuSlots = 20;   // register window of grid cells per lane
+constexpr int kNuSpreadThreads = 256;
+
+template <int R>
+struct alignas(16) NuRec {
+  double ut[3], ur[3];  // unit vectors from t_c and r_c to the centroid c at t_n
+  double g1;            // (f_c - mu tau_c) / c: turns per metre of dL
+  float rt, rr;         // |c - t_c|, |c - r_c|
+  float t0;             // f_c tau_c - mu tau_c^2 / 2 reduced to [-1/2, 1/2] turns
+  float frac;           // grid position of the phase-centre path minus `cell`
+  int32_t cell;         // its grid cell (0 .. n_g - 1)
+  int32_t valid;
+  float2 b[R];          // polynomial coefficients in grid cells (see the header comment)
+};
+static_assert(sizeof(NuRec<5>) == 128 && sizeof(NuRec<7>) == 144 && sizeof(NuRec<10>) == 160,
+              "record size");
+
+size_t nufft_record_bytes(int order) {
+  return order <= 5 ? sizeof(NuRec<5>) : order <= 7 ? sizeof(NuRec<7>) : sizeof(NuRec<10>);
+}
+int nufft_window_cells() { return kNuSlots; }
+int nufft_run_length() { return kNuSeg; }
+
+// Probabilists' Hermite polynomials He_r(y) = sum_k kHe.c[r][k] y^k, from
+// He_{r+1} = y He_r - r He_{r-1}.
+struct HermiteTable {
+  double c[kNuMaxOrder][kNuMaxOrder];
+};
+constexpr HermiteTable make_hermite() {
+  HermiteTable t{};
+  t.c[0][0] = 1.0;
+  t.c[1][1] = 1.0;
+  for (int r = 1; r + 1 < kNuMaxOrder; ++r)
+    for (int k = 0; k < kNuMaxOrder; ++k)
+      t.c[r + 1][k] = (k ? t.c[r][k - 1] : 0.0) - r * t.c[r - 1][k];
+  return t;
+}
+constexpr HermiteTable kHe = make_hermite();
+
+__device__ inline int wrap_cell(int64_t c, int ng) {
+  const int64_t r = c % ng;
+  return static_cast<int>(r < 0 ? r + ng : r);
+}
+
+// Grid position, cell (0 .. n_g - 1) and the two distances of an entry's phase-centre
+// path, FP64.
+__device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuShape &ns,
+                                   double *x_out, int *cell_out, double *Rt, double *Rr) {
+  double dt = 0.0, dr = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    dt += (g.c[k] - rc.tx_c[k]) * (g.c[k] - rc.tx_c[k]);
+    dr += (g.c[k] - rc.rx_c[k]) * (g.c[k] - rc.rx_c[k]);
+  }
+  *Rt = sqrt(dt);
+  *Rr = sqrt(dr);
+  const double x = (*Rt + *Rr) * (1.0 / kC0) * ns.cells_per_s;
+  *x_out = x;
+  *cell_out = wrap_cell(static_cast<int64_t>(floor(x)), ns.ng);
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst rc, NuShape ns,
+                                                        NuBuffers nb) {
+  const int nl = blockIdx.y;
+  const int n = ns.n0 + nl;
+  const int32_t cnt = sc.vis_cnt[n];
+  const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (item >= cnt + sc.n_points) return;
+  Geo g;
+  entry_geometry(sc, rc, n, cnt, item, g);
+  NuRec<R> out;
+  out.valid = g.valid;
+#pragma unroll
+  for (int k = 0; k < R; ++k) out.b[k] = {0.0f, 0.0f};
+  if (g.valid) {
+    const double turns_per_m = ns.fc / kC0;  // k_c / (2 pi)
+    const double A0 = turns_per_m * g.beta[0], A1 = turns_per_m * g.beta[1],
+                 A2 = turns_per_m * g.beta[2];
+    // divided differences of exp(j k_c beta) over beta, divided by k_c^2:
+    // [b0,b1,b2] = -Phi, [b1,b2] = -F[a1,a2] / k_c, [b2] = exp(j k_c b2) / k_c^2
+    // (Phi and F the second and first divided differences of -exp(jx) at a = k_c beta)
+    const double2 phi = phi_turns<double>(A0, A1, A2);
+    const double2 f12 = first_dd<double>(A1, A2);
+    const double ik = 1.0 / ns.kc;
+    double s2, c2;
+    sincospi_t(2.0 * (A2 - rint(A2)), &s2, &c2);
+    const double g2r = -phi.x, g2i = -phi.y;
+    const double g1r = -f12.x * ik, g1i = -f12.y * ik;
+    const double g0r = c2 * ik * ik, g0i = s2 * ik * ik;
+    const double b0 = g.beta[0], b1 = g.beta[1], b2 = g.beta[2];
+    const double e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
+    // a_r = D_r (-kappa / s)^r / r!, D_r = b0^r [b0,b1,b2] + h_{r-1}(b0,b1) [b1,b2]
+    //                                      + h_{r-2}(b0,b1,b2) [b2]
+    double ar[R], ai[R];
+    double p0 = 1.0;                       // b0^r
+    double q1m = 0.0, q1 = 0.0;            // h_{r-2}(b0,b1), h_{r-1}(b0,b1)
+    double t3 = 0.0, t2 = 0.0, t1 = 0.0;   // h_{r-4}, h_{r-3}, h_{r-2} of (b0,b1,b2)
+    double scale = 1.0;                    // (-kappa / s)^r / r!
+    const double step = -ns.kappa / ns.sigma;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r >= 1) {
+        p0 *= b0;
+        const double qn = (r == 1) ? 1.0 : (b0 + b1) * q1 - b0 * b1 * q1m;
+        q1m = q1;
+        q1 = qn;
+        scale *= step / r;
+      }
+      if (r >= 2) {
+        const double tn = (r == 2) ? 1.0 : e1 * t1 - e2 * t2 + e3 * t3;
+        t3 = t2;
+        t2 = t1;
+        t1 = tn;
+      }
+      const double dr = p0 * g2r + q1 * g1r + t1 * g0r;
+      const double di = p0 * g2i + q1 * g1i + t1 * g0i;
+      ar[r] = dr * scale;
+      ai[r] = di * scale;
+    }
+    // b_k = -amp / s^k sum_{r >= k} a_r He_{r,k}
+    double is_k = 1.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int r = k; r < R; ++r) {
+        sr += ar[r] * kHe.c[r][k];
+        si += ai[r] * kHe.c[r][k];
+      }
+      sr *= is_k;
+      si *= is_k;
+      is_k /= ns.sigma;
+      out.b[k] = {static_cast<float>(-(g.amp_re * sr - g.amp_im * si)),
+                  static_cast<float>(-(g.amp_re * si + g.amp_im * sr))};
+    }
+  }
+  // the phase-centre path (FP64; the same cell as the key pass)
+  double x, Rt, Rr;
+  int cell;
+  centre_cell(g, rc, ns, &x, &cell, &Rt, &Rr);
+  for (int k = 0; k < 3; ++k) {
+    out.ut[k] = (g.c[k] - rc.tx_c[k]) / Rt;
+    out.ur[k] = (g.c[k] - rc.rx_c[k]) / Rr;
+  }
+  const double tau = (Rt + Rr) * (1.0 / kC0);
+  const double turns = ns.fc * tau - 0.5 * rc.slope * tau * tau;
+  out.rt = static_cast<float>(Rt);
+  out.rr = static_cast<float>(Rr);
+  out.t0 = static_cast<float>(turns - rint(turns));
+  out.g1 = (ns.fc - rc.slope * tau) * (1.0 / kC0);
+  out.frac = static_cast<float>(x - floor(x));
+  out.cell = cell;
+  const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
+  static_cast<NuRec<R> *>(nb.srec)[row + nb.pos[row + item]] = out;
+}
+
+__global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst rc, NuShape ns,
+                                                       NuBuffers nb) {
+  const int nl = blockIdx.y;
+  const int n = ns.n0 + nl;
+  const int32_t cnt = sc.vis_cnt[n];
+  const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (item >= cnt + sc.n_points) return;
+  Geo g;
+  entry_geometry(sc, rc, n, cnt, item, g);
+  double x, Rt, Rr;
+  int cell;
+  centre_cell(g, rc, ns, &x, &cell, &Rt, &Rr);
+  nb.key[static_cast<int64_t>(nl) * ns.rec_stride + item] = cell;
+}
+
+// Per chirp: LDS counts per cell (the counter's old value is the rank within the cell),
+// exclusive scan, then position = cell offset + rank.
+__global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape ns, NuBuffers nb) {
+  __shared__ int32_t s_cnt[2048];
+  __shared__ int32_t s_part[1024];
+  const int nl = blockIdx.x;
+  const int n = ns.n0 + nl;
+  const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
+  const int32_t *key = nb.key + row;
+  int32_t *pos = nb.pos + row;
+  const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
+  for (int c = threadIdx.x; c < 2048; c += blockDim.x) s_cnt[c] = 0;
+  __syncthreads();
+  for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] = atomicAdd(&s_cnt[key[e]], 1);
+  __syncthreads();
+  // exclusive scan, two cells per thread (n_g <= 2048)
+  const int c0 = 2 * threadIdx.x;
+  const int32_t h0 = s_cnt[c0], h1 = s_cnt[c0 + 1];
+  s_part[threadIdx.x] = h0 + h1;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t v = threadIdx.x >= static_cast<unsigned>(off) ? s_part[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const int32_t base = s_part[threadIdx.x] - h0 - h1;
+  s_cnt[c0] = base;
+  s_cnt[c0 + 1] = base + h0;
+  __syncthreads();
+  for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] += s_cnt[key[e]];
+}
+
+template <int R>
+__global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
+    DevScene sc, RadarConst rc, NuShape ns, const double *elem,
+    const NuRec<R> *__restrict__ sorted, float2 *__restrict__ grids) {
+  const int wave = __builtin_amdgcn_readfirstlane(
+      static_cast<int>(blockIdx.x) * (kNuSpreadThreads / 64) + static_cast<int>(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  // item = (chirp, channel group, run); the runs of a chirp are consecutive
+  const int runs = ns.runs;
+  const int per_chirp = ns.spread_groups * runs;
+  const int nl = wave / per_chirp;
+  if (nl >= ns.n_chirps) return;
+  const int rem = wave - nl * per_chirp;
+  const int grp = rem / runs;
+  const int run = rem - grp * runs;
+  const int n = ns.n0 + nl;
+  const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
+  const int e_begin = run * kNuSeg;
+  if (e_begin >= n_ent) return;
+  const int e_end = min(n_ent, e_begin + kNuSeg);
+  const int ng = ns.ng;
+  const int O = rc.P * rc.Q;
+  const int o = grp * 64 + lane;
+  const bool on = o < O;
+  // this lane's element offsets from the phase centres
+  double at[3], ar[3];
+  float aat, aar;
+  {
+    const int oc = on ? o : 0;
+    const int p = oc / rc.Q, q = oc - p * rc.Q;
+    double st = 0.0, sr = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      at[k] = elem[3 * p + k] - rc.tx_c[k];
+      ar[k] = elem[3 * (rc.P + q) + k] - rc.rx_c[k];
+      st += at[k] * at[k];
+      sr += ar[k] * ar[k];
+    }
+    aat = static_cast<float>(st);
+    aar = static_cast<float>(sr);
+  }
+  const NuRec<R> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
+  float2 *grid = grids + (static_cast<int64_t>(nl) * O + (on ? o : 0)) * ng;
+  const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
+  const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
+  const float kappa = static_cast<float>(ns.kappa);
+  const float g2 = static_cast<float>(0.5 * rc.slope / (kC0 * kC0));
+  const float d = static_cast<float>(ns.chan_d);
+  const int b0 = static_cast<int>(ceilf(d + 0.5f * kNuWidth));  // key offset after a rebase
+  const float rel_hi = static_cast<float>(kNuSlots - 1) - d - 0.5f * kNuWidth;
+  float2 acc[kNuSlots];
+#pragma unroll
+  for (int s = 0; s < kNuSlots; ++s) acc[s] = {0.0f, 0.0f};
+  int base = 0, used_lo = kNuSlots, used_hi = -1;  // wave-uniform
+  bool have_base = false;
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int s = 0; s < kNuSlots; ++s) {
+      if (s >= used_lo && s <= used_hi) {
+        if (on) {
+          // base + s lies in [-ng, 2 ng) (n_g >= 32 > the window)
+          int cell = base + s;
+          cell += (cell < 0) ? ng : 0;
+          cell -= (cell >= ng) ? ng : 0;
+          atomicAdd(&grid[cell].x, acc[s].x);
+          atomicAdd(&grid[cell].y, acc[s].y);
+        }
+        acc[s] = {0.0f, 0.0f};
+      }
+    }
+    used_lo = kNuSlots;
+    used_hi = -1;
+  };
+
+  NuRec<R> nxt = srec[e_begin];
+  for (int i = e_begin; i < e_end; ++i) {
+    const NuRec<R> r = nxt;
+    if (i + 1 < e_end) nxt = srec[i + 1];
+    // window position of the phase-centre path (wrapped cell difference + fraction)
+    int rk = r.cell - base;
+    if (rk > ng / 2) rk -= ng;
+    if (rk < -ng / 2) rk += ng;
+    float rel_c = static_cast<float>(rk) + r.frac;
+    if (!have_base || rel_c < d + 0.5f * kNuWidth || rel_c > rel_hi) {
+      flush();
+      base = r.cell - b0;
+      rel_c = static_cast<float>(b0) + r.frac;
+      have_base = true;
+    }
+    if (!r.valid) continue;
+    // cells some channel reaches: |s - x_o| <= W/2 with |x_o - rel_c| <= d
+    const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - d - 0.5f * kNuWidth)));
+    const int s_hi = __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c + d + 0.5f * kNuWidth)));
+    used_lo = min(used_lo, s_lo);
+    used_hi = max(used_hi, s_hi);
+    // this channel's path difference dL = -(s_t + s_r) + e_t + e_r, amplitude, phase
+    // and grid position
+    const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
+    const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
+    const double ps = (st + sr) * r.g1;  // turns, up to ~25
+    const float pr = static_cast<float>(ps - rint(ps));
+    const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
+    const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
+    const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
+    const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
+    const float qt = ht * rdt, qr = hr * rdr;
+    const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
+    const float dRt = et - sft, dRr = er - sfr;
+    const float dL = dRt + dRr;
+    float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
+    t -= rintf(t);
+    const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
+    const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
+    const float xr = fmaf(kappa, dL, rel_c);
+    float2 cq[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      cq[k] = {qx * r.b[k].x - qy * r.b[k].y, qx * r.b[k].y + qy * r.b[k].x};
+    // Gaussian weights from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)
+    const float u0 = static_cast<float>(s_lo) - xr;
+    float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+    float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+#pragma unroll
+    for (int s = 0; s < kNuSlots; ++s) {
+      if (s >= s_lo && s <= s_hi) {
+        const float xx = static_cast<float>(s) - xr;
+        float pr = cq[R - 1].x, pi = cq[R - 1].y;
+#pragma unroll
+        for (int k = R - 2; k >= 0; --k) {
+          pr = fmaf(pr, xx, cq[k].x);
+          pi = fmaf(pi, xx, cq[k].y);
+        }
+        acc[s].x = fmaf(gw, pr, acc[s].x);
+        acc[s].y = fmaf(gw, pi, acc[s].y);
+        gw *= rho;
+        rho *= q_ratio;
+      }
+    }
+  }
+  flush();
+}
+
+// Per (chirp, group of cb channels): grid rows into LDS (zeroed behind for the next
+// call), forward FFT, deconvolution and the k_c^2 / k_m^2 factor on the M kept modes.
+__global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, RadarConst rc,
+                                                                NuShape ns, NuBuffers nb,
+                                                                const float2 *tw) {
+  extern __shared__ float2 nu_smem[];
+  const int nl = blockIdx.x / ns.groups;
+  const int grp = blockIdx.x - nl * ns.groups;
+  const int n = ns.n0 + nl;
+  const int ld = ns.ld, ng = ns.ng, cb = ns.cb;
+  const int O = rc.P * rc.Q;
+  float2 *lgrid = nu_smem;            // [cb][ld]
+  float2 *work = nu_smem + cb * ld;   // [kNuFftSeq][ld]
+  for (int i = threadIdx.x; i < cb * ng; i += blockDim.x) {
+    const int c = i / ng, l = i - c * ng;
+    const int o = grp * cb + c;
+    float2 v = {0.0f, 0.0f};
+    if (o < O) {
+      float2 *src = nb.grid + (static_cast<int64_t>(nl) * O + o) * ng + l;
+      v = *src;
+      *src = {0.0f, 0.0f};
+    }
+    lgrid[c * ld + l] = v;
+  }
+  __syncthreads();
+  const int M = rc.M;
+  const float s = static_cast<float>(ns.sigma);
+  const float hs2 = 0.5f * s * s;
+  const float inv_norm = static_cast<float>(1.0 / (ns.sigma * 2.5066282746310002));
+  const float w_per_mode = static_cast<float>(2.0 * kPi / ng);
+  float2 *echo = static_cast<float2 *>(sc.echo);
+  for (int c0 = 0; c0 < cb; c0 += kNuFftSeq) {
+    const int nseq = min(kNuFftSeq, cb - c0);
+    float2 *res = stockham(lgrid + c0 * ld, work, ng, nseq, ld, tw);
+    for (int idx = threadIdx.x; idx < nseq * M; idx += blockDim.x) {
+      const int sq = idx / M;
+      const int m = idx - sq * M;
+      const int oo = grp * cb + c0 + sq;
+      if (oo >= O) continue;
+      const int mp = m - M / 2;
+      const float2 u = res[sq * ld + (mp < 0 ? mp + ng : mp)];
+      const float w = w_per_mode * static_cast<float>(mp);
+      const float fr = static_cast<float>(ns.fc / (rc.f0 + m * rc.df));
+      const float corr = fr * fr * inv_norm * __expf(hs2 * w * w);
+      echo[(static_cast<int64_t>(oo) * rc.N + n) * M + m] = {u.x * corr, u.y * corr};
+    }
+    __syncthreads();
+  }
+}
+
+size_t nufft_smem_bytes(const NuShape &ns) {
+  return sizeof(float2) * static_cast<size_t>(ns.cb + kNuFftSeq) * ns.ld;
+}
+
+template <int R>
+hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double *elem,
+                          const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
+  if (ns.n_chirps <= 0) return hipSuccess;
+  const int64_t items = sc.n_facets + sc.n_points;
+  if (items > 0) {
+    dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
+    hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nufft_count_kernel, dim3(ns.n_chirps), dim3(1024), 0, s, sc, ns, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(nufft_prep_kernel<R>, grid, dim3(256), 0, s, sc, rc, ns, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t waves = static_cast<int64_t>(ns.n_chirps) * ns.spread_groups * ns.runs;
+    const int64_t blocks = (waves + kNuSpreadThreads / 64 - 1) / (kNuSpreadThreads / 64);
+    hipLaunchKernelGGL(nufft_spread_kernel<R>, dim3(static_cast<unsigned>(blocks)),
+                       dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
+                       static_cast<const NuRec<R> *>(nb.srec), nb.grid);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
+                     dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
+                     static_cast<const float2 *>(tw));
+  return hipGetLastError();
+}
+
+hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
+                        const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
+  if (ns.order == 5) return launch_nufft_t<5>(sc, rc, elem, ns, nb, tw, s);
+  if (ns.order == 7) return launch_nufft_t<7>(sc, rc, elem, ns, nb, tw, s);
+  if (ns.order == 10) return launch_nufft_t<10>(sc, rc, elem, ns, nb, tw, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rsim

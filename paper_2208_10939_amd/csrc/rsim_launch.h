@@ -54,6 +54,42 @@ hipError_t launch_echo_mfma_persistent(const DevScene *scenes, const int4 *items
                                        const EchoShape &sh, int n_groups, hipStream_t s);
 hipError_t mfma_occupancy(int P, int Q, const EchoShape &sh, int *groups_per_cu);
 
+// facet sum as a type-1 non-uniform FFT over the sample index (FP32, stop-and-hop,
+// single bounce): Gaussian spread of kNuWidth cells with standard deviation kNuSigma
+// cells onto n_g >= 2M cells
+constexpr int kNuWidth = 12;
+constexpr double kNuSigma = 1.1;
+struct NuShape {
+  int32_t ng, ld, cb, groups;  // grid cells, LDS row stride, channels per FFT workgroup, groups
+  int32_t order;               // Taylor terms of the spread (5, 7 or 10)
+  int32_t n0, n_chirps;        // chirps of this launch: n0 .. n0 + n_chirps - 1
+  int32_t runs;                // sorted-entry runs per chirp (one spread wave each)
+  int32_t spread_groups;       // 64-channel groups of the spread
+  int32_t pad;
+  int64_t rec_stride;          // records per chirp (facets + points)
+  double chan_d;               // largest grid offset of a channel from the phase-centre path
+  double fc, kc;               // f0 + (M/2) df; 2 pi fc / c
+  double cells_per_s;          // df ng: grid cells per second of round-trip delay
+  double kappa;                // df ng / c: grid cells per metre of path length
+  double sigma;                // kNuSigma
+};
+// Work buffers of one launch (n_chirps chirps): per (chirp, entry) the grid cell, the
+// position in cell order and the records in that order; grids [chirp][O][ng], zero on
+// entry and left zero.
+struct NuBuffers {
+  int32_t *key;
+  int32_t *pos;
+  void *srec;
+  float2 *grid;
+};
+size_t nufft_record_bytes(int order);
+size_t nufft_smem_bytes(const NuShape &ns);
+int nufft_window_cells();
+int nufft_run_length();
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
+                        const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s);
+
 hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t rows, int M,
                             int conj_in, const void *tw, hipStream_t s);
 hipError_t launch_doppler_fft(int precision, const void *in, void *y_out, void *rdm,

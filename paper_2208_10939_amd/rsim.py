@@ -26,6 +26,7 @@ RSIM_MASK_INPUT = 1
 RSIM_KERNEL_AUTO = 0
 RSIM_KERNEL_VECTOR = 1
 RSIM_KERNEL_MATRIX = 2
+RSIM_KERNEL_NUFFT = 3
 ABI_VERSION = 2
 N_STAGES = 8
 STAGES = ("visibility", "compaction", "facet_sum", "range_fft", "doppler_rdm",

@@ -162,3 +162,53 @@ def test_detect_and_noise_validation_host_only():
     assert L.rsim_add_noise(ctx._h, dummy, 1, 10.0, 1, None, None) == rsim.RSIM_EDEVICE
     ctx.close()
 
+
+
+def test_nufft_refusals_host_only():
+    """The NUFFT facet sum's eligibility is decided on the host before any device work:
+    FP64 is EINVAL; the intra-chirp delay, the ground bounce and facets spanning more
+    than 1.5 grid cells (2 r_max df n_g / c) are ERANGE; an eligible request reaches the
+    missing device."""
+    ctx = _host_ctx()
+    L = rsim.lib()
+    wf = scenes.paper_waveform(256, 8)
+    ctx.set_waveform(wf)
+    arr = scenes.sparse_mimo_12x16(wf, 2)
+    ctx.set_array(arr.tx, arr.rx)
+    fine = scenes.vehicle_mesh("car", 50_000)  # r_max 0.032 m: spread 0.27 cells at M = 256
+    coarse = scenes.vehicle_mesh("car", 300)   # r_max 0.58 m: 4.8 cells
+    ids = []
+    for m in (fine, coarse):
+        mid = ctx.load_mesh(m.verts, m.tris)
+        sid = ctx.create_scene()
+        ctx.add_instance(sid, mid, np.eye(3), np.array([2.0, 30.0, 0.0]), np.zeros(3))
+        ids.append(sid)
+    echo = ctypes.c_void_p(0x1000)
+    one = lambda sid: (ctypes.c_int32 * 1)(sid)
+
+    def call(sid, **kw):
+        o = rsim.Opts(kernel=rsim.RSIM_KERNEL_NUFFT, **kw)
+        return L.rsim_synthesize(ctx._h, one(sid), 1, echo, None, None, ctypes.byref(o))
+
+    assert call(ids[0]) == rsim.RSIM_EDEVICE
+    assert call(ids[0], precision=rsim.RSIM_FP64) == rsim.RSIM_EINVAL
+    assert call(ids[0], intra_chirp=1) == rsim.RSIM_ERANGE
+    assert call(ids[1]) == rsim.RSIM_ERANGE
+    assert b"grid cells" in L.rsim_last_error(ctx._h)
+    both = (ctypes.c_int32 * 2)(*ids)
+    o = rsim.Opts(kernel=rsim.RSIM_KERNEL_NUFFT)
+    assert L.rsim_synthesize(ctx._h, both, 2, echo, None, None, ctypes.byref(o)) == rsim.RSIM_ERANGE
+    # the automatic choice never refuses for this reason
+    o = rsim.Opts()
+    assert L.rsim_synthesize(ctx._h, one(ids[1]), 1, echo, None, None, ctypes.byref(o)) == rsim.RSIM_EDEVICE
+    # n_g = 2M rounded up to 2^a 3^b must stay <= 2048; M >= 16
+    ctx.set_waveform(scenes.paper_waveform(1100, 8))
+    assert call(ids[0]) == rsim.RSIM_ERANGE
+    ctx.set_waveform(scenes.paper_waveform(6, 8))
+    assert call(ids[0]) == rsim.RSIM_ERANGE
+    ctx.set_waveform(wf)
+    ctx.set_ground(True, 0.0, -0.9)
+    assert call(ids[0]) == rsim.RSIM_ERANGE
+    o_bad = rsim.Opts(kernel=4)
+    assert L.rsim_synthesize(ctx._h, one(ids[0]), 1, echo, None, None, ctypes.byref(o_bad)) == rsim.RSIM_EINVAL
+    ctx.close()
