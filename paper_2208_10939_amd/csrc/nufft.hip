@@ -261,6 +261,22 @@ __global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape 
   for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] += s_cnt[key[e]];
 }
 
+// A record read-only for the rest of the kernel, at a wave-uniform address: loaded
+// through the constant address space so that it lands in scalar registers (the
+// compiler cannot prove that atomic adds elsewhere leave global memory unchanged).
+template <typename T>
+__device__ inline T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  using CInt = const __attribute__((address_space(4))) int32_t;
+  CInt *q = (CInt *)p;
+  int32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) w[k] = q[k];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
 template <int R>
 __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,
@@ -313,10 +329,77 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
   float2 acc[kNuSlots];
 #pragma unroll
   for (int s = 0; s < kNuSlots; ++s) acc[s] = {0.0f, 0.0f};
-  int base = 0, used_lo = kNuSlots, used_hi = -1;  // wave-uniform
-  bool have_base = false;
-
-  auto flush = [&]() {
+  // windows: the records that fit one placement of the register window, then a flush;
+  // invalid records carry zero coefficients and need no test
+  int i = e_begin;
+  NuRec<R> nxt = load_uniform(srec + i);
+  while (i < e_end) {
+    const int base = nxt.cell - b0;  // wave-uniform
+    int used_lo = kNuSlots, used_hi = -1;
+    const int first = i;
+    for (; i < e_end; ++i) {
+      const NuRec<R> r = nxt;
+      // window position of the phase-centre path (wrapped cell difference + fraction);
+      // the record that placed the window always fits it (chan_d <= 2.5 cells), and is
+      // taken regardless so that every window makes progress
+      int rk = r.cell - base;
+      if (rk > ng / 2) rk -= ng;
+      if (rk < -ng / 2) rk += ng;
+      const float rel_c = static_cast<float>(rk) + r.frac;
+      if (i > first && (rel_c < d + 0.5f * kNuWidth || rel_c > rel_hi)) break;
+      if (i + 1 < e_end) nxt = load_uniform(srec + i + 1);
+      // cells some channel reaches: |s - x_o| <= W/2 with |x_o - rel_c| <= d
+      const int s_lo =
+          __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - d - 0.5f * kNuWidth)));
+      const int s_hi =
+          __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c + d + 0.5f * kNuWidth)));
+      used_lo = min(used_lo, s_lo);
+      used_hi = max(used_hi, s_hi);
+      // this channel's path difference dL = -(s_t + s_r) + e_t + e_r, amplitude, phase
+      // and grid position
+      const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
+      const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
+      const double ps = (st + sr) * r.g1;  // turns, up to ~25
+      const float pr = static_cast<float>(ps - rint(ps));
+      const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
+      const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
+      const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
+      const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
+      const float qt = ht * rdt, qr = hr * rdr;
+      const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
+      const float dRt = et - sft, dRr = er - sfr;
+      const float dL = dRt + dRr;
+      float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
+      t -= rintf(t);
+      const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
+      const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
+      const float xr = fmaf(kappa, dL, rel_c);
+      float2 cq[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        cq[k] = {qx * r.b[k].x - qy * r.b[k].y, qx * r.b[k].y + qy * r.b[k].x};
+      // Gaussian weights from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)
+      const float u0 = static_cast<float>(s_lo) - xr;
+      float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+      float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+#pragma unroll
+      for (int s = 0; s < kNuSlots; ++s) {
+        if (s >= s_lo && s <= s_hi) {
+          const float xx = static_cast<float>(s) - xr;
+          float pr2 = cq[R - 1].x, pi2 = cq[R - 1].y;
+#pragma unroll
+          for (int k = R - 2; k >= 0; --k) {
+            pr2 = fmaf(pr2, xx, cq[k].x);
+            pi2 = fmaf(pi2, xx, cq[k].y);
+          }
+          acc[s].x = fmaf(gw, pr2, acc[s].x);
+          acc[s].y = fmaf(gw, pi2, acc[s].y);
+          gw *= rho;
+          rho *= q_ratio;
+        }
+      }
+    }
+    // add the window to the grid row and clear it
 #pragma unroll
     for (int s = 0; s < kNuSlots; ++s) {
       if (s >= used_lo && s <= used_hi) {
@@ -331,76 +414,7 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
         acc[s] = {0.0f, 0.0f};
       }
     }
-    used_lo = kNuSlots;
-    used_hi = -1;
-  };
-
-  NuRec<R> nxt = srec[e_begin];
-  for (int i = e_begin; i < e_end; ++i) {
-    const NuRec<R> r = nxt;
-    if (i + 1 < e_end) nxt = srec[i + 1];
-    // window position of the phase-centre path (wrapped cell difference + fraction)
-    int rk = r.cell - base;
-    if (rk > ng / 2) rk -= ng;
-    if (rk < -ng / 2) rk += ng;
-    float rel_c = static_cast<float>(rk) + r.frac;
-    if (!have_base || rel_c < d + 0.5f * kNuWidth || rel_c > rel_hi) {
-      flush();
-      base = r.cell - b0;
-      rel_c = static_cast<float>(b0) + r.frac;
-      have_base = true;
-    }
-    if (!r.valid) continue;
-    // cells some channel reaches: |s - x_o| <= W/2 with |x_o - rel_c| <= d
-    const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - d - 0.5f * kNuWidth)));
-    const int s_hi = __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c + d + 0.5f * kNuWidth)));
-    used_lo = min(used_lo, s_lo);
-    used_hi = max(used_hi, s_hi);
-    // this channel's path difference dL = -(s_t + s_r) + e_t + e_r, amplitude, phase
-    // and grid position
-    const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
-    const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
-    const double ps = (st + sr) * r.g1;  // turns, up to ~25
-    const float pr = static_cast<float>(ps - rint(ps));
-    const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
-    const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
-    const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
-    const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
-    const float qt = ht * rdt, qr = hr * rdr;
-    const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
-    const float dRt = et - sft, dRr = er - sfr;
-    const float dL = dRt + dRr;
-    float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
-    t -= rintf(t);
-    const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
-    const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
-    const float xr = fmaf(kappa, dL, rel_c);
-    float2 cq[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-      cq[k] = {qx * r.b[k].x - qy * r.b[k].y, qx * r.b[k].y + qy * r.b[k].x};
-    // Gaussian weights from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)
-    const float u0 = static_cast<float>(s_lo) - xr;
-    float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
-    float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
-#pragma unroll
-    for (int s = 0; s < kNuSlots; ++s) {
-      if (s >= s_lo && s <= s_hi) {
-        const float xx = static_cast<float>(s) - xr;
-        float pr = cq[R - 1].x, pi = cq[R - 1].y;
-#pragma unroll
-        for (int k = R - 2; k >= 0; --k) {
-          pr = fmaf(pr, xx, cq[k].x);
-          pi = fmaf(pi, xx, cq[k].y);
-        }
-        acc[s].x = fmaf(gw, pr, acc[s].x);
-        acc[s].y = fmaf(gw, pi, acc[s].y);
-        gw *= rho;
-        rho *= q_ratio;
-      }
-    }
   }
-  flush();
 }
 
 // Per (chirp, group of cb channels): grid rows into LDS (zeroed behind for the next
