@@ -732,6 +732,10 @@ std::vector<DevScene> scene_views(rsim_ctx *ctx, const std::vector<int32_t> &ids
     uint32_t *mask = vis_mask ? vis_mask + mask_off : sc.d_mask;
     mask_off += static_cast<int64_t>(ctx->ground ? 4 : 1) * rc.N * ((sc.n_facets + 31) / 32);
     ds[i] = dev_scene(sc, mask, static_cast<char *>(echo) + i * cube * csize);
+    // a traversal keeps at most one pending node per level of its BVH
+    int depth = 0;
+    for (const InstRec &r : sc.inst) depth = std::max(depth, ctx->meshes[r.mesh].depth);
+    ds[i].stack_depth = depth + 1;
   }
   return ds;
 }

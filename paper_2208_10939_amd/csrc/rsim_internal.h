@@ -73,6 +73,8 @@ struct DevScene {
   int32_t *vis_idx;          // [N][n_facets] compacted lit facets per chirp
   int32_t *vis_cnt;          // [N]
   void *echo;                // [O][N][M] complex
+  int32_t stack_depth;       // traversal stack entries per thread (> deepest BVH level)
+  int32_t pad;
 };
 
 }  // namespace rsim

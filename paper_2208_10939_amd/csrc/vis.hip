@@ -10,7 +10,8 @@
 // runs in FP64 on world coordinates; the two shadow rays run in FP32 in each
 // candidate instance's body frame, starting at the facet centroid (close to the
 // occluders, so the FP32 Moller-Trumbore test keeps its precision). Each thread
-// owns a column of an LDS stack (stride = block size, conflict-free).
+// owns a column of an LDS stack (stride = block size, conflict-free) as deep as the
+// scene's deepest BVH, which sets how many waves share a CU.
 #include "rsim_internal.h"
 #include "rsim_launch.h"
 
@@ -31,10 +32,10 @@ __device__ inline int find_instance(const DevInstance *inst, int n_inst, int64_t
 }
 
 __device__ inline bool box_hit(const float *lo, const float *hi, float ox, float oy, float oz,
-                               float ix, float iy, float iz) {
-  float tx0 = (lo[0] - ox) * ix, tx1 = (hi[0] - ox) * ix;
-  float ty0 = (lo[1] - oy) * iy, ty1 = (hi[1] - oy) * iy;
-  float tz0 = (lo[2] - oz) * iz, tz1 = (hi[2] - oz) * iz;
+                               float ix, float iy, float iz, float pad = 0.0f) {
+  float tx0 = (lo[0] - pad - ox) * ix, tx1 = (hi[0] + pad - ox) * ix;
+  float ty0 = (lo[1] - pad - oy) * iy, ty1 = (hi[1] + pad - oy) * iy;
+  float tz0 = (lo[2] - pad - oz) * iz, tz1 = (hi[2] + pad - oz) * iz;
   float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
   float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), 1.0f));
   return tn <= tf;
@@ -185,23 +186,24 @@ __device__ inline bool leaf_hit2(const float4 *leaf, int32_t ref, float ox, floa
 }
 
 // Any-hit traversal of one BLAS for the two body-frame segments o -> o + d1 and
-// o -> o + d2 together: a node is entered when either segment meets its box, so the two
-// nearly parallel shadow rays of a facet share every node fetch.
+// o -> o + d2 together, so the two nearly parallel shadow rays of a facet share every
+// node fetch. A node is entered when the first segment meets its box grown by
+// |d1 - d2| on every side: the points of the two segments at the same parameter are at
+// most that far apart, so this enters every node either segment meets (and a few more);
+// the leaf tests are exact for both segments.
 __device__ bool blas_occluded2(const BvhNode *nodes, const float4 *leaf, float ox, float oy,
                                float oz, const float d[2][3], int32_t skip, int32_t *stack,
                                int stride) {
-  float inv[2][3];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-    for (int k = 0; k < 3; ++k) inv[r][k] = safe_inv(d[r][k]);
+  const float ix = safe_inv(d[0][0]), iy = safe_inv(d[0][1]), iz = safe_inv(d[0][2]);
+  const float ex = d[0][0] - d[1][0], ey = d[0][1] - d[1][1], ez = d[0][2] - d[1][2];
+  // |d1 - d2| rounded up (FP32 sqrt is correctly rounded; the factor covers the rest)
+  const float pad = __builtin_sqrtf(ex * ex + ey * ey + ez * ez) * 1.0001f + 1e-7f;
   int sp = 0;
   int32_t node = 0;
   while (true) {
     const BvhNode nd = nodes[node];
-    const bool h0 = box_hit(nd.lo0, nd.hi0, ox, oy, oz, inv[0][0], inv[0][1], inv[0][2]) ||
-                    box_hit(nd.lo0, nd.hi0, ox, oy, oz, inv[1][0], inv[1][1], inv[1][2]);
-    const bool h1 = box_hit(nd.lo1, nd.hi1, ox, oy, oz, inv[0][0], inv[0][1], inv[0][2]) ||
-                    box_hit(nd.lo1, nd.hi1, ox, oy, oz, inv[1][0], inv[1][1], inv[1][2]);
+    const bool h0 = box_hit(nd.lo0, nd.hi0, ox, oy, oz, ix, iy, iz, pad);
+    const bool h1 = box_hit(nd.lo1, nd.hi1, ox, oy, oz, ix, iy, iz, pad);
     int32_t next = -1;
     if (h0) {
       if (nd.c0 < 0) {
@@ -401,7 +403,7 @@ hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream
   if (sc.n_facets == 0) return hipSuccess;
   const int block = 128;
   dim3 grid(static_cast<unsigned>((sc.n_facets + block - 1) / block), rc.N);
-  const size_t lds = sizeof(int32_t) * kBvhStack * block;
+  const size_t lds = sizeof(int32_t) * static_cast<size_t>(sc.stack_depth) * block;
   hipLaunchKernelGGL(vis_kernel, grid, dim3(block), lds, s, sc, rc);
   return hipGetLastError();
 }
