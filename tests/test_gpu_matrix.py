@@ -156,7 +156,7 @@ def test_matrix_refusals(sim_mod):
         sim.synthesize(precision=1, kernel=MATRIX)
     assert e.value.code == RSIM_EINVAL
     with pytest.raises(RsimError) as e:
-        sim.synthesize(kernel=3)
+        sim.synthesize(kernel=4)
     assert e.value.code == RSIM_EINVAL
     # 13 Tx elements: no compiled tile shape
     tx = np.concatenate([arr.tx, arr.tx[:1] + [0.0, 0.0, 0.002]])
