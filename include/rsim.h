@@ -56,7 +56,7 @@ extern "C" {
                              /* per channel with a Taylor-expanded Gaussian, then an FFT and   */
                              /* deconvolution (relative error ~1e-5 or below). Exact per-      */
                              /* channel distances (no cross-term approximation). Eligible for  */
-                             /* stop-and-hop without the ground bounce, and when every facet   */
+                             /* stop-and-hop (ground bounce included), and when every facet    */
                              /* spans at most 1.5 grid cells: 2 r_max df n_g / c <= 1.5, r_max */
                              /* the largest vertex-to-centroid distance of the scenes' meshes, */
                              /* n_g the smallest 2^a 3^b >= 2M (32 <= n_g <= 2048), and when   */

@@ -488,7 +488,6 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
                              double r_max, NuShape *ns) {
   if (o.precision != RSIM_FP32_PHASE64) return "the NUFFT facet sum is FP32 only";
   if (o.intra_chirp) return "the NUFFT facet sum is stop-and-hop only";
-  if (ctx->ground) return "the NUFFT facet sum covers the single-bounce path only";
   const int ng = smooth_at_least(2 * rc.M);
   if (ng > kNuMaxGrid) return "the NUFFT facet sum needs 2M <= 2048";
   if (ng < 32) return "the NUFFT facet sum needs M >= 16";
@@ -870,7 +869,21 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
       DevScene dk = d;
       dk.mask = d.mask + static_cast<int64_t>(k) * rc.N * d.mask_words;
       HIP_TRY(ctx, launch_compact(dk, rc.N, s));
-      HIP_TRY(ctx, sum_plain(dk, rk, elem, sk));
+      if (pl.nufft) {
+        NuShape ns = pl.ns;
+        ns.accumulate = sk.accumulate;
+        ns.gamma_re = sk.gamma_re;
+        ns.gamma_im = sk.gamma_im;
+        ns.rec_stride = dk.n_facets + dk.n_points;
+        ns.runs = static_cast<int32_t>((ns.rec_stride + nufft_run_length() - 1) / nufft_run_length());
+        for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
+          ns.n0 = n0;
+          ns.n_chirps = std::min(pl.ns.n_chirps, rc.N - n0);
+          HIP_TRY(ctx, launch_nufft(dk, rk, elem, ns, pl.nb, pl.tw, s));
+        }
+      } else {
+        HIP_TRY(ctx, sum_plain(dk, rk, elem, sk));
+      }
     }
   }
   stage_end(ctx, timing, 2, s);

@@ -461,7 +461,15 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
       const float w = w_per_mode * static_cast<float>(mp);
       const float fr = static_cast<float>(ns.fc / (rc.f0 + m * rc.df));
       const float corr = fr * fr * inv_norm * __expf(hs2 * w * w);
-      echo[(static_cast<int64_t>(oo) * rc.N + n) * M + m] = {u.x * corr, u.y * corr};
+      float2 *dst = echo + (static_cast<int64_t>(oo) * rc.N + n) * M + m;
+      if (ns.accumulate) {  // a reflected path type: add gamma x its echo
+        const float gr = static_cast<float>(ns.gamma_re) * corr;
+        const float gi = static_cast<float>(ns.gamma_im) * corr;
+        const float2 h = *dst;
+        *dst = {h.x + gr * u.x - gi * u.y, h.y + gr * u.y + gi * u.x};
+      } else {
+        *dst = {u.x * corr, u.y * corr};
+      }
     }
     __syncthreads();
   }

@@ -72,6 +72,9 @@ struct NuShape {
   double cells_per_s;          // df ng: grid cells per second of round-trip delay
   double kappa;                // df ng / c: grid cells per metre of path length
   double sigma;                // kNuSigma
+  int32_t accumulate;          // 0: write the echo; 1: add gamma x (this path's echo) to it
+  int32_t pad2;
+  double gamma_re, gamma_im;
 };
 // Work buffers of one launch (n_chirps chirps): per (chirp, entry) the grid cell, the
 // position in cell order and the records in that order; grids [chirp][O][ng], zero on

@@ -166,9 +166,9 @@ def test_detect_and_noise_validation_host_only():
 
 def test_nufft_refusals_host_only():
     """The NUFFT facet sum's eligibility is decided on the host before any device work:
-    FP64 is EINVAL; the intra-chirp delay, the ground bounce and facets spanning more
-    than 1.5 grid cells (2 r_max df n_g / c) are ERANGE; an eligible request reaches the
-    missing device."""
+    FP64 is EINVAL; the intra-chirp delay and facets spanning more than 1.5 grid cells
+    (2 r_max df n_g / c) are ERANGE; an eligible request (the ground bounce included)
+    reaches the missing device."""
     ctx = _host_ctx()
     L = rsim.lib()
     wf = scenes.paper_waveform(256, 8)
@@ -207,8 +207,8 @@ def test_nufft_refusals_host_only():
     ctx.set_waveform(scenes.paper_waveform(6, 8))
     assert call(ids[0]) == rsim.RSIM_ERANGE
     ctx.set_waveform(wf)
-    ctx.set_ground(True, 0.0, -0.9)
-    assert call(ids[0]) == rsim.RSIM_ERANGE
+    ctx.set_ground(True, 0.0, -0.9)  # the four path types run as four NUFFT passes
+    assert call(ids[0]) == rsim.RSIM_EDEVICE
     o_bad = rsim.Opts(kernel=4)
     assert L.rsim_synthesize(ctx._h, one(ids[0]), 1, echo, None, None, ctypes.byref(o_bad)) == rsim.RSIM_EINVAL
     ctx.close()
