@@ -56,12 +56,13 @@ extern "C" {
                              /* per channel with a Taylor-expanded Gaussian, then an FFT and   */
                              /* deconvolution (relative error ~1e-5 or below). Exact per-      */
                              /* channel distances (no cross-term approximation). Eligible for  */
-                             /* stop-and-hop (ground bounce included), and when every facet    */
-                             /* spans at most 1.5 grid cells: 2 r_max df n_g / c <= 1.5, r_max */
-                             /* the largest vertex-to-centroid distance of the scenes' meshes, */
-                             /* n_g the smallest 2^a 3^b >= 2M (32 <= n_g <= 2048), and when   */
-                             /* every channel's path stays within 2.5 grid cells of the phase- */
-                             /* centre path (array aperture).                                  */
+                             /* stop-and-hop (ground bounce included) with n_g = the smallest   */
+                             /* 2^a 3^b >= 2M in 32..2048 and every channel's path within 2.5  */
+                             /* grid cells of the phase-centre path (array aperture). Facets   */
+                             /* spanning more than 1.5 grid cells (2 r_max df n_g / c, r_max   */
+                             /* the largest vertex-to-centroid distance of the scenes' meshes) */
+                             /* are split into 4, 16 or 64 midpoint sub-triangles; beyond 12   */
+                             /* cells the kernel is ineligible.                                */
 
 /* visibility-mask mode */
 #define RSIM_MASK_COMPUTE 0 /* compute the lit-facet mask; write it to vis_mask if given */

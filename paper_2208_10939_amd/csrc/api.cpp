@@ -461,6 +461,7 @@ EchoShape matrix_shape(const RadarConst &rc) {
 
 // NUFFT facet sum: largest facet spread on the grid (cells) and grid length.
 constexpr double kNuMaxSpread = 1.5;
+constexpr int kNuMaxSplit = 3;
 constexpr int kNuMaxGrid = 2048;
 constexpr size_t kNuRecBudget = size_t(4) << 30;  // work buffer: chirps per launch cap
 
@@ -492,8 +493,15 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
   if (ng > kNuMaxGrid) return "the NUFFT facet sum needs 2M <= 2048";
   if (ng < 32) return "the NUFFT facet sum needs M >= 16";
   const double kappa = rc.df * ng / kC0;
-  const double spread = 2.0 * r_max * kappa;
-  if (spread > kNuMaxSpread) return "facets span more than 1.5 NUFFT grid cells";
+  // facets spanning more than 1.5 grid cells are split into 4^split midpoint sub-triangles
+  // (halving the span per level), at most 64
+  double spread = 2.0 * r_max * kappa;
+  int split = 0;
+  while (spread > kNuMaxSpread && split < kNuMaxSplit) {
+    spread *= 0.5;
+    ++split;
+  }
+  if (spread > kNuMaxSpread) return "facets span more than 12 NUFFT grid cells";
   // every channel's grid position lies within chan_cells of the phase-centre path's
   double et = 0.0, er = 0.0;
   for (int p = 0; p < rc.P; ++p) {
@@ -531,6 +539,7 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
   s.kappa = kappa;
   s.sigma = kNuSigma;
   s.chan_d = chan_d;
+  s.split = split;
   s.spread_groups = (O + 63) / 64;
   s.n0 = 0;
   s.n_chirps = rc.N;
@@ -819,7 +828,7 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
       // per scene, in chirp chunks that fit the record buffer (batched calls included)
       for (const DevScene &d : ds) {
         NuShape ns = pl.ns;
-        ns.rec_stride = d.n_facets + d.n_points;
+        ns.rec_stride = (d.n_facets << (2 * ns.split)) + d.n_points;
         for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
           ns.n0 = n0;
           ns.n_chirps = std::min(pl.ns.n_chirps, rc.N - n0);
@@ -874,7 +883,7 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
         ns.accumulate = sk.accumulate;
         ns.gamma_re = sk.gamma_re;
         ns.gamma_im = sk.gamma_im;
-        ns.rec_stride = dk.n_facets + dk.n_points;
+        ns.rec_stride = (dk.n_facets << (2 * ns.split)) + dk.n_points;
         ns.runs = static_cast<int32_t>((ns.rec_stride + nufft_run_length() - 1) / nufft_run_length());
         for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
           ns.n0 = n0;
@@ -1268,7 +1277,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     if (rc) return rc;
     int64_t stride = 0;
     for (int32_t id : ids)
-      stride = std::max<int64_t>(stride, ctx->scenes[id].n_facets +
+      stride = std::max<int64_t>(stride, (ctx->scenes[id].n_facets << (2 * pl.ns.split)) +
                                              static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
     stride = std::max<int64_t>(stride, 1);
     const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q, ng = pl.ns.ng;

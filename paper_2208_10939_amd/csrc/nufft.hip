@@ -101,10 +101,12 @@ __device__ inline int wrap_cell(int64_t c, int ng) {
   return static_cast<int>(r < 0 ? r + ng : r);
 }
 
-// Grid position, cell (0 .. n_g - 1) and the two distances of an entry's phase-centre
-// path, FP64.
+// Grid position and cell (0 .. n_g - 1) of a source on the phase-centre path of an entry,
+// shifted by the node offset bc of a sub-triangle's centroid (x = kappa (L - bc)), and the
+// two distances of that path; FP64.
 __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuShape &ns,
-                                   double *x_out, int *cell_out, double *Rt, double *Rr) {
+                                   double bc, double *x_out, int *cell_out, double *Rt,
+                                   double *Rr) {
   double dt = 0.0, dr = 0.0;
   for (int k = 0; k < 3; ++k) {
     dt += (g.c[k] - rc.tx_c[k]) * (g.c[k] - rc.tx_c[k]);
@@ -112,9 +114,52 @@ __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuS
   }
   *Rt = sqrt(dt);
   *Rr = sqrt(dr);
-  const double x = (*Rt + *Rr) * (1.0 / kC0) * ns.cells_per_s;
+  const double x = (*Rt + *Rr) * (1.0 / kC0) * ns.cells_per_s - ns.kappa * bc;
   *x_out = x;
   *cell_out = wrap_cell(static_cast<int64_t>(floor(x)), ns.ng);
+}
+
+// Record `rec` of a chirp with `cnt` lit facets: facet records first (4^split per lit
+// facet), then one per point. Returns the entry (lit facet or point) and the sub-triangle.
+__device__ inline int32_t record_entry(int32_t rec, int32_t cnt, int split, int *sub) {
+  const int32_t subs = 1 << (2 * split);
+  if (rec < cnt * subs) {
+    *sub = rec & (subs - 1);
+    return rec >> (2 * split);
+  }
+  *sub = -1;  // a point: not split
+  return cnt + (rec - cnt * subs);
+}
+
+// Node offsets of sub-triangle `sub` (base-4 digits, most significant first; each digit
+// picks one of the four midpoint sub-triangles) of a facet with node offsets beta about its
+// centroid: offsets are linear in position, so a midpoint's is the mean of its ends.
+// Returns the offset of the sub-triangle's centroid; out[] = its nodes about that centroid.
+__device__ inline double sub_nodes(const double beta[3], int sub, int split, double out[3]) {
+  double p0 = beta[0], p1 = beta[1], p2 = beta[2];
+  for (int l = split - 1; l >= 0; --l) {
+    const int d = (sub >> (2 * l)) & 3;
+    const double m01 = 0.5 * (p0 + p1), m12 = 0.5 * (p1 + p2), m20 = 0.5 * (p2 + p0);
+    if (d == 0) {
+      p1 = m01;
+      p2 = m20;
+    } else if (d == 1) {
+      p0 = m01;
+      p2 = m12;
+    } else if (d == 2) {
+      p0 = m20;
+      p1 = m12;
+    } else {
+      p0 = m01;
+      p1 = m12;
+      p2 = m20;
+    }
+  }
+  const double c = (p0 + p1 + p2) * (1.0 / 3.0);
+  out[0] = p0 - c;
+  out[1] = p1 - c;
+  out[2] = p2 - c;
+  return c;
 }
 
 template <int R>
@@ -124,17 +169,33 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
   const int n = ns.n0 + nl;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (item >= cnt + sc.n_points) return;
+  if (item >= (cnt << (2 * ns.split)) + sc.n_points) return;
+  int sub;
+  const int32_t entry = record_entry(item, cnt, ns.split, &sub);
   Geo g;
-  entry_geometry(sc, rc, n, cnt, item, g);
+  entry_geometry(sc, rc, n, cnt, entry, g);
+  // a sub-triangle: its own nodes, a source shifted by its centroid's offset bc (the
+  // factor exp(j k_c bc) goes into the coefficients) and 4^-split of the area
+  double beta[3] = {g.beta[0], g.beta[1], g.beta[2]};
+  double bc = 0.0;
+  if (sub >= 0 && ns.split > 0) {
+    bc = sub_nodes(g.beta, sub, ns.split, beta);
+    const double scale = 1.0 / static_cast<double>(1 << (2 * ns.split));
+    double sb, cb;
+    const double tb = ns.fc / kC0 * bc;
+    sincospi_t(2.0 * (tb - rint(tb)), &sb, &cb);
+    const double ar = g.amp_re * scale, ai = g.amp_im * scale;
+    g.amp_re = ar * cb - ai * sb;
+    g.amp_im = ar * sb + ai * cb;
+  }
   NuRec<R> out;
   out.valid = g.valid;
 #pragma unroll
   for (int k = 0; k < R; ++k) out.b[k] = {0.0f, 0.0f};
   if (g.valid) {
     const double turns_per_m = ns.fc / kC0;  // k_c / (2 pi)
-    const double A0 = turns_per_m * g.beta[0], A1 = turns_per_m * g.beta[1],
-                 A2 = turns_per_m * g.beta[2];
+    const double A0 = turns_per_m * beta[0], A1 = turns_per_m * beta[1],
+                 A2 = turns_per_m * beta[2];
     // divided differences of exp(j k_c beta) over beta, divided by k_c^2:
     // [b0,b1,b2] = -Phi, [b1,b2] = -F[a1,a2] / k_c, [b2] = exp(j k_c b2) / k_c^2
     // (Phi and F the second and first divided differences of -exp(jx) at a = k_c beta)
@@ -146,7 +207,7 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
     const double g2r = -phi.x, g2i = -phi.y;
     const double g1r = -f12.x * ik, g1i = -f12.y * ik;
     const double g0r = c2 * ik * ik, g0i = s2 * ik * ik;
-    const double b0 = g.beta[0], b1 = g.beta[1], b2 = g.beta[2];
+    const double b0 = beta[0], b1 = beta[1], b2 = beta[2];
     const double e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
     // a_r = D_r (-kappa / s)^r / r!, D_r = b0^r [b0,b1,b2] + h_{r-1}(b0,b1) [b1,b2]
     //                                      + h_{r-2}(b0,b1,b2) [b2]
@@ -193,10 +254,11 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
                   static_cast<float>(-(g.amp_re * si + g.amp_im * sr))};
     }
   }
-  // the phase-centre path (FP64; the same cell as the key pass)
+  // the phase-centre path (FP64), and the source position on the grid (the same cell as
+  // the key pass)
   double x, Rt, Rr;
   int cell;
-  centre_cell(g, rc, ns, &x, &cell, &Rt, &Rr);
+  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr);
   for (int k = 0; k < 3; ++k) {
     out.ut[k] = (g.c[k] - rc.tx_c[k]) / Rt;
     out.ur[k] = (g.c[k] - rc.rx_c[k]) / Rr;
@@ -219,12 +281,16 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst 
   const int n = ns.n0 + nl;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (item >= cnt + sc.n_points) return;
+  if (item >= (cnt << (2 * ns.split)) + sc.n_points) return;
+  int sub;
+  const int32_t entry = record_entry(item, cnt, ns.split, &sub);
   Geo g;
-  entry_geometry(sc, rc, n, cnt, item, g);
+  entry_geometry(sc, rc, n, cnt, entry, g);
+  double nodes[3], bc = 0.0;
+  if (sub >= 0 && ns.split > 0) bc = sub_nodes(g.beta, sub, ns.split, nodes);
   double x, Rt, Rr;
   int cell;
-  centre_cell(g, rc, ns, &x, &cell, &Rt, &Rr);
+  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr);
   nb.key[static_cast<int64_t>(nl) * ns.rec_stride + item] = cell;
 }
 
@@ -238,7 +304,7 @@ __global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape 
   const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
   const int32_t *key = nb.key + row;
   int32_t *pos = nb.pos + row;
-  const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
+  const int32_t n_ent = (sc.vis_cnt[n] << (2 * ns.split)) + sc.n_points;
   for (int c = threadIdx.x; c < 2048; c += blockDim.x) s_cnt[c] = 0;
   __syncthreads();
   for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] = atomicAdd(&s_cnt[key[e]], 1);
@@ -293,7 +359,7 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
   const int grp = rem / runs;
   const int run = rem - grp * runs;
   const int n = ns.n0 + nl;
-  const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
+  const int32_t n_ent = (sc.vis_cnt[n] << (2 * ns.split)) + sc.n_points;
   const int e_begin = run * kNuSeg;
   if (e_begin >= n_ent) return;
   const int e_end = min(n_ent, e_begin + kNuSeg);
@@ -483,7 +549,7 @@ template <int R>
 hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
   if (ns.n_chirps <= 0) return hipSuccess;
-  const int64_t items = sc.n_facets + sc.n_points;
+  const int64_t items = (sc.n_facets << (2 * ns.split)) + sc.n_points;
   if (items > 0) {
     dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
     hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);

@@ -65,8 +65,8 @@ struct NuShape {
   int32_t n0, n_chirps;        // chirps of this launch: n0 .. n0 + n_chirps - 1
   int32_t runs;                // sorted-entry runs per chirp (one spread wave each)
   int32_t spread_groups;       // 64-channel groups of the spread
-  int32_t pad;
-  int64_t rec_stride;          // records per chirp (facets + points)
+  int32_t split;               // facets split into 4^split sub-triangles (midpoints)
+  int64_t rec_stride;          // records per chirp (facets x 4^split + points)
   double chan_d;               // largest grid offset of a channel from the phase-centre path
   double fc, kc;               // f0 + (M/2) df; 2 pi fc / c
   double cells_per_s;          // df ng: grid cells per second of round-trip delay

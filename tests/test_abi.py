@@ -166,9 +166,9 @@ def test_detect_and_noise_validation_host_only():
 
 def test_nufft_refusals_host_only():
     """The NUFFT facet sum's eligibility is decided on the host before any device work:
-    FP64 is EINVAL; the intra-chirp delay and facets spanning more than 1.5 grid cells
-    (2 r_max df n_g / c) are ERANGE; an eligible request (the ground bounce included)
-    reaches the missing device."""
+    FP64 is EINVAL; the intra-chirp delay and facets spanning more than 12 grid cells
+    (2 r_max df n_g / c; up to that they are split) are ERANGE; an eligible request (the
+    ground bounce and split facets included) reaches the missing device."""
     ctx = _host_ctx()
     L = rsim.lib()
     wf = scenes.paper_waveform(256, 8)
@@ -176,7 +176,8 @@ def test_nufft_refusals_host_only():
     arr = scenes.sparse_mimo_12x16(wf, 2)
     ctx.set_array(arr.tx, arr.rx)
     fine = scenes.vehicle_mesh("car", 50_000)  # r_max 0.032 m: spread 0.27 cells at M = 256
-    coarse = scenes.vehicle_mesh("car", 300)   # r_max 0.58 m: 4.8 cells
+    coarse = scenes.box_mesh((-2.0, -2.0, 0.0), (2.0, 2.0, 2.0), (1, 1, 1))  # 12 triangles,
+    # r_max 3.0 m: 25 cells, beyond 64 sub-triangles
     ids = []
     for m in (fine, coarse):
         mid = ctx.load_mesh(m.verts, m.tris)
@@ -198,6 +199,11 @@ def test_nufft_refusals_host_only():
     both = (ctypes.c_int32 * 2)(*ids)
     o = rsim.Opts(kernel=rsim.RSIM_KERNEL_NUFFT)
     assert L.rsim_synthesize(ctx._h, both, 2, echo, None, None, ctypes.byref(o)) == rsim.RSIM_ERANGE
+    # 300 triangles (r_max 0.58 m, 4.8 cells): split into 16 sub-triangles, eligible
+    mid = ctx.load_mesh(scenes.vehicle_mesh("car", 300).verts, scenes.vehicle_mesh("car", 300).tris)
+    sid = ctx.create_scene()
+    ctx.add_instance(sid, mid, np.eye(3), np.array([2.0, 30.0, 0.0]), np.zeros(3))
+    assert call(sid) == rsim.RSIM_EDEVICE
     # the automatic choice never refuses for this reason
     o = rsim.Opts()
     assert L.rsim_synthesize(ctx._h, one(ids[1]), 1, echo, None, None, ctypes.byref(o)) == rsim.RSIM_EDEVICE

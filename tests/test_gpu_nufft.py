@@ -43,7 +43,9 @@ def _subarray(arr, P, Q):
     (1500, 96, 12, 16),   # grid 192 = 2^6 3, 10 Taylor terms (spread bound 0.62 cells)
     (6000, 300, 3, 5),    # grid 648 = 2^3 3^4, ragged M, 10 terms (bound 1.0)
     (6000, 128, 1, 1),    # one channel
-    (50000, 64, 12, 16),  # grid 128, 6 terms (bound 0.07)
+    (50000, 64, 12, 16),  # grid 128, 5 terms (bound 0.07)
+    (1500, 300, 4, 6),    # bound 2.1 cells: facets split in 4 (1.04 cells, 10 terms)
+    (300, 256, 12, 16),   # bound 4.8 cells: facets split in 16 (1.2 cells, 10 terms)
 ])
 def test_nufft_against_oracle(sim_mod, n_tris, M, P, Q):
     cfg = scenes.small_single(n_samples=M, n_chirps=2, n_tris=n_tris)
@@ -58,6 +60,28 @@ def test_nufft_against_oracle(sim_mod, n_tris, M, P, Q):
     err = rel_rms(Hn, Ho)
     worst = float(np.max(np.abs(Hn - Ho)) / np.max(np.abs(Ho)))
     _log(f"  lit/chirp={omask.sum(1)} rel_rms={err:.3e} max|err|/max|H|={worst:.3e}")
+    assert err <= FP32_TOL
+
+
+def test_nufft_batched_coarse_meshes(sim_mod):
+    """The batched workload's meshes (1-20 vehicles of coarse to fine hulls per scene)
+    need split facets; one call over three scenes against the oracle on one of them and
+    the matrix cores on all."""
+    _log("case nufft sum on 3 scenes of the batched workload (split facets)")
+    cfg = scenes.c4(n_scenes=3, n_samples=256, n_chirps=2)  # scene 0 spans 2.2 cells: split
+    sim = sim_mod.Simulator(cfg.scenes, cfg.waveform, cfg.array)
+    mask = sim.mask_buffer()
+    Hm = sim.synthesize(mask=mask, kernel=MATRIX).cpu().numpy()
+    Hn = sim.synthesize(mask=mask, mask_mode=1, kernel=NUFFT).cpu().numpy()
+    d = rel_rms(Hn, Hm)
+    _log(f"  triangles {[s.n_tris for s in cfg.scenes]} nufft vs matrix cores {d:.3e}")
+    assert d <= FP32_TOL
+    k = int(np.argmin([s.n_tris for s in cfg.scenes]))
+    om = sim.masks_numpy(mask)[k]
+    Ho = oracle.synthesize(cfg.scenes[k], cfg.waveform, cfg.array, mask=om,
+                           channels=np.arange(0, cfg.array.n_channels, 7))
+    err = rel_rms(Hn[k][np.arange(0, cfg.array.n_channels, 7)], Ho)
+    _log(f"  scene {k} ({cfg.scenes[k].n_tris} triangles) vs oracle rel_rms={err:.3e}")
     assert err <= FP32_TOL
 
 
@@ -176,8 +200,11 @@ def test_nufft_refusals(sim_mod):
     with pytest.raises(RsimError) as e:
         sim.synthesize(kernel=NUFFT, intra_chirp=True)
     assert e.value.code == RSIM_ERANGE
-    # 300 triangles (r_max 0.58 m) at M = 256: the facets span ~4.8 grid cells
-    big = scenes.small_single(n_samples=256, n_chirps=2, n_tris=300).scenes[0]
+    # a 4 m box of 12 triangles at M = 256: the facets span ~25 grid cells, beyond the
+    # 64 sub-triangles of the deepest split
+    box = scenes.box_mesh((-2.0, -2.0, 0.0), (2.0, 2.0, 2.0), (1, 1, 1))
+    big = scenes.Scene(meshes=[box], instances=[scenes.Instance(
+        mesh=0, rot=np.eye(3), pos0=np.array([2.0, 30.0, 0.0]), vel=np.zeros(3))])
     sim2 = sim_mod.Simulator([big], scenes.paper_waveform(256, 2), arr)
     with pytest.raises(RsimError) as e:
         sim2.synthesize(kernel=NUFFT)
