@@ -327,22 +327,6 @@ __global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape 
   for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] += s_cnt[key[e]];
 }
 
-// A record read-only for the rest of the kernel, at a wave-uniform address: loaded
-// through the constant address space so that it lands in scalar registers (the
-// compiler cannot prove that atomic adds elsewhere leave global memory unchanged).
-template <typename T>
-__device__ inline T load_uniform(const T *p) {
-  static_assert(sizeof(T) % 4 == 0, "whole dwords");
-  using CInt = const __attribute__((address_space(4))) int32_t;
-  CInt *q = (CInt *)p;
-  int32_t w[sizeof(T) / 4];
-#pragma unroll
-  for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) w[k] = q[k];
-  T out;
-  __builtin_memcpy(&out, w, sizeof(T));
-  return out;
-}
-
 template <int R>
 __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,

@@ -49,6 +49,22 @@ struct DevInstance {
   int32_t pad;
 };
 
+// A value read-only for the rest of the kernel, at a wave-uniform address: loaded through
+// the constant address space so that it lands in scalar registers (the compiler cannot
+// otherwise prove that stores or atomics elsewhere in the kernel leave it unchanged).
+template <typename T>
+__device__ inline T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "whole dwords");
+  using CInt = const __attribute__((address_space(4))) int32_t;
+  CInt *q = (CInt *)p;
+  int32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) w[k] = q[k];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
 // Radar constants passed by value.
 struct RadarConst {
   double f0, slope, fs, df, tc;  // df = slope / fs
