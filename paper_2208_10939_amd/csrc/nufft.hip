@@ -54,7 +54,6 @@
 namespace rsim {
 
 constexpr int kNuFftThreads = 512;
-constexpr int kNuFftSeq = 2;   // channel grids per FFT pass group (the work buffer)
 constexpr int kNuMaxOrder = 10;
 constexpr int kNuSeg = 256;    // sorted records per spread wave
 constexpr int kNuSlots = 20;   // register window of grid cells per lane
@@ -468,7 +467,8 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
 }
 
 // Per (chirp, group of cb channels): grid rows into LDS (zeroed behind for the next
-// call), forward FFT, deconvolution and the k_c^2 / k_m^2 factor on the M kept modes.
+// call), forward FFT of all cb rows together (ping-pong buffers of cb rows), deconvolution
+// and the k_c^2 / k_m^2 factor on the M kept modes.
 __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, RadarConst rc,
                                                                 NuShape ns, NuBuffers nb,
                                                                 const float2 *tw) {
@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
   const int ld = ns.ld, ng = ns.ng, cb = ns.cb;
   const int O = rc.P * rc.Q;
   float2 *lgrid = nu_smem;            // [cb][ld]
-  float2 *work = nu_smem + cb * ld;   // [kNuFftSeq][ld]
+  float2 *work = nu_smem + cb * ld;   // [cb][ld]
   for (int i = threadIdx.x; i < cb * ng; i += blockDim.x) {
     const int c = i / ng, l = i - c * ng;
     const int o = grp * cb + c;
@@ -498,35 +498,31 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
   const float inv_norm = static_cast<float>(1.0 / (ns.sigma * 2.5066282746310002));
   const float w_per_mode = static_cast<float>(2.0 * kPi / ng);
   float2 *echo = static_cast<float2 *>(sc.echo);
-  for (int c0 = 0; c0 < cb; c0 += kNuFftSeq) {
-    const int nseq = min(kNuFftSeq, cb - c0);
-    float2 *res = stockham(lgrid + c0 * ld, work, ng, nseq, ld, tw);
-    for (int idx = threadIdx.x; idx < nseq * M; idx += blockDim.x) {
-      const int sq = idx / M;
-      const int m = idx - sq * M;
-      const int oo = grp * cb + c0 + sq;
-      if (oo >= O) continue;
-      const int mp = m - M / 2;
-      const float2 u = res[sq * ld + (mp < 0 ? mp + ng : mp)];
-      const float w = w_per_mode * static_cast<float>(mp);
-      const float fr = static_cast<float>(ns.fc / (rc.f0 + m * rc.df));
-      const float corr = fr * fr * inv_norm * __expf(hs2 * w * w);
-      float2 *dst = echo + (static_cast<int64_t>(oo) * rc.N + n) * M + m;
-      if (ns.accumulate) {  // a reflected path type: add gamma x its echo
-        const float gr = static_cast<float>(ns.gamma_re) * corr;
-        const float gi = static_cast<float>(ns.gamma_im) * corr;
-        const float2 h = *dst;
-        *dst = {h.x + gr * u.x - gi * u.y, h.y + gr * u.y + gi * u.x};
-      } else {
-        *dst = {u.x * corr, u.y * corr};
-      }
+  const float2 *res = stockham(lgrid, work, ng, cb, ld, tw);
+  for (int idx = threadIdx.x; idx < cb * M; idx += blockDim.x) {
+    const int sq = idx / M;
+    const int m = idx - sq * M;
+    const int oo = grp * cb + sq;
+    if (oo >= O) continue;
+    const int mp = m - M / 2;
+    const float2 u = res[sq * ld + (mp < 0 ? mp + ng : mp)];
+    const float w = w_per_mode * static_cast<float>(mp);
+    const float fr = static_cast<float>(ns.fc / (rc.f0 + m * rc.df));
+    const float corr = fr * fr * inv_norm * __expf(hs2 * w * w);
+    float2 *dst = echo + (static_cast<int64_t>(oo) * rc.N + n) * M + m;
+    if (ns.accumulate) {  // a reflected path type: add gamma x its echo
+      const float gr = static_cast<float>(ns.gamma_re) * corr;
+      const float gi = static_cast<float>(ns.gamma_im) * corr;
+      const float2 h = *dst;
+      *dst = {h.x + gr * u.x - gi * u.y, h.y + gr * u.y + gi * u.x};
+    } else {
+      *dst = {u.x * corr, u.y * corr};
     }
-    __syncthreads();
   }
 }
 
 size_t nufft_smem_bytes(const NuShape &ns) {
-  return sizeof(float2) * static_cast<size_t>(ns.cb + kNuFftSeq) * ns.ld;
+  return sizeof(float2) * static_cast<size_t>(2 * ns.cb) * ns.ld;
 }
 
 template <int R>
