@@ -555,6 +555,7 @@ struct SumPlan {
   EchoShape sh{};
   NuShape ns{};         // NUFFT: shape; n_chirps = chirps per launch
   NuBuffers nb{};       // NUFFT: work buffers
+  std::vector<int32_t> nu_split, nu_order;  // NUFFT: per scene of the call
   const void *tw = nullptr;  // NUFFT: twiddles of the grid length
   int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
 };
@@ -826,8 +827,11 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     stage_begin(ctx, timing, 2, s);
     if (pl.nufft) {
       // per scene, in chirp chunks that fit the record buffer (batched calls included)
-      for (const DevScene &d : ds) {
+      for (size_t i = 0; i < ds.size(); ++i) {
+        const DevScene &d = ds[i];
         NuShape ns = pl.ns;
+        ns.split = pl.nu_split[i];
+        ns.order = pl.nu_order[i];
         ns.rec_stride = (d.n_facets << (2 * ns.split)) + d.n_points;
         for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
           ns.n0 = n0;
@@ -874,12 +878,14 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     }
     sk.gamma_re = gr;
     sk.gamma_im = gi;
-    for (const DevScene &d : ds) {
-      DevScene dk = d;
-      dk.mask = d.mask + static_cast<int64_t>(k) * rc.N * d.mask_words;
+    for (size_t i = 0; i < ds.size(); ++i) {
+      DevScene dk = ds[i];
+      dk.mask = ds[i].mask + static_cast<int64_t>(k) * rc.N * ds[i].mask_words;
       HIP_TRY(ctx, launch_compact(dk, rc.N, s));
       if (pl.nufft) {
         NuShape ns = pl.ns;
+        ns.split = pl.nu_split[i];
+        ns.order = pl.nu_order[i];
         ns.accumulate = sk.accumulate;
         ns.gamma_re = sk.gamma_re;
         ns.gamma_im = sk.gamma_im;
@@ -1275,13 +1281,29 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     // a reallocated buffer invalidates captured graphs
     pl.tw = twiddles(ctx, pl.ns.ng, 0, &rc);
     if (rc) return rc;
+    // split level and Taylor order per scene (from its own meshes); the buffers hold the
+    // largest scene at the largest record
     int64_t stride = 0;
-    for (int32_t id : ids)
-      stride = std::max<int64_t>(stride, (ctx->scenes[id].n_facets << (2 * pl.ns.split)) +
+    size_t rec_b = 0;
+    pl.nu_split.clear();
+    pl.nu_order.clear();
+    for (int32_t id : ids) {
+      // eligible, since the call's largest r_max is
+      NuShape si{};
+      (void)nufft_ineligible(ctx, rcn, o, scenes_rmax(ctx, {id}), &si);
+      pl.nu_split.push_back(si.split);
+      pl.nu_order.push_back(si.order);
+      stride = std::max<int64_t>(stride, (ctx->scenes[id].n_facets << (2 * si.split)) +
                                              static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
+      rec_b = std::max(rec_b, nufft_record_bytes(si.order));
+    }
     stride = std::max<int64_t>(stride, 1);
     const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q, ng = pl.ns.ng;
-    const size_t rec_b = nufft_record_bytes(pl.ns.order);
+    // the layout only grows while channels, grid and record size stay: calls on
+    // smaller scenes reuse it, so captured graphs stay valid
+    if (ctx->nu_layout[2] == O && ctx->nu_layout[3] == ng &&
+        ctx->nu_layout[4] == static_cast<int64_t>(rec_b))
+      stride = std::max<int64_t>(stride, ctx->nu_layout[0]);
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t per_chirp = stride * (rec_b + 8) + O * ng * 8;
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
