@@ -56,9 +56,12 @@ extern "C" {
                              /* per channel with a Taylor-expanded Gaussian, then an FFT and   */
                              /* deconvolution (relative error ~1e-5 or below). Exact per-      */
                              /* channel distances (no cross-term approximation). Eligible for  */
-                             /* stop-and-hop (ground bounce included) with n_g = the smallest   */
-                             /* 2^a 3^b >= 2M in 32..2048 and every channel's path within 2.5  */
-                             /* grid cells of the phase-centre path (array aperture). Facets   */
+                             /* n_g = the smallest 2^a 3^b >= 2M in 32..2048 and every channel  */
+                             /* within 2.5 grid cells of the phase-centre path (aperture, and  */
+                             /* with intra_chirp twice the largest Doppler shift of a source,  */
+                             /* n_g (f0 + M df) 2 v_max / (c fs) cells). Ground bounce and     */
+                             /* intra_chirp are supported (the latter to first order in the    */
+                             /* sample time and in its m^2 phase term). Facets                 */
                              /* spanning more than 1.5 grid cells (2 r_max df n_g / c, r_max   */
                              /* the largest vertex-to-centroid distance of the scenes' meshes) */
                              /* are split into 4, 16 or 64 midpoint sub-triangles; beyond 12   */

@@ -485,10 +485,22 @@ double scenes_rmax(const rsim_ctx *ctx, const std::vector<int32_t> &ids) {
 
 // Why the NUFFT facet sum cannot run (nullptr: it can, and *ns holds its shape without
 // the chirp chunk and record stride).
+double scenes_vmax(const rsim_ctx *ctx, const std::vector<int32_t> &ids) {
+  double v = 0.0;
+  for (int32_t id : ids) {
+    const SceneRec &sc = ctx->scenes[id];
+    for (const InstRec &i : sc.inst)
+      v = std::max(v, std::sqrt(i.vel[0] * i.vel[0] + i.vel[1] * i.vel[1] + i.vel[2] * i.vel[2]));
+    for (size_t k = 0; k + 2 < sc.pt_vel.size(); k += 3)
+      v = std::max(v, std::sqrt(sc.pt_vel[k] * sc.pt_vel[k] + sc.pt_vel[k + 1] * sc.pt_vel[k + 1] +
+                                sc.pt_vel[k + 2] * sc.pt_vel[k + 2]));
+  }
+  return v;
+}
+
 const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o,
-                             double r_max, NuShape *ns) {
+                             double r_max, double v_max, NuShape *ns) {
   if (o.precision != RSIM_FP32_PHASE64) return "the NUFFT facet sum is FP32 only";
-  if (o.intra_chirp) return "the NUFFT facet sum is stop-and-hop only";
   const int ng = smooth_at_least(2 * rc.M);
   if (ng > kNuMaxGrid) return "the NUFFT facet sum needs 2M <= 2048";
   if (ng < 32) return "the NUFFT facet sum needs M >= 16";
@@ -515,8 +527,12 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
     er = std::max(er, std::sqrt(d));
   }
   // the register window of the spread holds every channel's cells while the sorted
-  // phase-centre positions advance: 2 d <= window - width - 3
-  const double chan_d = kappa * (et + er);
+  // phase-centre positions advance: 2 d <= window - width - 3. With the delay within the
+  // chirp a channel's source also moves by its Doppler shift (A + B M) n_g, at most
+  // n_g (f0 + M df) 2 v_max / (c fs) cells, relative to the record's by twice that.
+  double chan_d = kappa * (et + er);
+  if (o.intra_chirp)
+    chan_d += 2.0 * ng * (rc.f0 + rc.M * rc.df) * 2.0 * v_max / (kC0 * rc.fs);
   if (2.0 * chan_d > nufft_window_cells() - kNuWidth - 3)
     return "array aperture too wide for the NUFFT register window";
   NuShape s{};
@@ -560,12 +576,13 @@ struct SumPlan {
   int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
 };
 
-SumPlan plan_sum(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o, double r_max) {
+SumPlan plan_sum(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o, double r_max,
+                 double v_max) {
   SumPlan pl;
   pl.ts = pick_shape(ctx, o.precision, o);
   const bool eligible = matrix_ineligible(ctx, rc, o.precision) == nullptr;
   NuShape ns{};
-  const bool nu_ok = nufft_ineligible(ctx, rc, o, r_max, &ns) == nullptr;
+  const bool nu_ok = nufft_ineligible(ctx, rc, o, r_max, v_max, &ns) == nullptr;
   if (o.kernel == RSIM_KERNEL_NUFFT || (o.kernel == RSIM_KERNEL_AUTO && nu_ok &&
                                         pl.ts.kernel == RSIM_KERNEL_NUFFT && !o.tile_m &&
                                         !o.tile_f)) {
@@ -1265,13 +1282,13 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     if (const char *why = matrix_ineligible(ctx, rcn, o.precision))
       return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
   }
-  const double r_max = scenes_rmax(ctx, ids);
+  const double r_max = scenes_rmax(ctx, ids), v_max = scenes_vmax(ctx, ids);
   if (o.kernel == RSIM_KERNEL_NUFFT) {
     NuShape tmp{};
-    if (const char *why = nufft_ineligible(ctx, rcn, o, r_max, &tmp))
+    if (const char *why = nufft_ineligible(ctx, rcn, o, r_max, v_max, &tmp))
       return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
   }
-  SumPlan pl = plan_sum(ctx, rcn, o, r_max);
+  SumPlan pl = plan_sum(ctx, rcn, o, r_max, v_max);
   const TunedShape ts = pl.ts;
   if (!pl.matrix && !pl.nufft && !echo_variant_exists(o.precision, ts.mb, ts.ft))
     return fail(ctx, RSIM_EINVAL, "no facet-sum variant with tile_m=%d tile_f=%d", ts.mb, ts.ft);
@@ -1290,7 +1307,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     for (int32_t id : ids) {
       // eligible, since the call's largest r_max is
       NuShape si{};
-      (void)nufft_ineligible(ctx, rcn, o, scenes_rmax(ctx, {id}), &si);
+      (void)nufft_ineligible(ctx, rcn, o, scenes_rmax(ctx, {id}), v_max, &si);
       pl.nu_split.push_back(si.split);
       pl.nu_order.push_back(si.order);
       stride = std::max<int64_t>(stride, (ctx->scenes[id].n_facets << (2 * si.split)) +
@@ -1799,7 +1816,8 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
         dev_free(ctx, echo);
         return rc;
       }
-    if (!nufft_ineligible(ctx, rcn, probe, scenes_rmax(ctx, ids), &ns)) cands.push_back({-1, 0});
+    if (!nufft_ineligible(ctx, rcn, probe, scenes_rmax(ctx, ids), scenes_vmax(ctx, ids), &ns))
+      cands.push_back({-1, 0});
   }
   float best = 1e30f;
   TunedShape best_s{32, 16, RSIM_KERNEL_VECTOR};

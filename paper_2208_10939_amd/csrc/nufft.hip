@@ -68,9 +68,15 @@ struct alignas(16) NuRec {
   float frac;           // grid position of the phase-centre path minus `cell`
   int32_t cell;         // its grid cell (0 .. n_g - 1)
   int32_t valid;
+  // delay within the chirp (zero otherwise): velocity, its components along ut and ur,
+  // and the phase-centre path's Doppler shift of the source (cells; in cell and frac)
+  float v[3];
+  float vut, vur;
+  float dxc;
+  float pad;
   float2 b[R];          // polynomial coefficients in grid cells (see the header comment)
 };
-static_assert(sizeof(NuRec<5>) == 128 && sizeof(NuRec<7>) == 144 && sizeof(NuRec<10>) == 160,
+static_assert(sizeof(NuRec<5>) == 160 && sizeof(NuRec<7>) == 176 && sizeof(NuRec<10>) == 192,
               "record size");
 
 size_t nufft_record_bytes(int order) {
@@ -103,9 +109,27 @@ __device__ inline int wrap_cell(int64_t c, int ng) {
 // Grid position and cell (0 .. n_g - 1) of a source on the phase-centre path of an entry,
 // shifted by the node offset bc of a sub-triangle's centroid (x = kappa (L - bc)), and the
 // two distances of that path; FP64.
+// With the delay taken at each sample time (rc.intra), the path's delay grows by
+// tau' m / fs over the chirp (tau' = d tau / dt, first order; the second-order term is
+// below 1e-7 of a turn here), which adds A m + B m^2 turns to its phase with
+// A = (f0 - mu tau) tau' / fs and B = df tau' / fs. With m = m' + M/2 that is a constant
+// phase A M/2 + B M^2/4, a shift of the source by (A + B M) n_g cells, and B m'^2.
+__device__ inline double doppler_cells(const Geo &g, const RadarConst &rc, const NuShape &ns,
+                                       double Rt, double Rr, double tau) {
+  if (!rc.intra) return 0.0;
+  double vt = 0.0, vr = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    vt += g.vel[k] * (g.c[k] - rc.tx_c[k]);
+    vr += g.vel[k] * (g.c[k] - rc.rx_c[k]);
+  }
+  const double tdot = (vt / Rt + vr / Rr) * (1.0 / kC0);
+  const double A = (rc.f0 - rc.slope * tau) * tdot / rc.fs, B = rc.df * tdot / rc.fs;
+  return (A + B * rc.M) * ns.ng;
+}
+
 __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuShape &ns,
                                    double bc, double *x_out, int *cell_out, double *Rt,
-                                   double *Rr) {
+                                   double *Rr, double *dxc) {
   double dt = 0.0, dr = 0.0;
   for (int k = 0; k < 3; ++k) {
     dt += (g.c[k] - rc.tx_c[k]) * (g.c[k] - rc.tx_c[k]);
@@ -113,7 +137,9 @@ __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuS
   }
   *Rt = sqrt(dt);
   *Rr = sqrt(dr);
-  const double x = (*Rt + *Rr) * (1.0 / kC0) * ns.cells_per_s - ns.kappa * bc;
+  const double tau = (*Rt + *Rr) * (1.0 / kC0);
+  *dxc = doppler_cells(g, rc, ns, *Rt, *Rr, tau);
+  const double x = tau * ns.cells_per_s - ns.kappa * bc + *dxc;
   *x_out = x;
   *cell_out = wrap_cell(static_cast<int64_t>(floor(x)), ns.ng);
 }
@@ -255,9 +281,19 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
   }
   // the phase-centre path (FP64), and the source position on the grid (the same cell as
   // the key pass)
-  double x, Rt, Rr;
+  double x, Rt, Rr, dxc;
   int cell;
-  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr);
+  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr, &dxc);
+  double vut = 0.0, vur = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    out.v[k] = rc.intra ? static_cast<float>(g.vel[k]) : 0.0f;
+    vut += g.vel[k] * (g.c[k] - rc.tx_c[k]) / Rt;
+    vur += g.vel[k] * (g.c[k] - rc.rx_c[k]) / Rr;
+  }
+  out.vut = rc.intra ? static_cast<float>(vut) : 0.0f;
+  out.vur = rc.intra ? static_cast<float>(vur) : 0.0f;
+  out.dxc = static_cast<float>(dxc);
+  out.pad = 0.0f;
   for (int k = 0; k < 3; ++k) {
     out.ut[k] = (g.c[k] - rc.tx_c[k]) / Rt;
     out.ur[k] = (g.c[k] - rc.rx_c[k]) / Rr;
@@ -287,9 +323,9 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst 
   entry_geometry(sc, rc, n, cnt, entry, g);
   double nodes[3], bc = 0.0;
   if (sub >= 0 && ns.split > 0) bc = sub_nodes(g.beta, sub, ns.split, nodes);
-  double x, Rt, Rr;
+  double x, Rt, Rr, dxc;
   int cell;
-  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr);
+  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr, &dxc);
   nb.key[static_cast<int64_t>(nl) * ns.rec_stride + item] = cell;
 }
 
@@ -326,7 +362,7 @@ __global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape 
   for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] += s_cnt[key[e]];
 }
 
-template <int R>
+template <int R, bool INTRA>
 __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,
     const NuRec<R> *__restrict__ sorted, float2 *__restrict__ grids) {
@@ -352,7 +388,7 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
   const bool on = o < O;
   // this lane's element offsets from the phase centres
   double at[3], ar[3];
-  float aat, aar;
+  float aat, aar, atf[3], arf[3];
   {
     const int oc = on ? o : 0;
     const int p = oc / rc.Q, q = oc - p * rc.Q;
@@ -365,7 +401,18 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
     }
     aat = static_cast<float>(st);
     aar = static_cast<float>(sr);
+    for (int k = 0; k < 3; ++k) {
+      atf[k] = static_cast<float>(at[k]);
+      arf[k] = static_cast<float>(ar[k]);
+    }
   }
+  const float inv_c0 = static_cast<float>(1.0 / kC0), inv_fs = static_cast<float>(1.0 / rc.fs);
+  const float df_fs = static_cast<float>(rc.df / rc.fs);
+  const float half_m = 0.5f * rc.M, quarter_m2 = 0.25f * rc.M * rc.M, m_f = static_cast<float>(rc.M);
+  const float ngf = static_cast<float>(ns.ng);
+  const float eps_scale = static_cast<float>(static_cast<double>(ns.ng) * ns.ng / (2.0 * kPi));
+  const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
+  const float inv_s4 = inv_s2 * inv_s2;
   const NuRec<R> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
   float2 *grid = grids + (static_cast<int64_t>(nl) * O + (on ? o : 0)) * ng;
   const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
@@ -419,14 +466,49 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
       const float dRt = et - sft, dRr = er - sfr;
       const float dL = dRt + dRr;
       float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
+      float xr = fmaf(kappa, dL, rel_c);
+      float eps = 0.0f;  // B n_g^2 / (2 pi): weight of F'' for the B m'^2 term
+      if (INTRA) {
+        // this channel's tau' (first order in the sample time), its Doppler shift relative
+        // to the record's and the constant phase A M/2 + B M^2/4
+        const float vat = r.v[0] * atf[0] + r.v[1] * atf[1] + r.v[2] * atf[2];
+        const float var = r.v[0] * arf[0] + r.v[1] * arf[1] + r.v[2] * arf[2];
+        const float rdt_dot = fmaf(r.rt, r.vut, -vat) * __builtin_amdgcn_rcpf(r.rt + dRt);
+        const float rdr_dot = fmaf(r.rr, r.vur, -var) * __builtin_amdgcn_rcpf(r.rr + dRr);
+        const float tdot = (rdt_dot + rdr_dot) * inv_c0;
+        const float fmt = static_cast<float>(r.g1 * kC0 - (rc.M / 2) * rc.df);
+        const float A = fmt * tdot * inv_fs, B = df_fs * tdot;
+        t += fmaf(A, half_m, B * quarter_m2);
+        xr += fmaf(B, m_f, A) * ngf - r.dxc;
+        eps = B * eps_scale;
+      }
       t -= rintf(t);
       const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
       const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
-      const float xr = fmaf(kappa, dL, rel_c);
-      float2 cq[R];
+      constexpr int NC = INTRA ? R + 2 : R;  // the B m'^2 term raises the degree by two
+      float2 cq[NC];
 #pragma unroll
       for (int k = 0; k < R; ++k)
         cq[k] = {qx * r.b[k].x - qy * r.b[k].y, qx * r.b[k].y + qy * r.b[k].x};
+      if (INTRA) {
+        // (1 - j 2 pi B m'^2) on the modes is F + j eps F'' on the grid, F = psi P, with
+        // F'' = psi (P'' - (2u / s^2) P' + (u^2 / s^4 - 1 / s^2) P): coefficient k of the
+        // result is c_k + j eps (c_{k-2} / s^4 - (2k + 1) c_k / s^2 + (k + 1)(k + 2) c_{k+2})
+        float2 c[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const float2 ck = k < R ? cq[k] : make_float2(0.0f, 0.0f);
+          const float2 cm2 = (k >= 2 && k - 2 < R) ? cq[k - 2] : make_float2(0.0f, 0.0f);
+          const float2 cp2 = (k + 2 < R) ? cq[k + 2] : make_float2(0.0f, 0.0f);
+          const float wk = -(2.0f * k + 1.0f) * inv_s2;
+          const float wp = static_cast<float>((k + 1) * (k + 2));
+          const float dx = cm2.x * inv_s4 + wk * ck.x + wp * cp2.x;
+          const float dy = cm2.y * inv_s4 + wk * ck.y + wp * cp2.y;
+          c[k] = {ck.x - eps * dy, ck.y + eps * dx};
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) cq[k] = c[k];
+      }
       // Gaussian weights from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)
       const float u0 = static_cast<float>(s_lo) - xr;
       float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
@@ -435,9 +517,9 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
       for (int s = 0; s < kNuSlots; ++s) {
         if (s >= s_lo && s <= s_hi) {
           const float xx = static_cast<float>(s) - xr;
-          float pr2 = cq[R - 1].x, pi2 = cq[R - 1].y;
+          float pr2 = cq[NC - 1].x, pi2 = cq[NC - 1].y;
 #pragma unroll
-          for (int k = R - 2; k >= 0; --k) {
+          for (int k = NC - 2; k >= 0; --k) {
             pr2 = fmaf(pr2, xx, cq[k].x);
             pi2 = fmaf(pi2, xx, cq[k].y);
           }
@@ -541,9 +623,14 @@ hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t waves = static_cast<int64_t>(ns.n_chirps) * ns.spread_groups * ns.runs;
     const int64_t blocks = (waves + kNuSpreadThreads / 64 - 1) / (kNuSpreadThreads / 64);
-    hipLaunchKernelGGL(nufft_spread_kernel<R>, dim3(static_cast<unsigned>(blocks)),
-                       dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
-                       static_cast<const NuRec<R> *>(nb.srec), nb.grid);
+    if (rc.intra)
+      hipLaunchKernelGGL((nufft_spread_kernel<R, true>), dim3(static_cast<unsigned>(blocks)),
+                         dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
+                         static_cast<const NuRec<R> *>(nb.srec), nb.grid);
+    else
+      hipLaunchKernelGGL((nufft_spread_kernel<R, false>), dim3(static_cast<unsigned>(blocks)),
+                         dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
+                         static_cast<const NuRec<R> *>(nb.srec), nb.grid);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),

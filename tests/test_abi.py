@@ -166,8 +166,8 @@ def test_detect_and_noise_validation_host_only():
 
 def test_nufft_refusals_host_only():
     """The NUFFT facet sum's eligibility is decided on the host before any device work:
-    FP64 is EINVAL; the intra-chirp delay and facets spanning more than 12 grid cells
-    (2 r_max df n_g / c; up to that they are split) are ERANGE; an eligible request (the
+    FP64 is EINVAL; facets spanning more than 12 grid cells (2 r_max df n_g / c; up to
+    that they are split) are ERANGE; an eligible request (the delay within the chirp, the
     ground bounce and split facets included) reaches the missing device."""
     ctx = _host_ctx()
     L = rsim.lib()
@@ -193,7 +193,7 @@ def test_nufft_refusals_host_only():
 
     assert call(ids[0]) == rsim.RSIM_EDEVICE
     assert call(ids[0], precision=rsim.RSIM_FP64) == rsim.RSIM_EINVAL
-    assert call(ids[0], intra_chirp=1) == rsim.RSIM_ERANGE
+    assert call(ids[0], intra_chirp=1) == rsim.RSIM_EDEVICE  # Doppler shift within the window
     assert call(ids[1]) == rsim.RSIM_ERANGE
     assert b"grid cells" in L.rsim_last_error(ctx._h)
     both = (ctypes.c_int32 * 2)(*ids)
