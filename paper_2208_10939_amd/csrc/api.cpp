@@ -1312,7 +1312,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       pl.nu_order.push_back(si.order);
       stride = std::max<int64_t>(stride, (ctx->scenes[id].n_facets << (2 * si.split)) +
                                              static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
-      rec_b = std::max(rec_b, nufft_record_bytes(si.order));
+      rec_b = std::max(rec_b, nufft_record_bytes(si.order, o.intra_chirp != 0));
     }
     stride = std::max<int64_t>(stride, 1);
     const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q, ng = pl.ns.ng;
@@ -1342,7 +1342,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     }
     char *b = static_cast<char *>(ctx->nu_buf);
     pl.nb = NuBuffers{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
-                      b + off_srec, reinterpret_cast<float2 *>(b + off_grid)};
+                      b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b};
     pl.ns.n_chirps = static_cast<int32_t>(chunk);
     if (clear) {
       // the kernels leave the grids zero; a new layout starts from zero (on the

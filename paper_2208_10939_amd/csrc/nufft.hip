@@ -47,6 +47,8 @@
 //           the end of the run);
 //   fft     per (chirp, group of channels): grid rows into LDS (rows zeroed behind),
 //           in-LDS Stockham FFT, deconvolution, echo samples.
+#include <type_traits>
+
 #include "adjoint_common.h"
 #include "echo_common.h"
 #include "fft_common.h"
@@ -68,19 +70,32 @@ struct alignas(16) NuRec {
   float frac;           // grid position of the phase-centre path minus `cell`
   int32_t cell;         // its grid cell (0 .. n_g - 1)
   int32_t valid;
-  // delay within the chirp (zero otherwise): velocity, its components along ut and ur,
-  // and the phase-centre path's Doppler shift of the source (cells; in cell and frac)
+  float2 b[R];          // polynomial coefficients in grid cells (see the header comment)
+};
+// with the delay within the chirp: velocity, its components along ut and ur, and the
+// phase-centre path's Doppler shift of the source (cells; included in cell and frac)
+template <int R>
+struct alignas(16) NuRecIntra : NuRec<R> {
   float v[3];
   float vut, vur;
   float dxc;
-  float pad;
-  float2 b[R];          // polynomial coefficients in grid cells (see the header comment)
 };
-static_assert(sizeof(NuRec<5>) == 160 && sizeof(NuRec<7>) == 176 && sizeof(NuRec<10>) == 192,
+template <int R, bool INTRA>
+using NuRecT = typename std::conditional<INTRA, NuRecIntra<R>, NuRec<R>>::type;
+static_assert(sizeof(NuRec<5>) == 128 && sizeof(NuRec<7>) == 144 && sizeof(NuRec<10>) == 160,
+              "record size");
+// (the derived record reuses the base's tail padding: float2 is not plain old data)
+static_assert(sizeof(NuRecIntra<5>) == 144 && sizeof(NuRecIntra<7>) == 160 &&
+                  sizeof(NuRecIntra<10>) == 192,
               "record size");
 
-size_t nufft_record_bytes(int order) {
-  return order <= 5 ? sizeof(NuRec<5>) : order <= 7 ? sizeof(NuRec<7>) : sizeof(NuRec<10>);
+template <bool INTRA>
+static size_t record_bytes_t(int order) {
+  return order <= 5 ? sizeof(NuRecT<5, INTRA>)
+                    : order <= 7 ? sizeof(NuRecT<7, INTRA>) : sizeof(NuRecT<10, INTRA>);
+}
+size_t nufft_record_bytes(int order, bool intra) {
+  return intra ? record_bytes_t<true>(order) : record_bytes_t<false>(order);
 }
 int nufft_window_cells() { return kNuSlots; }
 int nufft_run_length() { return kNuSeg; }
@@ -187,7 +202,7 @@ __device__ inline double sub_nodes(const double beta[3], int sub, int split, dou
   return c;
 }
 
-template <int R>
+template <int R, bool INTRA>
 __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst rc, NuShape ns,
                                                         NuBuffers nb) {
   const int nl = blockIdx.y;
@@ -213,7 +228,7 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
     g.amp_re = ar * cb - ai * sb;
     g.amp_im = ar * sb + ai * cb;
   }
-  NuRec<R> out;
+  NuRecT<R, INTRA> out;
   out.valid = g.valid;
 #pragma unroll
   for (int k = 0; k < R; ++k) out.b[k] = {0.0f, 0.0f};
@@ -284,16 +299,17 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
   double x, Rt, Rr, dxc;
   int cell;
   centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr, &dxc);
-  double vut = 0.0, vur = 0.0;
-  for (int k = 0; k < 3; ++k) {
-    out.v[k] = rc.intra ? static_cast<float>(g.vel[k]) : 0.0f;
-    vut += g.vel[k] * (g.c[k] - rc.tx_c[k]) / Rt;
-    vur += g.vel[k] * (g.c[k] - rc.rx_c[k]) / Rr;
+  if constexpr (INTRA) {
+    double vut = 0.0, vur = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      out.v[k] = static_cast<float>(g.vel[k]);
+      vut += g.vel[k] * (g.c[k] - rc.tx_c[k]) / Rt;
+      vur += g.vel[k] * (g.c[k] - rc.rx_c[k]) / Rr;
+    }
+    out.vut = static_cast<float>(vut);
+    out.vur = static_cast<float>(vur);
+    out.dxc = static_cast<float>(dxc);
   }
-  out.vut = rc.intra ? static_cast<float>(vut) : 0.0f;
-  out.vur = rc.intra ? static_cast<float>(vur) : 0.0f;
-  out.dxc = static_cast<float>(dxc);
-  out.pad = 0.0f;
   for (int k = 0; k < 3; ++k) {
     out.ut[k] = (g.c[k] - rc.tx_c[k]) / Rt;
     out.ur[k] = (g.c[k] - rc.rx_c[k]) / Rr;
@@ -307,7 +323,7 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
   out.frac = static_cast<float>(x - floor(x));
   out.cell = cell;
   const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
-  static_cast<NuRec<R> *>(nb.srec)[row + nb.pos[row + item]] = out;
+  static_cast<NuRecT<R, INTRA> *>(nb.srec)[row + nb.pos[row + item]] = out;
 }
 
 __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst rc, NuShape ns,
@@ -365,7 +381,7 @@ __global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape 
 template <int R, bool INTRA>
 __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,
-    const NuRec<R> *__restrict__ sorted, float2 *__restrict__ grids) {
+    const NuRecT<R, INTRA> *__restrict__ sorted, float2 *__restrict__ grids) {
   const int wave = __builtin_amdgcn_readfirstlane(
       static_cast<int>(blockIdx.x) * (kNuSpreadThreads / 64) + static_cast<int>(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -413,7 +429,7 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
   const float eps_scale = static_cast<float>(static_cast<double>(ns.ng) * ns.ng / (2.0 * kPi));
   const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
   const float inv_s4 = inv_s2 * inv_s2;
-  const NuRec<R> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
+  const NuRecT<R, INTRA> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
   float2 *grid = grids + (static_cast<int64_t>(nl) * O + (on ? o : 0)) * ng;
   const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
   const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
@@ -428,13 +444,13 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
   // windows: the records that fit one placement of the register window, then a flush;
   // invalid records carry zero coefficients and need no test
   int i = e_begin;
-  NuRec<R> nxt = load_uniform(srec + i);
+  NuRecT<R, INTRA> nxt = load_uniform(srec + i);
   while (i < e_end) {
     const int base = nxt.cell - b0;  // wave-uniform
     int used_lo = kNuSlots, used_hi = -1;
     const int first = i;
     for (; i < e_end; ++i) {
-      const NuRec<R> r = nxt;
+      const NuRecT<R, INTRA> r = nxt;
       // window position of the phase-centre path (wrapped cell difference + fraction);
       // the record that placed the window always fits it (chan_d <= 2.5 cells), and is
       // taken regardless so that every window makes progress
@@ -468,7 +484,7 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
       float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
       float xr = fmaf(kappa, dL, rel_c);
       float eps = 0.0f;  // B n_g^2 / (2 pi): weight of F'' for the B m'^2 term
-      if (INTRA) {
+      if constexpr (INTRA) {
         // this channel's tau' (first order in the sample time), its Doppler shift relative
         // to the record's and the constant phase A M/2 + B M^2/4
         const float vat = r.v[0] * atf[0] + r.v[1] * atf[1] + r.v[2] * atf[2];
@@ -612,6 +628,8 @@ hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double
                           const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
   if (ns.n_chirps <= 0) return hipSuccess;
   const int64_t items = (sc.n_facets << (2 * ns.split)) + sc.n_points;
+  if ((rc.intra ? sizeof(NuRecT<R, true>) : sizeof(NuRecT<R, false>)) > nb.rec_bytes)
+    return hipErrorInvalidValue;
   if (items > 0) {
     dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
     hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);
@@ -619,18 +637,21 @@ hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(nufft_count_kernel, dim3(ns.n_chirps), dim3(1024), 0, s, sc, ns, nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(nufft_prep_kernel<R>, grid, dim3(256), 0, s, sc, rc, ns, nb);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t waves = static_cast<int64_t>(ns.n_chirps) * ns.spread_groups * ns.runs;
     const int64_t blocks = (waves + kNuSpreadThreads / 64 - 1) / (kNuSpreadThreads / 64);
-    if (rc.intra)
+    if (rc.intra) {
+      hipLaunchKernelGGL((nufft_prep_kernel<R, true>), grid, dim3(256), 0, s, sc, rc, ns, nb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL((nufft_spread_kernel<R, true>), dim3(static_cast<unsigned>(blocks)),
                          dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
-                         static_cast<const NuRec<R> *>(nb.srec), nb.grid);
-    else
+                         static_cast<const NuRecT<R, true> *>(nb.srec), nb.grid);
+    } else {
+      hipLaunchKernelGGL((nufft_prep_kernel<R, false>), grid, dim3(256), 0, s, sc, rc, ns, nb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL((nufft_spread_kernel<R, false>), dim3(static_cast<unsigned>(blocks)),
                          dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
-                         static_cast<const NuRec<R> *>(nb.srec), nb.grid);
+                         static_cast<const NuRecT<R, false> *>(nb.srec), nb.grid);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),

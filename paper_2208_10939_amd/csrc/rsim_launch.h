@@ -84,8 +84,9 @@ struct NuBuffers {
   int32_t *pos;
   void *srec;
   float2 *grid;
+  size_t rec_bytes;  // record slot size of srec (a launch refuses wider records)
 };
-size_t nufft_record_bytes(int order);
+size_t nufft_record_bytes(int order, bool intra);
 size_t nufft_smem_bytes(const NuShape &ns);
 int nufft_window_cells();
 int nufft_run_length();
