@@ -6,18 +6,23 @@
 // neither segment centroid -> phase centre is blocked by another triangle. The
 // geometry is that of chirp start t_n (stop-and-hop, eq. (12) per chirp).
 //
-// Layout: one thread per (facet, chirp); grid (ceil(F / 128), N). The facing test
+// Layout: a workgroup per (32 or more facets, up to 64 chirps), lane = chirp. The facing test
 // runs in FP64 on world coordinates; the two shadow rays run in FP32 in each
 // candidate instance's body frame, starting at the facet centroid (close to the
 // occluders, so the FP32 Moller-Trumbore test keeps its precision). Each thread
 // owns a column of an LDS stack (stride = block size, conflict-free) as deep as the
 // scene's deepest BVH, which sets how many waves share a CU.
+#include <algorithm>
+
 #include "rsim_internal.h"
 #include "rsim_launch.h"
 
 namespace rsim {
 
 namespace {
+
+constexpr int kVisThreads = 256;
+constexpr int kVisBitWords = 4 * 64;  // LDS bit words: path types x chirps x mask words
 
 __device__ inline int find_instance(const DevInstance *inst, int n_inst, int64_t f) {
   int lo = 0, hi = n_inst - 1;
@@ -285,8 +290,9 @@ __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], co
 // specular point (the road surface is skipped for these legs).
 __device__ void reflected_sides(const DevScene &sc, const RadarConst &rc, double t,
                                 const double c[3], const double n[3], const double E[3], double fe,
-                                int ii, int32_t lt, int32_t *stk, bool *direct, bool *refl) {
-  *direct = fe > 0.0 && !segment_blocked(sc, t, c, E, ii, lt, stk, blockDim.x);
+                                int ii, int32_t lt, int32_t *stk, int stride, bool *direct,
+                                bool *refl) {
+  *direct = fe > 0.0 && !segment_blocked(sc, t, c, E, ii, lt, stk, stride);
   *refl = false;
   if (!(c[2] > rc.z_ground)) return;
   const double ez = 2.0 * rc.z_ground - E[2];  // image height
@@ -294,71 +300,92 @@ __device__ void reflected_sides(const DevScene &sc, const RadarConst &rc, double
   if (!(fi > 0.0)) return;
   const double a = (c[2] - rc.z_ground) / (c[2] - ez);
   const double S[3] = {c[0] + a * (E[0] - c[0]), c[1] + a * (E[1] - c[1]), rc.z_ground};
-  *refl = !segment_blocked(sc, t, c, S, ii, lt, stk, blockDim.x, true) &&
-          !segment_blocked(sc, t, S, E, -1, -1, stk, blockDim.x, true);
+  *refl = !segment_blocked(sc, t, c, S, ii, lt, stk, stride, true) &&
+          !segment_blocked(sc, t, S, E, -1, -1, stk, stride, true);
 }
 
 }  // namespace
 
-__global__ void __launch_bounds__(128) vis_kernel(DevScene sc, RadarConst rc) {
-  extern __shared__ int32_t vis_stack[];
-  const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int n = blockIdx.y;
+namespace {
+
+// Lit decisions of facet f at chirp n: the single path (lit[0]) or, with the ground bounce,
+// the four path types (transmit side k & 1, receive side k >> 1).
+__device__ void facet_lit(const DevScene &sc, const RadarConst &rc, int64_t f, int n,
+                          int32_t *stk, int stride, bool lit[4]) {
+  lit[0] = lit[1] = lit[2] = lit[3] = false;
   const double t = n * rc.tc;
-  bool lit = false;
-  bool lit4[4] = {false, false, false, false};
-  if (f < sc.n_facets) {
-    const int ii = find_instance(sc.inst, sc.n_inst, f);
-    const DevInstance &I = sc.inst[ii];
-    const int32_t lt = static_cast<int32_t>(f - I.facet_base);
-    double x[3][3];
-    for (int v = 0; v < 3; ++v) {
-      const int32_t vi = I.tris[3 * lt + v];
-      const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
-      for (int k = 0; k < 3; ++k)
-        x[v][k] = I.rot[3 * k + 0] * b0 + I.rot[3 * k + 1] * b1 + I.rot[3 * k + 2] * b2 +
-                  (I.pos0[k] + I.vel[k] * t);
-    }
-    double c[3], e1[3], e2[3];
-    for (int k = 0; k < 3; ++k) {
-      c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
-      e1[k] = x[1][k] - x[0][k];
-      e2[k] = x[2][k] - x[0][k];
-    }
-    double nx = e1[1] * e2[2] - e1[2] * e2[1];
-    double ny = e1[2] * e2[0] - e1[0] * e2[2];
-    double nz = e1[0] * e2[1] - e1[1] * e2[0];
-    bool nonzero = (nx != 0.0 || ny != 0.0 || nz != 0.0);
-    double ft = nx * (rc.tx_c[0] - c[0]) + ny * (rc.tx_c[1] - c[1]) + nz * (rc.tx_c[2] - c[2]);
-    double fr = nx * (rc.rx_c[0] - c[0]) + ny * (rc.rx_c[1] - c[1]) + nz * (rc.rx_c[2] - c[2]);
-    int32_t *stk = vis_stack + threadIdx.x;
-    if (!rc.bounce) {
-      if (nonzero && ft > 0.0 && fr > 0.0)
-        lit = !pair_blocked(sc, t, c, rc.tx_c, rc.rx_c, ii, lt, stk, blockDim.x);
-    } else if (nonzero) {
-      // per side: direct (faces E, centroid -> E clear) and reflected on the ground plane;
-      // path type k takes the transmit side (k & 1) and the receive side (k >> 1)
-      const double nv[3] = {nx, ny, nz};
-      bool dt, it, dr, ir;
-      reflected_sides(sc, rc, t, c, nv, rc.tx_c, ft, ii, lt, stk, &dt, &it);
-      reflected_sides(sc, rc, t, c, nv, rc.rx_c, fr, ii, lt, stk, &dr, &ir);
-      lit4[0] = dt && dr;
-      lit4[1] = it && dr;
-      lit4[2] = dt && ir;
-      lit4[3] = it && ir;
-    }
+  const int ii = find_instance(sc.inst, sc.n_inst, f);
+  const DevInstance &I = sc.inst[ii];
+  const int32_t lt = static_cast<int32_t>(f - I.facet_base);
+  double x[3][3];
+  for (int v = 0; v < 3; ++v) {
+    const int32_t vi = I.tris[3 * lt + v];
+    const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
+    for (int k = 0; k < 3; ++k)
+      x[v][k] = I.rot[3 * k + 0] * b0 + I.rot[3 * k + 1] * b1 + I.rot[3 * k + 2] * b2 +
+                (I.pos0[k] + I.vel[k] * t);
   }
+  double c[3], e1[3], e2[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
+    e1[k] = x[1][k] - x[0][k];
+    e2[k] = x[2][k] - x[0][k];
+  }
+  const double nx = e1[1] * e2[2] - e1[2] * e2[1];
+  const double ny = e1[2] * e2[0] - e1[0] * e2[2];
+  const double nz = e1[0] * e2[1] - e1[1] * e2[0];
+  const bool nonzero = (nx != 0.0 || ny != 0.0 || nz != 0.0);
+  const double ft = nx * (rc.tx_c[0] - c[0]) + ny * (rc.tx_c[1] - c[1]) + nz * (rc.tx_c[2] - c[2]);
+  const double fr = nx * (rc.rx_c[0] - c[0]) + ny * (rc.rx_c[1] - c[1]) + nz * (rc.rx_c[2] - c[2]);
+  if (!rc.bounce) {
+    if (nonzero && ft > 0.0 && fr > 0.0)
+      lit[0] = !pair_blocked(sc, t, c, rc.tx_c, rc.rx_c, ii, lt, stk, stride);
+  } else if (nonzero) {
+    const double nv[3] = {nx, ny, nz};
+    bool dt, it, dr, ir;
+    reflected_sides(sc, rc, t, c, nv, rc.tx_c, ft, ii, lt, stk, stride, &dt, &it);
+    reflected_sides(sc, rc, t, c, nv, rc.rx_c, fr, ii, lt, stk, stride, &dr, &ir);
+    lit[0] = dt && dr;
+    lit[1] = it && dr;
+    lit[2] = dt && ir;
+    lit[3] = it && ir;
+  }
+}
+
+}  // namespace
+
+// A workgroup covers kVisFacetsPer facets (whole mask words) and `cw` consecutive chirps
+// (a power of two up to 64); lane = chirp within the group, so the lanes of a wave trace
+// nearly the same rays of one facet at neighbouring chirps and follow nearly one BVH path
+// (mapping lanes to neighbouring facets instead makes every wave walk the union of 64
+// different paths). Decisions are gathered as bits in LDS and written as whole words.
+__global__ void __launch_bounds__(kVisThreads) vis_kernel(DevScene sc, RadarConst rc, int cw,
+                                                        int facets_per_block) {
+  extern __shared__ int32_t vis_lds[];
+  const int words = facets_per_block >> 5;
   const int types = rc.bounce ? 4 : 1;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (k >= types) break;
-    const unsigned long long bits = __ballot(rc.bounce ? lit4[k] : lit);
-    if ((threadIdx.x & 63) == 0) {
-      const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 5;
-      uint32_t *row = sc.mask + (static_cast<int64_t>(k) * rc.N + n) * sc.mask_words;
-      if (w < sc.mask_words) row[w] = static_cast<uint32_t>(bits);
-      if (w + 1 < sc.mask_words) row[w + 1] = static_cast<uint32_t>(bits >> 32);
-    }
+  uint32_t *bits = reinterpret_cast<uint32_t *>(vis_lds);  // [types][cw][words]
+  int32_t *stk = vis_lds + kVisBitWords + threadIdx.x;      // column per thread
+  for (int k = threadIdx.x; k < types * cw * words; k += blockDim.x) bits[k] = 0u;
+  __syncthreads();
+  const int nl = threadIdx.x % cw;
+  const int n = blockIdx.y * cw + nl;
+  const int64_t f0 = static_cast<int64_t>(blockIdx.x) * facets_per_block;
+  for (int fl = threadIdx.x / cw; fl < facets_per_block; fl += blockDim.x / cw) {
+    const int64_t f = f0 + fl;
+    if (f >= sc.n_facets || n >= rc.N) continue;
+    bool lit[4];
+    facet_lit(sc, rc, f, n, stk, blockDim.x, lit);
+    for (int k = 0; k < types; ++k)
+      if (lit[k]) atomicOr(&bits[(k * cw + nl) * words + (fl >> 5)], 1u << (fl & 31));
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < types * cw * words; e += blockDim.x) {
+    const int w = e % words, r = e / words;  // r = k * cw + chirp within the group
+    const int k = r / cw, nn = blockIdx.y * cw + (r % cw);
+    const int64_t word = static_cast<int64_t>(blockIdx.x) * words + w;
+    if (nn < rc.N && word < sc.mask_words)
+      sc.mask[(static_cast<int64_t>(k) * rc.N + nn) * sc.mask_words + word] = bits[e];
   }
 }
 
@@ -401,10 +428,15 @@ __global__ void __launch_bounds__(1024) compact_kernel(DevScene sc) {
 
 hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream_t s) {
   if (sc.n_facets == 0) return hipSuccess;
-  const int block = 128;
-  dim3 grid(static_cast<unsigned>((sc.n_facets + block - 1) / block), rc.N);
-  const size_t lds = sizeof(int32_t) * static_cast<size_t>(sc.stack_depth) * block;
-  hipLaunchKernelGGL(vis_kernel, grid, dim3(block), lds, s, sc, rc);
+  int cw = 1;  // chirps per group: the smallest power of two >= N, at most 64
+  while (cw < rc.N && cw < 64) cw <<= 1;
+  // facets per workgroup: whole 32-bit mask words, every thread busy for cw >= 8
+  const int fpb = std::max(32, kVisThreads / cw);
+  dim3 grid(static_cast<unsigned>((sc.n_facets + fpb - 1) / fpb),
+            static_cast<unsigned>((rc.N + cw - 1) / cw));
+  // bit words: types x max(cw, 8) <= 4 x 64
+  const size_t lds = sizeof(int32_t) * (kVisBitWords + static_cast<size_t>(sc.stack_depth) * kVisThreads);
+  hipLaunchKernelGGL(vis_kernel, grid, dim3(kVisThreads), lds, s, sc, rc, cw, fpb);
   return hipGetLastError();
 }
 
