@@ -245,12 +245,17 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                       double *grad_vel, void *hip_stream);
 
 /* Facet-sum kernel of rsim_backward (Sections 2.2, 3.2; eqs. (7), (9)-(13), differentiated):
- * RSIM_KERNEL_AUTO (default) takes the matrix cores when the array allows them (the same
- * eligibility as rsim_opts.kernel: |2 pi slope d_p e_q| <= 1e-5 rad, P <= 12, Q <= 16) and
- * the vector units otherwise; RSIM_KERNEL_VECTOR always the vector units;
- * RSIM_KERNEL_MATRIX the matrix cores, rsim_backward then failing with ERANGE on an
- * ineligible array. EINVAL for another value. Both give the same gradients to FP32
- * rounding and the dropped cross term (relative <= 1e-5). */
+ * RSIM_KERNEL_AUTO (default) takes the NUFFT adjoint where the forward NUFFT would be
+ * eligible for the scene (see RSIM_KERNEL_NUFFT), else the matrix cores when the array
+ * allows them (the same eligibility as rsim_opts.kernel: |2 pi slope d_p e_q| <= 1e-5 rad,
+ * P <= 12, Q <= 16), else the vector units; RSIM_KERNEL_VECTOR always the vector units;
+ * RSIM_KERNEL_MATRIX the matrix cores and RSIM_KERNEL_NUFFT the NUFFT adjoint (a type-2
+ * transform: the echo gradient through the transposed FFT and deconvolution onto each
+ * channel's grid, then Gaussian-weighted moments gathered per lit facet), rsim_backward then
+ * failing with ERANGE where ineligible. EINVAL for another value. All give the same
+ * gradients to FP32 rounding, the dropped cross term and the NUFFT's error (relative
+ * <= 1e-5); the direct kernels are deterministic, the NUFFT adjoint adds its per-facet
+ * sums with atomics (reproducible to FP32 rounding, not bit for bit). */
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel);
 
 /* Gradient of L with respect to the echo given dL/dP of the power RDM P = |Y|^2 and

@@ -197,31 +197,6 @@ __device__ void adj_flush(const AdjSmem<MB, FT> &sm, const float *red, float *pa
   }
 }
 
-// Sum over the 64 lanes of a wave: DPP moves inside each 16-lane row (no LDS round
-// trips), then the four row sums read out with readlane (the DPP row-broadcast
-// controls do not exist on this GPU generation). Fixed order: deterministic.
-template <int kCtrl, int kRowMask>
-__device__ inline float dpp_add(float v) {
-  const int t = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, kRowMask, 0xF,
-                                            false);
-  return v + __builtin_bit_cast(float, t);
-}
-
-// DPP reads the registers of inactive lanes as they are: every caller runs it with the
-// whole wave active.
-__device__ inline float wave_sum(float v) {
-  v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-  v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]: quad sums
-  v = dpp_add<0x141, 0xF>(v);  // row_half_mirror: 8-lane sums
-  v = dpp_add<0x140, 0xF>(v);  // row_mirror: 16-lane (row) sums in every lane
-  const int iv = __builtin_bit_cast(int, v);
-  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 0));
-  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 16));
-  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 32));
-  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 48));
-  return (r0 + r1) + (r2 + r3);
-}
-
 // One workgroup per (chirp, sample tile, channel tile): accumulating waves (thread (o, b)
 // holds conj(g) for MB samples of channel o in registers) and two staging waves, with
 // double-buffered tiles of FT lit facets as in the forward kernel. Both branches pass

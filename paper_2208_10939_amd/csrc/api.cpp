@@ -131,6 +131,8 @@ struct rsim_ctx {
   // its count and grid regions were last cleared for
   void *nu_buf = nullptr;
   size_t nu_buf_bytes = 0;
+  void *nu_adj_buf = nullptr;  // work buffers of the NUFFT adjoint (grow-only)
+  size_t nu_adj_bytes = 0;
   std::array<int64_t, 5> nu_layout{};
   size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0, adj_gsum_n = 0;
   BatchTables batch;  // persistent launches outside graphs
@@ -1231,7 +1233,7 @@ int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double g
 
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
-  if (kernel < RSIM_KERNEL_AUTO || kernel > RSIM_KERNEL_MATRIX)
+  if (kernel < RSIM_KERNEL_AUTO || kernel > RSIM_KERNEL_NUFFT)
     return fail(ctx, RSIM_EINVAL, "rsim_set_backward_kernel: unknown kernel %d", kernel);
   ctx->bwd_kernel = kernel;
   return RSIM_OK;
@@ -1418,6 +1420,56 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
   return enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing, pl);
 }
 
+// NUFFT adjoint of one scene's facet sum into ctx->adj_partial (one slot per chirp and lit
+// facet), then the shared chain rule into ctx->adj_gxw. Work buffers per chunk of chirps:
+// keys, positions, records, adjoint records [chunk][facet records], grids [chunk][O][n_g].
+static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const RadarConst &rcn,
+                                     NuShape ns, const void *grad_echo, hipStream_t s) {
+  DevScene d = d_in;
+  d.n_points = 0;  // points carry no parameters
+  const int64_t F = d.n_facets, N = rcn.N, O = static_cast<int64_t>(rcn.P) * rcn.Q;
+  const int64_t stride = std::max<int64_t>(1, F << (2 * ns.split));
+  const size_t rec_b = nufft_record_bytes(ns.order, false), der_b = nufft_der_bytes(ns.order);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t per_chirp = stride * (8 + rec_b + der_b) + O * ns.ng * 8;
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
+  const size_t off_pos = al(chunk * stride * 4);
+  const size_t off_srec = off_pos + al(chunk * stride * 4);
+  const size_t off_sder = off_srec + al(chunk * stride * rec_b);
+  const size_t off_grid = off_sder + al(chunk * stride * der_b);
+  const size_t total = off_grid + chunk * O * ns.ng * 8;
+  int32_t rc = RSIM_OK;
+  if (ctx->nu_adj_bytes < total) {
+    HIP_TRY(ctx, hipDeviceSynchronize());  // earlier launches may still use the buffer
+    dev_free(ctx, ctx->nu_adj_buf);
+    ctx->nu_adj_buf = nullptr;
+    ctx->nu_adj_bytes = 0;
+    if ((rc = dev_alloc(ctx, &ctx->nu_adj_buf, total))) return rc;
+    ctx->nu_adj_bytes = total;
+  }
+  char *b = static_cast<char *>(ctx->nu_adj_buf);
+  NuBuffers nb{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
+               b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b, b + off_sder};
+  void *tw = twiddles(ctx, ns.ng, 0, &rc);
+  if (rc) return rc;
+  HIP_TRY(ctx, launch_fill_zero(ctx->adj_partial, N * F * kAdjSlotFloats, s));
+  ns.rec_stride = stride;
+  ns.runs = static_cast<int32_t>((stride + nufft_run_length() - 1) / nufft_run_length());
+  for (int64_t n0 = 0; n0 < N; n0 += chunk) {
+    ns.n0 = static_cast<int32_t>(n0);
+    ns.n_chirps = static_cast<int32_t>(std::min<int64_t>(chunk, N - n0));
+    HIP_TRY(ctx, launch_nufft_adjoint(d, rcn, ctx->d_elem, ns, nb, tw, grad_echo,
+                                      ctx->adj_partial, s));
+  }
+  EchoShape sh{};
+  sh.O = static_cast<int32_t>(O);
+  sh.o_tiles = 1;
+  sh.m_tiles = 1;
+  HIP_TRY(ctx, launch_fill_zero(ctx->adj_gxw, N * F * 9, s));
+  HIP_TRY(ctx, launch_adjoint_finish(d, rcn, sh, ctx->adj_partial, ctx->adj_gxw, s));
+  return RSIM_OK;
+}
+
 int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                       const uint32_t *vis_mask, float *const *grad_verts, int32_t n_meshes,
                       double *grad_vel, void *hip_stream) {
@@ -1436,14 +1488,30 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   if ((rc = need_device(ctx))) return rc;
   SceneRec &sc = ctx->scenes[scene_id];
   if ((rc = ensure_scene_device(ctx, sc))) return rc;
-  // matrix cores when the array allows them (unless the vector units are asked for)
+  // the NUFFT adjoint when asked for; else the matrix cores when the array allows them
+  // (unless the vector units are asked for)
+  // (AUTO: the NUFFT where eligible)
+  NuShape nsb{};
+  bool nufft = false;
+  if (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO) {
+    rsim_opts ob{};
+    ob.precision = RSIM_FP32_PHASE64;
+    const char *nwhy = nufft_ineligible(ctx, rcn, ob, scenes_rmax(ctx, {scene_id}), 0.0, &nsb);
+    if (nwhy && ctx->bwd_kernel == RSIM_KERNEL_NUFFT)
+      return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
+    nufft = !nwhy;
+  }
   const char *why = matrix_ineligible(ctx, rcn, RSIM_FP32_PHASE64);
   if (ctx->bwd_kernel == RSIM_KERNEL_MATRIX && why)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", why);
-  const bool matrix = !why && ctx->bwd_kernel != RSIM_KERNEL_VECTOR &&
+  const bool matrix = !nufft && !why && ctx->bwd_kernel != RSIM_KERNEL_VECTOR &&
                       adjoint_mfma_smem_bytes(rcn.P, rcn.Q, rcn.P + rcn.Q) <= ctx->max_lds;
   EchoShape sh{};
-  if (matrix) {
+  if (nufft) {
+    sh.O = rcn.P * rcn.Q;
+    sh.o_tiles = 1;
+    sh.m_tiles = 1;  // one adjoint slot per (chirp, lit facet)
+  } else if (matrix) {
     sh.O = rcn.P * rcn.Q;
     sh.E = rcn.P + rcn.Q;
     sh.O_w = sh.O;
@@ -1498,7 +1566,9 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   const bool timing = ctx->timing_pending;
   HIP_TRY(ctx, launch_compact(d, rcn.N, s));
   stage_begin(ctx, timing, 5, s);
-  if (matrix)
+  if (nufft) {
+    if ((rc = enqueue_nufft_adjoint(ctx, d, rcn, nsb, grad_echo, s))) return rc;
+  } else if (matrix)
     HIP_TRY(ctx, launch_adjoint_mfma(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial,
                                      ctx->adj_gxw, s));
   else

@@ -89,6 +89,23 @@ static_assert(sizeof(NuRecIntra<5>) == 144 && sizeof(NuRecIntra<7>) == 160 &&
                   sizeof(NuRecIntra<10>) == 192,
               "record size");
 
+// Adjoint record: derivatives of the Taylor coefficients and of the source position with
+// respect to the facet's three node offsets, and the facet's index in the lit list.
+template <int R>
+struct alignas(16) NuDer {
+  float2 db[3][R];  // d b_k / d beta_v (per metre)
+  float dx[3];      // d x / d beta_v (cells per metre; nonzero for sub-triangles)
+  int32_t item;
+};
+static_assert(sizeof(NuDer<5>) == 144 && sizeof(NuDer<7>) == 192 && sizeof(NuDer<10>) == 256,
+              "adjoint record size");
+static_assert(kAdjVals == kAdjSlotFloats, "adjoint slot layout");
+constexpr double kNuDerStep = 1e-6;  // metres: central differences of b_k in beta (FP64)
+
+size_t nufft_der_bytes(int order) {
+  return order <= 5 ? sizeof(NuDer<5>) : order <= 7 ? sizeof(NuDer<7>) : sizeof(NuDer<10>);
+}
+
 template <bool INTRA>
 static size_t record_bytes_t(int order) {
   return order <= 5 ? sizeof(NuRecT<5, INTRA>)
@@ -202,6 +219,113 @@ __device__ inline double sub_nodes(const double beta[3], int sub, int split, dou
   return c;
 }
 
+// Taylor coefficients b_k (FP64) of one record: the facet with node offsets beta_f about
+// its centroid, or its sub-triangle `sub` (own nodes about the sub-centroid, 4^-split of the
+// area, the factor exp(j k_c bc)). Returns bc, the sub-centroid's offset (0 unsplit).
+template <int R>
+__device__ double taylor_coeffs(const Geo &g, const double beta_f[3], int sub,
+                                const NuShape &ns, double br[R], double bi[R]) {
+  double beta[3] = {beta_f[0], beta_f[1], beta_f[2]};
+  double bc = 0.0;
+  double amp_re = g.amp_re, amp_im = g.amp_im;
+  if (sub >= 0 && ns.split > 0) {
+    bc = sub_nodes(beta_f, sub, ns.split, beta);
+    const double scale = 1.0 / static_cast<double>(1 << (2 * ns.split));
+    double sb, cb;
+    const double tb = ns.fc / kC0 * bc;
+    sincospi_t(2.0 * (tb - rint(tb)), &sb, &cb);
+    const double ar = amp_re * scale, ai = amp_im * scale;
+    amp_re = ar * cb - ai * sb;
+    amp_im = ar * sb + ai * cb;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) br[k] = bi[k] = 0.0;
+  if (!g.valid) return bc;
+  const double turns_per_m = ns.fc / kC0;  // k_c / (2 pi)
+  const double A0 = turns_per_m * beta[0], A1 = turns_per_m * beta[1],
+               A2 = turns_per_m * beta[2];
+  // divided differences of exp(j k_c beta) over beta, divided by k_c^2:
+  // [b0,b1,b2] = -Phi, [b1,b2] = -F[a1,a2] / k_c, [b2] = exp(j k_c b2) / k_c^2
+  // (Phi and F the second and first divided differences of -exp(jx) at a = k_c beta)
+  const double2 phi = phi_turns<double>(A0, A1, A2);
+  const double2 f12 = first_dd<double>(A1, A2);
+  const double ik = 1.0 / ns.kc;
+  double s2, c2;
+  sincospi_t(2.0 * (A2 - rint(A2)), &s2, &c2);
+  const double g2r = -phi.x, g2i = -phi.y;
+  const double g1r = -f12.x * ik, g1i = -f12.y * ik;
+  const double g0r = c2 * ik * ik, g0i = s2 * ik * ik;
+  const double b0 = beta[0], b1 = beta[1], b2 = beta[2];
+  const double e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
+  // a_r = D_r (-kappa / s)^r / r!, D_r = b0^r [b0,b1,b2] + h_{r-1}(b0,b1) [b1,b2]
+  //                                      + h_{r-2}(b0,b1,b2) [b2]
+  double ar[R], ai[R];
+  double p0 = 1.0;                       // b0^r
+  double q1m = 0.0, q1 = 0.0;            // h_{r-2}(b0,b1), h_{r-1}(b0,b1)
+  double t3 = 0.0, t2 = 0.0, t1 = 0.0;   // h_{r-4}, h_{r-3}, h_{r-2} of (b0,b1,b2)
+  double scale = 1.0;                    // (-kappa / s)^r / r!
+  const double step = -ns.kappa / ns.sigma;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (r >= 1) {
+      p0 *= b0;
+      const double qn = (r == 1) ? 1.0 : (b0 + b1) * q1 - b0 * b1 * q1m;
+      q1m = q1;
+      q1 = qn;
+      scale *= step / r;
+    }
+    if (r >= 2) {
+      const double tn = (r == 2) ? 1.0 : e1 * t1 - e2 * t2 + e3 * t3;
+      t3 = t2;
+      t2 = t1;
+      t1 = tn;
+    }
+    const double dr = p0 * g2r + q1 * g1r + t1 * g0r;
+    const double di = p0 * g2i + q1 * g1i + t1 * g0i;
+    ar[r] = dr * scale;
+    ai[r] = di * scale;
+  }
+  // b_k = -amp / s^k sum_{r >= k} a_r He_{r,k}
+  double is_k = 1.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int r = k; r < R; ++r) {
+      sr += ar[r] * kHe.c[r][k];
+      si += ai[r] * kHe.c[r][k];
+    }
+    sr *= is_k;
+    si *= is_k;
+    is_k /= ns.sigma;
+    br[k] = -(amp_re * sr - amp_im * si);
+    bi[k] = -(amp_re * si + amp_im * sr);
+  }
+  return bc;
+}
+
+// The phase-centre path of a record (FP64): unit vectors, distances, reduced phase, the
+// source's grid cell and fraction (the same cell as the key pass).
+template <int R>
+__device__ void path_fields(const Geo &g, const RadarConst &rc, const NuShape &ns, double bc,
+                            NuRec<R> &out, double *Rt, double *Rr, double *dxc) {
+  double x;
+  int cell;
+  centre_cell(g, rc, ns, bc, &x, &cell, Rt, Rr, dxc);
+  for (int k = 0; k < 3; ++k) {
+    out.ut[k] = (g.c[k] - rc.tx_c[k]) / *Rt;
+    out.ur[k] = (g.c[k] - rc.rx_c[k]) / *Rr;
+  }
+  const double tau = (*Rt + *Rr) * (1.0 / kC0);
+  const double turns = ns.fc * tau - 0.5 * rc.slope * tau * tau;
+  out.rt = static_cast<float>(*Rt);
+  out.rr = static_cast<float>(*Rr);
+  out.t0 = static_cast<float>(turns - rint(turns));
+  out.g1 = (ns.fc - rc.slope * tau) * (1.0 / kC0);
+  out.frac = static_cast<float>(x - floor(x));
+  out.cell = cell;
+}
+
 template <int R, bool INTRA>
 __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst rc, NuShape ns,
                                                         NuBuffers nb) {
@@ -214,91 +338,14 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
   const int32_t entry = record_entry(item, cnt, ns.split, &sub);
   Geo g;
   entry_geometry(sc, rc, n, cnt, entry, g);
-  // a sub-triangle: its own nodes, a source shifted by its centroid's offset bc (the
-  // factor exp(j k_c bc) goes into the coefficients) and 4^-split of the area
-  double beta[3] = {g.beta[0], g.beta[1], g.beta[2]};
-  double bc = 0.0;
-  if (sub >= 0 && ns.split > 0) {
-    bc = sub_nodes(g.beta, sub, ns.split, beta);
-    const double scale = 1.0 / static_cast<double>(1 << (2 * ns.split));
-    double sb, cb;
-    const double tb = ns.fc / kC0 * bc;
-    sincospi_t(2.0 * (tb - rint(tb)), &sb, &cb);
-    const double ar = g.amp_re * scale, ai = g.amp_im * scale;
-    g.amp_re = ar * cb - ai * sb;
-    g.amp_im = ar * sb + ai * cb;
-  }
   NuRecT<R, INTRA> out;
   out.valid = g.valid;
+  double br[R], bi[R];
+  const double bc = taylor_coeffs<R>(g, g.beta, sub, ns, br, bi);
 #pragma unroll
-  for (int k = 0; k < R; ++k) out.b[k] = {0.0f, 0.0f};
-  if (g.valid) {
-    const double turns_per_m = ns.fc / kC0;  // k_c / (2 pi)
-    const double A0 = turns_per_m * beta[0], A1 = turns_per_m * beta[1],
-                 A2 = turns_per_m * beta[2];
-    // divided differences of exp(j k_c beta) over beta, divided by k_c^2:
-    // [b0,b1,b2] = -Phi, [b1,b2] = -F[a1,a2] / k_c, [b2] = exp(j k_c b2) / k_c^2
-    // (Phi and F the second and first divided differences of -exp(jx) at a = k_c beta)
-    const double2 phi = phi_turns<double>(A0, A1, A2);
-    const double2 f12 = first_dd<double>(A1, A2);
-    const double ik = 1.0 / ns.kc;
-    double s2, c2;
-    sincospi_t(2.0 * (A2 - rint(A2)), &s2, &c2);
-    const double g2r = -phi.x, g2i = -phi.y;
-    const double g1r = -f12.x * ik, g1i = -f12.y * ik;
-    const double g0r = c2 * ik * ik, g0i = s2 * ik * ik;
-    const double b0 = beta[0], b1 = beta[1], b2 = beta[2];
-    const double e1 = b0 + b1 + b2, e2 = b0 * b1 + b0 * b2 + b1 * b2, e3 = b0 * b1 * b2;
-    // a_r = D_r (-kappa / s)^r / r!, D_r = b0^r [b0,b1,b2] + h_{r-1}(b0,b1) [b1,b2]
-    //                                      + h_{r-2}(b0,b1,b2) [b2]
-    double ar[R], ai[R];
-    double p0 = 1.0;                       // b0^r
-    double q1m = 0.0, q1 = 0.0;            // h_{r-2}(b0,b1), h_{r-1}(b0,b1)
-    double t3 = 0.0, t2 = 0.0, t1 = 0.0;   // h_{r-4}, h_{r-3}, h_{r-2} of (b0,b1,b2)
-    double scale = 1.0;                    // (-kappa / s)^r / r!
-    const double step = -ns.kappa / ns.sigma;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (r >= 1) {
-        p0 *= b0;
-        const double qn = (r == 1) ? 1.0 : (b0 + b1) * q1 - b0 * b1 * q1m;
-        q1m = q1;
-        q1 = qn;
-        scale *= step / r;
-      }
-      if (r >= 2) {
-        const double tn = (r == 2) ? 1.0 : e1 * t1 - e2 * t2 + e3 * t3;
-        t3 = t2;
-        t2 = t1;
-        t1 = tn;
-      }
-      const double dr = p0 * g2r + q1 * g1r + t1 * g0r;
-      const double di = p0 * g2i + q1 * g1i + t1 * g0i;
-      ar[r] = dr * scale;
-      ai[r] = di * scale;
-    }
-    // b_k = -amp / s^k sum_{r >= k} a_r He_{r,k}
-    double is_k = 1.0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int r = k; r < R; ++r) {
-        sr += ar[r] * kHe.c[r][k];
-        si += ai[r] * kHe.c[r][k];
-      }
-      sr *= is_k;
-      si *= is_k;
-      is_k /= ns.sigma;
-      out.b[k] = {static_cast<float>(-(g.amp_re * sr - g.amp_im * si)),
-                  static_cast<float>(-(g.amp_re * si + g.amp_im * sr))};
-    }
-  }
-  // the phase-centre path (FP64), and the source position on the grid (the same cell as
-  // the key pass)
-  double x, Rt, Rr, dxc;
-  int cell;
-  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr, &dxc);
+  for (int k = 0; k < R; ++k) out.b[k] = {static_cast<float>(br[k]), static_cast<float>(bi[k])};
+  double Rt, Rr, dxc;
+  path_fields(g, rc, ns, bc, out, &Rt, &Rr, &dxc);
   if constexpr (INTRA) {
     double vut = 0.0, vur = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -310,18 +357,6 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
     out.vur = static_cast<float>(vur);
     out.dxc = static_cast<float>(dxc);
   }
-  for (int k = 0; k < 3; ++k) {
-    out.ut[k] = (g.c[k] - rc.tx_c[k]) / Rt;
-    out.ur[k] = (g.c[k] - rc.rx_c[k]) / Rr;
-  }
-  const double tau = (Rt + Rr) * (1.0 / kC0);
-  const double turns = ns.fc * tau - 0.5 * rc.slope * tau * tau;
-  out.rt = static_cast<float>(Rt);
-  out.rr = static_cast<float>(Rr);
-  out.t0 = static_cast<float>(turns - rint(turns));
-  out.g1 = (ns.fc - rc.slope * tau) * (1.0 / kC0);
-  out.frac = static_cast<float>(x - floor(x));
-  out.cell = cell;
   const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
   static_cast<NuRecT<R, INTRA> *>(nb.srec)[row + nb.pos[row + item]] = out;
 }
@@ -619,6 +654,305 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
   }
 }
 
+
+// ---- adjoint (type-2 transform): the loss gradient G = dL/dRe H + j dL/dIm H of the
+// kept modes goes through the transpose of the deconvolution and FFT onto each channel's
+// grid, and every record then gathers Gaussian-weighted moments of that grid instead of
+// spreading onto it. With y = sum_m conj(G) H of one (record, channel),
+//   y = Q sum_k b_k mu_k,  mu_k = sum_l g(l) psi(l - x) (l - x)^k,
+//   dy/dx = Q sum_k b_k (mu_{k+1} / s^2 - k mu_{k-1}),
+// and the seven per-(facet, chirp) sums of the direct adjoint follow: dL/dc through the
+// element distances (the channel's delay and 1 / (R_t R_r)), sum Re y, and dL/dbeta_v
+// through b_k (and the sub-triangle's source position).
+
+// Adjoint preparation: the forward record plus d b_k / d beta_v by central differences in
+// FP64 (step kNuDerStep: truncation ~ (k_c h)^2 / 6 ~ 5e-7, rounding ~ 1e-10 relative).
+template <int R>
+__global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarConst rc,
+                                                            NuShape ns, NuBuffers nb) {
+  const int nl = blockIdx.y;
+  const int n = ns.n0 + nl;
+  const int32_t cnt = sc.vis_cnt[n];
+  const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (item >= (cnt << (2 * ns.split))) return;
+  int sub;
+  const int32_t entry = record_entry(item, cnt, ns.split, &sub);
+  Geo g;
+  entry_geometry(sc, rc, n, cnt, entry, g);
+  NuRec<R> out;
+  out.valid = g.valid;
+  NuDer<R> der;
+  der.item = entry;
+  double bc = 0.0;
+  double dbr[3][R], dbi[3][R], dbc[3] = {0.0, 0.0, 0.0};
+  const double h2 = 0.5 / kNuDerStep;
+#pragma unroll
+  for (int e = 0; e < 7; ++e) {  // the facet's offsets, then each one moved by +h and -h
+    double bt[3] = {g.beta[0], g.beta[1], g.beta[2]};
+    const int v = (e - 1) >> 1;
+    const double sgn = ((e - 1) & 1) ? -1.0 : 1.0;
+    if (e > 0) bt[v] += sgn * kNuDerStep;
+    double cr[R], ci[R];
+    const double c = taylor_coeffs<R>(g, bt, sub, ns, cr, ci);
+    if (e == 0) {
+      bc = c;
+#pragma unroll
+      for (int k = 0; k < R; ++k) out.b[k] = {static_cast<float>(cr[k]), static_cast<float>(ci[k])};
+    } else if (sgn > 0.0) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        dbr[v][k] = cr[k];
+        dbi[v][k] = ci[k];
+      }
+      dbc[v] = c;
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        der.db[v][k] = {static_cast<float>((dbr[v][k] - cr[k]) * h2),
+                        static_cast<float>((dbi[v][k] - ci[k]) * h2)};
+      }
+      der.dx[v] = static_cast<float>(-ns.kappa * (dbc[v] - c) * h2);
+    }
+  }
+  double Rt, Rr, dxc;
+  path_fields(g, rc, ns, bc, out, &Rt, &Rr, &dxc);
+  const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
+  const int64_t at = row + nb.pos[row + item];
+  static_cast<NuRec<R> *>(nb.srec)[at] = out;
+  static_cast<NuDer<R> *>(nb.sder)[at] = der;
+}
+
+// Per (chirp, group of cb channels): the transpose of nufft_fft_kernel. conj(G) of the kept
+// modes times the same deconvolution factor, placed at mode m' mod n_g and transformed with
+// the same sign, gives grid rows g(l) with sum_m conj(G(m)) H(m) = sum_l S(l) g(l) for the
+// spread S of the forward transform.
+__global__ void __launch_bounds__(kNuFftThreads) nufft_adj_fft_kernel(
+    DevScene sc, RadarConst rc, NuShape ns, NuBuffers nb, const float2 *tw,
+    const float2 *grad_echo) {
+  extern __shared__ float2 nu_smem[];
+  const int nl = blockIdx.x / ns.groups;
+  const int grp = blockIdx.x - nl * ns.groups;
+  const int n = ns.n0 + nl;
+  const int ld = ns.ld, ng = ns.ng, cb = ns.cb;
+  const int O = rc.P * rc.Q;
+  float2 *lgrid = nu_smem;            // [cb][ld]
+  float2 *work = nu_smem + cb * ld;   // [cb][ld]
+  for (int i = threadIdx.x; i < cb * ng; i += blockDim.x) {
+    const int c = i / ng, l = i - c * ng;
+    lgrid[c * ld + l] = {0.0f, 0.0f};
+  }
+  __syncthreads();
+  const int M = rc.M;
+  const float s = static_cast<float>(ns.sigma);
+  const float hs2 = 0.5f * s * s;
+  const float inv_norm = static_cast<float>(1.0 / (ns.sigma * 2.5066282746310002));
+  const float w_per_mode = static_cast<float>(2.0 * kPi / ng);
+  for (int idx = threadIdx.x; idx < cb * M; idx += blockDim.x) {
+    const int sq = idx / M;
+    const int m = idx - sq * M;
+    const int oo = grp * cb + sq;
+    if (oo >= O) continue;
+    const int mp = m - M / 2;
+    const float w = w_per_mode * static_cast<float>(mp);
+    const float fr = static_cast<float>(ns.fc / (rc.f0 + m * rc.df));
+    const float corr = fr * fr * inv_norm * __expf(hs2 * w * w);
+    const float2 G = grad_echo[(static_cast<int64_t>(oo) * rc.N + n) * M + m];
+    lgrid[sq * ld + (mp < 0 ? mp + ng : mp)] = {G.x * corr, -G.y * corr};
+  }
+  __syncthreads();
+  const float2 *res = stockham(lgrid, work, ng, cb, ld, tw);
+  for (int i = threadIdx.x; i < cb * ng; i += blockDim.x) {
+    const int c = i / ng, l = i - c * ng;
+    const int o = grp * cb + c;
+    if (o < O) nb.grid[(static_cast<int64_t>(nl) * O + o) * ng + l] = res[c * ld + l];
+  }
+}
+
+// One wave per (chirp, 64 channels, run of kNuSeg sorted records), as the spread: each
+// lane (channel) holds a window of its grid row in registers (reloaded when the sorted
+// positions leave it), forms the moments mu_0 .. mu_R of every record, and the wave sums
+// the seven per-facet values over its channels (DPP, fixed order) into
+// partial[chirp][lit facet][kAdjVals] with one atomic add each (sub-triangles and the
+// other channel groups add to the same facet).
+template <int R>
+__global__ void __launch_bounds__(kNuSpreadThreads) nufft_gather_kernel(
+    DevScene sc, RadarConst rc, NuShape ns, const double *elem, const NuRec<R> *__restrict__ sorted,
+    const NuDer<R> *__restrict__ ders, const float2 *__restrict__ grids, float *partial) {
+  const int wave = __builtin_amdgcn_readfirstlane(
+      static_cast<int>(blockIdx.x) * (kNuSpreadThreads / 64) + static_cast<int>(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int runs = ns.runs;
+  const int per_chirp = ns.spread_groups * runs;
+  const int nl = wave / per_chirp;
+  if (nl >= ns.n_chirps) return;
+  const int rem = wave - nl * per_chirp;
+  const int grp = rem / runs;
+  const int run = rem - grp * runs;
+  const int n = ns.n0 + nl;
+  const int32_t n_ent = sc.vis_cnt[n] << (2 * ns.split);
+  const int e_begin = run * kNuSeg;
+  if (e_begin >= n_ent) return;
+  const int e_end = min(n_ent, e_begin + kNuSeg);
+  const int ng = ns.ng;
+  const int O = rc.P * rc.Q;
+  const int o = grp * 64 + lane;
+  const bool on = o < O;
+  double at[3], ar[3];
+  float aat, aar, atf[3], arf[3];
+  {
+    const int oc = on ? o : 0;
+    const int p = oc / rc.Q, q = oc - p * rc.Q;
+    double st = 0.0, sr = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      at[k] = elem[3 * p + k] - rc.tx_c[k];
+      ar[k] = elem[3 * (rc.P + q) + k] - rc.rx_c[k];
+      st += at[k] * at[k];
+      sr += ar[k] * ar[k];
+    }
+    aat = static_cast<float>(st);
+    aar = static_cast<float>(sr);
+    for (int k = 0; k < 3; ++k) {
+      atf[k] = static_cast<float>(at[k]);
+      arf[k] = static_cast<float>(ar[k]);
+    }
+  }
+  const NuRec<R> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
+  const NuDer<R> *sder = ders + static_cast<int64_t>(nl) * ns.rec_stride;
+  const float2 *grow = grids + (static_cast<int64_t>(nl) * O + (on ? o : 0)) * ng;
+  float *prow = partial + static_cast<int64_t>(n) * sc.n_facets * kAdjVals;
+  const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
+  const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
+  const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
+  const float kappa = static_cast<float>(ns.kappa);
+  const float g2 = static_cast<float>(0.5 * rc.slope / (kC0 * kC0));
+  const float two_pi = static_cast<float>(2.0 * kPi);
+  const float d = static_cast<float>(ns.chan_d);
+  const int b0 = static_cast<int>(ceilf(d + 0.5f * kNuWidth));
+  const float rel_hi = static_cast<float>(kNuSlots - 1) - d - 0.5f * kNuWidth;
+  float2 win[kNuSlots];
+  int i = e_begin;
+  NuRec<R> nxt = load_uniform(srec + i);
+  while (i < e_end) {
+    const int base = nxt.cell - b0;  // wave-uniform
+#pragma unroll
+    for (int s = 0; s < kNuSlots; ++s) {
+      // base + s lies in [-ng, 2 ng) (n_g >= 32 > the window)
+      int cell = base + s;
+      cell += (cell < 0) ? ng : 0;
+      cell -= (cell >= ng) ? ng : 0;
+      win[s] = on ? grow[cell] : make_float2(0.0f, 0.0f);
+    }
+    const int first = i;
+    for (; i < e_end; ++i) {
+      const NuRec<R> r = nxt;
+      int rk = r.cell - base;
+      if (rk > ng / 2) rk -= ng;
+      if (rk < -ng / 2) rk += ng;
+      const float rel_c = static_cast<float>(rk) + r.frac;
+      if (i > first && (rel_c < d + 0.5f * kNuWidth || rel_c > rel_hi)) break;
+      if (i + 1 < e_end) nxt = load_uniform(srec + i + 1);
+      const int s_lo =
+          __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - d - 0.5f * kNuWidth)));
+      const int s_hi =
+          __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c + d + 0.5f * kNuWidth)));
+      // this channel's path (as in the spread)
+      const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
+      const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
+      const double ps = (st + sr) * r.g1;
+      const float pr = static_cast<float>(ps - rint(ps));
+      const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
+      const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
+      const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
+      const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
+      const float qt = ht * rdt, qr = hr * rdr;
+      const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
+      const float dRt = et - sft, dRr = er - sfr;
+      const float dL = dRt + dRr;
+      float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
+      const float xr = fmaf(kappa, dL, rel_c);
+      t -= rintf(t);
+      const float Rtp = r.rt + dRt, Rrq = r.rr + dRr;
+      const float amp = __builtin_amdgcn_rcpf(Rtp * Rrq);
+      const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
+      // moments of the grid row about x
+      float2 mu[R + 1];
+#pragma unroll
+      for (int k = 0; k <= R; ++k) mu[k] = {0.0f, 0.0f};
+      const float u0 = static_cast<float>(s_lo) - xr;
+      float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+      float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+#pragma unroll
+      for (int s = 0; s < kNuSlots; ++s) {
+        if (s >= s_lo && s <= s_hi) {
+          const float u = static_cast<float>(s) - xr;
+          const float wr = gw * win[s].x, wi = gw * win[s].y;
+          mu[0].x += wr;
+          mu[0].y += wi;
+          float up = 1.0f;
+#pragma unroll
+          for (int k = 1; k <= R; ++k) {
+            up *= u;
+            mu[k].x = fmaf(wr, up, mu[k].x);
+            mu[k].y = fmaf(wi, up, mu[k].y);
+          }
+          gw *= rho;
+          rho *= q_ratio;
+        }
+      }
+      // Q mu_k; y and dy/dx
+      float2 qm[R + 1];
+#pragma unroll
+      for (int k = 0; k <= R; ++k) qm[k] = {qx * mu[k].x - qy * mu[k].y, qx * mu[k].y + qy * mu[k].x};
+      float yr = 0.0f, yi = 0.0f, yxr = 0.0f;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const float2 b = r.b[k];
+        yr += b.x * qm[k].x - b.y * qm[k].y;
+        yi += b.x * qm[k].y + b.y * qm[k].x;
+        float nr = qm[k + 1].x * inv_s2, ni = qm[k + 1].y * inv_s2;
+        if (k > 0) {
+          nr = fmaf(-static_cast<float>(k), qm[k - 1].x, nr);
+          ni = fmaf(-static_cast<float>(k), qm[k - 1].y, ni);
+        }
+        yxr += b.x * nr - b.y * ni;
+      }
+      // dL/dbeta_v through b_k and the source position
+      const NuDer<R> dv = sder[i];
+      float tv[3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        float a = dv.dx[v] * yxr;
+#pragma unroll
+        for (int k = 0; k < R; ++k) a += dv.db[v][k].x * qm[k].x - dv.db[v][k].y * qm[k].y;
+        tv[v] = a;
+      }
+      // dL/dc through the element distances: d Re y / dR = K Im y + kappa Re(dy/dx) - Re y / R
+      // (K = 2 pi (f_c - mu tau) / c of this channel), with dR_tp / dc = -e_p
+      const float K = two_pi * fmaf(-2.0f * g2, dL, static_cast<float>(r.g1));
+      const float A = fmaf(K, yi, kappa * yxr);
+      const float ct = A - yr * __builtin_amdgcn_rcpf(Rtp);
+      const float cr = A - yr * __builtin_amdgcn_rcpf(Rrq);
+      const float irt = __builtin_amdgcn_rcpf(Rtp), irr = __builtin_amdgcn_rcpf(Rrq);
+      float vals[kAdjVals - 1];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float ep = (atf[k] - r.rt * static_cast<float>(r.ut[k])) * irt;
+        const float eq = (arf[k] - r.rr * static_cast<float>(r.ur[k])) * irr;
+        vals[k] = -(ct * ep + cr * eq);
+      }
+      vals[3] = yr;
+      vals[4] = tv[0];
+      vals[5] = tv[1];
+      vals[6] = tv[2];
+#pragma unroll
+      for (int k = 0; k < kAdjVals - 1; ++k) {
+        const float v = wave_sum(on ? vals[k] : 0.0f);
+        if (r.valid && lane == 0) atomicAdd(&prow[static_cast<int64_t>(dv.item) * kAdjVals + k], v);
+      }
+    }
+  }
+}
+
 size_t nufft_smem_bytes(const NuShape &ns) {
   return sizeof(float2) * static_cast<size_t>(2 * ns.cb) * ns.ld;
 }
@@ -665,6 +999,46 @@ hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *
   if (ns.order == 5) return launch_nufft_t<5>(sc, rc, elem, ns, nb, tw, s);
   if (ns.order == 7) return launch_nufft_t<7>(sc, rc, elem, ns, nb, tw, s);
   if (ns.order == 10) return launch_nufft_t<10>(sc, rc, elem, ns, nb, tw, s);
+  return hipErrorInvalidValue;
+}
+
+
+template <int R>
+hipError_t launch_nufft_adjoint_t(const DevScene &sc, const RadarConst &rc, const double *elem,
+                                  const NuShape &ns, const NuBuffers &nb, const void *tw,
+                                  const void *grad_echo, float *partial, hipStream_t s) {
+  if (ns.n_chirps <= 0) return hipSuccess;
+  if (sizeof(NuRec<R>) > nb.rec_bytes || !nb.sder || sc.n_points != 0 || rc.intra)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(nufft_adj_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
+                     dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
+                     static_cast<const float2 *>(tw), static_cast<const float2 *>(grad_echo));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t items = sc.n_facets << (2 * ns.split);
+  if (items == 0) return hipSuccess;
+  dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
+  hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(nufft_count_kernel, dim3(ns.n_chirps), dim3(1024), 0, s, sc, ns, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((nufft_adj_prep_kernel<R>), grid, dim3(256), 0, s, sc, rc, ns, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t waves = static_cast<int64_t>(ns.n_chirps) * ns.spread_groups * ns.runs;
+  const int64_t blocks = (waves + kNuSpreadThreads / 64 - 1) / (kNuSpreadThreads / 64);
+  hipLaunchKernelGGL((nufft_gather_kernel<R>), dim3(static_cast<unsigned>(blocks)),
+                     dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
+                     static_cast<const NuRec<R> *>(nb.srec), static_cast<const NuDer<R> *>(nb.sder),
+                     static_cast<const float2 *>(nb.grid), partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
+                                const NuShape &ns, const NuBuffers &nb, const void *tw,
+                                const void *grad_echo, float *partial, hipStream_t s) {
+  if (ns.order == 5) return launch_nufft_adjoint_t<5>(sc, rc, elem, ns, nb, tw, grad_echo, partial, s);
+  if (ns.order == 7) return launch_nufft_adjoint_t<7>(sc, rc, elem, ns, nb, tw, grad_echo, partial, s);
+  if (ns.order == 10) return launch_nufft_adjoint_t<10>(sc, rc, elem, ns, nb, tw, grad_echo, partial, s);
   return hipErrorInvalidValue;
 }
 

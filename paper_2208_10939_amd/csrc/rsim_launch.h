@@ -85,14 +85,29 @@ struct NuBuffers {
   void *srec;
   float2 *grid;
   size_t rec_bytes;  // record slot size of srec (a launch refuses wider records)
+  void *sder;        // adjoint records in the same order (adjoint only)
 };
 size_t nufft_record_bytes(int order, bool intra);
+size_t nufft_der_bytes(int order);
 size_t nufft_smem_bytes(const NuShape &ns);
 int nufft_window_cells();
 int nufft_run_length();
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
                         const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s);
+// Floats per (chirp, lit facet, slot) of the adjoint sums: dL/dc through the element
+// distances (3), sum Re y, dL/dbeta_v (3), pad.
+constexpr int kAdjSlotFloats = 8;
+// Per-(chirp, lit facet, slot) sums -> world-vertex gradients (FP64 chain rule) into gxw
+// (zero on entry), slots = sh.m_tiles * sh.o_tiles.
+hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
+                                 const float *partial, float *gxw, hipStream_t s);
+// Adjoint of launch_nufft for one chunk of chirps (stop-and-hop, facets only: sc.n_points
+// must be 0): adds the per-(chirp, lit facet) adjoint sums into partial
+// [N][n_facets][kAdjVals] (zero before the first chunk); nb.sder is required.
+hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
+                                const NuShape &ns, const NuBuffers &nb, const void *tw,
+                                const void *grad_echo, float *partial, hipStream_t s);
 
 hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t rows, int M,
                             int conj_in, const void *tw, hipStream_t s);

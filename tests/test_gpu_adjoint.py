@@ -51,9 +51,11 @@ def _with(sc, mesh_k=None, vert=None, axis=None, dv=0.0, inst_k=None, vaxis=None
     return Scene(meshes, insts)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_adjoint_matches_finite_differences(kernel):
-    """kernel 1: the vector-unit adjoint; 2: the matrix-core adjoint."""
+    """kernel 1: the vector-unit adjoint; 2: the matrix-core adjoint; 3: the NUFFT adjoint
+    (type-2 gather of Gaussian moments; Taylor-coefficient derivatives by FP64 central
+    differences)."""
     import torch
     from paper_2208_10939_amd.pipeline import Simulator
     _log(f"case adjoint vs FD (2 vehicles, 3x5 channels, M=32, N=8), kernel={kernel}")
@@ -117,12 +119,14 @@ def test_adjoint_matches_finite_differences(kernel):
     assert rel_c.max() <= 1e-2
 
 
-def test_adjoint_full_array_matches_finite_differences():
+@pytest.mark.parametrize("kernel", [0, 3])
+def test_adjoint_full_array_matches_finite_differences(kernel):
     """Same check with the 12 x 16 sparse array (192 channels: whole-wave workgroups,
-    the DPP reduction path) at a small frame."""
+    the DPP reduction path) at a small frame; kernel 0: the default choice, 3: the NUFFT
+    adjoint (three channel groups adding into one facet)."""
     import torch
     from paper_2208_10939_amd.pipeline import Simulator
-    _log("case adjoint vs FD (192 channels, M=16, N=4)")
+    _log(f"case adjoint vs FD (192 channels, M=16, N=4), kernel={kernel}")
     wf = scenes.paper_waveform(16, 4)
     arr = scenes.sparse_mimo_12x16(wf, 6)
     car = scenes.vehicle_mesh("car", 500)
@@ -145,6 +149,7 @@ def test_adjoint_full_array_matches_finite_differences():
     sim.ctx.rdm_backward(grad_rdm.contiguous(), y, ge)
     gv = [torch.zeros((car.verts.shape[0], 3), dtype=torch.float32, device="cuda")]
     gvel = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    sim.ctx.set_backward_kernel(kernel)
     sim.ctx.backward(sim.scene_ids[0], ge, m_t, gv, gvel)
     gv = gv[0].cpu().numpy().astype(np.float64)
     gvel = gvel.cpu().numpy()
