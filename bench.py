@@ -333,6 +333,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the forward+backward and batched-vs-plain measurements")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="only the forward + backward timing (for kernel traces of the adjoint)")
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--tile-f", type=int, default=0)
     ap.add_argument("--kernel", choices=("auto", "vector", "matrix", "nufft"), default="auto",
@@ -381,6 +383,9 @@ def main():
              f"{tuned['tile_m']} x {tuned['tile_f']}")
     kernel = (tuned["kernel"] if tuned else
               ("vector" if args.kernel == "auto" else args.kernel))
+    if args.fwd_bwd_only:
+        print(json.dumps({"facet_sum_kernel": kernel, "fwd_bwd": measure_fwd_bwd(sim)}))
+        return
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()

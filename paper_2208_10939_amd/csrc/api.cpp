@@ -1485,12 +1485,8 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   const RadarConst rcn = radar_const(ctx);
   if (cross_term_bound(ctx, rcn) > 3e-4)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: array aperture too large for the FP32 sum");
-  if ((rc = need_device(ctx))) return rc;
-  SceneRec &sc = ctx->scenes[scene_id];
-  if ((rc = ensure_scene_device(ctx, sc))) return rc;
-  // the NUFFT adjoint when asked for; else the matrix cores when the array allows them
-  // (unless the vector units are asked for)
-  // (AUTO: the NUFFT where eligible)
+  // the NUFFT adjoint when asked for, and with AUTO where eligible; else the matrix cores
+  // when the array allows them (unless the vector units are asked for)
   NuShape nsb{};
   bool nufft = false;
   if (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO) {
@@ -1501,6 +1497,9 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
       return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
     nufft = !nwhy;
   }
+  if ((rc = need_device(ctx))) return rc;
+  SceneRec &sc = ctx->scenes[scene_id];
+  if ((rc = ensure_scene_device(ctx, sc))) return rc;
   const char *why = matrix_ineligible(ctx, rcn, RSIM_FP32_PHASE64);
   if (ctx->bwd_kernel == RSIM_KERNEL_MATRIX && why)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", why);

@@ -218,3 +218,37 @@ def test_nufft_refusals_host_only():
     o_bad = rsim.Opts(kernel=4)
     assert L.rsim_synthesize(ctx._h, one(ids[0]), 1, echo, None, None, ctypes.byref(o_bad)) == rsim.RSIM_EINVAL
     ctx.close()
+
+
+def test_nufft_adjoint_refusals_host_only():
+    """The NUFFT adjoint (rsim_set_backward_kernel(RSIM_KERNEL_NUFFT)) has the forward's
+    eligibility, decided on the host: a coarse box beyond 64 sub-triangles is ERANGE, an
+    eligible scene reaches the missing device, AUTO never refuses for it, and kernel codes
+    beyond NUFFT are EINVAL."""
+    ctx = _host_ctx()
+    L = rsim.lib()
+    wf = scenes.paper_waveform(256, 8)
+    ctx.set_waveform(wf)
+    arr = scenes.sparse_mimo_12x16(wf, 2)
+    ctx.set_array(arr.tx, arr.rx)
+    ids = []
+    for m in (scenes.vehicle_mesh("car", 2000),
+              scenes.box_mesh((-2.0, -2.0, 0.0), (2.0, 2.0, 2.0), (1, 1, 1))):
+        mid = ctx.load_mesh(m.verts, m.tris)
+        sid = ctx.create_scene()
+        ctx.add_instance(sid, mid, np.eye(3), np.array([2.0, 30.0, 0.0]), np.zeros(3))
+        ids.append(sid)
+    dev = ctypes.c_void_p(0x1000)
+    gv = (ctypes.c_void_p * 1)(0x2000)
+
+    def bwd(sid):
+        return L.rsim_backward(ctx._h, sid, dev, dev, gv, 1, dev, None)
+
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT) == rsim.RSIM_OK
+    assert bwd(ids[0]) == rsim.RSIM_EDEVICE
+    assert bwd(ids[1]) == rsim.RSIM_ERANGE
+    assert b"grid cells" in L.rsim_last_error(ctx._h)
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_AUTO) == rsim.RSIM_OK
+    assert bwd(ids[1]) == rsim.RSIM_EDEVICE
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT + 1) == rsim.RSIM_EINVAL
+    ctx.close()
