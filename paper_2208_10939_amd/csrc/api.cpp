@@ -133,6 +133,7 @@ struct rsim_ctx {
   size_t nu_buf_bytes = 0;
   void *nu_adj_buf = nullptr;  // work buffers of the NUFFT adjoint (grow-only)
   size_t nu_adj_bytes = 0;
+  int32_t nu_chunk_max = 0;    // chirps per NUFFT chunk at most (0: as many as fit)
   std::array<int64_t, 5> nu_layout{};
   size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0, adj_gsum_n = 0;
   BatchTables batch;  // persistent launches outside graphs
@@ -1231,6 +1232,14 @@ int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double g
   return RSIM_OK;
 }
 
+int32_t rsim_set_nufft_chunk(rsim_ctx *ctx, int32_t max_chirps) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (max_chirps < 0)
+    return fail(ctx, RSIM_EINVAL, "rsim_set_nufft_chunk: max_chirps %d < 0", max_chirps);
+  ctx->nu_chunk_max = max_chirps;
+  return RSIM_OK;
+}
+
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
   if (kernel < RSIM_KERNEL_AUTO || kernel > RSIM_KERNEL_NUFFT)
@@ -1325,7 +1334,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       stride = std::max<int64_t>(stride, ctx->nu_layout[0]);
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t per_chirp = stride * (rec_b + 8) + O * ng * 8;
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
+    if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
     const size_t off_pos = al(chunk * stride * 4);
     const size_t off_srec = off_pos + al(chunk * stride * 4);
     const size_t off_grid = off_srec + al(chunk * stride * rec_b);
@@ -1432,7 +1442,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   const size_t rec_b = nufft_record_bytes(ns.order, false), der_b = nufft_der_bytes(ns.order);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t per_chirp = stride * (8 + rec_b + der_b) + O * ns.ng * 8;
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
+  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
+  if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
   const size_t off_pos = al(chunk * stride * 4);
   const size_t off_srec = off_pos + al(chunk * stride * 4);
   const size_t off_sder = off_srec + al(chunk * stride * rec_b);

@@ -251,4 +251,7 @@ def test_nufft_adjoint_refusals_host_only():
     assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_AUTO) == rsim.RSIM_OK
     assert bwd(ids[1]) == rsim.RSIM_EDEVICE
     assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT + 1) == rsim.RSIM_EINVAL
+    assert L.rsim_set_nufft_chunk(ctx._h, -1) == rsim.RSIM_EINVAL
+    assert L.rsim_set_nufft_chunk(ctx._h, 3) == rsim.RSIM_OK
+    assert L.rsim_set_nufft_chunk(ctx._h, 0) == rsim.RSIM_OK
     ctx.close()

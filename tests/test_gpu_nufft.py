@@ -277,3 +277,36 @@ def test_nufft_adjoint_equals_matrix_adjoint(sim_mod, coarse):
     dw = np.linalg.norm(wn - wm) / np.linalg.norm(wm)
     _log(f"  vertex gradients rel_l2={dv:.3e}, velocity gradients rel_l2={dw:.3e}")
     assert dv <= 1e-3 and dw <= 1e-3
+
+
+def test_nufft_chunked_equals_whole(sim_mod):
+    """Chirps in chunks of at most 3 (rsim_set_nufft_chunk) against one chunk: the forward
+    echo and the NUFFT adjoint's gradients agree to FP32 summation order."""
+    import torch
+    cfg = scenes.small_single(n_samples=128, n_chirps=8)
+    sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
+    _log("case nufft chunks of 3 chirps vs one chunk (N=8), forward and adjoint")
+    sim = sim_mod.Simulator([sc], wf, arr)
+    mask = sim.mask_buffer()
+    O = arr.tx.shape[0] * arr.rx.shape[0]
+    rng = np.random.default_rng(9)
+    g = (rng.standard_normal((O, wf.n_chirps, wf.n_samples)) +
+         1j * rng.standard_normal((O, wf.n_chirps, wf.n_samples))).astype(np.complex64)
+    ge = torch.from_numpy(g).cuda()
+    res = {}
+    for chunk in (0, 3):
+        sim.ctx.set_nufft_chunk(chunk)
+        H = sim.synthesize(mask=mask, kernel=NUFFT).cpu().numpy()
+        gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+              for m in sc.meshes]
+        gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+        sim.ctx.set_backward_kernel(NUFFT)
+        sim.ctx.backward(sim.scene_ids[0], ge, mask, gv, gvel)
+        res[chunk] = (H, np.concatenate([x.cpu().numpy().ravel() for x in gv]).astype(np.float64),
+                      gvel.cpu().numpy().ravel())
+    sim.ctx.set_nufft_chunk(0)
+    dh = rel_rms(res[3][0], res[0][0])
+    dv = np.linalg.norm(res[3][1] - res[0][1]) / np.linalg.norm(res[0][1])
+    dw = np.linalg.norm(res[3][2] - res[0][2]) / np.linalg.norm(res[0][2])
+    _log(f"  echo rel_rms={dh:.3e}, vertex gradients {dv:.3e}, velocity gradients {dw:.3e}")
+    assert dh <= 1e-6 and dv <= 1e-6 and dw <= 1e-6
