@@ -1432,7 +1432,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
 
 // NUFFT adjoint of one scene's facet sum into ctx->adj_partial (one slot per chirp and lit
 // facet), then the shared chain rule into ctx->adj_gxw. Work buffers per chunk of chirps:
-// keys, positions, records, adjoint records [chunk][facet records], grids [chunk][O][n_g].
+// records and adjoint records [chunk][facet records] in entry order, grids [chunk][O][n_g].
 static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const RadarConst &rcn,
                                      NuShape ns, const void *grad_echo, hipStream_t s) {
   DevScene d = d_in;
@@ -1441,11 +1441,10 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   const int64_t stride = std::max<int64_t>(1, F << (2 * ns.split));
   const size_t rec_b = nufft_record_bytes(ns.order, false), der_b = nufft_der_bytes(ns.order);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per_chirp = stride * (8 + rec_b + der_b) + O * ns.ng * 8;
+  const size_t per_chirp = stride * (rec_b + der_b) + O * ns.ng * 8;
   int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
   if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
-  const size_t off_pos = al(chunk * stride * 4);
-  const size_t off_srec = off_pos + al(chunk * stride * 4);
+  const size_t off_srec = 0;
   const size_t off_sder = off_srec + al(chunk * stride * rec_b);
   const size_t off_grid = off_sder + al(chunk * stride * der_b);
   const size_t total = off_grid + chunk * O * ns.ng * 8;
@@ -1459,8 +1458,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
     ctx->nu_adj_bytes = total;
   }
   char *b = static_cast<char *>(ctx->nu_adj_buf);
-  NuBuffers nb{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
-               b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b, b + off_sder};
+  NuBuffers nb{nullptr, nullptr, b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b,
+               b + off_sder};  // records in entry order: no keys or positions
   void *tw = twiddles(ctx, ns.ng, 0, &rc);
   if (rc) return rc;
   HIP_TRY(ctx, launch_fill_zero(ctx->adj_partial, N * F * kAdjSlotFloats, s));

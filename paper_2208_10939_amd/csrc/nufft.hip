@@ -60,6 +60,8 @@ constexpr int kNuMaxOrder = 10;
 constexpr int kNuSeg = 256;    // sorted records per spread wave
 constexpr int kNuSlots = 20;   // register window of grid cells per lane
 constexpr int kNuSpreadThreads = 256;
+constexpr int kNuGatherRecs = 256;  // records (lanes) per adjoint gather workgroup
+constexpr int kXcds = 8;            // accelerator complex dies: workgroups go round-robin
 
 template <int R>
 struct alignas(16) NuRec {
@@ -716,8 +718,7 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
   }
   double Rt, Rr, dxc;
   path_fields(g, rc, ns, bc, out, &Rt, &Rr, &dxc);
-  const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
-  const int64_t at = row + nb.pos[row + item];
+  const int64_t at = static_cast<int64_t>(nl) * ns.rec_stride + item;  // entry order
   static_cast<NuRec<R> *>(nb.srec)[at] = out;
   static_cast<NuDer<R> *>(nb.sder)[at] = der;
 }
@@ -768,189 +769,168 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_adj_fft_kernel(
   }
 }
 
-// One wave per (chirp, 64 channels, run of kNuSeg sorted records), as the spread: each
-// lane (channel) holds a window of its grid row in registers (reloaded when the sorted
-// positions leave it), forms the moments mu_0 .. mu_R of every record, and the wave sums
-// the seven per-facet values over its channels (DPP, fixed order) into
-// partial[chirp][lit facet][kAdjVals] with one atomic add each (sub-triangles and the
-// other channel groups add to the same facet).
+// One lane per (chirp, record), a workgroup per (chirp, kNuGatherRecs records in entry
+// order), looping over the channels: each channel's grid row of the chirp is staged in LDS
+// and every lane forms the moments mu_0 .. mu_R of its own 13 cells about its own position
+// (|l - x| <= kNuWidth / 2, the spread's truncation), then adds this channel's share of the
+// seven per-facet sums in registers: Re y, Re dy/dx and Q mu_k (for dL/dbeta_v, applied once
+// per record with d b_k / d beta_v) and dL/dc through the channel's distances. One atomic add
+// per value and record into partial[chirp][lit facet][kAdjVals] (sub-triangles of a facet
+// add into the same slot). Blocks are ordered so that those of one chirp share an XCD (and
+// its L2, which holds the chirp's grids).
 template <int R>
-__global__ void __launch_bounds__(kNuSpreadThreads) nufft_gather_kernel(
-    DevScene sc, RadarConst rc, NuShape ns, const double *elem, const NuRec<R> *__restrict__ sorted,
-    const NuDer<R> *__restrict__ ders, const float2 *__restrict__ grids, float *partial) {
-  const int wave = __builtin_amdgcn_readfirstlane(
-      static_cast<int>(blockIdx.x) * (kNuSpreadThreads / 64) + static_cast<int>(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const int runs = ns.runs;
-  const int per_chirp = ns.spread_groups * runs;
-  const int nl = wave / per_chirp;
-  if (nl >= ns.n_chirps) return;
-  const int rem = wave - nl * per_chirp;
-  const int grp = rem / runs;
-  const int run = rem - grp * runs;
+__global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
+    DevScene sc, RadarConst rc, NuShape ns, const double *elem, const NuRec<R> *__restrict__ recs,
+    const NuDer<R> *__restrict__ ders, const float2 *__restrict__ grids, float *partial,
+    int blocks_per_chirp) {
+  extern __shared__ float2 nu_row[];  // [n_g]
+  const int per_xcd = (gridDim.x + kXcds - 1) / kXcds;  // gridDim.x is a multiple of kXcds
+  const int logical = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
+  const int nl = logical / blocks_per_chirp;
+  if (nl >= ns.n_chirps) return;  // padding blocks (whole workgroup, before any barrier)
+  const int rb = logical - nl * blocks_per_chirp;
   const int n = ns.n0 + nl;
   const int32_t n_ent = sc.vis_cnt[n] << (2 * ns.split);
-  const int e_begin = run * kNuSeg;
-  if (e_begin >= n_ent) return;
-  const int e_end = min(n_ent, e_begin + kNuSeg);
+  if (rb * kNuGatherRecs >= n_ent) return;  // whole workgroup
+  const int32_t e = rb * kNuGatherRecs + static_cast<int32_t>(threadIdx.x);
+  const bool live = e < n_ent;
   const int ng = ns.ng;
   const int O = rc.P * rc.Q;
-  const int o = grp * 64 + lane;
-  const bool on = o < O;
-  double at[3], ar[3];
-  float aat, aar, atf[3], arf[3];
-  {
-    const int oc = on ? o : 0;
-    const int p = oc / rc.Q, q = oc - p * rc.Q;
-    double st = 0.0, sr = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      at[k] = elem[3 * p + k] - rc.tx_c[k];
-      ar[k] = elem[3 * (rc.P + q) + k] - rc.rx_c[k];
-      st += at[k] * at[k];
-      sr += ar[k] * ar[k];
-    }
-    aat = static_cast<float>(st);
-    aar = static_cast<float>(sr);
-    for (int k = 0; k < 3; ++k) {
-      atf[k] = static_cast<float>(at[k]);
-      arf[k] = static_cast<float>(ar[k]);
-    }
-  }
-  const NuRec<R> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
-  const NuDer<R> *sder = ders + static_cast<int64_t>(nl) * ns.rec_stride;
-  const float2 *grow = grids + (static_cast<int64_t>(nl) * O + (on ? o : 0)) * ng;
-  float *prow = partial + static_cast<int64_t>(n) * sc.n_facets * kAdjVals;
+  const int64_t rec_at = static_cast<int64_t>(nl) * ns.rec_stride + (live ? e : 0);
+  const NuRec<R> r = recs[rec_at];
+  const bool on = live && r.valid;
+  float2 b[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) b[k] = on ? r.b[k] : make_float2(0.0f, 0.0f);
+  const float utf[3] = {static_cast<float>(r.ut[0]), static_cast<float>(r.ut[1]),
+                        static_cast<float>(r.ut[2])};
+  const float urf[3] = {static_cast<float>(r.ur[0]), static_cast<float>(r.ur[1]),
+                        static_cast<float>(r.ur[2])};
+  // positions relative to the record's cell (small numbers: FP32 keeps ~1e-6 cells)
   const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
   const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
   const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
   const float kappa = static_cast<float>(ns.kappa);
   const float g2 = static_cast<float>(0.5 * rc.slope / (kC0 * kC0));
   const float two_pi = static_cast<float>(2.0 * kPi);
-  const float d = static_cast<float>(ns.chan_d);
-  const int b0 = static_cast<int>(ceilf(d + 0.5f * kNuWidth));
-  const float rel_hi = static_cast<float>(kNuSlots - 1) - d - 0.5f * kNuWidth;
-  float2 win[kNuSlots];
-  int i = e_begin;
-  NuRec<R> nxt = load_uniform(srec + i);
-  while (i < e_end) {
-    const int base = nxt.cell - b0;  // wave-uniform
+  const float g1f = static_cast<float>(r.g1);
+  const float half_w = 0.5f * kNuWidth;
+  float acc_c[3] = {0.0f, 0.0f, 0.0f}, acc_s = 0.0f, acc_yx = 0.0f;
+  float acc_mr[R], acc_mi[R];
 #pragma unroll
-    for (int s = 0; s < kNuSlots; ++s) {
-      // base + s lies in [-ng, 2 ng) (n_g >= 32 > the window)
-      int cell = base + s;
-      cell += (cell < 0) ? ng : 0;
-      cell -= (cell >= ng) ? ng : 0;
-      win[s] = on ? grow[cell] : make_float2(0.0f, 0.0f);
+  for (int k = 0; k < R; ++k) acc_mr[k] = acc_mi[k] = 0.0f;
+  const float2 *grow = grids + static_cast<int64_t>(nl) * O * ng;
+  for (int o = 0; o < O; ++o) {
+    __syncthreads();  // the previous channel's row is no longer read
+    for (int l = threadIdx.x; l < ng; l += blockDim.x) nu_row[l] = grow[static_cast<int64_t>(o) * ng + l];
+    __syncthreads();
+    // this channel's element offsets from the phase centres (wave-uniform)
+    const int p = o / rc.Q, q = o - p * rc.Q;
+    double at[3], ar[3];
+    double st2 = 0.0, sr2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      at[k] = elem[3 * p + k] - rc.tx_c[k];
+      ar[k] = elem[3 * (rc.P + q) + k] - rc.rx_c[k];
+      st2 += at[k] * at[k];
+      sr2 += ar[k] * ar[k];
     }
-    const int first = i;
-    for (; i < e_end; ++i) {
-      const NuRec<R> r = nxt;
-      int rk = r.cell - base;
-      if (rk > ng / 2) rk -= ng;
-      if (rk < -ng / 2) rk += ng;
-      const float rel_c = static_cast<float>(rk) + r.frac;
-      if (i > first && (rel_c < d + 0.5f * kNuWidth || rel_c > rel_hi)) break;
-      if (i + 1 < e_end) nxt = load_uniform(srec + i + 1);
-      const int s_lo =
-          __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - d - 0.5f * kNuWidth)));
-      const int s_hi =
-          __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c + d + 0.5f * kNuWidth)));
-      // this channel's path (as in the spread)
-      const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
-      const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
-      const double ps = (st + sr) * r.g1;
-      const float pr = static_cast<float>(ps - rint(ps));
-      const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
-      const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
-      const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
-      const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
-      const float qt = ht * rdt, qr = hr * rdr;
-      const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
-      const float dRt = et - sft, dRr = er - sfr;
-      const float dL = dRt + dRr;
-      float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
-      const float xr = fmaf(kappa, dL, rel_c);
-      t -= rintf(t);
-      const float Rtp = r.rt + dRt, Rrq = r.rr + dRr;
-      const float amp = __builtin_amdgcn_rcpf(Rtp * Rrq);
-      const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
-      // moments of the grid row about x
-      float2 mu[R + 1];
+    const float aat = static_cast<float>(st2), aar = static_cast<float>(sr2);
+    // the channel's path (as in the spread)
+    const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
+    const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
+    const double ps = (st + sr) * r.g1;
+    const float pr = static_cast<float>(ps - rint(ps));
+    const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
+    const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
+    const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
+    const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
+    const float qt = ht * rdt, qr = hr * rdr;
+    const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
+    const float dRt = et - sft, dRr = er - sfr;
+    const float dL = dRt + dRr;
+    float t = (r.t0 - pr) + fmaf(g1f, et + er, -g2 * dL * dL);
+    t -= rintf(t);
+    const float x = fmaf(kappa, dL, r.frac);  // grid position minus the record's cell
+    const float Rtp = r.rt + dRt, Rrq = r.rr + dRr;
+    const float irt = __builtin_amdgcn_rcpf(Rtp), irr = __builtin_amdgcn_rcpf(Rrq);
+    const float amp = irt * irr;
+    const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
+    // moments of the grid row about x over the cells |l - x| <= W / 2 (13 cells from
+    // ceil(x - W / 2); a 13th cell past x + W / 2 carries a weight below 4e-7)
+    const float s0 = ceilf(x - half_w);
+    int cell = (r.cell + static_cast<int>(s0)) % ng;  // r.cell + s0 lies in (-ng, 2 ng)
+    cell += (cell < 0) ? ng : 0;
+    const float u0 = s0 - x;
+    float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+    float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+    float2 mu[R + 1];
 #pragma unroll
-      for (int k = 0; k <= R; ++k) mu[k] = {0.0f, 0.0f};
-      const float u0 = static_cast<float>(s_lo) - xr;
-      float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
-      float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+    for (int k = 0; k <= R; ++k) mu[k] = {0.0f, 0.0f};
 #pragma unroll
-      for (int s = 0; s < kNuSlots; ++s) {
-        if (s >= s_lo && s <= s_hi) {
-          const float u = static_cast<float>(s) - xr;
-          const float wr = gw * win[s].x, wi = gw * win[s].y;
-          mu[0].x += wr;
-          mu[0].y += wi;
-          float up = 1.0f;
+    for (int j = 0; j <= kNuWidth; ++j) {
+      const float2 gv = nu_row[cell];
+      cell = (cell + 1 == ng) ? 0 : cell + 1;
+      const float u = u0 + static_cast<float>(j);
+      const float wr = gw * gv.x, wi = gw * gv.y;
+      mu[0].x += wr;
+      mu[0].y += wi;
+      float up = 1.0f;
 #pragma unroll
-          for (int k = 1; k <= R; ++k) {
-            up *= u;
-            mu[k].x = fmaf(wr, up, mu[k].x);
-            mu[k].y = fmaf(wi, up, mu[k].y);
-          }
-          gw *= rho;
-          rho *= q_ratio;
-        }
+      for (int k = 1; k <= R; ++k) {
+        up *= u;
+        mu[k].x = fmaf(wr, up, mu[k].x);
+        mu[k].y = fmaf(wi, up, mu[k].y);
       }
-      // Q mu_k; y and dy/dx
-      float2 qm[R + 1];
+      gw *= rho;
+      rho *= q_ratio;
+    }
+    // Q mu_k; y and dy/dx
+    float2 qm[R + 1];
 #pragma unroll
-      for (int k = 0; k <= R; ++k) qm[k] = {qx * mu[k].x - qy * mu[k].y, qx * mu[k].y + qy * mu[k].x};
-      float yr = 0.0f, yi = 0.0f, yxr = 0.0f;
+    for (int k = 0; k <= R; ++k) qm[k] = {qx * mu[k].x - qy * mu[k].y, qx * mu[k].y + qy * mu[k].x};
+    float yr = 0.0f, yi = 0.0f, yxr = 0.0f;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const float2 b = r.b[k];
-        yr += b.x * qm[k].x - b.y * qm[k].y;
-        yi += b.x * qm[k].y + b.y * qm[k].x;
-        float nr = qm[k + 1].x * inv_s2, ni = qm[k + 1].y * inv_s2;
-        if (k > 0) {
-          nr = fmaf(-static_cast<float>(k), qm[k - 1].x, nr);
-          ni = fmaf(-static_cast<float>(k), qm[k - 1].y, ni);
-        }
-        yxr += b.x * nr - b.y * ni;
+    for (int k = 0; k < R; ++k) {
+      yr += b[k].x * qm[k].x - b[k].y * qm[k].y;
+      yi += b[k].x * qm[k].y + b[k].y * qm[k].x;
+      float nr = qm[k + 1].x * inv_s2, ni = qm[k + 1].y * inv_s2;
+      if (k > 0) {
+        nr = fmaf(-static_cast<float>(k), qm[k - 1].x, nr);
+        ni = fmaf(-static_cast<float>(k), qm[k - 1].y, ni);
       }
-      // dL/dbeta_v through b_k and the source position
-      const NuDer<R> dv = sder[i];
-      float tv[3];
+      yxr += b[k].x * nr - b[k].y * ni;
+      acc_mr[k] += qm[k].x;
+      acc_mi[k] += qm[k].y;
+    }
+    acc_s += yr;
+    acc_yx += yxr;
+    // dL/dc through the element distances: d Re y / dR = K Im y + kappa Re(dy/dx) - Re y / R
+    // (K = 2 pi (f_c - mu tau) / c of this channel), with dR_tp / dc = -e_p
+    const float K = two_pi * fmaf(-2.0f * g2, dL, g1f);
+    const float A = fmaf(K, yi, kappa * yxr);
+    const float ct = A - yr * irt, cr = A - yr * irr;
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        float a = dv.dx[v] * yxr;
-#pragma unroll
-        for (int k = 0; k < R; ++k) a += dv.db[v][k].x * qm[k].x - dv.db[v][k].y * qm[k].y;
-        tv[v] = a;
-      }
-      // dL/dc through the element distances: d Re y / dR = K Im y + kappa Re(dy/dx) - Re y / R
-      // (K = 2 pi (f_c - mu tau) / c of this channel), with dR_tp / dc = -e_p
-      const float K = two_pi * fmaf(-2.0f * g2, dL, static_cast<float>(r.g1));
-      const float A = fmaf(K, yi, kappa * yxr);
-      const float ct = A - yr * __builtin_amdgcn_rcpf(Rtp);
-      const float cr = A - yr * __builtin_amdgcn_rcpf(Rrq);
-      const float irt = __builtin_amdgcn_rcpf(Rtp), irr = __builtin_amdgcn_rcpf(Rrq);
-      float vals[kAdjVals - 1];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float ep = (atf[k] - r.rt * static_cast<float>(r.ut[k])) * irt;
-        const float eq = (arf[k] - r.rr * static_cast<float>(r.ur[k])) * irr;
-        vals[k] = -(ct * ep + cr * eq);
-      }
-      vals[3] = yr;
-      vals[4] = tv[0];
-      vals[5] = tv[1];
-      vals[6] = tv[2];
-#pragma unroll
-      for (int k = 0; k < kAdjVals - 1; ++k) {
-        const float v = wave_sum(on ? vals[k] : 0.0f);
-        if (r.valid && lane == 0) atomicAdd(&prow[static_cast<int64_t>(dv.item) * kAdjVals + k], v);
-      }
+    for (int k = 0; k < 3; ++k) {
+      const float ep = (static_cast<float>(at[k]) - r.rt * utf[k]) * irt;
+      const float eq = (static_cast<float>(ar[k]) - r.rr * urf[k]) * irr;
+      acc_c[k] -= ct * ep + cr * eq;
     }
   }
+  if (!on) return;
+  // dL/dbeta_v = Re sum_k (d b_k / d beta_v) sum_o Q mu_k + (dx / dbeta_v) sum_o Re(dy/dx)
+  const NuDer<R> dv = ders[rec_at];
+  float tv[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    float a = dv.dx[v] * acc_yx;
+#pragma unroll
+    for (int k = 0; k < R; ++k) a += dv.db[v][k].x * acc_mr[k] - dv.db[v][k].y * acc_mi[k];
+    tv[v] = a;
+  }
+  float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + dv.item) * kAdjVals;
+  const float vals[kAdjVals - 1] = {acc_c[0], acc_c[1], acc_c[2], acc_s, tv[0], tv[1], tv[2]};
+#pragma unroll
+  for (int k = 0; k < kAdjVals - 1; ++k) atomicAdd(&slot[k], vals[k]);
 }
 
 size_t nufft_smem_bytes(const NuShape &ns) {
@@ -1018,18 +998,14 @@ hipError_t launch_nufft_adjoint_t(const DevScene &sc, const RadarConst &rc, cons
   const int64_t items = sc.n_facets << (2 * ns.split);
   if (items == 0) return hipSuccess;
   dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
-  hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(nufft_count_kernel, dim3(ns.n_chirps), dim3(1024), 0, s, sc, ns, nb);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_adj_prep_kernel<R>), grid, dim3(256), 0, s, sc, rc, ns, nb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t waves = static_cast<int64_t>(ns.n_chirps) * ns.spread_groups * ns.runs;
-  const int64_t blocks = (waves + kNuSpreadThreads / 64 - 1) / (kNuSpreadThreads / 64);
+  const int bpc = static_cast<int>((items + kNuGatherRecs - 1) / kNuGatherRecs);
+  const int64_t blocks = (static_cast<int64_t>(ns.n_chirps) * bpc + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL((nufft_gather_kernel<R>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
+                     dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem,
                      static_cast<const NuRec<R> *>(nb.srec), static_cast<const NuDer<R> *>(nb.sder),
-                     static_cast<const float2 *>(nb.grid), partial);
+                     static_cast<const float2 *>(nb.grid), partial, bpc);
   return hipGetLastError();
 }
 

@@ -104,7 +104,8 @@ hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const
                                  const float *partial, float *gxw, hipStream_t s);
 // Adjoint of launch_nufft for one chunk of chirps (stop-and-hop, facets only: sc.n_points
 // must be 0): adds the per-(chirp, lit facet) adjoint sums into partial
-// [N][n_facets][kAdjVals] (zero before the first chunk); nb.sder is required.
+// [N][n_facets][kAdjVals] (zero before the first chunk). Uses nb.srec and nb.sder (records
+// in entry order) and nb.grid; nb.key and nb.pos are not used.
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
                                 const void *grad_echo, float *partial, hipStream_t s);
