@@ -1338,7 +1338,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
     const size_t off_pos = al(chunk * stride * 4);
     const size_t off_srec = off_pos + al(chunk * stride * 4);
-    const size_t off_grid = off_srec + al(chunk * stride * rec_b);
+    const size_t off_range = off_srec + al(chunk * stride * rec_b);
+    const size_t off_grid = off_range + al(chunk * sizeof(int2));
     const size_t total = off_grid + chunk * O * ng * 8;
     const std::array<int64_t, 5> layout{stride, chunk, O, ng, static_cast<int64_t>(rec_b)};
     bool clear = layout != ctx->nu_layout;
@@ -1354,7 +1355,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     }
     char *b = static_cast<char *>(ctx->nu_buf);
     pl.nb = NuBuffers{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
-                      b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b};
+                      b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b, nullptr,
+                      reinterpret_cast<int2 *>(b + off_range)};
     pl.ns.n_chirps = static_cast<int32_t>(chunk);
     if (clear) {
       // the kernels leave the grids zero; a new layout starts from zero (on the

@@ -6,7 +6,7 @@
 // zero Doppler in row N/2; the RDM is |Y|^2. Unnormalised, no window.
 //
 // Both are HBM-bound: each workgroup loads a block of rows (range) or a tile of
-// columns (Doppler, coalesced along the range axis) into LDS, runs a mixed radix-2/3
+// columns (Doppler, coalesced along the range axis) into LDS, runs a mixed radix-4/2/3
 // Stockham FFT there and writes the result once. Twiddles come from an FP64-
 // accurate table, tw[i] = exp(-j 2 pi i / L), i < L.
 #include "fft_common.h"

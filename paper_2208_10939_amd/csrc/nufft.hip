@@ -393,9 +393,36 @@ __global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape 
   const int32_t *key = nb.key + row;
   int32_t *pos = nb.pos + row;
   const int32_t n_ent = (sc.vis_cnt[n] << (2 * ns.split)) + sc.n_points;
+  __shared__ int32_t s_lo, s_hi;
   for (int c = threadIdx.x; c < 2048; c += blockDim.x) s_cnt[c] = 0;
+  if (threadIdx.x == 0) {
+    s_lo = ns.ng;
+    s_hi = -1;
+  }
   __syncthreads();
   for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] = atomicAdd(&s_cnt[key[e]], 1);
+  __syncthreads();
+  // occupied cells, widened by every cell a window flush can reach (channel offsets, the
+  // Gaussian's half width and the fraction): the grid is zero outside; a wrapping interval
+  // becomes the whole row
+  {
+    const int c0 = 2 * threadIdx.x;
+    if (c0 < ns.ng && s_cnt[c0]) { atomicMin(&s_lo, c0); atomicMax(&s_hi, c0); }
+    if (c0 + 1 < ns.ng && s_cnt[c0 + 1]) { atomicMin(&s_lo, c0 + 1); atomicMax(&s_hi, c0 + 1); }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int m = static_cast<int>(ceil(ns.chan_d)) + kNuWidth / 2 + 2;
+    int lo = s_lo - m, hi = s_hi + m;
+    if (s_hi < 0) {
+      lo = 0;
+      hi = -1;
+    } else if (lo < 0 || hi >= ns.ng) {
+      lo = 0;
+      hi = ns.ng - 1;
+    }
+    nb.range[nl] = make_int2(lo, hi);
+  }
   __syncthreads();
   // exclusive scan, two cells per thread (n_g <= 2048)
   const int c0 = 2 * threadIdx.x;
@@ -606,7 +633,7 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
 // and the k_c^2 / k_m^2 factor on the M kept modes.
 __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, RadarConst rc,
                                                                 NuShape ns, NuBuffers nb,
-                                                                const float2 *tw) {
+                                                                const float2 *tw, bool ranged) {
   extern __shared__ float2 nu_smem[];
   const int nl = blockIdx.x / ns.groups;
   const int grp = blockIdx.x - nl * ns.groups;
@@ -615,16 +642,19 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
   const int O = rc.P * rc.Q;
   float2 *lgrid = nu_smem;            // [cb][ld]
   float2 *work = nu_smem + cb * ld;   // [cb][ld]
-  for (int i = threadIdx.x; i < cb * ng; i += blockDim.x) {
-    const int c = i / ng, l = i - c * ng;
+  // only the chirp's occupied cells are read (and zeroed behind); none without records
+  const int2 rg = ranged ? nb.range[nl] : make_int2(0, -1);
+  for (int c = 0; c < cb; ++c) {
     const int o = grp * cb + c;
-    float2 v = {0.0f, 0.0f};
-    if (o < O) {
-      float2 *src = nb.grid + (static_cast<int64_t>(nl) * O + o) * ng + l;
-      v = *src;
-      *src = {0.0f, 0.0f};
+    float2 *src = nb.grid + (static_cast<int64_t>(nl) * O + o) * ng;
+    for (int l = threadIdx.x; l < ng; l += blockDim.x) {
+      float2 v = {0.0f, 0.0f};
+      if (o < O && l >= rg.x && l <= rg.y) {
+        v = src[l];
+        src[l] = {0.0f, 0.0f};
+      }
+      lgrid[c * ld + l] = v;
     }
-    lgrid[c * ld + l] = v;
   }
   __syncthreads();
   const int M = rc.M;
@@ -970,7 +1000,7 @@ hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
                      dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
-                     static_cast<const float2 *>(tw));
+                     static_cast<const float2 *>(tw), items > 0);
   return hipGetLastError();
 }
 

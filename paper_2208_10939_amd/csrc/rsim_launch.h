@@ -86,6 +86,7 @@ struct NuBuffers {
   float2 *grid;
   size_t rec_bytes;  // record slot size of srec (a launch refuses wider records)
   void *sder;        // adjoint records in the same order (adjoint only)
+  int2 *range;       // per chirp: the grid cells [x, y] that can be nonzero (forward only)
 };
 size_t nufft_record_bytes(int order, bool intra);
 size_t nufft_der_bytes(int order);
