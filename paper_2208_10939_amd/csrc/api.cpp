@@ -319,7 +319,7 @@ int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
       }
       d.verts = static_cast<const float *>(m.d_verts);
       d.tris = static_cast<const int32_t *>(m.d_tris);
-      d.nodes = static_cast<const BvhNode *>(m.d_nodes);
+      d.nodes = static_cast<const BvhNode4 *>(m.d_nodes);
       d.leaf = static_cast<const float4 *>(m.d_leaf);
       d.facet_base = base;
       d.n_tris = static_cast<int32_t>(m.tris.size() / 3);
@@ -704,11 +704,12 @@ int32_t index_mesh(rsim_ctx *ctx, MeshRec &m, bool first_time) {
       m.r_max = std::max(m.r_max, std::sqrt(d));
     }
   }
-  std::vector<BvhNode> nodes;
+  std::vector<BvhNode4> nodes;
   std::vector<float> leaf;
   m.depth = build_bvh(m.verts.data(), m.tris.data(), n_tris, nodes, leaf);
-  if (m.depth >= kBvhStack)
-    return fail(ctx, RSIM_ERANGE, "BVH depth %d exceeds %d", m.depth, kBvhStack);
+  if (3 * (m.depth + 1) > kBvhStack)
+    return fail(ctx, RSIM_ERANGE, "BVH depth %d needs more than %d stack entries", m.depth,
+                kBvhStack);
   m.n_nodes = static_cast<int64_t>(nodes.size());
   m.n_leaf = static_cast<int64_t>(leaf.size() / 12);
   if (ctx->host_only) return RSIM_OK;
@@ -719,7 +720,7 @@ int32_t index_mesh(rsim_ctx *ctx, MeshRec &m, bool first_time) {
   dev_free(ctx, m.d_leaf);
   m.d_verts = m.d_nodes = m.d_leaf = nullptr;
   float *dv = nullptr;
-  BvhNode *dn = nullptr;
+  BvhNode4 *dn = nullptr;
   float *dl = nullptr;
   if ((rc = upload(ctx, &dv, m.verts.data(), m.verts.size()))) return rc;
   if ((rc = upload(ctx, &dn, nodes.data(), nodes.size()))) return rc;
@@ -761,10 +762,10 @@ std::vector<DevScene> scene_views(rsim_ctx *ctx, const std::vector<int32_t> &ids
     uint32_t *mask = vis_mask ? vis_mask + mask_off : sc.d_mask;
     mask_off += static_cast<int64_t>(ctx->ground ? 4 : 1) * rc.N * ((sc.n_facets + 31) / 32);
     ds[i] = dev_scene(sc, mask, static_cast<char *>(echo) + i * cube * csize);
-    // a traversal keeps at most one pending node per level of its BVH
+    // a traversal keeps at most three pending nodes per level of its four-wide BVH
     int depth = 0;
     for (const InstRec &r : sc.inst) depth = std::max(depth, ctx->meshes[r.mesh].depth);
-    ds[i].stack_depth = depth + 1;
+    ds[i].stack_depth = 3 * (depth + 1);
   }
   return ds;
 }

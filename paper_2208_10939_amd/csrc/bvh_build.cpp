@@ -163,11 +163,54 @@ static void inflate(float *lo, float *hi) {
   }
 }
 
-// Builds nodes (root = node 0) and leaf triangles (3 float4 each). Degenerate
-// (zero-area) triangles are left out: they never block. Returns the tree depth, or
-// -1 if no triangle has area.
+// Four-wide node `n4` from binary node n: its children are the two children of each inner
+// binary child (with the boxes that child holds) or the binary child itself when it is a
+// leaf; inner ones are collapsed in turn. Returns the four-wide index; *depth the deepest
+// four-wide level below (root level 0).
+static int32_t collapse(const std::vector<BvhNode> &bin, int32_t n, int level,
+                        std::vector<BvhNode4> &out, int *depth) {
+  *depth = std::max(*depth, level);
+  const int32_t me = static_cast<int32_t>(out.size());
+  out.emplace_back();
+  BvhNode4 nd;
+  std::memset(&nd, 0, sizeof(nd));
+  int ne = 0;
+  auto put = [&](int32_t ref, const float *lo, const float *hi) {
+    for (int k = 0; k < 3; ++k) {
+      nd.lo[k][ne] = lo[k];
+      nd.hi[k][ne] = hi[k];
+    }
+    nd.c[ne++] = ref;
+  };
+  const BvhNode &b = bin[n];
+  for (int side = 0; side < 2; ++side) {
+    const int32_t ref = side ? b.c1 : b.c0;
+    if (ref >= 0) {
+      const BvhNode &g = bin[ref];
+      put(g.c0, g.lo0, g.hi0);
+      put(g.c1, g.lo1, g.hi1);
+    } else {
+      put(ref, side ? b.lo1 : b.lo0, side ? b.hi1 : b.hi0);
+    }
+  }
+  for (; ne < 4; ++ne) {  // empty slots: never entered
+    for (int k = 0; k < 3; ++k) {
+      nd.lo[k][ne] = 1.0f;
+      nd.hi[k][ne] = -1.0f;
+    }
+    nd.c[ne] = Builder::leaf_ref(0, 0);
+  }
+  for (int i = 0; i < 4; ++i)
+    if (nd.c[i] >= 0) nd.c[i] = collapse(bin, nd.c[i], level + 1, out, depth);
+  out[me] = nd;
+  return me;
+}
+
+// Builds the four-wide nodes (root = node 0) and leaf triangles (3 float4 each).
+// Degenerate (zero-area) triangles are left out: they never block. Returns the depth of the
+// four-wide tree (root 0), or -1 if no triangle has area.
 int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
-              std::vector<BvhNode> &nodes_out, std::vector<float> &leaf_out) {
+              std::vector<BvhNode4> &nodes_out, std::vector<float> &leaf_out) {
   Builder bd;
   bd.prims.reserve(n_tris);
   for (int64_t t = 0; t < n_tris; ++t) {
@@ -221,7 +264,9 @@ int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
     inflate(nd.lo0, nd.hi0);
     inflate(nd.lo1, nd.hi1);
   }
-  nodes_out = std::move(bd.nodes);
+  nodes_out.reserve(bd.nodes.size() / 2 + 1);
+  int depth4 = 0;
+  collapse(bd.nodes, 0, 0, nodes_out, &depth4);
   leaf_out.resize(bd.order.size() * 12);
   for (size_t i = 0; i < bd.order.size(); ++i) {
     int32_t t = bd.order[i];
@@ -236,7 +281,7 @@ int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
     o[10] = 0.0f;
     o[11] = 0.0f;
   }
-  return bd.max_depth;
+  return depth4;
 }
 
 }  // namespace rsim

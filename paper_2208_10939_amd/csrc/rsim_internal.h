@@ -15,8 +15,8 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr float kTEps = 1e-6f;
 
 constexpr int kMaxElements = 128;  // Tx + Rx elements
-constexpr int kBvhStack = 64;      // traversal stack depth; the builder caps depth below
-constexpr int kBvhMaxDepth = 60;
+constexpr int kBvhStack = 96;      // traversal stack entries at most (3 per 4-wide level)
+constexpr int kBvhMaxDepth = 60;   // binary levels at most (the builder caps them at 58)
 constexpr int kLeafMax = 4;        // triangles per leaf (encoding allows 15)
 
 // Two-wide BVH node: both child boxes live in the parent so one 64-byte fetch tests
@@ -29,6 +29,17 @@ struct alignas(16) BvhNode {
 };
 static_assert(sizeof(BvhNode) == 64, "node size");
 
+// Four-wide node, the traversal's format (the binary tree collapsed: a node's children are
+// its binary grandchildren, or a binary child that is a leaf): one 128-byte fetch tests four
+// boxes, and a root-to-leaf chain of dependent fetches is half as long. Boxes as structure
+// of arrays; unused slots hold an empty box (lo > hi) and an empty leaf.
+struct alignas(16) BvhNode4 {
+  float lo[3][4], hi[3][4];  // [axis][child]
+  int32_t c[4];              // as BvhNode: >= 0 inner node, < 0 leaf
+  int32_t pad[4];
+};
+static_assert(sizeof(BvhNode4) == 128, "node size");
+
 // Leaf triangle in BVH order as three float4: (v0.xyz, e1.x) (e1.yz, e2.xy)
 // (e2.z, id bits, 0, 0) with e1 = v1 - v0, e2 = v2 - v0 and id the mesh-local index.
 
@@ -40,7 +51,7 @@ struct DevInstance {
   double box_lo[3], box_hi[3];  // world box of rot * body box (add pos0 + vel t)
   const float *verts;           // [V][3] body frame
   const int32_t *tris;          // [F][3]
-  const BvhNode *nodes;         // BVH, root = node 0
+  const BvhNode4 *nodes;        // four-wide BVH, root = node 0
   const float4 *leaf;           // [n_leaf_tris * 3]
   int64_t facet_base;           // scene-global index of this instance's triangle 0
   int32_t n_tris;

@@ -26,7 +26,7 @@ constexpr int kStagingThreads = 128;  // staging waves of the forward facet sum
 constexpr int kMaxComputeThreads = 384;  // + staging = 512 threads, 8 waves
 
 int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
-              std::vector<BvhNode> &nodes_out, std::vector<float> &leaf_out);
+              std::vector<BvhNode4> &nodes_out, std::vector<float> &leaf_out);
 
 hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream_t s);
 hipError_t launch_compact(const DevScene &sc, int n_chirps, hipStream_t s);

@@ -80,33 +80,31 @@ __device__ inline float safe_inv(float d) {
   return 1.0f / (fabsf(d) > tiny ? d : copysignf(tiny, d));
 }
 
-// Any-hit traversal of one BLAS for the body-frame segment o -> o + d.
-__device__ bool blas_occluded(const BvhNode *nodes, const float4 *leaf, float ox, float oy,
+// Any-hit traversal of one four-wide BLAS for the body-frame segment o -> o + d: leaves
+// are tested when their box is hit, the first hit inner child is entered next and the other
+// hit inner children (at most three per level) wait on the stack.
+__device__ bool blas_occluded(const BvhNode4 *nodes, const float4 *leaf, float ox, float oy,
                               float oz, float dx, float dy, float dz, int32_t skip,
                               int32_t *stack, int stride) {
   const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
   int sp = 0;
   int32_t node = 0;
   while (true) {
-    const BvhNode nd = nodes[node];
-    const bool h0 = box_hit(nd.lo0, nd.hi0, ox, oy, oz, ix, iy, iz);
-    const bool h1 = box_hit(nd.lo1, nd.hi1, ox, oy, oz, ix, iy, iz);
+    const BvhNode4 nd = nodes[node];
     int32_t next = -1;
-    if (h0) {
-      if (nd.c0 < 0) {
-        if (leaf_hit(leaf, nd.c0, ox, oy, oz, dx, dy, dz, skip)) return true;
-      } else {
-        next = nd.c0;
-      }
-    }
-    if (h1) {
-      if (nd.c1 < 0) {
-        if (leaf_hit(leaf, nd.c1, ox, oy, oz, dx, dy, dz, skip)) return true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float lo[3] = {nd.lo[0][i], nd.lo[1][i], nd.lo[2][i]};
+      const float hi[3] = {nd.hi[0][i], nd.hi[1][i], nd.hi[2][i]};
+      if (!box_hit(lo, hi, ox, oy, oz, ix, iy, iz)) continue;
+      const int32_t c = nd.c[i];
+      if (c < 0) {
+        if (leaf_hit(leaf, c, ox, oy, oz, dx, dy, dz, skip)) return true;
       } else if (next >= 0) {
-        stack[sp * stride] = nd.c1;  // depth <= kBvhMaxDepth < kBvhStack
+        stack[sp * stride] = c;  // <= 3 per level: stack_depth = 3 (depth + 1)
         ++sp;
       } else {
-        next = nd.c1;
+        next = c;
       }
     }
     if (next < 0) {
@@ -196,7 +194,7 @@ __device__ inline bool leaf_hit2(const float4 *leaf, int32_t ref, float ox, floa
 // |d1 - d2| on every side: the points of the two segments at the same parameter are at
 // most that far apart, so this enters every node either segment meets (and a few more);
 // the leaf tests are exact for both segments.
-__device__ bool blas_occluded2(const BvhNode *nodes, const float4 *leaf, float ox, float oy,
+__device__ bool blas_occluded2(const BvhNode4 *nodes, const float4 *leaf, float ox, float oy,
                                float oz, const float d[2][3], int32_t skip, int32_t *stack,
                                int stride) {
   const float ix = safe_inv(d[0][0]), iy = safe_inv(d[0][1]), iz = safe_inv(d[0][2]);
@@ -206,25 +204,21 @@ __device__ bool blas_occluded2(const BvhNode *nodes, const float4 *leaf, float o
   int sp = 0;
   int32_t node = 0;
   while (true) {
-    const BvhNode nd = nodes[node];
-    const bool h0 = box_hit(nd.lo0, nd.hi0, ox, oy, oz, ix, iy, iz, pad);
-    const bool h1 = box_hit(nd.lo1, nd.hi1, ox, oy, oz, ix, iy, iz, pad);
+    const BvhNode4 nd = nodes[node];
     int32_t next = -1;
-    if (h0) {
-      if (nd.c0 < 0) {
-        if (leaf_hit2(leaf, nd.c0, ox, oy, oz, d, skip)) return true;
-      } else {
-        next = nd.c0;
-      }
-    }
-    if (h1) {
-      if (nd.c1 < 0) {
-        if (leaf_hit2(leaf, nd.c1, ox, oy, oz, d, skip)) return true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float lo[3] = {nd.lo[0][i], nd.lo[1][i], nd.lo[2][i]};
+      const float hi[3] = {nd.hi[0][i], nd.hi[1][i], nd.hi[2][i]};
+      if (!box_hit(lo, hi, ox, oy, oz, ix, iy, iz, pad)) continue;
+      const int32_t c = nd.c[i];
+      if (c < 0) {
+        if (leaf_hit2(leaf, c, ox, oy, oz, d, skip)) return true;
       } else if (next >= 0) {
-        stack[sp * stride] = nd.c1;  // depth <= kBvhMaxDepth < kBvhStack
+        stack[sp * stride] = c;  // <= 3 per level: stack_depth = 3 (depth + 1)
         ++sp;
       } else {
-        next = nd.c1;
+        next = c;
       }
     }
     if (next < 0) {
