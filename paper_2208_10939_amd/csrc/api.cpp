@@ -838,12 +838,12 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
   };
   if (o.mask_mode == RSIM_MASK_COMPUTE) {
     stage_begin(ctx, timing, 0, s);
-    for (auto &d : ds) HIP_TRY(ctx, launch_visibility(d, rc, s));
+    for (auto &d : ds) HIP_TRY(ctx, launch_visibility(d, rc, 0, rc.N, s));
     stage_end(ctx, timing, 0, s);
   }
   if (!ctx->ground) {
     stage_begin(ctx, timing, 1, s);
-    for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, rc.N, s));
+    for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, 0, rc.N, s));
     stage_end(ctx, timing, 1, s);
     stage_begin(ctx, timing, 2, s);
     if (pl.nufft) {
@@ -902,7 +902,7 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     for (size_t i = 0; i < ds.size(); ++i) {
       DevScene dk = ds[i];
       dk.mask = ds[i].mask + static_cast<int64_t>(k) * rc.N * ds[i].mask_words;
-      HIP_TRY(ctx, launch_compact(dk, rc.N, s));
+      HIP_TRY(ctx, launch_compact(dk, 0, rc.N, s));
       if (pl.nufft) {
         NuShape ns = pl.ns;
         ns.split = pl.nu_split[i];
@@ -1576,7 +1576,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   DevScene d = dev_scene(sc, const_cast<uint32_t *>(vis_mask), nullptr);
   const bool timing = ctx->timing_pending;
-  HIP_TRY(ctx, launch_compact(d, rcn.N, s));
+  HIP_TRY(ctx, launch_compact(d, 0, rcn.N, s));
   stage_begin(ctx, timing, 5, s);
   if (nufft) {
     if ((rc = enqueue_nufft_adjoint(ctx, d, rcn, nsb, grad_echo, s))) return rc;

@@ -28,8 +28,11 @@ constexpr int kMaxComputeThreads = 384;  // + staging = 512 threads, 8 waves
 int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
               std::vector<BvhNode4> &nodes_out, std::vector<float> &leaf_out);
 
-hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream_t s);
-hipError_t launch_compact(const DevScene &sc, int n_chirps, hipStream_t s);
+// Lit-facet masks of chirps [n_begin, n_begin + n_chirps), and their compaction into the
+// per-chirp lit lists.
+hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, int n_begin, int n_chirps,
+                             hipStream_t s);
+hipError_t launch_compact(const DevScene &sc, int n_begin, int n_chirps, hipStream_t s);
 
 hipError_t launch_echo_plain(int precision, int mb, int ft, const DevScene &sc,
                              const RadarConst &rc, const double *elem, const EchoShape &sh,

@@ -354,7 +354,8 @@ __device__ void facet_lit(const DevScene &sc, const RadarConst &rc, int64_t f, i
 // (mapping lanes to neighbouring facets instead makes every wave walk the union of 64
 // different paths). Decisions are gathered as bits in LDS and written as whole words.
 __global__ void __launch_bounds__(kVisThreads) vis_kernel(DevScene sc, RadarConst rc, int cw,
-                                                        int facets_per_block) {
+                                                        int facets_per_block, int n_begin,
+                                                        int n_end) {
   extern __shared__ int32_t vis_lds[];
   const int words = facets_per_block >> 5;
   const int types = rc.bounce ? 4 : 1;
@@ -363,11 +364,11 @@ __global__ void __launch_bounds__(kVisThreads) vis_kernel(DevScene sc, RadarCons
   for (int k = threadIdx.x; k < types * cw * words; k += blockDim.x) bits[k] = 0u;
   __syncthreads();
   const int nl = threadIdx.x % cw;
-  const int n = blockIdx.y * cw + nl;
+  const int n = n_begin + static_cast<int>(blockIdx.y) * cw + nl;
   const int64_t f0 = static_cast<int64_t>(blockIdx.x) * facets_per_block;
   for (int fl = threadIdx.x / cw; fl < facets_per_block; fl += blockDim.x / cw) {
     const int64_t f = f0 + fl;
-    if (f >= sc.n_facets || n >= rc.N) continue;
+    if (f >= sc.n_facets || n >= n_end) continue;
     bool lit[4];
     facet_lit(sc, rc, f, n, stk, blockDim.x, lit);
     for (int k = 0; k < types; ++k)
@@ -376,17 +377,17 @@ __global__ void __launch_bounds__(kVisThreads) vis_kernel(DevScene sc, RadarCons
   __syncthreads();
   for (int e = threadIdx.x; e < types * cw * words; e += blockDim.x) {
     const int w = e % words, r = e / words;  // r = k * cw + chirp within the group
-    const int k = r / cw, nn = blockIdx.y * cw + (r % cw);
+    const int k = r / cw, nn = n_begin + static_cast<int>(blockIdx.y) * cw + (r % cw);
     const int64_t word = static_cast<int64_t>(blockIdx.x) * words + w;
-    if (nn < rc.N && word < sc.mask_words)
+    if (nn < n_end && word < sc.mask_words)
       sc.mask[(static_cast<int64_t>(k) * rc.N + nn) * sc.mask_words + word] = bits[e];
   }
 }
 
 // Per-chirp compaction of the mask into ascending facet indices (deterministic).
-__global__ void __launch_bounds__(1024) compact_kernel(DevScene sc) {
+__global__ void __launch_bounds__(1024) compact_kernel(DevScene sc, int n_begin) {
   __shared__ int32_t s_scan[1024];
-  const int n = blockIdx.x;
+  const int n = n_begin + static_cast<int>(blockIdx.x);
   const uint32_t *row = sc.mask + static_cast<int64_t>(n) * sc.mask_words;
   const int64_t per = (sc.mask_words + blockDim.x - 1) / blockDim.x;
   const int64_t w0 = static_cast<int64_t>(threadIdx.x) * per;
@@ -420,22 +421,26 @@ __global__ void __launch_bounds__(1024) compact_kernel(DevScene sc) {
   if (threadIdx.x == blockDim.x - 1) sc.vis_cnt[n] = s_scan[threadIdx.x];
 }
 
-hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, hipStream_t s) {
-  if (sc.n_facets == 0) return hipSuccess;
-  int cw = 1;  // chirps per group: the smallest power of two >= N, at most 64
-  while (cw < rc.N && cw < 64) cw <<= 1;
+hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, int n_begin, int n_chirps,
+                             hipStream_t s) {
+  if (sc.n_facets == 0 || n_chirps <= 0) return hipSuccess;
+  if (n_begin < 0 || n_begin + n_chirps > rc.N) return hipErrorInvalidValue;
+  int cw = 1;  // chirps per group: the smallest power of two >= the count, at most 64
+  while (cw < n_chirps && cw < 64) cw <<= 1;
   // facets per workgroup: whole 32-bit mask words, every thread busy for cw >= 8
   const int fpb = std::max(32, kVisThreads / cw);
   dim3 grid(static_cast<unsigned>((sc.n_facets + fpb - 1) / fpb),
-            static_cast<unsigned>((rc.N + cw - 1) / cw));
+            static_cast<unsigned>((n_chirps + cw - 1) / cw));
   // bit words: types x max(cw, 8) <= 4 x 64
   const size_t lds = sizeof(int32_t) * (kVisBitWords + static_cast<size_t>(sc.stack_depth) * kVisThreads);
-  hipLaunchKernelGGL(vis_kernel, grid, dim3(kVisThreads), lds, s, sc, rc, cw, fpb);
+  hipLaunchKernelGGL(vis_kernel, grid, dim3(kVisThreads), lds, s, sc, rc, cw, fpb, n_begin,
+                     n_begin + n_chirps);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const DevScene &sc, int n_chirps, hipStream_t s) {
-  hipLaunchKernelGGL(compact_kernel, dim3(n_chirps), dim3(1024), 0, s, sc);
+hipError_t launch_compact(const DevScene &sc, int n_begin, int n_chirps, hipStream_t s) {
+  if (n_chirps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_kernel, dim3(n_chirps), dim3(1024), 0, s, sc, n_begin);
   return hipGetLastError();
 }
 
