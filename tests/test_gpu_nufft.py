@@ -193,8 +193,9 @@ def test_nufft_full_size_against_matrix(sim_mod):
 
 def test_nufft_batched_and_graph(sim_mod):
     """Several scenes in one call (persistent flag and graph capture included) against
-    one-scene calls. The grids are accumulated with LDS atomic adds, so results agree to
-    FP32 rounding rather than bit for bit."""
+    one-scene calls, stop-and-hop and with the delay within the chirp (its own record
+    type). The grids are accumulated with global atomic adds, so results agree to FP32
+    rounding rather than bit for bit."""
     _log("case nufft sum: batched (4 scenes, persistent + graph) vs one scene per call")
     wf = scenes.paper_waveform(200, 4)
     arr = scenes.sparse_mimo_12x16(wf, 4)
@@ -212,6 +213,12 @@ def test_nufft_batched_and_graph(sim_mod):
         buf.zero_()
         sim.synthesize(echo=buf, persistent=True, use_graph=True, kernel=NUFFT)
         assert rel_rms(buf.cpu().numpy(), plain) <= 1e-5, f"replay {rep}"
+    plain_i = sim.synthesize(kernel=NUFFT, intra_chirp=True).cpu().numpy()
+    assert rel_rms(plain_i, plain) > 1e-3  # the delay within the chirp changes the echo
+    for rep in range(3):
+        buf.zero_()
+        sim.synthesize(echo=buf, persistent=True, use_graph=True, kernel=NUFFT, intra_chirp=True)
+        assert rel_rms(buf.cpu().numpy(), plain_i) <= 1e-5, f"intra replay {rep}"
     Ho = oracle.synthesize(scs[1], wf, arr)
     err = rel_rms(plain[1], Ho)
     _log(f"  scene 1 vs oracle rel_rms={err:.3e}")
