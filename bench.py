@@ -1,13 +1,17 @@
 """Benchmark: whole echo-synthesis hot path on one MI355X.
 
-Workload (default): a single procedural vehicle hull of ~50k triangles at a seeded
-pose 10-60 m from the radar, 12 Tx x 16 Rx sparse MIMO (192 virtual channels),
-256 samples x 128 chirps, FP32 facet sum with FP64 phase. One step = visibility +
-compaction + facet sum + range FFT + Doppler FFT/RDM of one frame; inputs resident
-in device memory. Prints ONE JSON line.
+Workload (default, `--workload c3`): the intersection scene, a 60 x 60 m ground grid at
+0.25 m (115,200 triangles) plus 20 procedural vehicles of the four classes (car, bus,
+truck, motorcycle; ~44k triangles each), 1,000,000 triangles in all, seeded positions
+and speeds; 12 Tx x 16 Rx sparse MIMO (192 virtual channels), 512 samples x 256 chirps
+(the paper's third waveform), FP32 facet sum with FP64 phase. `--workload c2` runs the
+single 50k-triangle vehicle (256 x 128). One step = visibility + compaction + facet sum
++ range FFT + Doppler FFT/RDM of one frame; inputs resident in device memory. Prints
+ONE JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--calib-copy MiB]
-                  [--kernel auto|vector|matrix|nufft] [--tile-m T --tile-f F]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c3|c2] [--no-cpu]
+                  [--no-extras] [--calib-copy MiB] [--kernel auto|vector|matrix|nufft]
+                  [--tile-m T --tile-f F]
 """
 from __future__ import annotations
 
@@ -70,13 +74,32 @@ def nufft_flop(units, entries, rows, ng, M):
             rows * (5 * ng * math.log2(ng) + 2 * M))
 
 
-PROFILE_TRAFFIC = {"vector": os.path.join(ROOT, "profiles", "facet_sum_c2_traffic.json"),
-                   "matrix": os.path.join(ROOT, "profiles", "facet_sum_mfma_c2_traffic.json"),
-                   "nufft": os.path.join(ROOT, "profiles", "facet_sum_nufft_c2_traffic.json")}
+PROFILE_TRAFFIC = {"vector": "facet_sum_{w}_traffic.json",
+                   "matrix": "facet_sum_mfma_{w}_traffic.json",
+                   "nufft": "facet_sum_nufft_{w}_traffic.json"}
 KERNEL_SOURCES = {"vector": ("echo.hip", "echo_common.h"),
                   "matrix": ("echo_mfma.hip", "echo_common.h"),
                   "nufft": ("nufft.hip", "echo_common.h", "fft_common.h")}
 KERNEL_CODES = {"auto": 0, "vector": 1, "matrix": 2, "nufft": 3}
+
+
+def _c3():
+    import scenes
+    return scenes.c3()
+
+
+def _c2():
+    import scenes
+    return scenes.c2()
+
+
+WORKLOADS = {
+    "c3": ("intersection scene: 0.25 m ground grid (115,200 triangles) + 20 vehicles of 4 "
+           "classes, 1,000,000 triangles; 12x16 sparse MIMO (192 ch), 512 samples x 256 "
+           "chirps, FP32 sum + FP64 phase", _c3),
+    "c2": ("single vehicle hull, 50k triangles, 12x16 sparse MIMO (192 ch), 256 samples x "
+           "128 chirps, FP32 sum + FP64 phase", _c2),
+}
 
 
 def _log(msg):
@@ -91,11 +114,11 @@ def _src_hash(kernel="vector"):
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel):
-    """HBM bytes per facet-sum launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+def _traffic(kernel, workload):
+    """HBM bytes per facet-sum launch from the committed counter summary of this kernel
+    and workload, if it was taken on the current kernel source."""
     try:
-        with open(PROFILE_TRAFFIC[kernel]) as f:
+        with open(os.path.join(ROOT, "profiles", PROFILE_TRAFFIC[kernel].format(w=workload))) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -104,7 +127,7 @@ def _traffic(kernel):
     return d.get("bytes_per_launch")
 
 
-def roofline(kernel, evals, fs_ms, shape=None):
+def roofline(kernel, evals, fs_ms, shape=None, workload="c3"):
     """Roofline object of the facet-sum kernel: algorithmic FLOP per launch (direct sums:
     FLOP_PER_EVAL per evaluation; NUFFT: nufft_flop) over the launch's measured duration,
     against the published FP32 peak of the units the kernel runs on."""
@@ -112,7 +135,7 @@ def roofline(kernel, evals, fs_ms, shape=None):
     achieved = FLOP_PER_EVAL * rate
     if kernel == "nufft":
         O, N, M = shape
-        ng = 2 * M  # 2^a 3^b already for M = 256
+        ng = 2 * M  # 2^a 3^b already for M = 256 and 512
         units = evals // M
         flop = nufft_flop(units, units // O, O * N, ng, M)
         ach = flop / (fs_ms * 1e-3)
@@ -122,7 +145,7 @@ def roofline(kernel, evals, fs_ms, shape=None):
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": ach / PEAK_FP32_VECTOR,
-            "traffic": _traffic("nufft"),
+            "traffic": _traffic("nufft", workload),
             "kernel": "facet-sum stage of five launches, dominated by "
                       "rsim::nufft_spread_kernel<5> (type-1 NUFFT: Taylor-expanded Gaussian "
                       "spread in registers, then in-LDS FFT and deconvolution)",
@@ -139,7 +162,7 @@ def roofline(kernel, evals, fs_ms, shape=None):
             "peak": PEAK_FP32_MFMA / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_MFMA,
-            "traffic": _traffic("matrix"),
+            "traffic": _traffic("matrix", workload),
             "kernel": "rsim::echo_mfma_kernel<3, 4, 16> (FP64 prep + facet integral + "
                       "separable Tx x Rx contraction on v_mfma_f32_4x4x1f32)",
             "flop_per_eval": FLOP_PER_EVAL,
@@ -153,7 +176,7 @@ def roofline(kernel, evals, fs_ms, shape=None):
         "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR,
-        "traffic": _traffic("vector"),
+        "traffic": _traffic("vector", workload),
         "kernel": "rsim::echo_kernel<float> (FP64 prep + facet integral + facet sum)",
         "flop_per_eval": FLOP_PER_EVAL,
         "evals_per_launch": evals,
@@ -163,34 +186,78 @@ def roofline(kernel, evals, fs_ms, shape=None):
     }
 
 
-def cpu_baseline(cfg, channels=32):
-    """Time the FP64 oracle on one chirp of the same workload: brute-force visibility
-    for chirp 0 and the facet sum for `channels` channels x all samples, then scale to a
-    whole chirp (all channels) -> evals/s on one host core."""
+_CPU_CFG = None  # the workload, shared with forked oracle workers (copy-on-write)
+
+
+def _cpu_worker(task):
+    """One host core: the oracle on chirp n for a seeded sample of facets (visibility)
+    and the lit ones among them (facet sum over `channels` x all samples). Returns the
+    times of the scene transform alone, of the visibility call and of the sum call."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     import oracle
+    n, facets, channels = task
+    sc, wf, arr = _CPU_CFG.scenes[0], _CPU_CFG.waveform, _CPU_CFG.array
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.world_triangles(sc, float(n) * wf.chirp_period)
+        t_geo = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        m, _ = oracle.visibility(sc, arr, wf, chirps=[n], facets=facets)
+        t_vis = time.perf_counter() - t0
+        row = np.zeros(sc.n_tris, bool)
+        row[facets[m[0]]] = True
+        t0 = time.perf_counter()
+        oracle.synthesize(sc, wf, arr, mask={int(n): row}, chirps=[n], channels=channels)
+        t_sum = time.perf_counter() - t0
+    return t_geo, t_vis, t_sum, int(m[0].sum())
+
+
+def cpu_baseline(cfg, sample_facets=3000, channels=24, max_workers=16):
+    """The FP64 oracle on the host's cores (one forked worker per core, BLAS threads = 1,
+    one chirp each): per worker, visibility of a seeded sample of facets and the facet
+    sum of the lit ones over `channels` evenly spaced channels x all samples. Whole-frame
+    oracle time = chirps x (two scene transforms + all facets' visibility + all lit
+    facets' sum over all channels) at the measured per-facet and per-evaluation costs,
+    spread over the workers; value = lit-facet evaluations of the frame / that time.
+    Must run before the process touches the GPU (the workers are forked)."""
+    import multiprocessing as mp
+    import numpy as np
+    global _CPU_CFG
+    _CPU_CFG = cfg
     sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
-    O = arr.n_channels
-    t0 = time.perf_counter()
-    m, _ = oracle.visibility(sc, arr, wf, chirps=[0])
-    t_vis = time.perf_counter() - t0
-    full = np.zeros((wf.n_chirps, m.shape[1]), bool)
-    full[0] = m[0]
+    F, O, M, N = sc.n_tris, arr.n_channels, wf.n_samples, wf.n_chirps
+    workers = max(1, min(os.cpu_count() or 1, max_workers, N))
+    rng = np.random.default_rng(cfg.seed + 1000)
+    chirps = np.linspace(0, N - 1, workers).astype(int)
     ch = np.linspace(0, O - 1, channels).astype(int)
+    tasks = [(int(n), np.sort(rng.choice(F, min(sample_facets, F), replace=False)), ch)
+             for n in chirps]
     t0 = time.perf_counter()
-    oracle.synthesize(sc, wf, arr, mask=full, chirps=[0], channels=ch)
-    t_sum = time.perf_counter() - t0
-    lit = int(m[0].sum())
-    t_chirp = t_vis + t_sum * O / channels
-    evals = lit * wf.n_samples * O
-    return {"value": evals / t_chirp, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": (f"chirp 0 of the same workload: visibility over all {m.shape[1]} facets "
-                       f"({t_vis:.1f} s) + facet sum for {channels} of {O} channels x "
-                       f"{wf.n_samples} samples ({t_sum:.1f} s), scaled to all channels; "
-                       f"{lit} lit facets; numpy float64, single thread")}
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_cpu_worker, tasks)
+    wall = time.perf_counter() - t0
+    per_chirp, lit_frac = [], []
+    for (t_geo, t_vis, t_sum, lit), (_, fac, _) in zip(res, tasks):
+        S = fac.size
+        v = max(t_vis - t_geo, 0.0) / S                      # per facet (visibility)
+        e = max(t_sum - t_geo, 0.0) / max(1, lit * M * channels)  # per evaluation
+        lit_all = F * lit / S
+        per_chirp.append(2.0 * t_geo + F * v + lit_all * M * O * e)
+        lit_frac.append(lit / S)
+    frame_s = N * float(np.mean(per_chirp)) / workers
+    evals = N * F * float(np.mean(lit_frac)) * M * O
+    return {"value": evals / frame_s, "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{workers} forked workers (numpy float64, BLAS threads 1), one chirp "
+                       f"each ({', '.join(str(int(n)) for n in chirps)}): visibility of "
+                       f"{tasks[0][1].size} seeded facets of {F}, facet sum of the lit ones "
+                       f"over {channels} of {O} channels x {M} samples; scaled to the whole "
+                       f"frame ({N} chirps, all facets and channels) on {workers} cores: "
+                       f"{frame_s:.0f} s per frame; sample wall time {wall:.1f} s"),
+            "host_cpus": os.cpu_count()}
 
 
-def measure_fwd_bwd(sim, reps=3):
+def measure_fwd_bwd(sim, reps=2):
     """Forward (echo + RDM) and forward + backward (RDM adjoint + facet-sum adjoint +
     vertex/velocity gather) for the loss sum (RDM - T)^2 with a fixed target T."""
     import numpy as np
@@ -232,7 +299,7 @@ def measure_fwd_bwd(sim, reps=3):
             "stage_ms": {k: round(v, 4) for k, v in stages.items()}}
 
 
-def measure_other_kernel(sim, echo, mask, kernel, evals, reps=5):
+def measure_other_kernel(sim, echo, mask, kernel, evals, workload, reps=2):
     """Facet-sum time and roofline of the kernel the autotuner did not pick, on the same
     frame (median of `reps` launches after one warm-up; results compared with the main
     kernel's to the FP32 bar)."""
@@ -251,65 +318,70 @@ def measure_other_kernel(sim, echo, mask, kernel, evals, reps=5):
     d = (buf - ref).abs().pow(2).sum().sqrt() / ref.abs().pow(2).sum().sqrt()
     wf = sim.wf
     return {"kernel": kernel, "facet_sum_ms": fs,
-            "roofline": roofline(kernel, evals, fs, (sim.O, wf.n_chirps, wf.n_samples)),
+            "roofline": roofline(kernel, evals, fs, (sim.O, wf.n_chirps, wf.n_samples), workload),
             "rel_rms_vs_main": float(d)}
 
 
-def measure_batched(n_scenes=8, reps=3, kernel="vector"):
-    """A slice of the 64-scene batched workload (seeds 400...): one persistent,
-    graph-captured launch over all scenes vs one plain launch per scene, with the
-    facet-sum kernel of the main measurement. The direct sums give bit-identical
-    results; the NUFFT accumulates with atomic adds, so its results agree to FP32
-    rounding (the relative RMS difference is reported)."""
+def measure_batched(n_scenes=64, reps=2, kernels=("matrix", "nufft")):
+    """The batched workload (64 scenes, seeds 400..463, 10k-400k triangles each): for each
+    kernel, one call over all scenes with the persistent launch under a captured graph
+    against one plain call per scene, timed end to end (visibility, compaction, facet
+    sum); the two results are compared bit for bit. A kernel the scenes make ineligible
+    is reported as such."""
     import numpy as np
     import torch
     import scenes
     from paper_2208_10939_amd.pipeline import Simulator
-    from paper_2208_10939_amd.rsim import RSIM_ERANGE, RsimError
+    from paper_2208_10939_amd.rsim import RsimError
     cfg = scenes.c4(n_scenes=n_scenes)
     sim = Simulator(cfg.scenes, cfg.waveform, cfg.array)
-    note = None
-    try:  # the NUFFT refuses meshes whose facets span more than 1.5 grid cells
-        sim.ctx.synthesize(sim.scene_ids, sim.echo_buffer(n_scenes), None, kernel=KERNEL_CODES[kernel])
-    except RsimError as e:
-        if e.code != RSIM_ERANGE:
-            raise
-        note = f"{kernel} ineligible here ({e}); matrix cores used"
-        kernel = "matrix"
-    kc = KERNEL_CODES[kernel]
     n = len(cfg.scenes)
     plain = sim.echo_buffer(n)
     batched = sim.echo_buffer(n)
     mask = sim.mask_buffer()
+    out = {"scenes": n, "triangles": int(sum(s.n_tris for s in cfg.scenes)), "legs": []}
+    evals = None
+    for kernel in kernels:
+        kc = KERNEL_CODES[kernel]
 
-    def run_plain():
-        for i in range(n):
-            sim.ctx.synthesize([sim.scene_ids[i]], plain[i:i + 1], None, kernel=kc)
+        def run_plain():
+            for i in range(n):
+                sim.ctx.synthesize([sim.scene_ids[i]], plain[i:i + 1], None, kernel=kc)
 
-    def run_batched():
-        sim.ctx.synthesize(sim.scene_ids, batched, mask, persistent=True, use_graph=True,
-                           kernel=kc)
+        def run_batched():
+            sim.ctx.synthesize(sim.scene_ids, batched, mask, persistent=True, use_graph=True,
+                               kernel=kc)
 
-    times = {}
-    for name, fn in (("plain", run_plain), ("batched", run_batched)):
-        fn()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        times[name] = 1e3 * float(np.median(ts))
-    lit = sum(int(m.sum()) for m in sim.masks_numpy(mask))
-    evals = lit * cfg.waveform.n_samples * cfg.array.n_channels
-    same = bool(torch.equal(plain, batched))
-    diff = float((plain - batched).abs().pow(2).sum().sqrt() / plain.abs().pow(2).sum().sqrt())
-    return {"scenes": n, "triangles": int(sum(s.n_tris for s in cfg.scenes)), "kernel": kernel,
-            "plain_ms": times["plain"], "batched_ms": times["batched"],
-            "plain_evals_per_s": evals / (times["plain"] * 1e-3),
-            "batched_evals_per_s": evals / (times["batched"] * 1e-3),
-            "bit_identical": same, "rel_rms_difference": diff, "note": note}
+        leg = {"kernel": kernel}
+        try:
+            times = {}
+            for name, fn in (("plain", run_plain), ("batched", run_batched)):
+                fn()
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    fn()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                times[name] = 1e3 * float(np.median(ts))
+        except RsimError as e:
+            leg["note"] = f"not run: {e}"
+            out["legs"].append(leg)
+            continue
+        if evals is None:
+            lit = sum(int(m.sum()) for m in sim.masks_numpy(mask))
+            evals = lit * cfg.waveform.n_samples * cfg.array.n_channels
+        diff = float((plain - batched).abs().pow(2).sum().sqrt() / plain.abs().pow(2).sum().sqrt())
+        leg.update({"plain_ms": times["plain"], "batched_ms": times["batched"],
+                    "plain_evals_per_s": evals / (times["plain"] * 1e-3),
+                    "batched_evals_per_s": evals / (times["batched"] * 1e-3),
+                    "bit_identical": bool(torch.equal(plain, batched)),
+                    "rel_rms_difference": diff})
+        _log(f"bench: batched {kernel}: plain {times['plain']:.1f} ms, batched "
+             f"{times['batched']:.1f} ms, bit-identical {leg['bit_identical']}")
+        out["legs"].append(leg)
+    return out
 
 
 def calib_copy(mib: int):
@@ -337,6 +409,9 @@ def main():
                     help="only the forward + backward timing (for kernel traces of the adjoint)")
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--tile-f", type=int, default=0)
+    ap.add_argument("--workload", choices=tuple(WORKLOADS), default="c3",
+                    help="c3: 1M-triangle intersection, 512 x 256 (default); c2: 50k-triangle "
+                         "vehicle, 256 x 128")
     ap.add_argument("--kernel", choices=("auto", "vector", "matrix", "nufft"), default="auto",
                     help="facet-sum kernel (auto: the autotuner's choice)")
     args = ap.parse_args()
@@ -349,16 +424,25 @@ def main():
         return
 
     import numpy as np
-    import torch
 
     import scenes
+
+    desc, make = WORKLOADS[args.workload]
+    cfg = make()
+    sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
+    _log(f"bench: {args.workload} workload, {sc.n_tris} triangles, O={arr.n_channels}, "
+         f"M={wf.n_samples}, N={wf.n_chirps}")
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's workers are forked: before anything touches the GPU
+        _log("bench: timing the FP64 oracle on the host cores (bounded sample)")
+        cpu = cpu_baseline(cfg)
+        _log(f"bench: oracle {cpu['value']:.3e} evals/s on {cpu['cores']} cores")
+
+    import torch
     from paper_2208_10939_amd.pipeline import Simulator
 
     torch.cuda.set_device(0)
-    cfg = scenes.c2()
-    sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
-    _log(f"bench: c2 workload, {sc.n_tris} triangles, O={arr.n_channels}, M={wf.n_samples}, "
-         f"N={wf.n_chirps}")
     sim = Simulator([sc], wf, arr)
     echo = sim.echo_buffer(1)
     mask = sim.mask_buffer()
@@ -407,8 +491,11 @@ def main():
     stage_avg = {n: round(float(v / args.steps), 4) for n, v in zip(names, stage_ms)}
     fs_ms = stage_ms[2] / args.steps
     achieved = FLOP_PER_EVAL * evals_per_step / (fs_ms * 1e-3)
-    _log(f"bench: {ms_per_step:.2f} ms/step, facet sum {fs_ms:.2f} ms, "
-         f"{achieved / 1e12:.2f} TFLOP/s algorithmic")
+    rl = roofline(kernel, evals_per_step, fs_ms, (arr.n_channels, wf.n_chirps, wf.n_samples),
+                  args.workload)
+    _log(f"bench: {ms_per_step:.2f} ms/step, facet sum {fs_ms:.2f} ms "
+         f"({achieved / 1e12:.2f} TFLOP/s direct-sum-equivalent); {kernel} kernel at "
+         f"{rl['achieved']:.2f} {rl['unit']} of its own work = {rl['frac']:.3f} of peak")
 
     out = {
         "metric": METRIC,
@@ -423,8 +510,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single vehicle hull, 50k triangles, 12x16 sparse MIMO "
-                               "(192 ch), 256 samples x 128 chirps, FP32 sum + FP64 phase",
+        "config": {"workload": desc,
                    "triangles": int(sc.n_tris), "channels": int(arr.n_channels),
                    "samples": int(wf.n_samples), "chirps": int(wf.n_chirps),
                    "lit_facets_per_chirp": float(lit.mean()), "seed": cfg.seed,
@@ -432,8 +518,7 @@ def main():
                    "facet_sum_tile": (tuned if tuned else
                                       {"tile_m": args.tile_m, "tile_f": args.tile_f})},
         "stage_ms": stage_avg,
-        "roofline": roofline(kernel, evals_per_step, fs_ms,
-                             (arr.n_channels, wf.n_chirps, wf.n_samples)),
+        "roofline": rl,
     }
     if not args.no_extras:
         out["other_kernels"] = []
@@ -442,14 +527,13 @@ def main():
                 continue
             _log(f"bench: the {other} kernel's facet sum on the same frame")
             out["other_kernels"].append(
-                measure_other_kernel(sim, echo, mask, other, evals_per_step))
+                measure_other_kernel(sim, echo, mask, other, evals_per_step, args.workload))
         _log("bench: forward + backward")
         out["fwd_bwd"] = measure_fwd_bwd(sim)
-        _log("bench: batched vs plain (8 scenes of the 64-scene workload)")
-        out["batched_vs_plain"] = measure_batched(kernel=kernel)
-    if not args.no_cpu:
-        _log("bench: timing the FP64 oracle on the host (bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        _log("bench: batched vs plain (the 64-scene workload)")
+        out["batched_vs_plain"] = measure_batched()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -19,15 +19,23 @@ class RadarRDM(torch.autograd.Function):
     """
 
     @staticmethod
+    def _load_geometry(sim: Simulator, scene_index: int, verts_np, vel_np):
+        """Upload this call's vertices and velocities into the library's scene."""
+        sid = sim.scene_ids[scene_index]
+        for mid, v in zip(sim.ctx.scene_meshes[sid], verts_np):
+            sim.ctx.update_mesh(mid, v)
+        pos0 = sim.inst_pos0[scene_index]
+        for i in range(len(pos0)):
+            sim.ctx.set_instance_motion(sid, i, pos0[i], vel_np[i])
+
+    @staticmethod
     def forward(ctx, sim: Simulator, scene_index: int, vel, *verts):
         sid = sim.scene_ids[scene_index]
         meshes = sim.ctx.scene_meshes[sid]
-        for mid, v in zip(meshes, verts):
-            sim.ctx.update_mesh(mid, v.detach().cpu().numpy())
+        verts_np = [v.detach().cpu().numpy().copy() for v in verts]
+        vel_np = vel.detach().cpu().numpy().copy()
+        RadarRDM._load_geometry(sim, scene_index, verts_np, vel_np)
         pos0 = sim.inst_pos0[scene_index]
-        vv = vel.detach().cpu().numpy()
-        for i in range(len(pos0)):
-            sim.ctx.set_instance_motion(sid, i, pos0[i], vv[i])
         mask = sim.mask_buffer([scene_index])
         echo = sim.synthesize([scene_index], mask=mask)
         rdm, y = sim.form_rdm(echo, want_y=True)
@@ -38,6 +46,10 @@ class RadarRDM(torch.autograd.Function):
         ctx.vert_devices = [v.device for v in verts]
         ctx.vel_device = vel.device
         ctx.n_inst = len(pos0)
+        # the backward recomputes the chirps from the library's scene, which a later
+        # forward on the same simulator may have replaced: keep this call's geometry
+        ctx.verts_np = verts_np
+        ctx.vel_np = vel_np
         ctx.save_for_backward(mask, y)
         return rdm[0]
 
@@ -57,6 +69,7 @@ class RadarRDM(torch.autograd.Function):
             per_id[mid] = t
             grads.append(t)
         grad_vel = torch.zeros((ctx.n_inst, 3), dtype=torch.float64, device=dev)
+        RadarRDM._load_geometry(sim, ctx.scene_index, ctx.verts_np, ctx.vel_np)
         sim.ctx.backward(sim.scene_ids[ctx.scene_index], grad_echo, mask, per_id, grad_vel)
         grads = [g.to(d) for g, d in zip(grads, ctx.vert_devices)]
         return (None, None, grad_vel.to(ctx.vel_device), *grads)

@@ -38,7 +38,8 @@ __global__ void __launch_bounds__(256) range_fft_kernel(const typename Cx2<R>::T
 }
 
 // Columns of length N (stride M) of each channel's [N][M] plane.
-// mode 0 (forward): Y = shift_n(FFT_n(X)); writes rdm = |Y|^2 and y_out if given.
+// mode 0 (forward): Y = shift_n(FFT_n(X)), row l holding Doppler index l - floor(N/2) for
+//   even and odd N alike; writes rdm = |Y|^2 and y_out if given.
 // mode 1 (adjoint input side): Z = FFT_n(conj(unshift_n(G))) written to y_out.
 // mode 2 (RDM backward): as mode 1 with G = 2 (dL/dP) Y formed on the fly from
 //   gp = dL/dP (rdm-shaped) and in = Y, since P = |Y|^2.
@@ -65,8 +66,8 @@ __global__ void __launch_bounds__(256) doppler_fft_kernel(const typename Cx2<R>:
     if (mode == 0) {
       a[c * ld + n] = src[static_cast<int64_t>(n) * M + k0 + c];
     } else {
-      // row l of G holds Doppler index l' = l - N/2; place it at l' mod N, conjugated
-      const int lp = (n + hN) % N;
+      // row l of G holds Doppler index l' = l - floor(N/2); place it at l' mod N, conjugated
+      const int lp = (n + N - hN) % N;
       const int64_t gi = static_cast<int64_t>(n) * M + k0 + c;
       C v = src[gi];
       if (mode == 2) {
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) doppler_fft_kernel(const typename Cx2<R>:
     if (c >= ncol) continue;
     const int64_t g = base + static_cast<int64_t>(l) * M + k0 + c;
     if (mode == 0) {
-      const C v = res[c * ld + (l + hN) % N];  // row l <- index l - N/2
+      const C v = res[c * ld + (l + N - hN) % N];  // row l <- index l - floor(N/2)
       if (rdm) rdm[g] = v.x * v.x + v.y * v.y;
       if (y_out) y_out[g] = v;
     } else {

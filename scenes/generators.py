@@ -511,3 +511,18 @@ def synthetic_y_cube(arr: RadarArray, wf: Waveform, seed: int, targets, noise_si
     for row, col, amp, u, w in targets:
         Y[:, row, col] += amp * np.exp(-2j * np.pi * (u * v[:, 0] + w * v[:, 2]) / lam)
     return Y.astype(np.complex64)
+
+
+def scene_digest(scene: Scene) -> str:
+    """Short hash of a scene's generated geometry and motion (vertices, triangles,
+    rotations, start positions, velocities), so that stored expectations can detect
+    generator drift."""
+    import hashlib
+    h = hashlib.sha256()
+    for m in scene.meshes:
+        h.update(np.ascontiguousarray(m.verts, np.float32).tobytes())
+        h.update(np.ascontiguousarray(m.tris, np.int32).tobytes())
+    for i in scene.instances:
+        for a in (i.rot, i.pos0, i.vel):
+            h.update(np.ascontiguousarray(a, np.float64).tobytes())
+    return h.hexdigest()[:16]

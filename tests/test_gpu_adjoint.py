@@ -202,6 +202,53 @@ def test_autograd_function_matches_direct_calls():
     assert torch.allclose(vel.grad.cuda(), gvel, rtol=1e-5, atol=1e-8 * gvel.abs().max().item())
 
 
+def test_autograd_two_forwards_one_backward():
+    """Two RadarRDM applies on one simulator with different vertices and velocities, one
+    backward through the sum of their losses: each apply's gradient is taken at its own
+    geometry (the backward re-loads it), so the result equals the two separate
+    backwards added."""
+    import torch
+    from paper_2208_10939_amd.autograd import RadarRDM
+    from paper_2208_10939_amd.pipeline import Simulator
+    _log("case RadarRDM: two forwards, one backward")
+    wf, arr, sc, target = _setup()
+    sim = Simulator([sc], wf, arr)
+    T = torch.from_numpy(oracle.rdm_from_echo(oracle.synthesize(target, wf, arr))[0]
+                         .astype(np.float32)).cuda()
+    rng = np.random.default_rng(5)
+    geo = []
+    for k in range(2):
+        vs = [m.verts.copy() + (k * rng.normal(scale=2e-3, size=m.verts.shape)).astype(np.float32)
+              for m in sc.meshes]
+        vel = np.stack([i.vel for i in sc.instances]) + k * np.array([0.3, -0.2, 0.0])
+        geo.append((vs, vel))
+
+    def leaves(k):
+        vs, vel = geo[k]
+        return ([torch.from_numpy(v.copy()).requires_grad_(True) for v in vs],
+                torch.from_numpy(vel.copy()).requires_grad_(True))
+
+    sep = []
+    for k in range(2):
+        verts, vel = leaves(k)
+        L = ((RadarRDM.apply(sim, 0, vel, *verts) - T) ** 2).sum()
+        L.backward()
+        sep.append(([v.grad.clone() for v in verts], vel.grad.clone()))
+    (v0, vel0), (v1, vel1) = leaves(0), leaves(1)
+    L = (((RadarRDM.apply(sim, 0, vel0, *v0) - T) ** 2).sum() +
+         ((RadarRDM.apply(sim, 0, vel1, *v1) - T) ** 2).sum())
+    L.backward()
+    for j in range(len(sc.meshes)):
+        want = [sep[0][0][j], sep[1][0][j]]
+        got = [v0[j].grad, v1[j].grad]
+        for a, b in zip(got, want):
+            assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * b.abs().max().item())
+    assert torch.allclose(vel0.grad, sep[0][1], rtol=1e-5, atol=1e-8 * sep[0][1].abs().max().item())
+    assert torch.allclose(vel1.grad, sep[1][1], rtol=1e-5, atol=1e-8 * sep[1][1].abs().max().item())
+    # the two geometries give different gradients (the check above is not vacuous)
+    assert not torch.allclose(sep[0][1], sep[1][1], rtol=1e-3)
+
+
 @pytest.mark.parametrize("P,Q,M", [(12, 16, 96), (3, 5, 64), (1, 4, 160), (6, 8, 40)])
 def test_matrix_adjoint_equals_vector_adjoint(P, Q, M):
     """The matrix-core adjoint against the vector-unit one on the same gradient input:

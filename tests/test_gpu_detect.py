@@ -118,12 +118,16 @@ def test_cfar_and_angle_on_synthetic_cubes(sim_mod, array, scale, max_points):
         assert n >= 1
 
 
-def test_detection_end_to_end_point_scatterers(sim_mod):
+@pytest.mark.parametrize("n_chirps", [32, 27])
+def test_detection_end_to_end_point_scatterers(sim_mod, n_chirps):
     """Point scatterers plus white noise at 0 dB per sample (the same seeded noise on
     both sides) through the whole GPU chain (echo, noise, RDM, detection) and through the
     oracle's chain: detections and points agree, and the strongest point near each
-    scatterer sits within one range, Doppler and angle cell of it."""
-    wf = scenes.paper_waveform(128, 32)
+    scatterer sits within one range, Doppler and angle cell of it. An odd chirp count
+    checks the Doppler rows and velocities of the shifted axis (row l: index
+    l - floor(N/2))."""
+    _log(f"case detection end to end, N={n_chirps}")
+    wf = scenes.paper_waveform(128, n_chirps)
     arr = scenes.sparse_mimo_12x16(wf, seed=2)
     pos = np.array([[4.0, 20.0, -6.0], [-8.0, 35.0, 2.0]])
     vel = np.array([[0.0, 2.0, 0.0], [1.0, -4.0, 0.0]])

@@ -2,6 +2,7 @@
 (FP32 sum with FP64 phase, default tiles), on outputs the FP64 oracle computes one by
 one: sampled chirps x channels x samples, sampled mask rows and properties that hold at
 any size. Tolerance 1e-4 relative RMS on the echo."""
+import os
 import sys
 
 import numpy as np
@@ -86,21 +87,71 @@ def test_single_vehicle_50k_full_size():
     assert abs(P / E - 1.0) < 1e-5
 
 
+C3_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "c3_oracle_samples.npz")
+
+
+def _unpack_rows(packed, n_facets):
+    bits = np.unpackbits(np.asarray(packed), axis=1, bitorder="little")
+    return bits[:, :n_facets].astype(bool)
+
+
 @pytest.mark.slow
-def test_intersection_1m_triangles_one_chirp():
+def test_intersection_1m_default_path_and_every_kernel():
+    """The 1M-triangle intersection (ground grid + 20 vehicles, 192 ch x 512 x 256) in
+    bench's launch configuration: the library's autotuner runs first and the default
+    (AUTO) facet sum is checked, then each facet-sum kernel explicitly on the same mask.
+    Against the FP64 oracle's stored values (tests/golden/make_c3_samples.py, oracle only):
+    the lit masks of chirps 0 and 255 over all 1M facets (mismatches only where the oracle
+    flags the decision ambiguous), and the echo of six channels spread over the array x
+    all 512 samples at those chirps, summed over every lit facet (bar 1e-4)."""
+    import torch
     from paper_2208_10939_amd.pipeline import Simulator
-    _log("case intersection ~1M triangles, 192 ch x 512 x 256: chirp 0, 2 channels, 64 samples")
+    g = np.load(C3_GOLDEN, allow_pickle=False)
+    chirps = [int(n) for n in g["chirps"]]
+    channels = np.asarray(g["channels"])
+    _log(f"case intersection 1M triangles, default path after autotune: chirps {chirps}, "
+         f"channels {list(channels)}, 512 samples")
     cfg = scenes.c3()
     sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
+    assert scenes.scene_digest(sc) == str(g["scene_sha16"]), "scene generator drift"
+    F = int(g["n_facets"])
+    om = _unpack_rows(g["mask"], F)
+    amb = _unpack_rows(g["ambiguous"], F)
     sim = Simulator([sc], wf, arr)
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".jsonl")
+    os.close(fd)
+    sim.ctx.autotune([sim.scene_ids[0]], path)
+    with open(path) as f:
+        import json
+        tuned = json.loads(f.read().strip().splitlines()[-1])
+    os.remove(path)
+    _log(f"  autotuned kernel: {tuned['kernel']}")
     mask = sim.mask_buffer()
-    sim.last_mask = mask
-    H = sim.synthesize(mask=mask).cpu().numpy()[0]
-    gm = sim.masks_numpy(mask)[0][[0]]
-    err, om, amb = _sampled_parity(sim, sc, wf, arr, [0], np.array([5, 150]),
-                                   np.arange(0, 512, 8), echo=H, gmask_rows=gm)
-    _log(f"  F={sc.n_tris} lit={om.sum()} ambiguous={amb.sum()} echo rel_rms={err:.3e}")
+    H = sim.synthesize(mask=mask)
+    torch.cuda.synchronize()
+    full = sim.masks_numpy(mask)[0]
+    gm = full[chirps]
+    mism = gm != om
+    _log(f"  lit={gm.sum(1)} oracle lit={om.sum(1)} ambiguous={amb.sum(1)} "
+         f"mismatched={mism.sum(1)}")
+    assert not (mism & ~amb).any(), f"{int((mism & ~amb).sum())} unambiguous mask mismatches"
+    if mism.any():  # rerun with the oracle's rows for the sampled chirps
+        full[chirps] = om
+        mask = sim.mask_from_numpy([full])
+        H = sim.synthesize(mask=mask, mask_mode=1)
+    Hs = H[0][torch.as_tensor(channels).cuda()][:, chirps].cpu().numpy()
+    err = rel_rms(Hs, g["echo"])
+    _log(f"  default ({tuned['kernel']}) echo rel_rms={err:.3e}")
     assert err <= TOL
+    for kernel, name in ((1, "vector"), (2, "matrix"), (3, "nufft")):
+        Hk = sim.synthesize(mask=mask, mask_mode=1, kernel=kernel)
+        Hs = Hk[0][torch.as_tensor(channels).cuda()][:, chirps].cpu().numpy()
+        errk = rel_rms(Hs, g["echo"])
+        _log(f"  {name} echo rel_rms={errk:.3e}")
+        assert errk <= TOL
+        del Hk
 
 
 @pytest.mark.slow

@@ -145,11 +145,12 @@ def test_experiment2_waveform_384_samples(sim_mod):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("M,N", [(256, 64), (384, 48), (162, 6)])
+@pytest.mark.parametrize("M,N", [(256, 64), (384, 48), (162, 6), (96, 9), (64, 81)])
 def test_rdm_fft_against_numpy(sim_mod, precision, M, N):
     """Range/Doppler FFTs and the RDM on a seeded random cube vs numpy.fft (FP64), at
     power-of-two lengths and at mixed radix-2/3 lengths (384 samples is the paper's
-    second experiment; 162 = 2 x 3^4)."""
+    second experiment; 162 = 2 x 3^4); odd chirp counts (9, 81) check that row l holds
+    Doppler index l - floor(N/2), as numpy's fftshift puts it."""
     import torch
     _log(f"case rdm_fft precision={precision} M={M} N={N}")
     wf = scenes.paper_waveform(M, N)
@@ -169,7 +170,7 @@ def test_rdm_fft_against_numpy(sim_mod, precision, M, N):
     assert e1 <= tol and e2 <= 2 * tol
 
 
-@pytest.mark.parametrize("M,N", [(128, 32), (96, 12)])
+@pytest.mark.parametrize("M,N", [(128, 32), (96, 12), (48, 27)])
 def test_rdm_adjoint_identity(sim_mod, M, N):
     """<A x, g> = <x, A^H g> (real inner product) for the linear map x -> Y."""
     import torch
