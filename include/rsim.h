@@ -221,6 +221,19 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
 int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm,
                       void *y_opt, void *hip_stream, const rsim_opts *opts);
 
+/* rsim_form_rdm for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same arguments, layouts,
+ * outputs and errors as rsim_form_rdm; it calls no hipMalloc, hipFree or allocating
+ * routine. Its work memory (twiddle tables, then the range-transformed planes of up to
+ * g = floor((32 MiB - twiddles) / (N M csize)) channel planes at a time, csize 8 or 16
+ * bytes) is one file-scope device array of 32 MiB per GPU, held from library load until
+ * the process ends and shared by every call on that GPU: calls that overlap on one GPU
+ * (other streams, threads or contexts) race. ERANGE when one N x M plane and its
+ * twiddles do not fit the 32 MiB (e.g. N = M = 2048 at FP32). opts->timing records
+ * the whole call as stage 3. */
+int32_t rsim_form_rdm_noalloc(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm,
+                              void *y_opt, void *hip_stream, const rsim_opts *opts);
+
 /* Per-stage device times (ms) of the last rsim_synthesize / rsim_form_rdm /
  * rsim_backward call made with opts.timing = 1, measured with HIP events on the
  * caller's stream. Blocks until those events complete. Stage order:

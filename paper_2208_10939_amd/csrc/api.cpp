@@ -151,6 +151,8 @@ struct rsim_ctx {
   double z_ground = 0.0, gamma_re = -1.0, gamma_im = 0.0;
   double *d_elem_img = nullptr;  // [3][E][3]: elements of path types 1..3 (images)
   uint64_t elem_img_version = 0;
+  // this device's copy of the allocation-free entry point's work array (never freed)
+  void *static_scratch = nullptr;
 };
 
 namespace {
@@ -991,6 +993,9 @@ int32_t rsim_create(int32_t hip_device, rsim_ctx **out) {
   }
   if ((e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
     return fail(nullptr, RSIM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+  if ((e = static_scratch_address(hip_device, &ctx->static_scratch)) != hipSuccess)
+    return fail(nullptr, RSIM_EDEVICE, "hipGetSymbolAddress of the static work array: %s",
+                hipGetErrorString(e));
   *out = ctx.release();
   return RSIM_OK;
 }
@@ -1673,6 +1678,60 @@ int32_t rsim_form_rdm(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rd
   stage_begin(ctx, timing, 4, s);
   HIP_TRY(ctx, launch_doppler_fft(precision, X, y_opt, rdm, planes, N, M, 0, twN, s));
   stage_end(ctx, timing, 4, s);
+  return RSIM_OK;
+}
+
+int32_t rsim_form_rdm_noalloc(rsim_ctx *ctx, const void *echo, int32_t n_cubes, void *rdm,
+                              void *y_opt, void *hip_stream, const rsim_opts *opts) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  rsim_opts o{};
+  if (opts) o = *opts;
+  if (!echo || n_cubes < 1 || (!rdm && !y_opt))
+    return fail(ctx, RSIM_EINVAL, "rsim_form_rdm_noalloc: need echo, n_cubes >= 1 and an output");
+  int32_t rc = check_radar(ctx);
+  if (rc) return rc;
+  const int M = ctx->wf.n_samples, N = ctx->wf.n_chirps;
+  if (!fft_size_ok(M) || !fft_size_ok(N))
+    return fail(ctx, RSIM_ERANGE, "rsim_form_rdm_noalloc: M=%d and N=%d must be 2^a 3^b in 2..4096",
+                M, N);
+  if ((rc = need_device(ctx))) return rc;
+  if (!ctx->static_scratch)
+    return fail(ctx, RSIM_EDEVICE, "rsim_form_rdm_noalloc: no static work array on this device");
+  const int precision = o.precision ? 1 : 0;
+  const size_t csize = precision ? 16 : 8;
+  const size_t need_lds = 2 * csize * (std::max(M, N) + 32);
+  if (need_lds > ctx->max_lds) return fail(ctx, RSIM_ERANGE, "FFT length exceeds LDS");
+  // layout of the static array: twiddles of M, twiddles of N, then X of g planes
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t tw_bytes = al(csize * M) + al(csize * N);
+  const size_t plane = csize * static_cast<size_t>(N) * M;
+  if (tw_bytes + plane > kStaticScratchBytes)
+    return fail(ctx, RSIM_ERANGE,
+                "rsim_form_rdm_noalloc: one %d x %d plane (%zu bytes) and its twiddles exceed the "
+                "static work array (%zu bytes)", N, M, plane, kStaticScratchBytes);
+  const int64_t O = static_cast<int64_t>(ctx->tx.size() / 3) * (ctx->rx.size() / 3);
+  const int64_t planes = O * n_cubes;
+  const int64_t group = static_cast<int64_t>((kStaticScratchBytes - tw_bytes) / plane);
+  char *base = static_cast<char *>(ctx->static_scratch);
+  void *twM = base, *twN = base + al(csize * M);
+  void *X = base + tw_bytes;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const bool timing = o.timing != 0;
+  if (timing && !ctx->timing_pending) timing_reset(ctx, true);
+  HIP_TRY(ctx, launch_twiddle_fill(twM, M, precision, s));
+  HIP_TRY(ctx, launch_twiddle_fill(twN, N, precision, s));
+  stage_begin(ctx, timing, 3, s);
+  for (int64_t p0 = 0; p0 < planes; p0 += group) {
+    const int64_t g = std::min(group, planes - p0);
+    const size_t off = static_cast<size_t>(p0) * N * M;
+    HIP_TRY(ctx, launch_range_fft(precision, static_cast<const char *>(echo) + off * csize, X,
+                                  g * N, M, 1, twM, s));
+    HIP_TRY(ctx, launch_doppler_fft(precision, X,
+                                    y_opt ? static_cast<char *>(y_opt) + off * csize : nullptr,
+                                    rdm ? static_cast<char *>(rdm) + off * (csize / 2) : nullptr,
+                                    g, N, M, 0, twN, s));
+  }
+  stage_end(ctx, timing, 3, s);
   return RSIM_OK;
 }
 

@@ -114,6 +114,13 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
                                 const void *grad_echo, float *partial, hipStream_t s);
 
+// Allocation-free range-Doppler processing: a file-scope device array of
+// kStaticScratchBytes per GPU, addressed through static_scratch_address (looked up once
+// per device with that device current), and twiddle tables written into it by a kernel.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+hipError_t static_scratch_address(int device, void **out);
+hipError_t launch_twiddle_fill(void *tw, int L, int precision, hipStream_t s);
+
 hipError_t launch_range_fft(int precision, const void *in, void *out, int64_t rows, int M,
                             int conj_in, const void *tw, hipStream_t s);
 hipError_t launch_doppler_fft(int precision, const void *in, void *y_out, void *rdm,

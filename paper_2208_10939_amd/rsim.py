@@ -39,7 +39,7 @@ EXPORTS = (
     "rsim_form_rdm", "rsim_last_timings", "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
     "rsim_rdm_backward", "rsim_detect", "rsim_add_noise", "rsim_set_ground",
-    "rsim_set_backward_kernel", "rsim_set_nufft_chunk",
+    "rsim_set_backward_kernel", "rsim_set_nufft_chunk", "rsim_form_rdm_noalloc",
 )
 
 
@@ -127,6 +127,7 @@ def lib() -> ctypes.CDLL:
         "rsim_set_ground": ([vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
         "rsim_set_backward_kernel": ([vp, i32], i32),
         "rsim_set_nufft_chunk": ([vp, i32], i32),
+        "rsim_form_rdm_noalloc": ([vp, vp, i32, vp, vp, vp, ctypes.POINTER(Opts)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -304,6 +305,13 @@ class Context:
         o = self.opts(**kw)
         self._check(self._L.rsim_form_rdm(self._h, _ptr(echo), int(n_cubes), _ptr(rdm), _ptr(y),
                                            _stream(stream), ctypes.byref(o)))
+
+    def form_rdm_noalloc(self, echo, rdm=None, y=None, n_cubes: int = 1, stream=None, **kw):
+        """rsim_form_rdm_noalloc: form_rdm with its work memory in the library's static
+        per-GPU array (no device allocation)."""
+        o = self.opts(**kw)
+        self._check(self._L.rsim_form_rdm_noalloc(self._h, _ptr(echo), int(n_cubes), _ptr(rdm),
+                                                  _ptr(y), _stream(stream), ctypes.byref(o)))
 
     def rdm_adjoint(self, grad_y, grad_echo, n_cubes: int = 1, stream=None):
         self._check(self._L.rsim_rdm_adjoint(self._h, _ptr(grad_y), int(n_cubes),
