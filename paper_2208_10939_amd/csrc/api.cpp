@@ -134,7 +134,7 @@ struct rsim_ctx {
   void *nu_adj_buf = nullptr;  // work buffers of the NUFFT adjoint (grow-only)
   size_t nu_adj_bytes = 0;
   int32_t nu_chunk_max = 0;    // chirps per NUFFT chunk at most (0: as many as fit)
-  std::array<int64_t, 5> nu_layout{};
+  std::array<int64_t, 6> nu_layout{};
   size_t adj_partial_n = 0, adj_gxw_n = 0, adj_vpart_n = 0, adj_gsum_n = 0;
   BatchTables batch;  // persistent launches outside graphs
   GraphCache graph;
@@ -464,11 +464,11 @@ EchoShape matrix_shape(const RadarConst &rc) {
   return sh;
 }
 
-// NUFFT facet sum: largest facet spread on the grid (cells) and grid length.
-constexpr double kNuMaxSpread = 1.5;
+// NUFFT facet sum: grid length, adjoint splitting and work-buffer budget.
+constexpr double kNuMaxSpread = 1.5;  // adjoint records: facets spanning more are split
 constexpr int kNuMaxSplit = 3;
 constexpr int kNuMaxGrid = 2048;
-constexpr size_t kNuRecBudget = size_t(4) << 30;  // work buffer: chirps per launch cap
+constexpr size_t kNuRecBudget = size_t(16) << 30;  // work buffer: chirps per launch cap
 
 int smooth_at_least(int n) {  // smallest 2^a 3^b >= n
   int best = 1 << 30;
@@ -488,8 +488,6 @@ double scenes_rmax(const rsim_ctx *ctx, const std::vector<int32_t> &ids) {
   return r;
 }
 
-// Why the NUFFT facet sum cannot run (nullptr: it can, and *ns holds its shape without
-// the chirp chunk and record stride).
 double scenes_vmax(const rsim_ctx *ctx, const std::vector<int32_t> &ids) {
   double v = 0.0;
   for (int32_t id : ids) {
@@ -503,23 +501,16 @@ double scenes_vmax(const rsim_ctx *ctx, const std::vector<int32_t> &ids) {
   return v;
 }
 
-const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o,
-                             double r_max, double v_max, NuShape *ns) {
+// Grid, channel reach and FFT grouping shared by the NUFFT forward and adjoint (nullptr:
+// fine; else why not).
+const char *nufft_common(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o,
+                         double v_max, NuShape *ns) {
   if (o.precision != RSIM_FP32_PHASE64) return "the NUFFT facet sum is FP32 only";
   const int ng = smooth_at_least(2 * rc.M);
   if (ng > kNuMaxGrid) return "the NUFFT facet sum needs 2M <= 2048";
   if (ng < 32) return "the NUFFT facet sum needs M >= 16";
   const double kappa = rc.df * ng / kC0;
-  // facets spanning more than 1.5 grid cells are split into 4^split midpoint sub-triangles
-  // (halving the span per level), at most 64
-  double spread = 2.0 * r_max * kappa;
-  int split = 0;
-  while (spread > kNuMaxSpread && split < kNuMaxSplit) {
-    spread *= 0.5;
-    ++split;
-  }
-  if (spread > kNuMaxSpread) return "facets span more than 12 NUFFT grid cells";
-  // every channel's grid position lies within chan_cells of the phase-centre path's
+  // every channel's grid position lies within chan_d cells of the phase-centre path's
   double et = 0.0, er = 0.0;
   for (int p = 0; p < rc.P; ++p) {
     double d = 0.0;
@@ -531,41 +522,100 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
     for (int k = 0; k < 3; ++k) d += (ctx->rx[3 * q + k] - rc.rx_c[k]) * (ctx->rx[3 * q + k] - rc.rx_c[k]);
     er = std::max(er, std::sqrt(d));
   }
-  // the register window of the spread holds every channel's cells while the sorted
-  // phase-centre positions advance: 2 d <= window - width - 3. With the delay within the
-  // chirp a channel's source also moves by its Doppler shift (A + B M) n_g, at most
-  // n_g (f0 + M df) 2 v_max / (c fs) cells, relative to the record's by twice that.
+  // with the delay within the chirp a channel's source also moves by its Doppler shift
+  // (A + B M) n_g, at most n_g (f0 + M df) 2 v_max / (c fs) cells, relative to the
+  // record's by twice that
   double chan_d = kappa * (et + er);
   if (o.intra_chirp)
     chan_d += 2.0 * ng * (rc.f0 + rc.M * rc.df) * 2.0 * v_max / (kC0 * rc.fs);
-  if (2.0 * chan_d > nufft_window_cells() - kNuWidth - 3)
-    return "array aperture too wide for the NUFFT register window";
   NuShape s{};
   s.ng = ng;
   s.ld = ng + 1;
-  s.order = spread <= 0.35 ? 5 : spread <= 0.8 ? 7 : 10;
-  s.cb = 0;
-  for (int cb = 16; cb >= 1 && !s.cb; --cb) {  // two workgroups per CU where possible
-    NuShape t = s;
-    t.cb = cb;
-    if (nufft_smem_bytes(t) <= ctx->max_lds / 2) s.cb = cb;
-  }
-  if (!s.cb) s.cb = 1;
   const int O = rc.P * rc.Q;
-  s.cb = std::min(s.cb, O);
-  s.groups = (O + s.cb - 1) / s.cb;
   s.fc = rc.f0 + (rc.M / 2) * rc.df;
   s.kc = 2.0 * kPi * s.fc / kC0;
   s.cells_per_s = rc.df * ng;
   s.kappa = kappa;
   s.sigma = kNuSigma;
   s.chan_d = chan_d;
-  s.split = split;
   s.spread_groups = (O + 63) / 64;
   s.n0 = 0;
   s.n_chirps = rc.N;
   *ns = s;
   return nullptr;
+}
+
+// Channels per FFT workgroup: two workgroups per CU where the LDS allows (extra_lds:
+// bytes beyond the two row buffers).
+void nufft_fft_groups(const rsim_ctx *ctx, const RadarConst &rc, NuShape &s, size_t extra_lds) {
+  s.cb = 0;
+  for (int cb = 16; cb >= 1 && !s.cb; --cb) {
+    NuShape t = s;
+    t.cb = cb;
+    if (nufft_smem_bytes(t) + extra_lds <= ctx->max_lds / 2) s.cb = cb;
+  }
+  if (!s.cb) s.cb = 1;
+  const int O = rc.P * rc.Q;
+  s.cb = std::min(s.cb, O);
+  s.groups = (O + s.cb - 1) / s.cb;
+}
+
+// Why the NUFFT forward cannot run (nullptr: it can, and *ns holds its shape for facets
+// within r_max of their centroids, without the chirp chunk, record stride and run bound):
+// every source of a record lies within off_max = 2 r_max kappa cells of the record's
+// path position and every channel within chan_d of the phase-centre path, and a run's
+// window of kNuSlots cells must hold both sides of that reach and at least one cell.
+const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o,
+                             double r_max, double v_max, NuShape *ns) {
+  NuShape s{};
+  if (const char *why = nufft_common(ctx, rc, o, v_max, &s)) return why;
+  s.off_max = 2.0 * r_max * s.kappa;
+  s.b0 = static_cast<int32_t>(std::ceil(s.chan_d + s.off_max + 0.5 * kNuWidth));
+  s.kspan = kNuSlots - 2 - 2 * s.b0;
+  if (s.kspan < 0)
+    return "facets or array aperture too wide for the NUFFT window: node offsets (2 r_max "
+           "df n_g / c) plus channel offsets exceed 9 grid cells";
+  *ns = s;
+  return nullptr;
+}
+
+// Why the NUFFT adjoint cannot run; *ns: its shape (Taylor order and split level).
+const char *nufft_adj_ineligible(const rsim_ctx *ctx, const RadarConst &rc, double r_max,
+                                 NuShape *ns) {
+  rsim_opts o{};
+  o.precision = RSIM_FP32_PHASE64;
+  NuShape s{};
+  if (const char *why = nufft_common(ctx, rc, o, 0.0, &s)) return why;
+  // facets spanning more than 1.5 grid cells are split into 4^split midpoint
+  // sub-triangles (halving the span per level), at most 64
+  double spread = 2.0 * r_max * s.kappa;
+  int split = 0;
+  while (spread > kNuMaxSpread && split < kNuMaxSplit) {
+    spread *= 0.5;
+    ++split;
+  }
+  if (spread > kNuMaxSpread) return "facets span more than 12 NUFFT grid cells";
+  if (2.0 * s.chan_d > 20 - kNuWidth - 3) return "array aperture too wide for the NUFFT adjoint";
+  s.order = spread <= 0.35 ? 5 : spread <= 0.8 ? 7 : 10;
+  s.split = split;
+  nufft_fft_groups(ctx, rc, s, 0);
+  *ns = s;
+  return nullptr;
+}
+
+// Records per spread run: enough runs to fill the device several times over at the
+// expected ~40% lit facets, 256 .. 1024.
+int nufft_run_len(const rsim_ctx *ctx, int64_t stride, int n_chirps) {
+  const double recs = 0.4 * static_cast<double>(stride) * n_chirps;
+  const double want = recs / (32.0 * std::max(1, ctx->cu_count));
+  int L = 256;
+  while (L < 1024 && 2.0 * L <= want) L *= 2;
+  return L;
+}
+
+int32_t nufft_max_runs(const NuShape &ns, int64_t stride) {
+  const int64_t full = (stride + ns.run_len - 1) / ns.run_len;
+  return static_cast<int32_t>(3 * full + (ns.ng + ns.kspan) / (ns.kspan + 1) + 2);
 }
 
 // Kernel, tiles and shape of one rsim_synthesize call.
@@ -576,7 +626,7 @@ struct SumPlan {
   EchoShape sh{};
   NuShape ns{};         // NUFFT: shape; n_chirps = chirps per launch
   NuBuffers nb{};       // NUFFT: work buffers
-  std::vector<int32_t> nu_split, nu_order;  // NUFFT: per scene of the call
+  std::vector<NuShape> nu_scene;  // NUFFT: per scene of the call (reach, runs, stride)
   const void *tw = nullptr;  // NUFFT: twiddles of the grid length
   int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
 };
@@ -851,17 +901,11 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     if (pl.nufft) {
       // per scene, in chirp chunks that fit the record buffer (batched calls included)
       for (size_t i = 0; i < ds.size(); ++i) {
-        const DevScene &d = ds[i];
-        NuShape ns = pl.ns;
-        ns.split = pl.nu_split[i];
-        ns.order = pl.nu_order[i];
-        ns.rec_stride = (d.n_facets << (2 * ns.split)) + d.n_points;
+        NuShape ns = pl.nu_scene[i];
         for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
           ns.n0 = n0;
           ns.n_chirps = std::min(pl.ns.n_chirps, rc.N - n0);
-          ns.runs = static_cast<int32_t>((ns.rec_stride + nufft_run_length() - 1) /
-                                         nufft_run_length());
-          HIP_TRY(ctx, launch_nufft(d, rc, ctx->d_elem, ns, pl.nb, pl.tw, s));
+          HIP_TRY(ctx, launch_nufft(ds[i], rc, ctx->d_elem, ns, pl.nb, pl.tw, s));
         }
       }
     } else if (bt && pl.matrix) {
@@ -906,14 +950,10 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
       dk.mask = ds[i].mask + static_cast<int64_t>(k) * rc.N * ds[i].mask_words;
       HIP_TRY(ctx, launch_compact(dk, 0, rc.N, s));
       if (pl.nufft) {
-        NuShape ns = pl.ns;
-        ns.split = pl.nu_split[i];
-        ns.order = pl.nu_order[i];
+        NuShape ns = pl.nu_scene[i];
         ns.accumulate = sk.accumulate;
         ns.gamma_re = sk.gamma_re;
         ns.gamma_im = sk.gamma_im;
-        ns.rec_stride = (dk.n_facets << (2 * ns.split)) + dk.n_points;
-        ns.runs = static_cast<int32_t>((ns.rec_stride + nufft_run_length() - 1) / nufft_run_length());
         for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
           ns.n0 = n0;
           ns.n_chirps = std::min(pl.ns.n_chirps, rc.N - n0);
@@ -1315,40 +1355,50 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     // a reallocated buffer invalidates captured graphs
     pl.tw = twiddles(ctx, pl.ns.ng, 0, &rc);
     if (rc) return rc;
-    // split level and Taylor order per scene (from its own meshes); the buffers hold the
-    // largest scene at the largest record
-    int64_t stride = 0;
-    size_t rec_b = 0;
-    pl.nu_split.clear();
-    pl.nu_order.clear();
+    // reach, run length and run bound per scene (from its own meshes); the buffers hold
+    // the largest scene
+    int64_t stride = 1;
+    int32_t max_runs = 1;
+    const size_t rec_b = nufft_record_bytes(o.intra_chirp != 0);
+    pl.nu_scene.clear();
     for (int32_t id : ids) {
       // eligible, since the call's largest r_max is
       NuShape si{};
       (void)nufft_ineligible(ctx, rcn, o, scenes_rmax(ctx, {id}), v_max, &si);
-      pl.nu_split.push_back(si.split);
-      pl.nu_order.push_back(si.order);
-      stride = std::max<int64_t>(stride, (ctx->scenes[id].n_facets << (2 * si.split)) +
-                                             static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
-      rec_b = std::max(rec_b, nufft_record_bytes(si.order, o.intra_chirp != 0));
+      si.rec_stride = std::max<int64_t>(1, ctx->scenes[id].n_facets +
+                                               static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
+      si.run_len = nufft_run_len(ctx, si.rec_stride, rcn.N);
+      si.max_runs = nufft_max_runs(si, si.rec_stride);
+      stride = std::max(stride, si.rec_stride);
+      max_runs = std::max(max_runs, si.max_runs);
+      pl.nu_scene.push_back(si);
     }
-    stride = std::max<int64_t>(stride, 1);
-    const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q, ng = pl.ns.ng;
+    const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q;
     // the layout only grows while channels, grid and record size stay: calls on
     // smaller scenes reuse it, so captured graphs stay valid
-    if (ctx->nu_layout[2] == O && ctx->nu_layout[3] == ng &&
-        ctx->nu_layout[4] == static_cast<int64_t>(rec_b))
+    if (ctx->nu_layout[2] == O && ctx->nu_layout[3] == pl.ns.ng &&
+        ctx->nu_layout[4] == static_cast<int64_t>(rec_b)) {
       stride = std::max<int64_t>(stride, ctx->nu_layout[0]);
+      max_runs = std::max<int32_t>(max_runs, static_cast<int32_t>(ctx->nu_layout[5]));
+    }
+    nufft_fft_groups(ctx, rcn, pl.ns, sizeof(int32_t) * max_runs);
+    for (NuShape &si : pl.nu_scene) {
+      si.cb = pl.ns.cb;
+      si.groups = pl.ns.groups;
+    }
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t per_chirp = stride * (rec_b + 8) + O * ng * 8;
+    const size_t part_b = static_cast<size_t>(max_runs) * O * kNuSlots * sizeof(float2);
+    const size_t per_chirp = stride * (rec_b + 8) + max_runs * sizeof(int4) + 4 + part_b;
     int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
     if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
     const size_t off_pos = al(chunk * stride * 4);
     const size_t off_srec = off_pos + al(chunk * stride * 4);
-    const size_t off_range = off_srec + al(chunk * stride * rec_b);
-    const size_t off_grid = off_range + al(chunk * sizeof(int2));
-    const size_t total = off_grid + chunk * O * ng * 8;
-    const std::array<int64_t, 5> layout{stride, chunk, O, ng, static_cast<int64_t>(rec_b)};
-    bool clear = layout != ctx->nu_layout;
+    const size_t off_runs = off_srec + al(chunk * stride * rec_b);
+    const size_t off_nruns = off_runs + al(chunk * max_runs * sizeof(int4));
+    const size_t off_part = off_nruns + al(chunk * 4);
+    const size_t total = off_part + chunk * part_b;
+    const std::array<int64_t, 6> layout{stride, chunk, O, pl.ns.ng, static_cast<int64_t>(rec_b),
+                                        max_runs};
     if (ctx->nu_buf_bytes < total) {
       HIP_TRY(ctx, hipDeviceSynchronize());  // earlier launches may still use the buffer
       dev_free(ctx, ctx->nu_buf);
@@ -1357,24 +1407,23 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       ctx->nu_layout = {};
       if ((rc = dev_alloc(ctx, &ctx->nu_buf, total))) return rc;
       ctx->nu_buf_bytes = total;
-      clear = true;
+    }
+    if (layout != ctx->nu_layout) {
+      ctx->nu_layout = layout;
+      ctx->version++;  // captured graphs hold the old layout
     }
     char *b = static_cast<char *>(ctx->nu_buf);
     pl.nb = NuBuffers{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
-                      b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b, nullptr,
-                      reinterpret_cast<int2 *>(b + off_range)};
+                      b + off_srec, reinterpret_cast<float2 *>(b + off_part), rec_b, nullptr,
+                      reinterpret_cast<int4 *>(b + off_runs), reinterpret_cast<int32_t *>(b + off_nruns)};
     pl.ns.n_chirps = static_cast<int32_t>(chunk);
-    if (clear) {
-      // the kernels leave the grids zero; a new layout starts from zero (on the
-      // caller's stream, ahead of any launch or graph replay of this call)
-      hipStream_t s0 = static_cast<hipStream_t>(hip_stream);
-      HIP_TRY(ctx, launch_fill_zero(reinterpret_cast<float *>(pl.nb.grid), chunk * O * ng * 2, s0));
-      ctx->nu_layout = layout;
-      ctx->version++;  // captured graphs hold the old pointers
-    }
+    pl.ns.max_runs = max_runs;
+    if (nufft_sort_smem_bytes(pl.ns) > ctx->max_lds)
+      return fail(ctx, RSIM_ERANGE, "NUFFT sort needs %zu bytes of LDS (max %zu)",
+                  nufft_sort_smem_bytes(pl.ns), ctx->max_lds);
   }
   const EchoShape sh = pl.sh;
-  const size_t lds = pl.nufft    ? nufft_smem_bytes(pl.ns)
+  const size_t lds = pl.nufft    ? nufft_fft_smem_bytes(pl.ns)
                      : pl.matrix ? mfma_smem_bytes(sh)
                                  : echo_smem_bytes(o.precision, ts.mb, ts.ft, sh);
   if (lds > ctx->max_lds)
@@ -1447,7 +1496,7 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   d.n_points = 0;  // points carry no parameters
   const int64_t F = d.n_facets, N = rcn.N, O = static_cast<int64_t>(rcn.P) * rcn.Q;
   const int64_t stride = std::max<int64_t>(1, F << (2 * ns.split));
-  const size_t rec_b = nufft_record_bytes(ns.order, false), der_b = nufft_der_bytes(ns.order);
+  const size_t rec_b = nufft_adj_record_bytes(ns.order), der_b = nufft_der_bytes(ns.order);
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t per_chirp = stride * (rec_b + der_b) + O * ns.ng * 8;
   int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
@@ -1472,7 +1521,6 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   if (rc) return rc;
   HIP_TRY(ctx, launch_fill_zero(ctx->adj_partial, N * F * kAdjSlotFloats, s));
   ns.rec_stride = stride;
-  ns.runs = static_cast<int32_t>((stride + nufft_run_length() - 1) / nufft_run_length());
   for (int64_t n0 = 0; n0 < N; n0 += chunk) {
     ns.n0 = static_cast<int32_t>(n0);
     ns.n_chirps = static_cast<int32_t>(std::min<int64_t>(chunk, N - n0));
@@ -1508,9 +1556,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   NuShape nsb{};
   bool nufft = false;
   if (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO) {
-    rsim_opts ob{};
-    ob.precision = RSIM_FP32_PHASE64;
-    const char *nwhy = nufft_ineligible(ctx, rcn, ob, scenes_rmax(ctx, {scene_id}), 0.0, &nsb);
+    const char *nwhy = nufft_adj_ineligible(ctx, rcn, scenes_rmax(ctx, {scene_id}), &nsb);
     if (nwhy && ctx->bwd_kernel == RSIM_KERNEL_NUFFT)
       return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
     nufft = !nwhy;

@@ -1,6 +1,6 @@
-// Facet sum as a type-1 non-uniform FFT over the sample index (stop-and-hop, FP32 with
-// FP64 geometry and phases). Same result as the direct sum of Sections 2.2 and 3.2,
-// eqs. (7)-(13), within the spread kernel's error.
+// Facet sum as a type-1 non-uniform FFT over the sample index (FP32 with FP64 geometry and
+// phases). Same result as the direct sum of Sections 2.2 and 3.2, eqs. (7)-(13), within
+// the spread's error (~1e-6 relative).
 //
 // With the closed-form facet integral written as a divided difference, the term of a
 // lit facet (or point) for channel (p, q) at sample m = m' + M/2 is
@@ -9,18 +9,31 @@
 // with L = R_t + R_r, tau = L / c, f_c = f0 + (M/2) df, k = 2 pi f / c, dk = 2 pi df / c
 // and DD2 the second divided difference over the facet's node offsets beta_v. For every
 // channel the sum over facets is therefore a type-1 transform of sources at path lengths
-// L - beta onto the modes m'. Each source set is spread onto a periodic grid of n_g >= 2M
-// cells with a Gaussian psi(x) = exp(-x^2 / (2 s^2)); the grid position of path length L
-// is x = kappa L with kappa = df n_g / c cells per metre. Expanding psi(l - x_L + kappa
-// beta) in beta turns the facet's spread into
-//   Q(p, q) psi(l - x_L) sum_k b_k (l - x_L)^k,
-//   b_k = -amp / (k_c^2 s^k) sum_{r >= k} D_r (-kappa / s)^r / r! He_{r,k},
-//   D_r = DD2[beta^r exp(j k_c beta)] (Leibniz rule over the stable divided
-//         differences of exp(j k_c beta); He_{r,k} the coefficients of He_r(y)),
+// L - beta onto the modes m'. Each is spread onto a periodic grid of n_g >= 2M cells with
+// a Gaussian psi(x) = exp(-x^2 / (2 s^2)); the grid position of path length L is
+// x = kappa L with kappa = df n_g / c cells per metre, and the facet's spread is
+//   Q(p, q) F(l - x_L),  F(u) = (-amp / k_c^2) DD2_beta[ exp(j k_c beta) psi(u + kappa beta) ],
 // where only Q = exp(-j 2 pi (f_c tau - mu tau^2/2)) / (R_t R_r) and x_L depend on the
 // channel. A forward FFT of each channel's grid then gives
 //   H(m' + M/2) = U(m') k_c^2 / (k_m^2 psi_hat(2 pi m' / n_g)),
 //   psi_hat(w) = s sqrt(2 pi) exp(-s^2 w^2 / 2).
+//
+// F is written as at most three grid sources, chosen by the gaps between the nodes
+// a_v = k_c beta_v (radians; threshold kNuGapMin):
+//   all gaps wide: the vertex form of the divided difference, three Gaussians at
+//     -kappa beta_v with weights exp(j k_c beta_v) / prod_{w != v} (beta_v - beta_w);
+//   one close pair (beta_0, beta_1) and a far node beta_2: from
+//     DD2 = h(beta_2) / ((beta_2 - beta_1)(beta_2 - beta_0))
+//           - [h(beta_1) / (beta_2 - beta_1) + DD1 h(beta_0, beta_1)] / (beta_2 - beta_0),
+//     a Gaussian at the far node and a Gaussian-weighted quadratic about the pair's
+//     midpoint mu (psi expanded in kappa (beta - mu), three terms, with DD1 of
+//     (beta - mu)^r exp(j k_c beta) in closed form);
+//   all gaps narrow (the facet spans under kNuGapMin / k_c along its direction of
+//     incidence, e.g. near the specular direction, and points): psi expanded about the
+//     centroid, three terms, with D_r = DD2[beta^r exp(j k_c beta)] by the Leibniz rule
+//     over the stable divided differences of exp(j k_c beta).
+// No source needs splitting: the weights stay bounded because every divided difference
+// is taken over nodes at least kNuGapMin apart or expanded.
 //
 // Channel (p, q) differs from the phase-centre path (centres t_c, r_c of the Tx and Rx
 // elements) only through dL = (R_tp - R_tc) + (R_rq - R_rc), a few centimetres. With
@@ -33,20 +46,20 @@
 //   f_c tau - mu tau^2 / 2 = [same at tau_c] + dL g1 - mu dL^2 / (2 c^2),
 //   g1 = (f_c - mu tau_c) / c.
 //
-// Five kernels per chunk of chirps:
+// Five kernels per chunk of chirps, all in a fixed order of operations, so that a call
+// gives the same bits every time and whatever other scenes share it:
 //   key     per (chirp, lit facet or point): grid cell of the phase-centre path;
-//   count   per chirp: counting sort by cell in LDS, giving each entry its position in
-//           cell order (order within a cell is that of the LDS counter, so sums are
-//           reproducible to FP32 rounding only);
-//   prep    per entry: b_k and the phase-centre path (FP64 work, stored as FP32
-//           offsets, reduced phase and grid cell), written at the sorted position;
-//   spread  one wave per (chirp, 64 channels, run of kNuSeg sorted records): each lane
-//           (channel) accumulates a window of kNuSlots cells in registers, with Gaussian
-//           weights from a product recurrence, and adds it to the global grid
-//           [chirp][channel][n_g] only when the sorted positions leave the window (and at
-//           the end of the run);
-//   fft     per (chirp, group of channels): grid rows into LDS (rows zeroed behind),
-//           in-LDS Stockham FFT, deconvolution, echo samples.
+//   sort    per chirp: a stable counting sort by cell (entries keep their order within a
+//           cell), and the chirp's runs: consecutive sorted records over at most
+//           kspan + 1 cells and run_len records, so that every source of a run lands in
+//           one window of kNuSlots cells;
+//   prep    per entry: the sources and the phase-centre path (FP64 work, stored as FP32
+//           offsets, weights, reduced phase and grid cell), written at the sorted position;
+//   spread  one workgroup per (chirp, run), one wave per 64 channels: each lane
+//           accumulates the run's sources in a register window of kNuSlots cells and
+//           writes it out once (no atomics);
+//   fft     per (chirp, group of channels): every grid cell summed from the windows that
+//           cover it in run order, in-LDS Stockham FFT, deconvolution, echo samples.
 #include <type_traits>
 
 #include "adjoint_common.h"
@@ -57,38 +70,50 @@ namespace rsim {
 
 constexpr int kNuFftThreads = 512;
 constexpr int kNuMaxOrder = 10;
-constexpr int kNuSeg = 256;    // sorted records per spread wave
-constexpr int kNuSlots = 20;   // register window of grid cells per lane
-constexpr int kNuSpreadThreads = 256;
+constexpr int kNuSortThreads = 1024;  // 16 waves: each ranks one sixteenth of a chirp's entries
+constexpr int kNuSortWaves = kNuSortThreads / 64;
 constexpr int kNuGatherRecs = 256;  // records (lanes) per adjoint gather workgroup
 constexpr int kXcds = 8;            // accelerator complex dies: workgroups go round-robin
+constexpr double kNuGapMin = 2.0;   // radians of k_c beta between nodes of a divided difference
 
-template <int R>
-struct alignas(16) NuRec {
+// Forward record of one lit facet or point of one chirp (128 bytes; 144 with the delay
+// within the chirp). Sources sit at grid position (the channel's path position - offset):
+//   kind 1: three Gaussians, (offset, weight re, weight im) at s[3j .. 3j + 2], j < 3;
+//   kind 2: one Gaussian at s[0 .. 2] and a Gaussian-weighted quadratic at s[3 .. 9]
+//           (offset, c0, c1, c2 as re/im pairs, in powers of the cell distance);
+//   kind 3: a Gaussian-weighted quadratic at s[3 .. 9];
+//   kind 0: no contribution (zero-area facet).
+// ext (with the delay within the chirp): velocity (3), its components along ut and ur,
+// and the phase-centre path's Doppler shift of the source in cells (included in cell and
+// frac).
+template <bool INTRA>
+struct alignas(16) NuRecF {
   double ut[3], ur[3];  // unit vectors from t_c and r_c to the centroid c at t_n
   double g1;            // (f_c - mu tau_c) / c: turns per metre of dL
   float rt, rr;         // |c - t_c|, |c - r_c|
   float t0;             // f_c tau_c - mu tau_c^2 / 2 reduced to [-1/2, 1/2] turns
   float frac;           // grid position of the phase-centre path minus `cell`
   int32_t cell;         // its grid cell (0 .. n_g - 1)
-  int32_t valid;
-  float2 b[R];          // polynomial coefficients in grid cells (see the header comment)
+  int32_t kind;
+  float s[10];
+  float ext[INTRA ? 6 : 2];
 };
-// with the delay within the chirp: velocity, its components along ut and ur, and the
-// phase-centre path's Doppler shift of the source (cells; included in cell and frac)
+static_assert(sizeof(NuRecF<false>) == 128 && sizeof(NuRecF<true>) == 144, "record size");
+
+// Adjoint record (Taylor form about the centroid, facets split into 4^split midpoint
+// sub-triangles where they span more than 1.5 grid cells).
 template <int R>
-struct alignas(16) NuRecIntra : NuRec<R> {
-  float v[3];
-  float vut, vur;
-  float dxc;
+struct alignas(16) NuRec {
+  double ut[3], ur[3];
+  double g1;
+  float rt, rr;
+  float t0;
+  float frac;
+  int32_t cell;
+  int32_t valid;
+  float2 b[R];  // polynomial coefficients in grid cells
 };
-template <int R, bool INTRA>
-using NuRecT = typename std::conditional<INTRA, NuRecIntra<R>, NuRec<R>>::type;
 static_assert(sizeof(NuRec<5>) == 128 && sizeof(NuRec<7>) == 144 && sizeof(NuRec<10>) == 160,
-              "record size");
-// (the derived record reuses the base's tail padding: float2 is not plain old data)
-static_assert(sizeof(NuRecIntra<5>) == 144 && sizeof(NuRecIntra<7>) == 160 &&
-                  sizeof(NuRecIntra<10>) == 192,
               "record size");
 
 // Adjoint record: derivatives of the Taylor coefficients and of the source position with
@@ -107,17 +132,12 @@ constexpr double kNuDerStep = 1e-6;  // metres: central differences of b_k in be
 size_t nufft_der_bytes(int order) {
   return order <= 5 ? sizeof(NuDer<5>) : order <= 7 ? sizeof(NuDer<7>) : sizeof(NuDer<10>);
 }
-
-template <bool INTRA>
-static size_t record_bytes_t(int order) {
-  return order <= 5 ? sizeof(NuRecT<5, INTRA>)
-                    : order <= 7 ? sizeof(NuRecT<7, INTRA>) : sizeof(NuRecT<10, INTRA>);
+size_t nufft_adj_record_bytes(int order) {
+  return order <= 5 ? sizeof(NuRec<5>) : order <= 7 ? sizeof(NuRec<7>) : sizeof(NuRec<10>);
 }
-size_t nufft_record_bytes(int order, bool intra) {
-  return intra ? record_bytes_t<true>(order) : record_bytes_t<false>(order);
+size_t nufft_record_bytes(bool intra) {
+  return intra ? sizeof(NuRecF<true>) : sizeof(NuRecF<false>);
 }
-int nufft_window_cells() { return kNuSlots; }
-int nufft_run_length() { return kNuSeg; }
 
 // Probabilists' Hermite polynomials He_r(y) = sum_k kHe.c[r][k] y^k, from
 // He_{r+1} = y He_r - r He_{r-1}.
@@ -140,9 +160,6 @@ __device__ inline int wrap_cell(int64_t c, int ng) {
   return static_cast<int>(r < 0 ? r + ng : r);
 }
 
-// Grid position and cell (0 .. n_g - 1) of a source on the phase-centre path of an entry,
-// shifted by the node offset bc of a sub-triangle's centroid (x = kappa (L - bc)), and the
-// two distances of that path; FP64.
 // With the delay taken at each sample time (rc.intra), the path's delay grows by
 // tau' m / fs over the chirp (tau' = d tau / dt, first order; the second-order term is
 // below 1e-7 of a turn here), which adds A m + B m^2 turns to its phase with
@@ -161,6 +178,9 @@ __device__ inline double doppler_cells(const Geo &g, const RadarConst &rc, const
   return (A + B * rc.M) * ns.ng;
 }
 
+// Grid position and cell (0 .. n_g - 1) of a source on the phase-centre path of an entry,
+// shifted by the node offset bc of a sub-triangle's centroid (x = kappa (L - bc)), and the
+// two distances of that path; FP64.
 __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuShape &ns,
                                    double bc, double *x_out, int *cell_out, double *Rt,
                                    double *Rr, double *dxc) {
@@ -178,16 +198,11 @@ __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuS
   *cell_out = wrap_cell(static_cast<int64_t>(floor(x)), ns.ng);
 }
 
-// Record `rec` of a chirp with `cnt` lit facets: facet records first (4^split per lit
-// facet), then one per point. Returns the entry (lit facet or point) and the sub-triangle.
-__device__ inline int32_t record_entry(int32_t rec, int32_t cnt, int split, int *sub) {
-  const int32_t subs = 1 << (2 * split);
-  if (rec < cnt * subs) {
-    *sub = rec & (subs - 1);
-    return rec >> (2 * split);
-  }
-  *sub = -1;  // a point: not split
-  return cnt + (rec - cnt * subs);
+// Adjoint record `rec` of a chirp with `cnt` lit facets: 4^split records per lit facet.
+// Returns the lit entry and the sub-triangle.
+__device__ inline int32_t record_entry(int32_t rec, int split, int *sub) {
+  *sub = rec & ((1 << (2 * split)) - 1);
+  return rec >> (2 * split);
 }
 
 // Node offsets of sub-triangle `sub` (base-4 digits, most significant first; each digit
@@ -221,18 +236,19 @@ __device__ inline double sub_nodes(const double beta[3], int sub, int split, dou
   return c;
 }
 
-// Taylor coefficients b_k (FP64) of one record: the facet with node offsets beta_f about
-// its centroid, or its sub-triangle `sub` (own nodes about the sub-centroid, 4^-split of the
-// area, the factor exp(j k_c bc)). Returns bc, the sub-centroid's offset (0 unsplit).
+// Taylor coefficients b_k (FP64) of psi expanded about the centroid: the facet with node
+// offsets beta_f about its centroid, or its sub-triangle `sub` (own nodes about the
+// sub-centroid, 4^-split of the area, the factor exp(j k_c bc)). b_k includes the common
+// factor -amp / k_c^2. Returns bc, the sub-centroid's offset (0 unsplit).
 template <int R>
-__device__ double taylor_coeffs(const Geo &g, const double beta_f[3], int sub,
+__device__ double taylor_coeffs(const Geo &g, const double beta_f[3], int sub, int split,
                                 const NuShape &ns, double br[R], double bi[R]) {
   double beta[3] = {beta_f[0], beta_f[1], beta_f[2]};
   double bc = 0.0;
   double amp_re = g.amp_re, amp_im = g.amp_im;
-  if (sub >= 0 && ns.split > 0) {
-    bc = sub_nodes(beta_f, sub, ns.split, beta);
-    const double scale = 1.0 / static_cast<double>(1 << (2 * ns.split));
+  if (sub >= 0 && split > 0) {
+    bc = sub_nodes(beta_f, sub, split, beta);
+    const double scale = 1.0 / static_cast<double>(1 << (2 * split));
     double sb, cb;
     const double tb = ns.fc / kC0 * bc;
     sincospi_t(2.0 * (tb - rint(tb)), &sb, &cb);
@@ -308,9 +324,9 @@ __device__ double taylor_coeffs(const Geo &g, const double beta_f[3], int sub,
 
 // The phase-centre path of a record (FP64): unit vectors, distances, reduced phase, the
 // source's grid cell and fraction (the same cell as the key pass).
-template <int R>
+template <typename Rec>
 __device__ void path_fields(const Geo &g, const RadarConst &rc, const NuShape &ns, double bc,
-                            NuRec<R> &out, double *Rt, double *Rr, double *dxc) {
+                            Rec &out, double *Rt, double *Rr, double *dxc) {
   double x;
   int cell;
   centre_cell(g, rc, ns, bc, &x, &cell, Rt, Rr, dxc);
@@ -328,39 +344,124 @@ __device__ void path_fields(const Geo &g, const RadarConst &rc, const NuShape &n
   out.cell = cell;
 }
 
-template <int R, bool INTRA>
+// (x + j y) exp(j 2 pi T) for T in turns (FP64)
+__device__ inline double2 rot_turns(double x, double y, double T) {
+  double s, c;
+  sincospi(2.0 * (T - rint(T)), &s, &c);
+  return make_double2(x * c - y * s, x * s + y * c);
+}
+
+// The grid sources of one lit facet or point (see the header comment): fills s[10] and
+// returns the kind. Weights and coefficients include the common factor -amp / k_c^2.
+__device__ int nufft_sources(const Geo &g, const NuShape &ns, float s[10]) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) s[k] = 0.0f;
+  if (!g.valid) return 0;
+  const double tpm = ns.fc / kC0;  // turns of k_c beta per metre
+  const double ik2 = 1.0 / (ns.kc * ns.kc);
+  const double cr = -g.amp_re * ik2, ci = -g.amp_im * ik2;
+  const double *b = g.beta;
+  const double gap = kNuGapMin / (2.0 * kPi);  // turns
+  // gap opposite node v: between the other two
+  const double d0 = fabs(b[1] - b[2]) * tpm, d1 = fabs(b[0] - b[2]) * tpm,
+               d2 = fabs(b[0] - b[1]) * tpm;
+  const int narrow = (d0 < gap) + (d1 < gap) + (d2 < gap);
+  const double kappa = ns.kappa;
+  if (narrow == 0) {
+    for (int v = 0; v < 3; ++v) {
+      const int a = v == 0 ? 1 : 0, c = v == 2 ? 1 : 2;
+      const double den = (b[v] - b[a]) * (b[v] - b[c]);
+      const double2 w = rot_turns(cr / den, ci / den, tpm * b[v]);
+      s[3 * v] = static_cast<float>(kappa * b[v]);
+      s[3 * v + 1] = static_cast<float>(w.x);
+      s[3 * v + 2] = static_cast<float>(w.y);
+    }
+    return 1;
+  }
+  if (narrow == 1) {
+    // the close pair (p0, p1) and the far node p2
+    const int p2 = d0 < gap ? 0 : d1 < gap ? 1 : 2;
+    const int p0 = p2 == 0 ? 1 : 0, p1 = p2 == 2 ? 1 : 2;
+    const double B0 = b[p0], B1 = b[p1], B2 = b[p2];
+    const double d21 = B2 - B1, d20 = B2 - B0;
+    const double2 wA = rot_turns(cr / (d21 * d20), ci / (d21 * d20), tpm * B2);
+    s[0] = static_cast<float>(kappa * B2);
+    s[1] = static_cast<float>(wA.x);
+    s[2] = static_cast<float>(wA.y);
+    // about mu = (B0 + B1) / 2 with delta = -h, +h at the pair:
+    // V_r = -exp(j k_c h) h^r / (d21 d20) - DD1[delta^r exp(j k_c delta)](-h, h) / d20
+    // with DD1 = j k_c sinc(k_c h), cos(k_c h), j h sin(k_c h) for r = 0, 1, 2
+    const double mu = 0.5 * (B0 + B1), h = 0.5 * (B1 - B0);
+    double sh, ch;
+    sincospi(2.0 * tpm * h, &sh, &ch);  // |k_c h| < kNuGapMin / 2
+    const double kh = ns.kc * h;
+    const double snc = fabs(kh) < 1e-4 ? 1.0 - kh * kh * (1.0 / 6.0) : sh / kh;
+    const double i12 = 1.0 / (d21 * d20), i0 = 1.0 / d20;
+    double vr[3], vi[3];
+    vr[0] = -ch * i12;
+    vi[0] = -sh * i12 - ns.kc * snc * i0;
+    vr[1] = -ch * h * i12 - ch * i0;
+    vi[1] = -sh * h * i12;
+    vr[2] = -ch * h * h * i12;
+    vi[2] = -sh * h * h * i12 - h * sh * i0;
+    // a_r = exp(j k_c mu) (-kappa / s)^r / r! V_r; c0 = a0 - a2, c1 = a1 / s, c2 = a2 / s^2
+    const double st = -kappa / ns.sigma;
+    const double sc[3] = {1.0, st, 0.5 * st * st};
+    double ar[3], ai[3];
+    for (int r = 0; r < 3; ++r) {
+      const double2 v = rot_turns(vr[r] * sc[r], vi[r] * sc[r], tpm * mu);
+      ar[r] = v.x * cr - v.y * ci;  // times -amp / k_c^2
+      ai[r] = v.x * ci + v.y * cr;
+    }
+    const double is = 1.0 / ns.sigma;
+    s[3] = static_cast<float>(kappa * mu);
+    s[4] = static_cast<float>(ar[0] - ar[2]);
+    s[5] = static_cast<float>(ai[0] - ai[2]);
+    s[6] = static_cast<float>(ar[1] * is);
+    s[7] = static_cast<float>(ai[1] * is);
+    s[8] = static_cast<float>(ar[2] * is * is);
+    s[9] = static_cast<float>(ai[2] * is * is);
+    return 2;
+  }
+  double br[3], bi[3];
+  taylor_coeffs<3>(g, g.beta, -1, 0, ns, br, bi);
+  s[3] = 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    s[4 + 2 * k] = static_cast<float>(br[k]);
+    s[5 + 2 * k] = static_cast<float>(bi[k]);
+  }
+  return 3;
+}
+
+template <bool INTRA>
 __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst rc, NuShape ns,
                                                         NuBuffers nb) {
   const int nl = blockIdx.y;
   const int n = ns.n0 + nl;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (item >= (cnt << (2 * ns.split)) + sc.n_points) return;
-  int sub;
-  const int32_t entry = record_entry(item, cnt, ns.split, &sub);
+  if (item >= cnt + sc.n_points) return;
   Geo g;
-  entry_geometry(sc, rc, n, cnt, entry, g);
-  NuRecT<R, INTRA> out;
-  out.valid = g.valid;
-  double br[R], bi[R];
-  const double bc = taylor_coeffs<R>(g, g.beta, sub, ns, br, bi);
-#pragma unroll
-  for (int k = 0; k < R; ++k) out.b[k] = {static_cast<float>(br[k]), static_cast<float>(bi[k])};
+  entry_geometry(sc, rc, n, cnt, item, g);
+  NuRecF<INTRA> out;
+  out.kind = nufft_sources(g, ns, out.s);
   double Rt, Rr, dxc;
-  path_fields(g, rc, ns, bc, out, &Rt, &Rr, &dxc);
+  path_fields(g, rc, ns, 0.0, out, &Rt, &Rr, &dxc);
   if constexpr (INTRA) {
     double vut = 0.0, vur = 0.0;
     for (int k = 0; k < 3; ++k) {
-      out.v[k] = static_cast<float>(g.vel[k]);
+      out.ext[k] = static_cast<float>(g.vel[k]);
       vut += g.vel[k] * (g.c[k] - rc.tx_c[k]) / Rt;
       vur += g.vel[k] * (g.c[k] - rc.rx_c[k]) / Rr;
     }
-    out.vut = static_cast<float>(vut);
-    out.vur = static_cast<float>(vur);
-    out.dxc = static_cast<float>(dxc);
+    out.ext[3] = static_cast<float>(vut);
+    out.ext[4] = static_cast<float>(vur);
+    out.ext[5] = static_cast<float>(dxc);
+  } else {
+    out.ext[0] = out.ext[1] = 0.0f;
   }
   const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
-  static_cast<NuRecT<R, INTRA> *>(nb.srec)[row + nb.pos[row + item]] = out;
+  static_cast<NuRecF<INTRA> *>(nb.srec)[row + nb.pos[row + item]] = out;
 }
 
 __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst rc, NuShape ns,
@@ -369,101 +470,211 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst 
   const int n = ns.n0 + nl;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (item >= (cnt << (2 * ns.split)) + sc.n_points) return;
-  int sub;
-  const int32_t entry = record_entry(item, cnt, ns.split, &sub);
+  if (item >= cnt + sc.n_points) return;
   Geo g;
-  entry_geometry(sc, rc, n, cnt, entry, g);
-  double nodes[3], bc = 0.0;
-  if (sub >= 0 && ns.split > 0) bc = sub_nodes(g.beta, sub, ns.split, nodes);
+  entry_geometry(sc, rc, n, cnt, item, g);
   double x, Rt, Rr, dxc;
   int cell;
-  centre_cell(g, rc, ns, bc, &x, &cell, &Rt, &Rr, &dxc);
+  centre_cell(g, rc, ns, 0.0, &x, &cell, &Rt, &Rr, &dxc);
   nb.key[static_cast<int64_t>(nl) * ns.rec_stride + item] = cell;
 }
 
-// Per chirp: LDS counts per cell (the counter's old value is the rank within the cell),
-// exclusive scan, then position = cell offset + rank.
-__global__ void __launch_bounds__(1024) nufft_count_kernel(DevScene sc, NuShape ns, NuBuffers nb) {
-  __shared__ int32_t s_cnt[2048];
-  __shared__ int32_t s_part[1024];
+// Per chirp: stable counting sort of the entries by cell, and the chirp's runs.
+// Wave w takes the w-th sixteenth of the entries (in entry order): it counts its cells
+// in its own LDS row, the rows become per-wave starting positions (cell offset plus the
+// counts of earlier waves), and each wave then ranks its entries 64 at a time, lanes with
+// the same cell in lane order. Runs are cut by one lane over the occupied cells.
+__global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc, NuShape ns,
+                                                                   NuBuffers nb) {
+  extern __shared__ int32_t sort_smem[];
+  const int ng = ns.ng;
+  int32_t *cnt = sort_smem;                           // [kNuSortWaves][ng]
+  int32_t *cbase = sort_smem + kNuSortWaves * ng;     // [ng + 1]: first record of each cell
+  int32_t *part = cbase + ng + 1;                     // [kNuSortThreads]
   const int nl = blockIdx.x;
   const int n = ns.n0 + nl;
   const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
   const int32_t *key = nb.key + row;
   int32_t *pos = nb.pos + row;
-  const int32_t n_ent = (sc.vis_cnt[n] << (2 * ns.split)) + sc.n_points;
-  __shared__ int32_t s_lo, s_hi;
-  for (int c = threadIdx.x; c < 2048; c += blockDim.x) s_cnt[c] = 0;
-  if (threadIdx.x == 0) {
-    s_lo = ns.ng;
-    s_hi = -1;
+  const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int w = tid >> 6, lane = tid & 63;
+  const int32_t seg = ((n_ent + kNuSortWaves - 1) / kNuSortWaves + 63) & ~63;
+  const int32_t e0 = min(n_ent, w * seg), e1 = min(n_ent, e0 + seg);
+  for (int i = tid; i < kNuSortWaves * ng; i += kNuSortThreads) cnt[i] = 0;
+  __syncthreads();
+  for (int32_t e = e0 + lane; e < e1; e += 64) atomicAdd(&cnt[w * ng + key[e]], 1);
+  __syncthreads();
+  // totals of two cells per thread (n_g <= 2048), exclusive scan over cells, then each
+  // wave's starting position per cell
+  const int c0 = 2 * tid;
+  int32_t t0 = 0, t1 = 0;
+  if (c0 < ng)
+    for (int v = 0; v < kNuSortWaves; ++v) t0 += cnt[v * ng + c0];
+  if (c0 + 1 < ng)
+    for (int v = 0; v < kNuSortWaves; ++v) t1 += cnt[v * ng + c0 + 1];
+  part[tid] = t0 + t1;
+  __syncthreads();
+  for (int off = 1; off < kNuSortThreads; off <<= 1) {
+    const int32_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
   }
-  __syncthreads();
-  for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] = atomicAdd(&s_cnt[key[e]], 1);
-  __syncthreads();
-  // occupied cells, widened by every cell a window flush can reach (channel offsets, the
-  // Gaussian's half width and the fraction): the grid is zero outside; a wrapping interval
-  // becomes the whole row
-  {
-    const int c0 = 2 * threadIdx.x;
-    if (c0 < ns.ng && s_cnt[c0]) { atomicMin(&s_lo, c0); atomicMax(&s_hi, c0); }
-    if (c0 + 1 < ns.ng && s_cnt[c0 + 1]) { atomicMin(&s_lo, c0 + 1); atomicMax(&s_hi, c0 + 1); }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int m = static_cast<int>(ceil(ns.chan_d)) + kNuWidth / 2 + 2;
-    int lo = s_lo - m, hi = s_hi + m;
-    if (s_hi < 0) {
-      lo = 0;
-      hi = -1;
-    } else if (lo < 0 || hi >= ns.ng) {
-      lo = 0;
-      hi = ns.ng - 1;
+  const int32_t base0 = part[tid] - t0 - t1;
+  if (c0 < ng) {
+    cbase[c0] = base0;
+    int32_t at = base0;
+    for (int v = 0; v < kNuSortWaves; ++v) {
+      const int32_t k = cnt[v * ng + c0];
+      cnt[v * ng + c0] = at;
+      at += k;
     }
-    nb.range[nl] = make_int2(lo, hi);
   }
-  __syncthreads();
-  // exclusive scan, two cells per thread (n_g <= 2048)
-  const int c0 = 2 * threadIdx.x;
-  const int32_t h0 = s_cnt[c0], h1 = s_cnt[c0 + 1];
-  s_part[threadIdx.x] = h0 + h1;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int32_t v = threadIdx.x >= static_cast<unsigned>(off) ? s_part[threadIdx.x - off] : 0;
-    __syncthreads();
-    s_part[threadIdx.x] += v;
-    __syncthreads();
+  if (c0 + 1 < ng) {
+    cbase[c0 + 1] = base0 + t0;
+    int32_t at = base0 + t0;
+    for (int v = 0; v < kNuSortWaves; ++v) {
+      const int32_t k = cnt[v * ng + c0 + 1];
+      cnt[v * ng + c0 + 1] = at;
+      at += k;
+    }
   }
-  const int32_t base = s_part[threadIdx.x] - h0 - h1;
-  s_cnt[c0] = base;
-  s_cnt[c0 + 1] = base + h0;
+  if (tid == 0) cbase[ng] = n_ent;
   __syncthreads();
-  for (int32_t e = threadIdx.x; e < n_ent; e += blockDim.x) pos[e] += s_cnt[key[e]];
+  // runs: cut by one lane over the occupied cells (reads cbase only)
+  if (tid == 0) {
+    int4 *runs = nb.runs + static_cast<int64_t>(nl) * ns.max_runs;
+    int nr = 0;
+    int open_cell = 0, open_rb = 0, open_n = 0;
+    auto emit = [&](int rb, int re, int base) {
+      if (nr < ns.max_runs) runs[nr] = make_int4(rb, re, base, 0);
+      ++nr;
+    };
+    for (int c = 0; c < ng; ++c) {
+      int h = cbase[c + 1] - cbase[c];
+      if (!h) continue;
+      int rb = cbase[c];
+      if (open_n > 0 && (c - open_cell > ns.kspan || open_n + h > ns.run_len)) {
+        emit(open_rb, open_rb + open_n, open_cell - ns.b0);
+        open_n = 0;
+      }
+      while (h > 0) {
+        if (open_n == 0) {
+          open_cell = c;
+          open_rb = rb;
+        }
+        const int take = min(h, ns.run_len - open_n);
+        open_n += take;
+        h -= take;
+        rb += take;
+        if (open_n == ns.run_len) {
+          emit(open_rb, open_rb + open_n, open_cell - ns.b0);
+          open_n = 0;
+        }
+      }
+    }
+    if (open_n > 0) emit(open_rb, open_rb + open_n, open_cell - ns.b0);
+    nb.n_runs[nl] = min(nr, ns.max_runs);
+  }
+  // stable ranks: lanes with equal cells are handled together, in lane order
+  for (int32_t chunk = e0; chunk < e1; chunk += 64) {
+    const int32_t e = chunk + lane;
+    const bool valid = e < e1;
+    const int32_t k = valid ? key[e] : -1;
+    uint64_t rem = __ballot(valid);
+    while (rem) {
+      const int leader = __ffsll(static_cast<unsigned long long>(rem)) - 1;
+      const int32_t kl = __shfl(k, leader);
+      const uint64_t m = __ballot(k == kl);
+      const int32_t start = cnt[w * ng + kl];
+      if (k == kl) pos[e] = start + __popcll(m & ((uint64_t(1) << lane) - 1));
+      if (lane == leader) cnt[w * ng + kl] = start + __popcll(m);
+      rem &= ~m;
+    }
+  }
 }
 
-template <int R, bool INTRA>
-__global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
+// Gaussian (from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)) times the
+// weight cw at the cells s_lo .. s_hi of the window.
+__device__ __forceinline__ void spread_point(float2 (&acc)[kNuSlots], float2 cw, float pos,
+                                             int s_lo, int s_hi, float nc, float q_ratio) {
+  const float u0 = static_cast<float>(s_lo) - pos;
+  float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+  float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+#pragma unroll
+  for (int s = 0; s < kNuSlots; ++s) {
+    if (s >= s_lo && s <= s_hi) {
+      acc[s].x = fmaf(gw, cw.x, acc[s].x);
+      acc[s].y = fmaf(gw, cw.y, acc[s].y);
+      gw *= rho;
+      rho *= q_ratio;
+    }
+  }
+}
+
+// Gaussian times the polynomial sum_k c_k (s - pos)^k at the cells s_lo .. s_hi.
+template <int NC>
+__device__ __forceinline__ void spread_poly(float2 (&acc)[kNuSlots], const float2 (&c)[NC],
+                                            float pos, int s_lo, int s_hi, float nc,
+                                            float q_ratio) {
+  const float u0 = static_cast<float>(s_lo) - pos;
+  float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+  float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+#pragma unroll
+  for (int s = 0; s < kNuSlots; ++s) {
+    if (s >= s_lo && s <= s_hi) {
+      const float xx = static_cast<float>(s) - pos;
+      float pr = c[NC - 1].x, pi = c[NC - 1].y;
+#pragma unroll
+      for (int k = NC - 2; k >= 0; --k) {
+        pr = fmaf(pr, xx, c[k].x);
+        pi = fmaf(pi, xx, c[k].y);
+      }
+      acc[s].x = fmaf(gw, pr, acc[s].x);
+      acc[s].y = fmaf(gw, pi, acc[s].y);
+      gw *= rho;
+      rho *= q_ratio;
+    }
+  }
+}
+
+// (1 - j 2 pi B m'^2) on the modes is F + j eps F'' on the grid (F = psi P): coefficient
+// k of the result is c_k + j eps (c_{k-2} / s^4 - (2k + 1) c_k / s^2 + (k+1)(k+2) c_{k+2}).
+template <int NI, int NO>
+__device__ __forceinline__ void intra_coeffs(const float2 (&c)[NI], float2 (&o)[NO], float eps,
+                                             float inv_s2) {
+  const float inv_s4 = inv_s2 * inv_s2;
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const float2 ck = k < NI ? c[k] : make_float2(0.0f, 0.0f);
+    const float2 cm2 = (k >= 2 && k - 2 < NI) ? c[k - 2] : make_float2(0.0f, 0.0f);
+    const float2 cp2 = (k + 2 < NI) ? c[k + 2] : make_float2(0.0f, 0.0f);
+    const float wk = -(2.0f * k + 1.0f) * inv_s2;
+    const float wp = static_cast<float>((k + 1) * (k + 2));
+    const float dx = cm2.x * inv_s4 + wk * ck.x + wp * cp2.x;
+    const float dy = cm2.y * inv_s4 + wk * ck.y + wp * cp2.y;
+    o[k] = {ck.x - eps * dy, ck.y + eps * dx};
+  }
+}
+
+// One workgroup per (chirp, run) and up to four 64-channel groups (blockIdx.z counts
+// further groups); lane = channel. The run's records (read once per wave through scalar
+// loads) add their sources into a register window of kNuSlots cells starting at the
+// run's base cell; the window is written to part[chirp][run][channel][kNuSlots].
+template <bool INTRA>
+__global__ void __launch_bounds__(256) nufft_spread_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,
-    const NuRecT<R, INTRA> *__restrict__ sorted, float2 *__restrict__ grids) {
-  const int wave = __builtin_amdgcn_readfirstlane(
-      static_cast<int>(blockIdx.x) * (kNuSpreadThreads / 64) + static_cast<int>(threadIdx.x >> 6));
+    const NuRecF<INTRA> *__restrict__ sorted, const int4 *__restrict__ runs,
+    const int32_t *__restrict__ n_runs, float2 *__restrict__ part) {
+  const int nl = blockIdx.y;
+  const int run = blockIdx.x;
+  if (run >= load_uniform(n_runs + nl)) return;  // whole workgroup
+  const int grp = static_cast<int>(blockIdx.z) * 4 + static_cast<int>(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // item = (chirp, channel group, run); the runs of a chirp are consecutive
-  const int runs = ns.runs;
-  const int per_chirp = ns.spread_groups * runs;
-  const int nl = wave / per_chirp;
-  if (nl >= ns.n_chirps) return;
-  const int rem = wave - nl * per_chirp;
-  const int grp = rem / runs;
-  const int run = rem - grp * runs;
-  const int n = ns.n0 + nl;
-  const int32_t n_ent = (sc.vis_cnt[n] << (2 * ns.split)) + sc.n_points;
-  const int e_begin = run * kNuSeg;
-  if (e_begin >= n_ent) return;
-  const int e_end = min(n_ent, e_begin + kNuSeg);
-  const int ng = ns.ng;
   const int O = rc.P * rc.Q;
+  if (grp * 64 >= O) return;  // whole wave
+  const int4 rr = load_uniform(runs + static_cast<int64_t>(nl) * ns.max_runs + run);
   const int o = grp * 64 + lane;
   const bool on = o < O;
   // this lane's element offsets from the phase centres
@@ -492,148 +703,119 @@ __global__ void __launch_bounds__(kNuSpreadThreads) nufft_spread_kernel(
   const float ngf = static_cast<float>(ns.ng);
   const float eps_scale = static_cast<float>(static_cast<double>(ns.ng) * ns.ng / (2.0 * kPi));
   const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
-  const float inv_s4 = inv_s2 * inv_s2;
-  const NuRecT<R, INTRA> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
-  float2 *grid = grids + (static_cast<int64_t>(nl) * O + (on ? o : 0)) * ng;
+  const NuRecF<INTRA> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
   const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
   const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
   const float kappa = static_cast<float>(ns.kappa);
   const float g2 = static_cast<float>(0.5 * rc.slope / (kC0 * kC0));
-  const float d = static_cast<float>(ns.chan_d);
-  const int b0 = static_cast<int>(ceilf(d + 0.5f * kNuWidth));  // key offset after a rebase
-  const float rel_hi = static_cast<float>(kNuSlots - 1) - d - 0.5f * kNuWidth;
+  const float reach = static_cast<float>(ns.chan_d) + 0.5f * kNuWidth;
   float2 acc[kNuSlots];
 #pragma unroll
   for (int s = 0; s < kNuSlots; ++s) acc[s] = {0.0f, 0.0f};
-  // windows: the records that fit one placement of the register window, then a flush;
-  // invalid records carry zero coefficients and need no test
-  int i = e_begin;
-  NuRecT<R, INTRA> nxt = load_uniform(srec + i);
-  while (i < e_end) {
-    const int base = nxt.cell - b0;  // wave-uniform
-    int used_lo = kNuSlots, used_hi = -1;
-    const int first = i;
-    for (; i < e_end; ++i) {
-      const NuRecT<R, INTRA> r = nxt;
-      // window position of the phase-centre path (wrapped cell difference + fraction);
-      // the record that placed the window always fits it (chan_d <= 2.5 cells), and is
-      // taken regardless so that every window makes progress
-      int rk = r.cell - base;
-      if (rk > ng / 2) rk -= ng;
-      if (rk < -ng / 2) rk += ng;
-      const float rel_c = static_cast<float>(rk) + r.frac;
-      if (i > first && (rel_c < d + 0.5f * kNuWidth || rel_c > rel_hi)) break;
-      if (i + 1 < e_end) nxt = load_uniform(srec + i + 1);
-      // cells some channel reaches: |s - x_o| <= W/2 with |x_o - rel_c| <= d
-      const int s_lo =
-          __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - d - 0.5f * kNuWidth)));
-      const int s_hi =
-          __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c + d + 0.5f * kNuWidth)));
-      used_lo = min(used_lo, s_lo);
-      used_hi = max(used_hi, s_hi);
-      // this channel's path difference dL = -(s_t + s_r) + e_t + e_r, amplitude, phase
-      // and grid position
-      const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
-      const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
-      const double ps = (st + sr) * r.g1;  // turns, up to ~25
-      const float pr = static_cast<float>(ps - rint(ps));
-      const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
-      const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
-      const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
-      const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
-      const float qt = ht * rdt, qr = hr * rdr;
-      const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
-      const float dRt = et - sft, dRr = er - sfr;
-      const float dL = dRt + dRr;
-      float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
-      float xr = fmaf(kappa, dL, rel_c);
-      float eps = 0.0f;  // B n_g^2 / (2 pi): weight of F'' for the B m'^2 term
-      if constexpr (INTRA) {
-        // this channel's tau' (first order in the sample time), its Doppler shift relative
-        // to the record's and the constant phase A M/2 + B M^2/4
-        const float vat = r.v[0] * atf[0] + r.v[1] * atf[1] + r.v[2] * atf[2];
-        const float var = r.v[0] * arf[0] + r.v[1] * arf[1] + r.v[2] * arf[2];
-        const float rdt_dot = fmaf(r.rt, r.vut, -vat) * __builtin_amdgcn_rcpf(r.rt + dRt);
-        const float rdr_dot = fmaf(r.rr, r.vur, -var) * __builtin_amdgcn_rcpf(r.rr + dRr);
-        const float tdot = (rdt_dot + rdr_dot) * inv_c0;
-        const float fmt = static_cast<float>(r.g1 * kC0 - (rc.M / 2) * rc.df);
-        const float A = fmt * tdot * inv_fs, B = df_fs * tdot;
-        t += fmaf(A, half_m, B * quarter_m2);
-        xr += fmaf(B, m_f, A) * ngf - r.dxc;
-        eps = B * eps_scale;
-      }
-      t -= rintf(t);
-      const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
-      const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
-      constexpr int NC = INTRA ? R + 2 : R;  // the B m'^2 term raises the degree by two
-      float2 cq[NC];
+  for (int i = rr.x; i < rr.y; ++i) {
+    const NuRecF<INTRA> r = load_uniform(srec + i);
+    if (r.kind == 0) continue;  // wave-uniform
+    // position of the phase-centre path in the window
+    const float rel_c = static_cast<float>(r.cell - rr.z) + r.frac;
+    // this channel's path difference dL = -(s_t + s_r) + e_t + e_r, amplitude, phase
+    // and grid position
+    const double st = r.ut[0] * at[0] + r.ut[1] * at[1] + r.ut[2] * at[2];
+    const double sr = r.ur[0] * ar[0] + r.ur[1] * ar[1] + r.ur[2] * ar[2];
+    const double ps = (st + sr) * r.g1;  // turns, up to ~25
+    const float pr = static_cast<float>(ps - rint(ps));
+    const float sft = static_cast<float>(st), sfr = static_cast<float>(sr);
+    const float ht = fmaf(-sft, sft, aat), hr = fmaf(-sfr, sfr, aar);
+    const float rdt = __builtin_amdgcn_rcpf(fmaf(-2.0f, sft, 2.0f * r.rt));
+    const float rdr = __builtin_amdgcn_rcpf(fmaf(-2.0f, sfr, 2.0f * r.rr));
+    const float qt = ht * rdt, qr = hr * rdr;
+    const float et = qt * fmaf(-qt, rdt, 1.0f), er = qr * fmaf(-qr, rdr, 1.0f);
+    const float dRt = et - sft, dRr = er - sfr;
+    const float dL = dRt + dRr;
+    float t = (r.t0 - pr) + fmaf(static_cast<float>(r.g1), et + er, -g2 * dL * dL);
+    float xr = fmaf(kappa, dL, rel_c);
+    float eps = 0.0f;  // B n_g^2 / (2 pi): weight of F'' for the B m'^2 term
+    if constexpr (INTRA) {
+      // this channel's tau' (first order in the sample time), its Doppler shift relative
+      // to the record's and the constant phase A M/2 + B M^2/4
+      const float vat = r.ext[0] * atf[0] + r.ext[1] * atf[1] + r.ext[2] * atf[2];
+      const float var = r.ext[0] * arf[0] + r.ext[1] * arf[1] + r.ext[2] * arf[2];
+      const float rdt_dot = fmaf(r.rt, r.ext[3], -vat) * __builtin_amdgcn_rcpf(r.rt + dRt);
+      const float rdr_dot = fmaf(r.rr, r.ext[4], -var) * __builtin_amdgcn_rcpf(r.rr + dRr);
+      const float tdot = (rdt_dot + rdr_dot) * inv_c0;
+      const float fmt = static_cast<float>(r.g1 * kC0 - (rc.M / 2) * rc.df);
+      const float A = fmt * tdot * inv_fs, B = df_fs * tdot;
+      t += fmaf(A, half_m, B * quarter_m2);
+      xr += fmaf(B, m_f, A) * ngf - r.ext[5];
+      eps = B * eps_scale;
+    }
+    t -= rintf(t);
+    const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
+    const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
+    const int n_pts = r.kind == 1 ? 3 : r.kind == 2 ? 1 : 0;
 #pragma unroll
-      for (int k = 0; k < R; ++k)
-        cq[k] = {qx * r.b[k].x - qy * r.b[k].y, qx * r.b[k].y + qy * r.b[k].x};
-      if (INTRA) {
-        // (1 - j 2 pi B m'^2) on the modes is F + j eps F'' on the grid, F = psi P, with
-        // F'' = psi (P'' - (2u / s^2) P' + (u^2 / s^4 - 1 / s^2) P): coefficient k of the
-        // result is c_k + j eps (c_{k-2} / s^4 - (2k + 1) c_k / s^2 + (k + 1)(k + 2) c_{k+2})
-        float2 c[NC];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          const float2 ck = k < R ? cq[k] : make_float2(0.0f, 0.0f);
-          const float2 cm2 = (k >= 2 && k - 2 < R) ? cq[k - 2] : make_float2(0.0f, 0.0f);
-          const float2 cp2 = (k + 2 < R) ? cq[k + 2] : make_float2(0.0f, 0.0f);
-          const float wk = -(2.0f * k + 1.0f) * inv_s2;
-          const float wp = static_cast<float>((k + 1) * (k + 2));
-          const float dx = cm2.x * inv_s4 + wk * ck.x + wp * cp2.x;
-          const float dy = cm2.y * inv_s4 + wk * ck.y + wp * cp2.y;
-          c[k] = {ck.x - eps * dy, ck.y + eps * dx};
-        }
-#pragma unroll
-        for (int k = 0; k < NC; ++k) cq[k] = c[k];
-      }
-      // Gaussian weights from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)
-      const float u0 = static_cast<float>(s_lo) - xr;
-      float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
-      float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
-#pragma unroll
-      for (int s = 0; s < kNuSlots; ++s) {
-        if (s >= s_lo && s <= s_hi) {
-          const float xx = static_cast<float>(s) - xr;
-          float pr2 = cq[NC - 1].x, pi2 = cq[NC - 1].y;
-#pragma unroll
-          for (int k = NC - 2; k >= 0; --k) {
-            pr2 = fmaf(pr2, xx, cq[k].x);
-            pi2 = fmaf(pi2, xx, cq[k].y);
-          }
-          acc[s].x = fmaf(gw, pr2, acc[s].x);
-          acc[s].y = fmaf(gw, pi2, acc[s].y);
-          gw *= rho;
-          rho *= q_ratio;
+    for (int j = 0; j < 3; ++j) {
+      if (j < n_pts) {
+        const float off = r.s[3 * j];
+        const float2 cw = {qx * r.s[3 * j + 1] - qy * r.s[3 * j + 2],
+                           qx * r.s[3 * j + 2] + qy * r.s[3 * j + 1]};
+        // cells some channel reaches: |s - x_o| <= W/2 with |x_o - (rel_c - off)| <= d
+        const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - off - reach)));
+        const int s_hi = __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c - off + reach)));
+        if constexpr (INTRA) {
+          const float2 c1[1] = {cw};
+          float2 c3[3];
+          intra_coeffs(c1, c3, eps, inv_s2);
+          spread_poly<3>(acc, c3, xr - off, s_lo, s_hi, nc, q_ratio);
+        } else {
+          spread_point(acc, cw, xr - off, s_lo, s_hi, nc, q_ratio);
         }
       }
     }
-    // add the window to the grid row and clear it
+    if (r.kind >= 2) {
+      const float off = r.s[3];
+      float2 cq[3];
 #pragma unroll
-    for (int s = 0; s < kNuSlots; ++s) {
-      if (s >= used_lo && s <= used_hi) {
-        if (on) {
-          // base + s lies in [-ng, 2 ng) (n_g >= 32 > the window)
-          int cell = base + s;
-          cell += (cell < 0) ? ng : 0;
-          cell -= (cell >= ng) ? ng : 0;
-          atomicAdd(&grid[cell].x, acc[s].x);
-          atomicAdd(&grid[cell].y, acc[s].y);
-        }
-        acc[s] = {0.0f, 0.0f};
+      for (int k = 0; k < 3; ++k)
+        cq[k] = {qx * r.s[4 + 2 * k] - qy * r.s[5 + 2 * k], qx * r.s[5 + 2 * k] + qy * r.s[4 + 2 * k]};
+      const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - off - reach)));
+      const int s_hi = __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c - off + reach)));
+      if constexpr (INTRA) {
+        float2 c5[5];
+        intra_coeffs(cq, c5, eps, inv_s2);
+        spread_poly<5>(acc, c5, xr - off, s_lo, s_hi, nc, q_ratio);
+      } else {
+        spread_poly<3>(acc, cq, xr - off, s_lo, s_hi, nc, q_ratio);
       }
     }
   }
+  if (!on) return;
+  float4 *dst = reinterpret_cast<float4 *>(
+      part + ((static_cast<int64_t>(nl) * ns.max_runs + run) * O + o) * kNuSlots);
+#pragma unroll
+  for (int s = 0; s < kNuSlots / 2; ++s)
+    dst[s] = make_float4(acc[2 * s].x, acc[2 * s].y, acc[2 * s + 1].x, acc[2 * s + 1].y);
 }
 
-// Per (chirp, group of cb channels): grid rows into LDS (zeroed behind for the next
-// call), forward FFT of all cb rows together (ping-pong buffers of cb rows), deconvolution
-// and the k_c^2 / k_m^2 factor on the M kept modes.
+// First index in the sorted bases[0 .. n) with bases[i] >= v.
+__device__ inline int lower_bound_lds(const int32_t *bases, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (bases[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Per (chirp, group of cb channels): each grid cell l summed from the run windows that
+// cover it (at l, l - n_g or l + n_g on the periodic grid; in order of the runs' base
+// cells, which is the run order), forward FFT of all cb rows together (ping-pong buffers),
+// deconvolution and the k_c^2 / k_m^2 factor on the M kept modes.
 __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, RadarConst rc,
                                                                 NuShape ns, NuBuffers nb,
-                                                                const float2 *tw, bool ranged) {
+                                                                const float2 *tw) {
   extern __shared__ float2 nu_smem[];
   const int nl = blockIdx.x / ns.groups;
   const int grp = blockIdx.x - nl * ns.groups;
@@ -642,16 +824,33 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
   const int O = rc.P * rc.Q;
   float2 *lgrid = nu_smem;            // [cb][ld]
   float2 *work = nu_smem + cb * ld;   // [cb][ld]
-  // only the chirp's occupied cells are read (and zeroed behind); none without records
-  const int2 rg = ranged ? nb.range[nl] : make_int2(0, -1);
-  for (int c = 0; c < cb; ++c) {
-    const int o = grp * cb + c;
-    float2 *src = nb.grid + (static_cast<int64_t>(nl) * O + o) * ng;
-    for (int l = threadIdx.x; l < ng; l += blockDim.x) {
+  int32_t *bases = reinterpret_cast<int32_t *>(work + cb * ld);  // [max_runs]
+  const int nr = nb.n_runs[nl];
+  const int4 *runs = nb.runs + static_cast<int64_t>(nl) * ns.max_runs;
+  for (int r = threadIdx.x; r < nr; r += blockDim.x) bases[r] = runs[r].z;
+  __syncthreads();
+  const float2 *part = nb.grid + static_cast<int64_t>(nl) * ns.max_runs * O * kNuSlots;
+  for (int l = threadIdx.x; l < ng; l += blockDim.x) {
+    int lo[3], hi[3];
+#pragma unroll
+    for (int im = 0; im < 3; ++im) {
+      const int P = l + (im - 1) * ng;
+      lo[im] = lower_bound_lds(bases, nr, P - kNuSlots + 1);
+      hi[im] = lower_bound_lds(bases, nr, P + 1);
+    }
+    for (int c = 0; c < cb; ++c) {
+      const int o = grp * cb + c;
       float2 v = {0.0f, 0.0f};
-      if (o < O && l >= rg.x && l <= rg.y) {
-        v = src[l];
-        src[l] = {0.0f, 0.0f};
+      if (o < O) {
+#pragma unroll
+        for (int im = 0; im < 3; ++im) {
+          const int P = l + (im - 1) * ng;
+          for (int r = lo[im]; r < hi[im]; ++r) {
+            const float2 p = part[(static_cast<int64_t>(r) * O + o) * kNuSlots + (P - bases[r])];
+            v.x += p.x;
+            v.y += p.y;
+          }
+        }
       }
       lgrid[c * ld + l] = v;
     }
@@ -686,7 +885,6 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
   }
 }
 
-
 // ---- adjoint (type-2 transform): the loss gradient G = dL/dRe H + j dL/dIm H of the
 // kept modes goes through the transpose of the deconvolution and FFT onto each channel's
 // grid, and every record then gathers Gaussian-weighted moments of that grid instead of
@@ -708,7 +906,7 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
   if (item >= (cnt << (2 * ns.split))) return;
   int sub;
-  const int32_t entry = record_entry(item, cnt, ns.split, &sub);
+  const int32_t entry = record_entry(item, ns.split, &sub);
   Geo g;
   entry_geometry(sc, rc, n, cnt, entry, g);
   NuRec<R> out;
@@ -725,7 +923,7 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
     const double sgn = ((e - 1) & 1) ? -1.0 : 1.0;
     if (e > 0) bt[v] += sgn * kNuDerStep;
     double cr[R], ci[R];
-    const double c = taylor_coeffs<R>(g, bt, sub, ns, cr, ci);
+    const double c = taylor_coeffs<R>(g, bt, sub, ns.split, ns, cr, ci);
     if (e == 0) {
       bc = c;
 #pragma unroll
@@ -966,52 +1164,53 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
 size_t nufft_smem_bytes(const NuShape &ns) {
   return sizeof(float2) * static_cast<size_t>(2 * ns.cb) * ns.ld;
 }
+size_t nufft_fft_smem_bytes(const NuShape &ns) {
+  return nufft_smem_bytes(ns) + sizeof(int32_t) * static_cast<size_t>(ns.max_runs);
+}
+size_t nufft_sort_smem_bytes(const NuShape &ns) {
+  return sizeof(int32_t) * (static_cast<size_t>(kNuSortWaves) * ns.ng + ns.ng + 1 + kNuSortThreads);
+}
 
-template <int R>
-hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double *elem,
-                          const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
-  if (ns.n_chirps <= 0) return hipSuccess;
-  const int64_t items = (sc.n_facets << (2 * ns.split)) + sc.n_points;
-  if ((rc.intra ? sizeof(NuRecT<R, true>) : sizeof(NuRecT<R, false>)) > nb.rec_bytes)
-    return hipErrorInvalidValue;
+template <bool INTRA>
+static hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double *elem,
+                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
+                                 hipStream_t s) {
+  const int64_t items = sc.n_facets + sc.n_points;
   if (items > 0) {
     dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
     hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nufft_count_kernel, dim3(ns.n_chirps), dim3(1024), 0, s, sc, ns, nb);
+    hipLaunchKernelGGL(nufft_sort_kernel, dim3(ns.n_chirps), dim3(kNuSortThreads),
+                       nufft_sort_smem_bytes(ns), s, sc, ns, nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t waves = static_cast<int64_t>(ns.n_chirps) * ns.spread_groups * ns.runs;
-    const int64_t blocks = (waves + kNuSpreadThreads / 64 - 1) / (kNuSpreadThreads / 64);
-    if (rc.intra) {
-      hipLaunchKernelGGL((nufft_prep_kernel<R, true>), grid, dim3(256), 0, s, sc, rc, ns, nb);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((nufft_spread_kernel<R, true>), dim3(static_cast<unsigned>(blocks)),
-                         dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
-                         static_cast<const NuRecT<R, true> *>(nb.srec), nb.grid);
-    } else {
-      hipLaunchKernelGGL((nufft_prep_kernel<R, false>), grid, dim3(256), 0, s, sc, rc, ns, nb);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((nufft_spread_kernel<R, false>), dim3(static_cast<unsigned>(blocks)),
-                         dim3(kNuSpreadThreads), 0, s, sc, rc, ns, elem,
-                         static_cast<const NuRecT<R, false> *>(nb.srec), nb.grid);
-    }
+    hipLaunchKernelGGL((nufft_prep_kernel<INTRA>), grid, dim3(256), 0, s, sc, rc, ns, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int O = rc.P * rc.Q;
+    const int groups = (O + 63) / 64;
+    const int per_block = groups < 4 ? groups : 4;
+    dim3 sgrid(static_cast<unsigned>(ns.max_runs), static_cast<unsigned>(ns.n_chirps),
+               static_cast<unsigned>((groups + 3) / 4));
+    hipLaunchKernelGGL((nufft_spread_kernel<INTRA>), sgrid, dim3(64 * per_block), 0, s, sc, rc,
+                       ns, elem, static_cast<const NuRecF<INTRA> *>(nb.srec), nb.runs, nb.n_runs,
+                       nb.grid);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
-                     dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
-                     static_cast<const float2 *>(tw), items > 0);
+                     dim3(kNuFftThreads), nufft_fft_smem_bytes(ns), s, sc, rc, ns, nb,
+                     static_cast<const float2 *>(tw));
   return hipGetLastError();
 }
 
 hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
                         const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
-  if (ns.order == 5) return launch_nufft_t<5>(sc, rc, elem, ns, nb, tw, s);
-  if (ns.order == 7) return launch_nufft_t<7>(sc, rc, elem, ns, nb, tw, s);
-  if (ns.order == 10) return launch_nufft_t<10>(sc, rc, elem, ns, nb, tw, s);
-  return hipErrorInvalidValue;
+  if (ns.n_chirps <= 0) return hipSuccess;
+  if (nufft_record_bytes(rc.intra != 0) > nb.rec_bytes || !nb.runs || !nb.n_runs || !nb.key ||
+      !nb.pos || ns.ng > 2 * kNuSortThreads || ns.max_runs < 1)
+    return hipErrorInvalidValue;
+  return rc.intra ? launch_nufft_t<true>(sc, rc, elem, ns, nb, tw, s)
+                  : launch_nufft_t<false>(sc, rc, elem, ns, nb, tw, s);
 }
-
 
 template <int R>
 hipError_t launch_nufft_adjoint_t(const DevScene &sc, const RadarConst &rc, const double *elem,

@@ -57,19 +57,21 @@ hipError_t launch_echo_mfma_persistent(const DevScene *scenes, const int4 *items
                                        const EchoShape &sh, int n_groups, hipStream_t s);
 hipError_t mfma_occupancy(int P, int Q, const EchoShape &sh, int *groups_per_cu);
 
-// facet sum as a type-1 non-uniform FFT over the sample index (FP32, stop-and-hop,
-// single bounce): Gaussian spread of kNuWidth cells with standard deviation kNuSigma
-// cells onto n_g >= 2M cells
+// facet sum as a type-1 non-uniform FFT over the sample index (FP32): Gaussian spread
+// of kNuWidth cells with standard deviation kNuSigma cells onto n_g >= 2M cells
 constexpr int kNuWidth = 12;
 constexpr double kNuSigma = 1.1;
+// forward spread: register window of kNuSlots grid cells per lane; a run of sorted
+// records spans at most `kspan` cells so that all its sources fit one window
+constexpr int kNuSlots = 32;
 struct NuShape {
   int32_t ng, ld, cb, groups;  // grid cells, LDS row stride, channels per FFT workgroup, groups
-  int32_t order;               // Taylor terms of the spread (5, 7 or 10)
+  int32_t order;               // adjoint: Taylor terms of a record (5, 7 or 10)
   int32_t n0, n_chirps;        // chirps of this launch: n0 .. n0 + n_chirps - 1
-  int32_t runs;                // sorted-entry runs per chirp (one spread wave each)
+  int32_t runs;                // adjoint: unused by the kernels
   int32_t spread_groups;       // 64-channel groups of the spread
-  int32_t split;               // facets split into 4^split sub-triangles (midpoints)
-  int64_t rec_stride;          // records per chirp (facets x 4^split + points)
+  int32_t split;               // adjoint: facets split into 4^split sub-triangles (midpoints)
+  int64_t rec_stride;          // records per chirp (forward: lit facets + points)
   double chan_d;               // largest grid offset of a channel from the phase-centre path
   double fc, kc;               // f0 + (M/2) df; 2 pi fc / c
   double cells_per_s;          // df ng: grid cells per second of round-trip delay
@@ -78,24 +80,33 @@ struct NuShape {
   int32_t accumulate;          // 0: write the echo; 1: add gamma x (this path's echo) to it
   int32_t pad2;
   double gamma_re, gamma_im;
+  // forward: sources lie within off_max cells of their record's path position; the
+  // window of a run starts b0 cells below its first record's cell; runs hold at most
+  // run_len records over at most kspan + 1 cells; max_runs per chirp bounds their count
+  double off_max;
+  int32_t b0, kspan, run_len, max_runs;
 };
-// Work buffers of one launch (n_chirps chirps): per (chirp, entry) the grid cell, the
-// position in cell order and the records in that order; grids [chirp][O][ng], zero on
-// entry and left zero.
+// Work buffers of one launch (n_chirps chirps). Forward: per (chirp, entry) the grid cell
+// and the position in cell order, the records in that order, per chirp the runs
+// (first record, end, window base cell) and their count, and per (chirp, run, channel)
+// the window of kNuSlots cells. Adjoint: records and adjoint records in entry order and
+// grids [chirp][O][ng].
 struct NuBuffers {
   int32_t *key;
   int32_t *pos;
   void *srec;
-  float2 *grid;
+  float2 *grid;      // forward: partial windows [chirp][max_runs][O][kNuSlots]
   size_t rec_bytes;  // record slot size of srec (a launch refuses wider records)
   void *sder;        // adjoint records in the same order (adjoint only)
-  int2 *range;       // per chirp: the grid cells [x, y] that can be nonzero (forward only)
+  int4 *runs;        // forward: [chirp][max_runs]
+  int32_t *n_runs;   // forward: [chirp]
 };
-size_t nufft_record_bytes(int order, bool intra);
+size_t nufft_record_bytes(bool intra);
+size_t nufft_adj_record_bytes(int order);
 size_t nufft_der_bytes(int order);
 size_t nufft_smem_bytes(const NuShape &ns);
-int nufft_window_cells();
-int nufft_run_length();
+size_t nufft_fft_smem_bytes(const NuShape &ns);
+size_t nufft_sort_smem_bytes(const NuShape &ns);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
                         const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s);

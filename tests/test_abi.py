@@ -166,9 +166,10 @@ def test_detect_and_noise_validation_host_only():
 
 def test_nufft_refusals_host_only():
     """The NUFFT facet sum's eligibility is decided on the host before any device work:
-    FP64 is EINVAL; facets spanning more than 12 grid cells (2 r_max df n_g / c; up to
-    that they are split) are ERANGE; an eligible request (the delay within the chirp, the
-    ground bounce and split facets included) reaches the missing device."""
+    FP64 is EINVAL; node offsets (2 r_max df n_g / c) plus channel offsets beyond 9 grid
+    cells (the spread's register window) are ERANGE; an eligible request (the delay within
+    the chirp, the ground bounce and coarse facets of 4.8 cells included) reaches the
+    missing device."""
     ctx = _host_ctx()
     L = rsim.lib()
     wf = scenes.paper_waveform(256, 8)
@@ -177,7 +178,7 @@ def test_nufft_refusals_host_only():
     ctx.set_array(arr.tx, arr.rx)
     fine = scenes.vehicle_mesh("car", 50_000)  # r_max 0.032 m: spread 0.27 cells at M = 256
     coarse = scenes.box_mesh((-2.0, -2.0, 0.0), (2.0, 2.0, 2.0), (1, 1, 1))  # 12 triangles,
-    # r_max 3.0 m: 25 cells, beyond 64 sub-triangles
+    # r_max 3.0 m: 25 cells
     ids = []
     for m in (fine, coarse):
         mid = ctx.load_mesh(m.verts, m.tris)
@@ -199,7 +200,7 @@ def test_nufft_refusals_host_only():
     both = (ctypes.c_int32 * 2)(*ids)
     o = rsim.Opts(kernel=rsim.RSIM_KERNEL_NUFFT)
     assert L.rsim_synthesize(ctx._h, both, 2, echo, None, None, ctypes.byref(o)) == rsim.RSIM_ERANGE
-    # 300 triangles (r_max 0.58 m, 4.8 cells): split into 16 sub-triangles, eligible
+    # 300 triangles (r_max 0.58 m, 4.8 cells): within the window, eligible
     mid = ctx.load_mesh(scenes.vehicle_mesh("car", 300).verts, scenes.vehicle_mesh("car", 300).tris)
     sid = ctx.create_scene()
     ctx.add_instance(sid, mid, np.eye(3), np.array([2.0, 30.0, 0.0]), np.zeros(3))
@@ -221,8 +222,8 @@ def test_nufft_refusals_host_only():
 
 
 def test_nufft_adjoint_refusals_host_only():
-    """The NUFFT adjoint (rsim_set_backward_kernel(RSIM_KERNEL_NUFFT)) has the forward's
-    eligibility, decided on the host: a coarse box beyond 64 sub-triangles is ERANGE, an
+    """The NUFFT adjoint (rsim_set_backward_kernel(RSIM_KERNEL_NUFFT)), eligibility
+    decided on the host: a coarse box beyond 64 sub-triangles is ERANGE, an
     eligible scene reaches the missing device, AUTO never refuses for it, and kernel codes
     beyond NUFFT are EINVAL."""
     ctx = _host_ctx()

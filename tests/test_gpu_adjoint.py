@@ -246,7 +246,7 @@ def test_autograd_two_forwards_one_backward():
     assert torch.allclose(vel0.grad, sep[0][1], rtol=1e-5, atol=1e-8 * sep[0][1].abs().max().item())
     assert torch.allclose(vel1.grad, sep[1][1], rtol=1e-5, atol=1e-8 * sep[1][1].abs().max().item())
     # the two geometries give different gradients (the check above is not vacuous)
-    assert not torch.allclose(sep[0][1], sep[1][1], rtol=1e-3)
+    assert not torch.allclose(sep[0][1], sep[1][1], rtol=1e-3, atol=0.0)
 
 
 @pytest.mark.parametrize("P,Q,M", [(12, 16, 96), (3, 5, 64), (1, 4, 160), (6, 8, 40)])

@@ -158,13 +158,14 @@ def test_intersection_1m_default_path_and_every_kernel():
 def test_batched_64_scenes_equals_plain_and_oracle():
     import torch
     from paper_2208_10939_amd.pipeline import Simulator
-    _log("case 64 scenes (10k-400k triangles): persistent graph launch vs plain, oracle samples")
+    _log("case 64 scenes (10k-400k triangles): persistent graph launch vs plain (vector, "
+         "NUFFT, matrix), oracle samples")
     cfg = scenes.c4()
     wf, arr = cfg.waveform, cfg.array
     sim = Simulator(cfg.scenes, wf, arr)
     n = len(cfg.scenes)
     mask = sim.mask_buffer()
-    for kernel in (1, 2):  # vector units, then matrix cores (kept in `batched`)
+    for kernel in (1, 3, 2):  # vector units, NUFFT, then matrix cores (kept in `batched`)
         batched = sim.synthesize(mask=mask, persistent=True, use_graph=True, kernel=kernel)
         torch.cuda.synchronize()
         same = True
@@ -190,95 +191,50 @@ def test_batched_64_scenes_equals_plain_and_oracle():
         assert err <= TOL
 
 
+C5_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_fd.npz")
+
+
 @pytest.mark.slow
-def test_gradient_200k_two_vehicles():
-    """Full 200k-triangle two-vehicle scene at a reduced frame (the oracle must form
-    every chirp): M=32, 4x4 channels, N=4. FD of the oracle loss uses the linearity of
-    the facet sum: a vertex move changes only its incident facets' terms."""
+@pytest.mark.parametrize("kernel", [0, 3, 2])
+def test_gradient_200k_two_vehicles(kernel):
+    """The gradient workload (two vehicles of 100k triangles, loss sum (RDM - T)^2 against
+    the seeded perturbed scene's RDM) at the reduced frame M = 32, 4 x 4 channels, N = 8,
+    the masks held fixed at the oracle's: the library's adjoint (default choice, then the
+    NUFFT and matrix-core adjoints explicitly) against the FP64 oracle's central finite
+    differences stored by tests/golden/make_c5_fd.py: 50 seeded body-frame vertices x 3
+    (25 uniform over both meshes, 25 on lit facets) and every velocity component of both
+    vehicles. Bar: relative L2 <= 1e-3 over each set, and relative error <= 1e-3 for every
+    component with |g| > 1e-3 max |g|."""
     import torch
     from paper_2208_10939_amd.pipeline import Simulator
-    from scenes import Instance, Mesh, RadarArray, Scene
-    _log("case gradient, 200k triangles, M=32 4x4 N=4")
-    base = scenes.c5(n_samples=32, n_chirps=4)
+    from scenes import RadarArray
+    g = np.load(C5_GOLDEN, allow_pickle=False)
+    M, P, Q, N = (int(v) for v in g["frame"])
+    _log(f"case gradient, 200k triangles, M={M} {P}x{Q} N={N}, backward kernel {kernel}")
+    base = scenes.c5(n_samples=M, n_chirps=N)
     sc, wf = base.scenes[0], base.waveform
-    arr = RadarArray(tx=base.array.tx[:4].copy(), rx=base.array.rx[:4].copy())
-    target = base.notes["target_scene"]
-    mask, amb = oracle.visibility(sc, arr, wf)
-    T, _ = oracle.rdm_from_echo(oracle.synthesize(target, wf, arr))
-    H0 = oracle.synthesize(sc, wf, arr, mask=mask)
-
-    def loss_from(H):
-        P, _ = oracle.rdm_from_echo(H)
-        return oracle.rdm_loss(P, T)
-
+    arr = RadarArray(tx=base.array.tx[:P].copy(), rx=base.array.rx[:Q].copy())
+    assert scenes.scene_digest(sc) == str(g["scene_sha16"]), "scene generator drift"
+    mask = _unpack_rows(g["mask"], int(g["n_facets"]))
     sim = Simulator([sc], wf, arr)
     m_t = sim.mask_from_numpy([mask])
     echo = sim.synthesize(mask=m_t, mask_mode=1)
     rdm, y = sim.form_rdm(echo, want_y=True)
-    g = 2.0 * (rdm - torch.from_numpy(T.astype(np.float32)).cuda()[None])
+    T = torch.from_numpy(np.asarray(g["target_rdm"], np.float32)).cuda()[None]
     ge = torch.empty_like(echo)
-    sim.ctx.rdm_backward(g.contiguous(), y, ge)
+    sim.ctx.rdm_backward((2.0 * (rdm - T)).contiguous(), y, ge)
     gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda") for m in sc.meshes]
-    gvel = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+    sim.ctx.set_backward_kernel(kernel)
     sim.ctx.backward(sim.scene_ids[0], ge, m_t, gv, gvel)
     gv = [x.cpu().numpy().astype(np.float64) for x in gv]
-    gvel = gvel.cpu().numpy()
-
-    tri0, inst_of, local_of = oracle.world_triangles(sc, 0.0)
-    P_, Q_ = arr.tx.shape[0], arr.rx.shape[0]
-    pq = [(o // Q_, o % Q_) for o in range(P_ * Q_)]
-    freqs = wf.f0 + wf.slope / wf.fs * np.arange(wf.n_samples)
-    import importlib
-    E = importlib.import_module("oracle.echo")
-
-    def delta_H(mesh_k, v, ax, dv):
-        """H(verts + dv e_ax) - H(verts), via the incident lit facets only."""
-        out = np.zeros_like(H0)
-        for ii, inst in enumerate(sc.instances):
-            if inst.mesh != mesh_k:
-                continue
-            m = sc.meshes[mesh_k]
-            inc = np.nonzero((m.tris == v).any(axis=1))[0]
-            base_idx = np.nonzero(inst_of == ii)[0][0]
-            for n in range(wf.n_chirps):
-                t = n * wf.chirp_period
-                lit = inc[mask[n, base_idx + inc]]
-                if lit.size == 0:
-                    continue
-                vb = m.verts.astype(np.float64)
-                vb2 = vb.copy()
-                vb2[v, ax] += dv
-                for vv, sign in ((vb2, 1.0), (vb, -1.0)):
-                    w = vv @ inst.rot.T + (inst.pos0 + inst.vel * t)
-                    out[:, n, :] += sign * E.facet_terms(w[m.tris[lit]], wf, arr, freqs, pq)
-        return out
-
-    rng = np.random.default_rng(13)
-    lit_f = np.nonzero(mask[0])[0]
-    fd, ad = [], []
-    for f in rng.choice(lit_f, 12, replace=False):
-        k = sc.instances[inst_of[f]].mesh
-        v = int(sc.meshes[k].tris[local_of[f], rng.integers(0, 3)])
-        for ax in range(3):
-            lp = loss_from(H0 + delta_H(k, v, ax, 1e-5))
-            lm = loss_from(H0 + delta_H(k, v, ax, -1e-5))
-            fd.append((lp - lm) / 2e-5)
-            ad.append(gv[k][v, ax])
-    fd, ad = np.array(fd), np.array(ad)
-    rel_l2 = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
-    _log(f"  vertices: rel_l2={rel_l2:.3e} (n={fd.size}, ambiguous facets={amb.sum()})")
-    assert rel_l2 <= 1e-3
-    # velocity: one component per vehicle (along the lane), full re-synthesis of the scene
-    fdv, adv = [], []
-    for ik in range(2):
-        hs = []
-        for dv in (1e-2, -1e-2):
-            insts = [Instance(i.mesh, i.rot, i.pos0, i.vel + (np.array([0.0, dv, 0.0]) if j == ik else 0.0))
-                     for j, i in enumerate(sc.instances)]
-            hs.append(loss_from(oracle.synthesize(Scene(sc.meshes, insts), wf, arr, mask=mask)))
-        fdv.append((hs[0] - hs[1]) / 2e-2)
-        adv.append(gvel[ik, 1])
-    fdv, adv = np.array(fdv), np.array(adv)
-    relv = np.linalg.norm(adv - fdv) / np.linalg.norm(fdv)
-    _log(f"  velocities: adj={adv} fd={fdv} rel_l2={relv:.3e}")
-    assert relv <= 1e-3
+    ad_v = np.array([gv[k][v] for k, v in zip(g["vert_mesh"], g["vert_index"])])
+    ad_w = gvel.cpu().numpy()
+    for name, ad, fd in (("vertices", ad_v, np.asarray(g["fd_vert"])),
+                         ("velocities", ad_w, np.asarray(g["fd_vel"]))):
+        rel_l2 = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+        big = np.abs(fd) > 1e-3 * np.abs(fd).max()
+        worst = float(np.max(np.abs(ad - fd)[big] / np.abs(fd)[big]))
+        _log(f"  {name}: n={fd.size} (above 1e-3 max: {int(big.sum())}) rel_l2={rel_l2:.3e} "
+             f"worst relative component error {worst:.3e}")
+        assert rel_l2 <= 1e-3 and worst <= 1e-3
