@@ -464,9 +464,7 @@ EchoShape matrix_shape(const RadarConst &rc) {
   return sh;
 }
 
-// NUFFT facet sum: grid length, adjoint splitting and work-buffer budget.
-constexpr double kNuMaxSpread = 1.5;  // adjoint records: facets spanning more are split
-constexpr int kNuMaxSplit = 3;
+// NUFFT facet sum: grid length and work-buffer budget.
 constexpr int kNuMaxGrid = 2048;
 constexpr size_t kNuRecBudget = size_t(16) << 30;  // work buffer: chirps per launch cap
 
@@ -572,6 +570,9 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
   s.off_max = 2.0 * r_max * s.kappa;
   s.b0 = static_cast<int32_t>(std::ceil(s.chan_d + s.off_max + 0.5 * kNuWidth));
   s.kspan = kNuSlots - 2 - 2 * s.b0;
+  if (nufft_cells_per_source(s) == 0)
+    return "array aperture too wide for the NUFFT spread (channels more than 4 grid cells "
+           "from the phase-centre path)";
   if (s.kspan < 0)
     return "facets or array aperture too wide for the NUFFT window: node offsets (2 r_max "
            "df n_g / c) plus channel offsets exceed 9 grid cells";
@@ -579,25 +580,13 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
   return nullptr;
 }
 
-// Why the NUFFT adjoint cannot run; *ns: its shape (Taylor order and split level).
-const char *nufft_adj_ineligible(const rsim_ctx *ctx, const RadarConst &rc, double r_max,
-                                 NuShape *ns) {
+// Why the NUFFT adjoint cannot run; *ns: its shape. Its gather reads each source's own
+// cells from a staged grid row, so no window bounds the node or channel offsets.
+const char *nufft_adj_ineligible(const rsim_ctx *ctx, const RadarConst &rc, NuShape *ns) {
   rsim_opts o{};
   o.precision = RSIM_FP32_PHASE64;
   NuShape s{};
   if (const char *why = nufft_common(ctx, rc, o, 0.0, &s)) return why;
-  // facets spanning more than 1.5 grid cells are split into 4^split midpoint
-  // sub-triangles (halving the span per level), at most 64
-  double spread = 2.0 * r_max * s.kappa;
-  int split = 0;
-  while (spread > kNuMaxSpread && split < kNuMaxSplit) {
-    spread *= 0.5;
-    ++split;
-  }
-  if (spread > kNuMaxSpread) return "facets span more than 12 NUFFT grid cells";
-  if (2.0 * s.chan_d > 20 - kNuWidth - 3) return "array aperture too wide for the NUFFT adjoint";
-  s.order = spread <= 0.35 ? 5 : spread <= 0.8 ? 7 : 10;
-  s.split = split;
   nufft_fft_groups(ctx, rc, s, 0);
   *ns = s;
   return nullptr;
@@ -1495,15 +1484,17 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   DevScene d = d_in;
   d.n_points = 0;  // points carry no parameters
   const int64_t F = d.n_facets, N = rcn.N, O = static_cast<int64_t>(rcn.P) * rcn.Q;
-  const int64_t stride = std::max<int64_t>(1, F << (2 * ns.split));
-  const size_t rec_b = nufft_adj_record_bytes(ns.order), der_b = nufft_der_bytes(ns.order);
+  const int64_t stride = std::max<int64_t>(1, F);
+  const size_t rec_b = nufft_record_bytes(false), der_b = nufft_der_bytes();
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per_chirp = stride * (rec_b + der_b) + O * ns.ng * 8;
+  const size_t per_chirp = stride * (rec_b + der_b + 8) + 8 + O * ns.ng * 8;
   int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
   if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
   const size_t off_srec = 0;
   const size_t off_sder = off_srec + al(chunk * stride * rec_b);
-  const size_t off_grid = off_sder + al(chunk * stride * der_b);
+  const size_t off_lists = off_sder + al(chunk * stride * der_b);
+  const size_t off_counts = off_lists + al(chunk * 2 * stride * 4);
+  const size_t off_grid = off_counts + al(chunk * 2 * 4);
   const size_t total = off_grid + chunk * O * ns.ng * 8;
   int32_t rc = RSIM_OK;
   if (ctx->nu_adj_bytes < total) {
@@ -1515,8 +1506,13 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
     ctx->nu_adj_bytes = total;
   }
   char *b = static_cast<char *>(ctx->nu_adj_buf);
-  NuBuffers nb{nullptr, nullptr, b + off_srec, reinterpret_cast<float2 *>(b + off_grid), rec_b,
-               b + off_sder};  // records in entry order: no keys or positions
+  NuBuffers nb{};
+  nb.key = reinterpret_cast<int32_t *>(b + off_lists);
+  nb.srec = b + off_srec;
+  nb.grid = reinterpret_cast<float2 *>(b + off_grid);
+  nb.rec_bytes = rec_b;
+  nb.sder = b + off_sder;
+  nb.n_runs = reinterpret_cast<int32_t *>(b + off_counts);
   void *tw = twiddles(ctx, ns.ng, 0, &rc);
   if (rc) return rc;
   HIP_TRY(ctx, launch_fill_zero(ctx->adj_partial, N * F * kAdjSlotFloats, s));
@@ -1556,7 +1552,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   NuShape nsb{};
   bool nufft = false;
   if (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO) {
-    const char *nwhy = nufft_adj_ineligible(ctx, rcn, scenes_rmax(ctx, {scene_id}), &nsb);
+    const char *nwhy = nufft_adj_ineligible(ctx, rcn, &nsb);
     if (nwhy && ctx->bwd_kernel == RSIM_KERNEL_NUFFT)
       return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
     nufft = !nwhy;

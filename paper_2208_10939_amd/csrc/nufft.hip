@@ -69,7 +69,7 @@
 namespace rsim {
 
 constexpr int kNuFftThreads = 512;
-constexpr int kNuMaxOrder = 10;
+constexpr int kNuMaxOrder = 4;  // Hermite table rows (three Taylor terms are used)
 constexpr int kNuSortThreads = 1024;  // 16 waves: each ranks one sixteenth of a chirp's entries
 constexpr int kNuSortWaves = kNuSortThreads / 64;
 constexpr int kNuGatherRecs = 256;  // records (lanes) per adjoint gather workgroup
@@ -100,41 +100,6 @@ struct alignas(16) NuRecF {
 };
 static_assert(sizeof(NuRecF<false>) == 128 && sizeof(NuRecF<true>) == 144, "record size");
 
-// Adjoint record (Taylor form about the centroid, facets split into 4^split midpoint
-// sub-triangles where they span more than 1.5 grid cells).
-template <int R>
-struct alignas(16) NuRec {
-  double ut[3], ur[3];
-  double g1;
-  float rt, rr;
-  float t0;
-  float frac;
-  int32_t cell;
-  int32_t valid;
-  float2 b[R];  // polynomial coefficients in grid cells
-};
-static_assert(sizeof(NuRec<5>) == 128 && sizeof(NuRec<7>) == 144 && sizeof(NuRec<10>) == 160,
-              "record size");
-
-// Adjoint record: derivatives of the Taylor coefficients and of the source position with
-// respect to the facet's three node offsets, and the facet's index in the lit list.
-template <int R>
-struct alignas(16) NuDer {
-  float2 db[3][R];  // d b_k / d beta_v (per metre)
-  float dx[3];      // d x / d beta_v (cells per metre; nonzero for sub-triangles)
-  int32_t item;
-};
-static_assert(sizeof(NuDer<5>) == 144 && sizeof(NuDer<7>) == 192 && sizeof(NuDer<10>) == 256,
-              "adjoint record size");
-static_assert(kAdjVals == kAdjSlotFloats, "adjoint slot layout");
-constexpr double kNuDerStep = 1e-6;  // metres: central differences of b_k in beta (FP64)
-
-size_t nufft_der_bytes(int order) {
-  return order <= 5 ? sizeof(NuDer<5>) : order <= 7 ? sizeof(NuDer<7>) : sizeof(NuDer<10>);
-}
-size_t nufft_adj_record_bytes(int order) {
-  return order <= 5 ? sizeof(NuRec<5>) : order <= 7 ? sizeof(NuRec<7>) : sizeof(NuRec<10>);
-}
 size_t nufft_record_bytes(bool intra) {
   return intra ? sizeof(NuRecF<true>) : sizeof(NuRecF<false>);
 }
@@ -198,67 +163,15 @@ __device__ inline void centre_cell(const Geo &g, const RadarConst &rc, const NuS
   *cell_out = wrap_cell(static_cast<int64_t>(floor(x)), ns.ng);
 }
 
-// Adjoint record `rec` of a chirp with `cnt` lit facets: 4^split records per lit facet.
-// Returns the lit entry and the sub-triangle.
-__device__ inline int32_t record_entry(int32_t rec, int split, int *sub) {
-  *sub = rec & ((1 << (2 * split)) - 1);
-  return rec >> (2 * split);
-}
-
-// Node offsets of sub-triangle `sub` (base-4 digits, most significant first; each digit
-// picks one of the four midpoint sub-triangles) of a facet with node offsets beta about its
-// centroid: offsets are linear in position, so a midpoint's is the mean of its ends.
-// Returns the offset of the sub-triangle's centroid; out[] = its nodes about that centroid.
-__device__ inline double sub_nodes(const double beta[3], int sub, int split, double out[3]) {
-  double p0 = beta[0], p1 = beta[1], p2 = beta[2];
-  for (int l = split - 1; l >= 0; --l) {
-    const int d = (sub >> (2 * l)) & 3;
-    const double m01 = 0.5 * (p0 + p1), m12 = 0.5 * (p1 + p2), m20 = 0.5 * (p2 + p0);
-    if (d == 0) {
-      p1 = m01;
-      p2 = m20;
-    } else if (d == 1) {
-      p0 = m01;
-      p2 = m12;
-    } else if (d == 2) {
-      p0 = m20;
-      p1 = m12;
-    } else {
-      p0 = m01;
-      p1 = m12;
-      p2 = m20;
-    }
-  }
-  const double c = (p0 + p1 + p2) * (1.0 / 3.0);
-  out[0] = p0 - c;
-  out[1] = p1 - c;
-  out[2] = p2 - c;
-  return c;
-}
-
-// Taylor coefficients b_k (FP64) of psi expanded about the centroid: the facet with node
-// offsets beta_f about its centroid, or its sub-triangle `sub` (own nodes about the
-// sub-centroid, 4^-split of the area, the factor exp(j k_c bc)). b_k includes the common
-// factor -amp / k_c^2. Returns bc, the sub-centroid's offset (0 unsplit).
+// Taylor coefficients b_k (FP64) of psi expanded about the centroid for a facet with node
+// offsets beta about it; b_k includes the common factor -amp / k_c^2.
 template <int R>
-__device__ double taylor_coeffs(const Geo &g, const double beta_f[3], int sub, int split,
-                                const NuShape &ns, double br[R], double bi[R]) {
-  double beta[3] = {beta_f[0], beta_f[1], beta_f[2]};
-  double bc = 0.0;
-  double amp_re = g.amp_re, amp_im = g.amp_im;
-  if (sub >= 0 && split > 0) {
-    bc = sub_nodes(beta_f, sub, split, beta);
-    const double scale = 1.0 / static_cast<double>(1 << (2 * split));
-    double sb, cb;
-    const double tb = ns.fc / kC0 * bc;
-    sincospi_t(2.0 * (tb - rint(tb)), &sb, &cb);
-    const double ar = amp_re * scale, ai = amp_im * scale;
-    amp_re = ar * cb - ai * sb;
-    amp_im = ar * sb + ai * cb;
-  }
+__device__ void taylor_coeffs(const Geo &g, const double beta[3], const NuShape &ns,
+                              double br[R], double bi[R]) {
+  const double amp_re = g.amp_re, amp_im = g.amp_im;
 #pragma unroll
   for (int k = 0; k < R; ++k) br[k] = bi[k] = 0.0;
-  if (!g.valid) return bc;
+  if (!g.valid) return;
   const double turns_per_m = ns.fc / kC0;  // k_c / (2 pi)
   const double A0 = turns_per_m * beta[0], A1 = turns_per_m * beta[1],
                A2 = turns_per_m * beta[2];
@@ -319,7 +232,6 @@ __device__ double taylor_coeffs(const Geo &g, const double beta_f[3], int sub, i
     br[k] = -(amp_re * sr - amp_im * si);
     bi[k] = -(amp_re * si + amp_im * sr);
   }
-  return bc;
 }
 
 // The phase-centre path of a record (FP64): unit vectors, distances, reduced phase, the
@@ -351,43 +263,59 @@ __device__ inline double2 rot_turns(double x, double y, double T) {
   return make_double2(x * c - y * s, x * s + y * c);
 }
 
-// The grid sources of one lit facet or point (see the header comment): fills s[10] and
-// returns the kind. Weights and coefficients include the common factor -amp / k_c^2.
-__device__ int nufft_sources(const Geo &g, const NuShape &ns, float s[10]) {
-#pragma unroll
-  for (int k = 0; k < 10; ++k) s[k] = 0.0f;
+// Source form of one lit facet or point (see the header comment): kind 1, 2 or 3 (0 for a
+// zero-area facet); for kind 2, *far = the node away from the close pair.
+__device__ inline int nufft_classify(const Geo &g, const NuShape &ns, int *far) {
+  *far = 0;
   if (!g.valid) return 0;
   const double tpm = ns.fc / kC0;  // turns of k_c beta per metre
-  const double ik2 = 1.0 / (ns.kc * ns.kc);
-  const double cr = -g.amp_re * ik2, ci = -g.amp_im * ik2;
   const double *b = g.beta;
   const double gap = kNuGapMin / (2.0 * kPi);  // turns
   // gap opposite node v: between the other two
   const double d0 = fabs(b[1] - b[2]) * tpm, d1 = fabs(b[0] - b[2]) * tpm,
                d2 = fabs(b[0] - b[1]) * tpm;
   const int narrow = (d0 < gap) + (d1 < gap) + (d2 < gap);
+  if (narrow == 0) return 1;
+  if (narrow == 1) {
+    *far = d0 < gap ? 0 : d1 < gap ? 1 : 2;
+    return 2;
+  }
+  return 3;
+}
+
+// The grid sources of a facet of the given kind with node offsets beta (FP64): fills
+// s[10]. Weights and coefficients include the common factor -amp / k_c^2.
+__device__ void nufft_fill(const Geo &g, const double beta[3], const NuShape &ns, int kind,
+                           int far, double s[10]) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) s[k] = 0.0;
+  if (kind == 0) return;
+  const double tpm = ns.fc / kC0;
+  const double ik2 = 1.0 / (ns.kc * ns.kc);
+  const double cr = -g.amp_re * ik2, ci = -g.amp_im * ik2;
+  const double *b = beta;
   const double kappa = ns.kappa;
-  if (narrow == 0) {
+  if (kind == 1) {
     for (int v = 0; v < 3; ++v) {
       const int a = v == 0 ? 1 : 0, c = v == 2 ? 1 : 2;
       const double den = (b[v] - b[a]) * (b[v] - b[c]);
       const double2 w = rot_turns(cr / den, ci / den, tpm * b[v]);
-      s[3 * v] = static_cast<float>(kappa * b[v]);
-      s[3 * v + 1] = static_cast<float>(w.x);
-      s[3 * v + 2] = static_cast<float>(w.y);
+      s[3 * v] = kappa * b[v];
+      s[3 * v + 1] = w.x;
+      s[3 * v + 2] = w.y;
     }
-    return 1;
+    return;
   }
-  if (narrow == 1) {
+  if (kind == 2) {
     // the close pair (p0, p1) and the far node p2
-    const int p2 = d0 < gap ? 0 : d1 < gap ? 1 : 2;
+    const int p2 = far;
     const int p0 = p2 == 0 ? 1 : 0, p1 = p2 == 2 ? 1 : 2;
     const double B0 = b[p0], B1 = b[p1], B2 = b[p2];
     const double d21 = B2 - B1, d20 = B2 - B0;
     const double2 wA = rot_turns(cr / (d21 * d20), ci / (d21 * d20), tpm * B2);
-    s[0] = static_cast<float>(kappa * B2);
-    s[1] = static_cast<float>(wA.x);
-    s[2] = static_cast<float>(wA.y);
+    s[0] = kappa * B2;
+    s[1] = wA.x;
+    s[2] = wA.y;
     // about mu = (B0 + B1) / 2 with delta = -h, +h at the pair:
     // V_r = -exp(j k_c h) h^r / (d21 d20) - DD1[delta^r exp(j k_c delta)](-h, h) / d20
     // with DD1 = j k_c sinc(k_c h), cos(k_c h), j h sin(k_c h) for r = 0, 1, 2
@@ -414,23 +342,33 @@ __device__ int nufft_sources(const Geo &g, const NuShape &ns, float s[10]) {
       ai[r] = v.x * ci + v.y * cr;
     }
     const double is = 1.0 / ns.sigma;
-    s[3] = static_cast<float>(kappa * mu);
-    s[4] = static_cast<float>(ar[0] - ar[2]);
-    s[5] = static_cast<float>(ai[0] - ai[2]);
-    s[6] = static_cast<float>(ar[1] * is);
-    s[7] = static_cast<float>(ai[1] * is);
-    s[8] = static_cast<float>(ar[2] * is * is);
-    s[9] = static_cast<float>(ai[2] * is * is);
-    return 2;
+    s[3] = kappa * mu;
+    s[4] = ar[0] - ar[2];
+    s[5] = ai[0] - ai[2];
+    s[6] = ar[1] * is;
+    s[7] = ai[1] * is;
+    s[8] = ar[2] * is * is;
+    s[9] = ai[2] * is * is;
+    return;
   }
   double br[3], bi[3];
-  taylor_coeffs<3>(g, g.beta, -1, 0, ns, br, bi);
-  s[3] = 0.0f;
+  taylor_coeffs<3>(g, beta, ns, br, bi);
+  s[3] = 0.0;
   for (int k = 0; k < 3; ++k) {
-    s[4 + 2 * k] = static_cast<float>(br[k]);
-    s[5 + 2 * k] = static_cast<float>(bi[k]);
+    s[4 + 2 * k] = br[k];
+    s[5 + 2 * k] = bi[k];
   }
-  return 3;
+}
+
+// The grid sources of one lit facet or point: fills s[10] (FP32) and returns the kind.
+__device__ int nufft_sources(const Geo &g, const NuShape &ns, float s[10]) {
+  int far;
+  const int kind = nufft_classify(g, ns, &far);
+  double sd[10];
+  nufft_fill(g, g.beta, ns, kind, far, sd);
+#pragma unroll
+  for (int k = 0; k < 10; ++k) s[k] = static_cast<float>(sd[k]);
+  return kind;
 }
 
 template <bool INTRA>
@@ -595,47 +533,87 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc,
   }
 }
 
-// Gaussian (from s_lo on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)) times the
-// weight cw at the cells s_lo .. s_hi of the window.
-__device__ __forceinline__ void spread_point(float2 (&acc)[kNuSlots], float2 cw, float pos,
-                                             int s_lo, int s_hi, float nc, float q_ratio) {
-  const float u0 = static_cast<float>(s_lo) - pos;
-  float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
-  float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+// Gaussian (from cell S0 on: g_{s+1} = g_s rho_s, rho_{s+1} = rho_s exp(-1/s^2)) times the
+// weight cw at the NCELL cells S0 .. S0 + NCELL - 1 of the window (cells past the window's
+// end are dropped at compile time; the runs keep every source inside).
+template <int S0, int NCELL>
+__device__ __forceinline__ void point_cells(float2 (&acc)[kNuSlots], float2 cw, float gw,
+                                            float rho, float q_ratio) {
 #pragma unroll
-  for (int s = 0; s < kNuSlots; ++s) {
-    if (s >= s_lo && s <= s_hi) {
-      acc[s].x = fmaf(gw, cw.x, acc[s].x);
-      acc[s].y = fmaf(gw, cw.y, acc[s].y);
+  for (int j = 0; j < NCELL; ++j) {
+    if (S0 + j < kNuSlots) {
+      acc[S0 + j].x = fmaf(gw, cw.x, acc[S0 + j].x);
+      acc[S0 + j].y = fmaf(gw, cw.y, acc[S0 + j].y);
       gw *= rho;
       rho *= q_ratio;
     }
   }
 }
 
-// Gaussian times the polynomial sum_k c_k (s - pos)^k at the cells s_lo .. s_hi.
-template <int NC>
-__device__ __forceinline__ void spread_poly(float2 (&acc)[kNuSlots], const float2 (&c)[NC],
-                                            float pos, int s_lo, int s_hi, float nc,
-                                            float q_ratio) {
-  const float u0 = static_cast<float>(s_lo) - pos;
-  float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
-  float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+// Gaussian times the polynomial sum_k c_k (s - pos)^k at the cells S0 .. S0 + NCELL - 1.
+template <int S0, int NCELL, int NC>
+__device__ __forceinline__ void poly_cells(float2 (&acc)[kNuSlots], const float2 (&c)[NC],
+                                           float u0, float gw, float rho, float q_ratio) {
 #pragma unroll
-  for (int s = 0; s < kNuSlots; ++s) {
-    if (s >= s_lo && s <= s_hi) {
-      const float xx = static_cast<float>(s) - pos;
+  for (int j = 0; j < NCELL; ++j) {
+    if (S0 + j < kNuSlots) {
+      const float xx = u0 + static_cast<float>(j);
       float pr = c[NC - 1].x, pi = c[NC - 1].y;
 #pragma unroll
       for (int k = NC - 2; k >= 0; --k) {
         pr = fmaf(pr, xx, c[k].x);
         pi = fmaf(pi, xx, c[k].y);
       }
-      acc[s].x = fmaf(gw, pr, acc[s].x);
-      acc[s].y = fmaf(gw, pi, acc[s].y);
+      acc[S0 + j].x = fmaf(gw, pr, acc[S0 + j].x);
+      acc[S0 + j].y = fmaf(gw, pi, acc[S0 + j].y);
       gw *= rho;
       rho *= q_ratio;
     }
+  }
+}
+
+// The window cell s_lo (wave-uniform) selects one straight-line block: one branch per
+// source instead of a test per cell. A source covers NCELL or fewer cells (its count is
+// floor(2 reach) or one more, NCELL at least the larger), so a block may reach up to four
+// cells past the last the runs guarantee inside the window; those are dropped (their
+// Gaussian weights are below psi(W/2) for every channel).
+#define RSIM_NU_CASES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
+  X(16) X(17) X(18) X(19) X(20) X(21) X(22)
+
+template <int NCELL>
+__device__ __forceinline__ void spread_point(float2 (&acc)[kNuSlots], float2 cw, float pos,
+                                             int s_lo, float nc, float q_ratio) {
+  const float u0 = static_cast<float>(s_lo) - pos;
+  const float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+  const float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+  switch (s_lo) {
+#define RSIM_NU_POINT(S) \
+  case S:                \
+    point_cells<S, NCELL>(acc, cw, gw, rho, q_ratio); \
+    break;
+    RSIM_NU_CASES(RSIM_NU_POINT)
+#undef RSIM_NU_POINT
+    default:
+      break;
+  }
+}
+
+template <int NCELL, int NC>
+__device__ __forceinline__ void spread_poly(float2 (&acc)[kNuSlots], const float2 (&c)[NC],
+                                            float pos, int s_lo, float nc, float q_ratio) {
+  const float u0 = static_cast<float>(s_lo) - pos;
+  const float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+  const float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+  switch (s_lo) {
+#define RSIM_NU_POLY(S) \
+  case S:               \
+    poly_cells<S, NCELL, NC>(acc, c, u0, gw, rho, q_ratio); \
+    break;
+    RSIM_NU_CASES(RSIM_NU_POLY)
+#undef RSIM_NU_POLY
+    default:
+      break;
   }
 }
 
@@ -662,7 +640,7 @@ __device__ __forceinline__ void intra_coeffs(const float2 (&c)[NI], float2 (&o)[
 // further groups); lane = channel. The run's records (read once per wave through scalar
 // loads) add their sources into a register window of kNuSlots cells starting at the
 // run's base cell; the window is written to part[chirp][run][channel][kNuSlots].
-template <bool INTRA>
+template <bool INTRA, int NCELL>
 __global__ void __launch_bounds__(256) nufft_spread_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,
     const NuRecF<INTRA> *__restrict__ sorted, const int4 *__restrict__ runs,
@@ -758,16 +736,16 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
         const float off = r.s[3 * j];
         const float2 cw = {qx * r.s[3 * j + 1] - qy * r.s[3 * j + 2],
                            qx * r.s[3 * j + 2] + qy * r.s[3 * j + 1]};
-        // cells some channel reaches: |s - x_o| <= W/2 with |x_o - (rel_c - off)| <= d
+        // cells some channel reaches: |s - x_o| <= W/2 with |x_o - (rel_c - off)| <= d,
+        // NCELL of them from s_lo
         const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - off - reach)));
-        const int s_hi = __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c - off + reach)));
         if constexpr (INTRA) {
           const float2 c1[1] = {cw};
           float2 c3[3];
           intra_coeffs(c1, c3, eps, inv_s2);
-          spread_poly<3>(acc, c3, xr - off, s_lo, s_hi, nc, q_ratio);
+          spread_poly<NCELL>(acc, c3, xr - off, s_lo, nc, q_ratio);
         } else {
-          spread_point(acc, cw, xr - off, s_lo, s_hi, nc, q_ratio);
+          spread_point<NCELL>(acc, cw, xr - off, s_lo, nc, q_ratio);
         }
       }
     }
@@ -778,13 +756,12 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
       for (int k = 0; k < 3; ++k)
         cq[k] = {qx * r.s[4 + 2 * k] - qy * r.s[5 + 2 * k], qx * r.s[5 + 2 * k] + qy * r.s[4 + 2 * k]};
       const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - off - reach)));
-      const int s_hi = __builtin_amdgcn_readfirstlane(static_cast<int>(floorf(rel_c - off + reach)));
       if constexpr (INTRA) {
         float2 c5[5];
         intra_coeffs(cq, c5, eps, inv_s2);
-        spread_poly<5>(acc, c5, xr - off, s_lo, s_hi, nc, q_ratio);
+        spread_poly<NCELL>(acc, c5, xr - off, s_lo, nc, q_ratio);
       } else {
-        spread_poly<3>(acc, cq, xr - off, s_lo, s_hi, nc, q_ratio);
+        spread_poly<NCELL>(acc, cq, xr - off, s_lo, nc, q_ratio);
       }
     }
   }
@@ -887,68 +864,99 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, R
 
 // ---- adjoint (type-2 transform): the loss gradient G = dL/dRe H + j dL/dIm H of the
 // kept modes goes through the transpose of the deconvolution and FFT onto each channel's
-// grid, and every record then gathers Gaussian-weighted moments of that grid instead of
-// spreading onto it. With y = sum_m conj(G) H of one (record, channel),
-//   y = Q sum_k b_k mu_k,  mu_k = sum_l g(l) psi(l - x) (l - x)^k,
-//   dy/dx = Q sum_k b_k (mu_{k+1} / s^2 - k mu_{k-1}),
-// and the seven per-(facet, chirp) sums of the direct adjoint follow: dL/dc through the
-// element distances (the channel's delay and 1 / (R_t R_r)), sum Re y, and dL/dbeta_v
-// through b_k (and the sub-triangle's source position).
+// grid g(l), and every record then gathers Gaussian-weighted moments of that grid at its
+// sources instead of spreading onto it. With y = sum_m conj(G) H of one (record, channel)
+// and the source positions x_s = x - off_s (x the channel's path position),
+//   y = Q sum_s sum_k c_sk mu_sk,  mu_sk = sum_l g(l) psi(l - x_s) (l - x_s)^k,
+//   dy/dx_s = Q sum_k c_sk (mu_s,k+1 / s^2 - k mu_s,k-1)
+// (a point has c_s0 = its weight only), and the seven per-(facet, chirp) sums of the direct
+// adjoint follow: dL/dc through the element distances (the channel's delay and
+// 1 / (R_t R_r); every source moves with x), sum Re y, and
+//   dL/dbeta_v = Re sum_sk (d c_sk / d beta_v) sum_o Q mu_sk
+//                - Re sum_s (d off_s / d beta_v) sum_o dy/dx_s,
+// one record per lit facet, so every per-facet slot is written once (no atomics).
 
-// Adjoint preparation: the forward record plus d b_k / d beta_v by central differences in
-// FP64 (step kNuDerStep: truncation ~ (k_c h)^2 / 6 ~ 5e-7, rounding ~ 1e-10 relative).
-template <int R>
+// Adjoint record: d s[j] / d beta_v of the forward record's sources and the facet's
+// index in the lit list.
+struct alignas(16) NuDerF {
+  float ds[3][10];
+  int32_t item;
+  int32_t pad;
+};
+static_assert(sizeof(NuDerF) == 128, "adjoint record size");
+static_assert(kAdjVals == kAdjSlotFloats, "adjoint slot layout");
+constexpr double kNuDerStep = 1e-6;  // metres: central differences of the sources in beta
+
+size_t nufft_der_bytes() { return sizeof(NuDerF); }
+
+// Adjoint preparation, one thread per (chirp, lit facet): the forward record and the
+// derivatives of its sources by central differences in FP64 with the source form held
+// (step kNuDerStep; every form is analytic in the node offsets: truncation
+// ~ (k_c h)^2 / 6 ~ 5e-7, rounding ~ 1e-10 relative), both in entry order; the facet's
+// entry is appended to its chirp's list of three-point records (class 0) or of the others
+// (class 1), so that a gather wave meets one kind of record. A zero-area facet gets a zero
+// slot here and no list entry.
 __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarConst rc,
-                                                            NuShape ns, NuBuffers nb) {
+                                                            NuShape ns, NuBuffers nb,
+                                                            float *partial) {
   const int nl = blockIdx.y;
   const int n = ns.n0 + nl;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (item >= (cnt << (2 * ns.split))) return;
-  int sub;
-  const int32_t entry = record_entry(item, ns.split, &sub);
-  Geo g;
-  entry_geometry(sc, rc, n, cnt, entry, g);
-  NuRec<R> out;
-  out.valid = g.valid;
-  NuDer<R> der;
-  der.item = entry;
-  double bc = 0.0;
-  double dbr[3][R], dbi[3][R], dbc[3] = {0.0, 0.0, 0.0};
-  const double h2 = 0.5 / kNuDerStep;
+  const bool live = item < cnt;
+  int kind = 0;
+  if (live) {
+    Geo g;
+    entry_geometry(sc, rc, n, cnt, item, g);
+    int far;
+    kind = nufft_classify(g, ns, &far);
+    NuRecF<false> out;
+    double sd[10];
+    nufft_fill(g, g.beta, ns, kind, far, sd);
 #pragma unroll
-  for (int e = 0; e < 7; ++e) {  // the facet's offsets, then each one moved by +h and -h
-    double bt[3] = {g.beta[0], g.beta[1], g.beta[2]};
-    const int v = (e - 1) >> 1;
-    const double sgn = ((e - 1) & 1) ? -1.0 : 1.0;
-    if (e > 0) bt[v] += sgn * kNuDerStep;
-    double cr[R], ci[R];
-    const double c = taylor_coeffs<R>(g, bt, sub, ns.split, ns, cr, ci);
-    if (e == 0) {
-      bc = c;
+    for (int k = 0; k < 10; ++k) out.s[k] = static_cast<float>(sd[k]);
+    out.kind = kind;
+    out.ext[0] = out.ext[1] = 0.0f;
+    double Rt, Rr, dxc;
+    path_fields(g, rc, ns, 0.0, out, &Rt, &Rr, &dxc);
+    NuDerF der;
+    der.item = item;
+    der.pad = 0;
+    const double h2 = 0.5 / kNuDerStep;
+    for (int v = 0; v < 3; ++v) {
+      double bp[3] = {g.beta[0], g.beta[1], g.beta[2]}, bm[3] = {g.beta[0], g.beta[1], g.beta[2]};
+      bp[v] += kNuDerStep;
+      bm[v] -= kNuDerStep;
+      double sp[10], sm[10];
+      nufft_fill(g, bp, ns, kind, far, sp);
+      nufft_fill(g, bm, ns, kind, far, sm);
 #pragma unroll
-      for (int k = 0; k < R; ++k) out.b[k] = {static_cast<float>(cr[k]), static_cast<float>(ci[k])};
-    } else if (sgn > 0.0) {
+      for (int k = 0; k < 10; ++k) der.ds[v][k] = static_cast<float>((sp[k] - sm[k]) * h2);
+    }
+    const int64_t at = static_cast<int64_t>(nl) * ns.rec_stride + item;  // entry order
+    static_cast<NuRecF<false> *>(nb.srec)[at] = out;
+    static_cast<NuDerF *>(nb.sder)[at] = der;
+    if (kind == 0) {
+      float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + item) * kAdjVals;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        dbr[v][k] = cr[k];
-        dbi[v][k] = ci[k];
-      }
-      dbc[v] = c;
-    } else {
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        der.db[v][k] = {static_cast<float>((dbr[v][k] - cr[k]) * h2),
-                        static_cast<float>((dbi[v][k] - ci[k]) * h2)};
-      }
-      der.dx[v] = static_cast<float>(-ns.kappa * (dbc[v] - c) * h2);
+      for (int k = 0; k < kAdjVals; ++k) slot[k] = 0.0f;
     }
   }
-  double Rt, Rr, dxc;
-  path_fields(g, rc, ns, bc, out, &Rt, &Rr, &dxc);
-  const int64_t at = static_cast<int64_t>(nl) * ns.rec_stride + item;  // entry order
-  static_cast<NuRec<R> *>(nb.srec)[at] = out;
-  static_cast<NuDer<R> *>(nb.sder)[at] = der;
+  // wave-aggregated appends to the two class lists
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const bool mine = live && kind != 0 && (kind == 1) == (c == 0);
+    const uint64_t m = __ballot(mine);
+    if (!m) continue;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(&nb.n_runs[2 * nl + c], __popcll(m));
+    base = __shfl(base, leader);
+    if (mine)
+      nb.key[(static_cast<int64_t>(2 * nl + c)) * ns.rec_stride + base +
+             __popcll(m & ((uint64_t(1) << lane) - 1))] = item;
+  }
 }
 
 // Per (chirp, group of cb channels): the transpose of nufft_fft_kernel. conj(G) of the kept
@@ -958,6 +966,7 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
 __global__ void __launch_bounds__(kNuFftThreads) nufft_adj_fft_kernel(
     DevScene sc, RadarConst rc, NuShape ns, NuBuffers nb, const float2 *tw,
     const float2 *grad_echo) {
+
   extern __shared__ float2 nu_smem[];
   const int nl = blockIdx.x / ns.groups;
   const int grp = blockIdx.x - nl * ns.groups;
@@ -997,20 +1006,62 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_adj_fft_kernel(
   }
 }
 
-// One lane per (chirp, record), a workgroup per (chirp, kNuGatherRecs records in entry
-// order), looping over the channels: each channel's grid row of the chirp is staged in LDS
-// and every lane forms the moments mu_0 .. mu_R of its own 13 cells about its own position
-// (|l - x| <= kNuWidth / 2, the spread's truncation), then adds this channel's share of the
-// seven per-facet sums in registers: Re y, Re dy/dx and Q mu_k (for dL/dbeta_v, applied once
-// per record with d b_k / d beta_v) and dL/dc through the channel's distances. One atomic add
-// per value and record into partial[chirp][lit facet][kAdjVals] (sub-triangles of a facet
-// add into the same slot). Blocks are ordered so that those of one chirp share an XCD (and
-// its L2, which holds the chirp's grids).
-template <int R>
+__global__ void __launch_bounds__(256) fill_zero_i32_kernel(int32_t *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Moments mu_0 .. mu_{K-1} of a staged grid row about the position xs (cells from the
+// record's cell rc0): the 13 cells from ceil(xs - W/2) (a 13th cell past xs + W/2 carries a
+// weight below 4e-7).
+template <int K>
+__device__ __forceinline__ void row_moments(const float2 *row, int ng, int rc0, float xs,
+                                            float nc, float q_ratio, float2 (&mu)[K]) {
+  const float s0 = ceilf(xs - 0.5f * kNuWidth);
+  int cell = (rc0 + static_cast<int>(s0)) % ng;  // rc0 + s0 lies in (-ng, 2 ng)
+  cell += (cell < 0) ? ng : 0;
+  const float u0 = s0 - xs;
+  float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+  float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+#pragma unroll
+  for (int k = 0; k < K; ++k) mu[k] = {0.0f, 0.0f};
+#pragma unroll
+  for (int j = 0; j <= kNuWidth; ++j) {
+    const float2 gv = row[cell];
+    cell = (cell + 1 == ng) ? 0 : cell + 1;
+    const float u = u0 + static_cast<float>(j);
+    const float wr = gw * gv.x, wi = gw * gv.y;
+    mu[0].x += wr;
+    mu[0].y += wi;
+    float up = 1.0f;
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      up *= u;
+      mu[k].x = fmaf(wr, up, mu[k].x);
+      mu[k].y = fmaf(wi, up, mu[k].y);
+    }
+    gw *= rho;
+    rho *= q_ratio;
+  }
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// One lane per (chirp, record of one class), a workgroup per (chirp, class, kNuGatherRecs
+// list entries), looping over the channels: each channel's grid row of the chirp is staged
+// in LDS and every lane forms the moments at its own sources, then adds this channel's
+// share of the per-facet sums in registers: Re y, dL/dc through the channel's distances,
+// and per source parameter sum_o Q mu (weights, coefficients) and sum_o dy/dx_s (offsets).
+// Class 0: three points (kind 1); class 1: a point (zero weight for kind 3) and a
+// quadratic. Blocks are ordered so that those of one chirp share an XCD (and its L2, which
+// holds the chirp's grids).
+template <int CLS>
 __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
-    DevScene sc, RadarConst rc, NuShape ns, const double *elem, const NuRec<R> *__restrict__ recs,
-    const NuDer<R> *__restrict__ ders, const float2 *__restrict__ grids, float *partial,
-    int blocks_per_chirp) {
+    DevScene sc, RadarConst rc, NuShape ns, const double *elem,
+    const NuRecF<false> *__restrict__ recs, const NuDerF *__restrict__ ders,
+    const int32_t *__restrict__ lists, const int32_t *__restrict__ counts,
+    const float2 *__restrict__ grids, float *partial, int blocks_per_chirp) {
   extern __shared__ float2 nu_row[];  // [n_g]
   const int per_xcd = (gridDim.x + kXcds - 1) / kXcds;  // gridDim.x is a multiple of kXcds
   const int logical = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
@@ -1018,23 +1069,38 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
   if (nl >= ns.n_chirps) return;  // padding blocks (whole workgroup, before any barrier)
   const int rb = logical - nl * blocks_per_chirp;
   const int n = ns.n0 + nl;
-  const int32_t n_ent = sc.vis_cnt[n] << (2 * ns.split);
-  if (rb * kNuGatherRecs >= n_ent) return;  // whole workgroup
-  const int32_t e = rb * kNuGatherRecs + static_cast<int32_t>(threadIdx.x);
-  const bool live = e < n_ent;
+  const int32_t count = counts[2 * nl + CLS];
+  if (rb * kNuGatherRecs >= count) return;  // whole workgroup
+  const int32_t idx = rb * kNuGatherRecs + static_cast<int32_t>(threadIdx.x);
+  const bool on = idx < count;
+  const int32_t item =
+      on ? lists[static_cast<int64_t>(2 * nl + CLS) * ns.rec_stride + idx] : 0;
   const int ng = ns.ng;
   const int O = rc.P * rc.Q;
-  const int64_t rec_at = static_cast<int64_t>(nl) * ns.rec_stride + (live ? e : 0);
-  const NuRec<R> r = recs[rec_at];
-  const bool on = live && r.valid;
-  float2 b[R];
+  const int64_t rec_at = static_cast<int64_t>(nl) * ns.rec_stride + item;
+  const NuRecF<false> r = recs[on ? rec_at : static_cast<int64_t>(nl) * ns.rec_stride];
+  // sources: class 0: points j = 0..2 at s[3j]; class 1: a point at s[0] and the quadratic
+  // at s[3]
+  constexpr int NP = CLS == 0 ? 3 : 1;
+  float offp[NP];
+  float2 wp[NP];
 #pragma unroll
-  for (int k = 0; k < R; ++k) b[k] = on ? r.b[k] : make_float2(0.0f, 0.0f);
+  for (int j = 0; j < NP; ++j) {
+    offp[j] = r.s[3 * j];
+    wp[j] = on ? make_float2(r.s[3 * j + 1], r.s[3 * j + 2]) : make_float2(0.0f, 0.0f);
+  }
+  float offq = 0.0f;
+  float2 cq[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
+  if (CLS == 1) {
+    offq = r.s[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      cq[k] = on ? make_float2(r.s[4 + 2 * k], r.s[5 + 2 * k]) : make_float2(0.0f, 0.0f);
+  }
   const float utf[3] = {static_cast<float>(r.ut[0]), static_cast<float>(r.ut[1]),
                         static_cast<float>(r.ut[2])};
   const float urf[3] = {static_cast<float>(r.ur[0]), static_cast<float>(r.ur[1]),
                         static_cast<float>(r.ur[2])};
-  // positions relative to the record's cell (small numbers: FP32 keeps ~1e-6 cells)
   const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
   const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
   const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
@@ -1042,11 +1108,12 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
   const float g2 = static_cast<float>(0.5 * rc.slope / (kC0 * kC0));
   const float two_pi = static_cast<float>(2.0 * kPi);
   const float g1f = static_cast<float>(r.g1);
-  const float half_w = 0.5f * kNuWidth;
-  float acc_c[3] = {0.0f, 0.0f, 0.0f}, acc_s = 0.0f, acc_yx = 0.0f;
-  float acc_mr[R], acc_mi[R];
+  float acc_c[3] = {0.0f, 0.0f, 0.0f}, acc_s = 0.0f;
+  float2 aw[NP], ax[NP], ac[3], axq = {0.0f, 0.0f};
 #pragma unroll
-  for (int k = 0; k < R; ++k) acc_mr[k] = acc_mi[k] = 0.0f;
+  for (int j = 0; j < NP; ++j) aw[j] = ax[j] = {0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ac[k] = {0.0f, 0.0f};
   const float2 *grow = grids + static_cast<int64_t>(nl) * O * ng;
   for (int o = 0; o < O; ++o) {
     __syncthreads();  // the previous channel's row is no longer read
@@ -1082,61 +1149,61 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     const float Rtp = r.rt + dRt, Rrq = r.rr + dRr;
     const float irt = __builtin_amdgcn_rcpf(Rtp), irr = __builtin_amdgcn_rcpf(Rrq);
     const float amp = irt * irr;
-    const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
-    // moments of the grid row about x over the cells |l - x| <= W / 2 (13 cells from
-    // ceil(x - W / 2); a 13th cell past x + W / 2 carries a weight below 4e-7)
-    const float s0 = ceilf(x - half_w);
-    int cell = (r.cell + static_cast<int>(s0)) % ng;  // r.cell + s0 lies in (-ng, 2 ng)
-    cell += (cell < 0) ? ng : 0;
-    const float u0 = s0 - x;
-    float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
-    float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
-    float2 mu[R + 1];
+    const float2 Q = {__builtin_amdgcn_cosf(t) * amp, -__builtin_amdgcn_sinf(t) * amp};
+    // y / Q and (dy/dx) / Q over the sources; per-parameter sums
+    float2 y = {0.0f, 0.0f}, yx = {0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k <= R; ++k) mu[k] = {0.0f, 0.0f};
-#pragma unroll
-    for (int j = 0; j <= kNuWidth; ++j) {
-      const float2 gv = nu_row[cell];
-      cell = (cell + 1 == ng) ? 0 : cell + 1;
-      const float u = u0 + static_cast<float>(j);
-      const float wr = gw * gv.x, wi = gw * gv.y;
-      mu[0].x += wr;
-      mu[0].y += wi;
-      float up = 1.0f;
-#pragma unroll
-      for (int k = 1; k <= R; ++k) {
-        up *= u;
-        mu[k].x = fmaf(wr, up, mu[k].x);
-        mu[k].y = fmaf(wi, up, mu[k].y);
-      }
-      gw *= rho;
-      rho *= q_ratio;
+    for (int j = 0; j < NP; ++j) {
+      float2 mu[2];
+      row_moments<2>(nu_row, ng, r.cell, x - offp[j], nc, q_ratio, mu);
+      const float2 ys = cmul(wp[j], mu[0]);
+      const float2 yxs = cmul(wp[j], make_float2(mu[1].x * inv_s2, mu[1].y * inv_s2));
+      y.x += ys.x;
+      y.y += ys.y;
+      yx.x += yxs.x;
+      yx.y += yxs.y;
+      const float2 qm = cmul(Q, mu[0]), qx = cmul(Q, yxs);
+      aw[j].x += qm.x;
+      aw[j].y += qm.y;
+      ax[j].x += qx.x;
+      ax[j].y += qx.y;
     }
-    // Q mu_k; y and dy/dx
-    float2 qm[R + 1];
+    if (CLS == 1) {
+      float2 mu[4];
+      row_moments<4>(nu_row, ng, r.cell, x - offq, nc, q_ratio, mu);
+      float2 yp = {0.0f, 0.0f}, yxp = {0.0f, 0.0f};
 #pragma unroll
-    for (int k = 0; k <= R; ++k) qm[k] = {qx * mu[k].x - qy * mu[k].y, qx * mu[k].y + qy * mu[k].x};
-    float yr = 0.0f, yi = 0.0f, yxr = 0.0f;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      yr += b[k].x * qm[k].x - b[k].y * qm[k].y;
-      yi += b[k].x * qm[k].y + b[k].y * qm[k].x;
-      float nr = qm[k + 1].x * inv_s2, ni = qm[k + 1].y * inv_s2;
-      if (k > 0) {
-        nr = fmaf(-static_cast<float>(k), qm[k - 1].x, nr);
-        ni = fmaf(-static_cast<float>(k), qm[k - 1].y, ni);
+      for (int k = 0; k < 3; ++k) {
+        const float2 a = cmul(cq[k], mu[k]);
+        yp.x += a.x;
+        yp.y += a.y;
+        float2 d = {mu[k + 1].x * inv_s2, mu[k + 1].y * inv_s2};
+        if (k > 0) {
+          d.x = fmaf(-static_cast<float>(k), mu[k - 1].x, d.x);
+          d.y = fmaf(-static_cast<float>(k), mu[k - 1].y, d.y);
+        }
+        const float2 b = cmul(cq[k], d);
+        yxp.x += b.x;
+        yxp.y += b.y;
+        const float2 qm = cmul(Q, mu[k]);
+        ac[k].x += qm.x;
+        ac[k].y += qm.y;
       }
-      yxr += b[k].x * nr - b[k].y * ni;
-      acc_mr[k] += qm[k].x;
-      acc_mi[k] += qm[k].y;
+      y.x += yp.x;
+      y.y += yp.y;
+      yx.x += yxp.x;
+      yx.y += yxp.y;
+      const float2 qx = cmul(Q, yxp);
+      axq.x += qx.x;
+      axq.y += qx.y;
     }
-    acc_s += yr;
-    acc_yx += yxr;
+    const float2 Y = cmul(Q, y), YX = cmul(Q, yx);
+    acc_s += Y.x;
     // dL/dc through the element distances: d Re y / dR = K Im y + kappa Re(dy/dx) - Re y / R
     // (K = 2 pi (f_c - mu tau) / c of this channel), with dR_tp / dc = -e_p
     const float K = two_pi * fmaf(-2.0f * g2, dL, g1f);
-    const float A = fmaf(K, yi, kappa * yxr);
-    const float ct = A - yr * irt, cr = A - yr * irr;
+    const float A = fmaf(K, Y.y, kappa * YX.x);
+    const float ct = A - Y.x * irt, cr = A - Y.x * irr;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float ep = (static_cast<float>(at[k]) - r.rt * utf[k]) * irt;
@@ -1145,20 +1212,28 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     }
   }
   if (!on) return;
-  // dL/dbeta_v = Re sum_k (d b_k / d beta_v) sum_o Q mu_k + (dx / dbeta_v) sum_o Re(dy/dx)
-  const NuDer<R> dv = ders[rec_at];
+  // dL/dbeta_v = Re sum (d param / d beta_v) (its sum) - Re sum (d off / d beta_v) sum dy/dx
+  const NuDerF dv = ders[rec_at];
   float tv[3];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    float a = dv.dx[v] * acc_yx;
+    float a = 0.0f;
 #pragma unroll
-    for (int k = 0; k < R; ++k) a += dv.db[v][k].x * acc_mr[k] - dv.db[v][k].y * acc_mi[k];
+    for (int j = 0; j < NP; ++j) {
+      a += aw[j].x * dv.ds[v][3 * j + 1] - aw[j].y * dv.ds[v][3 * j + 2];
+      a -= ax[j].x * dv.ds[v][3 * j];
+    }
+    if (CLS == 1) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a += ac[k].x * dv.ds[v][4 + 2 * k] - ac[k].y * dv.ds[v][5 + 2 * k];
+      a -= axq.x * dv.ds[v][3];
+    }
     tv[v] = a;
   }
   float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + dv.item) * kAdjVals;
-  const float vals[kAdjVals - 1] = {acc_c[0], acc_c[1], acc_c[2], acc_s, tv[0], tv[1], tv[2]};
+  const float vals[kAdjVals] = {acc_c[0], acc_c[1], acc_c[2], acc_s, tv[0], tv[1], tv[2], 0.0f};
 #pragma unroll
-  for (int k = 0; k < kAdjVals - 1; ++k) atomicAdd(&slot[k], vals[k]);
+  for (int k = 0; k < kAdjVals; ++k) slot[k] = vals[k];
 }
 
 size_t nufft_smem_bytes(const NuShape &ns) {
@@ -1167,6 +1242,13 @@ size_t nufft_smem_bytes(const NuShape &ns) {
 size_t nufft_fft_smem_bytes(const NuShape &ns) {
   return nufft_smem_bytes(ns) + sizeof(int32_t) * static_cast<size_t>(ns.max_runs);
 }
+// Cells a source covers over all channels of a wave: the integers within W/2 + chan_d of
+// its position, rounded up to a compiled block length (14, 16 or 20; 0 beyond).
+int nufft_cells_per_source(const NuShape &ns) {
+  const int need = static_cast<int>(std::floor(2.0 * (ns.chan_d + 0.5 * kNuWidth))) + 1;
+  return need <= 14 ? 14 : need <= 16 ? 16 : need <= 20 ? 20 : 0;
+}
+
 size_t nufft_sort_smem_bytes(const NuShape &ns) {
   return sizeof(int32_t) * (static_cast<size_t>(kNuSortWaves) * ns.ng + ns.ng + 1 + kNuSortThreads);
 }
@@ -1191,9 +1273,24 @@ static hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const
     const int per_block = groups < 4 ? groups : 4;
     dim3 sgrid(static_cast<unsigned>(ns.max_runs), static_cast<unsigned>(ns.n_chirps),
                static_cast<unsigned>((groups + 3) / 4));
-    hipLaunchKernelGGL((nufft_spread_kernel<INTRA>), sgrid, dim3(64 * per_block), 0, s, sc, rc,
-                       ns, elem, static_cast<const NuRecF<INTRA> *>(nb.srec), nb.runs, nb.n_runs,
-                       nb.grid);
+    const auto *recs = static_cast<const NuRecF<INTRA> *>(nb.srec);
+    const dim3 blk(64 * per_block);
+    switch (nufft_cells_per_source(ns)) {
+      case 14:
+        hipLaunchKernelGGL((nufft_spread_kernel<INTRA, 14>), sgrid, blk, 0, s, sc, rc, ns, elem,
+                           recs, nb.runs, nb.n_runs, nb.grid);
+        break;
+      case 16:
+        hipLaunchKernelGGL((nufft_spread_kernel<INTRA, 16>), sgrid, blk, 0, s, sc, rc, ns, elem,
+                           recs, nb.runs, nb.n_runs, nb.grid);
+        break;
+      case 20:
+        hipLaunchKernelGGL((nufft_spread_kernel<INTRA, 20>), sgrid, blk, 0, s, sc, rc, ns, elem,
+                           recs, nb.runs, nb.n_runs, nb.grid);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
@@ -1212,39 +1309,37 @@ hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *
                   : launch_nufft_t<false>(sc, rc, elem, ns, nb, tw, s);
 }
 
-template <int R>
-hipError_t launch_nufft_adjoint_t(const DevScene &sc, const RadarConst &rc, const double *elem,
-                                  const NuShape &ns, const NuBuffers &nb, const void *tw,
-                                  const void *grad_echo, float *partial, hipStream_t s) {
+hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
+                                const NuShape &ns, const NuBuffers &nb, const void *tw,
+                                const void *grad_echo, float *partial, hipStream_t s) {
   if (ns.n_chirps <= 0) return hipSuccess;
-  if (sizeof(NuRec<R>) > nb.rec_bytes || !nb.sder || sc.n_points != 0 || rc.intra)
+  if (sizeof(NuRecF<false>) > nb.rec_bytes || !nb.sder || !nb.key || !nb.n_runs ||
+      sc.n_points != 0 || rc.intra)
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(nufft_adj_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
                      dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
                      static_cast<const float2 *>(tw), static_cast<const float2 *>(grad_echo));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t items = sc.n_facets << (2 * ns.split);
+  const int64_t items = sc.n_facets;
   if (items == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_i32_kernel, dim3(1), dim3(256), 0, s, nb.n_runs, 2 * ns.n_chirps);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
-  hipLaunchKernelGGL((nufft_adj_prep_kernel<R>), grid, dim3(256), 0, s, sc, rc, ns, nb);
+  hipLaunchKernelGGL(nufft_adj_prep_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb, partial);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int bpc = static_cast<int>((items + kNuGatherRecs - 1) / kNuGatherRecs);
   const int64_t blocks = (static_cast<int64_t>(ns.n_chirps) * bpc + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL((nufft_gather_kernel<R>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem,
-                     static_cast<const NuRec<R> *>(nb.srec), static_cast<const NuDer<R> *>(nb.sder),
-                     static_cast<const float2 *>(nb.grid), partial, bpc);
+  const auto *recs = static_cast<const NuRecF<false> *>(nb.srec);
+  const auto *ders = static_cast<const NuDerF *>(nb.sder);
+  hipLaunchKernelGGL((nufft_gather_kernel<0>), dim3(static_cast<unsigned>(blocks)),
+                     dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem, recs, ders,
+                     nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((nufft_gather_kernel<1>), dim3(static_cast<unsigned>(blocks)),
+                     dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem, recs, ders,
+                     nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   return hipGetLastError();
-}
-
-hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
-                                const NuShape &ns, const NuBuffers &nb, const void *tw,
-                                const void *grad_echo, float *partial, hipStream_t s) {
-  if (ns.order == 5) return launch_nufft_adjoint_t<5>(sc, rc, elem, ns, nb, tw, grad_echo, partial, s);
-  if (ns.order == 7) return launch_nufft_adjoint_t<7>(sc, rc, elem, ns, nb, tw, grad_echo, partial, s);
-  if (ns.order == 10) return launch_nufft_adjoint_t<10>(sc, rc, elem, ns, nb, tw, grad_echo, partial, s);
-  return hipErrorInvalidValue;
 }
 
 }  // namespace rsim

@@ -66,11 +66,9 @@ constexpr double kNuSigma = 1.1;
 constexpr int kNuSlots = 32;
 struct NuShape {
   int32_t ng, ld, cb, groups;  // grid cells, LDS row stride, channels per FFT workgroup, groups
-  int32_t order;               // adjoint: Taylor terms of a record (5, 7 or 10)
   int32_t n0, n_chirps;        // chirps of this launch: n0 .. n0 + n_chirps - 1
-  int32_t runs;                // adjoint: unused by the kernels
   int32_t spread_groups;       // 64-channel groups of the spread
-  int32_t split;               // adjoint: facets split into 4^split sub-triangles (midpoints)
+  int32_t pad1;
   int64_t rec_stride;          // records per chirp (forward: lit facets + points)
   double chan_d;               // largest grid offset of a channel from the phase-centre path
   double fc, kc;               // f0 + (M/2) df; 2 pi fc / c
@@ -89,8 +87,7 @@ struct NuShape {
 // Work buffers of one launch (n_chirps chirps). Forward: per (chirp, entry) the grid cell
 // and the position in cell order, the records in that order, per chirp the runs
 // (first record, end, window base cell) and their count, and per (chirp, run, channel)
-// the window of kNuSlots cells. Adjoint: records and adjoint records in entry order and
-// grids [chirp][O][ng].
+// the window of kNuSlots cells. Adjoint: see launch_nufft_adjoint.
 struct NuBuffers {
   int32_t *key;
   int32_t *pos;
@@ -102,11 +99,11 @@ struct NuBuffers {
   int32_t *n_runs;   // forward: [chirp]
 };
 size_t nufft_record_bytes(bool intra);
-size_t nufft_adj_record_bytes(int order);
-size_t nufft_der_bytes(int order);
+size_t nufft_der_bytes();
 size_t nufft_smem_bytes(const NuShape &ns);
 size_t nufft_fft_smem_bytes(const NuShape &ns);
 size_t nufft_sort_smem_bytes(const NuShape &ns);
+int nufft_cells_per_source(const NuShape &ns);  // 14, 16 or 20; 0: channels too far apart
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
                         const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s);
@@ -118,9 +115,10 @@ constexpr int kAdjSlotFloats = 8;
 hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
                                  const float *partial, float *gxw, hipStream_t s);
 // Adjoint of launch_nufft for one chunk of chirps (stop-and-hop, facets only: sc.n_points
-// must be 0): adds the per-(chirp, lit facet) adjoint sums into partial
-// [N][n_facets][kAdjVals] (zero before the first chunk). Uses nb.srec and nb.sder (records
-// in entry order) and nb.grid; nb.key and nb.pos are not used.
+// must be 0): writes the per-(chirp, lit facet) adjoint sums into partial
+// [N][n_facets][kAdjVals]. Uses nb.srec and nb.sder (records in entry order, rec_stride per
+// chirp), nb.key (per chirp two lists of rec_stride entries: three-point records, others),
+// nb.n_runs (their two counts per chirp) and nb.grid (grid rows [chirp][O][n_g]).
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
                                 const void *grad_echo, float *partial, hipStream_t s);

@@ -223,9 +223,9 @@ def test_nufft_refusals_host_only():
 
 def test_nufft_adjoint_refusals_host_only():
     """The NUFFT adjoint (rsim_set_backward_kernel(RSIM_KERNEL_NUFFT)), eligibility
-    decided on the host: a coarse box beyond 64 sub-triangles is ERANGE, an
-    eligible scene reaches the missing device, AUTO never refuses for it, and kernel codes
-    beyond NUFFT are EINVAL."""
+    decided on the host: its gather reads each source's own cells, so coarse facets (a 4 m
+    box) are eligible and reach the missing device; a grid beyond 2048 cells (M = 1100) is
+    ERANGE, AUTO never refuses for it, and kernel codes beyond NUFFT are EINVAL."""
     ctx = _host_ctx()
     L = rsim.lib()
     wf = scenes.paper_waveform(256, 8)
@@ -247,10 +247,13 @@ def test_nufft_adjoint_refusals_host_only():
 
     assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT) == rsim.RSIM_OK
     assert bwd(ids[0]) == rsim.RSIM_EDEVICE
-    assert bwd(ids[1]) == rsim.RSIM_ERANGE
-    assert b"grid cells" in L.rsim_last_error(ctx._h)
-    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_AUTO) == rsim.RSIM_OK
     assert bwd(ids[1]) == rsim.RSIM_EDEVICE
+    ctx.set_waveform(scenes.paper_waveform(1100, 8))
+    assert bwd(ids[0]) == rsim.RSIM_ERANGE
+    assert b"2048" in L.rsim_last_error(ctx._h)
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_AUTO) == rsim.RSIM_OK
+    assert bwd(ids[0]) == rsim.RSIM_EDEVICE
+    ctx.set_waveform(wf)
     assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT + 1) == rsim.RSIM_EINVAL
     assert L.rsim_set_nufft_chunk(ctx._h, -1) == rsim.RSIM_EINVAL
     assert L.rsim_set_nufft_chunk(ctx._h, 3) == rsim.RSIM_OK
