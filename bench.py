@@ -44,34 +44,37 @@ MFMA_FLOP_PER_EVAL = 8
 # FP32 FMA issue without packed-math instructions, which this build keeps out of all
 # device code: 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz.
 PEAK_FP32_NON_PACKED = 256 * 4 * 16 * 2 * 2.4e9
-# NUFFT facet sum (type-1 non-uniform FFT over the sample index): spread width (grid
-# cells) and Taylor terms on this workload (facet spread bound 0.27 cells <= 0.35).
+# NUFFT facet sum (type-1 non-uniform FFT over the sample index): every lit (facet or
+# point, chirp) record becomes one to three Gaussian grid sources per channel, spread over
+# the NUFFT_WIDTH cells within half that width of each source.
 NUFFT_WIDTH = 12
-NUFFT_ORDER = 5
+# Algorithmic FP32/FP64 FLOP of the spread per (record, channel), by part:
+#  * setup, once per (record, channel): the channel's path difference from the record's
+#    phase-centre path (two FP64 dot products and the phase in turns, 13), the second-order
+#    range corrections, amplitude, phase reduction and grid position (FP32, 35) and the
+#    channel's complex factor (cos, sin: 2);
+#  * a point source: its complex weight times the channel factor (6), the Gaussian's
+#    start value and ratio (8); per cell the Gaussian-weighted complex accumulation
+#    (2 FMA, 4) and the Gaussian recurrence (2 multiplies);
+#  * a quadratic-weighted source: three complex coefficients times the channel factor
+#    (18), the Gaussian start (8); per cell the abscissa (1), the degree-2 complex Horner
+#    step (2 x 2 FMA, 8), the accumulation (4) and the recurrence (2).
+NUFFT_SETUP_FLOP = 50
+NUFFT_POINT_FLOP = 14 + NUFFT_WIDTH * 6
+NUFFT_QUAD_FLOP = 26 + NUFFT_WIDTH * 15
+# per form of rsim_last_census: none, three points, point + quadratic, one quadratic
+NUFFT_FORM_FLOP = {
+    "none": 0,
+    "three_points": NUFFT_SETUP_FLOP + 3 * NUFFT_POINT_FLOP,
+    "point_and_quadratic": NUFFT_SETUP_FLOP + NUFFT_POINT_FLOP + NUFFT_QUAD_FLOP,
+    "quadratic": NUFFT_SETUP_FLOP + NUFFT_QUAD_FLOP,
+}
 
 
-# FP64 work per lit entry of the NUFFT preparation: facet geometry (~100), the divided
-# differences of exp(j k_c beta) (~100), Taylor coefficients and the phase-centre path
-# (~100).
-NUFFT_PREP_FLOP = 300
-
-
-def nufft_unit_flop():
-    """Spread FLOP per (lit entry, channel, chirp) unit: the coefficient scaling (R
-    complex products, 6 R), the channel's path difference and phase (30), and per grid
-    cell the Horner polynomial (R - 1 complex-by-real steps, 4 (R - 1)), the Gaussian
-    weight recurrence (3), the weighting (2) and the accumulation (2)."""
-    R, W = NUFFT_ORDER, NUFFT_WIDTH
-    return 6 * R + 30 + W * (4 * (R - 1) + 7)
-
-
-def nufft_flop(units, entries, rows, ng, M):
-    """Algorithmic FLOP of one NUFFT facet-sum stage: spread units x nufft_unit_flop,
-    entries x NUFFT_PREP_FLOP, and per (channel, chirp) row an n_g-point FFT
-    (5 n_g log2 n_g) and the deconvolution of M samples (2 M)."""
-    import math
-    return (units * nufft_unit_flop() + entries * NUFFT_PREP_FLOP +
-            rows * (5 * ng * math.log2(ng) + 2 * M))
+def nufft_spread_flop(census, channels):
+    """Algorithmic FLOP of the NUFFT spread over one frame: records of each source form
+    (the library's census) x channels x the form's FLOP per (record, channel)."""
+    return sum(census[k] * channels * NUFFT_FORM_FLOP[k] for k in NUFFT_FORM_FLOP)
 
 
 PROFILE_TRAFFIC = {"vector": "facet_sum_{w}_traffic.json",
@@ -115,8 +118,9 @@ def _src_hash(kernel="vector"):
 
 
 def _traffic(kernel, workload):
-    """HBM bytes per facet-sum launch from the committed counter summary of this kernel
-    and workload, if it was taken on the current kernel source."""
+    """HBM bytes of the roofline's unit (direct sums: one facet-sum launch; NUFFT: the
+    spread's launches of one frame) from the committed counter summary of this kernel and
+    workload, if it was taken on the current kernel source."""
     try:
         with open(os.path.join(ROOT, "profiles", PROFILE_TRAFFIC[kernel].format(w=workload))) as f:
             d = json.load(f)
@@ -124,21 +128,24 @@ def _traffic(kernel, workload):
         return None
     if d.get("echo_hip_sha256_16") != _src_hash(kernel):
         return None
-    return d.get("bytes_per_launch")
+    return d.get("bytes_per_frame" if kernel == "nufft" else "bytes_per_launch")
 
 
-def roofline(kernel, evals, fs_ms, shape=None, workload="c3"):
-    """Roofline object of the facet-sum kernel: algorithmic FLOP per launch (direct sums:
-    FLOP_PER_EVAL per evaluation; NUFFT: nufft_flop) over the launch's measured duration,
-    against the published FP32 peak of the units the kernel runs on."""
+def roofline(kernel, evals, fs_ms, shape=None, workload="c3", nufft=None):
+    """Roofline object of the facet sum's dominant kernel: algorithmic FLOP per launch
+    over the launch's measured duration against the published FP32 peak of the units it
+    runs on. Direct sums: FLOP_PER_EVAL per evaluation over the facet-sum launch. NUFFT:
+    the spread kernel alone (nufft = {"census", "spread_ms"}: records by source form over
+    the frame and the summed event time of the spread's launches in the frame, one per
+    chunk of chirps), nufft_spread_flop over that time; weighting each launch by its work
+    this is the per-launch figure."""
     rate = evals / (fs_ms * 1e-3)
     achieved = FLOP_PER_EVAL * rate
     if kernel == "nufft":
-        O, N, M = shape
-        ng = 2 * M  # 2^a 3^b already for M = 256 and 512
-        units = evals // M
-        flop = nufft_flop(units, units // O, O * N, ng, M)
-        ach = flop / (fs_ms * 1e-3)
+        O = shape[0]
+        census, sp_ms = nufft["census"], nufft["spread_ms"]
+        flop = nufft_spread_flop(census, O)
+        ach = flop / (sp_ms * 1e-3)
         return {
             "bound": "alu",
             "achieved": ach / 1e12,
@@ -146,13 +153,15 @@ def roofline(kernel, evals, fs_ms, shape=None, workload="c3"):
             "unit": "TFLOP/s",
             "frac": ach / PEAK_FP32_VECTOR,
             "traffic": _traffic("nufft", workload),
-            "kernel": "facet-sum stage of five launches, dominated by "
-                      "rsim::nufft_spread_kernel<5> (type-1 NUFFT: Taylor-expanded Gaussian "
-                      "spread in registers, then in-LDS FFT and deconvolution)",
-            "flop_per_launch": flop,
-            "units_per_launch": units,
-            "flop_per_unit": nufft_unit_flop(),
+            "kernel": "rsim::nufft_spread_kernel (type-1 NUFFT spread: each run of "
+                      "cell-sorted records adds its Gaussian grid sources into a per-channel "
+                      "register window of 32 cells)",
+            "spread_ms_per_frame": sp_ms,
+            "flop_per_frame": flop,
+            "records_by_form": census,
+            "flop_per_record_channel": NUFFT_FORM_FLOP,
             "frac_of_non_packed_fp32_peak": ach / PEAK_FP32_NON_PACKED,
+            "facet_sum_stage_ms": fs_ms,
             "direct_sum_equivalent_tflops": achieved / 1e12,
         }
     if kernel == "matrix":
@@ -309,17 +318,30 @@ def measure_other_kernel(sim, echo, mask, kernel, evals, workload, reps=2):
     kc = KERNEL_CODES[kernel]
     buf = torch.empty_like(echo)
     sim.ctx.synthesize([sim.scene_ids[0]], buf, mask, kernel=kc)
-    ts = []
+    ts, sp = [], []
     for _ in range(reps):
         sim.ctx.synthesize([sim.scene_ids[0]], buf, mask, timing=True, kernel=kc)
-        ts.append(sim.ctx.last_timings()["facet_sum"])
+        t = sim.ctx.last_timings()
+        ts.append(t["facet_sum"])
+        sp.append(t["nufft_spread"])
     torch.cuda.synchronize()
     fs = float(np.median(ts))
+    nu = nufft_info(sim, mask, float(np.median(sp))) if kernel == "nufft" else None
     d = (buf - ref).abs().pow(2).sum().sqrt() / ref.abs().pow(2).sum().sqrt()
     wf = sim.wf
     return {"kernel": kernel, "facet_sum_ms": fs,
-            "roofline": roofline(kernel, evals, fs, (sim.O, wf.n_chirps, wf.n_samples), workload),
+            "roofline": roofline(kernel, evals, fs, (sim.O, wf.n_chirps, wf.n_samples), workload,
+                                 nu),
             "rel_rms_vs_main": float(d)}
+
+
+def nufft_info(sim, mask, spread_ms):
+    """The NUFFT roofline's inputs: the record census of one untimed NUFFT call on the same
+    frame (visibility mask as given) and the spread's measured time."""
+    echo = sim.echo_buffer(1)
+    sim.ctx.synthesize([sim.scene_ids[0]], echo, mask, mask_mode=1, kernel=KERNEL_CODES["nufft"],
+                       census=True)
+    return {"census": sim.ctx.last_census(), "spread_ms": spread_ms}
 
 
 def measure_batched(n_scenes=64, reps=2, kernels=("matrix", "nufft")):
@@ -473,29 +495,36 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    lit = sim.masks_numpy(mask)[0].sum(axis=1)
-    evals_per_step = int(lit.sum()) * wf.n_samples * arr.n_channels
-    _log(f"bench: lit facets per chirp mean {lit.mean():.0f}, evals/step {evals_per_step:.3e}")
 
-    stage_ms = np.zeros(8)
+    names = None
+    stage_ms = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(True)
         t = sim.ctx.last_timings()  # waits for this step's events
+        if stage_ms is None:
+            names, stage_ms = list(t.keys()), np.zeros(len(t))
         stage_ms += np.array(list(t.values()))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
-    names = list(sim.ctx.last_timings().keys())
+    # the frame's lit facets (the same every step: the scene and chirp times are fixed)
+    lit = sim.masks_numpy(mask)[0].sum(axis=1)
+    evals_per_step = int(lit.sum()) * wf.n_samples * arr.n_channels
+    _log(f"bench: lit facets per chirp mean {lit.mean():.0f}, evals/step {evals_per_step:.3e}")
     stage_avg = {n: round(float(v / args.steps), 4) for n, v in zip(names, stage_ms)}
-    fs_ms = stage_ms[2] / args.steps
+    fs_ms = stage_ms[names.index("facet_sum")] / args.steps
     achieved = FLOP_PER_EVAL * evals_per_step / (fs_ms * 1e-3)
+    nu = None
+    if kernel == "nufft":
+        nu = nufft_info(sim, mask, stage_ms[names.index("nufft_spread")] / args.steps)
     rl = roofline(kernel, evals_per_step, fs_ms, (arr.n_channels, wf.n_chirps, wf.n_samples),
-                  args.workload)
+                  args.workload, nu)
     _log(f"bench: {ms_per_step:.2f} ms/step, facet sum {fs_ms:.2f} ms "
-         f"({achieved / 1e12:.2f} TFLOP/s direct-sum-equivalent); {kernel} kernel at "
-         f"{rl['achieved']:.2f} {rl['unit']} of its own work = {rl['frac']:.3f} of peak")
+         f"({achieved / 1e12:.2f} TFLOP/s direct-sum-equivalent); {kernel} kernel "
+         f"{'(spread) ' if kernel == 'nufft' else ''}at {rl['achieved']:.2f} {rl['unit']} of "
+         f"its own work = {rl['frac']:.3f} of peak")
 
     out = {
         "metric": METRIC,

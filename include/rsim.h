@@ -103,7 +103,9 @@ typedef struct {
   int32_t kernel;    /* RSIM_KERNEL_AUTO (default), _VECTOR, _MATRIX or _NUFFT; MATRIX or   */
                      /* NUFFT where ineligible fails with ERANGE (with RSIM_FP64: EINVAL);  */
                      /* AUTO falls back to VECTOR there                                     */
-  int32_t reserved[3];
+  int32_t census;    /* NUFFT facet sum: also count its records by source form (read with */
+                     /* rsim_last_census); no effect on the results. Not with use_graph    */
+  int32_t reserved[2];
 } rsim_opts;
 
 /* ---- context ---------------------------------------------------------------------- */
@@ -238,9 +240,21 @@ int32_t rsim_form_rdm_noalloc(rsim_ctx *ctx, const void *echo, int32_t n_cubes, 
  * rsim_backward call made with opts.timing = 1, measured with HIP events on the
  * caller's stream. Blocks until those events complete. Stage order:
  * 0 visibility, 1 compaction, 2 facet sum (incl. FP64 prep), 3 range FFT,
- * 4 Doppler FFT + RDM, 5 adjoint facet sum, 6 adjoint FFTs, 7 vertex gather.
- * Stages not run report 0. n_stages up to 8. */
+ * 4 Doppler FFT + RDM, 5 adjoint facet sum, 6 adjoint FFTs, 7 vertex gather,
+ * 8 the NUFFT spread kernel alone (summed over its launches; part of stage 2),
+ * 9 the NUFFT adjoint's gather kernels alone (part of stage 5).
+ * Stages not run report 0. n_stages up to 10. */
 int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages);
+
+/* Record census of the last rsim_synthesize call that ran the NUFFT facet sum with
+ * opts.census set: counts[k] = (lit facet or point, chirp) records whose grid sources take
+ * form k: 0 none (zero-area facet), 1 three point Gaussians (one per vertex: the divided
+ * difference of the facet integral when every pair of vertex phases differs by more than
+ * 2 rad), 2 a point Gaussian and a quadratic-weighted one (one close pair), 3 one
+ * quadratic-weighted Gaussian about the centroid (a small facet, or a point scatterer).
+ * The spread's work per (record, channel) follows from them. Blocks until that call's
+ * work is done. ESTATE if no such call ran on ctx. */
+int32_t rsim_last_census(rsim_ctx *ctx, int64_t counts[4]);
 
 /* ---- adjoint ------------------------------------------------------------------------ */
 

@@ -29,7 +29,10 @@ namespace {
 
 thread_local std::string g_thread_error;
 
-constexpr int kStages = 8;
+constexpr int kStages = 10;
+// stages 8 and 9 sum their own event pairs: the NUFFT spread kernel (one pair per launch)
+// and the NUFFT adjoint's gather kernels (one pair per chunk)
+constexpr int kKernelStage0 = 8;
 
 struct MeshRec {
   std::vector<float> verts;
@@ -75,7 +78,8 @@ struct BatchTables {
   DevScene *d_scenes = nullptr;
   int4 *d_items = nullptr;
   int32_t *d_queue = nullptr;
-  size_t scenes_cap = 0, items_cap = 0;
+  NuUnit *d_units = nullptr;  // NUFFT: (scene, chirp) units of every chunk, longest first
+  size_t scenes_cap = 0, items_cap = 0, units_cap = 0;
   int32_t n_items = 0;
   // key of the uploaded contents
   std::vector<int32_t> ids;
@@ -118,6 +122,8 @@ struct rsim_ctx {
   size_t scratch_bytes = 0;
   hipEvent_t ev0[kStages] = {}, ev1[kStages] = {};
   bool stage_ran[kStages] = {};
+  std::vector<hipEvent_t> kern_ev[2];  // event pairs of stages 8 and 9 (grow-only pools)
+  int kern_used[2] = {0, 0};           // pairs recorded since the timing reset
   bool timing_pending = false;
   hipStream_t capture_stream = nullptr;
   int cu_count = 0;
@@ -129,6 +135,8 @@ struct rsim_ctx {
   double *adj_vpart = nullptr, *adj_gsum = nullptr;  // gsum: [2][F][9] (plain, t_n-weighted)
   // NUFFT facet sum work buffer (records, keys, order, cell counts, grids) and the layout
   // its count and grid regions were last cleared for
+  unsigned long long *d_census = nullptr;  // NUFFT record census [kNuCensusSlots][4]
+  bool census_ready = false;                // the last census call ran the NUFFT
   void *nu_buf = nullptr;
   size_t nu_buf_bytes = 0;
   void *nu_adj_buf = nullptr;  // work buffers of the NUFFT adjoint (grow-only)
@@ -523,19 +531,42 @@ const char *nufft_common(const rsim_ctx *ctx, const RadarConst &rc, const rsim_o
   // with the delay within the chirp a channel's source also moves by its Doppler shift
   // (A + B M) n_g, at most n_g (f0 + M df) 2 v_max / (c fs) cells, relative to the
   // record's by twice that
+  // within one wave of the spread (channels 64 g .. 64 g + 63) a channel lies within
+  // kappa (|a_t - a_t0| + |a_r - a_r0|) cells of the wave's first (triangle inequality on
+  // the two path lengths), plus rounding
+  const int O = rc.P * rc.Q;
+  double wd = 0.0;
+  for (int o0 = 0; o0 < O; o0 += 64) {
+    const int p0 = o0 / rc.Q, q0 = o0 % rc.Q;
+    for (int o = o0; o < std::min(O, o0 + 64); ++o) {
+      const int p = o / rc.Q, q = o % rc.Q;
+      double dt = 0.0, dr = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double a = ctx->tx[3 * p + k] - ctx->tx[3 * p0 + k];
+        const double b = ctx->rx[3 * q + k] - ctx->rx[3 * q0 + k];
+        dt += a * a;
+        dr += b * b;
+      }
+      wd = std::max(wd, std::sqrt(dt) + std::sqrt(dr));
+    }
+  }
   double chan_d = kappa * (et + er);
-  if (o.intra_chirp)
-    chan_d += 2.0 * ng * (rc.f0 + rc.M * rc.df) * 2.0 * v_max / (kC0 * rc.fs);
+  double wave_d = kappa * wd + 1e-3;
+  if (o.intra_chirp) {
+    const double dop = 2.0 * ng * (rc.f0 + rc.M * rc.df) * 2.0 * v_max / (kC0 * rc.fs);
+    chan_d += dop;
+    wave_d += dop;
+  }
   NuShape s{};
   s.ng = ng;
   s.ld = ng + 1;
-  const int O = rc.P * rc.Q;
   s.fc = rc.f0 + (rc.M / 2) * rc.df;
   s.kc = 2.0 * kPi * s.fc / kC0;
   s.cells_per_s = rc.df * ng;
   s.kappa = kappa;
   s.sigma = kNuSigma;
   s.chan_d = chan_d;
+  s.wave_d = wave_d;
   s.spread_groups = (O + 63) / 64;
   s.n0 = 0;
   s.n_chirps = rc.N;
@@ -571,8 +602,8 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
   s.b0 = static_cast<int32_t>(std::ceil(s.chan_d + s.off_max + 0.5 * kNuWidth));
   s.kspan = kNuSlots - 2 - 2 * s.b0;
   if (nufft_cells_per_source(s) == 0)
-    return "array aperture too wide for the NUFFT spread (channels more than 4 grid cells "
-           "from the phase-centre path)";
+    return "array aperture too wide for the NUFFT spread (channels of one 64-channel group "
+           "more than 4 grid cells apart)";
   if (s.kspan < 0)
     return "facets or array aperture too wide for the NUFFT window: node offsets (2 r_max "
            "df n_g / c) plus channel offsets exceed 9 grid cells";
@@ -602,9 +633,11 @@ int nufft_run_len(const rsim_ctx *ctx, int64_t stride, int n_chirps) {
   return L;
 }
 
+// Runs of a chirp: every run but those cut by a gap of more than kspan cells (at most
+// n_g / (kspan + 1) + 1 of them) and the last holds run_len records.
 int32_t nufft_max_runs(const NuShape &ns, int64_t stride) {
-  const int64_t full = (stride + ns.run_len - 1) / ns.run_len;
-  return static_cast<int32_t>(3 * full + (ns.ng + ns.kspan) / (ns.kspan + 1) + 2);
+  const int64_t full = stride / ns.run_len;
+  return static_cast<int32_t>(full + (ns.ng + ns.kspan) / (ns.kspan + 1) + 2);
 }
 
 // Kernel, tiles and shape of one rsim_synthesize call.
@@ -616,6 +649,10 @@ struct SumPlan {
   NuShape ns{};         // NUFFT: shape; n_chirps = chirps per launch
   NuBuffers nb{};       // NUFFT: work buffers
   std::vector<NuShape> nu_scene;  // NUFFT: per scene of the call (reach, runs, stride)
+  // NUFFT batched (persistent) calls: the units and the chunks of one launch each
+  // (first unit, units, largest record stride, largest run bound)
+  std::vector<NuUnit> nu_units;
+  std::vector<std::array<int64_t, 4>> nu_chunks;
   const void *tw = nullptr;  // NUFFT: twiddles of the grid length
   int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
 };
@@ -701,9 +738,25 @@ void stage_begin(rsim_ctx *ctx, bool on, int k, hipStream_t s) {
 void stage_end(rsim_ctx *ctx, bool on, int k, hipStream_t s) {
   if (on) (void)hipEventRecord(ctx->ev1[k], s);
 }
+// Next event pair of kernel stage k (8 or 9) for this call's timing; nullptr without
+// timing or when an event cannot be created.
+const hipEvent_t *kernel_events(rsim_ctx *ctx, bool on, int k) {
+  if (!on) return nullptr;
+  std::vector<hipEvent_t> &pool = ctx->kern_ev[k - kKernelStage0];
+  int &used = ctx->kern_used[k - kKernelStage0];
+  while (static_cast<int>(pool.size()) < 2 * (used + 1)) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+  }
+  ctx->stage_ran[k] = true;
+  return &pool[2 * used++];
+}
+
 void timing_reset(rsim_ctx *ctx, bool on) {
   if (!on) return;
   for (int k = 0; k < kStages; ++k) ctx->stage_ran[k] = false;
+  ctx->kern_used[0] = ctx->kern_used[1] = 0;
   ctx->timing_pending = true;
 }
 
@@ -864,6 +917,47 @@ int32_t prepare_batch(rsim_ctx *ctx, BatchTables &bt, const std::vector<int32_t>
   return RSIM_OK;
 }
 
+// Upload (synchronously, after draining `s`) the scene and unit tables of a batched NUFFT
+// call unless the same tables are already resident.
+int32_t prepare_nufft_batch(rsim_ctx *ctx, BatchTables &bt, const std::vector<int32_t> &ids,
+                            const std::vector<DevScene> &ds, void *echo, uint32_t *vis_mask,
+                            const SumPlan &pl, hipStream_t s) {
+  if (bt.d_units && bt.ids == ids && bt.echo == echo && bt.mask == vis_mask &&
+      bt.version == ctx->version && bt.mb == -1 && bt.precision == 0 &&
+      bt.n_items == static_cast<int32_t>(pl.nu_units.size()))
+    return RSIM_OK;
+  HIP_TRY(ctx, hipStreamSynchronize(s));  // a previous launch may still read the tables
+  auto grow = [&](void **p, size_t *cap, size_t need) -> int32_t {
+    if (*cap >= need && *p) return RSIM_OK;
+    dev_free(ctx, *p);
+    *p = nullptr;
+    *cap = 0;
+    int32_t r = dev_alloc(ctx, p, need);
+    if (!r) *cap = need;
+    return r;
+  };
+  size_t scap = bt.scenes_cap * sizeof(DevScene), ucap = bt.units_cap * sizeof(NuUnit);
+  int32_t r;
+  if ((r = grow(reinterpret_cast<void **>(&bt.d_scenes), &scap, sizeof(DevScene) * ds.size())))
+    return r;
+  bt.scenes_cap = scap / sizeof(DevScene);
+  if ((r = grow(reinterpret_cast<void **>(&bt.d_units), &ucap,
+                sizeof(NuUnit) * std::max<size_t>(1, pl.nu_units.size()))))
+    return r;
+  bt.units_cap = ucap / sizeof(NuUnit);
+  HIP_TRY(ctx, hipMemcpy(bt.d_scenes, ds.data(), sizeof(DevScene) * ds.size(), hipMemcpyHostToDevice));
+  HIP_TRY(ctx, hipMemcpy(bt.d_units, pl.nu_units.data(), sizeof(NuUnit) * pl.nu_units.size(),
+                         hipMemcpyHostToDevice));
+  bt.n_items = static_cast<int32_t>(pl.nu_units.size());
+  bt.ids = ids;
+  bt.echo = echo;
+  bt.mask = vis_mask;
+  bt.version = ctx->version;
+  bt.mb = -1;
+  bt.precision = 0;
+  return RSIM_OK;
+}
+
 // Enqueue visibility + compaction + facet sum (kernels only; capturable).
 int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const BatchTables *bt,
                           hipStream_t s, const rsim_opts &o, bool timing, const SumPlan &pl) {
@@ -871,6 +965,8 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
   rc.intra = o.intra_chirp ? 1 : 0;
   const int precision = o.precision;
   const TunedShape ts = pl.ts;
+  if (pl.nufft && pl.nb.census)
+    HIP_TRY(ctx, launch_fill_zero(reinterpret_cast<float *>(pl.nb.census), 8 * kNuCensusSlots, s));
   const EchoShape sh = pl.sh;
   auto sum_plain = [&](const DevScene &d, const RadarConst &r, const double *elem,
                        const EchoShape &shk) {
@@ -887,14 +983,26 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
     for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, 0, rc.N, s));
     stage_end(ctx, timing, 1, s);
     stage_begin(ctx, timing, 2, s);
-    if (pl.nufft) {
-      // per scene, in chirp chunks that fit the record buffer (batched calls included)
+    if (pl.nufft && bt) {
+      // batched: one launch per stage over each chunk of (scene, chirp) units
+      for (const auto &ch : pl.nu_chunks) {
+        NuShape ns = pl.ns;
+        ns.n_chirps = static_cast<int32_t>(ch[1]);
+        ns.rec_stride = ch[2];
+        ns.max_runs = static_cast<int32_t>(ch[3]);
+        const NuBatch batch{bt->d_scenes, bt->d_units + ch[0]};
+        HIP_TRY(ctx, launch_nufft(ds[0], rc, ctx->d_elem, ns, pl.nb, pl.tw, s, batch,
+                                  kernel_events(ctx, timing, kKernelStage0)));
+      }
+    } else if (pl.nufft) {
+      // per scene, in chirp chunks that fit the record buffer
       for (size_t i = 0; i < ds.size(); ++i) {
         NuShape ns = pl.nu_scene[i];
         for (int n0 = 0; n0 < rc.N; n0 += pl.ns.n_chirps) {
           ns.n0 = n0;
           ns.n_chirps = std::min(pl.ns.n_chirps, rc.N - n0);
-          HIP_TRY(ctx, launch_nufft(ds[i], rc, ctx->d_elem, ns, pl.nb, pl.tw, s));
+          HIP_TRY(ctx, launch_nufft(ds[i], rc, ctx->d_elem, ns, pl.nb, pl.tw, s, NuBatch{},
+                                    kernel_events(ctx, timing, kKernelStage0)));
         }
       }
     } else if (bt && pl.matrix) {
@@ -1041,6 +1149,8 @@ void rsim_destroy(rsim_ctx *ctx) {
       if (ctx->ev0[k]) (void)hipEventDestroy(ctx->ev0[k]);
       if (ctx->ev1[k]) (void)hipEventDestroy(ctx->ev1[k]);
     }
+    for (auto &pool : ctx->kern_ev)
+      for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   }
   delete ctx;
@@ -1310,6 +1420,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
   if (ctx->ground && o.persistent)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the ground bounce runs with plain launches "
                 "(persistent = 0)");
+  if (o.census && o.use_graph)
+    return fail(ctx, RSIM_EINVAL, "rsim_synthesize: census is not taken under a captured graph");
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   std::vector<int32_t> ids(scene_ids, scene_ids + n_scenes);
@@ -1365,29 +1477,80 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     const int64_t O = static_cast<int64_t>(rcn.P) * rcn.Q;
     // the layout only grows while channels, grid and record size stay: calls on
     // smaller scenes reuse it, so captured graphs stay valid
-    if (ctx->nu_layout[2] == O && ctx->nu_layout[3] == pl.ns.ng &&
-        ctx->nu_layout[4] == static_cast<int64_t>(rec_b)) {
-      stride = std::max<int64_t>(stride, ctx->nu_layout[0]);
-      max_runs = std::max<int32_t>(max_runs, static_cast<int32_t>(ctx->nu_layout[5]));
-    }
+    (void)0;
     nufft_fft_groups(ctx, rcn, pl.ns, sizeof(int32_t) * max_runs);
     for (NuShape &si : pl.nu_scene) {
       si.cb = pl.ns.cb;
       si.groups = pl.ns.groups;
     }
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t part_b = static_cast<size_t>(max_runs) * O * kNuSlots * sizeof(float2);
-    const size_t per_chirp = stride * (rec_b + 8) + max_runs * sizeof(int4) + 4 + part_b;
-    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
-    if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
-    const size_t off_pos = al(chunk * stride * 4);
-    const size_t off_srec = off_pos + al(chunk * stride * 4);
-    const size_t off_runs = off_srec + al(chunk * stride * rec_b);
-    const size_t off_nruns = off_runs + al(chunk * max_runs * sizeof(int4));
+    const size_t run_b = sizeof(int4) + static_cast<size_t>(O) * kNuSlots * sizeof(float2);
+    // work-buffer extents: records (and keys, positions), runs and units per launch
+    int64_t ext_rec = 0, ext_run = 0, chunk = 0;
+    pl.nu_units.clear();
+    pl.nu_chunks.clear();
+    if (o.persistent) {
+      // batched: (scene, chirp) units, the scenes with the most records first, cut into
+      // launches of at most kNuRecBudget bytes and 65535 units
+      std::vector<int> order(ids.size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return pl.nu_scene[a].rec_stride > pl.nu_scene[c].rec_stride;
+      });
+      int64_t u0 = 0, rec = 0, run = 0, big_s = 0, big_r = 0;
+      auto close = [&]() {
+        const int64_t n_u = static_cast<int64_t>(pl.nu_units.size()) - u0;
+        if (n_u <= 0) return;
+        pl.nu_chunks.push_back({u0, n_u, big_s, big_r});
+        ext_rec = std::max(ext_rec, rec);
+        ext_run = std::max(ext_run, run);
+        chunk = std::max(chunk, n_u);
+        u0 = static_cast<int64_t>(pl.nu_units.size());
+        rec = run = big_s = big_r = 0;
+      };
+      for (int i : order) {
+        const NuShape &si = pl.nu_scene[i];
+        const size_t unit_b = si.rec_stride * (rec_b + 8) + si.max_runs * run_b + 4;
+        for (int n = 0; n < rcn.N; ++n) {
+          const size_t used = rec * (rec_b + 8) + run * run_b +
+                              4 * (static_cast<size_t>(pl.nu_units.size()) - u0);
+          if (static_cast<int64_t>(pl.nu_units.size()) > u0 &&
+              (used + unit_b > kNuRecBudget ||
+               static_cast<int64_t>(pl.nu_units.size()) - u0 >= 65535))
+            close();
+          NuUnit un{};
+          un.scene = i;
+          un.n = n;
+          un.rec_base = rec;
+          un.rec_stride = si.rec_stride;
+          un.run_base = run;
+          un.max_runs = si.max_runs;
+          un.run_len = si.run_len;
+          un.b0 = si.b0;
+          un.kspan = si.kspan;
+          pl.nu_units.push_back(un);
+          rec += si.rec_stride;
+          run += si.max_runs;
+          big_s = std::max(big_s, si.rec_stride);
+          big_r = std::max<int64_t>(big_r, si.max_runs);
+        }
+      }
+      close();
+    } else {
+      const size_t per_chirp = stride * (rec_b + 8) + max_runs * run_b + 4;
+      chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
+      if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
+      ext_rec = chunk * stride;
+      ext_run = chunk * max_runs;
+    }
+    const size_t off_pos = al(ext_rec * 4);
+    const size_t off_srec = off_pos + al(ext_rec * 4);
+    const size_t off_runs = off_srec + al(ext_rec * rec_b);
+    const size_t off_nruns = off_runs + al(ext_run * sizeof(int4));
     const size_t off_part = off_nruns + al(chunk * 4);
-    const size_t total = off_part + chunk * part_b;
-    const std::array<int64_t, 6> layout{stride, chunk, O, pl.ns.ng, static_cast<int64_t>(rec_b),
-                                        max_runs};
+    const size_t total = off_part + ext_run * static_cast<size_t>(O) * kNuSlots * sizeof(float2);
+    const std::array<int64_t, 6> layout{ext_rec, chunk, O, pl.ns.ng, static_cast<int64_t>(rec_b),
+                                        ext_run};
     if (ctx->nu_buf_bytes < total) {
       HIP_TRY(ctx, hipDeviceSynchronize());  // earlier launches may still use the buffer
       dev_free(ctx, ctx->nu_buf);
@@ -1405,6 +1568,14 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     pl.nb = NuBuffers{reinterpret_cast<int32_t *>(b), reinterpret_cast<int32_t *>(b + off_pos),
                       b + off_srec, reinterpret_cast<float2 *>(b + off_part), rec_b, nullptr,
                       reinterpret_cast<int4 *>(b + off_runs), reinterpret_cast<int32_t *>(b + off_nruns)};
+    if (o.census) {
+      if (!ctx->d_census) {
+        void *p = nullptr;
+        if ((rc = dev_alloc(ctx, &p, sizeof(unsigned long long) * 4 * kNuCensusSlots))) return rc;
+        ctx->d_census = static_cast<unsigned long long *>(p);
+      }
+      pl.nb.census = ctx->d_census;
+    }
     pl.ns.n_chirps = static_cast<int32_t>(chunk);
     pl.ns.max_runs = max_runs;
     if (nufft_sort_smem_bytes(pl.ns) > ctx->max_lds)
@@ -1437,7 +1608,10 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       g.exec = nullptr;
       g.graph = nullptr;
       g.valid = false;
-      if (o.persistent &&
+      if (o.persistent && pl.nufft &&
+          (rc = prepare_nufft_batch(ctx, g.tables, ids, ds, echo, vis_mask, pl, s)))
+        return rc;
+      if (o.persistent && !pl.nufft &&
           (rc = prepare_batch(ctx, g.tables, ids, ds, echo, vis_mask, o.precision, pl.batch_key,
                               sh, s)))
         return rc;
@@ -1469,11 +1643,18 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     stage_end(ctx, timing, 2, s);
     return RSIM_OK;
   }
-  if (o.persistent &&
+  if (o.persistent && pl.nufft &&
+      (rc = prepare_nufft_batch(ctx, ctx->batch, ids, ds, echo, vis_mask, pl, s)))
+    return rc;
+  if (o.persistent && !pl.nufft &&
       (rc = prepare_batch(ctx, ctx->batch, ids, ds, echo, vis_mask, o.precision, pl.batch_key, sh,
                           s)))
     return rc;
-  return enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing, pl);
+  if (o.census) ctx->census_ready = false;
+  if ((rc = enqueue_synthesis(ctx, ds, o.persistent ? &ctx->batch : nullptr, s, o, timing, pl)))
+    return rc;
+  if (o.census) ctx->census_ready = pl.nufft;
+  return RSIM_OK;
 }
 
 // NUFFT adjoint of one scene's facet sum into ctx->adj_partial (one slot per chirp and lit
@@ -1521,7 +1702,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
     ns.n0 = static_cast<int32_t>(n0);
     ns.n_chirps = static_cast<int32_t>(std::min<int64_t>(chunk, N - n0));
     HIP_TRY(ctx, launch_nufft_adjoint(d, rcn, ctx->d_elem, ns, nb, tw, grad_echo,
-                                      ctx->adj_partial, s));
+                                      ctx->adj_partial, s,
+                                      kernel_events(ctx, ctx->timing_pending, kKernelStage0 + 1)));
   }
   EchoShape sh{};
   sh.O = static_cast<int32_t>(O);
@@ -1803,6 +1985,24 @@ int32_t rsim_rdm_adjoint(rsim_ctx *ctx, const void *grad_y, int32_t n_cubes, voi
   return RSIM_OK;
 }
 
+int32_t rsim_last_census(rsim_ctx *ctx, int64_t counts[4]) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (!counts) return fail(ctx, RSIM_EINVAL, "rsim_last_census: counts is NULL");
+  if (ctx->host_only) return fail(ctx, RSIM_EDEVICE, "host-only context");
+  if (!ctx->census_ready)
+    return fail(ctx, RSIM_ESTATE, "rsim_last_census: no NUFFT facet sum ran with census set");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  std::vector<unsigned long long> h(4 * kNuCensusSlots);
+  HIP_TRY(ctx, hipMemcpy(h.data(), ctx->d_census, sizeof(unsigned long long) * h.size(),
+                         hipMemcpyDeviceToHost));
+  for (int k = 0; k < 4; ++k) {
+    counts[k] = 0;
+    for (int r = 0; r < kNuCensusSlots; ++r) counts[k] += static_cast<int64_t>(h[4 * r + k]);
+  }
+  return RSIM_OK;
+}
+
 int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
   if (!ms || n_stages < 1 || n_stages > kStages)
@@ -1811,6 +2011,16 @@ int32_t rsim_last_timings(rsim_ctx *ctx, float *ms, int32_t n_stages) {
   for (int k = 0; k < n_stages; ++k) {
     ms[k] = 0.0f;
     if (!ctx->stage_ran[k]) continue;
+    if (k >= kKernelStage0) {
+      const std::vector<hipEvent_t> &pool = ctx->kern_ev[k - kKernelStage0];
+      for (int i = 0; i < ctx->kern_used[k - kKernelStage0]; ++i) {
+        HIP_TRY(ctx, hipEventSynchronize(pool[2 * i + 1]));
+        float v = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&v, pool[2 * i], pool[2 * i + 1]));
+        ms[k] += v;
+      }
+      continue;
+    }
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev1[k]));
     float v = 0.0f;
     HIP_TRY(ctx, hipEventElapsedTime(&v, ctx->ev0[k], ctx->ev1[k]));

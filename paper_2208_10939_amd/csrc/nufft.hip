@@ -50,9 +50,9 @@
 // gives the same bits every time and whatever other scenes share it:
 //   key     per (chirp, lit facet or point): grid cell of the phase-centre path;
 //   sort    per chirp: a stable counting sort by cell (entries keep their order within a
-//           cell), and the chirp's runs: consecutive sorted records over at most
-//           kspan + 1 cells and run_len records, so that every source of a run lands in
-//           one window of kNuSlots cells;
+//           cell), and the chirp's runs: consecutive sorted records, run_len of them unless
+//           the next record's cell is more than kspan past the run's first, so that every
+//           source of a run lands in one window of kNuSlots cells;
 //   prep    per entry: the sources and the phase-centre path (FP64 work, stored as FP32
 //           offsets, weights, reduced phase and grid cell), written at the sorted position;
 //   spread  one workgroup per (chirp, run), one wave per 64 channels: each lane
@@ -371,13 +371,70 @@ __device__ int nufft_sources(const Geo &g, const NuShape &ns, float s[10]) {
   return kind;
 }
 
+// Where one (scene, chirp) unit of a launch keeps its work: a plain launch covers chirps
+// n0 .. n0 + n_chirps - 1 of one scene at fixed strides; a batched one reads the unit's
+// scene, chirp, strides and run bounds from its table.
+struct NuWork {
+  const DevScene *sc;
+  int n;
+  int64_t rec;     // first record (and key, position) slot
+  int64_t run;     // first run slot
+  int64_t stride;  // record slots of the unit
+  int32_t max_runs, run_len, b0, kspan;
+};
+
+__device__ inline NuWork nu_work(const DevScene &sc, const NuShape &ns, const NuBatch &bt, int u) {
+  NuWork w;
+  if (!bt.units) {
+    w.sc = &sc;
+    w.n = ns.n0 + u;
+    w.rec = static_cast<int64_t>(u) * ns.rec_stride;
+    w.run = static_cast<int64_t>(u) * ns.max_runs;
+    w.stride = ns.rec_stride;
+    w.max_runs = ns.max_runs;
+    w.run_len = ns.run_len;
+    w.b0 = ns.b0;
+    w.kspan = ns.kspan;
+  } else {
+    const NuUnit un = load_uniform(bt.units + u);
+    w.sc = bt.scenes + un.scene;
+    w.n = un.n;
+    w.rec = un.rec_base;
+    w.run = un.run_base;
+    w.stride = un.rec_stride;
+    w.max_runs = un.max_runs;
+    w.run_len = un.run_len;
+    w.b0 = un.b0;
+    w.kspan = un.kspan;
+  }
+  return w;
+}
+
 template <bool INTRA>
-__global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst rc, NuShape ns,
-                                                        NuBuffers nb) {
-  const int nl = blockIdx.y;
-  const int n = ns.n0 + nl;
+__global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc0, RadarConst rc, NuShape ns,
+                                                        NuBuffers nb, NuBatch bt) {
+  const NuWork w = nu_work(sc0, ns, bt, blockIdx.y);
+  const DevScene &sc = *w.sc;
+  const int n = w.n;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (nb.census) {
+    // wave counts of each form, added into one of kNuCensusSlots rows
+    int kind = -1;
+    if (item < cnt + sc.n_points) {
+      Geo g;
+      entry_geometry(sc, rc, n, cnt, item, g);
+      int far;
+      kind = nufft_classify(g, ns, &far);
+    }
+    const int row = static_cast<int>((blockIdx.y * gridDim.x + blockIdx.x) * (blockDim.x >> 6) +
+                                     (threadIdx.x >> 6)) % kNuCensusSlots;
+    for (int k = 0; k < 4; ++k) {
+      const unsigned long long m = __ballot(kind == k);
+      if ((threadIdx.x & 63) == 0 && m)
+        atomicAdd(nb.census + 4 * row + k, static_cast<unsigned long long>(__popcll(m)));
+    }
+  }
   if (item >= cnt + sc.n_points) return;
   Geo g;
   entry_geometry(sc, rc, n, cnt, item, g);
@@ -398,14 +455,14 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc, RadarConst
   } else {
     out.ext[0] = out.ext[1] = 0.0f;
   }
-  const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
-  static_cast<NuRecF<INTRA> *>(nb.srec)[row + nb.pos[row + item]] = out;
+  static_cast<NuRecF<INTRA> *>(nb.srec)[w.rec + nb.pos[w.rec + item]] = out;
 }
 
-__global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst rc, NuShape ns,
-                                                       NuBuffers nb) {
-  const int nl = blockIdx.y;
-  const int n = ns.n0 + nl;
+__global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc0, RadarConst rc, NuShape ns,
+                                                       NuBuffers nb, NuBatch bt) {
+  const NuWork w = nu_work(sc0, ns, bt, blockIdx.y);
+  const DevScene &sc = *w.sc;
+  const int n = w.n;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
   if (item >= cnt + sc.n_points) return;
@@ -414,7 +471,7 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst 
   double x, Rt, Rr, dxc;
   int cell;
   centre_cell(g, rc, ns, 0.0, &x, &cell, &Rt, &Rr, &dxc);
-  nb.key[static_cast<int64_t>(nl) * ns.rec_stride + item] = cell;
+  nb.key[w.rec + item] = cell;
 }
 
 // Per chirp: stable counting sort of the entries by cell, and the chirp's runs.
@@ -422,18 +479,19 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc, RadarConst 
 // in its own LDS row, the rows become per-wave starting positions (cell offset plus the
 // counts of earlier waves), and each wave then ranks its entries 64 at a time, lanes with
 // the same cell in lane order. Runs are cut by one lane over the occupied cells.
-__global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc, NuShape ns,
-                                                                   NuBuffers nb) {
+__global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc0, NuShape ns,
+                                                                   NuBuffers nb, NuBatch bt) {
   extern __shared__ int32_t sort_smem[];
   const int ng = ns.ng;
   int32_t *cnt = sort_smem;                           // [kNuSortWaves][ng]
   int32_t *cbase = sort_smem + kNuSortWaves * ng;     // [ng + 1]: first record of each cell
   int32_t *part = cbase + ng + 1;                     // [kNuSortThreads]
   const int nl = blockIdx.x;
-  const int n = ns.n0 + nl;
-  const int64_t row = static_cast<int64_t>(nl) * ns.rec_stride;
-  const int32_t *key = nb.key + row;
-  int32_t *pos = nb.pos + row;
+  const NuWork wk = nu_work(sc0, ns, bt, nl);
+  const DevScene &sc = *wk.sc;
+  const int n = wk.n;
+  const int32_t *key = nb.key + wk.rec;
+  int32_t *pos = nb.pos + wk.rec;
   const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
   const int tid = static_cast<int>(threadIdx.x);
   const int w = tid >> 6, lane = tid & 63;
@@ -482,19 +540,19 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc,
   __syncthreads();
   // runs: cut by one lane over the occupied cells (reads cbase only)
   if (tid == 0) {
-    int4 *runs = nb.runs + static_cast<int64_t>(nl) * ns.max_runs;
+    int4 *runs = nb.runs + wk.run;
     int nr = 0;
     int open_cell = 0, open_rb = 0, open_n = 0;
     auto emit = [&](int rb, int re, int base) {
-      if (nr < ns.max_runs) runs[nr] = make_int4(rb, re, base, 0);
+      if (nr < wk.max_runs) runs[nr] = make_int4(rb, re, base, 0);
       ++nr;
     };
     for (int c = 0; c < ng; ++c) {
       int h = cbase[c + 1] - cbase[c];
       if (!h) continue;
       int rb = cbase[c];
-      if (open_n > 0 && (c - open_cell > ns.kspan || open_n + h > ns.run_len)) {
-        emit(open_rb, open_rb + open_n, open_cell - ns.b0);
+      if (open_n > 0 && c - open_cell > wk.kspan) {
+        emit(open_rb, open_rb + open_n, open_cell - wk.b0);
         open_n = 0;
       }
       while (h > 0) {
@@ -502,18 +560,18 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc,
           open_cell = c;
           open_rb = rb;
         }
-        const int take = min(h, ns.run_len - open_n);
+        const int take = min(h, wk.run_len - open_n);
         open_n += take;
         h -= take;
         rb += take;
-        if (open_n == ns.run_len) {
-          emit(open_rb, open_rb + open_n, open_cell - ns.b0);
+        if (open_n == wk.run_len) {
+          emit(open_rb, open_rb + open_n, open_cell - wk.b0);
           open_n = 0;
         }
       }
     }
-    if (open_n > 0) emit(open_rb, open_rb + open_n, open_cell - ns.b0);
-    nb.n_runs[nl] = min(nr, ns.max_runs);
+    if (open_n > 0) emit(open_rb, open_rb + open_n, open_cell - wk.b0);
+    nb.n_runs[nl] = min(nr, wk.max_runs);
   }
   // stable ranks: lanes with equal cells are handled together, in lane order
   for (int32_t chunk = e0; chunk < e1; chunk += 64) {
@@ -572,11 +630,21 @@ __device__ __forceinline__ void poly_cells(float2 (&acc)[kNuSlots], const float2
   }
 }
 
-// The window cell s_lo (wave-uniform) selects one straight-line block: one branch per
-// source instead of a test per cell. A source covers NCELL or fewer cells (its count is
-// floor(2 reach) or one more, NCELL at least the larger), so a block may reach up to four
-// cells past the last the runs guarantee inside the window; those are dropped (their
-// Gaussian weights are below psi(W/2) for every channel).
+// The window cell s_lo (wave-uniform) selects one straight-line block of NCELL cells. A
+// source covers NCELL or fewer cells (its count is floor(2 reach) or one more, NCELL at
+// least the larger), so a block may reach up to four cells past the last the runs
+// guarantee inside the window; those are dropped (their Gaussian weights are below
+// psi(W/2) for every channel). The blocks sit behind a chain of independent scalar bit
+// tests rather than a switch: every block then updates the window registers in place,
+// where the merge of a switch's cases costs register copies of the untouched cells.
+// First cell of a source's block: the lowest cell within `reach` of the source's
+// position for the wave's first channel, clamped to the blocks the chain holds (the
+// runs keep every channel's cells inside the window, so a clamp never drops one of them).
+__device__ __forceinline__ int block_start(float x0, float reach) {
+  const int s = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(x0 - reach)));
+  return s < 0 ? 0 : s > 22 ? 22 : s;
+}
+
 #define RSIM_NU_CASES(X) \
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
   X(16) X(17) X(18) X(19) X(20) X(21) X(22)
@@ -587,16 +655,11 @@ __device__ __forceinline__ void spread_point(float2 (&acc)[kNuSlots], float2 cw,
   const float u0 = static_cast<float>(s_lo) - pos;
   const float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
   const float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
-  switch (s_lo) {
+  const uint32_t bit = static_cast<uint32_t>(s_lo) < 32u ? 1u << s_lo : 0u;  // none: no cell
 #define RSIM_NU_POINT(S) \
-  case S:                \
-    point_cells<S, NCELL>(acc, cw, gw, rho, q_ratio); \
-    break;
-    RSIM_NU_CASES(RSIM_NU_POINT)
+  if (bit & (1u << S)) point_cells<S, NCELL>(acc, cw, gw, rho, q_ratio);
+  RSIM_NU_CASES(RSIM_NU_POINT)
 #undef RSIM_NU_POINT
-    default:
-      break;
-  }
 }
 
 template <int NCELL, int NC>
@@ -605,16 +668,11 @@ __device__ __forceinline__ void spread_poly(float2 (&acc)[kNuSlots], const float
   const float u0 = static_cast<float>(s_lo) - pos;
   const float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
   const float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
-  switch (s_lo) {
+  const uint32_t bit = static_cast<uint32_t>(s_lo) < 32u ? 1u << s_lo : 0u;  // none: no cell
 #define RSIM_NU_POLY(S) \
-  case S:               \
-    poly_cells<S, NCELL, NC>(acc, c, u0, gw, rho, q_ratio); \
-    break;
-    RSIM_NU_CASES(RSIM_NU_POLY)
+  if (bit & (1u << S)) poly_cells<S, NCELL, NC>(acc, c, u0, gw, rho, q_ratio);
+  RSIM_NU_CASES(RSIM_NU_POLY)
 #undef RSIM_NU_POLY
-    default:
-      break;
-  }
 }
 
 // (1 - j 2 pi B m'^2) on the modes is F + j eps F'' on the grid (F = psi P): coefficient
@@ -642,24 +700,25 @@ __device__ __forceinline__ void intra_coeffs(const float2 (&c)[NI], float2 (&o)[
 // run's base cell; the window is written to part[chirp][run][channel][kNuSlots].
 template <bool INTRA, int NCELL>
 __global__ void __launch_bounds__(256) nufft_spread_kernel(
-    DevScene sc, RadarConst rc, NuShape ns, const double *elem,
+    DevScene sc0, RadarConst rc, NuShape ns, const double *elem,
     const NuRecF<INTRA> *__restrict__ sorted, const int4 *__restrict__ runs,
-    const int32_t *__restrict__ n_runs, float2 *__restrict__ part) {
+    const int32_t *__restrict__ n_runs, float2 *__restrict__ part, NuBatch bt) {
   const int nl = blockIdx.y;
   const int run = blockIdx.x;
   if (run >= load_uniform(n_runs + nl)) return;  // whole workgroup
+  const NuWork w = nu_work(sc0, ns, bt, nl);
   const int grp = static_cast<int>(blockIdx.z) * 4 + static_cast<int>(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int O = rc.P * rc.Q;
   if (grp * 64 >= O) return;  // whole wave
-  const int4 rr = load_uniform(runs + static_cast<int64_t>(nl) * ns.max_runs + run);
+  const int4 rr = load_uniform(runs + w.run + run);
   const int o = grp * 64 + lane;
   const bool on = o < O;
   // this lane's element offsets from the phase centres
   double at[3], ar[3];
   float aat, aar, atf[3], arf[3];
   {
-    const int oc = on ? o : 0;
+    const int oc = on ? o : grp * 64;  // idle lanes: the wave's first channel
     const int p = oc / rc.Q, q = oc - p * rc.Q;
     double st = 0.0, sr = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -681,12 +740,12 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
   const float ngf = static_cast<float>(ns.ng);
   const float eps_scale = static_cast<float>(static_cast<double>(ns.ng) * ns.ng / (2.0 * kPi));
   const float inv_s2 = static_cast<float>(1.0 / (ns.sigma * ns.sigma));
-  const NuRecF<INTRA> *srec = sorted + static_cast<int64_t>(nl) * ns.rec_stride;
+  const NuRecF<INTRA> *srec = sorted + w.rec;
   const float nc = static_cast<float>(-1.4426950408889634 / (2.0 * ns.sigma * ns.sigma));
   const float q_ratio = __builtin_amdgcn_exp2f(2.0f * nc);  // exp(-1 / s^2)
   const float kappa = static_cast<float>(ns.kappa);
   const float g2 = static_cast<float>(0.5 * rc.slope / (kC0 * kC0));
-  const float reach = static_cast<float>(ns.chan_d) + 0.5f * kNuWidth;
+  const float reach = static_cast<float>(ns.wave_d) + 0.5f * kNuWidth;
   float2 acc[kNuSlots];
 #pragma unroll
   for (int s = 0; s < kNuSlots; ++s) acc[s] = {0.0f, 0.0f};
@@ -727,6 +786,9 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
       eps = B * eps_scale;
     }
     t -= rintf(t);
+    // the wave's first channel: every channel of the wave lies within wave_d cells of it
+    const float x0 = __builtin_bit_cast(
+        float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, xr)));
     const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
     const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
     const int n_pts = r.kind == 1 ? 3 : r.kind == 2 ? 1 : 0;
@@ -736,9 +798,9 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
         const float off = r.s[3 * j];
         const float2 cw = {qx * r.s[3 * j + 1] - qy * r.s[3 * j + 2],
                            qx * r.s[3 * j + 2] + qy * r.s[3 * j + 1]};
-        // cells some channel reaches: |s - x_o| <= W/2 with |x_o - (rel_c - off)| <= d,
+        // cells some channel reaches: |s - (x_o - off)| <= W/2 with |x_o - x0| <= wave_d,
         // NCELL of them from s_lo
-        const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - off - reach)));
+        const int s_lo = block_start(x0 - off, reach);
         if constexpr (INTRA) {
           const float2 c1[1] = {cw};
           float2 c3[3];
@@ -755,7 +817,7 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
 #pragma unroll
       for (int k = 0; k < 3; ++k)
         cq[k] = {qx * r.s[4 + 2 * k] - qy * r.s[5 + 2 * k], qx * r.s[5 + 2 * k] + qy * r.s[4 + 2 * k]};
-      const int s_lo = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(rel_c - off - reach)));
+      const int s_lo = block_start(x0 - off, reach);
       if constexpr (INTRA) {
         float2 c5[5];
         intra_coeffs(cq, c5, eps, inv_s2);
@@ -767,7 +829,7 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
   }
   if (!on) return;
   float4 *dst = reinterpret_cast<float4 *>(
-      part + ((static_cast<int64_t>(nl) * ns.max_runs + run) * O + o) * kNuSlots);
+      part + ((w.run + run) * O + o) * kNuSlots);
 #pragma unroll
   for (int s = 0; s < kNuSlots / 2; ++s)
     dst[s] = make_float4(acc[2 * s].x, acc[2 * s].y, acc[2 * s + 1].x, acc[2 * s + 1].y);
@@ -790,23 +852,25 @@ __device__ inline int lower_bound_lds(const int32_t *bases, int n, int v) {
 // cover it (at l, l - n_g or l + n_g on the periodic grid; in order of the runs' base
 // cells, which is the run order), forward FFT of all cb rows together (ping-pong buffers),
 // deconvolution and the k_c^2 / k_m^2 factor on the M kept modes.
-__global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc, RadarConst rc,
+__global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc0, RadarConst rc,
                                                                 NuShape ns, NuBuffers nb,
-                                                                const float2 *tw) {
+                                                                const float2 *tw, NuBatch bt) {
   extern __shared__ float2 nu_smem[];
   const int nl = blockIdx.x / ns.groups;
   const int grp = blockIdx.x - nl * ns.groups;
-  const int n = ns.n0 + nl;
+  const NuWork wk = nu_work(sc0, ns, bt, nl);
+  const DevScene &sc = *wk.sc;
+  const int n = wk.n;
   const int ld = ns.ld, ng = ns.ng, cb = ns.cb;
   const int O = rc.P * rc.Q;
   float2 *lgrid = nu_smem;            // [cb][ld]
   float2 *work = nu_smem + cb * ld;   // [cb][ld]
   int32_t *bases = reinterpret_cast<int32_t *>(work + cb * ld);  // [max_runs]
   const int nr = nb.n_runs[nl];
-  const int4 *runs = nb.runs + static_cast<int64_t>(nl) * ns.max_runs;
+  const int4 *runs = nb.runs + wk.run;
   for (int r = threadIdx.x; r < nr; r += blockDim.x) bases[r] = runs[r].z;
   __syncthreads();
-  const float2 *part = nb.grid + static_cast<int64_t>(nl) * ns.max_runs * O * kNuSlots;
+  const float2 *part = nb.grid + wk.run * O * kNuSlots;
   for (int l = threadIdx.x; l < ng; l += blockDim.x) {
     int lo[3], hi[3];
 #pragma unroll
@@ -1242,10 +1306,11 @@ size_t nufft_smem_bytes(const NuShape &ns) {
 size_t nufft_fft_smem_bytes(const NuShape &ns) {
   return nufft_smem_bytes(ns) + sizeof(int32_t) * static_cast<size_t>(ns.max_runs);
 }
-// Cells a source covers over all channels of a wave: the integers within W/2 + chan_d of
-// its position, rounded up to a compiled block length (14, 16 or 20; 0 beyond).
+// Cells a source covers over all channels of a wave: the integers within W/2 + wave_d of
+// its position for the wave's first channel, rounded up to a compiled block length (14,
+// 16 or 20; 0 beyond).
 int nufft_cells_per_source(const NuShape &ns) {
-  const int need = static_cast<int>(std::floor(2.0 * (ns.chan_d + 0.5 * kNuWidth))) + 1;
+  const int need = static_cast<int>(std::floor(2.0 * (ns.wave_d + 0.5 * kNuWidth))) + 1;
   return need <= 14 ? 14 : need <= 16 ? 16 : need <= 20 ? 20 : 0;
 }
 
@@ -1256,17 +1321,17 @@ size_t nufft_sort_smem_bytes(const NuShape &ns) {
 template <bool INTRA>
 static hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double *elem,
                                  const NuShape &ns, const NuBuffers &nb, const void *tw,
-                                 hipStream_t s) {
-  const int64_t items = sc.n_facets + sc.n_points;
+                                 hipStream_t s, const NuBatch &bt, const hipEvent_t *ev) {
+  const int64_t items = bt.units ? ns.rec_stride : sc.n_facets + sc.n_points;
   if (items > 0) {
     dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
-    hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb);
+    hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb, bt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(nufft_sort_kernel, dim3(ns.n_chirps), dim3(kNuSortThreads),
-                       nufft_sort_smem_bytes(ns), s, sc, ns, nb);
+                       nufft_sort_smem_bytes(ns), s, sc, ns, nb, bt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((nufft_prep_kernel<INTRA>), grid, dim3(256), 0, s, sc, rc, ns, nb);
+    hipLaunchKernelGGL((nufft_prep_kernel<INTRA>), grid, dim3(256), 0, s, sc, rc, ns, nb, bt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int O = rc.P * rc.Q;
     const int groups = (O + 63) / 64;
@@ -1275,43 +1340,47 @@ static hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const
                static_cast<unsigned>((groups + 3) / 4));
     const auto *recs = static_cast<const NuRecF<INTRA> *>(nb.srec);
     const dim3 blk(64 * per_block);
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     switch (nufft_cells_per_source(ns)) {
       case 14:
         hipLaunchKernelGGL((nufft_spread_kernel<INTRA, 14>), sgrid, blk, 0, s, sc, rc, ns, elem,
-                           recs, nb.runs, nb.n_runs, nb.grid);
+                           recs, nb.runs, nb.n_runs, nb.grid, bt);
         break;
       case 16:
         hipLaunchKernelGGL((nufft_spread_kernel<INTRA, 16>), sgrid, blk, 0, s, sc, rc, ns, elem,
-                           recs, nb.runs, nb.n_runs, nb.grid);
+                           recs, nb.runs, nb.n_runs, nb.grid, bt);
         break;
       case 20:
         hipLaunchKernelGGL((nufft_spread_kernel<INTRA, 20>), sgrid, blk, 0, s, sc, rc, ns, elem,
-                           recs, nb.runs, nb.n_runs, nb.grid);
+                           recs, nb.runs, nb.n_runs, nb.grid, bt);
         break;
       default:
         return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
                      dim3(kNuFftThreads), nufft_fft_smem_bytes(ns), s, sc, rc, ns, nb,
-                     static_cast<const float2 *>(tw));
+                     static_cast<const float2 *>(tw), bt);
   return hipGetLastError();
 }
 
 hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
-                        const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s) {
+                        const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s,
+                        const NuBatch &bt, const hipEvent_t *ev) {
   if (ns.n_chirps <= 0) return hipSuccess;
   if (nufft_record_bytes(rc.intra != 0) > nb.rec_bytes || !nb.runs || !nb.n_runs || !nb.key ||
-      !nb.pos || ns.ng > 2 * kNuSortThreads || ns.max_runs < 1)
+      !nb.pos || ns.ng > 2 * kNuSortThreads || ns.max_runs < 1 || (bt.units && !bt.scenes))
     return hipErrorInvalidValue;
-  return rc.intra ? launch_nufft_t<true>(sc, rc, elem, ns, nb, tw, s)
-                  : launch_nufft_t<false>(sc, rc, elem, ns, nb, tw, s);
+  return rc.intra ? launch_nufft_t<true>(sc, rc, elem, ns, nb, tw, s, bt, ev)
+                  : launch_nufft_t<false>(sc, rc, elem, ns, nb, tw, s, bt, ev);
 }
 
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
-                                const void *grad_echo, float *partial, hipStream_t s) {
+                                const void *grad_echo, float *partial, hipStream_t s,
+                                const hipEvent_t *ev) {
   if (ns.n_chirps <= 0) return hipSuccess;
   if (sizeof(NuRecF<false>) > nb.rec_bytes || !nb.sder || !nb.key || !nb.n_runs ||
       sc.n_points != 0 || rc.intra)
@@ -1332,6 +1401,7 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
   const int64_t blocks = (static_cast<int64_t>(ns.n_chirps) * bpc + kXcds - 1) / kXcds * kXcds;
   const auto *recs = static_cast<const NuRecF<false> *>(nb.srec);
   const auto *ders = static_cast<const NuDerF *>(nb.sder);
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<0>), dim3(static_cast<unsigned>(blocks)),
                      dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem, recs, ders,
                      nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
@@ -1339,7 +1409,9 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
   hipLaunchKernelGGL((nufft_gather_kernel<1>), dim3(static_cast<unsigned>(blocks)),
                      dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem, recs, ders,
                      nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 }  // namespace rsim

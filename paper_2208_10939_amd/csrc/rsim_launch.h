@@ -71,6 +71,7 @@ struct NuShape {
   int32_t pad1;
   int64_t rec_stride;          // records per chirp (forward: lit facets + points)
   double chan_d;               // largest grid offset of a channel from the phase-centre path
+  double wave_d;               // largest grid offset of a channel from the first of its wave
   double fc, kc;               // f0 + (M/2) df; 2 pi fc / c
   double cells_per_s;          // df ng: grid cells per second of round-trip delay
   double kappa;                // df ng / c: grid cells per metre of path length
@@ -97,6 +98,26 @@ struct NuBuffers {
   void *sder;        // adjoint records in the same order (adjoint only)
   int4 *runs;        // forward: [chirp][max_runs]
   int32_t *n_runs;   // forward: [chirp]
+  // forward, optional: record counts by source form, kNuCensusSlots rows of 4 (summed by
+  // the host); nullptr: no census
+  unsigned long long *census;
+};
+constexpr int kNuCensusSlots = 64;
+// One (scene, chirp) unit of a batched NUFFT launch: the scene's index in the launch's
+// scene table, the chirp, where its records and runs start in the work buffers and the
+// scene's own record capacity, run bound and run cutting (as in NuShape).
+struct NuUnit {
+  int32_t scene, n;
+  int64_t rec_base;
+  int64_t rec_stride;
+  int64_t run_base;
+  int32_t max_runs, run_len, b0, kspan;
+};
+// Batched NUFFT launch: units[0 .. ns.n_chirps) of scenes[]; {nullptr, nullptr}: a plain
+// launch over chirps n0 .. n0 + n_chirps - 1 of one scene.
+struct NuBatch {
+  const DevScene *scenes;
+  const NuUnit *units;
 };
 size_t nufft_record_bytes(bool intra);
 size_t nufft_der_bytes();
@@ -105,8 +126,13 @@ size_t nufft_fft_smem_bytes(const NuShape &ns);
 size_t nufft_sort_smem_bytes(const NuShape &ns);
 int nufft_cells_per_source(const NuShape &ns);  // 14, 16 or 20; 0: channels too far apart
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+// Forward NUFFT facet sum of ns.n_chirps units (plain: chirps of sc; batched: bt.units,
+// with ns.rec_stride and ns.max_runs the largest of the launch's units).
+// ev (optional): two events recorded just before and just after the spread kernel.
 hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *elem,
-                        const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s);
+                        const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s,
+                        const NuBatch &bt = NuBatch{nullptr, nullptr},
+                        const hipEvent_t *ev = nullptr);
 // Floats per (chirp, lit facet, slot) of the adjoint sums: dL/dc through the element
 // distances (3), sum Re y, dL/dbeta_v (3), pad.
 constexpr int kAdjSlotFloats = 8;
@@ -119,9 +145,11 @@ hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const
 // [N][n_facets][kAdjVals]. Uses nb.srec and nb.sder (records in entry order, rec_stride per
 // chirp), nb.key (per chirp two lists of rec_stride entries: three-point records, others),
 // nb.n_runs (their two counts per chirp) and nb.grid (grid rows [chirp][O][n_g]).
+// ev (optional): two events recorded around the two gather kernels.
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
-                                const void *grad_echo, float *partial, hipStream_t s);
+                                const void *grad_echo, float *partial, hipStream_t s,
+                                const hipEvent_t *ev = nullptr);
 
 // Allocation-free range-Doppler processing: a file-scope device array of
 // kStaticScratchBytes per GPU, addressed through static_scratch_address (looked up once

@@ -28,15 +28,16 @@ RSIM_KERNEL_VECTOR = 1
 RSIM_KERNEL_MATRIX = 2
 RSIM_KERNEL_NUFFT = 3
 ABI_VERSION = 2
-N_STAGES = 8
+CENSUS_FORMS = ("none", "three_points", "point_and_quadratic", "quadratic")
+N_STAGES = 10
 STAGES = ("visibility", "compaction", "facet_sum", "range_fft", "doppler_rdm",
-          "adjoint_facet_sum", "adjoint_fft", "vertex_gather")
+          "adjoint_facet_sum", "adjoint_fft", "vertex_gather", "nufft_spread", "nufft_gather")
 
 EXPORTS = (
     "rsim_abi_version", "rsim_create", "rsim_destroy", "rsim_last_error", "rsim_set_mem_limit",
     "rsim_load_mesh", "rsim_create_scene", "rsim_add_instance", "rsim_add_points",
     "rsim_scene_info", "rsim_set_waveform", "rsim_set_array", "rsim_synthesize",
-    "rsim_form_rdm", "rsim_last_timings", "rsim_backward", "rsim_rdm_adjoint",
+    "rsim_form_rdm", "rsim_last_timings", "rsim_last_census", "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
     "rsim_rdm_backward", "rsim_detect", "rsim_add_noise", "rsim_set_ground",
     "rsim_set_backward_kernel", "rsim_set_nufft_chunk", "rsim_form_rdm_noalloc",
@@ -60,7 +61,8 @@ class Opts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("tile_m", ctypes.c_int32),
                 ("tile_f", ctypes.c_int32), ("intra_chirp", ctypes.c_int32),
-                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("kernel", ctypes.c_int32), ("census", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class CfarOpts(ctypes.Structure):
@@ -115,6 +117,7 @@ def lib() -> ctypes.CDLL:
         "rsim_synthesize": ([vp, ctypes.POINTER(i32), i32, vp, vp, vp, ctypes.POINTER(Opts)], i32),
         "rsim_form_rdm": ([vp, vp, i32, vp, vp, vp, ctypes.POINTER(Opts)], i32),
         "rsim_last_timings": ([vp, ctypes.POINTER(ctypes.c_float), i32], i32),
+        "rsim_last_census": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
         "rsim_backward": ([vp, i32, vp, vp, ctypes.POINTER(vp), i32, vp, vp], i32),
         "rsim_rdm_adjoint": ([vp, vp, i32, vp, vp], i32),
         "rsim_autotune": ([vp, ctypes.POINTER(i32), i32, ctypes.c_char_p], i32),
@@ -290,10 +293,10 @@ class Context:
     @staticmethod
     def opts(precision=RSIM_FP32_PHASE64, mask_mode=RSIM_MASK_COMPUTE, use_graph=False,
              persistent=False, timing=False, tile_m=0, tile_f=0, intra_chirp=False,
-             kernel=RSIM_KERNEL_AUTO) -> Opts:
+             kernel=RSIM_KERNEL_AUTO, census=False) -> Opts:
         return Opts(int(precision), int(mask_mode), int(bool(use_graph)), int(bool(persistent)),
                     int(bool(timing)), int(tile_m), int(tile_f), int(bool(intra_chirp)),
-                    int(kernel))
+                    int(kernel), int(bool(census)))
 
     def synthesize(self, scene_ids: Sequence[int], echo, mask=None, stream=None, **kw):
         ids = (ctypes.c_int32 * len(scene_ids))(*[int(s) for s in scene_ids])
@@ -348,6 +351,12 @@ class Context:
         buf = (ctypes.c_float * N_STAGES)()
         self._check(self._L.rsim_last_timings(self._h, buf, N_STAGES))
         return {name: float(buf[i]) for i, name in enumerate(STAGES)}
+
+    def last_census(self) -> dict:
+        """Record counts by source form of the last NUFFT call made with census=1."""
+        buf = (ctypes.c_int64 * 4)()
+        self._check(self._L.rsim_last_census(self._h, buf))
+        return {name: int(buf[i]) for i, name in enumerate(CENSUS_FORMS)}
 
     def autotune(self, scene_ids: Sequence[int], cache_path: Optional[str] = None):
         ids = (ctypes.c_int32 * len(scene_ids))(*[int(s) for s in scene_ids])

@@ -86,6 +86,60 @@ def test_nufft_batched_coarse_meshes(sim_mod):
     assert err <= FP32_TOL
 
 
+def _census_from_geometry(sc, wf, arr, mask):
+    """Source forms of the lit (facet, chirp) records from the geometry alone: node
+    offsets beta_v = (v - c).(u_t + u_r) with u_t, u_r the unit vectors from the centroid
+    c to the Tx and Rx phase centres; a node pair is close when k_c |beta_a - beta_b| < 2
+    rad, k_c = 2 pi (f0 + (M/2) df) / c. No close pair: three points; one: a point and a
+    quadratic; more: one quadratic; zero area: no source."""
+    C0 = 299_792_458.0
+    fc = wf.f0 + (wf.n_samples // 2) * wf.slope / wf.fs
+    kc = 2.0 * np.pi * fc / C0
+    tx_c, rx_c = np.asarray(arr.tx, np.float64).mean(0), np.asarray(arr.rx, np.float64).mean(0)
+    counts = np.zeros(4, np.int64)
+    for n in range(wf.n_chirps):
+        tri, _, _ = oracle.world_triangles(sc, n * wf.chirp_period)
+        tri = tri[mask[n]]
+        c = tri.mean(axis=1)
+        ut = tx_c - c
+        ur = rx_c - c
+        w = (ut / np.linalg.norm(ut, axis=1, keepdims=True) +
+             ur / np.linalg.norm(ur, axis=1, keepdims=True))
+        beta = np.einsum("fvk,fk->fv", tri - c[:, None, :], w)
+        area2 = np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1)
+        gaps = kc * np.abs(np.stack([beta[:, 1] - beta[:, 2], beta[:, 0] - beta[:, 2],
+                                     beta[:, 0] - beta[:, 1]], axis=1))
+        narrow = (gaps < 2.0).sum(axis=1)
+        kind = np.where(narrow == 0, 1, np.where(narrow == 1, 2, 3))
+        kind[area2 <= 0.0] = 0
+        counts += np.bincount(kind, minlength=4)
+    return counts
+
+
+def test_nufft_census(sim_mod):
+    """rsim_last_census counts each lit (facet, chirp) record once, by the source form its
+    geometry fixes (here three-point and close-pair records); the census changes no output
+    bit."""
+    _log("case nufft record census, 6000 and 300 triangles, M=256, N=2")
+    for n_tris in (6000, 300):
+        cfg = scenes.small_single(n_samples=256, n_chirps=2, n_tris=n_tris)
+        sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
+        sim = sim_mod.Simulator([sc], wf, arr)
+        omask, _ = oracle.visibility(sc, arr, wf)
+        m_in = sim.mask_from_numpy([omask])
+        H0 = sim.synthesize(mask=m_in, mask_mode=1, kernel=NUFFT).cpu().numpy()
+        H1 = sim.synthesize(mask=m_in, mask_mode=1, kernel=NUFFT, census=True).cpu().numpy()
+        got = sim.ctx.last_census()
+        want = _census_from_geometry(sc, wf, arr, omask)
+        g = np.array([got[k] for k in ("none", "three_points", "point_and_quadratic",
+                                       "quadratic")])
+        _log(f"  {n_tris} triangles: census {g.tolist()} from the geometry {want.tolist()}")
+        assert g.sum() == omask.sum()
+        # a node gap within rounding of the 2 rad threshold may fall either way
+        assert np.abs(g - want).max() <= 2
+        assert np.array_equal(H0, H1)
+
+
 def test_nufft_points(sim_mod):
     """Point scatterers only (a point is a degenerate facet with all nodes at the
     centroid: three Taylor terms are nonzero)."""
