@@ -597,6 +597,9 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc0
 template <int S0, int NCELL>
 __device__ __forceinline__ void point_cells(float2 (&acc)[kNuSlots], float2 cw, float gw,
                                             float rho, float q_ratio) {
+  // the weights are formed here, in the block: hoisted ahead of the chain of blocks (they
+  // are the same in every block) they would hold NCELL registers more across it
+  asm volatile("" : "+v"(gw), "+v"(rho));
 #pragma unroll
   for (int j = 0; j < NCELL; ++j) {
     if (S0 + j < kNuSlots) {
@@ -612,6 +615,7 @@ __device__ __forceinline__ void point_cells(float2 (&acc)[kNuSlots], float2 cw, 
 template <int S0, int NCELL, int NC>
 __device__ __forceinline__ void poly_cells(float2 (&acc)[kNuSlots], const float2 (&c)[NC],
                                            float u0, float gw, float rho, float q_ratio) {
+  asm volatile("" : "+v"(u0), "+v"(gw), "+v"(rho));  // formed in the block, as above
 #pragma unroll
   for (int j = 0; j < NCELL; ++j) {
     if (S0 + j < kNuSlots) {
@@ -696,10 +700,14 @@ __device__ __forceinline__ void intra_coeffs(const float2 (&c)[NI], float2 (&o)[
 
 // One workgroup per (chirp, run) and up to four 64-channel groups (blockIdx.z counts
 // further groups); lane = channel. The run's records (read once per wave through scalar
-// loads) add their sources into a register window of kNuSlots cells starting at the
-// run's base cell; the window is written to part[chirp][run][channel][kNuSlots].
+// loads, the next one in flight while the current one is spread) add their sources into a
+// register window of kNuSlots cells starting at the run's base cell; the window is written
+// to part[chirp][run][channel][kNuSlots]. The kernel waits mostly on latencies (record
+// loads, transcendental results, the branch chain), so occupancy pays: the stop-and-hop
+// form is held to five waves per SIMD (96 registers), the other to four.
 template <bool INTRA, int NCELL>
-__global__ void __launch_bounds__(256) nufft_spread_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(INTRA ? 4 : 5, 8)))
+nufft_spread_kernel(
     DevScene sc0, RadarConst rc, NuShape ns, const double *elem,
     const NuRecF<INTRA> *__restrict__ sorted, const int4 *__restrict__ runs,
     const int32_t *__restrict__ n_runs, float2 *__restrict__ part, NuBatch bt) {
@@ -749,8 +757,10 @@ __global__ void __launch_bounds__(256) nufft_spread_kernel(
   float2 acc[kNuSlots];
 #pragma unroll
   for (int s = 0; s < kNuSlots; ++s) acc[s] = {0.0f, 0.0f};
+  NuRecF<INTRA> nxt = load_uniform(srec + rr.x);
   for (int i = rr.x; i < rr.y; ++i) {
-    const NuRecF<INTRA> r = load_uniform(srec + i);
+    const NuRecF<INTRA> r = nxt;
+    nxt = load_uniform(srec + (i + 1 < rr.y ? i + 1 : i));
     if (r.kind == 0) continue;  // wave-uniform
     // position of the phase-centre path in the window
     const float rel_c = static_cast<float>(r.cell - rr.z) + r.frac;
