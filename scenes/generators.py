@@ -492,6 +492,32 @@ def plate_scene(a, b, n_a, n_b, distance, tilt_rad=0.0, centre=RADAR_POS) -> Sce
     return Scene(meshes=[mesh], instances=[inst])
 
 
+def dihedral_scene(a, b, distance, n_a=1, n_b=1, centre=RADAR_POS) -> Scene:
+    """Right-angle dihedral (two a x b plates meeting on a fold line of length a along
+    world x) at `distance` along +Y from `centre`, opening towards it: the plates leave the
+    fold at +45 and -45 degrees from the line of sight in the y-z plane, with normals
+    facing into the corner. Each plate is an n_a x n_b grid of quads (two triangles each)."""
+    xs = np.linspace(-0.5 * a, 0.5 * a, n_a + 1)
+    ss = np.linspace(0.0, b, n_b + 1)
+    h = np.sqrt(0.5)
+    meshes_pts, meshes_tris = [], []
+    for sign in (1.0, -1.0):
+        def p(i, j, sign=sign):
+            return np.stack([xs[i], -h * ss[j], sign * h * ss[j]], 1)
+        pts, tris = _grid_quads(p, n_a, n_b)
+        nrm = np.array([0.0, -h, -sign * h])
+        tris = _orient(pts, tris, lambda c, nrm=nrm: np.tile(nrm, (c.shape[0], 1)))
+        meshes_pts.append(pts)
+        meshes_tris.append(tris)
+    off = meshes_pts[0].shape[0]
+    pts = np.concatenate(meshes_pts)
+    tris = np.concatenate([meshes_tris[0], meshes_tris[1] + off])
+    mesh = Mesh(verts=pts.astype(np.float32), tris=tris.astype(np.int32), name="dihedral")
+    pos0 = np.asarray(centre, np.float64) + np.array([0.0, distance, 0.0])
+    inst = Instance(mesh=0, rot=np.eye(3), pos0=pos0, vel=np.zeros(3))
+    return Scene(meshes=[mesh], instances=[inst])
+
+
 # ----------------------------------------------------------------------------------
 # synthetic range-Doppler cubes for the detection stage
 # ----------------------------------------------------------------------------------
