@@ -193,6 +193,32 @@ int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx,
 int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double gamma_re,
                         double gamma_im);
 
+/* Facet-to-facet double bounce (Section 2.2: a ray followed as the facets reflect it and
+ * a ray from the other end joined on a facet). With enable = 1, rsim_synthesize adds for
+ * each chirp the paths T -> A -> B -> R over pairs of facets, each found from both ends:
+ * a ray launched from a phase centre E (the Tx one, then the Rx one) reflects specularly
+ * off the centroid of facet A (lit from E: facing it, unblocked) and first hits facet B,
+ * which must face the image E' of E in A's plane and the other phase centre O with the
+ * segment hit point -> O clear. The connection's echo is gamma / 2 times the facet term of
+ * eqs. (7), (9)-(13) of the footprint of A's reflected tube on B's plane (the central
+ * projection from E' of A's vertices, taken whole, not clipped to B) with E's elements
+ * replaced by their images in A's plane; the two launching ends of a path each give half.
+ * Connections are kept when every projection parameter exceeds 1/2 and the footprint lies
+ * within 1.5 times the scene's largest facet radius of its centroid. Point scatterers
+ * take no double bounce. gamma: complex reflection coefficient (-1: perfect conductor).
+ * Runs in the NUFFT facet sum only: rsim_synthesize then fails with EINVAL for
+ * RSIM_KERNEL_VECTOR / MATRIX, RSIM_FP64, intra_chirp, persistent or the ground plane,
+ * with ERANGE where the NUFFT is ineligible (its window also holds the footprints); the
+ * lit mask covers the single-bounce path only. A caller's vis_mask buffer then holds,
+ * after each scene's N * mask_words words, that scene's connection table [2][N][F]
+ * int32: for the ray launched from the Tx (first plane) or Rx (second) end at chirp n and
+ * facet A, the facet B it connects to, or -1 (output with RSIM_MASK_COMPUTE, input with
+ * RSIM_MASK_INPUT; a given entry outside 0 .. F-1 means no connection). rsim_backward
+ * returns ESTATE and
+ * rsim_autotune ESTATE while it is on. EINVAL for enable not 0/1 or a non-finite gamma.
+ * Device memory: 16 N F + 8 N bytes per scene for the connections. */
+int32_t rsim_set_double_bounce(rsim_ctx *ctx, int32_t enable, double gamma_re, double gamma_im);
+
 /* ---- echo and RDM ------------------------------------------------------------------ */
 
 /* Echo frequency response H (Sections 2.2, 3.2; eqs. (7), (9)-(13)) of each scene:

@@ -150,7 +150,8 @@ def double_bounce_pairs(scene, array, wf, chirps=None):
     """The connections (A, B) launched from both ends, per chirp: a list (one entry per
     chirp) of dicts k -> {"A": [P], "B": [P], "F": [P,3,3], "plane_p": [P,3],
     "plane_n": [P,3], "amb": [P]} over the kept pairs, plus "amb_rejected": the number of
-    rejected candidates A whose rejection hung on an ambiguous decision."""
+    rejected candidates A whose rejection hung on an ambiguous decision, and "amb_facets":
+    every candidate A (kept or rejected) with an ambiguous decision."""
     tx_c = np.asarray(array.tx, np.float64).mean(axis=0)
     rx_c = np.asarray(array.rx, np.float64).mean(axis=0)
     chirps = np.arange(wf.n_chirps) if chirps is None else np.asarray(chirps)
@@ -210,9 +211,19 @@ def double_bounce_pairs(scene, array, wf, chirps=None):
             sel = np.nonzero(keep)[0]
             per[k] = {"A": cand[sel], "B": B[sel], "F": Ft[sel], "plane_p": c[cand[sel]],
                       "plane_n": nrm[cand[sel]], "amb": amb[sel],
-                      "amb_rejected": int(np.count_nonzero(amb & ~keep))}
+                      "amb_rejected": int(np.count_nonzero(amb & ~keep)),
+                      "amb_facets": cand[amb]}
         out.append(per)
     return out
+
+
+def connection_table(pairs, n_facets: int) -> np.ndarray:
+    """[2, n_chirps, F] int32: the facet B each launched ray connects to, or -1."""
+    t = np.full((2, len(pairs), n_facets), -1, np.int32)
+    for ni, per in enumerate(pairs):
+        for k in (0, 1):
+            t[k, ni, per[k]["A"]] = per[k]["B"]
+    return t
 
 
 def synthesize_double(scene, wf, array, gamma: complex = -1.0, pairs=None, chirps=None,

@@ -65,6 +65,9 @@ struct SceneRec {
   uint32_t *d_mask = nullptr;
   int32_t *d_vis_idx = nullptr;
   int32_t *d_vis_cnt = nullptr;
+  // double bounce: connections [2][N][F], connected facets [2][N][F], counts [2][N]
+  int32_t db_N = -1;
+  int32_t *d_db = nullptr;
 };
 
 struct TunedShape {
@@ -159,6 +162,9 @@ struct rsim_ctx {
   double z_ground = 0.0, gamma_re = -1.0, gamma_im = 0.0;
   double *d_elem_img = nullptr;  // [3][E][3]: elements of path types 1..3 (images)
   uint64_t elem_img_version = 0;
+  // facet-to-facet double bounce (rsim_set_double_bounce)
+  bool dbounce = false;
+  double db_gamma_re = -1.0, db_gamma_im = 0.0;
   // this device's copy of the allocation-free entry point's work array (never freed)
   void *static_scratch = nullptr;
 };
@@ -381,6 +387,16 @@ int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
     sc.buf_N = N;
     sc.buf_types = types;
   }
+  if (ctx->dbounce && sc.db_N != N) {
+    dev_free(ctx, sc.d_db);
+    sc.d_db = nullptr;
+    sc.db_N = -1;
+    const size_t words = 4 * static_cast<size_t>(N) * std::max<int64_t>(1, sc.n_facets) + 2 * N;
+    int32_t rc;
+    if ((rc = dev_alloc(ctx, reinterpret_cast<void **>(&sc.d_db), sizeof(int32_t) * words)))
+      return rc;
+    sc.db_N = N;
+  }
   return RSIM_OK;
 }
 
@@ -598,7 +614,8 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
                              double r_max, double v_max, NuShape *ns) {
   NuShape s{};
   if (const char *why = nufft_common(ctx, rc, o, v_max, &s)) return why;
-  s.off_max = 2.0 * r_max * s.kappa;
+  // a double-bounce footprint reaches 1.5 times the largest facet radius
+  s.off_max = (ctx->dbounce ? 3.0 : 2.0) * r_max * s.kappa;
   s.b0 = static_cast<int32_t>(std::ceil(s.chan_d + s.off_max + 0.5 * kNuWidth));
   s.kspan = kNuSlots - 2 - 2 * s.b0;
   if (nufft_cells_per_source(s) == 0)
@@ -654,6 +671,8 @@ struct SumPlan {
   std::vector<NuUnit> nu_units;
   std::vector<std::array<int64_t, 4>> nu_chunks;
   const void *tw = nullptr;  // NUFFT: twiddles of the grid length
+  // double bounce, per scene: metres a reflected ray is followed; largest facet radius
+  std::vector<double> db_ray_len, db_r_lim;
   int batch_key = 0;  // tile key of the persistent work tables (0 for the matrix cores)
 };
 
@@ -664,9 +683,9 @@ SumPlan plan_sum(const rsim_ctx *ctx, const RadarConst &rc, const rsim_opts &o, 
   const bool eligible = matrix_ineligible(ctx, rc, o.precision) == nullptr;
   NuShape ns{};
   const bool nu_ok = nufft_ineligible(ctx, rc, o, r_max, v_max, &ns) == nullptr;
-  if (o.kernel == RSIM_KERNEL_NUFFT || (o.kernel == RSIM_KERNEL_AUTO && nu_ok &&
-                                        pl.ts.kernel == RSIM_KERNEL_NUFFT && !o.tile_m &&
-                                        !o.tile_f)) {
+  if (o.kernel == RSIM_KERNEL_NUFFT || ctx->dbounce ||
+      (o.kernel == RSIM_KERNEL_AUTO && nu_ok && pl.ts.kernel == RSIM_KERNEL_NUFFT &&
+       !o.tile_m && !o.tile_f)) {
     pl.nufft = true;
     pl.ns = ns;
     pl.sh = echo_shape(ctx, rc, 64);
@@ -856,6 +875,21 @@ std::vector<DevScene> scene_views(rsim_ctx *ctx, const std::vector<int32_t> &ids
     uint32_t *mask = vis_mask ? vis_mask + mask_off : sc.d_mask;
     mask_off += static_cast<int64_t>(ctx->ground ? 4 : 1) * rc.N * ((sc.n_facets + 31) / 32);
     ds[i] = dev_scene(sc, mask, static_cast<char *>(echo) + i * cube * csize);
+    if (ctx->dbounce && sc.d_db) {
+      // the connection table follows the scene's mask words in a caller's mask buffer
+      const int64_t plane = 2 * static_cast<int64_t>(rc.N) * std::max<int64_t>(1, sc.n_facets);
+      ds[i].db_on = 1;
+      ds[i].db_b = sc.d_db;
+      if (vis_mask) {
+        ds[i].db_b = reinterpret_cast<const int32_t *>(vis_mask + mask_off);
+        mask_off += 2 * static_cast<int64_t>(rc.N) * sc.n_facets;
+      }
+      ds[i].db_idx = sc.d_db + plane;
+      ds[i].db_cnt = sc.d_db + 2 * plane;
+      ds[i].db_gamma_re = ctx->db_gamma_re;
+      ds[i].db_gamma_im = ctx->db_gamma_im;
+      ds[i].db_n = rc.N;
+    }
     // a traversal keeps at most three pending nodes per level of its four-wide BVH
     int depth = 0;
     for (const InstRec &r : sc.inst) depth = std::max(depth, ctx->meshes[r.mesh].depth);
@@ -981,6 +1015,15 @@ int32_t enqueue_synthesis(rsim_ctx *ctx, const std::vector<DevScene> &ds, const 
   if (!ctx->ground) {
     stage_begin(ctx, timing, 1, s);
     for (auto &d : ds) HIP_TRY(ctx, launch_compact(d, 0, rc.N, s));
+    for (size_t i = 0; i < ds.size() && ctx->dbounce; ++i) {
+      // facet-to-facet connections (computed, or given with the mask), then their lists
+      const DevScene &d = ds[i];
+      const int64_t plane = 2 * static_cast<int64_t>(rc.N) * std::max<int64_t>(1, d.n_facets);
+      int32_t *work = const_cast<int32_t *>(d.db_idx) - plane;
+      HIP_TRY(ctx, launch_dbounce(d, rc, o.mask_mode == RSIM_MASK_COMPUTE ? pl.db_ray_len[i] : 0.0,
+                                  pl.db_r_lim[i], const_cast<int32_t *>(d.db_b), work + plane,
+                                  work + 2 * plane, s));
+    }
     stage_end(ctx, timing, 1, s);
     stage_begin(ctx, timing, 2, s);
     if (pl.nufft && bt) {
@@ -1377,6 +1420,18 @@ int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double g
   return RSIM_OK;
 }
 
+int32_t rsim_set_double_bounce(rsim_ctx *ctx, int32_t enable, double gamma_re,
+                               double gamma_im) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if ((enable != 0 && enable != 1) || !std::isfinite(gamma_re) || !std::isfinite(gamma_im))
+    return fail(ctx, RSIM_EINVAL, "rsim_set_double_bounce: enable 0/1 and a finite gamma");
+  ctx->dbounce = enable != 0;
+  ctx->db_gamma_re = gamma_re;
+  ctx->db_gamma_im = gamma_im;
+  ctx->version++;  // captured graphs hold the old entries
+  return RSIM_OK;
+}
+
 int32_t rsim_set_nufft_chunk(rsim_ctx *ctx, int32_t max_chirps) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
   if (max_chirps < 0)
@@ -1422,6 +1477,15 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
                 "(persistent = 0)");
   if (o.census && o.use_graph)
     return fail(ctx, RSIM_EINVAL, "rsim_synthesize: census is not taken under a captured graph");
+  if (ctx->dbounce) {
+    if (o.precision != RSIM_FP32_PHASE64 || o.kernel == RSIM_KERNEL_VECTOR ||
+        o.kernel == RSIM_KERNEL_MATRIX)
+      return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the facet-to-facet double bounce is "
+                  "implemented in the NUFFT facet sum only (FP32, kernel AUTO or NUFFT)");
+    if (o.intra_chirp || o.persistent || ctx->ground)
+      return fail(ctx, RSIM_EINVAL, "rsim_synthesize: the facet-to-facet double bounce runs "
+                  "stop-and-hop, with plain launches and without the ground plane");
+  }
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   std::vector<int32_t> ids(scene_ids, scene_ids + n_scenes);
@@ -1441,12 +1505,41 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
   }
   const double r_max = scenes_rmax(ctx, ids), v_max = scenes_vmax(ctx, ids);
-  if (o.kernel == RSIM_KERNEL_NUFFT) {
+  if (o.kernel == RSIM_KERNEL_NUFFT || ctx->dbounce) {
     NuShape tmp{};
     if (const char *why = nufft_ineligible(ctx, rcn, o, r_max, v_max, &tmp))
       return fail(ctx, RSIM_ERANGE, "rsim_synthesize: %s", why);
   }
   SumPlan pl = plan_sum(ctx, rcn, o, r_max, v_max);
+  if (ctx->dbounce) {
+    // per scene: a reflected ray is followed across the scene's extent over the frame
+    // (the union of its instances' world boxes at the first and last chirp); the
+    // footprint limit is its largest facet radius
+    const double T = (rcn.N - 1) * rcn.tc;
+    for (int32_t id : ids) {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (const InstRec &r : ctx->scenes[id].inst) {
+        const MeshRec &m = ctx->meshes[r.mesh];
+        for (int corner = 0; corner < 8; ++corner) {
+          const double b[3] = {(corner & 1) ? m.box_hi[0] : m.box_lo[0],
+                               (corner & 2) ? m.box_hi[1] : m.box_lo[1],
+                               (corner & 4) ? m.box_hi[2] : m.box_lo[2]};
+          for (int q = 0; q < 3; ++q) {
+            const double x = r.rot[3 * q] * b[0] + r.rot[3 * q + 1] * b[1] + r.rot[3 * q + 2] * b[2] +
+                             r.pos0[q];
+            for (const double tt : {0.0, T}) {
+              lo[q] = std::min(lo[q], x + r.vel[q] * tt);
+              hi[q] = std::max(hi[q], x + r.vel[q] * tt);
+            }
+          }
+        }
+      }
+      double diag = 0.0;
+      for (int q = 0; q < 3; ++q) diag += hi[q] > lo[q] ? (hi[q] - lo[q]) * (hi[q] - lo[q]) : 0.0;
+      pl.db_ray_len.push_back(std::sqrt(diag) + 1.0);
+      pl.db_r_lim.push_back(scenes_rmax(ctx, {id}));
+    }
+  }
   const TunedShape ts = pl.ts;
   if (!pl.matrix && !pl.nufft && !echo_variant_exists(o.precision, ts.mb, ts.ft))
     return fail(ctx, RSIM_EINVAL, "no facet-sum variant with tile_m=%d tile_f=%d", ts.mb, ts.ft);
@@ -1466,8 +1559,9 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       // eligible, since the call's largest r_max is
       NuShape si{};
       (void)nufft_ineligible(ctx, rcn, o, scenes_rmax(ctx, {id}), v_max, &si);
-      si.rec_stride = std::max<int64_t>(1, ctx->scenes[id].n_facets +
-                                               static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
+      si.rec_stride = std::max<int64_t>(
+          1, ctx->scenes[id].n_facets * (ctx->dbounce ? 3 : 1) +
+                 static_cast<int64_t>(ctx->scenes[id].pt_amp.size() / 2));
       si.run_len = nufft_run_len(ctx, si.rec_stride, rcn.N);
       si.max_runs = nufft_max_runs(si, si.rec_stride);
       stride = std::max(stride, si.rec_stride);
@@ -1726,6 +1820,9 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   if (ctx->ground)
     return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path; "
                 "disable the ground bounce (rsim_set_ground) first");
+  if (ctx->dbounce)
+    return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path; "
+                "disable the double bounce (rsim_set_double_bounce) first");
   const RadarConst rcn = radar_const(ctx);
   if (cross_term_bound(ctx, rcn) > 3e-4)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: array aperture too large for the FP32 sum");
@@ -2187,6 +2284,9 @@ int32_t rsim_autotune(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes,
                       const char *cache_json_path) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
   if (!scene_ids || n_scenes < 1) return fail(ctx, RSIM_EINVAL, "rsim_autotune: no scenes");
+  if (ctx->dbounce)
+    return fail(ctx, RSIM_ESTATE, "rsim_autotune: with the double bounce the facet sum is the "
+                "NUFFT; disable it (rsim_set_double_bounce) to time the kernels");
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   if ((rc = need_device(ctx))) return rc;

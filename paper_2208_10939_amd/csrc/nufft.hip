@@ -410,6 +410,131 @@ __device__ inline NuWork nu_work(const DevScene &sc, const NuShape &ns, const Nu
   return w;
 }
 
+// Geometry of facet-sum entry `item` of chirp n and the phase centres its path starts
+// from: a lit facet or a point (entry_geometry, rc_e = rc, *side = -1), or a facet-to-facet
+// double-bounce connection (A, B) launched from end *side (0 Tx, 1 Rx): the footprint of
+// A's reflected tube on B's plane (central projection from the image E' of that end's
+// phase centre in A's plane, ordered to B's normal) as the facet, that centre replaced by
+// E' in rc_e, gamma / 2 in the amplitude (the connection is one of the two evaluations of
+// its path), and A's unit normal in refl: the mirror that maps that end's channel offsets
+// to the image elements' (distances from image elements are those of the folded path).
+__device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int32_t cnt,
+                            int32_t item, Geo &g, RadarConst &rc_e, double refl[3], int *side) {
+  rc_e = rc;
+  refl[0] = refl[1] = refl[2] = 0.0;
+  *side = -1;
+  const int32_t base = cnt + sc.n_points;
+  if (!sc.db_on || item < base) {
+    entry_geometry(sc, rc, n, cnt, item, g);
+    return;
+  }
+  int32_t j = item - base;
+  int k = 0;
+  const int32_t c0 = sc.db_cnt[n];
+  if (j >= c0) {
+    k = 1;
+    j -= c0;
+  }
+  const int64_t row = (static_cast<int64_t>(k) * sc.db_n + n) * sc.n_facets;
+  const int64_t fa = sc.db_idx[row + j];
+  const int64_t fb = sc.db_b[row + fa];
+  const double t = n * rc.tc;
+  double xa[3][3], xb[3][3];
+  for (int w = 0; w < 2; ++w) {
+    const int64_t f = w ? fb : fa;
+    const DevInstance &I = sc.inst[find_inst(sc.inst, sc.n_inst, f)];
+    const int64_t lt = f - I.facet_base;
+    for (int v = 0; v < 3; ++v) {
+      const int32_t vi = I.tris[3 * lt + v];
+      const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
+      for (int q = 0; q < 3; ++q) {
+        const double x = I.rot[3 * q + 0] * b0 + I.rot[3 * q + 1] * b1 + I.rot[3 * q + 2] * b2 +
+                         (I.pos0[q] + I.vel[q] * t);
+        (w ? xb : xa)[v][q] = x;
+      }
+    }
+  }
+  auto unit_normal = [](const double x[3][3], double nrm[3], double c[3]) {
+    double e1[3], e2[3];
+    for (int q = 0; q < 3; ++q) {
+      c[q] = (x[0][q] + x[1][q] + x[2][q]) * (1.0 / 3.0);
+      e1[q] = x[1][q] - x[0][q];
+      e2[q] = x[2][q] - x[0][q];
+    }
+    nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double a = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+    for (int q = 0; q < 3; ++q) nrm[q] /= a;
+  };
+  double na[3], ca[3], nb[3], cb[3];
+  unit_normal(xa, na, ca);
+  unit_normal(xb, nb, cb);
+  const double *E = k ? rc.rx_c : rc.tx_c;
+  const double fe = na[0] * (E[0] - ca[0]) + na[1] * (E[1] - ca[1]) + na[2] * (E[2] - ca[2]);
+  double ei[3];
+  for (int q = 0; q < 3; ++q) ei[q] = E[q] - 2.0 * fe * na[q];
+  const double num = nb[0] * (cb[0] - ei[0]) + nb[1] * (cb[1] - ei[1]) + nb[2] * (cb[2] - ei[2]);
+  double x[3][3];
+  for (int v = 0; v < 3; ++v) {
+    const double d0 = xa[v][0] - ei[0], d1 = xa[v][1] - ei[1], d2 = xa[v][2] - ei[2];
+    const double sv = num / (nb[0] * d0 + nb[1] * d1 + nb[2] * d2);
+    x[v][0] = ei[0] + sv * d0;
+    x[v][1] = ei[1] + sv * d1;
+    x[v][2] = ei[2] + sv * d2;
+  }
+  double c[3], e1[3], e2[3];
+  for (int q = 0; q < 3; ++q) {
+    c[q] = (x[0][q] + x[1][q] + x[2][q]) * (1.0 / 3.0);
+    e1[q] = x[1][q] - x[0][q];
+    e2[q] = x[2][q] - x[0][q];
+  }
+  double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                  e1[0] * e2[1] - e1[1] * e2[0]};
+  if (nv[0] * nb[0] + nv[1] * nb[1] + nv[2] * nb[2] < 0.0) {
+    // ordered to B's normal: swapping two vertices flips the winding
+    for (int q = 0; q < 3; ++q) {
+      const double tmp = x[1][q];
+      x[1][q] = x[2][q];
+      x[2][q] = tmp;
+      nv[q] = -nv[q];
+    }
+  }
+  for (int q = 0; q < 3; ++q) {
+    if (k == 0)
+      rc_e.tx_c[q] = ei[q];
+    else
+      rc_e.rx_c[q] = ei[q];
+    refl[q] = na[q];
+  }
+  *side = k;
+  const double two_area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  double ut[3], ur[3];
+  for (int q = 0; q < 3; ++q) {
+    ut[q] = rc_e.tx_c[q] - c[q];
+    ur[q] = rc_e.rx_c[q] - c[q];
+  }
+  const double rt = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+  const double rr = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
+  double w[3];
+  for (int q = 0; q < 3; ++q) w[q] = ut[q] / rt + ur[q] / rr;
+  const double nw = nv[0] * w[0] + nv[1] * w[1] + nv[2] * w[2];
+  for (int v = 0; v < 3; ++v)
+    g.beta[v] = w[0] * (x[v][0] - c[0]) + w[1] * (x[v][1] - c[1]) + w[2] * (x[v][2] - c[2]);
+  // j (o A / (2 pi)) times gamma / 2
+  const double xo = two_area > 0.0 ? nw * (0.25 / (2.0 * kPi)) : 0.0;
+  g.amp_re = -0.5 * xo * sc.db_gamma_im;
+  g.amp_im = 0.5 * xo * sc.db_gamma_re;
+  g.tref_t = rt / kC0;
+  g.tref_r = rr / kC0;
+  for (int q = 0; q < 3; ++q) {
+    g.vel[q] = 0.0;
+    g.c[q] = c[q];
+  }
+  g.valid = two_area > 0.0;
+  g.pad = 0;
+}
+
 template <bool INTRA>
 __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc0, RadarConst rc, NuShape ns,
                                                         NuBuffers nb, NuBatch bt) {
@@ -418,12 +543,16 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc0, RadarCons
   const int n = w.n;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  const int32_t total = entry_total(sc, n);
   if (nb.census) {
     // wave counts of each form, added into one of kNuCensusSlots rows
     int kind = -1;
-    if (item < cnt + sc.n_points) {
+    if (item < total) {
       Geo g;
-      entry_geometry(sc, rc, n, cnt, item, g);
+      RadarConst rc_e;
+      double refl[3];
+      int side;
+      nufft_entry(sc, rc, n, cnt, item, g, rc_e, refl, &side);
       int far;
       kind = nufft_classify(g, ns, &far);
     }
@@ -435,13 +564,22 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc0, RadarCons
         atomicAdd(nb.census + 4 * row + k, static_cast<unsigned long long>(__popcll(m)));
     }
   }
-  if (item >= cnt + sc.n_points) return;
+  if (item >= total) return;
   Geo g;
-  entry_geometry(sc, rc, n, cnt, item, g);
+  RadarConst rc_e;
+  double refl[3];
+  int side;
+  nufft_entry(sc, rc, n, cnt, item, g, rc_e, refl, &side);
   NuRecF<INTRA> out;
   out.kind = nufft_sources(g, ns, out.s);
   double Rt, Rr, dxc;
-  path_fields(g, rc, ns, 0.0, out, &Rt, &Rr, &dxc);
+  path_fields(g, rc_e, ns, 0.0, out, &Rt, &Rr, &dxc);
+  if (side >= 0) {
+    // the launching end's channel offsets act through its mirrored direction
+    double *u = side == 0 ? out.ut : out.ur;
+    const double un = u[0] * refl[0] + u[1] * refl[1] + u[2] * refl[2];
+    for (int q = 0; q < 3; ++q) u[q] -= 2.0 * un * refl[q];
+  }
   if constexpr (INTRA) {
     double vut = 0.0, vur = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -465,12 +603,15 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc0, RadarConst
   const int n = w.n;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  if (item >= cnt + sc.n_points) return;
+  if (item >= entry_total(sc, n)) return;
   Geo g;
-  entry_geometry(sc, rc, n, cnt, item, g);
+  RadarConst rc_e;
+  double refl[3];
+  int side;
+  nufft_entry(sc, rc, n, cnt, item, g, rc_e, refl, &side);
   double x, Rt, Rr, dxc;
   int cell;
-  centre_cell(g, rc, ns, 0.0, &x, &cell, &Rt, &Rr, &dxc);
+  centre_cell(g, rc_e, ns, 0.0, &x, &cell, &Rt, &Rr, &dxc);
   nb.key[w.rec + item] = cell;
 }
 
@@ -492,7 +633,7 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc0
   const int n = wk.n;
   const int32_t *key = nb.key + wk.rec;
   int32_t *pos = nb.pos + wk.rec;
-  const int32_t n_ent = sc.vis_cnt[n] + sc.n_points;
+  const int32_t n_ent = entry_total(sc, n);
   const int tid = static_cast<int>(threadIdx.x);
   const int w = tid >> 6, lane = tid & 63;
   const int32_t seg = ((n_ent + kNuSortWaves - 1) / kNuSortWaves + 63) & ~63;
@@ -1332,7 +1473,8 @@ template <bool INTRA>
 static hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const double *elem,
                                  const NuShape &ns, const NuBuffers &nb, const void *tw,
                                  hipStream_t s, const NuBatch &bt, const hipEvent_t *ev) {
-  const int64_t items = bt.units ? ns.rec_stride : sc.n_facets + sc.n_points;
+  const int64_t items = bt.units ? ns.rec_stride
+                                 : sc.n_facets + sc.n_points + (sc.db_on ? 2 * sc.n_facets : 0);
   if (items > 0) {
     dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
     hipLaunchKernelGGL(nufft_key_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb, bt);

@@ -101,7 +101,23 @@ struct DevScene {
   int32_t *vis_cnt;          // [N]
   void *echo;                // [O][N][M] complex
   int32_t stack_depth;       // traversal stack entries per thread (> deepest BVH level)
-  int32_t pad;
+  // facet-to-facet double bounce (db_on = 1): per (end k, chirp n, facet A) the facet B
+  // that A's reflected ray connects to or -1, the connected A per (k, n) in ascending
+  // order and their counts; N = db_n chirps; gamma of the reflection
+  int32_t db_on;
+  const int32_t *db_b;       // [2][N][n_facets]
+  const int32_t *db_idx;     // [2][N][n_facets]
+  const int32_t *db_cnt;     // [2][N]
+  double db_gamma_re, db_gamma_im;
+  int32_t db_n, db_pad;
 };
+
+// Facet-sum entries of chirp n: its lit facets, the points, then (double bounce) the
+// connections launched from the Tx side and from the Rx side.
+__device__ inline int32_t entry_total(const DevScene &sc, int n) {
+  int32_t e = sc.vis_cnt[n] + sc.n_points;
+  if (sc.db_on) e += sc.db_cnt[n] + sc.db_cnt[sc.db_n + n];
+  return e;
+}
 
 }  // namespace rsim

@@ -33,6 +33,13 @@ int build_bvh(const float *verts, const int32_t *tris, int64_t n_tris,
 hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, int n_begin, int n_chirps,
                              hipStream_t s);
 hipError_t launch_compact(const DevScene &sc, int n_begin, int n_chirps, hipStream_t s);
+// Facet-to-facet double bounce: the connection of every (launching end, chirp, facet)
+// into pair_b [2][N][F] (the connected facet or -1), then per (end, chirp) the connected
+// facets in ascending order into idx [2][N][F] and their counts into cnt [2][N]. ray_len:
+// metres a reflected ray is followed (0: pair_b is given; only the compaction runs);
+// r_lim: the scene's largest facet radius.
+hipError_t launch_dbounce(const DevScene &sc, const RadarConst &rc, double ray_len, double r_lim,
+                          int32_t *pair_b, int32_t *idx, int32_t *cnt, hipStream_t s);
 
 hipError_t launch_echo_plain(int precision, int mb, int ft, const DevScene &sc,
                              const RadarConst &rc, const double *elem, const EchoShape &sh,

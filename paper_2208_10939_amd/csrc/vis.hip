@@ -421,6 +421,289 @@ __global__ void __launch_bounds__(1024) compact_kernel(DevScene sc, int n_begin)
   if (threadIdx.x == blockDim.x - 1) sc.vis_cnt[n] = s_scan[threadIdx.x];
 }
 
+// ---- facet-to-facet double bounce: connections ----------------------------------------
+
+namespace {
+
+// Slab test of the body-frame ray o + t d against a box for t in [0, t_end].
+__device__ inline bool box_hit_t(const float *lo, const float *hi, float ox, float oy, float oz,
+                                 float ix, float iy, float iz, float t_end) {
+  float tx0 = (lo[0] - ox) * ix, tx1 = (hi[0] - ox) * ix;
+  float ty0 = (lo[1] - oy) * iy, ty1 = (hi[1] - oy) * iy;
+  float tz0 = (lo[2] - oz) * iz, tz1 = (hi[2] - oz) * iz;
+  float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), t_end));
+  return tn <= tf;
+}
+
+// Nearer hits of the leaf's triangles by o + t d, t in (t_min, t_best) (closed test):
+// shrinks t_best and records the triangle id.
+__device__ inline void leaf_closest(const float4 *leaf, int32_t ref, float ox, float oy, float oz,
+                                    float dx, float dy, float dz, int32_t skip, float t_min,
+                                    float &t_best, int32_t &id) {
+  uint32_t code = static_cast<uint32_t>(-ref - 1);
+  uint32_t first = code >> 4, count = code & 15u;
+  for (uint32_t k = 0; k < count; ++k) {
+    const float4 a = leaf[3 * (first + k) + 0];
+    const float4 b = leaf[3 * (first + k) + 1];
+    const float4 c = leaf[3 * (first + k) + 2];
+    const int32_t tid = __float_as_int(c.y);
+    if (tid == skip) continue;
+    float e1x = a.w, e1y = b.x, e1z = b.y;
+    float e2x = b.z, e2y = b.w, e2z = c.x;
+    float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    float det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0f) continue;
+    float inv = 1.0f / det;
+    float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
+    float u = (sx * px + sy * py + sz * pz) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) continue;
+    float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    float v = (dx * qx + dy * qy + dz * qz) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) continue;
+    float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    if (t > t_min && t < t_best) {
+      t_best = t;
+      id = tid;
+    }
+  }
+}
+
+// Closest-hit traversal of one four-wide BLAS (body frame; the same stack discipline as
+// blas_occluded: at most three pending children per level).
+__device__ void blas_closest(const BvhNode4 *nodes, const float4 *leaf, float ox, float oy,
+                             float oz, float dx, float dy, float dz, int32_t skip, float t_min,
+                             float &t_best, int32_t &id, int32_t *stack, int stride) {
+  const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const BvhNode4 nd = nodes[node];
+    int32_t next = -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float lo[3] = {nd.lo[0][i], nd.lo[1][i], nd.lo[2][i]};
+      const float hi[3] = {nd.hi[0][i], nd.hi[1][i], nd.hi[2][i]};
+      if (!box_hit_t(lo, hi, ox, oy, oz, ix, iy, iz, t_best)) continue;
+      const int32_t c = nd.c[i];
+      if (c < 0) {
+        leaf_closest(leaf, c, ox, oy, oz, dx, dy, dz, skip, t_min, t_best, id);
+      } else if (next >= 0) {
+        stack[sp * stride] = c;
+        ++sp;
+      } else {
+        next = c;
+      }
+    }
+    if (next < 0) {
+      if (sp == 0) return;
+      --sp;
+      next = stack[sp * stride];
+    }
+    node = next;
+  }
+}
+
+__device__ inline void world_vertices(const DevInstance &I, int64_t lt, double t, double x[3][3]) {
+  for (int v = 0; v < 3; ++v) {
+    const int32_t vi = I.tris[3 * lt + v];
+    const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
+    for (int k = 0; k < 3; ++k)
+      x[v][k] = I.rot[3 * k + 0] * b0 + I.rot[3 * k + 1] * b1 + I.rot[3 * k + 2] * b2 +
+                (I.pos0[k] + I.vel[k] * t);
+  }
+}
+
+// Unit normal (CCW) and centroid of a world triangle; false for zero area.
+__device__ inline bool tri_frame(const double x[3][3], double c[3], double n[3]) {
+  double e1[3], e2[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = (x[0][k] + x[1][k] + x[2][k]) / 3.0;
+    e1[k] = x[1][k] - x[0][k];
+    e2[k] = x[2][k] - x[0][k];
+  }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double a = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  if (!(a > 0.0)) return false;
+  for (int k = 0; k < 3; ++k) n[k] /= a;
+  return true;
+}
+
+__device__ inline double dot3(const double *a, const double *b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Facet B that the ray launched from end k (0: Tx phase centre, 1: Rx) reflected off facet A
+// (scene index f) connects to at chirp n, or -1 (Section 2.2; the rules of the oracle's
+// facet-to-facet double bounce): A faces the launching centre E and sees it; the specular
+// ray from A's centroid first hits B (FP32 traversal over a segment of ray_len metres); B
+// faces the image E' of E in A's plane and the other centre O, and the segment from the
+// hit point to O is clear; the central projection from E' of A's vertices onto B's plane
+// lies ahead of E' (parameters above 1/2) and within 1.5 r_lim of its centroid.
+__device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t f, int n, int k,
+                              double ray_len, double r_lim, int32_t *stk, int stride) {
+  const double t = n * rc.tc;
+  const double *E = k ? rc.rx_c : rc.tx_c;
+  const double *O = k ? rc.tx_c : rc.rx_c;
+  const int ia = find_instance(sc.inst, sc.n_inst, f);
+  const DevInstance &IA = sc.inst[ia];
+  const int32_t la = static_cast<int32_t>(f - IA.facet_base);
+  double xa[3][3], ca[3], na[3];
+  world_vertices(IA, la, t, xa);
+  if (!tri_frame(xa, ca, na)) return -1;
+  double de[3] = {E[0] - ca[0], E[1] - ca[1], E[2] - ca[2]};
+  const double fe = dot3(na, de);
+  if (!(fe > 0.0)) return -1;
+  if (segment_blocked(sc, t, ca, E, ia, la, stk, stride)) return -1;
+  // specular direction of d = (c_A - E) / |c_A - E|
+  const double ld = sqrt(dot3(de, de));
+  double r[3];
+  for (int q = 0; q < 3; ++q) r[q] = -de[q] / ld;
+  const double rn = dot3(r, na);
+  for (int q = 0; q < 3; ++q) r[q] -= 2.0 * rn * na[q];
+  // first hit over all instances (A excluded), t as a fraction of ray_len
+  float t_best = 1.0f;
+  int32_t id_best = -1, inst_best = -1;
+  const float t_min = static_cast<float>(1e-6 / ray_len);
+  for (int j = 0; j < sc.n_inst; ++j) {
+    const DevInstance &I = sc.inst[j];
+    if (!I.has_bvh) continue;
+    double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
+    double tn = 0.0, tf = static_cast<double>(t_best);
+    bool miss = false;
+    for (int q = 0; q < 3; ++q) {
+      const double lo = I.box_lo[q] + p[q], hi = I.box_hi[q] + p[q];
+      const double dq = r[q] * ray_len;
+      if (dq == 0.0) {
+        if (ca[q] < lo || ca[q] > hi) miss = true;
+        continue;
+      }
+      const double a = (lo - ca[q]) / dq, b = (hi - ca[q]) / dq;
+      tn = fmax(tn, fmin(a, b));
+      tf = fmin(tf, fmax(a, b));
+    }
+    if (miss || tn > tf) continue;
+    const double *R = I.rot;
+    const double q0 = ca[0] - p[0], q1 = ca[1] - p[1], q2 = ca[2] - p[2];
+    const float ox = static_cast<float>(R[0] * q0 + R[3] * q1 + R[6] * q2);
+    const float oy = static_cast<float>(R[1] * q0 + R[4] * q1 + R[7] * q2);
+    const float oz = static_cast<float>(R[2] * q0 + R[5] * q1 + R[8] * q2);
+    const double d0 = r[0] * ray_len, d1 = r[1] * ray_len, d2 = r[2] * ray_len;
+    const float dx = static_cast<float>(R[0] * d0 + R[3] * d1 + R[6] * d2);
+    const float dy = static_cast<float>(R[1] * d0 + R[4] * d1 + R[7] * d2);
+    const float dz = static_cast<float>(R[2] * d0 + R[5] * d1 + R[8] * d2);
+    int32_t id = -1;
+    blas_closest(I.nodes, I.leaf, ox, oy, oz, dx, dy, dz, j == ia ? la : -1, t_min, t_best, id,
+                 stk, stride);
+    if (id >= 0) {
+      id_best = id;
+      inst_best = j;
+    }
+  }
+  if (id_best < 0) return -1;
+  const DevInstance &IB = sc.inst[inst_best];
+  double xb[3][3], cb[3], nb[3];
+  world_vertices(IB, id_best, t, xb);
+  if (!tri_frame(xb, cb, nb)) return -1;
+  const double th = static_cast<double>(t_best) * ray_len;
+  const double h[3] = {ca[0] + th * r[0], ca[1] + th * r[1], ca[2] + th * r[2]};
+  double ei[3];
+  for (int q = 0; q < 3; ++q) ei[q] = E[q] - 2.0 * fe * na[q];
+  const double f1 = nb[0] * (ei[0] - h[0]) + nb[1] * (ei[1] - h[1]) + nb[2] * (ei[2] - h[2]);
+  const double f2 = nb[0] * (O[0] - h[0]) + nb[1] * (O[1] - h[1]) + nb[2] * (O[2] - h[2]);
+  if (!(f1 > 0.0) || !(f2 > 0.0)) return -1;
+  if (segment_blocked(sc, t, h, O, inst_best, id_best, stk, stride)) return -1;
+  // footprint of A's tube on B's plane
+  const double num = nb[0] * (cb[0] - ei[0]) + nb[1] * (cb[1] - ei[1]) + nb[2] * (cb[2] - ei[2]);
+  double fp[3][3], cf[3] = {0.0, 0.0, 0.0};
+  for (int v = 0; v < 3; ++v) {
+    double dv[3] = {xa[v][0] - ei[0], xa[v][1] - ei[1], xa[v][2] - ei[2]};
+    const double den = dot3(nb, dv);
+    const double sv = num / den;
+    if (!(sv > 0.5) || !isfinite(sv)) return -1;
+    for (int q = 0; q < 3; ++q) {
+      fp[v][q] = ei[q] + sv * dv[q];
+      cf[q] += fp[v][q] / 3.0;
+    }
+  }
+  const double lim2 = 2.25 * r_lim * r_lim;
+  for (int v = 0; v < 3; ++v) {
+    const double a = fp[v][0] - cf[0], b = fp[v][1] - cf[1], c = fp[v][2] - cf[2];
+    if (!(a * a + b * b + c * c <= lim2)) return -1;
+  }
+  return static_cast<int32_t>(IB.facet_base + id_best);
+}
+
+}  // namespace
+
+// Connections of every facet at chirps n_begin .. n_begin + n_chirps - 1, both launching
+// ends: pair_b[(k N + n) F + f]. Workgroups as in vis_kernel (lane = chirp).
+__global__ void __launch_bounds__(kVisThreads) dbounce_kernel(DevScene sc, RadarConst rc, int cw,
+                                                            int facets_per_block, int n_begin,
+                                                            int n_end, double ray_len,
+                                                            double r_lim, int32_t *pair_b) {
+  extern __shared__ int32_t db_lds[];
+  int32_t *stk = db_lds + threadIdx.x;  // column per thread
+  const int nl = threadIdx.x % cw;
+  const int n = n_begin + static_cast<int>(blockIdx.y) * cw + nl;
+  const int64_t f0 = static_cast<int64_t>(blockIdx.x) * facets_per_block;
+  for (int fl = threadIdx.x / cw; fl < facets_per_block; fl += blockDim.x / cw) {
+    const int64_t f = f0 + fl;
+    if (f >= sc.n_facets || n >= n_end) continue;
+    for (int k = 0; k < 2; ++k)
+      pair_b[(static_cast<int64_t>(k) * rc.N + n) * sc.n_facets + f] =
+          db_connect(sc, rc, f, n, k, ray_len, r_lim, stk, blockDim.x);
+  }
+}
+
+// Per (end, chirp): the connected facets in ascending order and their count (deterministic).
+__global__ void __launch_bounds__(1024) db_compact_kernel(const int32_t *pair_b, int64_t F,
+                                                          int32_t *idx, int32_t *cnt) {
+  __shared__ int32_t s_scan[1024];
+  const int64_t row = blockIdx.x;  // k N + n
+  const int32_t *b = pair_b + row * F;
+  const int64_t per = (F + blockDim.x - 1) / blockDim.x;
+  const int64_t i0 = static_cast<int64_t>(threadIdx.x) * per;
+  const int64_t i1 = min(F, i0 + per);
+  int32_t c = 0;
+  for (int64_t i = i0; i < i1; ++i) c += b[i] >= 0 && b[i] < F;  // others: no connection
+  s_scan[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
+    int32_t v = (threadIdx.x >= static_cast<unsigned>(off)) ? s_scan[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int32_t pos = s_scan[threadIdx.x] - c;
+  int32_t *out = idx + row * F;
+  for (int64_t i = i0; i < i1; ++i)
+    if (b[i] >= 0 && b[i] < F) out[pos++] = static_cast<int32_t>(i);
+  if (threadIdx.x == blockDim.x - 1) cnt[row] = s_scan[threadIdx.x];
+}
+
+hipError_t launch_dbounce(const DevScene &sc, const RadarConst &rc, double ray_len, double r_lim,
+                          int32_t *pair_b, int32_t *idx, int32_t *cnt, hipStream_t s) {
+  if (rc.N <= 0) return hipSuccess;
+  if (sc.n_facets > 0 && ray_len > 0.0) {
+    int cw = 1;
+    while (cw < rc.N && cw < 64) cw <<= 1;
+    const int fpb = std::max(32, kVisThreads / cw);
+    dim3 grid(static_cast<unsigned>((sc.n_facets + fpb - 1) / fpb),
+              static_cast<unsigned>((rc.N + cw - 1) / cw));
+    const size_t lds = sizeof(int32_t) * static_cast<size_t>(sc.stack_depth) * kVisThreads;
+    hipLaunchKernelGGL(dbounce_kernel, grid, dim3(kVisThreads), lds, s, sc, rc, cw, fpb, 0,
+                       rc.N, ray_len, r_lim, pair_b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(db_compact_kernel, dim3(static_cast<unsigned>(2 * rc.N)), dim3(1024), 0, s,
+                     pair_b, sc.n_facets, idx, cnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_visibility(const DevScene &sc, const RadarConst &rc, int n_begin, int n_chirps,
                              hipStream_t s) {
   if (sc.n_facets == 0 || n_chirps <= 0) return hipSuccess;

@@ -53,11 +53,45 @@ class Simulator:
         self.ctx.set_ground(enable, z_ground, gamma)
         self.mask_types = 4 if enable else 1
 
+    def set_double_bounce(self, enable: bool, gamma: complex = -1.0):
+        """Facet-to-facet double bounce on/off; while on, a scene's part of a mask buffer
+        is followed by its connection table [2][N][F] int32."""
+        self.ctx.set_double_bounce(enable, gamma)
+        self.db = bool(enable)
+
+    def _mask_span(self, i):
+        types = getattr(self, "mask_types", 1)
+        span = types * self.wf.n_chirps * self.mask_words[i]
+        if getattr(self, "db", False):
+            span += 2 * self.wf.n_chirps * self.n_facets[i]
+        return span
+
     def mask_buffer(self, which: Optional[Sequence[int]] = None):
         which = range(len(self.scene_ids)) if which is None else which
-        types = getattr(self, "mask_types", 1)
-        total = sum(types * self.wf.n_chirps * self.mask_words[i] for i in which)
+        total = sum(self._mask_span(i) for i in which)
         return torch.zeros(max(1, total), dtype=torch.int32, device=self.dev)
+
+    def connections_numpy(self, mask_tensor, which: Optional[Sequence[int]] = None):
+        """The connection tables [2, N, F] (facet B or -1) of a mask buffer (double bounce)."""
+        which = list(range(len(self.scene_ids))) if which is None else list(which)
+        raw = mask_tensor.cpu().numpy().view("<i4")
+        out, off = [], 0
+        for i in which:
+            words = getattr(self, "mask_types", 1) * self.wf.n_chirps * self.mask_words[i]
+            n = 2 * self.wf.n_chirps * self.n_facets[i]
+            out.append(raw[off + words:off + words + n].reshape(2, self.wf.n_chirps,
+                                                                self.n_facets[i]).copy())
+            off += self._mask_span(i)
+        return out
+
+    def mask_with_connections(self, masks: Sequence[np.ndarray], tables: Sequence[np.ndarray]):
+        """A device mask buffer from per-scene lit masks [N, F] and connection tables
+        [2, N, F] (double bounce)."""
+        parts = []
+        for m, t in zip(masks, tables):
+            parts.append(pack_mask(m).reshape(-1).view(np.int32))
+            parts.append(np.asarray(t, np.int32).reshape(-1))
+        return torch.from_numpy(np.concatenate(parts).copy()).to(self.dev)
 
     def synthesize(self, which: Optional[Sequence[int]] = None, precision=RSIM_FP32_PHASE64,
                    echo=None, mask=None, mask_mode=RSIM_MASK_COMPUTE, **kw):
@@ -117,7 +151,7 @@ class Simulator:
             cnt = self.wf.n_chirps * self.mask_words[i]
             words = raw[off:off + cnt].reshape(self.wf.n_chirps, self.mask_words[i])
             out.append(unpack_mask(words, self.n_facets[i]))
-            off += cnt
+            off += self._mask_span(i)
         return out
 
     def mask_from_numpy(self, masks: Sequence[np.ndarray]):

@@ -37,7 +37,8 @@ EXPORTS = (
     "rsim_abi_version", "rsim_create", "rsim_destroy", "rsim_last_error", "rsim_set_mem_limit",
     "rsim_load_mesh", "rsim_create_scene", "rsim_add_instance", "rsim_add_points",
     "rsim_scene_info", "rsim_set_waveform", "rsim_set_array", "rsim_synthesize",
-    "rsim_form_rdm", "rsim_last_timings", "rsim_last_census", "rsim_backward", "rsim_rdm_adjoint",
+    "rsim_form_rdm", "rsim_last_timings", "rsim_last_census", "rsim_set_double_bounce",
+    "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
     "rsim_rdm_backward", "rsim_detect", "rsim_add_noise", "rsim_set_ground",
     "rsim_set_backward_kernel", "rsim_set_nufft_chunk", "rsim_form_rdm_noalloc",
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
         "rsim_form_rdm": ([vp, vp, i32, vp, vp, vp, ctypes.POINTER(Opts)], i32),
         "rsim_last_timings": ([vp, ctypes.POINTER(ctypes.c_float), i32], i32),
         "rsim_last_census": ([vp, ctypes.POINTER(ctypes.c_int64)], i32),
+        "rsim_set_double_bounce": ([vp, i32, ctypes.c_double, ctypes.c_double], i32),
         "rsim_backward": ([vp, i32, vp, vp, ctypes.POINTER(vp), i32, vp, vp], i32),
         "rsim_rdm_adjoint": ([vp, vp, i32, vp, vp], i32),
         "rsim_autotune": ([vp, ctypes.POINTER(i32), i32, ctypes.c_char_p], i32),
@@ -278,6 +280,10 @@ class Context:
         g = complex(gamma)
         self._check(self._L.rsim_set_ground(self._h, int(bool(enable)), float(z_ground), g.real,
                                             g.imag))
+
+    def set_double_bounce(self, enable: bool, gamma: complex = -1.0):
+        g = complex(gamma)
+        self._check(self._L.rsim_set_double_bounce(self._h, int(bool(enable)), g.real, g.imag))
 
     def set_backward_kernel(self, kernel: int = RSIM_KERNEL_AUTO):
         self._check(self._L.rsim_set_backward_kernel(self._h, int(kernel)))

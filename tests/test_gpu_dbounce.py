@@ -1,0 +1,153 @@
+"""GPU parity of the facet-to-facet double bounce (Section 2.2: a ray reflected by one facet
+joined with a ray from the other end on a second facet; the connection rules and the
+footprint term of oracle/dbounce.py) through the C ABI, against the FP64 oracle:
+
+* the connection table the library computes (the facet B of every launching end, chirp
+  and facet A) equals the oracle's except where the oracle marks a decision ambiguous;
+* given the oracle's connections and no lit facet (RSIM_MASK_INPUT), the echo is the
+  double bounce alone: against the oracle's at the FP32 bar (1e-4 relative RMS), and the
+  record census counts exactly those connections;
+* the whole echo (single + double bounce, complex gamma) against the oracle's sum;
+* the dihedral closed form (sigma = 8 pi a^2 b^2 / lambda^2) through the GPU path;
+* the refusals.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import dbounce
+from scenes import RadarArray, Waveform
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-4
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def _sim(sc, wf, arr, gamma=-1.0):
+    from paper_2208_10939_amd.pipeline import Simulator
+    sim = Simulator([sc], wf, arr)
+    sim.set_double_bounce(True, gamma)
+    return sim
+
+
+def _cases():
+    small = scenes.small_single(n_samples=64, n_chirps=2, n_tris=1500)
+    fine = scenes.small_single(n_samples=64, n_chirps=2, n_tris=6000)
+    inter = scenes.small_intersection(n_samples=64, n_chirps=2)
+    wf_d = Waveform(f0=77e9, slope=12.5e12, fs=5.12e6, chirp_period=60e-6, n_samples=64,
+                    n_chirps=2)
+    dih = scenes.dihedral_scene(0.3, 0.2, 30.0, 4, 4)
+    return [("vehicle 1.5k", small.scenes[0], small.waveform, small.array, 4, 6),
+            ("vehicle 6k", fine.scenes[0], fine.waveform, fine.array, 4, 4),
+            ("intersection", inter.scenes[0], inter.waveform, inter.array, 3, 4),
+            ("dihedral 30 m", dih, wf_d, small.array, 2, 4)]
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_double_bounce_against_oracle(case):
+    name, sc, wf, arr, P, Q = _cases()[case]
+    arr = RadarArray(tx=np.array(arr.tx[:P]), rx=np.array(arr.rx[:Q]))
+    _log(f"case double bounce: {name}, {sc.n_tris} triangles, {P}x{Q}, M={wf.n_samples}")
+    sim = _sim(sc, wf, arr)
+    F, N = sim.n_facets[0], wf.n_chirps
+    pairs = dbounce.double_bounce_pairs(sc, arr, wf)
+    want = dbounce.connection_table(pairs, F)
+    n_pairs = int((want >= 0).sum())
+    assert n_pairs > 0
+    # 1. the library's connections
+    mask = sim.mask_buffer()
+    sim.synthesize(mask=mask)
+    got = sim.connections_numpy(mask)[0]
+    amb = np.zeros_like(want, bool)
+    for ni, per in enumerate(pairs):
+        for k in (0, 1):
+            amb[k, ni, per[k]["amb_facets"]] = True
+    diff = got != want
+    _log(f"  connections: oracle {n_pairs}, library {int((got >= 0).sum())}, differing "
+         f"{int(diff.sum())} (all on ambiguous decisions: {bool(not (diff & ~amb).any())}, "
+         f"ambiguous {int(amb.sum())})")
+    assert not (diff & ~amb).any()
+    # 2. the double bounce alone on the oracle's connections
+    m_in = sim.mask_with_connections([np.zeros((N, F), bool)], [want])
+    H = sim.synthesize(mask=m_in, mask_mode=1, census=True).cpu().numpy()[0]
+    n_rec = sum(sim.ctx.last_census().values())
+    Ho = dbounce.synthesize_double(sc, wf, arr, pairs=pairs)
+    err = rel_rms(H, Ho)
+    _log(f"  records {n_rec}; double bounce alone rel_rms={err:.3e}")
+    assert n_rec == n_pairs
+    assert err <= FP32_TOL
+
+
+def test_double_bounce_with_single_bounce():
+    """The whole echo: the oracle's lit set and connections, against the oracle's single +
+    double bounce; gamma complex."""
+    cfg = scenes.small_single(n_samples=64, n_chirps=2, n_tris=6000)
+    sc, wf = cfg.scenes[0], cfg.waveform
+    arr = RadarArray(tx=np.array(cfg.array.tx[:4]), rx=np.array(cfg.array.rx[:4]))
+    g = -0.8 + 0.3j
+    _log("case double bounce + single bounce, 6k-triangle vehicle, gamma -0.8+0.3j")
+    sim = _sim(sc, wf, arr, g)
+    om, _ = oracle.visibility(sc, arr, wf)
+    pairs = dbounce.double_bounce_pairs(sc, arr, wf)
+    m_in = sim.mask_with_connections([om], [dbounce.connection_table(pairs, sim.n_facets[0])])
+    H = sim.synthesize(mask=m_in, mask_mode=1).cpu().numpy()[0]
+    Hd = dbounce.synthesize_double(sc, wf, arr, gamma=g, pairs=pairs)
+    Ho = oracle.synthesize(sc, wf, arr, mask=om) + Hd
+    err = rel_rms(H, Ho)
+    _log(f"  rel_rms={err:.3e} (the double bounce is {rel_rms(Ho - Hd, Ho):.2f} of the echo)")
+    assert err <= FP32_TOL
+
+
+def test_dihedral_closed_form_on_gpu():
+    """Far field (1e6 m), monostatic: the GPU's double bounce of a 0.3 x 0.2 m dihedral
+    has the magnitude of the oracle's flat plate of area sqrt(2) a b."""
+    p = scenes.RADAR_POS[None, :].astype(np.float64)
+    arr = RadarArray(tx=p.copy(), rx=p.copy())
+    wf = Waveform(f0=77e9, slope=12.5e12, fs=5.12e6, chirp_period=60e-6, n_samples=32,
+                  n_chirps=1)
+    D = 1e6
+    sc = scenes.dihedral_scene(0.3, 0.2, D, 3, 2)
+    _log("case dihedral closed form, far field")
+    sim = _sim(sc, wf, arr)
+    pairs = dbounce.double_bounce_pairs(sc, arr, wf)
+    m_in = sim.mask_with_connections([np.zeros((1, sim.n_facets[0]), bool)],
+                                     [dbounce.connection_table(pairs, sim.n_facets[0])])
+    H = sim.synthesize(mask=m_in, mask_mode=1).cpu().numpy()[0, 0, 0]
+    # the library finds the same connections (no decision is ambiguous here)
+    mask = sim.mask_buffer()
+    sim.synthesize(mask=mask)
+    assert np.array_equal(sim.connections_numpy(mask)[0],
+                          dbounce.connection_table(pairs, sim.n_facets[0]))
+    Hp = oracle.synthesize(scenes.plate_scene(0.3, np.sqrt(2.0) * 0.2, 1, 1, D), wf, arr)[0, 0]
+    r = np.abs(H) / np.abs(Hp)
+    _log(f"  |H| / |H_plate| in [{r.min():.6f}, {r.max():.6f}]")
+    assert np.allclose(r, 1.0, rtol=1e-4)
+
+
+def test_double_bounce_refusals():
+    from paper_2208_10939_amd.rsim import RsimError
+    cfg = scenes.small_single(n_samples=32, n_chirps=2, n_tris=300)
+    sc, wf = cfg.scenes[0], cfg.waveform
+    arr = RadarArray(tx=np.array(cfg.array.tx[:2]), rx=np.array(cfg.array.rx[:2]))
+    sim = _sim(sc, wf, arr)
+    for kw in ({"kernel": 1}, {"kernel": 2}, {"precision": 1}, {"intra_chirp": True}):
+        with pytest.raises(RsimError) as e:
+            sim.synthesize(**kw)
+        assert e.value.code == -1, kw  # EINVAL
+    with pytest.raises(RsimError) as e:
+        sim.ctx.autotune(sim.scene_ids)
+    assert e.value.code == -4  # ESTATE
+    sim.ctx.set_double_bounce(False)
+    sim.synthesize(kernel=1)  # the direct kernels again
