@@ -11,7 +11,11 @@ ONE JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c3|c2] [--no-cpu]
                   [--no-extras] [--calib-copy MiB] [--kernel auto|vector|matrix|nufft]
-                  [--tile-m T --tile-f F]
+                  [--tile-m T --tile-f F] [--fwd-bwd-only] [--double-bounce-only]
+
+Extras (unless --no-extras): the two other facet-sum kernels on the same frame, forward +
+backward, the same frame with the facet-to-facet double bounce, and batched (persistent +
+graph) against plain calls on the 64-scene workload.
 """
 from __future__ import annotations
 
@@ -82,7 +86,7 @@ PROFILE_TRAFFIC = {"vector": "facet_sum_{w}_traffic.json",
                    "nufft": "facet_sum_nufft_{w}_traffic.json"}
 KERNEL_SOURCES = {"vector": ("echo.hip", "echo_common.h"),
                   "matrix": ("echo_mfma.hip", "echo_common.h"),
-                  "nufft": ("nufft.hip", "echo_common.h", "fft_common.h")}
+                  "nufft": ("nufft_spread.hip", "nufft_common.h")}
 KERNEL_CODES = {"auto": 0, "vector": 1, "matrix": 2, "nufft": 3}
 
 
@@ -406,6 +410,39 @@ def measure_batched(n_scenes=64, reps=2, kernels=("matrix", "nufft")):
     return out
 
 
+def measure_double_bounce(sim, lit_per_step, reps=2):
+    """The same frame with the facet-to-facet double bounce on (NUFFT facet sum): frame
+    time with its stages (the connection search runs in the compaction stage), and the
+    number of connections (census records beyond the lit facets)."""
+    import numpy as np
+    import torch
+    sim.set_double_bounce(True, -1.0)
+    try:
+        echo = sim.echo_buffer(1)
+        mask = sim.mask_buffer()
+        rdm = torch.empty(echo.shape, dtype=torch.float32, device="cuda")
+        sid = sim.scene_ids[0]
+        sim.ctx.synthesize([sid], echo, mask)
+        ts, st = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.ctx.synthesize([sid], echo, mask, timing=True)
+            sim.ctx.form_rdm(echo, rdm, None, n_cubes=1, timing=True)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            st.append(sim.ctx.last_timings())
+        sim.ctx.synthesize([sid], echo, mask, mask_mode=1, census=True)
+        records = sum(sim.ctx.last_census().values())
+        i = int(np.argmin(ts))
+        return {"ms_per_frame": 1e3 * float(np.median(ts)),
+                "stage_ms": {k: round(v, 4) for k, v in st[i].items()},
+                "connections_per_frame": int(records - lit_per_step),
+                "lit_facet_records_per_frame": int(lit_per_step)}
+    finally:
+        sim.set_double_bounce(False)
+
+
 def calib_copy(mib: int):
     """Plain elementwise copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -429,6 +466,8 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB")
     ap.add_argument("--fwd-bwd-only", action="store_true",
                     help="only the forward + backward timing (for kernel traces of the adjoint)")
+    ap.add_argument("--double-bounce-only", action="store_true",
+                    help="only the frame with the facet-to-facet double bounce")
     ap.add_argument("--tile-m", type=int, default=0)
     ap.add_argument("--tile-f", type=int, default=0)
     ap.add_argument("--workload", choices=tuple(WORKLOADS), default="c3",
@@ -491,6 +530,12 @@ def main():
               ("vector" if args.kernel == "auto" else args.kernel))
     if args.fwd_bwd_only:
         print(json.dumps({"facet_sum_kernel": kernel, "fwd_bwd": measure_fwd_bwd(sim)}))
+        return
+    if args.double_bounce_only:
+        step(False)
+        torch.cuda.synchronize()
+        lit0 = int(sim.masks_numpy(mask)[0].sum())
+        print(json.dumps({"double_bounce": measure_double_bounce(sim, lit0)}))
         return
     for _ in range(args.warmup):
         step(False)
@@ -559,6 +604,8 @@ def main():
                 measure_other_kernel(sim, echo, mask, other, evals_per_step, args.workload))
         _log("bench: forward + backward")
         out["fwd_bwd"] = measure_fwd_bwd(sim)
+        _log("bench: the facet-to-facet double bounce on the same frame")
+        out["double_bounce"] = measure_double_bounce(sim, int(lit.sum()))
         _log("bench: batched vs plain (the 64-scene workload)")
         out["batched_vs_plain"] = measure_batched()
     if cpu is not None:

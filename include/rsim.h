@@ -312,11 +312,13 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel);
 
 /* Work buffers of the NUFFT facet sum and its adjoint (RSIM_KERNEL_NUFFT): per chirp the
- * grid cells, sorted positions and records of every possible lit facet (and its
- * sub-triangles) plus O grids of n_g cells. A call runs its chirps in chunks that fit 4 GiB;
+ * grid cells, sorted positions and records of every possible entry (facets, points, and
+ * with the double bounce two connections per facet), the runs and their windows of O x 32
+ * grid cells (forward), or O grids of n_g cells (adjoint). A call runs its chirps in chunks
+ * that fit 48 GiB, half the device memory free at the call and the context's memory limit;
  * max_chirps > 0 caps the chunk further (less device memory, more launches), 0 restores
- * the default. Results do not depend on the chunking beyond FP32 summation order. EINVAL
- * for max_chirps < 0. Takes effect at the next call (a captured graph is re-captured). */
+ * the default. Results do not depend on the chunking (the same bits). EINVAL for
+ * max_chirps < 0. Takes effect at the next call (a captured graph is re-captured). */
 int32_t rsim_set_nufft_chunk(rsim_ctx *ctx, int32_t max_chirps);
 
 /* Gradient of L with respect to the echo given dL/dP of the power RDM P = |Y|^2 and

@@ -146,12 +146,13 @@ def footprints(A_tri: np.ndarray, E_img: np.ndarray, B_c: np.ndarray, B_n: np.nd
     return F, ok, s.min(axis=1)
 
 
-def double_bounce_pairs(scene, array, wf, chirps=None):
+def double_bounce_pairs(scene, array, wf, chirps=None, facets=None):
     """The connections (A, B) launched from both ends, per chirp: a list (one entry per
     chirp) of dicts k -> {"A": [P], "B": [P], "F": [P,3,3], "plane_p": [P,3],
     "plane_n": [P,3], "amb": [P]} over the kept pairs, plus "amb_rejected": the number of
     rejected candidates A whose rejection hung on an ambiguous decision, and "amb_facets":
-    every candidate A (kept or rejected) with an ambiguous decision."""
+    every candidate A (kept or rejected) with an ambiguous decision. facets: launch only
+    from these facets A (a sample; every facet can still be hit)."""
     tx_c = np.asarray(array.tx, np.float64).mean(axis=0)
     rx_c = np.asarray(array.rx, np.float64).mean(axis=0)
     chirps = np.arange(wf.n_chirps) if chirps is None else np.asarray(chirps)
@@ -174,7 +175,12 @@ def double_bounce_pairs(scene, array, wf, chirps=None):
             dE = E - c
             fe = np.einsum("ij,ij->i", nrm, dE)
             near = np.abs(fe) < COS_MARGIN * np.linalg.norm(dE, axis=1)
-            cand = np.nonzero((area > 0) & ((fe > 0) | near))[0]
+            ok_a = (area > 0) & ((fe > 0) | near)
+            if facets is not None:
+                sub = np.zeros_like(ok_a)
+                sub[np.asarray(facets)] = True
+                ok_a &= sub
+            cand = np.nonzero(ok_a)[0]
             keep = np.ones(cand.size, bool)
             amb = np.zeros(cand.size, bool)
             stage(fe[cand] > 0, near[cand])

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "librsim.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "bvh_build.cpp", "vis.hip", "echo.hip", "fft.hip", "adjoint.hip", "detect.hip", "echo_mfma.hip", "adjoint_mfma.hip", "nufft.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "bvh_build.cpp", "vis.hip", "echo.hip", "fft.hip", "adjoint.hip", "detect.hip", "echo_mfma.hip", "adjoint_mfma.hip", "nufft.hip", "nufft_spread.hip", "noalloc.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -490,7 +490,19 @@ EchoShape matrix_shape(const RadarConst &rc) {
 
 // NUFFT facet sum: grid length and work-buffer budget.
 constexpr int kNuMaxGrid = 2048;
-constexpr size_t kNuRecBudget = size_t(16) << 30;  // work buffer: chirps per launch cap
+// NUFFT work buffer cap (chirps per launch): up to 48 GiB, within half the device memory
+// free at the call and within the context's memory limit. A whole frame per launch keeps
+// the per-chirp kernels (sort: one workgroup per chirp) filling the device.
+constexpr size_t kNuRecBudgetMax = size_t(48) << 30;
+
+size_t nufft_budget(const rsim_ctx *ctx, size_t held) {
+  size_t free_b = 0, total_b = 0;
+  size_t b = kNuRecBudgetMax;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) b = std::min(b, (free_b + held) / 2);
+  if (ctx->mem_limit)
+    b = std::min(b, ctx->mem_limit > ctx->mem_used - held ? ctx->mem_limit - (ctx->mem_used - held) : 0);
+  return std::max<size_t>(b, size_t(256) << 20);
+}
 
 int smooth_at_least(int n) {  // smallest 2^a 3^b >= n
   int best = 1 << 30;
@@ -1581,11 +1593,12 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
     const size_t run_b = sizeof(int4) + static_cast<size_t>(O) * kNuSlots * sizeof(float2);
     // work-buffer extents: records (and keys, positions), runs and units per launch
     int64_t ext_rec = 0, ext_run = 0, chunk = 0;
+    const size_t budget = nufft_budget(ctx, ctx->nu_buf_bytes);
     pl.nu_units.clear();
     pl.nu_chunks.clear();
     if (o.persistent) {
       // batched: (scene, chirp) units, the scenes with the most records first, cut into
-      // launches of at most kNuRecBudget bytes and 65535 units
+      // launches of at most the work-buffer budget and 65535 units
       std::vector<int> order(ids.size());
       for (size_t i = 0; i < order.size(); ++i) order[i] = static_cast<int>(i);
       std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -1609,7 +1622,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
           const size_t used = rec * (rec_b + 8) + run * run_b +
                               4 * (static_cast<size_t>(pl.nu_units.size()) - u0);
           if (static_cast<int64_t>(pl.nu_units.size()) > u0 &&
-              (used + unit_b > kNuRecBudget ||
+              (used + unit_b > budget ||
                static_cast<int64_t>(pl.nu_units.size()) - u0 >= 65535))
             close();
           NuUnit un{};
@@ -1632,7 +1645,7 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
       close();
     } else {
       const size_t per_chirp = stride * (rec_b + 8) + max_runs * run_b + 4;
-      chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, kNuRecBudget / per_chirp));
+      chunk = std::max<int64_t>(1, std::min<int64_t>(rcn.N, budget / per_chirp));
       if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
       ext_rec = chunk * stride;
       ext_run = chunk * max_runs;
@@ -1763,7 +1776,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   const size_t rec_b = nufft_record_bytes(false), der_b = nufft_der_bytes();
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t per_chirp = stride * (rec_b + der_b + 8) + 8 + O * ns.ng * 8;
-  int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(N, kNuRecBudget / per_chirp));
+  int64_t chunk = std::max<int64_t>(
+      1, std::min<int64_t>(N, nufft_budget(ctx, ctx->nu_adj_bytes) / per_chirp));
   if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
   const size_t off_srec = 0;
   const size_t off_sder = off_srec + al(chunk * stride * rec_b);

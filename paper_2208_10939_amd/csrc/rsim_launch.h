@@ -140,6 +140,12 @@ hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *
                         const NuShape &ns, const NuBuffers &nb, const void *tw, hipStream_t s,
                         const NuBatch &bt = NuBatch{nullptr, nullptr},
                         const hipEvent_t *ev = nullptr);
+// The spread of launch_nufft (nufft_spread.hip): the runs of ns.n_chirps units into the
+// partial windows part [unit's runs][O][kNuSlots].
+hipError_t launch_nufft_spread(const DevScene &sc, const RadarConst &rc, const NuShape &ns,
+                               const double *elem, const void *srec, const int4 *runs,
+                               const int32_t *n_runs, float2 *part, const NuBatch &bt,
+                               hipStream_t s);
 // Floats per (chirp, lit facet, slot) of the adjoint sums: dL/dc through the element
 // distances (3), sum Re y, dL/dbeta_v (3), pad.
 constexpr int kAdjSlotFloats = 8;

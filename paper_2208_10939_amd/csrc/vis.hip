@@ -122,6 +122,10 @@ __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
                                 const double s[3], int self_inst, int32_t self_local,
                                 int32_t *stack, int stride, bool skip_plane = false) {
   double d[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
+  // reciprocals once per segment (the boxes are padded, so the rounding of a product
+  // instead of a quotient cannot turn a hit box into a miss)
+  const double id[3] = {d[0] != 0.0 ? 1.0 / d[0] : 0.0, d[1] != 0.0 ? 1.0 / d[1] : 0.0,
+                        d[2] != 0.0 ? 1.0 / d[2] : 0.0};
   for (int j = 0; j < sc.n_inst; ++j) {
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
@@ -136,7 +140,7 @@ __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
         if (c[k] < lo || c[k] > hi) miss = true;
         continue;
       }
-      double a = (lo - c[k]) / d[k], b = (hi - c[k]) / d[k];
+      double a = (lo - c[k]) * id[k], b = (hi - c[k]) * id[k];
       tn = fmax(tn, fmin(a, b));
       tf = fmin(tf, fmax(a, b));
     }
@@ -238,6 +242,9 @@ __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], co
                              int32_t *stack, int stride) {
   const double dw[2][3] = {{s1[0] - c[0], s1[1] - c[1], s1[2] - c[2]},
                            {s2[0] - c[0], s2[1] - c[1], s2[2] - c[2]}};
+  double idw[2][3];  // reciprocals once per segment, as in segment_blocked
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k) idw[r][k] = dw[r][k] != 0.0 ? 1.0 / dw[r][k] : 0.0;
   for (int j = 0; j < sc.n_inst; ++j) {
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
@@ -253,7 +260,7 @@ __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], co
           if (c[k] < lo || c[k] > hi) miss = true;
           continue;
         }
-        double a = (lo - c[k]) / dw[r][k], b = (hi - c[k]) / dw[r][k];
+        double a = (lo - c[k]) * idw[r][k], b = (hi - c[k]) * idw[r][k];
         tn = fmax(tn, fmin(a, b));
         tf = fmin(tf, fmax(a, b));
       }
@@ -566,6 +573,9 @@ __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t 
   // first hit over all instances (A excluded), t as a fraction of ray_len
   float t_best = 1.0f;
   int32_t id_best = -1, inst_best = -1;
+  const double ir[3] = {r[0] != 0.0 ? 1.0 / (r[0] * ray_len) : 0.0,
+                        r[1] != 0.0 ? 1.0 / (r[1] * ray_len) : 0.0,
+                        r[2] != 0.0 ? 1.0 / (r[2] * ray_len) : 0.0};
   const float t_min = static_cast<float>(1e-6 / ray_len);
   for (int j = 0; j < sc.n_inst; ++j) {
     const DevInstance &I = sc.inst[j];
@@ -575,12 +585,11 @@ __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t 
     bool miss = false;
     for (int q = 0; q < 3; ++q) {
       const double lo = I.box_lo[q] + p[q], hi = I.box_hi[q] + p[q];
-      const double dq = r[q] * ray_len;
-      if (dq == 0.0) {
+      if (r[q] == 0.0) {
         if (ca[q] < lo || ca[q] > hi) miss = true;
         continue;
       }
-      const double a = (lo - ca[q]) / dq, b = (hi - ca[q]) / dq;
+      const double a = (lo - ca[q]) * ir[q], b = (hi - ca[q]) * ir[q];
       tn = fmax(tn, fmin(a, b));
       tf = fmin(tf, fmax(a, b));
     }

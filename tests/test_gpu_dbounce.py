@@ -151,3 +151,34 @@ def test_double_bounce_refusals():
     assert e.value.code == -4  # ESTATE
     sim.ctx.set_double_bounce(False)
     sim.synthesize(kernel=1)  # the direct kernels again
+
+
+def test_connections_full_size_sampled():
+    """The 50k-triangle vehicle at its full array and waveform (192 channels, 256 x 128),
+    chirps 0 and 127: the library's connection of 400 seeded facets per chirp against the
+    oracle's, launched from those facets over the whole scene (differences only on
+    decisions the oracle marks ambiguous)."""
+    cfg = scenes.c2()
+    sc, wf, arr = cfg.scenes[0], cfg.waveform, cfg.array
+    _log("case double bounce connections, 50k-triangle vehicle, full frame, sampled")
+    sim = _sim(sc, wf, arr)
+    F = sim.n_facets[0]
+    mask = sim.mask_buffer()
+    sim.synthesize(mask=mask)
+    got = sim.connections_numpy(mask)[0]
+    rng = np.random.default_rng(77)
+    sample = np.sort(rng.choice(F, 400, replace=False))
+    total = 0
+    for n in (0, wf.n_chirps - 1):
+        per = dbounce.double_bounce_pairs(sc, arr, wf, chirps=[n], facets=sample)[0]
+        for k in (0, 1):
+            want = np.full(F, -1, np.int32)
+            want[per[k]["A"]] = per[k]["B"]
+            amb = np.zeros(F, bool)
+            amb[per[k]["amb_facets"]] = True
+            diff = (got[k, n, sample] != want[sample]) & ~amb[sample]
+            total += int((want[sample] >= 0).sum())
+            assert not diff.any(), (n, k, sample[diff][:5])
+    _log(f"  {total} connections among the samples match; the whole frame has "
+         f"{int((got >= 0).sum())}")
+    assert total > 0
