@@ -270,9 +270,10 @@ def cpu_baseline(cfg, sample_facets=3000, channels=24, max_workers=16):
             "host_cpus": os.cpu_count()}
 
 
-def measure_fwd_bwd(sim, reps=2):
-    """Forward (echo + RDM) and forward + backward (RDM adjoint + facet-sum adjoint +
-    vertex/velocity gather) for the loss sum (RDM - T)^2 with a fixed target T."""
+def measure_fwd_bwd(sim, kernel, reps=2):
+    """Forward (echo + RDM, the given facet-sum kernel) and forward + backward (RDM adjoint +
+    facet-sum adjoint, the library's default for the scene + vertex/velocity gather) for the
+    loss sum (RDM - T)^2 with a fixed target T."""
     import numpy as np
     import torch
     echo = sim.echo_buffer(1)
@@ -280,7 +281,8 @@ def measure_fwd_bwd(sim, reps=2):
     rdm = torch.empty(echo.shape, dtype=torch.float32, device="cuda")
     y = torch.empty_like(echo)
     sid = sim.scene_ids[0]
-    sim.ctx.synthesize([sid], echo, mask)
+    kc = KERNEL_CODES[kernel]
+    sim.ctx.synthesize([sid], echo, mask, kernel=kc)
     sim.ctx.form_rdm(echo, rdm, y)
     target = (0.5 * rdm).contiguous()
     ge = torch.empty_like(echo)
@@ -294,7 +296,7 @@ def measure_fwd_bwd(sim, reps=2):
     for _ in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sim.ctx.synthesize([sid], echo, mask, timing=True)
+        sim.ctx.synthesize([sid], echo, mask, timing=True, kernel=kc)
         sim.ctx.form_rdm(echo, rdm, y, timing=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -529,7 +531,7 @@ def main():
     kernel = (tuned["kernel"] if tuned else
               ("vector" if args.kernel == "auto" else args.kernel))
     if args.fwd_bwd_only:
-        print(json.dumps({"facet_sum_kernel": kernel, "fwd_bwd": measure_fwd_bwd(sim)}))
+        print(json.dumps({"facet_sum_kernel": kernel, "fwd_bwd": measure_fwd_bwd(sim, kernel)}))
         return
     if args.double_bounce_only:
         step(False)
@@ -603,7 +605,7 @@ def main():
             out["other_kernels"].append(
                 measure_other_kernel(sim, echo, mask, other, evals_per_step, args.workload))
         _log("bench: forward + backward")
-        out["fwd_bwd"] = measure_fwd_bwd(sim)
+        out["fwd_bwd"] = measure_fwd_bwd(sim, kernel)
         _log("bench: the facet-to-facet double bounce on the same frame")
         out["double_bounce"] = measure_double_bounce(sim, int(lit.sum()))
         _log("bench: batched vs plain (the 64-scene workload)")

@@ -187,7 +187,8 @@ int32_t rsim_set_array(rsim_ctx *ctx, const double *tx_xyz, int32_t n_tx,
  * clear; instances lying in the plane (the road surface) do not block those legs.
  * While enabled, rsim_synthesize's vis_mask holds 4 mask sets per scene (path types
  * 0: direct, 1: Tx side reflected, 2: Rx side reflected, 3: both; type-major), the
- * persistent form is refused (EINVAL) and rsim_backward returns ESTATE.
+ * persistent form is refused (EINVAL) and rsim_backward differentiates all four path types
+ * (gamma held fixed).
  * ERANGE if an array element does not lie above the plane. Point scatterers take all
  * four paths. */
 int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double gamma_re,
@@ -285,9 +286,12 @@ int32_t rsim_last_census(rsim_ctx *ctx, int64_t counts[4]);
 /* ---- adjoint ------------------------------------------------------------------------ */
 
 /* Gradient of a real loss L through the echo of one scene (FP32 path), with the
- * lit-facet mask held fixed and chirps recomputed rather than stored.
+ * lit-facet mask held fixed and chirps recomputed rather than stored (stop-and-hop
+ * geometry; with the ground plane on, all four path types; ESTATE while the facet-to-facet
+ * double bounce is on).
  *   grad_echo  DEVICE [O][N][M] complex64: dL/dRe(H) + j dL/dIm(H)
- *   vis_mask   DEVICE mask of that scene from the forward call (N * mask_words)
+ *   vis_mask   DEVICE mask of that scene from the forward call (N * mask_words; four
+ *              sets with the ground plane)
  *   grad_verts host array of n_meshes DEVICE pointers, each [n_verts][3] float32 of
  *              the scene's meshes in mesh-id order (NULL entries skipped); dL/dx_body
  *              summed over the instances of each mesh, ACCUMULATED into the buffers.
@@ -307,8 +311,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
  * channel's grid, then Gaussian-weighted moments gathered per lit facet), rsim_backward then
  * failing with ERANGE where ineligible. EINVAL for another value. All give the same
  * gradients to FP32 rounding, the dropped cross term and the NUFFT's error (relative
- * <= 1e-5); the direct kernels are deterministic, the NUFFT adjoint adds its per-facet
- * sums with atomics (reproducible to FP32 rounding, not bit for bit). */
+ * <= 1e-5); all three are deterministic (a fixed order of operations, no atomics). */
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel);
 
 /* Work buffers of the NUFFT facet sum and its adjoint (RSIM_KERNEL_NUFFT): per chirp the

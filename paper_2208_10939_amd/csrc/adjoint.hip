@@ -16,6 +16,8 @@
 // vertices; a third gathers per-vertex gradients through a vertex -> (triangle,
 // corner) index, rotates them to the body frame and sums t_n-weighted gradients into
 // the velocity gradient. No floating-point atomics: results are deterministic.
+#include <algorithm>
+
 #include "adjoint_common.h"
 
 namespace rsim {
@@ -431,7 +433,19 @@ __global__ void __launch_bounds__(256) facet_grad_kernel(DevScene sc, RadarConst
   }
   float *out = gxw + (static_cast<int64_t>(n) * sc.n_facets + f) * 9;
   for (int v = 0; v < 3; ++v)
-    for (int k = 0; k < 3; ++k) out[3 * v + k] = static_cast<float>(gx[v][k]);
+    for (int k = 0; k < 3; ++k) {
+      const float g = static_cast<float>(gx[v][k]);
+      out[3 * v + k] = sh.accumulate ? out[3 * v + k] + g : g;  // accumulate: further path types
+    }
+}
+
+// out = conj(gamma) in: the echo gradient of a path type whose echo was added times gamma.
+__global__ void scale_conj_kernel(const float2 *in, float2 *out, int64_t n, float gr, float gi) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float2 v = in[i];
+    out[i] = make_float2(gr * v.x + gi * v.y, gr * v.y - gi * v.x);
+  }
 }
 
 __global__ void fill_zero_kernel(float *p, int64_t n) {
@@ -534,13 +548,24 @@ hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double
                           hipStream_t s) {
   AdjShape ash{sh, static_cast<int32_t>(sc.n_facets), 0};
   const int threads = sh.n_compute + kStagingThreads;
-  const hipError_t e = launch_fill_zero(gxw, static_cast<int64_t>(rc.N) * sc.n_facets * 9, s);
+  const hipError_t e =
+      sh.accumulate ? hipSuccess : launch_fill_zero(gxw, static_cast<int64_t>(rc.N) * sc.n_facets * 9, s);
   if (e != hipSuccess || sc.n_facets == 0) return e;
   const unsigned grid = static_cast<unsigned>(rc.N) * sh.m_tiles * sh.o_tiles;
   hipLaunchKernelGGL((adjoint_echo_kernel<kAdjMB, kAdjFT>), dim3(grid), dim3(threads),
                      adjoint_smem_bytes(sh), s, sc, rc, elem, ash,
                      static_cast<const float2 *>(grad_echo), partial);
   return launch_adjoint_finish(sc, rc, sh, partial, gxw, s);
+}
+
+hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, double gi,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(scale_conj_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                     static_cast<const float2 *>(in), static_cast<float2 *>(out), n,
+                     static_cast<float>(gr), static_cast<float>(gi));
+  return hipGetLastError();
 }
 
 hipError_t launch_facet_chirp_sum(const float *gxw, int64_t n_facets, int N, double tc,

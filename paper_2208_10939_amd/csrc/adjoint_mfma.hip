@@ -469,7 +469,8 @@ hipError_t launch_adjoint_mfma(const DevScene &sc, const RadarConst &rc, const d
       sh.m_tiles != (rc.M + kAmTile - 1) / kAmTile)
     return hipErrorInvalidValue;
   AdjShape ash{sh, static_cast<int32_t>(sc.n_facets), 0};
-  const hipError_t e = launch_fill_zero(gxw, static_cast<int64_t>(rc.N) * sc.n_facets * 9, s);
+  const hipError_t e =
+      sh.accumulate ? hipSuccess : launch_fill_zero(gxw, static_cast<int64_t>(rc.N) * sc.n_facets * 9, s);
   if (e != hipSuccess || sc.n_facets == 0) return e;
   const unsigned grid = static_cast<unsigned>(rc.N) * sh.m_tiles;
   const size_t lds = adjoint_mfma_smem_bytes(rc.P, rc.Q, sh.E);

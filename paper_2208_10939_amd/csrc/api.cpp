@@ -142,6 +142,8 @@ struct rsim_ctx {
   bool census_ready = false;                // the last census call ran the NUFFT
   void *nu_buf = nullptr;
   size_t nu_buf_bytes = 0;
+  void *adj_gscaled = nullptr;  // echo gradient times conj(gamma) (ground-bounce adjoint)
+  size_t adj_gscaled_bytes = 0;
   void *nu_adj_buf = nullptr;  // work buffers of the NUFFT adjoint (grow-only)
   size_t nu_adj_bytes = 0;
   int32_t nu_chunk_max = 0;    // chirps per NUFFT chunk at most (0: as many as fit)
@@ -1768,7 +1770,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
 // facet), then the shared chain rule into ctx->adj_gxw. Work buffers per chunk of chirps:
 // records and adjoint records [chunk][facet records] in entry order, grids [chunk][O][n_g].
 static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const RadarConst &rcn,
-                                     NuShape ns, const void *grad_echo, hipStream_t s) {
+                                     const double *elem, NuShape ns, const void *grad_echo,
+                                     bool accumulate, hipStream_t s) {
   DevScene d = d_in;
   d.n_points = 0;  // points carry no parameters
   const int64_t F = d.n_facets, N = rcn.N, O = static_cast<int64_t>(rcn.P) * rcn.Q;
@@ -1809,7 +1812,7 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   for (int64_t n0 = 0; n0 < N; n0 += chunk) {
     ns.n0 = static_cast<int32_t>(n0);
     ns.n_chirps = static_cast<int32_t>(std::min<int64_t>(chunk, N - n0));
-    HIP_TRY(ctx, launch_nufft_adjoint(d, rcn, ctx->d_elem, ns, nb, tw, grad_echo,
+    HIP_TRY(ctx, launch_nufft_adjoint(d, rcn, elem, ns, nb, tw, grad_echo,
                                       ctx->adj_partial, s,
                                       kernel_events(ctx, ctx->timing_pending, kKernelStage0 + 1)));
   }
@@ -1817,7 +1820,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   sh.O = static_cast<int32_t>(O);
   sh.o_tiles = 1;
   sh.m_tiles = 1;
-  HIP_TRY(ctx, launch_fill_zero(ctx->adj_gxw, N * F * 9, s));
+  sh.accumulate = accumulate ? 1 : 0;
+  if (!accumulate) HIP_TRY(ctx, launch_fill_zero(ctx->adj_gxw, N * F * 9, s));
   HIP_TRY(ctx, launch_adjoint_finish(d, rcn, sh, ctx->adj_partial, ctx->adj_gxw, s));
   return RSIM_OK;
 }
@@ -1831,12 +1835,9 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   if ((rc = check_scene(ctx, scene_id))) return rc;
-  if (ctx->ground)
-    return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path; "
-                "disable the ground bounce (rsim_set_ground) first");
   if (ctx->dbounce)
-    return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path; "
-                "disable the double bounce (rsim_set_double_bounce) first");
+    return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path and "
+                "the ground bounce; disable the double bounce (rsim_set_double_bounce) first");
   const RadarConst rcn = radar_const(ctx);
   if (cross_term_bound(ctx, rcn) > 3e-4)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: array aperture too large for the FP32 sum");
@@ -1916,16 +1917,52 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   DevScene d = dev_scene(sc, const_cast<uint32_t *>(vis_mask), nullptr);
   const bool timing = ctx->timing_pending;
-  HIP_TRY(ctx, launch_compact(d, 0, rcn.N, s));
+  // With the ground plane the forward added four path types (their own masks, mirrored
+  // elements and gamma per bounce); the adjoint runs each with the echo gradient times
+  // conj(gamma^bounces) and adds their world-vertex gradients in path-type order.
+  const int types = ctx->ground ? 4 : 1;
+  const int E = rcn.P + rcn.Q;
+  if (ctx->ground) {
+    if ((rc = ensure_elem_images(ctx))) return rc;
+    const size_t cube = static_cast<size_t>(rcn.P) * rcn.Q * rcn.N * rcn.M * 8;
+    if (ctx->adj_gscaled_bytes < cube) {
+      dev_free(ctx, ctx->adj_gscaled);
+      ctx->adj_gscaled = nullptr;
+      ctx->adj_gscaled_bytes = 0;
+      if ((rc = dev_alloc(ctx, &ctx->adj_gscaled, cube))) return rc;
+      ctx->adj_gscaled_bytes = cube;
+    }
+  }
   stage_begin(ctx, timing, 5, s);
-  if (nufft) {
-    if ((rc = enqueue_nufft_adjoint(ctx, d, rcn, nsb, grad_echo, s))) return rc;
-  } else if (matrix)
-    HIP_TRY(ctx, launch_adjoint_mfma(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial,
-                                     ctx->adj_gxw, s));
-  else
-    HIP_TRY(ctx, launch_adjoint(d, rcn, ctx->d_elem, sh, grad_echo, ctx->adj_partial,
-                                ctx->adj_gxw, s));
+  for (int k = 0; k < types; ++k) {
+    DevScene dk = d;
+    dk.mask = d.mask + static_cast<int64_t>(k) * rcn.N * d.mask_words;
+    HIP_TRY(ctx, launch_compact(dk, 0, rcn.N, s));
+    RadarConst rk = rcn;
+    if (k & 1) rk.tx_c[2] = 2.0 * ctx->z_ground - rcn.tx_c[2];
+    if (k >> 1) rk.rx_c[2] = 2.0 * ctx->z_ground - rcn.rx_c[2];
+    const double *elem = k ? ctx->d_elem_img + static_cast<size_t>(k - 1) * 3 * E : ctx->d_elem;
+    const void *gk = grad_echo;
+    if (k) {
+      double gr = 1.0, gi = 0.0;
+      for (int b = 0; b < ((k & 1) + (k >> 1)); ++b) {
+        const double t = gr * ctx->gamma_re - gi * ctx->gamma_im;
+        gi = gr * ctx->gamma_im + gi * ctx->gamma_re;
+        gr = t;
+      }
+      const int64_t n = static_cast<int64_t>(rcn.P) * rcn.Q * rcn.N * rcn.M;
+      HIP_TRY(ctx, launch_scale_conj(grad_echo, ctx->adj_gscaled, n, gr, gi, s));
+      gk = ctx->adj_gscaled;
+    }
+    EchoShape sk = sh;
+    sk.accumulate = k ? 1 : 0;
+    if (nufft) {
+      if ((rc = enqueue_nufft_adjoint(ctx, dk, rk, elem, nsb, gk, k > 0, s))) return rc;
+    } else if (matrix)
+      HIP_TRY(ctx, launch_adjoint_mfma(dk, rk, elem, sk, gk, ctx->adj_partial, ctx->adj_gxw, s));
+    else
+      HIP_TRY(ctx, launch_adjoint(dk, rk, elem, sk, gk, ctx->adj_partial, ctx->adj_gxw, s));
+  }
   stage_end(ctx, timing, 5, s);
   stage_begin(ctx, timing, 7, s);
   double *gsum = ctx->adj_gsum, *gtsum = ctx->adj_gsum + 9 * F;

@@ -913,37 +913,56 @@ __global__ void __launch_bounds__(256) fill_zero_i32_kernel(int32_t *p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-// Moments mu_0 .. mu_{K-1} of a staged grid row about the position xs (cells from the
-// record's cell rc0): the 13 cells from ceil(xs - W/2) (a 13th cell past xs + W/2 carries a
-// weight below 4e-7).
+// Gaussian-weighted moments mu_k = sum_l g(l) psi(l - x) (l - x)^k, k < K, of a grid row
+// over the kNuWidth + 1 cells from the first within W/2 of x = rc0 + xs. The row holds
+// n_g + kNuWidth cells (its first kNuWidth repeated at the end), so no index wraps and the
+// reads are fixed offsets from one base. With l - x = c + j' (c = s0 + W/2 - xs in (-1, 0],
+// j' = j - W/2 in [-W/2, W/2]) the sums T_m = sum g psi j'^m come first, the powers of j'
+// being constants of the unrolled loop, and mu_k = sum_m binom(k, m) c^(k - m) T_m (|c| < 1:
+// no cancellation).
 template <int K>
 __device__ __forceinline__ void row_moments(const float2 *row, int ng, int rc0, float xs,
                                             float nc, float q_ratio, float2 (&mu)[K]) {
+  static_assert(K == 2 || K == 4, "moment counts used");
   const float s0 = ceilf(xs - 0.5f * kNuWidth);
   int cell = (rc0 + static_cast<int>(s0)) % ng;  // rc0 + s0 lies in (-ng, 2 ng)
   cell += (cell < 0) ? ng : 0;
+  const float2 *rp = row + cell;
   const float u0 = s0 - xs;
   float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
   float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+  float2 T[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) mu[k] = {0.0f, 0.0f};
+  for (int k = 0; k < K; ++k) T[k] = {0.0f, 0.0f};
 #pragma unroll
   for (int j = 0; j <= kNuWidth; ++j) {
-    const float2 gv = row[cell];
-    cell = (cell + 1 == ng) ? 0 : cell + 1;
-    const float u = u0 + static_cast<float>(j);
-    const float wr = gw * gv.x, wi = gw * gv.y;
-    mu[0].x += wr;
-    mu[0].y += wi;
-    float up = 1.0f;
+    const float2 v = rp[j];
+    constexpr int h = kNuWidth / 2;
+    T[0].x = fmaf(gw, v.x, T[0].x);
+    T[0].y = fmaf(gw, v.y, T[0].y);
+    if (j != h) {
+      const float jp = static_cast<float>(j - h);
+      float pw = jp;
 #pragma unroll
-    for (int k = 1; k < K; ++k) {
-      up *= u;
-      mu[k].x = fmaf(wr, up, mu[k].x);
-      mu[k].y = fmaf(wi, up, mu[k].y);
+      for (int m = 1; m < K; ++m) {
+        const float gm = gw * pw;
+        T[m].x = fmaf(gm, v.x, T[m].x);
+        T[m].y = fmaf(gm, v.y, T[m].y);
+        pw *= jp;
+      }
     }
     gw *= rho;
     rho *= q_ratio;
+  }
+  const float c = u0 + 0.5f * kNuWidth;
+  mu[0] = T[0];
+  mu[1] = {fmaf(c, T[0].x, T[1].x), fmaf(c, T[0].y, T[1].y)};
+  if constexpr (K == 4) {
+    const float c2 = c * c, c3 = c2 * c;
+    mu[2] = {fmaf(c2, T[0].x, fmaf(2.0f * c, T[1].x, T[2].x)),
+             fmaf(c2, T[0].y, fmaf(2.0f * c, T[1].y, T[2].y))};
+    mu[3] = {fmaf(c3, T[0].x, fmaf(3.0f * c2, T[1].x, fmaf(3.0f * c, T[2].x, T[3].x))),
+             fmaf(c3, T[0].y, fmaf(3.0f * c2, T[1].y, fmaf(3.0f * c, T[2].y, T[3].y)))};
   }
 }
 
@@ -965,7 +984,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     const NuRecF<false> *__restrict__ recs, const NuDerF *__restrict__ ders,
     const int32_t *__restrict__ lists, const int32_t *__restrict__ counts,
     const float2 *__restrict__ grids, float *partial, int blocks_per_chirp) {
-  extern __shared__ float2 nu_row[];  // [n_g]
+  extern __shared__ float2 nu_row[];  // [n_g + kNuWidth]: the row and its first cells again
   const int per_xcd = (gridDim.x + kXcds - 1) / kXcds;  // gridDim.x is a multiple of kXcds
   const int logical = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
   const int nl = logical / blocks_per_chirp;
@@ -1020,7 +1039,8 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
   const float2 *grow = grids + static_cast<int64_t>(nl) * O * ng;
   for (int o = 0; o < O; ++o) {
     __syncthreads();  // the previous channel's row is no longer read
-    for (int l = threadIdx.x; l < ng; l += blockDim.x) nu_row[l] = grow[static_cast<int64_t>(o) * ng + l];
+    for (int l = threadIdx.x; l < ng + kNuWidth; l += blockDim.x)
+      nu_row[l] = grow[static_cast<int64_t>(o) * ng + (l < ng ? l : l - ng)];
     __syncthreads();
     // this channel's element offsets from the phase centres (wave-uniform)
     const int p = o / rc.Q, q = o - p * rc.Q;
@@ -1222,11 +1242,11 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
   const auto *ders = static_cast<const NuDerF *>(nb.sder);
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<0>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem, recs, ders,
+                     dim3(kNuGatherRecs), sizeof(float2) * (ns.ng + kNuWidth), s, sc, rc, ns, elem, recs, ders,
                      nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<1>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * ns.ng, s, sc, rc, ns, elem, recs, ders,
+                     dim3(kNuGatherRecs), sizeof(float2) * (ns.ng + kNuWidth), s, sc, rc, ns, elem, recs, ders,
                      nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;

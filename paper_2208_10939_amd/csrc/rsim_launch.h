@@ -150,7 +150,8 @@ hipError_t launch_nufft_spread(const DevScene &sc, const RadarConst &rc, const N
 // distances (3), sum Re y, dL/dbeta_v (3), pad.
 constexpr int kAdjSlotFloats = 8;
 // Per-(chirp, lit facet, slot) sums -> world-vertex gradients (FP64 chain rule) into gxw
-// (zero on entry), slots = sh.m_tiles * sh.o_tiles.
+// (zero on entry; added to it with sh.accumulate), slots = sh.m_tiles * sh.o_tiles. The
+// adjoint launchers below clear gxw first unless sh.accumulate.
 hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
                                  const float *partial, float *gxw, hipStream_t s);
 // Adjoint of launch_nufft for one chunk of chirps (stop-and-hop, facets only: sc.n_points
@@ -206,6 +207,9 @@ hipError_t launch_adjoint_mfma(const DevScene &sc, const RadarConst &rc, const d
 hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
                           hipStream_t s);
+// out[i] = conj(gamma) in[i] (complex64): the echo gradient of a path type added times gamma
+hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, double gi,
+                             hipStream_t s);
 // world-vertex gradients [N][F][9] -> per-facet sums over chirps, plain and t_n-weighted
 hipError_t launch_facet_chirp_sum(const float *gxw, int64_t n_facets, int N, double tc,
                                   double *gsum, double *gtsum, hipStream_t s);

@@ -52,6 +52,70 @@ def _with(sc, mesh_k=None, vert=None, axis=None, dv=0.0, inst_k=None, vaxis=None
 
 
 @pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_adjoint_ground_bounce_matches_finite_differences(kernel):
+    """With the ground plane (gamma -0.7 + 0.2j): the backward differentiates all four path
+    types (their masks from the oracle, held fixed) against central differences of the
+    oracle's loss over the image-method echo (oracle/bounce.py)."""
+    import torch
+    from oracle import bounce
+    from paper_2208_10939_amd.pipeline import Simulator, pack_mask
+    g = -0.7 + 0.2j
+    _log(f"case adjoint with the ground bounce vs FD, kernel={kernel}")
+    wf, arr, sc, target = _setup()
+    masks, amb = bounce.visibility_bounce(sc, arr, wf, 0.0)
+    T, _ = oracle.rdm_from_echo(bounce.synthesize_bounce(target, wf, arr, 0.0, g))
+
+    def loss(scene):
+        P, _ = oracle.rdm_from_echo(bounce.synthesize_bounce(scene, wf, arr, 0.0, g, masks=masks))
+        return oracle.rdm_loss(P, T)
+
+    sim = Simulator([sc], wf, arr)
+    sim.set_ground(True, 0.0, g)
+    packed = np.concatenate([pack_mask(masks[k]).reshape(-1) for k in range(4)])
+    m_t = torch.from_numpy(packed.view(np.int32).copy()).cuda()
+    echo = sim.synthesize(mask=m_t, mask_mode=1)
+    rdm, y = sim.form_rdm(echo, want_y=True)
+    Tt = torch.from_numpy(T.astype(np.float32)).cuda()[None]
+    grad_echo = torch.empty_like(echo)
+    sim.ctx.rdm_backward((2.0 * (rdm - Tt)).contiguous(), y, grad_echo)
+    gverts = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+              for m in sc.meshes]
+    gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+    sim.ctx.set_backward_kernel(kernel)
+    sim.ctx.backward(sim.scene_ids[0], grad_echo, m_t, gverts, gvel)
+    gverts = [g_.cpu().numpy().astype(np.float64) for g_ in gverts]
+    gvel = gvel.cpu().numpy()
+    rng = np.random.default_rng(12)
+    tri, inst_of, local_of = oracle.world_triangles(sc, 0.0)
+    lit_f = np.nonzero(masks[:, 0].any(axis=0))[0]
+    picks = []
+    for f in rng.choice(lit_f, size=6, replace=False):
+        k = inst_of[f]
+        picks.append((sc.instances[k].mesh,
+                      int(sc.meshes[sc.instances[k].mesh].tris[local_of[f], rng.integers(0, 3)])))
+    h = 1e-5
+    fd, ad = [], []
+    for (mk, v) in picks:
+        for ax in range(3):
+            fd.append((loss(_with(sc, mk, v, ax, +h)) - loss(_with(sc, mk, v, ax, -h))) / (2 * h))
+            ad.append(gverts[mk][v, ax])
+    hv = 1e-2
+    for ik in range(len(sc.instances)):
+        for ax in range(2):
+            fd.append((loss(_with(sc, inst_k=ik, vaxis=ax, dvel=+hv)) -
+                       loss(_with(sc, inst_k=ik, vaxis=ax, dvel=-hv))) / (2 * hv))
+            ad.append(gvel[ik, ax])
+    fd, ad = np.array(fd), np.array(ad)
+    rel_l2 = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    big = np.abs(fd) > 1e-3 * np.abs(fd).max()
+    rel_c = np.abs(ad - fd)[big] / np.abs(fd)[big]
+    _log(f"  lit per type {[int(masks[k].sum()) for k in range(4)]} rel_l2={rel_l2:.3e} "
+         f"max_rel_component={rel_c.max():.3e} (n={fd.size}, ambiguous={int(amb.sum())})")
+    assert rel_l2 <= 1e-3
+    assert rel_c.max() <= 1e-2
+
+
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 def test_adjoint_matches_finite_differences(kernel):
     """kernel 1: the vector-unit adjoint; 2: the matrix-core adjoint; 3: the NUFFT adjoint
     (type-2 gather of Gaussian moments; Taylor-coefficient derivatives by FP64 central
