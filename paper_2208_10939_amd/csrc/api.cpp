@@ -1768,7 +1768,8 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
 
 // NUFFT adjoint of one scene's facet sum into ctx->adj_partial (one slot per chirp and lit
 // facet), then the shared chain rule into ctx->adj_gxw. Work buffers per chunk of chirps:
-// records and adjoint records [chunk][facet records] in entry order, grids [chunk][O][n_g].
+// records and adjoint records [chunk][facet records] in entry order, the two class lists,
+// their cells and the lists ordered by cell [chunk][2][facet records], grids [chunk][O][n_g].
 static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const RadarConst &rcn,
                                      const double *elem, NuShape ns, const void *grad_echo,
                                      bool accumulate, hipStream_t s) {
@@ -1778,14 +1779,16 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   const int64_t stride = std::max<int64_t>(1, F);
   const size_t rec_b = nufft_record_bytes(false), der_b = nufft_der_bytes();
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per_chirp = stride * (rec_b + der_b + 8) + 8 + O * ns.ng * 8;
+  const size_t per_chirp = stride * (rec_b + der_b + 24) + 8 + O * ns.ng * 8;
   int64_t chunk = std::max<int64_t>(
       1, std::min<int64_t>(N, nufft_budget(ctx, ctx->nu_adj_bytes) / per_chirp));
   if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
   const size_t off_srec = 0;
   const size_t off_sder = off_srec + al(chunk * stride * rec_b);
   const size_t off_lists = off_sder + al(chunk * stride * der_b);
-  const size_t off_counts = off_lists + al(chunk * 2 * stride * 4);
+  const size_t off_cells = off_lists + al(chunk * 2 * stride * 4);
+  const size_t off_order = off_cells + al(chunk * 2 * stride * 4);
+  const size_t off_counts = off_order + al(chunk * 2 * stride * 4);
   const size_t off_grid = off_counts + al(chunk * 2 * 4);
   const size_t total = off_grid + chunk * O * ns.ng * 8;
   int32_t rc = RSIM_OK;
@@ -1800,6 +1803,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   char *b = static_cast<char *>(ctx->nu_adj_buf);
   NuBuffers nb{};
   nb.key = reinterpret_cast<int32_t *>(b + off_lists);
+  nb.pos = reinterpret_cast<int32_t *>(b + off_cells);
+  nb.order = reinterpret_cast<int32_t *>(b + off_order);
   nb.srec = b + off_srec;
   nb.grid = reinterpret_cast<float2 *>(b + off_grid);
   nb.rec_bytes = rec_b;

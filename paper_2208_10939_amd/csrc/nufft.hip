@@ -797,8 +797,8 @@ size_t nufft_der_bytes() { return sizeof(NuDerF); }
 // (step kNuDerStep; every form is analytic in the node offsets: truncation
 // ~ (k_c h)^2 / 6 ~ 5e-7, rounding ~ 1e-10 relative), both in entry order; the facet's
 // entry is appended to its chirp's list of three-point records (class 0) or of the others
-// (class 1), so that a gather wave meets one kind of record. A zero-area facet gets a zero
-// slot here and no list entry.
+// (class 1), so that a gather wave meets one kind of record, with the record's cell beside
+// it (nb.pos). A zero-area facet gets a zero slot here and no list entry.
 __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarConst rc,
                                                             NuShape ns, NuBuffers nb,
                                                             float *partial) {
@@ -807,7 +807,7 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
   const bool live = item < cnt;
-  int kind = 0;
+  int kind = 0, cell = 0;
   if (live) {
     Geo g;
     entry_geometry(sc, rc, n, cnt, item, g);
@@ -822,6 +822,7 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
     out.ext[0] = out.ext[1] = 0.0f;
     double Rt, Rr, dxc;
     path_fields(g, rc, ns, 0.0, out, &Rt, &Rr, &dxc);
+    cell = out.cell;
     NuDerF der;
     der.item = item;
     der.pad = 0;
@@ -856,10 +857,49 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
     int32_t base = 0;
     if (lane == leader) base = atomicAdd(&nb.n_runs[2 * nl + c], __popcll(m));
     base = __shfl(base, leader);
-    if (mine)
-      nb.key[(static_cast<int64_t>(2 * nl + c)) * ns.rec_stride + base +
-             __popcll(m & ((uint64_t(1) << lane) - 1))] = item;
+    if (mine) {
+      const int64_t at = static_cast<int64_t>(2 * nl + c) * ns.rec_stride + base +
+                         __popcll(m & ((uint64_t(1) << lane) - 1));
+      nb.key[at] = item;
+      nb.pos[at] = cell;
+    }
   }
+}
+
+// Per (chirp, class): the class list reordered by the records' cells (a counting sort; the
+// order within a cell is whatever the LDS atomics give, which no result depends on: every
+// record's sums stay in its own lane), so that the lanes of a gather wave read neighbouring
+// cells of the staged row instead of all of its banks.
+__global__ void __launch_bounds__(kNuSortThreads) nufft_adj_sort_kernel(NuShape ns,
+                                                                       NuBuffers nb) {
+  extern __shared__ int32_t sort_smem[];
+  const int ng = ns.ng;
+  int32_t *cnt = sort_smem;        // [ng]
+  int32_t *part = sort_smem + ng;  // [kNuSortThreads]
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * ns.rec_stride;  // blockIdx = 2 nl + c
+  const int32_t count = nb.n_runs[blockIdx.x];
+  const int32_t *items = nb.key + lo, *cells = nb.pos + lo;
+  const int tid = static_cast<int>(threadIdx.x);
+  for (int i = tid; i < ng; i += kNuSortThreads) cnt[i] = 0;
+  __syncthreads();
+  for (int32_t e = tid; e < count; e += kNuSortThreads) atomicAdd(&cnt[cells[e]], 1);
+  __syncthreads();
+  const int c0 = 2 * tid;
+  const int32_t t0 = c0 < ng ? cnt[c0] : 0, t1 = c0 + 1 < ng ? cnt[c0 + 1] : 0;
+  part[tid] = t0 + t1;
+  __syncthreads();
+  for (int off = 1; off < kNuSortThreads; off <<= 1) {
+    const int32_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  const int32_t base0 = part[tid] - t0 - t1;
+  if (c0 < ng) cnt[c0] = base0;
+  if (c0 + 1 < ng) cnt[c0 + 1] = base0 + t0;
+  __syncthreads();
+  for (int32_t e = tid; e < count; e += kNuSortThreads)
+    nb.order[lo + atomicAdd(&cnt[cells[e]], 1)] = items[e];
 }
 
 // Per (chirp, group of cb channels): the transpose of nufft_fft_kernel. conj(G) of the kept
@@ -971,7 +1011,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // One lane per (chirp, record of one class), a workgroup per (chirp, class, kNuGatherRecs
-// list entries), looping over the channels: each channel's grid row of the chirp is staged
+// entries of the list ordered by cell), looping over the channels: each channel's grid row of the chirp is staged
 // in LDS and every lane forms the moments at its own sources, then adds this channel's
 // share of the per-facet sums in registers: Re y, dL/dc through the channel's distances,
 // and per source parameter sum_o Q mu (weights, coefficients) and sum_o dy/dx_s (offsets).
@@ -1221,8 +1261,8 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
                                 const void *grad_echo, float *partial, hipStream_t s,
                                 const hipEvent_t *ev) {
   if (ns.n_chirps <= 0) return hipSuccess;
-  if (sizeof(NuRecF<false>) > nb.rec_bytes || !nb.sder || !nb.key || !nb.n_runs ||
-      sc.n_points != 0 || rc.intra)
+  if (sizeof(NuRecF<false>) > nb.rec_bytes || !nb.sder || !nb.key || !nb.pos || !nb.order ||
+      !nb.n_runs || sc.n_points != 0 || rc.intra || ns.ng > 2 * kNuSortThreads)
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(nufft_adj_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
                      dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
@@ -1236,6 +1276,9 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
   dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
   hipLaunchKernelGGL(nufft_adj_prep_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb, partial);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(nufft_adj_sort_kernel, dim3(static_cast<unsigned>(2 * ns.n_chirps)),
+                     dim3(kNuSortThreads), sizeof(int32_t) * (ns.ng + kNuSortThreads), s, ns, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int bpc = static_cast<int>((items + kNuGatherRecs - 1) / kNuGatherRecs);
   const int64_t blocks = (static_cast<int64_t>(ns.n_chirps) * bpc + kXcds - 1) / kXcds * kXcds;
   const auto *recs = static_cast<const NuRecF<false> *>(nb.srec);
@@ -1243,11 +1286,11 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<0>), dim3(static_cast<unsigned>(blocks)),
                      dim3(kNuGatherRecs), sizeof(float2) * (ns.ng + kNuWidth), s, sc, rc, ns, elem, recs, ders,
-                     nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
+                     nb.order, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<1>), dim3(static_cast<unsigned>(blocks)),
                      dim3(kNuGatherRecs), sizeof(float2) * (ns.ng + kNuWidth), s, sc, rc, ns, elem, recs, ders,
-                     nb.key, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
+                     nb.order, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   return hipSuccess;

@@ -108,6 +108,7 @@ struct NuBuffers {
   // forward, optional: record counts by source form, kNuCensusSlots rows of 4 (summed by
   // the host); nullptr: no census
   unsigned long long *census;
+  int32_t *order;  // adjoint: the class lists ordered by cell [chirp][2][rec_stride]
 };
 constexpr int kNuCensusSlots = 64;
 // One (scene, chirp) unit of a batched NUFFT launch: the scene's index in the launch's
