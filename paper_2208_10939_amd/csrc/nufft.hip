@@ -76,6 +76,7 @@ constexpr int kNuMaxOrder = 4;  // Hermite table rows (three Taylor terms are us
 constexpr int kNuSortThreads = 1024;  // 16 waves: each ranks one sixteenth of a chirp's entries
 constexpr int kNuSortWaves = kNuSortThreads / 64;
 constexpr int kNuGatherRecs = 256;  // records (lanes) per adjoint gather workgroup
+constexpr int kNuRedBatch = 8;      // run windows read together by a cell sum of the FFT kernel
 constexpr int kXcds = 8;            // accelerator complex dies: workgroups go round-robin
 constexpr double kNuGapMin = 2.0;   // radians of k_c beta between nodes of a divided difference
 
@@ -287,10 +288,12 @@ __device__ void nufft_fill(const Geo &g, const double beta[3], const NuShape &ns
     return;
   }
   if (kind == 2) {
-    // the close pair (p0, p1) and the far node p2
-    const int p2 = far;
-    const int p0 = p2 == 0 ? 1 : 0, p1 = p2 == 2 ? 1 : 2;
-    const double B0 = b[p0], B1 = b[p1], B2 = b[p2];
+    // the close pair (p0, p1) = the two nodes other than the far node p2, in index order
+    // (picked by selects: an index known only at run time would move the geometry to
+    // scratch memory)
+    const double B0 = far == 0 ? b[1] : b[0];
+    const double B1 = far == 2 ? b[1] : b[2];
+    const double B2 = far == 0 ? b[0] : far == 1 ? b[1] : b[2];
     const double d21 = B2 - B1, d20 = B2 - B0;
     const double2 wA = rot_turns(cr / (d21 * d20), ci / (d21 * d20), tpm * B2);
     s[0] = kappa * B2;
@@ -477,6 +480,12 @@ __device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int
   g.pad = 0;
 }
 
+// u minus twice its component along the unit normal nrm (a mirror image of the direction)
+__device__ __forceinline__ void mirror_dir(double (&u)[3], const double nrm[3]) {
+  const double un = u[0] * nrm[0] + u[1] * nrm[1] + u[2] * nrm[2];
+  for (int q = 0; q < 3; ++q) u[q] -= 2.0 * un * nrm[q];
+}
+
 template <bool INTRA>
 __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc0, RadarConst rc, NuShape ns,
                                                         NuBuffers nb, NuBatch bt) {
@@ -516,12 +525,10 @@ __global__ void __launch_bounds__(256) nufft_prep_kernel(DevScene sc0, RadarCons
   out.kind = nufft_sources(g, ns, out.s);
   double Rt, Rr, dxc;
   path_fields(g, rc_e, ns, 0.0, out, &Rt, &Rr, &dxc);
-  if (side >= 0) {
-    // the launching end's channel offsets act through its mirrored direction
-    double *u = side == 0 ? out.ut : out.ur;
-    const double un = u[0] * refl[0] + u[1] * refl[1] + u[2] * refl[2];
-    for (int q = 0; q < 3; ++q) u[q] -= 2.0 * un * refl[q];
-  }
+  // the launching end's channel offsets act through its mirrored direction (each side
+  // named by a constant: a pointer chosen at run time would move the record to scratch)
+  if (side == 0) mirror_dir(out.ut, refl);
+  if (side == 1) mirror_dir(out.ur, refl);
   if constexpr (INTRA) {
     double vut = 0.0, vur = 0.0;
     for (int k = 0; k < 3; ++k) {
@@ -725,10 +732,23 @@ __global__ void __launch_bounds__(kNuFftThreads) nufft_fft_kernel(DevScene sc0, 
 #pragma unroll
         for (int im = 0; im < 3; ++im) {
           const int P = l + (im - 1) * ng;
-          for (int r = lo[im]; r < hi[im]; ++r) {
-            const float2 p = part[(static_cast<int64_t>(r) * O + o) * kNuSlots + (P - bases[r])];
-            v.x += p.x;
-            v.y += p.y;
+          // kNuRedBatch windows' loads in flight together, then added in run order (the
+          // loads are independent; only the sum is ordered)
+          for (int r0 = lo[im]; r0 < hi[im]; r0 += kNuRedBatch) {
+            float2 p[kNuRedBatch];
+#pragma unroll
+            for (int k = 0; k < kNuRedBatch; ++k) {
+              const int r = r0 + k;
+              if (r < hi[im])
+                p[k] = part[(static_cast<int64_t>(r) * O + o) * kNuSlots + (P - bases[r])];
+            }
+#pragma unroll
+            for (int k = 0; k < kNuRedBatch; ++k) {
+              if (r0 + k < hi[im]) {
+                v.x += p[k].x;
+                v.y += p[k].y;
+              }
+            }
           }
         }
       }
@@ -823,9 +843,13 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
     double Rt, Rr, dxc;
     path_fields(g, rc, ns, 0.0, out, &Rt, &Rr, &dxc);
     cell = out.cell;
-    NuDerF der;
-    der.item = item;
-    der.pad = 0;
+    const int64_t at = static_cast<int64_t>(nl) * ns.rec_stride + item;  // entry order
+    static_cast<NuRecF<false> *>(nb.srec)[at] = out;
+    // derivatives stored row by row (a local record indexed by the loop's v would sit in
+    // scratch)
+    NuDerF *der = static_cast<NuDerF *>(nb.sder) + at;
+    der->item = item;
+    der->pad = 0;
     const double h2 = 0.5 / kNuDerStep;
     for (int v = 0; v < 3; ++v) {
       double bp[3] = {g.beta[0], g.beta[1], g.beta[2]}, bm[3] = {g.beta[0], g.beta[1], g.beta[2]};
@@ -835,11 +859,8 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
       nufft_fill(g, bp, ns, kind, far, sp);
       nufft_fill(g, bm, ns, kind, far, sm);
 #pragma unroll
-      for (int k = 0; k < 10; ++k) der.ds[v][k] = static_cast<float>((sp[k] - sm[k]) * h2);
+      for (int k = 0; k < 10; ++k) der->ds[v][k] = static_cast<float>((sp[k] - sm[k]) * h2);
     }
-    const int64_t at = static_cast<int64_t>(nl) * ns.rec_stride + item;  // entry order
-    static_cast<NuRecF<false> *>(nb.srec)[at] = out;
-    static_cast<NuDerF *>(nb.sder)[at] = der;
     if (kind == 0) {
       float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + item) * kAdjVals;
 #pragma unroll
