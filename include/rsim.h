@@ -287,8 +287,9 @@ int32_t rsim_last_census(rsim_ctx *ctx, int64_t counts[4]);
 
 /* Gradient of a real loss L through the echo of one scene (FP32 path), with the
  * lit-facet mask held fixed and chirps recomputed rather than stored (stop-and-hop
- * geometry; with the ground plane on, all four path types; ESTATE while the facet-to-facet
- * double bounce is on).
+ * geometry, or the delay within the chirp after rsim_set_backward_intra_chirp(ctx, 1);
+ * with the ground plane on, all four path types; ESTATE while the facet-to-facet double
+ * bounce is on).
  *   grad_echo  DEVICE [O][N][M] complex64: dL/dRe(H) + j dL/dIm(H)
  *   vis_mask   DEVICE mask of that scene from the forward call (N * mask_words; four
  *              sets with the ground plane)
@@ -313,6 +314,19 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
  * gradients to FP32 rounding, the dropped cross term and the NUFFT's error (relative
  * <= 1e-5); all three are deterministic (a fixed order of operations, no atomics). */
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel);
+
+/* Which forward rsim_backward differentiates (Section 3.2, eq. (12) at the sample times):
+ * enable = 0 (default) the stop-and-hop echo; 1 the echo synthesized with
+ * rsim_opts.intra_chirp = 1 (each facet's delay taken at t_n + m / fs, its centroid moving
+ * with its velocity within the chirp; amplitude, facet integral and lit set at t_n). The
+ * velocity gradient then gains the sum over samples of (m / fs) times the phase's
+ * derivative in the centroid. That adjoint runs on the vector units: with enable = 1,
+ * RSIM_KERNEL_AUTO takes them and rsim_backward fails with EINVAL for a backward kernel of
+ * RSIM_KERNEL_MATRIX or RSIM_KERNEL_NUFFT. The phase's derivatives take the delays and unit
+ * vectors at t_n (they move by v m / fs within a chirp: relative changes near 1e-6).
+ * EINVAL for enable not 0/1. Device memory while enabled: 16 N F slots + 12 N F bytes
+ * (slots = sample tiles x channel tiles of the vector-unit adjoint). */
+int32_t rsim_set_backward_intra_chirp(rsim_ctx *ctx, int32_t enable);
 
 /* Work buffers of the NUFFT facet sum and its adjoint (RSIM_KERNEL_NUFFT): per chirp the
  * grid cells, sorted positions and records of every possible entry (facets, points, and

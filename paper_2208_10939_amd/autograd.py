@@ -11,7 +11,8 @@ from .pipeline import Simulator
 class RadarRDM(torch.autograd.Function):
     """rdm = RadarRDM.apply(sim, scene_index, vel, *verts)
 
-    sim         Simulator holding the scene
+    sim         Simulator holding the scene (sim.intra_chirp: the delay within the chirp in
+                the forward and the backward; Simulator.set_intra_chirp)
     scene_index index into sim.scene_ids
     vel         [n_instances, 3] float64 tensor: instance velocities (world frame)
     verts       one [n_verts, 3] float32 tensor per mesh of the scene, body frame
@@ -37,7 +38,7 @@ class RadarRDM(torch.autograd.Function):
         RadarRDM._load_geometry(sim, scene_index, verts_np, vel_np)
         pos0 = sim.inst_pos0[scene_index]
         mask = sim.mask_buffer([scene_index])
-        echo = sim.synthesize([scene_index], mask=mask)
+        echo = sim.synthesize([scene_index], mask=mask, intra_chirp=sim.intra_chirp)
         rdm, y = sim.form_rdm(echo, want_y=True)
         ctx.sim = sim
         ctx.scene_index = scene_index
@@ -46,6 +47,7 @@ class RadarRDM(torch.autograd.Function):
         ctx.vert_devices = [v.device for v in verts]
         ctx.vel_device = vel.device
         ctx.n_inst = len(pos0)
+        ctx.intra_chirp = sim.intra_chirp
         # the backward recomputes the chirps from the library's scene, which a later
         # forward on the same simulator may have replaced: keep this call's geometry
         ctx.verts_np = verts_np
@@ -70,6 +72,7 @@ class RadarRDM(torch.autograd.Function):
             grads.append(t)
         grad_vel = torch.zeros((ctx.n_inst, 3), dtype=torch.float64, device=dev)
         RadarRDM._load_geometry(sim, ctx.scene_index, ctx.verts_np, ctx.vel_np)
+        sim.ctx.set_backward_intra_chirp(ctx.intra_chirp)
         sim.ctx.backward(sim.scene_ids[ctx.scene_index], grad_echo, mask, per_id, grad_vel)
         grads = [g.to(d) for g, d in zip(grads, ctx.vert_devices)]
         return (None, None, grad_vel.to(ctx.vel_device), *grads)

@@ -16,6 +16,15 @@
 // vertices; a third gathers per-vertex gradients through a vertex -> (triangle,
 // corner) index, rotates them to the body frame and sums t_n-weighted gradients into
 // the velocity gradient. No floating-point atomics: results are deterministic.
+//
+// With the delay taken at the sample times (eq. (12) at t_n + m / fs; amplitude, facet
+// integral and lit set at t_n), the forward's element phasors run along the chord of
+// each block of MB samples and the phase-centre path's curvature rides in G; the adjoint
+// stages the same. The centroid then moves with the facet's velocity within the chirp,
+// so the velocity gradient gains sum_m (m / fs) dL/dc|_phase(m): per channel
+//   -(2 pi / c) / fs * sum_m m (f_0 - slope tau + m df) Im y_m * (e_p + e_q)
+// (e the unit vectors centroid -> element); its phase derivative takes the delay and the
+// unit vectors at t_n (they move by v m / fs, a relative change below 1e-6 here).
 #include <algorithm>
 
 #include "adjoint_common.h"
@@ -30,11 +39,15 @@ namespace {
 template <int MB, int FT>
 struct AdjLayout {
   size_t elem, geo, glin, red, buf[2], GD, U, rat, off, er, tau, total;
-  int waves;  // accumulating waves
+  int waves;      // accumulating waves
+  int rat_b;      // element ratios per element: one, or one per block (delay within the chirp)
+  int red_vals;   // per-wave sums per facet: kAdjVals, or kAdjRedIntra with the chirp delay
 
-  __host__ __device__ explicit AdjLayout(const EchoShape &sh) {
+  __host__ __device__ AdjLayout(const EchoShape &sh, bool intra) {
     auto up = [](size_t b) { return (b + 15) & ~size_t(15); };
     waves = sh.n_compute / 64;
+    rat_b = intra ? sh.B_w : 1;
+    red_vals = intra ? kAdjRedIntra : kAdjVals;
     size_t b = 0;
     elem = b;
     b = up(b + sizeof(double) * 3 * sh.E);
@@ -42,15 +55,15 @@ struct AdjLayout {
     b = up(b + sizeof(Geo) * FT);
     glin = b;
     b = up(b + sizeof(GLin) * FT);
-    red = b;  // [2][FT][waves][kAdjVals]
-    b = up(b + sizeof(float) * 2 * FT * waves * kAdjVals);
+    red = b;  // [2][FT][waves][red_vals]
+    b = up(b + sizeof(float) * 2 * FT * waves * red_vals);
     size_t t = 0;
     GD = t;  // [FT][M_t][2] float4: (G, D0), (D1, D2)
     t += sizeof(float4) * FT * 2 * sh.M_t;
     U = t;  // [FT][E][B_w]
     t += sizeof(float2) * FT * sh.E * sh.B_w;
-    rat = t;  // [FT][E]
-    t += sizeof(float2) * FT * sh.E;
+    rat = t;  // [FT][E][rat_b]
+    t += sizeof(float2) * FT * sh.E * rat_b;
     er = t;  // [FT][E]: unit vector centroid -> element (xyz), 1 / R (w)
     t += sizeof(float4) * FT * sh.E;
     off = t;  // [FT][E]
@@ -78,10 +91,10 @@ struct AdjSmem {
   float *red;
   unsigned char *buf0;
   size_t stride, oGD, oU, orat, oer, ooff, otau;
-  int waves;
+  int waves, rat_b, red_vals;
 
-  __device__ void carve(unsigned char *base, const EchoShape &sh) {
-    const AdjLayout<MB, FT> L(sh);
+  __device__ void carve(unsigned char *base, const EchoShape &sh, bool intra) {
+    const AdjLayout<MB, FT> L(sh, intra);
     elem = reinterpret_cast<double *>(base + L.elem);
     geo = reinterpret_cast<Geo *>(base + L.geo);
     glin = reinterpret_cast<GLin *>(base + L.glin);
@@ -95,6 +108,8 @@ struct AdjSmem {
     ooff = L.off;
     otau = L.tau;
     waves = L.waves;
+    rat_b = L.rat_b;
+    red_vals = L.red_vals;
   }
   __device__ AdjTile tile(int k) const {
     unsigned char *t = buf0 + static_cast<size_t>(k) * stride;
@@ -102,7 +117,7 @@ struct AdjSmem {
             reinterpret_cast<float2 *>(t + orat), reinterpret_cast<float4 *>(t + oer),
             reinterpret_cast<float *>(t + ooff), reinterpret_cast<float *>(t + otau)};
   }
-  __device__ float *red_buf(int k) const { return red + static_cast<size_t>(k) * FT * waves * kAdjVals; }
+  __device__ float *red_buf(int k) const { return red + static_cast<size_t>(k) * FT * waves * red_vals; }
 };
 
 // Orders a wave's own LDS writes before its later LDS reads by other lanes.
@@ -131,15 +146,17 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
     else
       geo[i].valid = 0;
     make_glin(geo[i], rc, m_tile0, glin[i]);
+    if (rc.intra && geo[i].valid) glin[i].quad = static_cast<float>(chord_curvature(geo[i], rc, m_tile0, MB));
   }
   wave_lds_sync_adj();
   for (int task = lane; task < kHalf * E; task += 64) {
     const int i = i0 + task / E, e = task % E;
     const Geo g = lds_copy(geo[i]);  // one batch of LDS reads
     float2 *Ue = tl.U + (i * E + e) * sh.B_w;
+    float2 *re = tl.rat + (i * E + e) * sm.rat_b;
     if (!g.valid) {
       for (int bb = 0; bb < sh.B_w; ++bb) Ue[bb] = make_float2(0.0f, 0.0f);
-      tl.rat[i * E + e] = make_float2(1.0f, 0.0f);
+      for (int bb = 0; bb < sm.rat_b; ++bb) re[bb] = make_float2(1.0f, 0.0f);
       tl.off[i * E + e] = 0.0f;
       tl.er[i * E + e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       tl.tau[i * E + e] = 0.0f;
@@ -162,9 +179,20 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
     double delta = rc.df * tau;
     delta -= floor(delta);
     const float inv_r = static_cast<float>(inv_rd);
-    for (int bb = 0; bb < sh.B_w; ++bb)
-      Ue[bb] = phasor_m2pi<float>(psi0 + static_cast<double>(m_tile0 + bb * MB) * delta, inv_r);
-    tl.rat[i * E + e] = phasor_m2pi<float>(delta, 1.0f);
+    if (!rc.intra) {
+      for (int bb = 0; bb < sh.B_w; ++bb)
+        Ue[bb] = phasor_m2pi<float>(psi0 + static_cast<double>(m_tile0 + bb * MB) * delta, inv_r);
+      re[0] = phasor_m2pi<float>(delta, 1.0f);
+    } else {
+      // as the forward: exact FP64 phases at both ends of each block, joined by the chord
+      for (int bb = 0; bb < sh.B_w; ++bb) {
+        const int ma = m_tile0 + bb * MB;
+        const double pa = element_phase(g, rc, sm.elem + 3 * e, tx, ma);
+        const double pb = element_phase(g, rc, sm.elem + 3 * e, tx, ma + MB);
+        Ue[bb] = phasor_m2pi<float>(pa - floor(pa), inv_r);
+        re[bb] = phasor_m2pi<float>((pb - pa) * (1.0 / MB), 1.0f);
+      }
+    }
     tl.off[i * E + e] = static_cast<float>(offv);
     tl.er[i * E + e] = make_float4(static_cast<float>(dx * inv_rd), static_cast<float>(dy * inv_rd),
                                    static_cast<float>(dz * inv_rd), inv_r);
@@ -178,6 +206,15 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
     for (int j = lane; j < sh.M_t; j += 64) {
       float2 gv, dv[3];
       g_lin_grad(q, j, gv, dv);
+      if (rc.intra) {
+        // the forward's curvature factor exp(-j 2 pi q jj (jj - MB)) to first order, on G
+        // and on its node derivatives alike
+        const int jj = j % MB;
+        const float x = 6.283185307179586f * q.quad * static_cast<float>(jj * (jj - MB));
+        gv = make_float2(fmaf(gv.y, x, gv.x), fmaf(-gv.x, x, gv.y));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dv[k] = make_float2(fmaf(dv[k].y, x, dv[k].x), fmaf(-dv[k].x, x, dv[k].y));
+      }
       float4 *dst = tl.GD + (static_cast<int64_t>(i) * sh.M_t + j) * 2;
       dst[0] = make_float4(gv.x, gv.y, dv[0].x, dv[0].y);
       dst[1] = make_float4(dv[1].x, dv[1].y, dv[2].x, dv[2].y);
@@ -187,15 +224,21 @@ __device__ void adj_stage_tile(const DevScene &sc, const RadarConst &rc, const E
 
 // Sums of a finished tile's per-wave channel sums (fixed wave order) into the
 // per-(chirp, facet, tile) partials, by the staging waves.
+// With the delay within the chirp, the three velocity sums go to partial_v [slot][4].
 template <int MB, int FT>
-__device__ void adj_flush(const AdjSmem<MB, FT> &sm, const float *red, float *partial, int64_t F,
-                          const EchoShape &sh, int n, int mt, int ot, int32_t t0, int nf, int st) {
-  for (int task = st; task < nf * 7; task += kStagingThreads) {
-    const int i = task / 7, k = task % 7;
+__device__ void adj_flush(const AdjSmem<MB, FT> &sm, const float *red, float *partial,
+                          float *partial_v, int64_t F, const EchoShape &sh, int n, int mt, int ot,
+                          int32_t t0, int nf, int st) {
+  const int nv = partial_v ? 10 : 7;
+  for (int task = st; task < nf * nv; task += kStagingThreads) {
+    const int i = task / nv, k = task % nv;
     float s = 0.0f;
-    for (int wv = 0; wv < sm.waves; ++wv) s += red[(i * sm.waves + wv) * kAdjVals + k];
+    for (int wv = 0; wv < sm.waves; ++wv) s += red[(i * sm.waves + wv) * sm.red_vals + k];
     const int64_t slot = ((static_cast<int64_t>(n) * F + t0 + i) * sh.m_tiles + mt) * sh.o_tiles + ot;
-    partial[slot * kAdjVals + k] = s;
+    if (k < 7)
+      partial[slot * kAdjVals + k] = s;
+    else
+      partial_v[slot * 4 + (k - 7)] = s;
   }
 }
 
@@ -203,15 +246,16 @@ __device__ void adj_flush(const AdjSmem<MB, FT> &sm, const float *red, float *pa
 // holds conj(g) for MB samples of channel o in registers) and two staging waves, with
 // double-buffered tiles of FT lit facets as in the forward kernel. Both branches pass
 // the same barriers: one per tile and a final one.
-template <int MB, int FT>
+// INTRA: the delay within the chirp (rc.intra), with the velocity sums into partial_v.
+template <int MB, int FT, bool INTRA>
 __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarConst rc,
                                                            const double *elem, AdjShape ash,
                                                            const float2 *grad_echo,
-                                                           float *partial) {
+                                                           float *partial, float *partial_v) {
   extern __shared__ __align__(16) unsigned char adj_smem[];
   const EchoShape &sh = ash.sh;
   AdjSmem<MB, FT> sm;
-  sm.carve(adj_smem, sh);
+  sm.carve(adj_smem, sh, INTRA);
   const int tid = threadIdx.x;
   for (int i = tid; i < 3 * sh.E; i += blockDim.x) sm.elem[i] = elem[i];
   __syncthreads();
@@ -229,8 +273,8 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
     for (int32_t k = 0; k < n_tiles; ++k) {
       __syncthreads();
       if (k > 0)
-        adj_flush<MB, FT>(sm, sm.red_buf((k - 1) & 1), partial, ash.F, sh, n, mt, ot, (k - 1) * FT,
-                          min(FT, cnt - (k - 1) * FT), st);
+        adj_flush<MB, FT>(sm, sm.red_buf((k - 1) & 1), partial, partial_v, ash.F, sh, n, mt, ot,
+                          (k - 1) * FT, min(FT, cnt - (k - 1) * FT), st);
       const int32_t t1 = (k + 1) * FT;
       if (t1 < cnt)
         adj_stage_tile<MB, FT>(sc, rc, sh, sm, sm.tile((k & 1) ^ 1), n, cnt, t1, min(FT, cnt - t1),
@@ -238,8 +282,8 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
     }
     __syncthreads();
     if (n_tiles > 0)
-      adj_flush<MB, FT>(sm, sm.red_buf((n_tiles - 1) & 1), partial, ash.F, sh, n, mt, ot,
-                        (n_tiles - 1) * FT, min(FT, cnt - (n_tiles - 1) * FT), st);
+      adj_flush<MB, FT>(sm, sm.red_buf((n_tiles - 1) & 1), partial, partial_v, ash.F, sh, n, mt,
+                        ot, (n_tiles - 1) * FT, min(FT, cnt - (n_tiles - 1) * FT), st);
     return;
   }
 
@@ -271,18 +315,23 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
     float *red = sm.red_buf(kt & 1);
     const int nf = min(FT, cnt - kt * FT);
     for (int i = 0; i < nf; ++i) {
-      float v[7] = {0, 0, 0, 0, 0, 0, 0};
+      constexpr int NV = INTRA ? 10 : 7;
+      float v[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k] = 0.0f;
       if (o_ok) {
         const float2 up = tl.U[(i * E + p) * sh.B_w + b];
         const float2 uq = tl.U[(i * E + P + q) * sh.B_w + b];
-        const float2 rp = tl.rat[i * E + p], rq = tl.rat[i * E + P + q];
+        const int rb = INTRA ? b : 0;
+        const float2 rp = tl.rat[(i * E + p) * sm.rat_b + rb];
+        const float2 rq = tl.rat[(i * E + P + q) * sm.rat_b + rb];
         const float eps = tl.off[i * E + p] * tl.off[i * E + P + q];
         float2 z = make_float2(fma_r(up.x, uq.x, -up.y * uq.y), fma_r(up.x, uq.y, up.y * uq.x));
         z = make_float2(fma_r(-eps, z.y, z.x), fma_r(eps, z.x, z.y));
         const float2 r = make_float2(fma_r(rp.x, rq.x, -rp.y * rq.y), fma_r(rp.x, rq.y, rp.y * rq.x));
         // per sample: (G, D0) and (D1, D2) as two 16-byte LDS reads, a block ahead
         const float4 *gd = tl.GD + (static_cast<int64_t>(i) * sh.M_t + b * MB) * 2;
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
         constexpr int kB = 2;
         float4 ca[2 * kB], cb[2 * kB];
 #pragma unroll
@@ -304,6 +353,7 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
             const float yy = fma_r(g0.x, w.y, g0.y * w.x);
             s1 += yy;
             s2 = fma_r(static_cast<float>(j), yy, s2);
+            if constexpr (INTRA) s3 = fma_r(static_cast<float>(j * j), yy, s3);
             a0 = fma_r(g0.z, w.x, fma_r(-g0.w, w.y, a0));
             a1 = fma_r(g1.x, w.x, fma_r(-g1.y, w.y, a1));
             a2 = fma_r(g1.z, w.x, fma_r(-g1.w, w.y, a2));
@@ -314,8 +364,11 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
 #pragma unroll
           for (int u = 0; u < 2 * kB; ++u) ca[u] = cb[u];
         }
-        // sum_m m Im(y) with m counted from the block start; shift to absolute m
-        s2 = fma_r(static_cast<float>(m_base), s1, s2);
+        // sum_m m Im(y) (and m^2 Im(y)) with m counted from the block start; shift to
+        // absolute m
+        const float mb = static_cast<float>(m_base);
+        if constexpr (INTRA) s3 = fma_r(mb * mb, s1, fma_r(2.0f * mb, s2, s3));
+        s2 = fma_r(mb, s1, s2);
         // dL/dR_p and dL/dR_q of this channel, then onto the centroid: dR/dc = -e_hat
         const float tpq = tl.tau[i * E + p] + tl.tau[i * E + P + q];
         const float f0mu = static_cast<float>(rc.f0 - slope * static_cast<double>(tpq));
@@ -329,12 +382,20 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
         v[4] = a0;
         v[5] = a1;
         v[6] = a2;
+        if constexpr (INTRA) {
+          // the velocity's share through the phase at the sample times
+          const float kv = -kf0 * static_cast<float>(1.0 / rc.fs) *
+                           (f0mu * s2 + static_cast<float>(rc.df) * s3);
+          v[7] = kv * (ep.x + eq.x);
+          v[8] = kv * (ep.y + eq.y);
+          v[9] = kv * (ep.z + eq.z);
+        }
       }
       // every lane of the (whole) wave takes part: DPP reads all lanes
 #pragma unroll
-      for (int k = 0; k < 7; ++k) {
+      for (int k = 0; k < NV; ++k) {
         const float s = wave_sum(v[k]);
-        if ((tid & 63) == 0) red[(i * sm.waves + wv) * kAdjVals + k] = s;
+        if ((tid & 63) == 0) red[(i * sm.waves + wv) * sm.red_vals + k] = s;
       }
     }
   }
@@ -342,10 +403,12 @@ __global__ void __launch_bounds__(512) adjoint_echo_kernel(DevScene sc, RadarCon
 }
 
 // Per lit (chirp, facet): sum the partials and apply the chain rule to the three
-// world vertices (FP64). Writes gxw[(n F + f) * 9 + 3 corner + axis].
+// world vertices (FP64). Writes gxw[(n F + f) * 9 + 3 corner + axis]; with partial_v, the
+// velocity's sums over samples into gxv[(n F + f) * 3 + axis].
 __global__ void __launch_bounds__(256) facet_grad_kernel(DevScene sc, RadarConst rc,
                                                          AdjShape ash, const float *partial,
-                                                         float *gxw) {
+                                                         float *gxw, const float *partial_v,
+                                                         float *gxv) {
   const int n = blockIdx.y;
   const int32_t item = blockIdx.x * blockDim.x + threadIdx.x;
   if (item >= sc.vis_cnt[n]) return;
@@ -356,6 +419,17 @@ __global__ void __launch_bounds__(256) facet_grad_kernel(DevScene sc, RadarConst
   for (int s = 0; s < nslots; ++s)
     for (int k = 0; k < 7; ++k) acc[k] += src[s * kAdjVals + k];
   const int64_t f = sc.vis_idx[static_cast<int64_t>(n) * sc.n_facets + item];
+  if (partial_v) {
+    double vs[3] = {0.0, 0.0, 0.0};
+    const float *pv = partial_v + (static_cast<int64_t>(n) * ash.F + item) * nslots * 4;
+    for (int s = 0; s < nslots; ++s)
+      for (int k = 0; k < 3; ++k) vs[k] += pv[s * 4 + k];
+    float *ov = gxv + (static_cast<int64_t>(n) * sc.n_facets + f) * 3;
+    for (int k = 0; k < 3; ++k) {
+      const float g = static_cast<float>(vs[k]);
+      ov[k] = sh.accumulate ? ov[k] + g : g;
+    }
+  }
   const int ii = find_inst(sc.inst, sc.n_inst, f);
   const DevInstance &I = sc.inst[ii];
   const int64_t lt = f - I.facet_base;
@@ -456,17 +530,22 @@ __global__ void fill_zero_kernel(float *p, int64_t n) {
 
 // Per facet and component: the sum over chirps of the world-vertex gradients and of t_n
 // times them (FP64, chirp order): gsum[f * 9 + c], gtsum[f * 9 + c]. Consecutive threads
-// read consecutive components of one chirp's row.
-__global__ void __launch_bounds__(256) facet_chirp_sum_kernel(const float *gxw, int64_t n_facets,
-                                                              int N, double tc, double *gsum,
-                                                              double *gtsum) {
+// read consecutive components of one chirp's row. gxv (or null): the velocity's sums over
+// the samples of each chirp [N][F][3], a third of which joins the t_n-weighted sum of each
+// corner (the vertex gather adds the three corners back up for the velocity).
+__global__ void __launch_bounds__(256) facet_chirp_sum_kernel(const float *gxw, const float *gxv,
+                                                              int64_t n_facets, int N, double tc,
+                                                              double *gsum, double *gtsum) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n_facets * 9) return;
+  const int64_t f = idx / 9;
+  const int axis = static_cast<int>(idx % 3);
   double g = 0.0, gt = 0.0;
   for (int n = 0; n < N; ++n) {
     const double v = gxw[static_cast<int64_t>(n) * n_facets * 9 + idx];
     g += v;
     gt += (n * tc) * v;
+    if (gxv) gt += gxv[(static_cast<int64_t>(n) * n_facets + f) * 3 + axis] * (1.0 / 3.0);
   }
   gsum[idx] = g;
   gtsum[idx] = gt;
@@ -527,7 +606,9 @@ size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F) {
 
 int adjoint_tile_m() { return kAdjMB; }
 
-size_t adjoint_smem_bytes(const EchoShape &sh) { return AdjLayout<kAdjMB, kAdjFT>(sh).total; }
+size_t adjoint_smem_bytes(const EchoShape &sh, bool intra) {
+  return AdjLayout<kAdjMB, kAdjFT>(sh, intra).total;
+}
 
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(fill_zero_kernel, dim3(1024), dim3(256), 0, s, p, n);
@@ -535,27 +616,40 @@ hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
-                                 const float *partial, float *gxw, hipStream_t s) {
+                                 const float *partial, float *gxw, hipStream_t s,
+                                 const float *partial_v, float *gxv) {
   if (sc.n_facets == 0) return hipGetLastError();
+  if ((partial_v == nullptr) != (gxv == nullptr)) return hipErrorInvalidValue;
   AdjShape ash{sh, static_cast<int32_t>(sc.n_facets), 0};
   dim3 g2(static_cast<unsigned>((sc.n_facets + 255) / 256), rc.N);
-  hipLaunchKernelGGL(facet_grad_kernel, g2, dim3(256), 0, s, sc, rc, ash, partial, gxw);
+  hipLaunchKernelGGL(facet_grad_kernel, g2, dim3(256), 0, s, sc, rc, ash, partial, gxw, partial_v,
+                     gxv);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
-                          hipStream_t s) {
+                          hipStream_t s, float *partial_v, float *gxv) {
   AdjShape ash{sh, static_cast<int32_t>(sc.n_facets), 0};
   const int threads = sh.n_compute + kStagingThreads;
-  const hipError_t e =
+  const bool intra = rc.intra != 0;
+  if (intra != (partial_v != nullptr) || (partial_v == nullptr) != (gxv == nullptr))
+    return hipErrorInvalidValue;
+  hipError_t e =
       sh.accumulate ? hipSuccess : launch_fill_zero(gxw, static_cast<int64_t>(rc.N) * sc.n_facets * 9, s);
+  if (e == hipSuccess && intra && !sh.accumulate)
+    e = launch_fill_zero(gxv, static_cast<int64_t>(rc.N) * sc.n_facets * 3, s);
   if (e != hipSuccess || sc.n_facets == 0) return e;
   const unsigned grid = static_cast<unsigned>(rc.N) * sh.m_tiles * sh.o_tiles;
-  hipLaunchKernelGGL((adjoint_echo_kernel<kAdjMB, kAdjFT>), dim3(grid), dim3(threads),
-                     adjoint_smem_bytes(sh), s, sc, rc, elem, ash,
-                     static_cast<const float2 *>(grad_echo), partial);
-  return launch_adjoint_finish(sc, rc, sh, partial, gxw, s);
+  if (intra)
+    hipLaunchKernelGGL((adjoint_echo_kernel<kAdjMB, kAdjFT, true>), dim3(grid), dim3(threads),
+                       adjoint_smem_bytes(sh, true), s, sc, rc, elem, ash,
+                       static_cast<const float2 *>(grad_echo), partial, partial_v);
+  else
+    hipLaunchKernelGGL((adjoint_echo_kernel<kAdjMB, kAdjFT, false>), dim3(grid), dim3(threads),
+                       adjoint_smem_bytes(sh, false), s, sc, rc, elem, ash,
+                       static_cast<const float2 *>(grad_echo), partial, nullptr);
+  return launch_adjoint_finish(sc, rc, sh, partial, gxw, s, partial_v, gxv);
 }
 
 hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, double gi,
@@ -568,12 +662,12 @@ hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, do
   return hipGetLastError();
 }
 
-hipError_t launch_facet_chirp_sum(const float *gxw, int64_t n_facets, int N, double tc,
-                                  double *gsum, double *gtsum, hipStream_t s) {
+hipError_t launch_facet_chirp_sum(const float *gxw, const float *gxv, int64_t n_facets, int N,
+                                  double tc, double *gsum, double *gtsum, hipStream_t s) {
   if (n_facets > 0) {
     const int64_t n = n_facets * 9;
     hipLaunchKernelGGL(facet_chirp_sum_kernel, dim3(static_cast<unsigned>((n + 255) / 256)),
-                       dim3(256), 0, s, gxw, n_facets, N, tc, gsum, gtsum);
+                       dim3(256), 0, s, gxw, gxv, n_facets, N, tc, gsum, gtsum);
   }
   return hipGetLastError();
 }

@@ -8,6 +8,9 @@
 namespace rsim {
 
 constexpr int kAdjVals = 8;  // grad_c (3), sum Re y, t0, t1, t2, pad
+// per-wave sums of the vector-unit adjoint with the delay within the chirp: the seven
+// above, then the velocity's sum over samples (3), padding
+constexpr int kAdjRedIntra = 12;
 
 // sinc(u) and sinc'(u) = (cos u - sinc u) / u at u = x0 + j x_i (rad), t = u / (2 pi)
 // (turns, centred at j = 0). Series below |u| = 0.3.
@@ -162,10 +165,6 @@ struct AdjShape {
   int32_t pad;
 };
 
-// Per-(chirp, lit facet, tile) sums -> world-vertex gradients (FP64 chain rule), after
-// zeroing gxw: shared by both adjoint facet sums.
-hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
-                                 const float *partial, float *gxw, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 
 }  // namespace rsim

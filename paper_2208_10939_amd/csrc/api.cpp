@@ -133,6 +133,10 @@ struct rsim_ctx {
   size_t max_lds = 0;
   std::map<std::tuple<int, int, int>, TunedShape> tuned;  // (M, O, precision) -> shape
   int32_t bwd_kernel = RSIM_KERNEL_AUTO;  // facet-sum kernel of rsim_backward
+  int32_t bwd_intra = 0;  // rsim_backward differentiates the delay within the chirp
+  // velocity sums of that adjoint: per (chirp, lit facet, slot) [4] and per facet [N][F][3]
+  void *adj_pv = nullptr, *adj_gxv = nullptr;
+  size_t adj_pv_bytes = 0, adj_gxv_bytes = 0;
   // adjoint work buffers
   float *adj_partial = nullptr, *adj_gxw = nullptr;
   double *adj_vpart = nullptr, *adj_gsum = nullptr;  // gsum: [2][F][9] (plain, t_n-weighted)
@@ -1462,6 +1466,14 @@ int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel) {
   return RSIM_OK;
 }
 
+int32_t rsim_set_backward_intra_chirp(rsim_ctx *ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
+  if (enable != 0 && enable != 1)
+    return fail(ctx, RSIM_EINVAL, "rsim_set_backward_intra_chirp: enable must be 0 or 1");
+  ctx->bwd_intra = enable;
+  return RSIM_OK;
+}
+
 int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scenes, void *echo,
                         uint32_t *vis_mask, void *hip_stream, const rsim_opts *opts) {
   if (!ctx) return fail(nullptr, RSIM_EINVAL, "ctx is NULL");
@@ -1843,14 +1855,21 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   if (ctx->dbounce)
     return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path and "
                 "the ground bounce; disable the double bounce (rsim_set_double_bounce) first");
-  const RadarConst rcn = radar_const(ctx);
+  if (ctx->bwd_intra &&
+      (ctx->bwd_kernel == RSIM_KERNEL_MATRIX || ctx->bwd_kernel == RSIM_KERNEL_NUFFT))
+    return fail(ctx, RSIM_EINVAL, "rsim_backward: the adjoint with the delay within the chirp "
+                "runs on the vector units (backward kernel AUTO or VECTOR)");
+  RadarConst rcn = radar_const(ctx);
+  rcn.intra = ctx->bwd_intra;
   if (cross_term_bound(ctx, rcn) > 3e-4)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: array aperture too large for the FP32 sum");
   // the NUFFT adjoint when asked for, and with AUTO where eligible; else the matrix cores
-  // when the array allows them (unless the vector units are asked for)
+  // when the array allows them (unless the vector units are asked for, or the delay within
+  // the chirp, which only the vector-unit adjoint takes)
   NuShape nsb{};
   bool nufft = false;
-  if (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO) {
+  if (!ctx->bwd_intra &&
+      (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO)) {
     const char *nwhy = nufft_adj_ineligible(ctx, rcn, &nsb);
     if (nwhy && ctx->bwd_kernel == RSIM_KERNEL_NUFFT)
       return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
@@ -1862,7 +1881,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   const char *why = matrix_ineligible(ctx, rcn, RSIM_FP32_PHASE64);
   if (ctx->bwd_kernel == RSIM_KERNEL_MATRIX && why)
     return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", why);
-  const bool matrix = !nufft && !why && ctx->bwd_kernel != RSIM_KERNEL_VECTOR &&
+  const bool matrix = !nufft && !why && !ctx->bwd_intra && ctx->bwd_kernel != RSIM_KERNEL_VECTOR &&
                       adjoint_mfma_smem_bytes(rcn.P, rcn.Q, rcn.P + rcn.Q) <= ctx->max_lds;
   EchoShape sh{};
   if (nufft) {
@@ -1880,11 +1899,13 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
     sh.n_compute = 256;
     sh.two_pi_slope = 2.0 * kPi * rcn.slope;
   } else {
+    const bool intra = ctx->bwd_intra != 0;
     sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads);
-    while (sh.B_w > 1 && adjoint_smem_bytes(sh) > ctx->max_lds)
+    while (sh.B_w > 1 && adjoint_smem_bytes(sh, intra) > ctx->max_lds)
       sh = echo_shape(ctx, rcn, adjoint_tile_m(), kMaxComputeThreads, sh.B_w - 1);
-    if (adjoint_smem_bytes(sh) > ctx->max_lds)
-      return fail(ctx, RSIM_ERANGE, "adjoint tile needs %zu bytes of LDS", adjoint_smem_bytes(sh));
+    if (adjoint_smem_bytes(sh, intra) > ctx->max_lds)
+      return fail(ctx, RSIM_ERANGE, "adjoint tile needs %zu bytes of LDS",
+                  adjoint_smem_bytes(sh, intra));
   }
   const int64_t F = sc.n_facets, N = rcn.N;
   size_t vmax = 1;
@@ -1902,6 +1923,15 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                    std::max<size_t>(1, adjoint_partial_floats(sh, N, F)))))
     return rc;
   if ((rc = grow_f(ctx->adj_gxw, ctx->adj_gxw_n, std::max<size_t>(1, N * F * 9)))) return rc;
+  float *pv = nullptr, *gxv = nullptr;
+  if (ctx->bwd_intra) {
+    const size_t pv_b = sizeof(float) * 4 * std::max<size_t>(1, adjoint_partial_floats(sh, N, F) / kAdjSlotFloats);
+    const size_t gxv_b = sizeof(float) * 3 * std::max<int64_t>(1, N * F);
+    if ((rc = grow_bytes(ctx, &ctx->adj_pv, &ctx->adj_pv_bytes, pv_b))) return rc;
+    if ((rc = grow_bytes(ctx, &ctx->adj_gxv, &ctx->adj_gxv_bytes, gxv_b))) return rc;
+    pv = static_cast<float *>(ctx->adj_pv);
+    gxv = static_cast<float *>(ctx->adj_gxv);
+  }
   if (ctx->adj_gsum_n < static_cast<size_t>(2 * 9 * std::max<int64_t>(1, F))) {
     dev_free(ctx, ctx->adj_gsum);
     ctx->adj_gsum = nullptr;
@@ -1966,12 +1996,12 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
     } else if (matrix)
       HIP_TRY(ctx, launch_adjoint_mfma(dk, rk, elem, sk, gk, ctx->adj_partial, ctx->adj_gxw, s));
     else
-      HIP_TRY(ctx, launch_adjoint(dk, rk, elem, sk, gk, ctx->adj_partial, ctx->adj_gxw, s));
+      HIP_TRY(ctx, launch_adjoint(dk, rk, elem, sk, gk, ctx->adj_partial, ctx->adj_gxw, s, pv, gxv));
   }
   stage_end(ctx, timing, 5, s);
   stage_begin(ctx, timing, 7, s);
   double *gsum = ctx->adj_gsum, *gtsum = ctx->adj_gsum + 9 * F;
-  HIP_TRY(ctx, launch_facet_chirp_sum(ctx->adj_gxw, F, rcn.N, rcn.tc, gsum, gtsum, s));
+  HIP_TRY(ctx, launch_facet_chirp_sum(ctx->adj_gxw, gxv, F, rcn.N, rcn.tc, gsum, gtsum, s));
   for (size_t i = 0; i < sc.inst.size(); ++i) {
     const InstRec &r = sc.inst[i];
     const MeshRec &m = ctx->meshes[r.mesh];

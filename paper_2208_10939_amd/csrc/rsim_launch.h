@@ -152,9 +152,12 @@ hipError_t launch_nufft_spread(const DevScene &sc, const RadarConst &rc, const N
 constexpr int kAdjSlotFloats = 8;
 // Per-(chirp, lit facet, slot) sums -> world-vertex gradients (FP64 chain rule) into gxw
 // (zero on entry; added to it with sh.accumulate), slots = sh.m_tiles * sh.o_tiles. The
-// adjoint launchers below clear gxw first unless sh.accumulate.
+// adjoint launchers below clear gxw first unless sh.accumulate. partial_v / gxv (the
+// vector-unit adjoint with the delay within the chirp, else both null): the velocity's
+// sums over samples per slot [slot][4], summed into gxv [N][F][3] (as gxw for accumulate).
 hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const EchoShape &sh,
-                                 const float *partial, float *gxw, hipStream_t s);
+                                 const float *partial, float *gxw, hipStream_t s,
+                                 const float *partial_v = nullptr, float *gxv = nullptr);
 // Adjoint of launch_nufft for one chunk of chirps (stop-and-hop, facets only: sc.n_points
 // must be 0): writes the per-(chirp, lit facet) adjoint sums into partial
 // [N][n_facets][kAdjVals]. Uses nb.srec and nb.sder (records in entry order, rec_stride per
@@ -196,7 +199,7 @@ int noise_partials_per_cube();
 // adjoint of the facet sum (FP32): partial sums per (chirp, lit facet, tile), then
 // per-facet world-vertex gradients gxw [N][F][9]
 size_t adjoint_partial_floats(const EchoShape &sh, int64_t N, int64_t F);
-size_t adjoint_smem_bytes(const EchoShape &sh);
+size_t adjoint_smem_bytes(const EchoShape &sh, bool intra);
 int adjoint_tile_m();
 // adjoint on the matrix cores (FP32, separable form): one workgroup per (chirp,
 // 64-sample tile); EchoShape with o_tiles = 1 and m_tiles = ceil(M / 64)
@@ -205,15 +208,19 @@ size_t adjoint_mfma_smem_bytes(int P, int Q, int E);
 hipError_t launch_adjoint_mfma(const DevScene &sc, const RadarConst &rc, const double *elem,
                                const EchoShape &sh, const void *grad_echo, float *partial,
                                float *gxw, hipStream_t s);
+// rc.intra: the delay within the chirp (then partial_v [N][F][slots][4] and gxv [N][F][3]
+// are required, else both null).
 hipError_t launch_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                           const EchoShape &sh, const void *grad_echo, float *partial, float *gxw,
-                          hipStream_t s);
+                          hipStream_t s, float *partial_v = nullptr, float *gxv = nullptr);
 // out[i] = conj(gamma) in[i] (complex64): the echo gradient of a path type added times gamma
 hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, double gi,
                              hipStream_t s);
-// world-vertex gradients [N][F][9] -> per-facet sums over chirps, plain and t_n-weighted
-hipError_t launch_facet_chirp_sum(const float *gxw, int64_t n_facets, int N, double tc,
-                                  double *gsum, double *gtsum, hipStream_t s);
+// world-vertex gradients [N][F][9] -> per-facet sums over chirps, plain and t_n-weighted;
+// gxv (or null): the velocity's sums over samples [N][F][3], a third added to the
+// t_n-weighted sum of each corner
+hipError_t launch_facet_chirp_sum(const float *gxw, const float *gxv, int64_t n_facets, int N,
+                                  double tc, double *gsum, double *gtsum, hipStream_t s);
 hipError_t launch_vertex_gather(const double *gsum, const double *gtsum, const double *rot_dev,
                                 int64_t facet_base, const int32_t *csr_off, const int32_t *csr_ent,
                                 int32_t n_verts, float *gv, double *vpart, double *vel_out,

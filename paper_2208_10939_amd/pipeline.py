@@ -42,11 +42,17 @@ class Simulator:
         self.n_facets = [self.ctx.scene_info(s)[0] for s in self.scene_ids]
         self.mask_words = [self.ctx.scene_info(s)[1] for s in self.scene_ids]
         self.dev = torch.device("cuda", device)
+        self.intra_chirp = False  # RadarRDM: delay within the chirp, forward and backward
 
     def echo_buffer(self, n_scenes: int = 1, precision: int = RSIM_FP32_PHASE64):
         dt = torch.complex128 if precision == RSIM_FP64 else torch.complex64
         return torch.empty((n_scenes, self.O, self.wf.n_chirps, self.wf.n_samples), dtype=dt,
                            device=self.dev)
+
+    def set_intra_chirp(self, enable: bool):
+        """RadarRDM's forward takes each facet's delay at the sample times (opts.intra_chirp)
+        and its backward differentiates that echo (rsim_set_backward_intra_chirp)."""
+        self.intra_chirp = bool(enable)
 
     def set_ground(self, enable: bool, z_ground: float = 0.0, gamma: complex = -1.0):
         """Ground double bounce on/off; while on, masks hold four path types per scene."""

@@ -41,7 +41,8 @@ EXPORTS = (
     "rsim_backward", "rsim_rdm_adjoint",
     "rsim_autotune", "rsim_sync", "rsim_update_mesh", "rsim_set_instance_motion",
     "rsim_rdm_backward", "rsim_detect", "rsim_add_noise", "rsim_set_ground",
-    "rsim_set_backward_kernel", "rsim_set_nufft_chunk", "rsim_form_rdm_noalloc",
+    "rsim_set_backward_kernel", "rsim_set_backward_intra_chirp", "rsim_set_nufft_chunk",
+    "rsim_form_rdm_noalloc",
 )
 
 
@@ -131,6 +132,7 @@ def lib() -> ctypes.CDLL:
         "rsim_add_noise": ([vp, vp, i32, ctypes.c_double, u64, vp, ctypes.POINTER(Opts)], i32),
         "rsim_set_ground": ([vp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
         "rsim_set_backward_kernel": ([vp, i32], i32),
+        "rsim_set_backward_intra_chirp": ([vp, i32], i32),
         "rsim_set_nufft_chunk": ([vp, i32], i32),
         "rsim_form_rdm_noalloc": ([vp, vp, i32, vp, vp, vp, ctypes.POINTER(Opts)], i32),
     }
@@ -287,6 +289,9 @@ class Context:
 
     def set_backward_kernel(self, kernel: int = RSIM_KERNEL_AUTO):
         self._check(self._L.rsim_set_backward_kernel(self._h, int(kernel)))
+
+    def set_backward_intra_chirp(self, enable: bool):
+        self._check(self._L.rsim_set_backward_intra_chirp(self._h, int(bool(enable))))
 
     def set_nufft_chunk(self, max_chirps: int = 0):
         self._check(self._L.rsim_set_nufft_chunk(self._h, int(max_chirps)))

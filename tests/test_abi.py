@@ -259,3 +259,38 @@ def test_nufft_adjoint_refusals_host_only():
     assert L.rsim_set_nufft_chunk(ctx._h, 3) == rsim.RSIM_OK
     assert L.rsim_set_nufft_chunk(ctx._h, 0) == rsim.RSIM_OK
     ctx.close()
+
+
+def test_intra_chirp_adjoint_refusals_host_only():
+    """rsim_set_backward_intra_chirp: 0/1 only; with it on, the adjoint runs on the vector
+    units, so a backward kernel of MATRIX or NUFFT is EINVAL on the host and AUTO / VECTOR
+    reach the (missing) device."""
+    ctx = _host_ctx()
+    L = rsim.lib()
+    wf = scenes.paper_waveform(64, 8)
+    ctx.set_waveform(wf)
+    arr = scenes.sparse_mimo_12x16(wf, 2)
+    ctx.set_array(arr.tx, arr.rx)
+    m = scenes.vehicle_mesh("car", 500)
+    mid = ctx.load_mesh(m.verts, m.tris)
+    sid = ctx.create_scene()
+    ctx.add_instance(sid, mid, np.eye(3), np.array([2.0, 30.0, 0.0]), np.array([0.0, 5.0, 0.0]))
+    dev = ctypes.c_void_p(0x1000)
+    gv = (ctypes.c_void_p * 1)(0x2000)
+
+    def bwd():
+        return L.rsim_backward(ctx._h, sid, dev, dev, gv, 1, dev, None)
+
+    assert L.rsim_set_backward_intra_chirp(ctx._h, 2) == rsim.RSIM_EINVAL
+    assert L.rsim_set_backward_intra_chirp(ctx._h, 1) == rsim.RSIM_OK
+    for k in (rsim.RSIM_KERNEL_MATRIX, rsim.RSIM_KERNEL_NUFFT):
+        assert L.rsim_set_backward_kernel(ctx._h, k) == rsim.RSIM_OK
+        assert bwd() == rsim.RSIM_EINVAL
+        assert b"vector units" in L.rsim_last_error(ctx._h)
+    for k in (rsim.RSIM_KERNEL_AUTO, rsim.RSIM_KERNEL_VECTOR):
+        assert L.rsim_set_backward_kernel(ctx._h, k) == rsim.RSIM_OK
+        assert bwd() == rsim.RSIM_EDEVICE
+    assert L.rsim_set_backward_intra_chirp(ctx._h, 0) == rsim.RSIM_OK
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT) == rsim.RSIM_OK
+    assert bwd() == rsim.RSIM_EDEVICE
+    ctx.close()
