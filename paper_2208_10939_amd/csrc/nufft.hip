@@ -564,11 +564,30 @@ __global__ void __launch_bounds__(256) nufft_key_kernel(DevScene sc0, RadarConst
   nb.key[w.rec + item] = cell;
 }
 
+// Lane `lane`'s key k (0 <= k < 2^nbits; valid: the lane holds an entry) among the keys of
+// its wave: how many earlier lanes hold k, and how many lanes in all. The lanes holding
+// the same key are found bit by bit from one ballot per key bit (a wave-uniform mask of
+// the lanes with that bit set, or its complement): a fixed amount of work per 64 entries,
+// where a loop over the distinct keys would wait on a shuffle and an LDS round trip for
+// each.
+__device__ inline void chunk_rank(int32_t k, bool valid, int nbits, int lane, int *before,
+                                  int *total) {
+  uint64_t eq = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const uint64_t m = __ballot(valid && ((k >> b) & 1));
+    eq &= ((k >> b) & 1) ? m : ~m;
+  }
+  *before = __popcll(eq & ((uint64_t(1) << lane) - 1));
+  *total = __popcll(eq);
+}
+
 // Per chirp: stable counting sort of the entries by cell, and the chirp's runs.
-// Wave w takes the w-th sixteenth of the entries (in entry order): it counts its cells
-// in its own LDS row, the rows become per-wave starting positions (cell offset plus the
-// counts of earlier waves), and each wave then ranks its entries 64 at a time, lanes with
-// the same cell in lane order. Runs are cut by one lane over the occupied cells.
+// Wave w takes the w-th sixteenth of the entries (in entry order), 64 at a time: it counts
+// its cells in its own LDS row (the first lane of each cell in a chunk adds the chunk's
+// count), the rows become per-wave starting positions (cell offset plus the counts of
+// earlier waves), and each wave then ranks its entries 64 at a time: start of the cell
+// plus the earlier lanes of the chunk with that cell (chunk_rank). Runs are cut by one
+// lane over the occupied cells.
 __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc0, NuShape ns,
                                                                    NuBuffers nb, NuBatch bt) {
   extern __shared__ int32_t sort_smem[];
@@ -585,11 +604,20 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc0
   const int32_t n_ent = entry_total(sc, n);
   const int tid = static_cast<int>(threadIdx.x);
   const int w = tid >> 6, lane = tid & 63;
+  int nbits = 1;
+  while ((1 << nbits) < ng) ++nbits;  // cells are below 2^nbits
   const int32_t seg = ((n_ent + kNuSortWaves - 1) / kNuSortWaves + 63) & ~63;
   const int32_t e0 = min(n_ent, w * seg), e1 = min(n_ent, e0 + seg);
   for (int i = tid; i < kNuSortWaves * ng; i += kNuSortThreads) cnt[i] = 0;
   __syncthreads();
-  for (int32_t e = e0 + lane; e < e1; e += 64) atomicAdd(&cnt[w * ng + key[e]], 1);
+  for (int32_t chunk = e0; chunk < e1; chunk += 64) {
+    const int32_t e = chunk + lane;
+    const bool valid = e < e1;
+    const int32_t k = valid ? key[e] : 0;
+    int before, total;
+    chunk_rank(k, valid, nbits, lane, &before, &total);
+    if (valid && before == 0) cnt[w * ng + k] += total;  // one lane per cell: no race
+  }
   __syncthreads();
   // totals of two cells per thread (n_g <= 2048), exclusive scan over cells, then each
   // wave's starting position per cell
@@ -663,20 +691,19 @@ __global__ void __launch_bounds__(kNuSortThreads) nufft_sort_kernel(DevScene sc0
     if (open_n > 0) emit(open_rb, open_rb + open_n, open_cell - wk.b0);
     nb.n_runs[nl] = min(nr, wk.max_runs);
   }
-  // stable ranks: lanes with equal cells are handled together, in lane order
+  // stable ranks: start of the cell for this wave plus the earlier lanes of the chunk
   for (int32_t chunk = e0; chunk < e1; chunk += 64) {
     const int32_t e = chunk + lane;
     const bool valid = e < e1;
-    const int32_t k = valid ? key[e] : -1;
-    uint64_t rem = __ballot(valid);
-    while (rem) {
-      const int leader = __ffsll(static_cast<unsigned long long>(rem)) - 1;
-      const int32_t kl = __shfl(k, leader);
-      const uint64_t m = __ballot(k == kl);
-      const int32_t start = cnt[w * ng + kl];
-      if (k == kl) pos[e] = start + __popcll(m & ((uint64_t(1) << lane) - 1));
-      if (lane == leader) cnt[w * ng + kl] = start + __popcll(m);
-      rem &= ~m;
+    const int32_t k = valid ? key[e] : 0;
+    int before, total;
+    chunk_rank(k, valid, nbits, lane, &before, &total);
+    if (valid) {
+      // one LDS read by every lane of the wave, then one write by the first lane of each
+      // cell (in that order: a wave's LDS instructions run in program order)
+      const int32_t start = cnt[w * ng + k];
+      pos[e] = start + before;
+      if (before == 0) cnt[w * ng + k] = start + total;
     }
   }
 }
