@@ -355,7 +355,17 @@ int32_t ensure_scene_device(rsim_ctx *ctx, SceneRec &sc) {
         flat = std::fabs(z - ctx->z_ground) <= 1e-6;
       }
       d.in_plane = flat ? 1 : 0;
-      d.pad = 0;
+      // horizontal at any height: the vertex height range, when no wider than 2e-6 m
+      double zlo = 0.0, zhi = 0.0;
+      for (size_t v = 0; v < m.verts.size() / 3; ++v) {
+        const double z = r.rot[6] * m.verts[3 * v] + r.rot[7] * m.verts[3 * v + 1] +
+                         r.rot[8] * m.verts[3 * v + 2] + r.pos0[2];
+        zlo = v ? std::min(zlo, z) : z;
+        zhi = v ? std::max(zhi, z) : z;
+      }
+      d.flat = (!m.verts.empty() && r.vel[2] == 0.0 && zhi - zlo <= 2e-6) ? 1 : 0;
+      d.flat_lo = zlo;
+      d.flat_hi = zhi;
       base += d.n_tris;
     }
     sc.n_facets = base;

@@ -57,7 +57,8 @@ struct DevInstance {
   int32_t n_tris;
   int32_t has_bvh;              // 0 if the mesh has no non-degenerate triangle
   int32_t in_plane;             // 1: lies in the reflecting ground plane (never blocks legs ending on it)
-  int32_t pad;
+  int32_t flat;                 // 1: horizontal (world vertex heights within 2e-6 m), no vertical motion
+  double flat_lo, flat_hi;      // lowest and highest world vertex height of a flat instance
 };
 
 // A value read-only for the rest of the kernel, at a wave-uniform address: loaded through

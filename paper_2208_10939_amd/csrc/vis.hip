@@ -116,6 +116,14 @@ __device__ bool blas_occluded(const BvhNode4 *nodes, const float4 *leaf, float o
   }
 }
 
+// A flat (horizontal) instance cannot block the segment c -> s: c lies no lower than its
+// lowest vertex and at most 0.5e-6 m below its highest, and s lies at least 1 m above c,
+// so for t >= kTEps the segment runs at least 0.5e-6 m above every vertex (a ground facet's
+// rays towards the array leave the road grid's BVH untouched).
+__device__ inline bool flat_below(const DevInstance &I, const double c[3], double s_z) {
+  return I.flat && c[2] >= I.flat_lo && I.flat_hi - c[2] <= 0.5e-6 && s_z - c[2] >= 1.0;
+}
+
 // Is the world segment c -> s blocked by any triangle of the scene at time t
 // (triangle `self_local` of instance `self_inst` excluded)?
 __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
@@ -130,6 +138,7 @@ __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
     if (skip_plane && I.in_plane) continue;  // the road surface under a reflected leg
+    if (flat_below(I, c, s[2])) continue;
     double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
     // world-space slab test against the instance box (FP64, conservative box)
     double tn = 0.0, tf = 1.0;
@@ -248,6 +257,7 @@ __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], co
   for (int j = 0; j < sc.n_inst; ++j) {
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
+    if (flat_below(I, c, s1[2]) && flat_below(I, c, s2[2])) continue;
     double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
     // world-space slab test of each segment against the instance box (FP64)
     bool any = false;
