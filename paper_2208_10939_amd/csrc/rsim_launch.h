@@ -162,7 +162,8 @@ hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const
 // must be 0): writes the per-(chirp, lit facet) adjoint sums into partial
 // [N][n_facets][kAdjVals]. Uses nb.srec and nb.sder (records in entry order, rec_stride per
 // chirp), nb.key (per chirp two lists of rec_stride entries: three-point records, others),
-// nb.n_runs (their two counts per chirp) and nb.grid (grid rows [chirp][O][n_g]).
+// nb.pos (the records' cells beside them), nb.order (the lists ordered by cell), nb.n_runs
+// (their two counts per chirp) and nb.grid (grid rows [chirp][O][n_g]); n_g <= 2048.
 // ev (optional): two events recorded around the two gather kernels.
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
