@@ -1002,19 +1002,23 @@ __global__ void __launch_bounds__(256) fill_zero_i32_kernel(int32_t *p, int n) {
 }
 
 // Gaussian-weighted moments mu_k = sum_l g(l) psi(l - x) (l - x)^k, k < K, of a grid row
-// over the kNuWidth + 1 cells from the first within W/2 of x = rc0 + xs. The row holds
-// n_g + kNuWidth cells (its first kNuWidth repeated at the end), so no index wraps and the
-// reads are fixed offsets from one base. With l - x = c + j' (c = s0 + W/2 - xs in (-1, 0],
+// over the kNuWidth + 1 cells from the first within W/2 of x = rc0 + xs. With wrap the row
+// holds n_g + kNuWidth cells (its first kNuWidth repeated at the end) and the first cell is
+// taken modulo n_g; without, the row is a stretch of the grid staged from cell 0 of rc0's
+// frame and holds every cell asked for. Either way the reads are fixed offsets from one
+// base. With l - x = c + j' (c = s0 + W/2 - xs in (-1, 0],
 // j' = j - W/2 in [-W/2, W/2]) the sums T_m = sum g psi j'^m come first, the powers of j'
 // being constants of the unrolled loop, and mu_k = sum_m binom(k, m) c^(k - m) T_m (|c| < 1:
 // no cancellation).
 template <int K>
-__device__ __forceinline__ void row_moments(const float2 *row, int ng, int rc0, float xs,
-                                            float nc, float q_ratio, float2 (&mu)[K]) {
+__device__ __forceinline__ void row_moments(const float2 *row, int ng, bool wrap, int rc0,
+                                            float xs, float nc, float q_ratio,
+                                            float2 (&mu)[K]) {
   static_assert(K == 2 || K == 4, "moment counts used");
   const float s0 = ceilf(xs - 0.5f * kNuWidth);
-  int cell = (rc0 + static_cast<int>(s0)) % ng;  // rc0 + s0 lies in (-ng, 2 ng)
-  cell += (cell < 0) ? ng : 0;
+  int cell = rc0 + static_cast<int>(s0);  // with wrap in (-ng, 2 ng)
+  cell -= (wrap && cell >= ng) ? ng : 0;
+  cell += (wrap && cell < 0) ? ng : 0;
   const float2 *rp = row + cell;
   const float u0 = s0 - xs;
   float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
@@ -1059,8 +1063,11 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // One lane per (chirp, record of one class), a workgroup per (chirp, class, kNuGatherRecs
-// entries of the list ordered by cell), looping over the channels: each channel's grid row of the chirp is staged
-// in LDS and every lane forms the moments at its own sources, then adds this channel's
+// entries of the list ordered by cell), looping over the channels: each channel's grid
+// cells that the workgroup's sources reach are staged in LDS (the records of a workgroup
+// lie within a few cells of each other, so this is a short stretch of the row; the whole
+// row when the stretch would be longer) and every lane forms the moments at its own
+// sources, then adds this channel's
 // share of the per-facet sums in registers: Re y, dL/dc through the channel's distances,
 // and per source parameter sum_o Q mu (weights, coefficients) and sum_o dy/dx_s (offsets).
 // Class 0: three points (kind 1); class 1: a point (zero weight for kind 3) and a
@@ -1072,7 +1079,10 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     const NuRecF<false> *__restrict__ recs, const NuDerF *__restrict__ ders,
     const int32_t *__restrict__ lists, const int32_t *__restrict__ counts,
     const float2 *__restrict__ grids, float *partial, int blocks_per_chirp) {
-  extern __shared__ float2 nu_row[];  // [n_g + kNuWidth]: the row and its first cells again
+  extern __shared__ float2 nu_row[];  // [n_g + kNuWidth]: the row and its first cells again,
+                                      // or the stretch [lo, lo + span) the sources reach
+  __shared__ int32_t reach[3];        // lowest and one past the highest cell reached; 1 if
+                                      // some bound lies outside [-n_g, 2 n_g]
   const int per_xcd = (gridDim.x + kXcds - 1) / kXcds;  // gridDim.x is a multiple of kXcds
   const int logical = static_cast<int>(blockIdx.x % kXcds) * per_xcd + static_cast<int>(blockIdx.x / kXcds);
   const int nl = logical / blocks_per_chirp;
@@ -1125,10 +1135,54 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
 #pragma unroll
   for (int k = 0; k < 3; ++k) ac[k] = {0.0f, 0.0f};
   const float2 *grow = grids + static_cast<int64_t>(nl) * O * ng;
+  // cells the lane's sources reach over every channel: a source at x - off with
+  // |x| <= chan_d + 1 cell reads W + 1 cells from ceil(x - off - W/2)
+  {
+    float mn = -offp[0], mx = -offp[0];
+#pragma unroll
+    for (int j = 1; j < NP; ++j) {
+      mn = fminf(mn, -offp[j]);
+      mx = fmaxf(mx, -offp[j]);
+    }
+    if (CLS == 1) {
+      mn = fminf(mn, -offq);
+      mx = fmaxf(mx, -offq);
+    }
+    const float cd = static_cast<float>(ns.chan_d);
+    if (threadIdx.x == 0) {
+      reach[0] = INT32_MAX;
+      reach[1] = INT32_MIN;
+      reach[2] = 0;
+    }
+    __syncthreads();
+    const float lo_f = static_cast<float>(r.cell) + floorf(mn - cd - 0.5f * kNuWidth - 1.0f);
+    const float hi_f = static_cast<float>(r.cell) + ceilf(mx + cd + 0.5f * kNuWidth + 2.0f);
+    if (on) {
+      if (lo_f >= -static_cast<float>(ng) && hi_f <= 2.0f * ng) {
+        atomicMin(&reach[0], static_cast<int32_t>(lo_f));
+        atomicMax(&reach[1], static_cast<int32_t>(hi_f));
+      } else {
+        atomicOr(&reach[2], 1);
+      }
+    }
+    __syncthreads();
+  }
+  const int32_t lo = reach[0];
+  const int64_t span = static_cast<int64_t>(reach[1]) - reach[0];
+  // the whole row when a source reaches far or the stretch would be as long; else the
+  // stretch [lo, lo + span) (lo >= -n_g, lo + span <= 2 n_g)
+  const bool wrap = reach[2] != 0 || span > ng + kNuWidth;
+  const int rc0 = wrap ? r.cell : r.cell - lo;
+  const int n_stage = wrap ? ng + kNuWidth : static_cast<int>(span);
+  const int s_base = wrap ? 0 : (lo % ng + ng) % ng;  // grid cell of the first staged one
   for (int o = 0; o < O; ++o) {
     __syncthreads();  // the previous channel's row is no longer read
-    for (int l = threadIdx.x; l < ng + kNuWidth; l += blockDim.x)
-      nu_row[l] = grow[static_cast<int64_t>(o) * ng + (l < ng ? l : l - ng)];
+    for (int l = threadIdx.x; l < n_stage; l += blockDim.x) {
+      int c = s_base + l;  // < 2 n_g + kNuWidth
+      c -= (c >= ng) ? ng : 0;
+      c -= (c >= ng) ? ng : 0;
+      nu_row[l] = grow[static_cast<int64_t>(o) * ng + c];
+    }
     __syncthreads();
     // this channel's element offsets from the phase centres (wave-uniform)
     const int p = o / rc.Q, q = o - p * rc.Q;
@@ -1166,7 +1220,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
       float2 mu[2];
-      row_moments<2>(nu_row, ng, r.cell, x - offp[j], nc, q_ratio, mu);
+      row_moments<2>(nu_row, ng, wrap, rc0, x - offp[j], nc, q_ratio, mu);
       const float2 ys = cmul(wp[j], mu[0]);
       const float2 yxs = cmul(wp[j], make_float2(mu[1].x * inv_s2, mu[1].y * inv_s2));
       y.x += ys.x;
@@ -1181,7 +1235,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     }
     if (CLS == 1) {
       float2 mu[4];
-      row_moments<4>(nu_row, ng, r.cell, x - offq, nc, q_ratio, mu);
+      row_moments<4>(nu_row, ng, wrap, rc0, x - offq, nc, q_ratio, mu);
       float2 yp = {0.0f, 0.0f}, yxp = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
