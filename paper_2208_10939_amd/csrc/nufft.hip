@@ -77,6 +77,8 @@ constexpr int kNuSortThreads = 1024;  // 16 waves: each ranks one sixteenth of a
 constexpr int kNuSortWaves = kNuSortThreads / 64;
 constexpr int kNuGatherRecs = 256;  // records (lanes) per adjoint gather workgroup
 constexpr int kNuRedBatch = 8;      // run windows read together by a cell sum of the FFT kernel
+constexpr int kNuGatherStage = 4096;  // grid cells staged in LDS by a gather workgroup (32 KB)
+static_assert(kNuGatherStage >= 2048 + 12, "a whole row fits the gather's staging");
 constexpr int kXcds = 8;            // accelerator complex dies: workgroups go round-robin
 constexpr double kNuGapMin = 2.0;   // radians of k_c beta between nodes of a divided difference
 
@@ -1079,8 +1081,9 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     const NuRecF<false> *__restrict__ recs, const NuDerF *__restrict__ ders,
     const int32_t *__restrict__ lists, const int32_t *__restrict__ counts,
     const float2 *__restrict__ grids, float *partial, int blocks_per_chirp) {
-  extern __shared__ float2 nu_row[];  // [n_g + kNuWidth]: the row and its first cells again,
-                                      // or the stretch [lo, lo + span) the sources reach
+  extern __shared__ float2 nu_row[];  // [kNuGatherStage]: rows of consecutive channels,
+                                      // each the row and its first cells again, or the
+                                      // stretch [lo, lo + span) the sources reach
   __shared__ int32_t reach[3];        // lowest and one past the highest cell reached; 1 if
                                       // some bound lies outside [-n_g, 2 n_g]
   const int per_xcd = (gridDim.x + kXcds - 1) / kXcds;  // gridDim.x is a multiple of kXcds
@@ -1167,23 +1170,30 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     }
     __syncthreads();
   }
-  const int32_t lo = reach[0];
-  const int64_t span = static_cast<int64_t>(reach[1]) - reach[0];
+  // workgroup-uniform values, held in scalar registers
+  const int32_t lo = __builtin_amdgcn_readfirstlane(reach[0]);
+  const int64_t span = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(reach[1])) - lo;
   // the whole row when a source reaches far or the stretch would be as long; else the
   // stretch [lo, lo + span) (lo >= -n_g, lo + span <= 2 n_g)
-  const bool wrap = reach[2] != 0 || span > ng + kNuWidth;
+  const bool wrap = __builtin_amdgcn_readfirstlane(reach[2]) != 0 || span > ng + kNuWidth;
   const int rc0 = wrap ? r.cell : r.cell - lo;
   const int n_stage = wrap ? ng + kNuWidth : static_cast<int>(span);
   const int s_base = wrap ? 0 : (lo % ng + ng) % ng;  // grid cell of the first staged one
-  for (int o = 0; o < O; ++o) {
-    __syncthreads();  // the previous channel's row is no longer read
-    for (int l = threadIdx.x; l < n_stage; l += blockDim.x) {
-      int c = s_base + l;  // < 2 n_g + kNuWidth
-      c -= (c >= ng) ? ng : 0;
-      c -= (c >= ng) ? ng : 0;
-      nu_row[l] = grow[static_cast<int64_t>(o) * ng + c];
-    }
-    __syncthreads();
+  // as many channels' rows per staging (and barrier pair) as kNuGatherStage cells hold
+  const int per_stage = max(1, min(O, kNuGatherStage / n_stage));
+  for (int o0 = 0; o0 < O; o0 += per_stage) {
+  const int nch = min(per_stage, O - o0);
+  __syncthreads();  // the previous channels' rows are no longer read
+  for (int i = threadIdx.x; i < nch * n_stage; i += blockDim.x) {
+    const int ch = i / n_stage, l = i - ch * n_stage;
+    int c = s_base + l;  // < 2 n_g + kNuWidth
+    c -= (c >= ng) ? ng : 0;
+    c -= (c >= ng) ? ng : 0;
+    nu_row[i] = grow[static_cast<int64_t>(o0 + ch) * ng + c];
+  }
+  __syncthreads();
+  for (int o = o0; o < o0 + nch; ++o) {
+    const float2 *row = nu_row + (o - o0) * n_stage;
     // this channel's element offsets from the phase centres (wave-uniform)
     const int p = o / rc.Q, q = o - p * rc.Q;
     double at[3], ar[3];
@@ -1220,7 +1230,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
       float2 mu[2];
-      row_moments<2>(nu_row, ng, wrap, rc0, x - offp[j], nc, q_ratio, mu);
+      row_moments<2>(row, ng, wrap, rc0, x - offp[j], nc, q_ratio, mu);
       const float2 ys = cmul(wp[j], mu[0]);
       const float2 yxs = cmul(wp[j], make_float2(mu[1].x * inv_s2, mu[1].y * inv_s2));
       y.x += ys.x;
@@ -1235,7 +1245,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     }
     if (CLS == 1) {
       float2 mu[4];
-      row_moments<4>(nu_row, ng, wrap, rc0, x - offq, nc, q_ratio, mu);
+      row_moments<4>(row, ng, wrap, rc0, x - offq, nc, q_ratio, mu);
       float2 yp = {0.0f, 0.0f}, yxp = {0.0f, 0.0f};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -1275,6 +1285,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
       const float eq = (static_cast<float>(ar[k]) - r.rr * urf[k]) * irr;
       acc_c[k] -= ct * ep + cr * eq;
     }
+  }
   }
   if (!on) return;
   // dL/dbeta_v = Re sum (d param / d beta_v) (its sum) - Re sum (d off / d beta_v) sum dy/dx
@@ -1387,11 +1398,11 @@ hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const 
   const auto *ders = static_cast<const NuDerF *>(nb.sder);
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<0>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * (ns.ng + kNuWidth), s, sc, rc, ns, elem, recs, ders,
+                     dim3(kNuGatherRecs), sizeof(float2) * kNuGatherStage, s, sc, rc, ns, elem, recs, ders,
                      nb.order, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<1>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * (ns.ng + kNuWidth), s, sc, rc, ns, elem, recs, ders,
+                     dim3(kNuGatherRecs), sizeof(float2) * kNuGatherStage, s, sc, rc, ns, elem, recs, ders,
                      nb.order, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
