@@ -1834,7 +1834,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   nb.n_runs = reinterpret_cast<int32_t *>(b + off_counts);
   void *tw = twiddles(ctx, ns.ng, 0, &rc);
   if (rc) return rc;
-  HIP_TRY(ctx, launch_fill_zero(ctx->adj_partial, N * F * kAdjSlotFloats, s));
+  // every lit (chirp, facet) slot of adj_partial is written by the preparation (zero-area
+  // facets) or a gather, and facet_grad reads lit slots only: no clearing
   ns.rec_stride = stride;
   for (int64_t n0 = 0; n0 < N; n0 += chunk) {
     ns.n0 = static_cast<int32_t>(n0);

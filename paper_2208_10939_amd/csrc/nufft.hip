@@ -842,9 +842,10 @@ constexpr double kNuDerStep = 1e-6;  // metres: central differences of the sourc
 size_t nufft_der_bytes() { return sizeof(NuDerF); }
 
 // Adjoint preparation, one thread per (chirp, lit facet): the forward record and the
-// derivatives of its sources by central differences in FP64 with the source form held
-// (step kNuDerStep; every form is analytic in the node offsets: truncation
-// ~ (k_c h)^2 / 6 ~ 5e-7, rounding ~ 1e-10 relative), both in entry order; the facet's
+// derivatives of its sources in FP64 with the source form held (closed form for three
+// points; central differences for the others, step kNuDerStep: every form is analytic in
+// the node offsets, truncation ~ (k_c h)^2 / 6 ~ 5e-7, rounding ~ 1e-10 relative), both in
+// entry order; the facet's
 // entry is appended to its chirp's list of three-point records (class 0) or of the others
 // (class 1), so that a gather wave meets one kind of record, with the record's cell beside
 // it (nb.pos). A zero-area facet gets a zero slot here and no list entry.
@@ -879,16 +880,45 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
     NuDerF *der = static_cast<NuDerF *>(nb.sder) + at;
     der->item = item;
     der->pad = 0;
-    const double h2 = 0.5 / kNuDerStep;
-    for (int v = 0; v < 3; ++v) {
-      double bp[3] = {g.beta[0], g.beta[1], g.beta[2]}, bm[3] = {g.beta[0], g.beta[1], g.beta[2]};
-      bp[v] += kNuDerStep;
-      bm[v] -= kNuDerStep;
-      double sp[10], sm[10];
-      nufft_fill(g, bp, ns, kind, far, sp);
-      nufft_fill(g, bm, ns, kind, far, sm);
+    if (kind == 1) {
+      // three points: s[3v] = kappa beta_v and w_v = C exp(j k_c beta_v) / prod_{u != v}
+      // (beta_v - beta_u) (s[3v + 1], s[3v + 2]) have closed-form derivatives:
+      // dw_v/dbeta_v = w_v (j k_c - sum_{u != v} 1 / (beta_v - beta_u)),
+      // dw_v/dbeta_u = w_v / (beta_v - beta_u)
+      const double kc = 2.0 * kPi * ns.fc / kC0;
+      const double *b = g.beta;
+      for (int u = 0; u < 3; ++u) {
+        double d[10];
+        d[9] = 0.0;
+        for (int v = 0; v < 3; ++v) {
+          const double wr = sd[3 * v + 1], wi = sd[3 * v + 2];
+          d[3 * v] = u == v ? ns.kappa : 0.0;
+          if (u == v) {
+            const int a = v == 0 ? 1 : 0, c = v == 2 ? 1 : 2;
+            const double fr = -(1.0 / (b[v] - b[a]) + 1.0 / (b[v] - b[c]));
+            d[3 * v + 1] = wr * fr - wi * kc;
+            d[3 * v + 2] = wr * kc + wi * fr;
+          } else {
+            const double f = 1.0 / (b[v] - b[u]);
+            d[3 * v + 1] = wr * f;
+            d[3 * v + 2] = wi * f;
+          }
+        }
 #pragma unroll
-      for (int k = 0; k < 10; ++k) der->ds[v][k] = static_cast<float>((sp[k] - sm[k]) * h2);
+        for (int k = 0; k < 10; ++k) der->ds[u][k] = static_cast<float>(d[k]);
+      }
+    } else {
+      const double h2 = 0.5 / kNuDerStep;
+      for (int v = 0; v < 3; ++v) {
+        double bp[3] = {g.beta[0], g.beta[1], g.beta[2]}, bm[3] = {g.beta[0], g.beta[1], g.beta[2]};
+        bp[v] += kNuDerStep;
+        bm[v] -= kNuDerStep;
+        double sp[10], sm[10];
+        nufft_fill(g, bp, ns, kind, far, sp);
+        nufft_fill(g, bm, ns, kind, far, sm);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) der->ds[v][k] = static_cast<float>((sp[k] - sm[k]) * h2);
+      }
     }
     if (kind == 0) {
       float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + item) * kAdjVals;
