@@ -656,13 +656,20 @@ const char *nufft_ineligible(const rsim_ctx *ctx, const RadarConst &rc, const rs
   return nullptr;
 }
 
-// Why the NUFFT adjoint cannot run; *ns: its shape. Its gather reads each source's own
-// cells from a staged grid row, so no window bounds the node or channel offsets.
-const char *nufft_adj_ineligible(const rsim_ctx *ctx, const RadarConst &rc, NuShape *ns) {
+// Why the NUFFT adjoint cannot run for facets within r_max of their centroids; *ns: its
+// shape. Its gather reads each source's own cells from a staged grid row, so no run window
+// bounds the node or channel offsets; they must stay within half the grid (a source's
+// cells then lie within half a grid of its record's cell, which the gather's periodic
+// indexing assumes).
+const char *nufft_adj_ineligible(const rsim_ctx *ctx, const RadarConst &rc, double r_max,
+                                 NuShape *ns) {
   rsim_opts o{};
   o.precision = RSIM_FP32_PHASE64;
   NuShape s{};
   if (const char *why = nufft_common(ctx, rc, o, 0.0, &s)) return why;
+  if (2.0 * r_max * s.kappa + s.chan_d + 0.5 * kNuWidth + 2.0 >= 0.5 * s.ng)
+    return "facets too large for the NUFFT adjoint: node offsets (2 r_max df n_g / c) plus "
+           "channel offsets reach half the grid";
   nufft_fft_groups(ctx, rc, s, 0);
   *ns = s;
   return nullptr;
@@ -1881,7 +1888,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   bool nufft = false;
   if (!ctx->bwd_intra &&
       (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO)) {
-    const char *nwhy = nufft_adj_ineligible(ctx, rcn, &nsb);
+    const char *nwhy = nufft_adj_ineligible(ctx, rcn, scenes_rmax(ctx, {scene_id}), &nsb);
     if (nwhy && ctx->bwd_kernel == RSIM_KERNEL_NUFFT)
       return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
     nufft = !nwhy;

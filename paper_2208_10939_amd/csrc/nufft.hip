@@ -1048,7 +1048,9 @@ __device__ __forceinline__ void row_moments(const float2 *row, int ng, bool wrap
                                             float2 (&mu)[K]) {
   static_assert(K == 2 || K == 4, "moment counts used");
   const float s0 = ceilf(xs - 0.5f * kNuWidth);
-  int cell = rc0 + static_cast<int>(s0);  // with wrap in (-ng, 2 ng)
+  // with wrap in (-ng / 2, 3 ng / 2): the host keeps node and channel offsets within half
+  // the grid
+  int cell = rc0 + static_cast<int>(s0);
   cell -= (wrap && cell >= ng) ? ng : 0;
   cell += (wrap && cell < 0) ? ng : 0;
   const float2 *rp = row + cell;

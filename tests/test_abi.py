@@ -224,8 +224,9 @@ def test_nufft_refusals_host_only():
 def test_nufft_adjoint_refusals_host_only():
     """The NUFFT adjoint (rsim_set_backward_kernel(RSIM_KERNEL_NUFFT)), eligibility
     decided on the host: its gather reads each source's own cells, so coarse facets (a 4 m
-    box) are eligible and reach the missing device; a grid beyond 2048 cells (M = 1100) is
-    ERANGE, AUTO never refuses for it, and kernel codes beyond NUFFT are EINVAL."""
+    box) are eligible and reach the missing device; a grid beyond 2048 cells (M = 1100) and
+    facets reaching half the grid (a 200 m box) are ERANGE, AUTO never refuses for them, and
+    kernel codes beyond NUFFT are EINVAL."""
     ctx = _host_ctx()
     L = rsim.lib()
     wf = scenes.paper_waveform(256, 8)
@@ -254,6 +255,17 @@ def test_nufft_adjoint_refusals_host_only():
     assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_AUTO) == rsim.RSIM_OK
     assert bwd(ids[0]) == rsim.RSIM_EDEVICE
     ctx.set_waveform(wf)
+    # facets whose node offsets reach half the grid (a 200 m box): ERANGE for the NUFFT
+    # adjoint, AUTO takes another kernel
+    big = scenes.box_mesh((-100.0, -100.0, 0.0), (100.0, 100.0, 2.0), (1, 1, 1))
+    mid = ctx.load_mesh(big.verts, big.tris)
+    sid_big = ctx.create_scene()
+    ctx.add_instance(sid_big, mid, np.eye(3), np.array([2.0, 130.0, 0.0]), np.zeros(3))
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT) == rsim.RSIM_OK
+    assert bwd(sid_big) == rsim.RSIM_ERANGE
+    assert b"half the grid" in L.rsim_last_error(ctx._h)
+    assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_AUTO) == rsim.RSIM_OK
+    assert bwd(sid_big) == rsim.RSIM_EDEVICE
     assert L.rsim_set_backward_kernel(ctx._h, rsim.RSIM_KERNEL_NUFFT + 1) == rsim.RSIM_EINVAL
     assert L.rsim_set_nufft_chunk(ctx._h, -1) == rsim.RSIM_EINVAL
     assert L.rsim_set_nufft_chunk(ctx._h, 3) == rsim.RSIM_OK
