@@ -303,8 +303,10 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
                       double *grad_vel, void *hip_stream);
 
 /* Facet-sum kernel of rsim_backward (Sections 2.2, 3.2; eqs. (7), (9)-(13), differentiated):
- * RSIM_KERNEL_AUTO (default) takes the NUFFT adjoint where the forward NUFFT would be
- * eligible for the scene (see RSIM_KERNEL_NUFFT), else the matrix cores when the array
+ * RSIM_KERNEL_AUTO (default) takes the NUFFT adjoint where it is eligible for the scene
+ * (grid of at most 2048 cells; node offsets 2 r_max df n_g / c plus the array's channel
+ * offsets below half the grid, r_max the largest vertex-to-centroid distance), else the
+ * matrix cores when the array
  * allows them (the same eligibility as rsim_opts.kernel: |2 pi slope d_p e_q| <= 1e-5 rad,
  * P <= 12, Q <= 16), else the vector units; RSIM_KERNEL_VECTOR always the vector units;
  * RSIM_KERNEL_MATRIX the matrix cores and RSIM_KERNEL_NUFFT the NUFFT adjoint (a type-2
