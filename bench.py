@@ -113,6 +113,34 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def platform_info():
+    """GPU name and architecture, HIP runtime and ROCm versions, and the current and top
+    shader clocks as rocm-smi reports them (each entry null where not available)."""
+    import subprocess
+    import torch
+    info = {"gpu": None, "arch": None, "hip": getattr(torch.version, "hip", None), "rocm": None,
+            "sclk": None}
+    try:
+        prop = torch.cuda.get_device_properties(0)
+        info["gpu"] = prop.name
+        info["arch"] = getattr(prop, "gcnArchName", None)
+    except Exception:
+        pass
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            info["rocm"] = f.read().strip()
+    except OSError:
+        pass
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                           timeout=20)
+        lines = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln.lower()]
+        info["sclk"] = lines[:2] or None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
 def _src_hash(kernel="vector"):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
@@ -592,9 +620,13 @@ def main():
                    "lit_facets_per_chirp": float(lit.mean()), "seed": cfg.seed,
                    "facet_sum_kernel": kernel,
                    "facet_sum_tile": (tuned if tuned else
-                                      {"tile_m": args.tile_m, "tile_f": args.tile_f})},
+                                      {"tile_m": args.tile_m, "tile_f": args.tile_f}),
+                   # every facet of every chirp, lit or not: F M O N
+                   "nominal_evals_per_step": int(sc.n_tris) * wf.n_samples * arr.n_channels *
+                                             wf.n_chirps},
         "stage_ms": stage_avg,
         "roofline": rl,
+        "platform": platform_info(),
     }
     if not args.no_extras:
         out["other_kernels"] = []
