@@ -232,6 +232,32 @@ def connection_table(pairs, n_facets: int) -> np.ndarray:
     return t
 
 
+def pairs_for_table(scene, array, wf, table: np.ndarray, chirps=None):
+    """The connections of a given table ([2, n_chirps, F] from connection_table: launching
+    end k, chirp, facet A -> facet B or -1) with their geometry taken from the scene as it
+    is (steps 4 and 5 without the decisions of steps 1-4): for each kept (A, B) the image
+    E' of the launching phase centre in A's plane and the footprint of A's vertices
+    projected from E' onto B's plane, ordered to B's normal. The same dicts as
+    double_bounce_pairs (without the ambiguity fields), for synthesize_double; with the
+    scene perturbed and the table held, the echo is a smooth function of the vertices."""
+    tx_c = np.asarray(array.tx, np.float64).mean(axis=0)
+    rx_c = np.asarray(array.rx, np.float64).mean(axis=0)
+    chirps = np.arange(wf.n_chirps) if chirps is None else np.asarray(chirps)
+    out = []
+    for ni, n in enumerate(chirps):
+        tri, _, _ = world_triangles(scene, float(n) * wf.chirp_period)
+        c, nrm, _ = facet_frames(tri)
+        per = {}
+        for k, E in enumerate((tx_c, rx_c)):
+            A = np.nonzero(table[k, ni] >= 0)[0]
+            B = table[k, ni, A].astype(np.int64)
+            E_img = np.array([mirror_points(E, c[a], nrm[a]) for a in A]).reshape(-1, 3)
+            Ft, _, _ = footprints(tri[A], E_img, c[B], nrm[B])
+            per[k] = {"A": A, "B": B, "F": Ft, "plane_p": c[A], "plane_n": nrm[A]}
+        out.append(per)
+    return out
+
+
 def synthesize_double(scene, wf, array, gamma: complex = -1.0, pairs=None, chirps=None,
                       channels=None, samples=None):
     """Double-bounce echo H[o, n, m]: gamma / 2 times the footprint terms of the

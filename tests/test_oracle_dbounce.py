@@ -11,6 +11,8 @@ joined on a facet after a reflection; eqs. (7), (9)-(13) for the facet term).
 * The first-hit search against hand-made triangles.
 * Planted mistakes (sign of the reflection, images in a tilted plane, both ends counted
   in full) each fail the closed form.
+* pairs_for_table (geometry of a held connection table) reproduces the connection search's
+  footprints, planes and echo on the scene the table came from, and follows a moved vertex.
 """
 import numpy as np
 import pytest
@@ -139,3 +141,41 @@ def test_planted_mistakes_fail_the_closed_form(monkeypatch):
     H2 = 2.0 * dbounce.synthesize_double(sc, wf, arr)[0, 0]
     Hp = oracle.synthesize(scenes.plate_scene(0.3, np.sqrt(2.0) * 0.2, 1, 1, 1e6), wf, arr)[0, 0]
     assert not np.allclose(np.abs(H2) / np.abs(Hp), 1.0, rtol=1e-2)
+
+
+def test_pairs_for_table_reproduces_the_search():
+    sc, wf, arr = _vehicle_case()
+    pairs = dbounce.double_bounce_pairs(sc, arr, wf)
+    F = sum(m.tris.shape[0] for m in [sc.meshes[i.mesh] for i in sc.instances])
+    table = dbounce.connection_table(pairs, F)
+    held = dbounce.pairs_for_table(sc, arr, wf, table)
+    n_conn = 0
+    for ni in range(wf.n_chirps):
+        for k in (0, 1):
+            a, b = pairs[ni][k], held[ni][k]
+            order = np.argsort(a["A"])
+            assert np.array_equal(a["A"][order], b["A"])
+            assert np.array_equal(a["B"][order], b["B"])
+            assert np.array_equal(a["F"][order], b["F"])
+            assert np.array_equal(a["plane_n"][order], b["plane_n"])
+            n_conn += b["A"].size
+    assert n_conn > 10
+    H = dbounce.synthesize_double(sc, wf, arr, pairs=pairs)
+    Hh = dbounce.synthesize_double(sc, wf, arr, pairs=held)
+    assert np.max(np.abs(H - Hh)) <= 1e-12 * np.max(np.abs(H))
+    # a vertex of a connected facet B moved off B's plane (along its normal, in the body
+    # frame) moves the footprint with it
+    ni, k = 0, 0
+    B0 = held[ni][k]["B"][0]
+    tri, inst_of, local_of = oracle.world_triangles(sc, 0.0)
+    inst = sc.instances[inst_of[B0]]
+    mesh = sc.meshes[inst.mesh]
+    v = int(mesh.tris[local_of[B0], 0])
+    _, nrm, _ = oracle.facet_frames(tri[B0][None])
+    verts = mesh.verts.astype(np.float64).copy()
+    verts[v] += 1e-3 * (np.asarray(inst.rot, np.float64).T @ nrm[0])
+    from scenes import Mesh, Scene
+    meshes = [Mesh(verts=verts, tris=m.tris, name=m.name) if m is mesh else m for m in sc.meshes]
+    moved = dbounce.pairs_for_table(Scene(meshes, sc.instances), arr, wf, table)
+    dF = np.abs(moved[ni][k]["F"][0] - held[ni][k]["F"][0]).max()
+    assert 0.0 < dF < 1e-2
