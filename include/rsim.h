@@ -215,8 +215,9 @@ int32_t rsim_set_ground(rsim_ctx *ctx, int32_t enable, double z_ground, double g
  * int32: for the ray launched from the Tx (first plane) or Rx (second) end at chirp n and
  * facet A, the facet B it connects to, or -1 (output with RSIM_MASK_COMPUTE, input with
  * RSIM_MASK_INPUT; a given entry outside 0 .. F-1 means no connection). rsim_backward
- * returns ESTATE and
- * rsim_autotune ESTATE while it is on. EINVAL for enable not 0/1 or a non-finite gamma.
+ * differentiates the connections with the table held (the NUFFT adjoint only: see there);
+ * rsim_autotune fails with ESTATE while it is on. EINVAL for enable not 0/1 or a
+ * non-finite gamma.
  * Device memory: 16 N F + 8 N bytes per scene for the connections. */
 int32_t rsim_set_double_bounce(rsim_ctx *ctx, int32_t enable, double gamma_re, double gamma_im);
 
@@ -288,11 +289,22 @@ int32_t rsim_last_census(rsim_ctx *ctx, int64_t counts[4]);
 /* Gradient of a real loss L through the echo of one scene (FP32 path), with the
  * lit-facet mask held fixed and chirps recomputed rather than stored (stop-and-hop
  * geometry, or the delay within the chirp after rsim_set_backward_intra_chirp(ctx, 1);
- * with the ground plane on, all four path types; ESTATE while the facet-to-facet double
- * bounce is on).
+ * with the ground plane on, all four path types).
+ * With the facet-to-facet double bounce on, the connections too, their table held: each
+ * connection's adjoint sums (its footprint's node offsets and amplitude, and the distance
+ * from every channel element, the launching side's mirrored in A's plane) are carried
+ * through the footprint construction to the vertices of A and B, whose derivatives are
+ * taken by FP64 central differences (step 1e-6 m); those gradients are added with FP64
+ * atomics, so their last bits depend on arrival order. That runs in the NUFFT adjoint,
+ * stop-and-hop, without the ground plane and for at most 32 Tx + Rx elements: EINVAL with
+ * the ground plane, rsim_set_backward_intra_chirp(ctx, 1) or a backward kernel of
+ * RSIM_KERNEL_VECTOR / MATRIX; ERANGE where the NUFFT adjoint is ineligible or for more
+ * elements. Device memory: 144 F bytes and, per chirp of a chunk, 2 F (32 + 4 (P + Q))
+ * bytes beside the NUFFT adjoint's work, whose record lists grow to 3 F entries.
  *   grad_echo  DEVICE [O][N][M] complex64: dL/dRe(H) + j dL/dIm(H)
  *   vis_mask   DEVICE mask of that scene from the forward call (N * mask_words; four
- *              sets with the ground plane)
+ *              sets with the ground plane; with the double bounce followed by the
+ *              connection table [2][N][F] int32 of that call)
  *   grad_verts host array of n_meshes DEVICE pointers, each [n_verts][3] float32 of
  *              the scene's meshes in mesh-id order (NULL entries skipped); dL/dx_body
  *              summed over the instances of each mesh, ACCUMULATED into the buffers.
@@ -314,7 +326,8 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
  * channel's grid, then Gaussian-weighted moments gathered per lit facet), rsim_backward then
  * failing with ERANGE where ineligible. EINVAL for another value. All give the same
  * gradients to FP32 rounding, the dropped cross term and the NUFFT's error (relative
- * <= 1e-5); all three are deterministic (a fixed order of operations, no atomics). */
+ * <= 1e-5); all three are deterministic (a fixed order of operations, no atomics) except
+ * for the double bounce's connections (rsim_backward). */
 int32_t rsim_set_backward_kernel(rsim_ctx *ctx, int32_t kernel);
 
 /* Which forward rsim_backward differentiates (Section 3.2, eq. (12) at the sample times):

@@ -535,7 +535,8 @@ __global__ void fill_zero_kernel(float *p, int64_t n) {
 // corner (the vertex gather adds the three corners back up for the velocity).
 __global__ void __launch_bounds__(256) facet_chirp_sum_kernel(const float *gxw, const float *gxv,
                                                               int64_t n_facets, int N, double tc,
-                                                              double *gsum, double *gtsum) {
+                                                              double *gsum, double *gtsum,
+                                                              const double *dbsum) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= n_facets * 9) return;
   const int64_t f = idx / 9;
@@ -546,6 +547,10 @@ __global__ void __launch_bounds__(256) facet_chirp_sum_kernel(const float *gxw, 
     g += v;
     gt += (n * tc) * v;
     if (gxv) gt += gxv[(static_cast<int64_t>(n) * n_facets + f) * 3 + axis] * (1.0 / 3.0);
+  }
+  if (dbsum) {  // the double-bounce connections' sums over chirps (plain, t_n-weighted)
+    g += dbsum[idx];
+    gt += dbsum[n_facets * 9 + idx];
   }
   gsum[idx] = g;
   gtsum[idx] = gt;
@@ -663,11 +668,12 @@ hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, do
 }
 
 hipError_t launch_facet_chirp_sum(const float *gxw, const float *gxv, int64_t n_facets, int N,
-                                  double tc, double *gsum, double *gtsum, hipStream_t s) {
+                                  double tc, double *gsum, double *gtsum, hipStream_t s,
+                                  const double *dbsum) {
   if (n_facets > 0) {
     const int64_t n = n_facets * 9;
     hipLaunchKernelGGL(facet_chirp_sum_kernel, dim3(static_cast<unsigned>((n + 255) / 256)),
-                       dim3(256), 0, s, gxw, gxv, n_facets, N, tc, gsum, gtsum);
+                       dim3(256), 0, s, gxw, gxv, n_facets, N, tc, gsum, gtsum, dbsum);
   }
   return hipGetLastError();
 }

@@ -137,6 +137,9 @@ struct rsim_ctx {
   // velocity sums of that adjoint: per (chirp, lit facet, slot) [4] and per facet [N][F][3]
   void *adj_pv = nullptr, *adj_gxv = nullptr;
   size_t adj_pv_bytes = 0, adj_gxv_bytes = 0;
+  // double-bounce adjoint: the connections' per-facet chirp sums [2][F][9] FP64
+  void *adj_dbsum = nullptr;
+  size_t adj_dbsum_bytes = 0;
   // adjoint work buffers
   float *adj_partial = nullptr, *adj_gxw = nullptr;
   double *adj_vpart = nullptr, *adj_gsum = nullptr;  // gsum: [2][F][9] (plain, t_n-weighted)
@@ -1801,25 +1804,34 @@ int32_t rsim_synthesize(rsim_ctx *ctx, const int32_t *scene_ids, int32_t n_scene
 // their cells and the lists ordered by cell [chunk][2][facet records], grids [chunk][O][n_g].
 static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const RadarConst &rcn,
                                      const double *elem, NuShape ns, const void *grad_echo,
-                                     bool accumulate, hipStream_t s) {
+                                     bool accumulate, hipStream_t s, double *dbsum = nullptr,
+                                     double *dbtsum = nullptr) {
   DevScene d = d_in;
   d.n_points = 0;  // points carry no parameters
   const int64_t F = d.n_facets, N = rcn.N, O = static_cast<int64_t>(rcn.P) * rcn.Q;
-  const int64_t stride = std::max<int64_t>(1, F);
+  const int64_t E = rcn.P + rcn.Q;
+  const bool db = d.db_on != 0;
+  // entries per chirp: the lit facets, then (double bounce) up to 2 F connections
+  const int64_t stride = std::max<int64_t>(1, db ? 3 * F : F);
+  const int64_t db_stride = db ? std::max<int64_t>(1, 2 * F) : 0;
+  const int64_t ncls = db ? 4 : 2;
   const size_t rec_b = nufft_record_bytes(false), der_b = nufft_der_bytes();
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t per_chirp = stride * (rec_b + der_b + 24) + 8 + O * ns.ng * 8;
+  const size_t per_chirp = stride * (rec_b + der_b + 12 * ncls) + 4 * ncls + O * ns.ng * 8 +
+                           db_stride * (kAdjSlotFloats + E) * 4;
   int64_t chunk = std::max<int64_t>(
       1, std::min<int64_t>(N, nufft_budget(ctx, ctx->nu_adj_bytes) / per_chirp));
   if (ctx->nu_chunk_max > 0) chunk = std::min<int64_t>(chunk, ctx->nu_chunk_max);
   const size_t off_srec = 0;
   const size_t off_sder = off_srec + al(chunk * stride * rec_b);
   const size_t off_lists = off_sder + al(chunk * stride * der_b);
-  const size_t off_cells = off_lists + al(chunk * 2 * stride * 4);
-  const size_t off_order = off_cells + al(chunk * 2 * stride * 4);
-  const size_t off_counts = off_order + al(chunk * 2 * stride * 4);
-  const size_t off_grid = off_counts + al(chunk * 2 * 4);
-  const size_t total = off_grid + chunk * O * ns.ng * 8;
+  const size_t off_cells = off_lists + al(chunk * ncls * stride * 4);
+  const size_t off_order = off_cells + al(chunk * ncls * stride * 4);
+  const size_t off_counts = off_order + al(chunk * ncls * stride * 4);
+  const size_t off_grid = off_counts + al(chunk * ncls * 4);
+  const size_t off_pdb = off_grid + al(chunk * O * ns.ng * 8);
+  const size_t off_eldb = off_pdb + al(chunk * db_stride * kAdjSlotFloats * 4);
+  const size_t total = off_eldb + chunk * db_stride * E * 4;
   int32_t rc = RSIM_OK;
   if (ctx->nu_adj_bytes < total) {
     HIP_TRY(ctx, hipDeviceSynchronize());  // earlier launches may still use the buffer
@@ -1839,6 +1851,11 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
   nb.rec_bytes = rec_b;
   nb.sder = b + off_sder;
   nb.n_runs = reinterpret_cast<int32_t *>(b + off_counts);
+  if (db) {
+    nb.part_db = reinterpret_cast<float *>(b + off_pdb);
+    nb.el_db = reinterpret_cast<float *>(b + off_eldb);
+    nb.db_stride = db_stride;
+  }
   void *tw = twiddles(ctx, ns.ng, 0, &rc);
   if (rc) return rc;
   // every lit (chirp, facet) slot of adj_partial is written by the preparation (zero-area
@@ -1849,7 +1866,8 @@ static int32_t enqueue_nufft_adjoint(rsim_ctx *ctx, const DevScene &d_in, const 
     ns.n_chirps = static_cast<int32_t>(std::min<int64_t>(chunk, N - n0));
     HIP_TRY(ctx, launch_nufft_adjoint(d, rcn, elem, ns, nb, tw, grad_echo,
                                       ctx->adj_partial, s,
-                                      kernel_events(ctx, ctx->timing_pending, kKernelStage0 + 1)));
+                                      kernel_events(ctx, ctx->timing_pending, kKernelStage0 + 1),
+                                      dbsum, dbtsum));
   }
   EchoShape sh{};
   sh.O = static_cast<int32_t>(O);
@@ -1870,9 +1888,18 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   int32_t rc = check_radar(ctx);
   if (rc) return rc;
   if ((rc = check_scene(ctx, scene_id))) return rc;
-  if (ctx->dbounce)
-    return fail(ctx, RSIM_ESTATE, "rsim_backward: the adjoint covers the single-bounce path and "
-                "the ground bounce; disable the double bounce (rsim_set_double_bounce) first");
+  if (ctx->dbounce) {
+    // the connections' chain rule runs in the NUFFT adjoint, stop-and-hop
+    if (ctx->ground || ctx->bwd_intra)
+      return fail(ctx, RSIM_EINVAL, "rsim_backward: the facet-to-facet double bounce runs "
+                  "stop-and-hop and without the ground plane");
+    if (ctx->bwd_kernel == RSIM_KERNEL_VECTOR || ctx->bwd_kernel == RSIM_KERNEL_MATRIX)
+      return fail(ctx, RSIM_EINVAL, "rsim_backward: the facet-to-facet double bounce is "
+                  "differentiated by the NUFFT adjoint (backward kernel AUTO or NUFFT)");
+    if ((ctx->tx.size() + ctx->rx.size()) / 3 > static_cast<size_t>(kNuDbMaxElems))
+      return fail(ctx, RSIM_ERANGE, "rsim_backward: the double-bounce adjoint keeps one LDS "
+                  "column per element: at most %d Tx + Rx elements", kNuDbMaxElems);
+  }
   if (ctx->bwd_intra &&
       (ctx->bwd_kernel == RSIM_KERNEL_MATRIX || ctx->bwd_kernel == RSIM_KERNEL_NUFFT))
     return fail(ctx, RSIM_EINVAL, "rsim_backward: the adjoint with the delay within the chirp "
@@ -1889,7 +1916,7 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   if (!ctx->bwd_intra &&
       (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->bwd_kernel == RSIM_KERNEL_AUTO)) {
     const char *nwhy = nufft_adj_ineligible(ctx, rcn, scenes_rmax(ctx, {scene_id}), &nsb);
-    if (nwhy && ctx->bwd_kernel == RSIM_KERNEL_NUFFT)
+    if (nwhy && (ctx->bwd_kernel == RSIM_KERNEL_NUFFT || ctx->dbounce))
       return fail(ctx, RSIM_ERANGE, "rsim_backward: %s", nwhy);
     nufft = !nwhy;
   }
@@ -1969,6 +1996,25 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   DevScene d = dev_scene(sc, const_cast<uint32_t *>(vis_mask), nullptr);
+  double *dbsum = nullptr, *dbtsum = nullptr;
+  if (ctx->dbounce) {
+    // the connection table follows the mask words in the caller's buffer; its lists are
+    // rebuilt here, and the connections' chain rule adds into per-facet FP64 sums
+    if (!sc.d_db) return fail(ctx, RSIM_ESTATE, "rsim_backward: no connection table");
+    const int64_t plane = 2 * static_cast<int64_t>(rcn.N) * std::max<int64_t>(1, sc.n_facets);
+    d.db_on = 1;
+    d.db_b = reinterpret_cast<const int32_t *>(vis_mask + static_cast<int64_t>(rcn.N) * d.mask_words);
+    d.db_idx = sc.d_db + plane;
+    d.db_cnt = sc.d_db + 2 * plane;
+    d.db_gamma_re = ctx->db_gamma_re;
+    d.db_gamma_im = ctx->db_gamma_im;
+    d.db_n = rcn.N;
+    const size_t need = sizeof(double) * 2 * 9 * static_cast<size_t>(std::max<int64_t>(1, F));
+    if ((rc = grow_bytes(ctx, &ctx->adj_dbsum, &ctx->adj_dbsum_bytes, need))) return rc;
+    dbsum = static_cast<double *>(ctx->adj_dbsum);
+    dbtsum = dbsum + 9 * std::max<int64_t>(1, F);
+    HIP_TRY(ctx, launch_fill_zero(reinterpret_cast<float *>(dbsum), 2 * 2 * 9 * std::max<int64_t>(1, F), s));
+  }
   const bool timing = ctx->timing_pending;
   // With the ground plane the forward added four path types (their own masks, mirrored
   // elements and gamma per bounce); the adjoint runs each with the echo gradient times
@@ -1991,6 +2037,13 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
     DevScene dk = d;
     dk.mask = d.mask + static_cast<int64_t>(k) * rcn.N * d.mask_words;
     HIP_TRY(ctx, launch_compact(dk, 0, rcn.N, s));
+    if (dk.db_on) {
+      const int64_t plane = 2 * static_cast<int64_t>(rcn.N) * std::max<int64_t>(1, dk.n_facets);
+      int32_t *work = const_cast<int32_t *>(dk.db_idx) - plane;
+      HIP_TRY(ctx, launch_dbounce(dk, rcn, 0.0, scenes_rmax(ctx, {scene_id}),
+                                  const_cast<int32_t *>(dk.db_b), work + plane, work + 2 * plane,
+                                  s));
+    }
     RadarConst rk = rcn;
     if (k & 1) rk.tx_c[2] = 2.0 * ctx->z_ground - rcn.tx_c[2];
     if (k >> 1) rk.rx_c[2] = 2.0 * ctx->z_ground - rcn.rx_c[2];
@@ -2010,7 +2063,8 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
     EchoShape sk = sh;
     sk.accumulate = k ? 1 : 0;
     if (nufft) {
-      if ((rc = enqueue_nufft_adjoint(ctx, dk, rk, elem, nsb, gk, k > 0, s))) return rc;
+      if ((rc = enqueue_nufft_adjoint(ctx, dk, rk, elem, nsb, gk, k > 0, s, dbsum, dbtsum)))
+        return rc;
     } else if (matrix)
       HIP_TRY(ctx, launch_adjoint_mfma(dk, rk, elem, sk, gk, ctx->adj_partial, ctx->adj_gxw, s));
     else
@@ -2019,7 +2073,8 @@ int32_t rsim_backward(rsim_ctx *ctx, int32_t scene_id, const void *grad_echo,
   stage_end(ctx, timing, 5, s);
   stage_begin(ctx, timing, 7, s);
   double *gsum = ctx->adj_gsum, *gtsum = ctx->adj_gsum + 9 * F;
-  HIP_TRY(ctx, launch_facet_chirp_sum(ctx->adj_gxw, gxv, F, rcn.N, rcn.tc, gsum, gtsum, s));
+  HIP_TRY(ctx, launch_facet_chirp_sum(ctx->adj_gxw, gxv, F, rcn.N, rcn.tc, gsum, gtsum, s,
+                                      dbsum));
   for (size_t i = 0; i < sc.inst.size(); ++i) {
     const InstRec &r = sc.inst[i];
     const MeshRec &m = ctx->meshes[r.mesh];

@@ -357,72 +357,67 @@ __device__ int nufft_sources(const Geo &g, const NuShape &ns, float s[10]) {
 }
 
 
-// Geometry of facet-sum entry `item` of chirp n and the phase centres its path starts
-// from: a lit facet or a point (entry_geometry, rc_e = rc, *side = -1), or a facet-to-facet
-// double-bounce connection (A, B) launched from end *side (0 Tx, 1 Rx): the footprint of
-// A's reflected tube on B's plane (central projection from the image E' of that end's
-// phase centre in A's plane, ordered to B's normal) as the facet, that centre replaced by
-// E' in rc_e, gamma / 2 in the amplitude (the connection is one of the two evaluations of
-// its path), and A's unit normal in refl: the mirror that maps that end's channel offsets
-// to the image elements' (distances from image elements are those of the folded path).
-__device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int32_t cnt,
-                            int32_t item, Geo &g, RadarConst &rc_e, double refl[3], int *side) {
-  rc_e = rc;
-  refl[0] = refl[1] = refl[2] = 0.0;
-  *side = -1;
-  const int32_t base = cnt + sc.n_points;
-  if (!sc.db_on || item < base) {
-    entry_geometry(sc, rc, n, cnt, item, g);
-    return;
-  }
-  int32_t j = item - base;
-  int k = 0;
+// Connection j (0-based among chirp n's connections, both launching ends) of the
+// facet-to-facet double bounce: its launching end k (0 Tx, 1 Rx), facet A it reflects off
+// and facet B it meets.
+__device__ inline void db_connection(const DevScene &sc, int n, int32_t j, int *k, int64_t *fa,
+                                     int64_t *fb) {
+  *k = 0;
   const int32_t c0 = sc.db_cnt[n];
   if (j >= c0) {
-    k = 1;
+    *k = 1;
     j -= c0;
   }
-  const int64_t row = (static_cast<int64_t>(k) * sc.db_n + n) * sc.n_facets;
-  const int64_t fa = sc.db_idx[row + j];
-  const int64_t fb = sc.db_b[row + fa];
-  const double t = n * rc.tc;
-  double xa[3][3], xb[3][3];
-  for (int w = 0; w < 2; ++w) {
-    const int64_t f = w ? fb : fa;
-    const DevInstance &I = sc.inst[find_inst(sc.inst, sc.n_inst, f)];
-    const int64_t lt = f - I.facet_base;
-    for (int v = 0; v < 3; ++v) {
-      const int32_t vi = I.tris[3 * lt + v];
-      const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
-      for (int q = 0; q < 3; ++q) {
-        const double x = I.rot[3 * q + 0] * b0 + I.rot[3 * q + 1] * b1 + I.rot[3 * q + 2] * b2 +
-                         (I.pos0[q] + I.vel[q] * t);
-        (w ? xb : xa)[v][q] = x;
-      }
-    }
+  const int64_t row = (static_cast<int64_t>(*k) * sc.db_n + n) * sc.n_facets;
+  *fa = sc.db_idx[row + j];
+  *fb = sc.db_b[row + *fa];
+}
+
+// World vertices of scene facet f at time t (FP64).
+__device__ inline void facet_world(const DevScene &sc, int64_t f, double t, double x[3][3]) {
+  const DevInstance &I = sc.inst[find_inst(sc.inst, sc.n_inst, f)];
+  const int64_t lt = f - I.facet_base;
+  for (int v = 0; v < 3; ++v) {
+    const int32_t vi = I.tris[3 * lt + v];
+    const double b0 = I.verts[3 * vi + 0], b1 = I.verts[3 * vi + 1], b2 = I.verts[3 * vi + 2];
+    for (int q = 0; q < 3; ++q)
+      x[v][q] = I.rot[3 * q + 0] * b0 + I.rot[3 * q + 1] * b1 + I.rot[3 * q + 2] * b2 +
+                (I.pos0[q] + I.vel[q] * t);
   }
-  auto unit_normal = [](const double x[3][3], double nrm[3], double c[3]) {
-    double e1[3], e2[3];
-    for (int q = 0; q < 3; ++q) {
-      c[q] = (x[0][q] + x[1][q] + x[2][q]) * (1.0 / 3.0);
-      e1[q] = x[1][q] - x[0][q];
-      e2[q] = x[2][q] - x[0][q];
-    }
-    nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
-    nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
-    nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
-    const double a = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
-    for (int q = 0; q < 3; ++q) nrm[q] /= a;
-  };
-  double na[3], ca[3], nb[3], cb[3];
+}
+
+// Centroid c and unit normal of a world triangle.
+__device__ inline void unit_normal(const double x[3][3], double nrm[3], double c[3]) {
+  double e1[3], e2[3];
+  for (int q = 0; q < 3; ++q) {
+    c[q] = (x[0][q] + x[1][q] + x[2][q]) * (1.0 / 3.0);
+    e1[q] = x[1][q] - x[0][q];
+    e2[q] = x[2][q] - x[0][q];
+  }
+  nrm[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  nrm[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  nrm[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double a = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);
+  for (int q = 0; q < 3; ++q) nrm[q] /= a;
+}
+
+// The footprint of a connection launched from end k (0: E is the Tx phase centre, 1: the
+// Rx one) from world triangles xa (A) and xb (B) and the launching and other phase
+// centres E and O: the image ei of E in A's plane, A's unit normal na, the
+// footprint x (central projection from ei of A's vertices onto B's plane, ordered to B's
+// normal) as the facet of g (centroid, node offsets along w = unit vectors to ei and O,
+// amplitude gamma / 2 times j o A / (2 pi), reference delays), and the footprint's
+// centroid in c (also g.c). Shared by the forward entry and the adjoint's chain rule.
+__device__ inline void db_footprint(const double xa[3][3], const double xb[3][3],
+                                    const double E[3], const double O[3], int k,
+                                    double gamma_re, double gamma_im, Geo &g, double ei[3],
+                                    double na[3], double x[3][3], double *xo_out = nullptr) {
+  double ca[3], nb[3], cb[3];
   unit_normal(xa, na, ca);
   unit_normal(xb, nb, cb);
-  const double *E = k ? rc.rx_c : rc.tx_c;
   const double fe = na[0] * (E[0] - ca[0]) + na[1] * (E[1] - ca[1]) + na[2] * (E[2] - ca[2]);
-  double ei[3];
   for (int q = 0; q < 3; ++q) ei[q] = E[q] - 2.0 * fe * na[q];
   const double num = nb[0] * (cb[0] - ei[0]) + nb[1] * (cb[1] - ei[1]) + nb[2] * (cb[2] - ei[2]);
-  double x[3][3];
   for (int v = 0; v < 3; ++v) {
     const double d0 = xa[v][0] - ei[0], d1 = xa[v][1] - ei[1], d2 = xa[v][2] - ei[2];
     const double sv = num / (nb[0] * d0 + nb[1] * d1 + nb[2] * d2);
@@ -447,19 +442,12 @@ __device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int
       nv[q] = -nv[q];
     }
   }
-  for (int q = 0; q < 3; ++q) {
-    if (k == 0)
-      rc_e.tx_c[q] = ei[q];
-    else
-      rc_e.rx_c[q] = ei[q];
-    refl[q] = na[q];
-  }
-  *side = k;
   const double two_area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  // the path's Tx-side and Rx-side centres: the image on the launching side
   double ut[3], ur[3];
   for (int q = 0; q < 3; ++q) {
-    ut[q] = rc_e.tx_c[q] - c[q];
-    ur[q] = rc_e.rx_c[q] - c[q];
+    ut[q] = (k ? O[q] : ei[q]) - c[q];
+    ur[q] = (k ? ei[q] : O[q]) - c[q];
   }
   const double rt = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
   const double rr = sqrt(ur[0] * ur[0] + ur[1] * ur[1] + ur[2] * ur[2]);
@@ -470,8 +458,9 @@ __device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int
     g.beta[v] = w[0] * (x[v][0] - c[0]) + w[1] * (x[v][1] - c[1]) + w[2] * (x[v][2] - c[2]);
   // j (o A / (2 pi)) times gamma / 2
   const double xo = two_area > 0.0 ? nw * (0.25 / (2.0 * kPi)) : 0.0;
-  g.amp_re = -0.5 * xo * sc.db_gamma_im;
-  g.amp_im = 0.5 * xo * sc.db_gamma_re;
+  if (xo_out) *xo_out = xo;
+  g.amp_re = -0.5 * xo * gamma_im;
+  g.amp_im = 0.5 * xo * gamma_re;
   g.tref_t = rt / kC0;
   g.tref_r = rr / kC0;
   for (int q = 0; q < 3; ++q) {
@@ -480,6 +469,44 @@ __device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int
   }
   g.valid = two_area > 0.0;
   g.pad = 0;
+}
+
+// Geometry of facet-sum entry `item` of chirp n and the phase centres its path starts
+// from: a lit facet or a point (entry_geometry, rc_e = rc, *side = -1), or a facet-to-facet
+// double-bounce connection (A, B) launched from end *side (0 Tx, 1 Rx): the footprint of
+// A's reflected tube on B's plane (db_footprint) as the facet, that end's phase centre
+// replaced by its image E' in rc_e, gamma / 2 in the amplitude (the connection is one of
+// the two evaluations of its path), and A's unit normal in refl: the mirror that maps that
+// end's channel offsets to the image elements' (distances from image elements are those of
+// the folded path).
+__device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int32_t cnt,
+                            int32_t item, Geo &g, RadarConst &rc_e, double refl[3], int *side) {
+  rc_e = rc;
+  refl[0] = refl[1] = refl[2] = 0.0;
+  *side = -1;
+  const int32_t base = cnt + sc.n_points;
+  if (!sc.db_on || item < base) {
+    entry_geometry(sc, rc, n, cnt, item, g);
+    return;
+  }
+  int k;
+  int64_t fa, fb;
+  db_connection(sc, n, item - base, &k, &fa, &fb);
+  const double t = n * rc.tc;
+  double xa[3][3], xb[3][3], x[3][3], ei[3], na[3];
+  facet_world(sc, fa, t, xa);
+  facet_world(sc, fb, t, xb);
+  const double *E = k ? rc.rx_c : rc.tx_c;
+  const double *O = k ? rc.tx_c : rc.rx_c;
+  db_footprint(xa, xb, E, O, k, sc.db_gamma_re, sc.db_gamma_im, g, ei, na, x);
+  for (int q = 0; q < 3; ++q) {
+    if (k == 0)
+      rc_e.tx_c[q] = ei[q];
+    else
+      rc_e.rx_c[q] = ei[q];
+    refl[q] = na[q];
+  }
+  *side = k;
 }
 
 // u minus twice its component along the unit normal nrm (a mirror image of the direction)
@@ -856,11 +883,16 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
   const int n = ns.n0 + nl;
   const int32_t cnt = sc.vis_cnt[n];
   const int32_t item = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
-  const bool live = item < cnt;
+  const bool live = item < entry_total(sc, n);
+  const bool conn = item >= cnt;  // a double-bounce connection (the adjoint has no points)
+  const int ncls = sc.db_on ? 4 : 2;  // class lists per chirp: facets, then connections
   int kind = 0, cell = 0;
   if (live) {
     Geo g;
-    entry_geometry(sc, rc, n, cnt, item, g);
+    RadarConst rc_e;
+    double refl[3];
+    int side;
+    nufft_entry(sc, rc, n, cnt, item, g, rc_e, refl, &side);
     int far;
     kind = nufft_classify(g, ns, &far);
     NuRecF<false> out;
@@ -871,7 +903,10 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
     out.kind = kind;
     out.ext[0] = out.ext[1] = 0.0f;
     double Rt, Rr, dxc;
-    path_fields(g, rc, ns, 0.0, out, &Rt, &Rr, &dxc);
+    path_fields(g, rc_e, ns, 0.0, out, &Rt, &Rr, &dxc);
+    // a connection's launching end acts through its mirrored direction, as in the forward
+    if (side == 0) mirror_dir(out.ut, refl);
+    if (side == 1) mirror_dir(out.ur, refl);
     cell = out.cell;
     const int64_t at = static_cast<int64_t>(nl) * ns.rec_stride + item;  // entry order
     static_cast<NuRecF<false> *>(nb.srec)[at] = out;
@@ -921,27 +956,114 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
       }
     }
     if (kind == 0) {
-      float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + item) * kAdjVals;
+      float *slot = conn ? nb.part_db + (static_cast<int64_t>(nl) * nb.db_stride + item - cnt) *
+                                            kAdjVals
+                         : partial + (static_cast<int64_t>(n) * sc.n_facets + item) * kAdjVals;
 #pragma unroll
       for (int k = 0; k < kAdjVals; ++k) slot[k] = 0.0f;
     }
   }
-  // wave-aggregated appends to the two class lists
+  // wave-aggregated appends to the class lists: three-point facets, other facets, then
+  // (with the double bounce) three-point connections, other connections
   const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    const bool mine = live && kind != 0 && (kind == 1) == (c == 0);
+  for (int c = 0; c < ncls; ++c) {
+    const bool mine = live && kind != 0 && (kind == 1) == ((c & 1) == 0) && conn == (c >= 2);
     const uint64_t m = __ballot(mine);
     if (!m) continue;
     const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
     int32_t base = 0;
-    if (lane == leader) base = atomicAdd(&nb.n_runs[2 * nl + c], __popcll(m));
+    if (lane == leader) base = atomicAdd(&nb.n_runs[ncls * nl + c], __popcll(m));
     base = __shfl(base, leader);
     if (mine) {
-      const int64_t at = static_cast<int64_t>(2 * nl + c) * ns.rec_stride + base +
+      const int64_t at = static_cast<int64_t>(ncls * nl + c) * ns.rec_stride + base +
                          __popcll(m & ((uint64_t(1) << lane) - 1));
       nb.key[at] = item;
       nb.pos[at] = cell;
+    }
+  }
+}
+
+// Chain rule of one facet-to-facet connection (chirp n, connection j) to the world vertices
+// of its facets A and B: its adjoint sums (dL/dbeta_v of the footprint's node offsets, the
+// sum of Re y = dL/d ln(amplitude)) and per-element sums dL/dR_e of the distances from the
+// channel elements (the launching side's mirrored in A's plane) to the footprint's
+// centroid give
+//   dL/dtheta = sum_e (dL/dR_e) dR_e/dtheta + sum_v (dL/dbeta_v) dbeta_v/dtheta
+//               + (sum Re y) d ln(o A)/dtheta
+// for each of the 18 vertex coordinates theta, the derivatives of the FP64 footprint
+// construction (db_footprint) taken by central differences (step kDbStep). The gradients
+// are added with FP64 atomics into the per-facet chirp sums (plain and t_n-weighted, [F][9]
+// each), so their last bits depend on the order in which connections meeting the same
+// facet arrive.
+constexpr double kDbStep = 1e-6;  // metres
+
+__global__ void __launch_bounds__(128) nufft_db_grad_kernel(DevScene sc, RadarConst rc,
+                                                           NuShape ns, NuBuffers nb,
+                                                           const double *elem, double *dbsum,
+                                                           double *dbtsum) {
+  const int nl = blockIdx.y;
+  const int n = ns.n0 + nl;
+  const int32_t j = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j >= sc.db_cnt[n] + sc.db_cnt[sc.db_n + n]) return;
+  const int32_t cnt = sc.vis_cnt[n];
+  const auto *rec = static_cast<const NuRecF<false> *>(nb.srec) +
+                    static_cast<int64_t>(nl) * ns.rec_stride + cnt + j;
+  if (rec->kind == 0) return;  // zero-area footprint: no echo
+  const int64_t slot = static_cast<int64_t>(nl) * nb.db_stride + j;
+  const float *sums = nb.part_db + slot * kAdjVals;
+  const int P = rc.P, Q = rc.Q, E = P + Q;
+  const float *del = nb.el_db + slot * E;
+  int k;
+  int64_t fa, fb;
+  db_connection(sc, n, j, &k, &fa, &fb);
+  const double t = n * rc.tc;
+  double xw[2][3][3];
+  facet_world(sc, fa, t, xw[0]);
+  facet_world(sc, fb, t, xw[1]);
+  const double *Ec = k ? rc.rx_c : rc.tx_c;
+  const double *Oc = k ? rc.tx_c : rc.rx_c;
+  const double S = sums[3];
+  const double gb[3] = {sums[4], sums[5], sums[6]};
+  // L's first-order change for a geometry: distances, node offsets and amplitude weighted
+  // by their adjoint sums
+  auto lin = [&](const double (&xa)[3][3], const double (&xb)[3][3]) {
+    Geo g;
+    double ei[3], na[3], x[3][3], xo;
+    db_footprint(xa, xb, Ec, Oc, k, 1.0, 0.0, g, ei, na, x, &xo);
+    double v = gb[0] * g.beta[0] + gb[1] * g.beta[1] + gb[2] * g.beta[2];
+    v += S * log(fabs(xo));
+    for (int e = 0; e < E; ++e) {
+      const bool tx = e < P;
+      const double *el = elem + 3 * e;
+      double pe[3] = {el[0], el[1], el[2]};
+      if (tx == (k == 0)) {
+        // the launching side's element by its image in A's plane: ei + M (e - E)
+        double a[3] = {el[0] - Ec[0], el[1] - Ec[1], el[2] - Ec[2]};
+        const double an = a[0] * na[0] + a[1] * na[1] + a[2] * na[2];
+        for (int q = 0; q < 3; ++q) pe[q] = ei[q] + a[q] - 2.0 * an * na[q];
+      }
+      const double d0 = pe[0] - g.c[0], d1 = pe[1] - g.c[1], d2 = pe[2] - g.c[2];
+      v += static_cast<double>(del[e]) * sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    return v;
+  };
+  const double h2 = 0.5 / kDbStep;
+  for (int w = 0; w < 2; ++w) {
+    const int64_t f = w ? fb : fa;
+    double gr[9];
+    for (int c = 0; c < 9; ++c) {
+      const int vtx = c / 3, q = c - 3 * vtx;
+      double xp[2][3][3], xm[2][3][3];
+      for (int u = 0; u < 2; ++u)
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) xp[u][a][b] = xm[u][a][b] = xw[u][a][b];
+      xp[w][vtx][q] += kDbStep;
+      xm[w][vtx][q] -= kDbStep;
+      gr[c] = (lin(xp[0], xp[1]) - lin(xm[0], xm[1])) * h2;
+    }
+    for (int c = 0; c < 9; ++c) {
+      atomicAdd(dbsum + f * 9 + c, gr[c]);
+      atomicAdd(dbtsum + f * 9 + c, t * gr[c]);
     }
   }
 }
@@ -1112,7 +1234,8 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     DevScene sc, RadarConst rc, NuShape ns, const double *elem,
     const NuRecF<false> *__restrict__ recs, const NuDerF *__restrict__ ders,
     const int32_t *__restrict__ lists, const int32_t *__restrict__ counts,
-    const float2 *__restrict__ grids, float *partial, int blocks_per_chirp) {
+    const float2 *__restrict__ grids, float *partial, int blocks_per_chirp, float *part_db,
+    float *el_db, int64_t nb_db_stride) {
   extern __shared__ float2 nu_row[];  // [kNuGatherStage]: rows of consecutive channels,
                                       // each the row and its first cells again, or the
                                       // stretch [lo, lo + span) the sources reach
@@ -1124,19 +1247,24 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
   if (nl >= ns.n_chirps) return;  // padding blocks (whole workgroup, before any barrier)
   const int rb = logical - nl * blocks_per_chirp;
   const int n = ns.n0 + nl;
-  const int32_t count = counts[2 * nl + CLS];
+  const int ncls = sc.db_on ? 4 : 2;
+  const int32_t count = counts[ncls * nl + CLS];
   if (rb * kNuGatherRecs >= count) return;  // whole workgroup
   const int32_t idx = rb * kNuGatherRecs + static_cast<int32_t>(threadIdx.x);
   const bool on = idx < count;
   const int32_t item =
-      on ? lists[static_cast<int64_t>(2 * nl + CLS) * ns.rec_stride + idx] : 0;
+      on ? lists[static_cast<int64_t>(ncls * nl + CLS) * ns.rec_stride + idx] : 0;
   const int ng = ns.ng;
   const int O = rc.P * rc.Q;
   const int64_t rec_at = static_cast<int64_t>(nl) * ns.rec_stride + item;
   const NuRecF<false> r = recs[on ? rec_at : static_cast<int64_t>(nl) * ns.rec_stride];
-  // sources: class 0: points j = 0..2 at s[3j]; class 1: a point at s[0] and the quadratic
-  // at s[3]
-  constexpr int NP = CLS == 0 ? 3 : 1;
+  // sources: classes 0 and 2: points j = 0..2 at s[3j]; classes 1 and 3: a point at s[0]
+  // and the quadratic at s[3]. Classes 2 and 3 are double-bounce connections: they also
+  // sum dL/dR over the channels of each element (for the chain rule through the image
+  // elements and the footprint).
+  constexpr int SRC = CLS & 1;
+  constexpr bool DB = CLS >= 2;
+  constexpr int NP = SRC == 0 ? 3 : 1;
   float offp[NP];
   float2 wp[NP];
 #pragma unroll
@@ -1146,7 +1274,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
   }
   float offq = 0.0f;
   float2 cq[3] = {{0.0f, 0.0f}, {0.0f, 0.0f}, {0.0f, 0.0f}};
-  if (CLS == 1) {
+  if (SRC == 1) {
     offq = r.s[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -1170,6 +1298,11 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
 #pragma unroll
   for (int k = 0; k < 3; ++k) ac[k] = {0.0f, 0.0f};
   const float2 *grow = grids + static_cast<int64_t>(nl) * O * ng;
+  // connections: dL/dR per element, one LDS column per lane ([P + Q][kNuGatherRecs] after
+  // the staging area)
+  float *el_acc = reinterpret_cast<float *>(nu_row + kNuGatherStage);
+  if (DB)
+    for (int e = 0; e < rc.P + rc.Q; ++e) el_acc[e * kNuGatherRecs + threadIdx.x] = 0.0f;
   // cells the lane's sources reach over every channel: a source at x - off with
   // |x| <= chan_d + 1 cell reads W + 1 cells from ceil(x - off - W/2)
   {
@@ -1179,7 +1312,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
       mn = fminf(mn, -offp[j]);
       mx = fmaxf(mx, -offp[j]);
     }
-    if (CLS == 1) {
+    if (SRC == 1) {
       mn = fminf(mn, -offq);
       mx = fmaxf(mx, -offq);
     }
@@ -1275,7 +1408,7 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
       ax[j].x += qx.x;
       ax[j].y += qx.y;
     }
-    if (CLS == 1) {
+    if (SRC == 1) {
       float2 mu[4];
       row_moments<4>(row, ng, wrap, rc0, x - offq, nc, q_ratio, mu);
       float2 yp = {0.0f, 0.0f}, yxp = {0.0f, 0.0f};
@@ -1311,6 +1444,10 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
     const float K = two_pi * fmaf(-2.0f * g2, dL, g1f);
     const float A = fmaf(K, Y.y, kappa * YX.x);
     const float ct = A - Y.x * irt, cr = A - Y.x * irr;
+    if (DB) {
+      el_acc[p * kNuGatherRecs + threadIdx.x] += ct;
+      el_acc[(rc.P + q) * kNuGatherRecs + threadIdx.x] += cr;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float ep = (static_cast<float>(at[k]) - r.rt * utf[k]) * irt;
@@ -1331,14 +1468,19 @@ __global__ void __launch_bounds__(kNuGatherRecs) nufft_gather_kernel(
       a += aw[j].x * dv.ds[v][3 * j + 1] - aw[j].y * dv.ds[v][3 * j + 2];
       a -= ax[j].x * dv.ds[v][3 * j];
     }
-    if (CLS == 1) {
+    if (SRC == 1) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) a += ac[k].x * dv.ds[v][4 + 2 * k] - ac[k].y * dv.ds[v][5 + 2 * k];
       a -= axq.x * dv.ds[v][3];
     }
     tv[v] = a;
   }
-  float *slot = partial + (static_cast<int64_t>(n) * sc.n_facets + dv.item) * kAdjVals;
+  const int64_t dslot = static_cast<int64_t>(nl) * nb_db_stride + (dv.item - sc.vis_cnt[n]);
+  float *slot = DB ? part_db + dslot * kAdjVals
+                   : partial + (static_cast<int64_t>(n) * sc.n_facets + dv.item) * kAdjVals;
+  if (DB)
+    for (int e = 0; e < rc.P + rc.Q; ++e)
+      el_db[dslot * (rc.P + rc.Q) + e] = el_acc[e * kNuGatherRecs + threadIdx.x];
   const float vals[kAdjVals] = {acc_c[0], acc_c[1], acc_c[2], acc_s, tv[0], tv[1], tv[2], 0.0f};
 #pragma unroll
   for (int k = 0; k < kAdjVals; ++k) slot[k] = vals[k];
@@ -1404,40 +1546,64 @@ hipError_t launch_nufft(const DevScene &sc, const RadarConst &rc, const double *
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
                                 const void *grad_echo, float *partial, hipStream_t s,
-                                const hipEvent_t *ev) {
+                                const hipEvent_t *ev, double *dbsum, double *dbtsum) {
   if (ns.n_chirps <= 0) return hipSuccess;
   if (sizeof(NuRecF<false>) > nb.rec_bytes || !nb.sder || !nb.key || !nb.pos || !nb.order ||
       !nb.n_runs || sc.n_points != 0 || rc.intra || ns.ng > 2 * kNuSortThreads)
+    return hipErrorInvalidValue;
+  if (sc.db_on && (!nb.part_db || !nb.el_db || nb.db_stride < 2 * sc.n_facets || !dbsum ||
+                   !dbtsum || ns.rec_stride < 3 * sc.n_facets || rc.P + rc.Q > kNuDbMaxElems))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(nufft_adj_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
                      dim3(kNuFftThreads), nufft_smem_bytes(ns), s, sc, rc, ns, nb,
                      static_cast<const float2 *>(tw), static_cast<const float2 *>(grad_echo));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t items = sc.n_facets;
-  if (items == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_zero_i32_kernel, dim3(1), dim3(256), 0, s, nb.n_runs, 2 * ns.n_chirps);
+  const int64_t items = sc.n_facets * (sc.db_on ? 3 : 1);  // facets, then connections
+  if (sc.n_facets == 0) return hipSuccess;
+  const int ncls = sc.db_on ? 4 : 2;
+  hipLaunchKernelGGL(fill_zero_i32_kernel, dim3(1), dim3(256), 0, s, nb.n_runs, ncls * ns.n_chirps);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   dim3 grid(static_cast<unsigned>((items + 255) / 256), static_cast<unsigned>(ns.n_chirps));
   hipLaunchKernelGGL(nufft_adj_prep_kernel, grid, dim3(256), 0, s, sc, rc, ns, nb, partial);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(nufft_adj_sort_kernel, dim3(static_cast<unsigned>(2 * ns.n_chirps)),
+  hipLaunchKernelGGL(nufft_adj_sort_kernel, dim3(static_cast<unsigned>(ncls * ns.n_chirps)),
                      dim3(kNuSortThreads), sizeof(int32_t) * (ns.ng + kNuSortThreads), s, ns, nb);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int bpc = static_cast<int>((items + kNuGatherRecs - 1) / kNuGatherRecs);
   const int64_t blocks = (static_cast<int64_t>(ns.n_chirps) * bpc + kXcds - 1) / kXcds * kXcds;
   const auto *recs = static_cast<const NuRecF<false> *>(nb.srec);
   const auto *ders = static_cast<const NuDerF *>(nb.sder);
+  const auto *grids = static_cast<const float2 *>(nb.grid);
+  const size_t lds = sizeof(float2) * kNuGatherStage;
+  const size_t lds_db = lds + sizeof(float) * (rc.P + rc.Q) * kNuGatherRecs;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<0>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * kNuGatherStage, s, sc, rc, ns, elem, recs, ders,
-                     nb.order, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
+                     dim3(kNuGatherRecs), lds, s, sc, rc, ns, elem, recs, ders, nb.order,
+                     nb.n_runs, grids, partial, bpc, nb.part_db, nb.el_db, nb.db_stride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((nufft_gather_kernel<1>), dim3(static_cast<unsigned>(blocks)),
-                     dim3(kNuGatherRecs), sizeof(float2) * kNuGatherStage, s, sc, rc, ns, elem, recs, ders,
-                     nb.order, nb.n_runs, static_cast<const float2 *>(nb.grid), partial, bpc);
+                     dim3(kNuGatherRecs), lds, s, sc, rc, ns, elem, recs, ders, nb.order,
+                     nb.n_runs, grids, partial, bpc, nb.part_db, nb.el_db, nb.db_stride);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (sc.db_on) {
+    hipLaunchKernelGGL((nufft_gather_kernel<2>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kNuGatherRecs), lds_db, s, sc, rc, ns, elem, recs, ders, nb.order,
+                       nb.n_runs, grids, partial, bpc, nb.part_db, nb.el_db, nb.db_stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((nufft_gather_kernel<3>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(kNuGatherRecs), lds_db, s, sc, rc, ns, elem, recs, ders, nb.order,
+                       nb.n_runs, grids, partial, bpc, nb.part_db, nb.el_db, nb.db_stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  if (sc.db_on) {
+    dim3 g2(static_cast<unsigned>((2 * sc.n_facets + 127) / 128),
+            static_cast<unsigned>(ns.n_chirps));
+    hipLaunchKernelGGL(nufft_db_grad_kernel, g2, dim3(128), 0, s, sc, rc, ns, nb, elem, dbsum,
+                       dbtsum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 

@@ -108,9 +108,18 @@ struct NuBuffers {
   // forward, optional: record counts by source form, kNuCensusSlots rows of 4 (summed by
   // the host); nullptr: no census
   unsigned long long *census;
-  int32_t *order;  // adjoint: the class lists ordered by cell [chirp][2][rec_stride]
+  int32_t *order;  // adjoint: the class lists ordered by cell [chirp][classes][rec_stride]
+  // adjoint with the facet-to-facet double bounce (else null / 0): per connection (chirp,
+  // connection j) its seven adjoint sums [chirp][db_stride][kAdjVals] and its per-element
+  // distance sums [chirp][db_stride][P + Q] (dL/dR of each Tx, then each Rx element)
+  float *part_db;
+  float *el_db;
+  int64_t db_stride;
 };
 constexpr int kNuCensusSlots = 64;
+// Tx + Rx elements the double-bounce adjoint's gather takes (an LDS column of 256 lanes per
+// element beside the 32 KB staging area: 64 KB at most)
+constexpr int kNuDbMaxElems = 32;
 // One (scene, chirp) unit of a batched NUFFT launch: the scene's index in the launch's
 // scene table, the chirp, where its records and runs start in the work buffers and the
 // scene's own record capacity, run bound and run cutting (as in NuShape).
@@ -165,10 +174,15 @@ hipError_t launch_adjoint_finish(const DevScene &sc, const RadarConst &rc, const
 // nb.pos (the records' cells beside them), nb.order (the lists ordered by cell), nb.n_runs
 // (their two counts per chirp) and nb.grid (grid rows [chirp][O][n_g]); n_g <= 2048.
 // ev (optional): two events recorded around the two gather kernels.
+// With the facet-to-facet double bounce (sc.db_on): the chirps' connections too (entries
+// after the lit facets, rec_stride >= 3 F; classes 2 and 3 of the lists), their sums into
+// nb.part_db / nb.el_db (db_stride >= 2 F) and their chain rule added into dbsum / dbtsum
+// ([F][9] FP64 per-facet chirp sums, plain and t_n-weighted).
 hipError_t launch_nufft_adjoint(const DevScene &sc, const RadarConst &rc, const double *elem,
                                 const NuShape &ns, const NuBuffers &nb, const void *tw,
                                 const void *grad_echo, float *partial, hipStream_t s,
-                                const hipEvent_t *ev = nullptr);
+                                const hipEvent_t *ev = nullptr, double *dbsum = nullptr,
+                                double *dbtsum = nullptr);
 
 // Allocation-free range-Doppler processing: a file-scope device array of
 // kStaticScratchBytes per GPU, addressed through static_scratch_address (looked up once
@@ -219,9 +233,11 @@ hipError_t launch_scale_conj(const void *in, void *out, int64_t n, double gr, do
                              hipStream_t s);
 // world-vertex gradients [N][F][9] -> per-facet sums over chirps, plain and t_n-weighted;
 // gxv (or null): the velocity's sums over samples [N][F][3], a third added to the
-// t_n-weighted sum of each corner
+// t_n-weighted sum of each corner; dbsum (or null): [2][F][9] sums added to both (the
+// double-bounce connections')
 hipError_t launch_facet_chirp_sum(const float *gxw, const float *gxv, int64_t n_facets, int N,
-                                  double tc, double *gsum, double *gtsum, hipStream_t s);
+                                  double tc, double *gsum, double *gtsum, hipStream_t s,
+                                  const double *dbsum = nullptr);
 hipError_t launch_vertex_gather(const double *gsum, const double *gtsum, const double *rot_dev,
                                 int64_t facet_base, const int32_t *csr_off, const int32_t *csr_ent,
                                 int32_t n_verts, float *gv, double *vpart, double *vel_out,

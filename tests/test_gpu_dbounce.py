@@ -9,6 +9,8 @@ footprint term of oracle/dbounce.py) through the C ABI, against the FP64 oracle:
   record census counts exactly those connections;
 * the whole echo (single + double bounce, complex gamma) against the oracle's sum;
 * the dihedral closed form (sigma = 8 pi a^2 b^2 / lambda^2) through the GPU path;
+* the adjoint (NUFFT, connections held) against FP64 central differences of the oracle's
+  loss over the single + double-bounce echo (oracle/dbounce.pairs_for_table);
 * the refusals.
 """
 import sys
@@ -136,6 +138,112 @@ def test_dihedral_closed_form_on_gpu():
     assert np.allclose(r, 1.0, rtol=1e-4)
 
 
+def _with_vertex(sc, mesh_k, vert, axis, dv):
+    from scenes import Mesh, Scene
+    meshes = []
+    for k, m in enumerate(sc.meshes):
+        v = m.verts.astype(np.float64)
+        if k == mesh_k:
+            v = v.copy()
+            v[vert, axis] += dv
+        meshes.append(Mesh(verts=v, tris=m.tris, name=m.name))
+    return Scene(meshes, sc.instances)
+
+
+def _with_velocity(sc, inst_k, axis, dv):
+    from scenes import Instance, Scene
+    insts = []
+    for k, i in enumerate(sc.instances):
+        vel = np.array(i.vel, np.float64).copy()
+        if k == inst_k:
+            vel[axis] += dv
+        insts.append(Instance(i.mesh, i.rot, i.pos0, vel))
+    return Scene(sc.meshes, insts)
+
+
+def test_double_bounce_adjoint_matches_finite_differences():
+    """rsim_backward with the double bounce on (NUFFT adjoint): each connection's sums go
+    through the footprint construction to the vertices of both facets. Against central
+    differences of the oracle's loss sum (RDM - T)^2 over the single-bounce echo (lit mask
+    held) plus the double bounce of the held connection table (footprints recomputed from
+    the perturbed scene), on vertices of connected facets and the velocity. The adjoint
+    without the double bounce misses the bar, so the check sees its terms."""
+    import torch
+    cfg = scenes.small_single(n_samples=64, n_chirps=2, n_tris=1500)
+    sc, wf = cfg.scenes[0], cfg.waveform
+    arr = RadarArray(tx=np.array(cfg.array.tx[:4]), rx=np.array(cfg.array.rx[:6]))
+    g = -0.8 + 0.3j
+    _log("case double-bounce adjoint vs FD, 1.5k-triangle vehicle, 4x6 channels, M=64, N=2")
+    sim = _sim(sc, wf, arr, g)
+    F = sim.n_facets[0]
+    om, _ = oracle.visibility(sc, arr, wf)
+    table = dbounce.connection_table(dbounce.double_bounce_pairs(sc, arr, wf), F)
+
+    def echo(scene):
+        return (oracle.synthesize(scene, wf, arr, mask=om) +
+                dbounce.synthesize_double(scene, wf, arr, gamma=g,
+                                          pairs=dbounce.pairs_for_table(scene, arr, wf, table)))
+
+    P0, _ = oracle.rdm_from_echo(echo(sc))
+    T = 0.5 * P0
+
+    def loss(scene):
+        P, _ = oracle.rdm_from_echo(echo(scene))
+        return oracle.rdm_loss(P, T)
+
+    m_in = sim.mask_with_connections([om], [table])
+    H = sim.synthesize(mask=m_in, mask_mode=1)
+    rdm, y = sim.form_rdm(H, want_y=True)
+    ge = torch.empty_like(H)
+    sim.ctx.rdm_backward((2.0 * (rdm - torch.from_numpy(T.astype(np.float32)).cuda()[None]))
+                         .contiguous(), y, ge)
+
+    def adjoint():
+        gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+              for m in sc.meshes]
+        gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+        sim.ctx.backward(sim.scene_ids[0], ge, m_in, gv, gvel)
+        return [x.cpu().numpy().astype(np.float64) for x in gv], gvel.cpu().numpy()
+
+    gverts, gvel = adjoint()
+    sim.ctx.set_double_bounce(False)
+    sv, svel = adjoint()
+    sim.ctx.set_double_bounce(True, g)
+    # vertices of the A and B facets of seeded connections
+    rng = np.random.default_rng(31)
+    tri, inst_of, local_of = oracle.world_triangles(sc, 0.0)
+    kk, aa = np.nonzero(table[:, 0, :] >= 0)
+    picks = []
+    for i in rng.choice(aa.size, size=3, replace=False):
+        for f in (aa[i], table[kk[i], 0, aa[i]]):
+            mesh_k = sc.instances[inst_of[f]].mesh
+            picks.append((mesh_k, int(sc.meshes[mesh_k].tris[local_of[f], rng.integers(0, 3)])))
+    h, hv = 1e-5, 1e-2
+    fd, ad, sh = [], [], []
+    for (mk, v) in picks:
+        for ax in range(3):
+            fd.append((loss(_with_vertex(sc, mk, v, ax, h)) -
+                       loss(_with_vertex(sc, mk, v, ax, -h))) / (2 * h))
+            ad.append(gverts[mk][v, ax])
+            sh.append(sv[mk][v, ax])
+    for ax in range(2):
+        fd.append((loss(_with_velocity(sc, 0, ax, hv)) - loss(_with_velocity(sc, 0, ax, -hv))) /
+                  (2 * hv))
+        ad.append(gvel[0, ax])
+        sh.append(svel[0, ax])
+    fd, ad, sh = np.array(fd), np.array(ad), np.array(sh)
+    rel_l2 = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    big = np.abs(fd) > 1e-3 * np.abs(fd).max()
+    rel_c = np.abs(ad - fd)[big] / np.abs(fd)[big]
+    rel_sh = np.linalg.norm(sh - fd) / np.linalg.norm(fd)
+    _log(f"  connections {int((table >= 0).sum())}; rel_l2={rel_l2:.3e} "
+         f"max_rel_component={rel_c.max():.3e} (n={fd.size}); without the double bounce "
+         f"rel_l2={rel_sh:.3e}")
+    assert rel_l2 <= 1e-3
+    assert rel_c.max() <= 1e-2
+    assert rel_sh > 2e-3
+
+
 def test_double_bounce_refusals():
     from paper_2208_10939_amd.rsim import RsimError
     cfg = scenes.small_single(n_samples=32, n_chirps=2, n_tris=300)
@@ -149,6 +257,19 @@ def test_double_bounce_refusals():
     with pytest.raises(RsimError) as e:
         sim.ctx.autotune(sim.scene_ids)
     assert e.value.code == -4  # ESTATE
+    # the backward: the NUFFT adjoint only
+    import torch
+    mask = sim.mask_buffer()
+    H = sim.synthesize(mask=mask)
+    gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+          for m in sc.meshes]
+    gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+    for k in (1, 2):
+        sim.ctx.set_backward_kernel(k)
+        with pytest.raises(RsimError) as e:
+            sim.ctx.backward(sim.scene_ids[0], H, mask, gv, gvel)
+        assert e.value.code == -1, k  # EINVAL
+    sim.ctx.set_backward_kernel(0)
     sim.ctx.set_double_bounce(False)
     sim.synthesize(kernel=1)  # the direct kernels again
 
