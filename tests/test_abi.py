@@ -273,6 +273,50 @@ def test_nufft_adjoint_refusals_host_only():
     ctx.close()
 
 
+def test_double_bounce_adjoint_refusals_host_only():
+    """With the facet-to-facet double bounce on, rsim_backward runs the NUFFT adjoint only,
+    stop-and-hop, without the ground plane and for at most 32 elements: the other cases are
+    refused on the host (EINVAL / ERANGE), AUTO and NUFFT reach the (missing) device."""
+    ctx = _host_ctx()
+    L = rsim.lib()
+    wf = scenes.paper_waveform(64, 8)
+    ctx.set_waveform(wf)
+    arr = scenes.sparse_mimo_12x16(wf, 2)
+    ctx.set_array(arr.tx, arr.rx)
+    m = scenes.vehicle_mesh("car", 500)
+    mid = ctx.load_mesh(m.verts, m.tris)
+    sid = ctx.create_scene()
+    ctx.add_instance(sid, mid, np.eye(3), np.array([2.0, 30.0, 0.0]), np.array([0.0, 5.0, 0.0]))
+    dev = ctypes.c_void_p(0x1000)
+    gv = (ctypes.c_void_p * 1)(0x2000)
+
+    def bwd():
+        return L.rsim_backward(ctx._h, sid, dev, dev, gv, 1, dev, None)
+
+    ctx.set_double_bounce(True, -1.0)
+    for k in (rsim.RSIM_KERNEL_VECTOR, rsim.RSIM_KERNEL_MATRIX):
+        assert L.rsim_set_backward_kernel(ctx._h, k) == rsim.RSIM_OK
+        assert bwd() == rsim.RSIM_EINVAL
+        assert b"NUFFT adjoint" in L.rsim_last_error(ctx._h)
+    for k in (rsim.RSIM_KERNEL_AUTO, rsim.RSIM_KERNEL_NUFFT):
+        assert L.rsim_set_backward_kernel(ctx._h, k) == rsim.RSIM_OK
+        assert bwd() == rsim.RSIM_EDEVICE
+    assert L.rsim_set_backward_intra_chirp(ctx._h, 1) == rsim.RSIM_OK
+    assert bwd() == rsim.RSIM_EINVAL
+    assert L.rsim_set_backward_intra_chirp(ctx._h, 0) == rsim.RSIM_OK
+    ctx.set_ground(True, 0.0, -0.7)
+    assert bwd() == rsim.RSIM_EINVAL
+    ctx.set_ground(False)
+    # 20 Tx + 16 Rx elements: beyond the gather's 32 LDS columns
+    tx = np.concatenate([arr.tx, arr.tx[:8] + np.array([0.0, 0.0, 0.01])])
+    ctx.set_array(tx, arr.rx)
+    assert bwd() == rsim.RSIM_ERANGE
+    assert b"32" in L.rsim_last_error(ctx._h)
+    ctx.set_array(arr.tx, arr.rx)
+    ctx.set_double_bounce(False)
+    ctx.close()
+
+
 def test_intra_chirp_adjoint_refusals_host_only():
     """rsim_set_backward_intra_chirp: 0/1 only; with it on, the adjoint runs on the vector
     units, so a backward kernel of MATRIX or NUFFT is EINVAL on the host and AUTO / VECTOR
