@@ -65,8 +65,9 @@ __device__ __forceinline__ void poly_cells(float2 (&acc)[kNuSlots], const float2
 // First cell of a source's block: the lowest cell within `reach` of the source's
 // position for the wave's first channel, clamped to the blocks the chain holds (the
 // runs keep every channel's cells inside the window, so a clamp never drops one of them).
-__device__ __forceinline__ int block_start(float x0, float reach) {
-  const int s = __builtin_amdgcn_readfirstlane(static_cast<int>(ceilf(x0 - reach)));
+// lo_lanes holds the unclamped cell of the record's source at s[3 j] in lane j (j < 3).
+__device__ __forceinline__ int block_start(int lo_lanes, int j) {
+  const int s = __builtin_amdgcn_readlane(lo_lanes, j);
   return s < 0 ? 0 : s > 22 ? 22 : s;
 }
 
@@ -225,6 +226,13 @@ nufft_spread_kernel(
     const float amp = __builtin_amdgcn_rcpf((r.rt + dRt) * (r.rr + dRr));
     const float qx = __builtin_amdgcn_cosf(t) * amp, qy = -__builtin_amdgcn_sinf(t) * amp;
     const int n_pts = r.kind == 1 ? 3 : r.kind == 2 ? 1 : 0;
+    // the block starts of the record's sources at s[0], s[3], s[6], one per lane (lanes 0,
+    // 1, 2) in one pass instead of one wave-wide pass each
+    int off_i = __builtin_bit_cast(int, r.s[0]);
+    asm volatile("v_writelane_b32 %0, %1, 1" : "+v"(off_i) : "s"(__builtin_bit_cast(int, r.s[3])));
+    asm volatile("v_writelane_b32 %0, %1, 2" : "+v"(off_i) : "s"(__builtin_bit_cast(int, r.s[6])));
+    const float off_l = __builtin_bit_cast(float, off_i);
+    const int lo_lanes = static_cast<int>(ceilf((x0 - off_l) - reach));
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       if (j < n_pts) {
@@ -233,7 +241,7 @@ nufft_spread_kernel(
                            qx * r.s[3 * j + 2] + qy * r.s[3 * j + 1]};
         // cells some channel reaches: |s - (x_o - off)| <= W/2 with |x_o - x0| <= wave_d,
         // NCELL of them from s_lo
-        const int s_lo = block_start(x0 - off, reach);
+        const int s_lo = block_start(lo_lanes, j);
         if constexpr (INTRA) {
           const float2 c1[1] = {cw};
           float2 c3[3];
@@ -250,7 +258,7 @@ nufft_spread_kernel(
 #pragma unroll
       for (int k = 0; k < 3; ++k)
         cq[k] = {qx * r.s[4 + 2 * k] - qy * r.s[5 + 2 * k], qx * r.s[5 + 2 * k] + qy * r.s[4 + 2 * k]};
-      const int s_lo = block_start(x0 - off, reach);
+      const int s_lo = block_start(lo_lanes, 1);
       if constexpr (INTRA) {
         float2 c5[5];
         intra_coeffs(cq, c5, eps, inv_s2);
