@@ -228,10 +228,7 @@ nufft_spread_kernel(
     const int n_pts = r.kind == 1 ? 3 : r.kind == 2 ? 1 : 0;
     // the block starts of the record's sources at s[0], s[3], s[6], one per lane (lanes 0,
     // 1, 2) in one pass instead of one wave-wide pass each
-    int off_i = __builtin_bit_cast(int, r.s[0]);
-    asm volatile("v_writelane_b32 %0, %1, 1" : "+v"(off_i) : "s"(__builtin_bit_cast(int, r.s[3])));
-    asm volatile("v_writelane_b32 %0, %1, 2" : "+v"(off_i) : "s"(__builtin_bit_cast(int, r.s[6])));
-    const float off_l = __builtin_bit_cast(float, off_i);
+    const float off_l = lane == 0 ? r.s[0] : lane == 1 ? r.s[3] : r.s[6];
     const int lo_lanes = static_cast<int>(ceilf((x0 - off_l) - reach));
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
