@@ -22,6 +22,7 @@ namespace rsim {
 namespace {
 
 constexpr int kVisThreads = 256;
+constexpr int kVisFilterFacets = 32;  // facets per workgroup with 64 chirps per group
 constexpr int kVisBitWords = 4 * 64;  // LDS bit words: path types x chirps x mask words
 
 __device__ inline int find_instance(const DevInstance *inst, int n_inst, int64_t f) {
@@ -248,13 +249,14 @@ __device__ bool blas_occluded2(const BvhNode4 *nodes, const float4 *leaf, float 
 // of segment_blocked joined by "or".
 __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], const double s1[3],
                              const double s2[3], int self_inst, int32_t self_local,
-                             int32_t *stack, int stride) {
+                             int32_t *stack, int stride, uint64_t cand) {
   const double dw[2][3] = {{s1[0] - c[0], s1[1] - c[1], s1[2] - c[2]},
                            {s2[0] - c[0], s2[1] - c[1], s2[2] - c[2]}};
   double idw[2][3];  // reciprocals once per segment, as in segment_blocked
   for (int r = 0; r < 2; ++r)
     for (int k = 0; k < 3; ++k) idw[r][k] = dw[r][k] != 0.0 ? 1.0 / dw[r][k] : 0.0;
   for (int j = 0; j < sc.n_inst; ++j) {
+    if (j < 64 && !((cand >> j) & 1u)) continue;  // no segment of the wave meets its box
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
     if (flat_below(I, c, s1[2]) && flat_below(I, c, s2[2])) continue;
@@ -295,6 +297,60 @@ __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], co
   return false;
 }
 
+// Instances (bit j for instance j < 64) whose box some segment c(t) -> T or c(t) -> R of
+// the wave may meet, c(t) the centroid of facet f (the wave's one facet) at the chirp times
+// t of chirps n_a .. n_b. Lane j tests instance j: the segments from the centroid at the
+// middle time, against the box swept over the chirps' times and grown by the centroid's
+// sweep about its middle position (the point at parameter s of c(t) -> S differs from that
+// of c_m -> S by (1 - s)(c(t) - c_m)) and by 1e-6 m against rounding. A superset of the
+// instances the per-chirp FP64 box test admits, so the decisions are those without it;
+// instances from 64 on are not filtered.
+__device__ uint64_t wave_candidates(const DevScene &sc, const RadarConst &rc, int64_t f, int n_a,
+                                    int n_b) {
+  const int lane = threadIdx.x & 63;
+  const double ta = n_a * rc.tc, tb = n_b * rc.tc, tm = 0.5 * (ta + tb);
+  const DevInstance &F = sc.inst[find_instance(sc.inst, sc.n_inst, f)];
+  const int32_t lt = static_cast<int32_t>(f - F.facet_base);
+  double b[3] = {0.0, 0.0, 0.0};
+  for (int v = 0; v < 3; ++v) {
+    const int32_t vi = F.tris[3 * lt + v];
+    for (int k = 0; k < 3; ++k) b[k] += F.verts[3 * vi + k];
+  }
+  double cm[3], hw[3];
+  for (int k = 0; k < 3; ++k) {
+    cm[k] = (F.rot[3 * k + 0] * b[0] + F.rot[3 * k + 1] * b[1] + F.rot[3 * k + 2] * b[2]) / 3.0 +
+            (F.pos0[k] + F.vel[k] * tm);
+    hw[k] = fabs(F.vel[k]) * (0.5 * (tb - ta)) + 1e-6;
+  }
+  bool cand = false;
+  if (lane < sc.n_inst) {
+    const DevInstance &I = sc.inst[lane];
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      const double pa = I.pos0[k] + I.vel[k] * ta, pb = I.pos0[k] + I.vel[k] * tb;
+      lo[k] = I.box_lo[k] + fmin(pa, pb) - hw[k];
+      hi[k] = I.box_hi[k] + fmax(pa, pb) + hw[k];
+    }
+    for (int r = 0; r < 2; ++r) {
+      const double *S = r ? rc.rx_c : rc.tx_c;
+      double tn = 0.0, tf = 1.0;
+      bool miss = false;
+      for (int k = 0; k < 3; ++k) {
+        const double d = S[k] - cm[k];
+        if (d == 0.0) {
+          if (cm[k] < lo[k] || cm[k] > hi[k]) miss = true;
+          continue;
+        }
+        const double a = (lo[k] - cm[k]) / d, e = (hi[k] - cm[k]) / d;
+        tn = fmax(tn, fmin(a, e));
+        tf = fmin(tf, fmax(a, e));
+      }
+      cand = cand || !(miss || tn > tf);
+    }
+  }
+  return __ballot(cand);
+}
+
 // One side (phase centre E, facing value fe = n . (E - c)) of a facet: *direct when it
 // faces E and centroid -> E is clear; *reflected when the centroid lies above the ground
 // plane, the facet faces the image E' and both legs centroid -> S -> E are clear, S the
@@ -322,7 +378,7 @@ namespace {
 // Lit decisions of facet f at chirp n: the single path (lit[0]) or, with the ground bounce,
 // the four path types (transmit side k & 1, receive side k >> 1).
 __device__ void facet_lit(const DevScene &sc, const RadarConst &rc, int64_t f, int n,
-                          int32_t *stk, int stride, bool lit[4]) {
+                          int32_t *stk, int stride, uint64_t cand, bool lit[4]) {
   lit[0] = lit[1] = lit[2] = lit[3] = false;
   const double t = n * rc.tc;
   const int ii = find_instance(sc.inst, sc.n_inst, f);
@@ -350,7 +406,7 @@ __device__ void facet_lit(const DevScene &sc, const RadarConst &rc, int64_t f, i
   const double fr = nx * (rc.rx_c[0] - c[0]) + ny * (rc.rx_c[1] - c[1]) + nz * (rc.rx_c[2] - c[2]);
   if (!rc.bounce) {
     if (nonzero && ft > 0.0 && fr > 0.0)
-      lit[0] = !pair_blocked(sc, t, c, rc.tx_c, rc.rx_c, ii, lt, stk, stride);
+      lit[0] = !pair_blocked(sc, t, c, rc.tx_c, rc.rx_c, ii, lt, stk, stride, cand);
   } else if (nonzero) {
     const double nv[3] = {nx, ny, nz};
     bool dt, it, dr, ir;
@@ -370,10 +426,11 @@ __device__ void facet_lit(const DevScene &sc, const RadarConst &rc, int64_t f, i
 // nearly the same rays of one facet at neighbouring chirps and follow nearly one BVH path
 // (mapping lanes to neighbouring facets instead makes every wave walk the union of 64
 // different paths). Decisions are gathered as bits in LDS and written as whole words.
-__global__ void __launch_bounds__(kVisThreads) vis_kernel(DevScene sc, RadarConst rc, int cw,
+__global__ void __launch_bounds__(kVisThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) vis_kernel(DevScene sc, RadarConst rc, int cw,
                                                         int facets_per_block, int n_begin,
                                                         int n_end) {
   extern __shared__ int32_t vis_lds[];
+  __shared__ uint64_t cand_lds[kVisFilterFacets];
   const int words = facets_per_block >> 5;
   const int types = rc.bounce ? 4 : 1;
   uint32_t *bits = reinterpret_cast<uint32_t *>(vis_lds);  // [types][cw][words]
@@ -383,11 +440,26 @@ __global__ void __launch_bounds__(kVisThreads) vis_kernel(DevScene sc, RadarCons
   const int nl = threadIdx.x % cw;
   const int n = n_begin + static_cast<int>(blockIdx.y) * cw + nl;
   const int64_t f0 = static_cast<int64_t>(blockIdx.x) * facets_per_block;
+  // With 64 chirps per group (a wave per facet) and the single path, the instances each
+  // facet's segments may meet are found first, one wave per facet in turn, into LDS.
+  const bool filter = cw == 64 && !rc.bounce && facets_per_block <= kVisFilterFacets;
+  if (filter) {
+    const int n_a = n_begin + static_cast<int>(blockIdx.y) * cw;
+    const int n_b = min(n_end, n_a + cw) - 1;
+    for (int fl = threadIdx.x >> 6; fl < facets_per_block; fl += blockDim.x >> 6) {
+      const int64_t f = f0 + fl;
+      if (f >= sc.n_facets) break;  // wave-uniform
+      const uint64_t m = wave_candidates(sc, rc, f, n_a, n_b);
+      if ((threadIdx.x & 63) == 0) cand_lds[fl] = m;
+    }
+    __syncthreads();
+  }
   for (int fl = threadIdx.x / cw; fl < facets_per_block; fl += blockDim.x / cw) {
     const int64_t f = f0 + fl;
     if (f >= sc.n_facets || n >= n_end) continue;
+    const uint64_t cand = filter ? cand_lds[fl] : ~uint64_t(0);
     bool lit[4];
-    facet_lit(sc, rc, f, n, stk, blockDim.x, lit);
+    facet_lit(sc, rc, f, n, stk, blockDim.x, cand, lit);
     for (int k = 0; k < types; ++k)
       if (lit[k]) atomicOr(&bits[(k * cw + nl) * words + (fl >> 5)], 1u << (fl & 31));
   }
