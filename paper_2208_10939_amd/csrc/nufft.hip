@@ -496,14 +496,17 @@ __device__ void nufft_entry(const DevScene &sc, const RadarConst &rc, int n, int
   double xa[3][3], xb[3][3], x[3][3], ei[3], na[3];
   facet_world(sc, fa, t, xa);
   facet_world(sc, fb, t, xb);
-  const double *E = k ? rc.rx_c : rc.tx_c;
-  const double *O = k ? rc.tx_c : rc.rx_c;
+  // the launching and other centres by value (selects, not a pointer chosen at run time,
+  // which would move the centres to scratch memory)
+  double E[3], O[3];
+  for (int q = 0; q < 3; ++q) {
+    E[q] = k ? rc.rx_c[q] : rc.tx_c[q];
+    O[q] = k ? rc.tx_c[q] : rc.rx_c[q];
+  }
   db_footprint(xa, xb, E, O, k, sc.db_gamma_re, sc.db_gamma_im, g, ei, na, x);
   for (int q = 0; q < 3; ++q) {
-    if (k == 0)
-      rc_e.tx_c[q] = ei[q];
-    else
-      rc_e.rx_c[q] = ei[q];
+    rc_e.tx_c[q] = k == 0 ? ei[q] : rc.tx_c[q];
+    rc_e.rx_c[q] = k == 1 ? ei[q] : rc.rx_c[q];
     refl[q] = na[q];
   }
   *side = k;
