@@ -114,9 +114,11 @@ def _log(msg):
 
 
 def platform_info():
-    """GPU name and architecture, HIP runtime and ROCm versions, and the current and top
-    shader clocks as rocm-smi reports them (each entry null where not available)."""
-    import subprocess
+    """GPU name and architecture, HIP runtime and ROCm versions, and the shader clock levels
+    the driver lists in sysfs (pp_dpm_sclk, the current one marked '*'; each entry null where
+    not available). Read from files: no helper program is started (a child started after
+    the GPU is initialised may not exec another program on every host)."""
+    import glob
     import torch
     info = {"gpu": None, "arch": None, "hip": getattr(torch.version, "hip", None), "rocm": None,
             "sclk": None}
@@ -131,13 +133,15 @@ def platform_info():
             info["rocm"] = f.read().strip()
     except OSError:
         pass
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
-                           timeout=20)
-        lines = [ln.strip() for ln in r.stdout.splitlines() if "sclk" in ln.lower()]
-        info["sclk"] = lines[:2] or None
-    except (OSError, subprocess.SubprocessError):
-        pass
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(path) as f:
+                levels = [ln.strip() for ln in f if ln.strip()]
+        except OSError:
+            continue
+        if levels:
+            info["sclk"] = levels
+            break
     return info
 
 
