@@ -37,7 +37,8 @@ hipError_t launch_compact(const DevScene &sc, int n_begin, int n_chirps, hipStre
 // into pair_b [2][N][F] (the connected facet or -1), then per (end, chirp) the connected
 // facets in ascending order into idx [2][N][F] and their counts into cnt [2][N]. ray_len:
 // metres a reflected ray is followed (0: pair_b is given; only the compaction runs);
-// r_lim: the scene's largest facet radius.
+// r_lim: the scene's largest facet radius. With ray_len > 0, sc.mask holds the chirps'
+// single-path lit masks (a lit facet sees both phase centres).
 hipError_t launch_dbounce(const DevScene &sc, const RadarConst &rc, double ray_len, double r_lim,
                           int32_t *pair_b, int32_t *idx, int32_t *cnt, hipStream_t s);
 

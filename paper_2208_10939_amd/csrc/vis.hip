@@ -630,7 +630,8 @@ __device__ inline double dot3(const double *a, const double *b) {
 // ray from A's centroid first hits B (FP32 traversal over a segment of ray_len metres); B
 // faces the image E' of E in A's plane and the other centre O, and the segment from the
 // hit point to O is clear; the central projection from E' of A's vertices onto B's plane
-// lies ahead of E' (parameters above 1/2) and within 1.5 r_lim of its centroid.
+// lies ahead of E' (parameters above 1/2) and within 1.5 r_lim of its centroid. Reads
+// the chirp's lit mask (computed before, single path).
 __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t f, int n, int k,
                               double ray_len, double r_lim, int32_t *stk, int stride) {
   const double t = n * rc.tc;
@@ -645,7 +646,10 @@ __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t 
   double de[3] = {E[0] - ca[0], E[1] - ca[1], E[2] - ca[2]};
   const double fe = dot3(na, de);
   if (!(fe > 0.0)) return -1;
-  if (segment_blocked(sc, t, ca, E, ia, la, stk, stride)) return -1;
+  // A lit facet (single path, this chirp's mask) faces both centres with both segments from
+  // its centroid clear, the one to E among them: its test is not repeated
+  const bool lit = (sc.mask[static_cast<int64_t>(n) * sc.mask_words + (f >> 5)] >> (f & 31)) & 1u;
+  if (!lit && segment_blocked(sc, t, ca, E, ia, la, stk, stride)) return -1;
   // specular direction of d = (c_A - E) / |c_A - E|
   const double ld = sqrt(dot3(de, de));
   double r[3];
