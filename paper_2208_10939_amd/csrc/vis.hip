@@ -129,13 +129,15 @@ __device__ inline bool flat_below(const DevInstance &I, const double c[3], doubl
 // (triangle `self_local` of instance `self_inst` excluded)?
 __device__ bool segment_blocked(const DevScene &sc, double t, const double c[3],
                                 const double s[3], int self_inst, int32_t self_local,
-                                int32_t *stack, int stride, bool skip_plane = false) {
+                                int32_t *stack, int stride, bool skip_plane = false,
+                                uint64_t cand = ~uint64_t(0)) {
   double d[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
   // reciprocals once per segment (the boxes are padded, so the rounding of a product
   // instead of a quotient cannot turn a hit box into a miss)
   const double id[3] = {d[0] != 0.0 ? 1.0 / d[0] : 0.0, d[1] != 0.0 ? 1.0 / d[1] : 0.0,
                         d[2] != 0.0 ? 1.0 / d[2] : 0.0};
   for (int j = 0; j < sc.n_inst; ++j) {
+    if (j < 64 && !((cand >> j) & 1u)) continue;  // no segment of the wave meets its box
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
     if (skip_plane && I.in_plane) continue;  // the road surface under a reflected leg
@@ -295,6 +297,33 @@ __device__ bool pair_blocked(const DevScene &sc, double t, const double c[3], co
     if (blas_occluded2(I.nodes, I.leaf, ox, oy, oz, d, skip, stack, stride)) return true;
   }
   return false;
+}
+
+// Does the segment a -> b meet the box [lo, hi] (FP64 slab test, closed)?
+__device__ inline bool seg_box(const double a[3], const double b[3], const double lo[3],
+                               const double hi[3]) {
+  double tn = 0.0, tf = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    const double d = b[k] - a[k];
+    if (d == 0.0) {
+      if (a[k] < lo[k] || a[k] > hi[k]) return false;
+      continue;
+    }
+    const double u = (lo[k] - a[k]) / d, w = (hi[k] - a[k]) / d;
+    tn = fmax(tn, fmin(u, w));
+    tf = fmin(tf, fmax(u, w));
+  }
+  return tn <= tf;
+}
+
+// World box of instance I swept over the times [ta, tb] and grown by g[k] on each side.
+__device__ inline void swept_box(const DevInstance &I, double ta, double tb, const double g[3],
+                                 double lo[3], double hi[3]) {
+  for (int k = 0; k < 3; ++k) {
+    const double pa = I.pos0[k] + I.vel[k] * ta, pb = I.pos0[k] + I.vel[k] * tb;
+    lo[k] = I.box_lo[k] + fmin(pa, pb) - g[k];
+    hi[k] = I.box_hi[k] + fmax(pa, pb) + g[k];
+  }
 }
 
 // Instances (bit j for instance j < 64) whose box some segment c(t) -> T or c(t) -> R of
@@ -624,6 +653,64 @@ __device__ inline double dot3(const double *a, const double *b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// The pair search's instance filter for facet f (the wave's one facet) at chirps n_a .. n_b:
+// for each launching end k, the instances (bit j for instance j < 64) that the shadow
+// segment c(t) -> E (out[2 k]) or the specular segment c(t) -> c(t) + ray_len r(t)
+// (out[2 k + 1]) of some chirp may meet. Lane j tests instance j with the segments at the
+// middle time against its box swept over the chirps' times and grown: by the centroid's
+// sweep per axis for the shadow segment (as in visibility); for the specular one by
+// |delta| (1 + 2 ray_len / (|E - c_m| - |delta|)), |delta| the centroid's largest
+// displacement from its middle position (the unit vector towards E turns by at most
+// 2 |delta| / (|E - c_m| - |delta|), and the mirror in A's plane, fixed under translation,
+// keeps that), plus 1e-6 m against rounding. Supersets of what the per-chirp FP64 box
+// tests admit; all instances where that bound does not apply.
+__device__ void db_wave_candidates(const DevScene &sc, const RadarConst &rc, int64_t f, int n_a,
+                                   int n_b, double ray_len, uint64_t out[4]) {
+  const int lane = threadIdx.x & 63;
+  const double ta = n_a * rc.tc, tb = n_b * rc.tc, tm = 0.5 * (ta + tb);
+  const DevInstance &A = sc.inst[find_instance(sc.inst, sc.n_inst, f)];
+  double x[3][3], c[3], na[3];
+  world_vertices(A, f - A.facet_base, tm, x);
+  const bool ok = tri_frame(x, c, na);
+  double hw[3], sweep = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double dk = fabs(A.vel[k]) * (0.5 * (tb - ta));
+    hw[k] = dk + 1e-6;
+    sweep += dk * dk;
+  }
+  sweep = sqrt(sweep);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double *E = k ? rc.rx_c : rc.tx_c;
+    double de[3] = {E[0] - c[0], E[1] - c[1], E[2] - c[2]};
+    const double ld = sqrt(dot3(de, de));
+    bool all = !ok || !(ld - sweep > 0.0);
+    double end[3], gr[3];
+    if (!all) {
+      double r[3];
+      for (int q = 0; q < 3; ++q) r[q] = -de[q] / ld;
+      const double rn = dot3(r, na);
+      for (int q = 0; q < 3; ++q) {
+        r[q] -= 2.0 * rn * na[q];
+        end[q] = c[q] + ray_len * r[q];
+      }
+      const double g = sweep * (1.0 + 2.0 * ray_len / (ld - sweep)) + 1e-6;
+      gr[0] = gr[1] = gr[2] = g;
+    }
+    bool ce = true, cr = true;
+    if (lane < sc.n_inst && !all) {
+      const DevInstance &I = sc.inst[lane];
+      double lo[3], hi[3];
+      swept_box(I, ta, tb, hw, lo, hi);
+      ce = seg_box(c, E, lo, hi);
+      swept_box(I, ta, tb, gr, lo, hi);
+      cr = seg_box(c, end, lo, hi);
+    }
+    out[2 * k] = __ballot(ce);
+    out[2 * k + 1] = __ballot(cr);
+  }
+}
+
 // Facet B that the ray launched from end k (0: Tx phase centre, 1: Rx) reflected off facet A
 // (scene index f) connects to at chirp n, or -1 (Section 2.2; the rules of the oracle's
 // facet-to-facet double bounce): A faces the launching centre E and sees it; the specular
@@ -633,7 +720,8 @@ __device__ inline double dot3(const double *a, const double *b) {
 // lies ahead of E' (parameters above 1/2) and within 1.5 r_lim of its centroid. Reads
 // the chirp's lit mask (computed before, single path).
 __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t f, int n, int k,
-                              double ray_len, double r_lim, int32_t *stk, int stride) {
+                              double ray_len, double r_lim, int32_t *stk, int stride,
+                              uint64_t cand_e, uint64_t cand_r) {
   const double t = n * rc.tc;
   const double *E = k ? rc.rx_c : rc.tx_c;
   const double *O = k ? rc.tx_c : rc.rx_c;
@@ -649,7 +737,7 @@ __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t 
   // A lit facet (single path, this chirp's mask) faces both centres with both segments from
   // its centroid clear, the one to E among them: its test is not repeated
   const bool lit = (sc.mask[static_cast<int64_t>(n) * sc.mask_words + (f >> 5)] >> (f & 31)) & 1u;
-  if (!lit && segment_blocked(sc, t, ca, E, ia, la, stk, stride)) return -1;
+  if (!lit && segment_blocked(sc, t, ca, E, ia, la, stk, stride, false, cand_e)) return -1;
   // specular direction of d = (c_A - E) / |c_A - E|
   const double ld = sqrt(dot3(de, de));
   double r[3];
@@ -664,6 +752,7 @@ __device__ int32_t db_connect(const DevScene &sc, const RadarConst &rc, int64_t 
                         r[2] != 0.0 ? 1.0 / (r[2] * ray_len) : 0.0};
   const float t_min = static_cast<float>(1e-6 / ray_len);
   for (int j = 0; j < sc.n_inst; ++j) {
+    if (j < 64 && !((cand_r >> j) & 1u)) continue;  // no specular segment of the wave meets it
     const DevInstance &I = sc.inst[j];
     if (!I.has_bvh) continue;
     double p[3] = {I.pos0[0] + I.vel[0] * t, I.pos0[1] + I.vel[1] * t, I.pos0[2] + I.vel[2] * t};
@@ -740,16 +829,35 @@ __global__ void __launch_bounds__(kVisThreads) dbounce_kernel(DevScene sc, Radar
                                                             int n_end, double ray_len,
                                                             double r_lim, int32_t *pair_b) {
   extern __shared__ int32_t db_lds[];
+  __shared__ uint64_t cand_lds[kVisFilterFacets][4];
   int32_t *stk = db_lds + threadIdx.x;  // column per thread
   const int nl = threadIdx.x % cw;
   const int n = n_begin + static_cast<int>(blockIdx.y) * cw + nl;
   const int64_t f0 = static_cast<int64_t>(blockIdx.x) * facets_per_block;
+  // with 64 chirps per group (a wave per facet) each facet's instances are filtered first
+  const bool filter = cw == 64 && facets_per_block <= kVisFilterFacets;
+  if (filter) {
+    const int n_a = n_begin + static_cast<int>(blockIdx.y) * cw;
+    const int n_b = min(n_end, n_a + cw) - 1;
+    for (int fl = threadIdx.x >> 6; fl < facets_per_block; fl += blockDim.x >> 6) {
+      const int64_t f = f0 + fl;
+      if (f >= sc.n_facets) break;  // wave-uniform
+      uint64_t m[4];
+      db_wave_candidates(sc, rc, f, n_a, n_b, ray_len, m);
+      if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 4; ++q) cand_lds[fl][q] = m[q];
+    }
+    __syncthreads();
+  }
   for (int fl = threadIdx.x / cw; fl < facets_per_block; fl += blockDim.x / cw) {
     const int64_t f = f0 + fl;
     if (f >= sc.n_facets || n >= n_end) continue;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) {
+      const uint64_t ce = filter ? cand_lds[fl][2 * k] : ~uint64_t(0);
+      const uint64_t cr = filter ? cand_lds[fl][2 * k + 1] : ~uint64_t(0);
       pair_b[(static_cast<int64_t>(k) * rc.N + n) * sc.n_facets + f] =
-          db_connect(sc, rc, f, n, k, ray_len, r_lim, stk, blockDim.x);
+          db_connect(sc, rc, f, n, k, ray_len, r_lim, stk, blockDim.x, ce, cr);
+    }
   }
 }
 
