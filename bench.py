@@ -153,10 +153,10 @@ def _src_hash(kernel="vector"):
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel, workload):
+def _traffic(kernel, workload, key=None):
     """HBM bytes of the roofline's unit (direct sums: one facet-sum launch; NUFFT: the
     spread's launches of one frame) from the committed counter summary of this kernel and
-    workload, if it was taken on the current kernel source."""
+    workload, if it was taken on the current kernel source (key: another entry of it)."""
     try:
         with open(os.path.join(ROOT, "profiles", PROFILE_TRAFFIC[kernel].format(w=workload))) as f:
             d = json.load(f)
@@ -164,7 +164,7 @@ def _traffic(kernel, workload):
         return None
     if d.get("echo_hip_sha256_16") != _src_hash(kernel):
         return None
-    return d.get("bytes_per_frame" if kernel == "nufft" else "bytes_per_launch")
+    return d.get(key or ("bytes_per_frame" if kernel == "nufft" else "bytes_per_launch"))
 
 
 def roofline(kernel, evals, fs_ms, shape=None, workload="c3", nufft=None):
@@ -189,6 +189,10 @@ def roofline(kernel, evals, fs_ms, shape=None, workload="c3", nufft=None):
             "unit": "TFLOP/s",
             "frac": ach / PEAK_FP32_VECTOR,
             "traffic": _traffic("nufft", workload),
+            # the same counters resolved by read-request size: FETCH_SIZE's copy-kernel
+            # factor of 2 corrects 128-B requests, the spread's reads are 64-B requests
+            "traffic_by_request_size": _traffic("nufft", workload,
+                                                "bytes_per_frame_by_request_size"),
             "kernel": "rsim::nufft_spread_kernel (type-1 NUFFT spread: each run of "
                       "cell-sorted records adds its Gaussian grid sources into a per-channel "
                       "register window of 32 cells)",
