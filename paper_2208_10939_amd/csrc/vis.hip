@@ -862,29 +862,35 @@ __global__ void __launch_bounds__(kVisThreads) dbounce_kernel(DevScene sc, Radar
 }
 
 // Per (end, chirp): the connected facets in ascending order and their count (deterministic).
+// The row is read in tiles of one element per thread (coalesced); ballots and the waves'
+// counts in LDS (two sets, alternating per tile, so one barrier per tile) place each
+// connected facet.
 __global__ void __launch_bounds__(1024) db_compact_kernel(const int32_t *pair_b, int64_t F,
                                                           int32_t *idx, int32_t *cnt) {
-  __shared__ int32_t s_scan[1024];
+  __shared__ int32_t s_w[2][16];
   const int64_t row = blockIdx.x;  // k N + n
   const int32_t *b = pair_b + row * F;
-  const int64_t per = (F + blockDim.x - 1) / blockDim.x;
-  const int64_t i0 = static_cast<int64_t>(threadIdx.x) * per;
-  const int64_t i1 = min(F, i0 + per);
-  int32_t c = 0;
-  for (int64_t i = i0; i < i1; ++i) c += b[i] >= 0 && b[i] < F;  // others: no connection
-  s_scan[threadIdx.x] = c;
-  __syncthreads();
-  for (int off = 1; off < static_cast<int>(blockDim.x); off <<= 1) {
-    int32_t v = (threadIdx.x >= static_cast<unsigned>(off)) ? s_scan[threadIdx.x - off] : 0;
-    __syncthreads();
-    s_scan[threadIdx.x] += v;
-    __syncthreads();
-  }
-  int32_t pos = s_scan[threadIdx.x] - c;
   int32_t *out = idx + row * F;
-  for (int64_t i = i0; i < i1; ++i)
-    if (b[i] >= 0 && b[i] < F) out[pos++] = static_cast<int32_t>(i);
-  if (threadIdx.x == blockDim.x - 1) cnt[row] = s_scan[threadIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int32_t base = 0;
+  int par = 0;
+  for (int64_t t0 = 0; t0 < F; t0 += blockDim.x, par ^= 1) {
+    const int64_t i = t0 + threadIdx.x;
+    const int32_t v = i < F ? b[i] : -1;
+    const bool on = v >= 0 && v < F;  // others: no connection
+    const uint64_t m = __ballot(on);
+    if (lane == 0) s_w[par][wv] = __popcll(m);
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int32_t c = s_w[par][w];
+      before += w < wv ? c : 0;
+      total += c;
+    }
+    if (on) out[base + before + __popcll(m & ((uint64_t(1) << lane) - 1))] = static_cast<int32_t>(i);
+    base += total;
+  }
+  if (threadIdx.x == 0) cnt[row] = base;
 }
 
 hipError_t launch_dbounce(const DevScene &sc, const RadarConst &rc, double ray_len, double r_lim,
