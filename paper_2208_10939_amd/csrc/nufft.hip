@@ -993,8 +993,13 @@ __global__ void __launch_bounds__(256) nufft_adj_prep_kernel(DevScene sc, RadarC
 // centroid give
 //   dL/dtheta = sum_e (dL/dR_e) dR_e/dtheta + sum_v (dL/dbeta_v) dbeta_v/dtheta
 //               + (sum Re y) d ln(o A)/dtheta
-// for each of the 18 vertex coordinates theta, the derivatives of the FP64 footprint
-// construction (db_footprint) taken by central differences (step kDbStep). The gradients
+// for each of the 18 vertex coordinates theta. With u_e the unit vector from the centroid
+// c to element e and a_e = e - E, the element image E' + M a_e (M = I - 2 n n^T, n A's unit
+// normal) moves by dE' - 2 (dn (n . a_e) + n (dn . a_e)), so the distance term's change is
+//   -S . dc + S_L . dE' - 2 V . dn,   S = sum_e (dL/dR_e) u_e,  S_L the same over the
+//   launching side,  V = sum over that side of (dL/dR_e) ((n . a_e) u_e + (u_e . n) a_e),
+// formed once; the derivatives of the FP64 footprint construction (db_footprint: c, E', n,
+// the node offsets and o A) are taken by central differences (step kDbStep). The gradients
 // are added with FP64 atomics into the per-facet chirp sums (plain and t_n-weighted, [F][9]
 // each), so their last bits depend on the order in which connections meeting the same
 // facet arrive.
@@ -1023,50 +1028,66 @@ __global__ void __launch_bounds__(128) nufft_db_grad_kernel(DevScene sc, RadarCo
   double xw[2][3][3];
   facet_world(sc, fa, t, xw[0]);
   facet_world(sc, fb, t, xw[1]);
-  const double *Ec = k ? rc.rx_c : rc.tx_c;
-  const double *Oc = k ? rc.tx_c : rc.rx_c;
+  // the launching and other centres by value (selects: no run-time pointer into rc)
+  double Ec[3], Oc[3];
+  for (int q = 0; q < 3; ++q) {
+    Ec[q] = k ? rc.rx_c[q] : rc.tx_c[q];
+    Oc[q] = k ? rc.tx_c[q] : rc.rx_c[q];
+  }
   const double S = sums[3];
   const double gb[3] = {sums[4], sums[5], sums[6]};
-  // L's first-order change for a geometry: distances, node offsets and amplitude weighted
-  // by their adjoint sums
-  auto lin = [&](const double (&xa)[3][3], const double (&xb)[3][3]) {
+  // the element sums at the connection's geometry
+  double sa[3] = {0.0, 0.0, 0.0}, sl[3] = {0.0, 0.0, 0.0}, vv[3] = {0.0, 0.0, 0.0};
+  {
+    Geo g0;
+    double ei[3], na[3], x[3][3], xo;
+    db_footprint(xw[0], xw[1], Ec, Oc, k, 1.0, 0.0, g0, ei, na, x, &xo);
+    for (int e = 0; e < E; ++e) {
+      const bool launching = (e < P) == (k == 0);
+      const double de = static_cast<double>(del[e]);
+      double a[3], pe[3];
+      for (int q = 0; q < 3; ++q) a[q] = elem[3 * e + q] - Ec[q];
+      const double an = a[0] * na[0] + a[1] * na[1] + a[2] * na[2];
+      for (int q = 0; q < 3; ++q)
+        pe[q] = launching ? ei[q] + a[q] - 2.0 * an * na[q] : elem[3 * e + q];
+      double u[3] = {pe[0] - g0.c[0], pe[1] - g0.c[1], pe[2] - g0.c[2]};
+      const double r = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      for (int q = 0; q < 3; ++q) u[q] /= r;
+      const double un = u[0] * na[0] + u[1] * na[1] + u[2] * na[2];
+      for (int q = 0; q < 3; ++q) {
+        sa[q] += de * u[q];
+        sl[q] += launching ? de * u[q] : 0.0;
+        vv[q] += launching ? de * (an * u[q] + un * a[q]) : 0.0;
+      }
+    }
+  }
+  // L's first-order change for a geometry: node offsets, amplitude and the element term
+  auto lin = [&](const double (&xq)[2][3][3]) {
     Geo g;
     double ei[3], na[3], x[3][3], xo;
-    db_footprint(xa, xb, Ec, Oc, k, 1.0, 0.0, g, ei, na, x, &xo);
-    double v = gb[0] * g.beta[0] + gb[1] * g.beta[1] + gb[2] * g.beta[2];
-    v += S * log(fabs(xo));
-    for (int e = 0; e < E; ++e) {
-      const bool tx = e < P;
-      const double *el = elem + 3 * e;
-      double pe[3] = {el[0], el[1], el[2]};
-      if (tx == (k == 0)) {
-        // the launching side's element by its image in A's plane: ei + M (e - E)
-        double a[3] = {el[0] - Ec[0], el[1] - Ec[1], el[2] - Ec[2]};
-        const double an = a[0] * na[0] + a[1] * na[1] + a[2] * na[2];
-        for (int q = 0; q < 3; ++q) pe[q] = ei[q] + a[q] - 2.0 * an * na[q];
-      }
-      const double d0 = pe[0] - g.c[0], d1 = pe[1] - g.c[1], d2 = pe[2] - g.c[2];
-      v += static_cast<double>(del[e]) * sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    }
+    db_footprint(xq[0], xq[1], Ec, Oc, k, 1.0, 0.0, g, ei, na, x, &xo);
+    double v = gb[0] * g.beta[0] + gb[1] * g.beta[1] + gb[2] * g.beta[2] + S * log(fabs(xo));
+    for (int q = 0; q < 3; ++q) v += -sa[q] * g.c[q] + sl[q] * ei[q] - 2.0 * vv[q] * na[q];
     return v;
+  };
+  // coordinate cc of facet w moved by dh (selects: no run-time index into the arrays)
+  auto lin_at = [&](int w, int cc, double dh) {
+    double xq[2][3][3];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) xq[u][v][q] = xw[u][v][q] + ((u == w && 3 * v + q == cc) ? dh : 0.0);
+    return lin(xq);
   };
   const double h2 = 0.5 / kDbStep;
   for (int w = 0; w < 2; ++w) {
     const int64_t f = w ? fb : fa;
-    double gr[9];
-    for (int c = 0; c < 9; ++c) {
-      const int vtx = c / 3, q = c - 3 * vtx;
-      double xp[2][3][3], xm[2][3][3];
-      for (int u = 0; u < 2; ++u)
-        for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) xp[u][a][b] = xm[u][a][b] = xw[u][a][b];
-      xp[w][vtx][q] += kDbStep;
-      xm[w][vtx][q] -= kDbStep;
-      gr[c] = (lin(xp[0], xp[1]) - lin(xm[0], xm[1])) * h2;
-    }
-    for (int c = 0; c < 9; ++c) {
-      atomicAdd(dbsum + f * 9 + c, gr[c]);
-      atomicAdd(dbtsum + f * 9 + c, t * gr[c]);
+    for (int cc = 0; cc < 9; ++cc) {
+      const double gr = (lin_at(w, cc, kDbStep) - lin_at(w, cc, -kDbStep)) * h2;
+      atomicAdd(dbsum + f * 9 + cc, gr);
+      atomicAdd(dbtsum + f * 9 + cc, t * gr);
     }
   }
 }
