@@ -286,6 +286,42 @@ def test_autograd_double_bounce_matches_direct_calls():
     assert torch.allclose(vel.grad.cuda(), gvel, rtol=1e-5, atol=1e-8 * gvel.abs().max().item())
 
 
+def test_double_bounce_chunked_equals_whole():
+    """Chirps in chunks of at most 3 (rsim_set_nufft_chunk) against one chunk, with the
+    double bounce: the forward echo bit for bit; the adjoint's gradients to the last bits
+    of the connections' FP64 atomic sums (their order differs)."""
+    import torch
+    cfg = scenes.small_single(n_samples=64, n_chirps=8, n_tris=1500)
+    sc, wf = cfg.scenes[0], cfg.waveform
+    arr = RadarArray(tx=np.array(cfg.array.tx[:4]), rx=np.array(cfg.array.rx[:6]))
+    _log("case double bounce, nufft chunks of 3 chirps vs one chunk (N=8), forward and adjoint")
+    sim = _sim(sc, wf, arr, -0.8 + 0.3j)
+    mask = sim.mask_buffer()
+    O = arr.tx.shape[0] * arr.rx.shape[0]
+    rng = np.random.default_rng(9)
+    g = (rng.standard_normal((O, wf.n_chirps, wf.n_samples)) +
+         1j * rng.standard_normal((O, wf.n_chirps, wf.n_samples))).astype(np.complex64)
+    ge = torch.from_numpy(g).cuda()
+    res = {}
+    for chunk in (0, 3):
+        sim.ctx.set_nufft_chunk(chunk)
+        H = sim.synthesize(mask=mask).cpu().numpy()
+        gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+              for m in sc.meshes]
+        gvel = torch.zeros((len(sc.instances), 3), dtype=torch.float64, device="cuda")
+        sim.ctx.backward(sim.scene_ids[0], ge, mask, gv, gvel)
+        res[chunk] = (H, np.concatenate([x.cpu().numpy().ravel() for x in gv]).astype(np.float64),
+                      gvel.cpu().numpy().ravel())
+    sim.ctx.set_nufft_chunk(0)
+    assert int((sim.connections_numpy(mask)[0] >= 0).sum()) > 0
+    dh = rel_rms(res[3][0], res[0][0])
+    dv = np.linalg.norm(res[3][1] - res[0][1]) / np.linalg.norm(res[0][1])
+    dw = np.linalg.norm(res[3][2] - res[0][2]) / np.linalg.norm(res[0][2])
+    _log(f"  echo rel_rms={dh:.3e}, vertex gradients {dv:.3e}, velocity gradients {dw:.3e}")
+    assert dh == 0.0
+    assert dv <= 1e-6 and dw <= 1e-10
+
+
 def test_double_bounce_refusals():
     from paper_2208_10939_amd.rsim import RsimError
     cfg = scenes.small_single(n_samples=32, n_chirps=2, n_tris=300)
