@@ -481,6 +481,34 @@ def measure_double_bounce(sim, lit_per_step, reps=2):
         sim.set_double_bounce(False)
 
 
+def measure_intra_chirp(sim, echo_ref, reps=2):
+    """The same frame with the delay within the chirp (rsim_opts.intra_chirp = 1, the
+    default facet-sum kernel): frame time with its stages, and the echo's relative RMS
+    difference from the stop-and-hop echo echo_ref (the range-Doppler coupling)."""
+    import numpy as np
+    import torch
+    echo = sim.echo_buffer(1)
+    mask = sim.mask_buffer()
+    rdm = torch.empty(echo.shape, dtype=torch.float32, device="cuda")
+    sid = sim.scene_ids[0]
+    sim.ctx.synthesize([sid], echo, mask, intra_chirp=1)
+    ts, st = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.ctx.synthesize([sid], echo, mask, timing=True, intra_chirp=1)
+        sim.ctx.form_rdm(echo, rdm, None, n_cubes=1, timing=True)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        st.append(sim.ctx.last_timings())
+    sim.ctx.synthesize([sid], echo, mask, intra_chirp=1)
+    d = float(torch.linalg.vector_norm(echo - echo_ref) / torch.linalg.vector_norm(echo_ref))
+    i = int(np.argmin(ts))
+    return {"ms_per_frame": 1e3 * float(np.median(ts)),
+            "stage_ms": {k: round(v, 4) for k, v in st[i].items()},
+            "rel_rms_vs_stop_and_hop": d}
+
+
 def calib_copy(mib: int):
     """Plain elementwise copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -648,6 +676,8 @@ def main():
         out["fwd_bwd"] = measure_fwd_bwd(sim, kernel)
         _log("bench: the facet-to-facet double bounce on the same frame")
         out["double_bounce"] = measure_double_bounce(sim, int(lit.sum()))
+        _log("bench: the delay within the chirp on the same frame")
+        out["intra_chirp"] = measure_intra_chirp(sim, echo)
         _log("bench: batched vs plain (the 64-scene workload)")
         out["batched_vs_plain"] = measure_batched()
     if cpu is not None:
