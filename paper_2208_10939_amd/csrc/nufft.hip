@@ -1549,6 +1549,11 @@ static hipError_t launch_nufft_t(const DevScene &sc, const RadarConst &rc, const
         hipSuccess)
       return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  } else {
+    // no entries (no facet or point): no runs, so the FFT kernel transforms empty grids
+    hipLaunchKernelGGL(fill_zero_i32_kernel, dim3(1), dim3(256), 0, s, nb.n_runs, ns.n_chirps);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(nufft_fft_kernel, dim3(static_cast<unsigned>(ns.n_chirps * ns.groups)),
                      dim3(kNuFftThreads), nufft_fft_smem_bytes(ns), s, sc, rc, ns, nb,

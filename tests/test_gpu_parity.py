@@ -327,3 +327,56 @@ def test_facet_integral_regimes(sim_mod, precision):
             err = float(np.max(np.abs(H - Ho) / np.abs(Ho)))
             _log(f"  max elementwise rel={err:.3e} rel_rms={rel_rms(H, Ho):.3e}")
             assert err <= 2e-5
+
+
+def test_degenerate_scenes(sim_mod):
+    """Scenes with nothing to sum: no instance at all, and one with a triangle facing away
+    from both phase centres (never lit) beside a mesh of zero-area triangles only. Every
+    facet-sum kernel (vector units, matrix cores, NUFFT) gives all-zero echoes and RDMs;
+    called with a vehicle scene, plain and persistent, the vehicle's echo is the bits of its
+    own call; the backward gives zero gradients."""
+    import torch
+    from scenes import Instance, Mesh, Scene
+    cfg = scenes.small_single(n_samples=64, n_chirps=8, n_tris=800)
+    wf = cfg.waveform
+    arr = RadarArray(tx=np.array(cfg.array.tx[:3]), rx=np.array(cfg.array.rx[:4]))
+    away = Mesh(verts=np.array([[0, 20, 0], [0, 20, 1], [1, 20, 0]], np.float32),
+                tris=np.array([[0, 1, 2]], np.int32), name="away")  # normal +y: faces away
+    line = Mesh(verts=np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32),
+                tris=np.array([[0, 1, 2], [2, 1, 0]], np.int32), name="zero-area")
+    eye = np.eye(3)
+    dark = Scene([away, line], [Instance(0, eye, np.zeros(3), np.array([0.0, 2.0, 0.0])),
+                                Instance(1, eye, np.array([0.0, 15.0, 1.0]), np.zeros(3))])
+    _log("case degenerate scenes (empty; unlit + zero-area) with every kernel")
+    sim = sim_mod.Simulator([Scene([], []), dark, cfg.scenes[0]], wf, arr)
+    assert sim.n_facets[0] == 0 and sim.n_facets[1] == 3
+    for kernel in (1, 2, 3):
+        for i in (0, 1):
+            H = sim.synthesize([i], mask=sim.mask_buffer([i]), kernel=kernel)
+            P = sim.form_rdm(H)
+            assert torch.count_nonzero(H).item() == 0, (kernel, i)
+            assert torch.count_nonzero(P).item() == 0, (kernel, i)
+        Hv = sim.synthesize([2], mask=sim.mask_buffer([2]), kernel=kernel).cpu()
+        assert torch.count_nonzero(Hv).item() > 0
+        for persistent in (False, True):
+            Ha = sim.synthesize(mask=sim.mask_buffer(), kernel=kernel, persistent=persistent).cpu()
+            assert torch.count_nonzero(Ha[:2]).item() == 0, (kernel, persistent)
+            assert torch.equal(Ha[2], Hv[0]), (kernel, persistent)
+    O = arr.tx.shape[0] * arr.rx.shape[0]
+    rng = np.random.default_rng(5)
+    g = (rng.standard_normal((O, wf.n_chirps, wf.n_samples)) +
+         1j * rng.standard_normal((O, wf.n_chirps, wf.n_samples))).astype(np.complex64)
+    ge = torch.from_numpy(g).cuda()
+    for kernel in (1, 3):
+        sim.ctx.set_backward_kernel(kernel)
+        for i in (0, 1):
+            mask = sim.mask_buffer([i])
+            sim.synthesize([i], mask=mask, kernel=kernel)
+            gv = [torch.zeros((m.verts.shape[0], 3), dtype=torch.float32, device="cuda")
+                  for m in ([] if i == 0 else dark.meshes)]
+            gvel = torch.full((max(1, 2 * i), 3), 0.0, dtype=torch.float64, device="cuda")
+            sim.ctx.backward(sim.scene_ids[i], ge, mask, gv, gvel)
+            assert all(torch.count_nonzero(x).item() == 0 for x in gv), (kernel, i)
+            assert torch.count_nonzero(gvel).item() == 0, (kernel, i)
+    sim.ctx.set_backward_kernel(0)
+
