@@ -145,12 +145,14 @@ def test_experiment2_waveform_384_samples(sim_mod):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("M,N", [(256, 64), (384, 48), (162, 6), (96, 9), (64, 81)])
+@pytest.mark.parametrize("M,N", [(256, 64), (384, 48), (162, 6), (96, 9), (64, 81),
+                                 (4096, 2), (3888, 2), (2, 4096)])
 def test_rdm_fft_against_numpy(sim_mod, precision, M, N):
     """Range/Doppler FFTs and the RDM on a seeded random cube vs numpy.fft (FP64), at
     power-of-two lengths and at mixed radix-2/3 lengths (384 samples is the paper's
     second experiment; 162 = 2 x 3^4); odd chirp counts (9, 81) check that row l holds
-    Doppler index l - floor(N/2), as numpy's fftshift puts it."""
+    Doppler index l - floor(N/2), as numpy's fftshift puts it; the largest lengths the
+    transforms take (4096 samples or chirps; 3888 = 2^4 3^5) and the smallest (2)."""
     import torch
     _log(f"case rdm_fft precision={precision} M={M} N={N}")
     wf = scenes.paper_waveform(M, N)
