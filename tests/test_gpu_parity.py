@@ -382,3 +382,34 @@ def test_degenerate_scenes(sim_mod):
             assert torch.count_nonzero(gvel).item() == 0, (kernel, i)
     sim.ctx.set_backward_kernel(0)
 
+
+@pytest.mark.parametrize("case", ["samples", "chirps"])
+def test_synthesis_at_maximum_sizes(sim_mod, case):
+    """The facet sum at the largest frame sizes the library takes: 4096 samples per chirp
+    (a 300-triangle vehicle, oracle visibility as input mask; the vector units, the matrix
+    cores and the default kernel) and 4096 chirps (point targets, which need no
+    visibility), FP32 sum with FP64 phase against the FP64 oracle."""
+    if case == "samples":
+        cfg = scenes.small_single(n_samples=4096, n_chirps=2, n_tris=300)
+        sc, wf = cfg.scenes[0], cfg.waveform
+        arr = RadarArray(tx=np.array(cfg.array.tx[:2]), rx=np.array(cfg.array.rx[:2]))
+        mask, _ = oracle.visibility(sc, arr, wf)
+        kernels = (1, 2, 0)
+    else:
+        wf = scenes.paper_waveform(2, 4096)
+        sc = scenes.point_scene([12.3, 37.9], [-7.0, 3.3], amps=[1.0, 0.5 - 0.2j],
+                                az_deg=[-20.0, 5.0])
+        arr = scenes.ula_1tx4rx(wf)
+        mask = None
+        kernels = (1, 0)
+    _log(f"case synthesis at maximum size: {case} (M={wf.n_samples}, N={wf.n_chirps})")
+    sim = sim_mod.Simulator([sc], wf, arr)
+    Ho = oracle.synthesize(sc, wf, arr, mask=mask)
+    m_t = sim.mask_from_numpy([mask]) if mask is not None else sim.mask_buffer()
+    for k in kernels:
+        mode = 1 if mask is not None else 0
+        H = sim.synthesize(mask=m_t, mask_mode=mode, kernel=k).cpu().numpy()[0]
+        err = rel_rms(H, Ho)
+        _log(f"  kernel {k}: rel_rms={err:.3e}")
+        assert err <= 1e-4, k
+
