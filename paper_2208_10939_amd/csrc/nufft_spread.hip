@@ -55,6 +55,26 @@ __device__ __forceinline__ void poly_cells(float2 (&acc)[kNuSlots], const float2
   }
 }
 
+// Gaussian times c0 + c2 (s - pos)^2 (no linear term: a point source under the delay
+// within the chirp) at the cells S0 .. S0 + NCELL - 1.
+template <int S0, int NCELL>
+__device__ __forceinline__ void even2_cells(float2 (&acc)[kNuSlots], float2 c0, float2 c2,
+                                            float u0, float gw, float rho, float q_ratio) {
+  asm volatile("" : "+v"(u0), "+v"(gw), "+v"(rho));  // formed in the block, as above
+#pragma unroll
+  for (int j = 0; j < NCELL; ++j) {
+    if (S0 + j < kNuSlots) {
+      const float xx = u0 + static_cast<float>(j);
+      const float x2 = xx * xx;
+      const float pr = fmaf(c2.x, x2, c0.x), pi = fmaf(c2.y, x2, c0.y);
+      acc[S0 + j].x = fmaf(gw, pr, acc[S0 + j].x);
+      acc[S0 + j].y = fmaf(gw, pi, acc[S0 + j].y);
+      gw *= rho;
+      rho *= q_ratio;
+    }
+  }
+}
+
 // The window cell s_lo (wave-uniform) selects one straight-line block of NCELL cells. A
 // source covers NCELL or fewer cells (its count is floor(2 reach) or one more, NCELL at
 // least the larger), so a block may reach up to four cells past the last the runs
@@ -86,6 +106,19 @@ __device__ __forceinline__ void spread_point(float2 (&acc)[kNuSlots], float2 cw,
   if (bit & (1u << S)) point_cells<S, NCELL>(acc, cw, gw, rho, q_ratio);
   RSIM_NU_CASES(RSIM_NU_POINT)
 #undef RSIM_NU_POINT
+}
+
+template <int NCELL>
+__device__ __forceinline__ void spread_even2(float2 (&acc)[kNuSlots], float2 c0, float2 c2,
+                                             float pos, int s_lo, float nc, float q_ratio) {
+  const float u0 = static_cast<float>(s_lo) - pos;
+  const float gw = __builtin_amdgcn_exp2f(nc * u0 * u0);
+  const float rho = __builtin_amdgcn_exp2f(nc * fmaf(2.0f, u0, 1.0f));
+  const uint32_t bit = static_cast<uint32_t>(s_lo) < 32u ? 1u << s_lo : 0u;  // none: no cell
+#define RSIM_NU_EVEN2(S) \
+  if (bit & (1u << S)) even2_cells<S, NCELL>(acc, c0, c2, u0, gw, rho, q_ratio);
+  RSIM_NU_CASES(RSIM_NU_EVEN2)
+#undef RSIM_NU_EVEN2
 }
 
 template <int NCELL, int NC>
@@ -240,10 +273,12 @@ nufft_spread_kernel(
         // NCELL of them from s_lo
         const int s_lo = block_start(lo_lanes, j);
         if constexpr (INTRA) {
-          const float2 c1[1] = {cw};
-          float2 c3[3];
-          intra_coeffs(c1, c3, eps, inv_s2);
-          spread_poly<NCELL>(acc, c3, xr - off, s_lo, nc, q_ratio);
+          // (1 - j 2 pi B m'^2) on a point's modes: cw (1 - j eps / s^2) + j eps cw / s^4 x^2
+          // (intra_coeffs of one coefficient; its linear term is zero)
+          const float e2 = eps * inv_s2, e4 = e2 * inv_s2;
+          const float2 c0 = {fmaf(e2, cw.y, cw.x), fmaf(-e2, cw.x, cw.y)};
+          const float2 c2 = {-e4 * cw.y, e4 * cw.x};
+          spread_even2<NCELL>(acc, c0, c2, xr - off, s_lo, nc, q_ratio);
         } else {
           spread_point<NCELL>(acc, cw, xr - off, s_lo, nc, q_ratio);
         }
