@@ -450,8 +450,9 @@ def measure_batched(n_scenes=64, reps=2, kernels=("matrix", "nufft")):
 
 def measure_double_bounce(sim, lit_per_step, reps=2):
     """The same frame with the facet-to-facet double bounce on (NUFFT facet sum): frame
-    time with its stages (the connection search runs in the compaction stage), and the
-    number of connections (census records beyond the lit facets)."""
+    time with its stages (the connection search runs in the compaction stage), the number
+    of connections (census records beyond the lit facets), and the time of rsim_backward
+    for the loss sum RDM^2 through that echo (NUFFT adjoint, connection table held)."""
     import numpy as np
     import torch
     sim.set_double_bounce(True, -1.0)
@@ -472,9 +473,28 @@ def measure_double_bounce(sim, lit_per_step, reps=2):
             st.append(sim.ctx.last_timings())
         sim.ctx.synthesize([sid], echo, mask, mask_mode=1, census=True)
         records = sum(sim.ctx.last_census().values())
+        # the backward of sum RDM^2 through this echo (NUFFT adjoint, connections held)
+        y = torch.empty_like(echo)
+        sim.ctx.form_rdm(echo, rdm, y, n_cubes=1)
+        ge = torch.empty_like(echo)
+        sim.ctx.rdm_backward((2.0 * rdm).contiguous(), y, ge)
+        meshes = sim.ctx.scene_meshes[sid]
+        gv = [None] * (max(meshes) + 1)
+        for mid in meshes:
+            gv[mid] = torch.zeros((sim.ctx.mesh_nverts[mid], 3), dtype=torch.float32,
+                                  device="cuda")
+        gvel = torch.zeros((len(sim.inst_pos0[0]), 3), dtype=torch.float64, device="cuda")
+        bs = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.ctx.backward(sid, ge, mask, gv, gvel)
+            torch.cuda.synchronize()
+            bs.append(time.perf_counter() - t0)
         i = int(np.argmin(ts))
         return {"ms_per_frame": 1e3 * float(np.median(ts)),
                 "stage_ms": {k: round(v, 4) for k, v in st[i].items()},
+                "backward_ms": 1e3 * float(np.median(bs[1:])),
                 "connections_per_frame": int(records - lit_per_step),
                 "lit_facet_records_per_frame": int(lit_per_step)}
     finally:
